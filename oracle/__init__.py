@@ -1,0 +1,193 @@
+"""CPU oracle for the MESSI hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_2009_00786_amd``) and never imports it.  The arithmetic lives in
+``oracle.c`` (plain C, built with gcc -O2 -ffp-contract=off); this module only
+marshals numpy arrays.
+
+Each function cites the passage of the paper (Peng, Fatourou, Palpanas,
+"MESSI: In-Memory Data Series Indexing") or the textbook definition it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+LEAF_DTYPE = np.dtype([("card", np.uint8, (16,)), ("prefix", np.uint8, (16,)),
+                       ("start", np.uint32), ("count", np.uint32)])
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no multiply-add contraction, no fast math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-pthread", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=False)
+        lib = ctypes.CDLL(LIB)
+        vp, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        lib.oracle_breakpoints.argtypes = [ctypes.c_int, vp]
+        lib.oracle_breakpoints.restype = ctypes.c_int
+        lib.oracle_znorm.argtypes = [vp, i64, i32, vp]
+        lib.oracle_paa.argtypes = [vp, i64, i32, i32, vp]
+        lib.oracle_symbols.argtypes = [vp, i64, i32, i32, vp, vp]
+        lib.oracle_root_keys.argtypes = [vp, i64, i32, i32, vp]
+        lib.oracle_build_leaves.argtypes = [vp, i64, i32, i32, i64, vp, vp]
+        lib.oracle_build_leaves.restype = i64
+        lib.oracle_d64.argtypes = [vp, vp, i32]
+        lib.oracle_d64.restype = d
+        lib.oracle_mindist_sq.argtypes = [vp, i32, i32, vp, vp, i32, vp, d]
+        lib.oracle_mindist_sq.restype = d
+        lib.oracle_mindist_sq_f.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+        lib.oracle_mindist_sq_f.restype = d
+        lib.oracle_knn_brute.argtypes = [vp, i64, i32, vp, i32, i32, ctypes.c_int, i64, vp, vp]
+        lib.oracle_knn_brute.restype = ctypes.c_int
+        lib.oracle_knn_isax.argtypes = [vp, i64, i32, vp, i32, i32, vp, i64, vp, vp, i32, i32, vp, vp, vp]
+        lib.oracle_knn_isax.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def breakpoints(card_bits: int) -> np.ndarray:
+    """beta_j = fl32(Phi^-1(j / 2^b)), j = 1 .. 2^b - 1 (iSAX regions, Preliminaries)."""
+    out = np.zeros(255, dtype=np.float32)
+    cnt = _load().oracle_breakpoints(card_bits, out.ctypes.data)
+    if cnt < 0:
+        raise ValueError("card_bits must be in [1, 8]")
+    return out[:cnt].copy()
+
+
+def znorm(x) -> np.ndarray:
+    """Per-series z-normalisation, fp64 statistics (Preliminaries)."""
+    x = _f32(x)
+    n, length = x.shape
+    z = np.empty_like(x)
+    _load().oracle_znorm(x.ctypes.data, n, length, z.ctypes.data)
+    return z
+
+
+def paa(z, segments: int) -> np.ndarray:
+    """Segment means, fp32, fold-halving order (PAA, Preliminaries)."""
+    z = _f32(z)
+    n, length = z.shape
+    if length % segments:
+        raise ValueError("length must be a multiple of segments")
+    out = np.empty((n, segments), dtype=np.float32)
+    _load().oracle_paa(z.ctypes.data, n, length, segments, out.ctypes.data)
+    return out
+
+
+def symbols(paa_values, card_bits: int) -> np.ndarray:
+    """iSAX word: number of breakpoints <= each PAA value (Preliminaries)."""
+    p = _f32(paa_values)
+    n, w = p.shape
+    bp = breakpoints(card_bits)
+    full = np.zeros(255, dtype=np.float32)
+    full[:bp.size] = bp
+    out = np.empty((n, w), dtype=np.uint8)
+    _load().oracle_symbols(p.ctypes.data, n, w, card_bits, full.ctypes.data, out.ctypes.data)
+    return out
+
+
+def words(z, segments: int, card_bits: int) -> np.ndarray:
+    return symbols(paa(z, segments), card_bits)
+
+
+def root_keys(words_, card_bits: int) -> np.ndarray:
+    wd = np.ascontiguousarray(words_, dtype=np.uint8)
+    n, w = wd.shape
+    out = np.empty(n, dtype=np.uint32)
+    _load().oracle_root_keys(wd.ctypes.data, n, w, card_bits, out.ctypes.data)
+    return out
+
+
+def build_leaves(words_, card_bits: int, leaf_cap: int):
+    """Leaf partition by the order-free top-down rule (TreeConstruction/SplitNode).
+
+    Returns (leaves structured array in depth-first order, pos uint32[n])."""
+    wd = np.ascontiguousarray(words_, dtype=np.uint8)
+    n, w = wd.shape
+    leaves = np.zeros(n, dtype=LEAF_DTYPE)
+    pos = np.zeros(n, dtype=np.uint32)
+    cnt = _load().oracle_build_leaves(wd.ctypes.data, n, w, card_bits, leaf_cap, leaves.ctypes.data,
+                                      pos.ctypes.data)
+    if cnt < 0:
+        raise ValueError("bad arguments to build_leaves")
+    return leaves[:cnt].copy(), pos
+
+
+def d64(q, x) -> float:
+    """Canonical squared ED: sequential fp64 sum, no fused multiply-add."""
+    q, x = _f32(q), _f32(x)
+    return _load().oracle_d64(q.ctypes.data, x.ctypes.data, q.size)
+
+
+def mindist_sq(qpaa, card, prefix, card_bits: int, m: int, slack: float = 0.0) -> float:
+    """iSAX MINDIST^2 of a (fp64) query PAA against a node region."""
+    qp = np.ascontiguousarray(qpaa, dtype=np.float64)
+    w = qp.size
+    c = np.zeros(16, dtype=np.uint8); c[:w] = card
+    p = np.zeros(16, dtype=np.uint8); p[:w] = prefix
+    bp = np.zeros(255, dtype=np.float32)
+    b = breakpoints(card_bits); bp[:b.size] = b
+    return _load().oracle_mindist_sq(qp.ctypes.data, w, m, c.ctypes.data, p.ctypes.data, card_bits,
+                                     bp.ctypes.data, float(slack))
+
+
+def knn_brute(data, queries, k: int, nthreads: int = 1, row_offset: int = 0):
+    """Exact k-NN by full scan: k smallest (D64, index), ascending.
+
+    Returns (idx int64[nq, k], d64 float64[nq, k], dist float32[nq, k] = fl32(sqrt(D64)))."""
+    data, queries = _f32(data), _f32(queries)
+    n, length = data.shape
+    nq = queries.shape[0]
+    idx = np.zeros((nq, k), dtype=np.int64)
+    dd = np.zeros((nq, k), dtype=np.float64)
+    rc = _load().oracle_knn_brute(data.ctypes.data, n, length, queries.ctypes.data, nq, k, int(nthreads),
+                                  int(row_offset), idx.ctypes.data, dd.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments to knn_brute")
+    return idx, dd, np.sqrt(dd).astype(np.float32)
+
+
+def knn_isax(data, words_, card_bits, leaves, pos, queries, k: int, return_stats=False):
+    """Plain iSAX exact search over the oracle's own index (must equal knn_brute)."""
+    data, queries = _f32(data), _f32(queries)
+    wd = np.ascontiguousarray(words_, dtype=np.uint8)
+    n, length = data.shape
+    w = wd.shape[1]
+    nq = queries.shape[0]
+    leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+    pos = np.ascontiguousarray(pos, dtype=np.uint32)
+    idx = np.zeros((nq, k), dtype=np.int64)
+    dd = np.zeros((nq, k), dtype=np.float64)
+    stats = np.zeros((nq, 4), dtype=np.int64)
+    rc = _load().oracle_knn_isax(data.ctypes.data, n, length, wd.ctypes.data, w, card_bits, leaves.ctypes.data,
+                                 leaves.size, pos.ctypes.data, queries.ctypes.data, nq, k, idx.ctypes.data,
+                                 dd.ctypes.data, stats.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments to knn_isax")
+    out = (idx, dd, np.sqrt(dd).astype(np.float32))
+    return out + (stats,) if return_stats else out
