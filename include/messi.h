@@ -1,0 +1,199 @@
+/*
+ * messi.h -- C ABI of an MI355X (gfx950) implementation of MESSI's data-parallel
+ * hot path: iSAX index construction and exact k-NN search under Euclidean
+ * distance (Peng, Fatourou, Palpanas, "MESSI: In-Memory Data Series Indexing",
+ * ICDE 2020).
+ *
+ * Problem (paper, Preliminaries, "Similarity Search"): given a collection of N
+ * series of one length L and a query of that length, find the series with the
+ * smallest Euclidean distance to the query.  This library returns the k
+ * smallest, ordered by (distance, series index): ties go to the lower index.
+ *
+ * Conventions
+ *  - Pointers named series / queries / out_* are DEVICE pointers (memory the
+ *    caller allocated on the GPU, e.g. with hipMalloc or a torch CUDA tensor)
+ *    unless the name says host_.  A host pointer where a device pointer is
+ *    required is rejected with MESSI_EINVAL.
+ *  - Series are fp32, row-major [n][len]; series i is the i-th row.
+ *  - Every call runs on the calling thread's current HIP device.  The
+ *    synchronous calls (messi_build, messi_knn, messi_znorm) return after the
+ *    device work has finished.
+ *  - Errors: functions returning int return MESSI_OK (0) or a negative
+ *    MESSI_E* code; functions returning a pointer return NULL on error.  In
+ *    both cases messi_last_error() gives the code and a message (per thread).
+ *    A MESSI_EDEVICE error leaves the index unusable: free it and rebuild.
+ */
+#ifndef MESSI_H
+#define MESSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MESSI_OK 0
+#define MESSI_EINVAL -1    /* bad argument: null/host pointer, sizes out of range, non-finite input */
+#define MESSI_ENOMEM -2    /* device allocation failed or the memory budget is exceeded */
+#define MESSI_EDEVICE -3   /* a HIP runtime call or kernel launch failed */
+#define MESSI_ENODEV -4    /* no usable GPU */
+#define MESSI_EBUSY -5     /* server has no free slot (non-blocking submit) */
+#define MESSI_EOVERFLOW -6 /* a query has more tied candidates than the candidate buffer holds */
+
+#define MESSI_MAX_SEGMENTS 16
+#define MESSI_MAX_LEN 1024
+#define MESSI_MAX_K 1024
+
+/* Search modes of messi_knn_ex. */
+#define MESSI_MODE_FP32 0        /* ordered leaf scan, fp32 early-abandoning squared ED */
+#define MESSI_MODE_BF16 1        /* batched BF16 matrix-core filter with a rounding bound, fp32 recheck */
+
+typedef struct messi_index messi_index;
+
+/* A leaf of the index: per segment i, the node's symbol prefix prefix[i] of
+ * card[i] bits (segments >= `segments` are 0), and the range
+ * [start, start + count) of the leaf's members in the position array. */
+typedef struct {
+    uint8_t card[16];
+    uint8_t prefix[16];
+    uint32_t start;
+    uint32_t count;
+} messi_leaf;
+
+typedef struct {
+    int32_t znorm;       /* 1: z-normalise `series` in place before summarising (see messi_znorm) */
+    int32_t bf16_shadow; /* 1: also keep a BF16 copy of every row, in leaf order, and fp32 squared
+                            norms; required by MESSI_MODE_BF16 (costs 2 * len bytes per series) */
+    void* stream;        /* hipStream_t for the build; NULL = the null stream */
+} messi_build_opts;
+
+typedef struct {
+    int64_t n;
+    int32_t len, segments, card_bits, leaf_cap;
+    int64_t n_leaves;
+    int64_t max_leaf;        /* largest leaf (> leaf_cap only for leaves of identical words) */
+    int32_t levels;          /* split levels the build ran */
+    int32_t has_bf16;
+    uint64_t device_bytes;   /* device memory the index owns */
+    float data_absmax;       /* max |x| over the collection (used for the bound's slack) */
+    double ms_znorm, ms_summarize, ms_bucket, ms_split, ms_finalize, ms_shadow, ms_total;
+} messi_info;
+
+/* Per-call counters and timings of messi_knn_ex (totals over the call's queries).
+ * Filled only when a non-NULL pointer is passed (counting adds device atomics). */
+typedef struct {
+    int64_t leaves_total;     /* n_leaves * nq */
+    int64_t leaves_kept;      /* (query, leaf) pairs whose bound did not exceed the first upper bound */
+    int64_t leaves_scanned;   /* pairs whose members were examined */
+    int64_t series_bounded;   /* per-series lower bounds computed */
+    int64_t series_distance;  /* fp32 distances (FP32 mode) or BF16 filter evaluations (BF16 mode) */
+    int64_t series_abandoned; /* fp32 distances stopped early */
+    int64_t series_recheck;   /* BF16 mode: compensated fp32 rechecks */
+    int64_t candidates;       /* canonical fp64 distances computed for the final order */
+    int64_t bytes_scan;       /* algorithmic HBM bytes of the scan kernels (words + rows read) */
+    double ms_total, ms_prep, ms_leaf_lb, ms_approx, ms_order, ms_scan, ms_final;
+    int32_t scan_launches;
+} messi_knn_stats;
+
+/* ---- index ------------------------------------------------------------- */
+
+/* Build the iSAX index of series[n][len] (paper: Index Construction, Algorithms
+ * CreateIndex, CalculateiSAXSummaries, TreeConstruction).  Per series: PAA over
+ * `segments` equal segments, an iSAX word of card_bits-bit symbols against
+ * N(0,1) breakpoints, the root child from the top bit of every symbol; then
+ * leaves of at most leaf_cap series by balanced binary splits (a leaf holds
+ * more only if all its series have the same full word).  `series` is used as
+ * given (call messi_znorm first for z-normalised data) and is BORROWED: it must
+ * stay valid and unchanged until messi_free.  Limits: 1 <= n < 2^32,
+ * 1 <= segments <= 16, len % segments == 0, len <= 1024, 1 <= card_bits <= 8,
+ * leaf_cap >= 1.  Non-finite values -> MESSI_EINVAL. */
+messi_index* messi_build(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
+                         int32_t leaf_cap);
+messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
+                            int32_t leaf_cap, const messi_build_opts* opts);
+
+/* Exact k-NN (paper: Query Answering, Algorithms ExactSearch .. CalculateRealDistance,
+ * generalised from 1 to k).  queries[nq][len] (device, fp32); out_idx[nq][k]
+ * (device, int64) and out_dist[nq][k] (device, fp32) receive, per query, the k
+ * series with the smallest (distance, index), ascending; distances are
+ * fl32(sqrt(D)), D the squared distance summed in fp64 in index order.
+ * 1 <= k <= min(n, 1024); nq == 0 is a no-op.  Synchronous. */
+int messi_knn(const messi_index* index, const float* queries, int32_t nq, int32_t k, int64_t* out_idx,
+              float* out_dist);
+
+/* Same, stream-ordered on `stream` (hipStream_t, NULL = null stream), with a
+ * search mode (MESSI_MODE_*) and optional counters.  The call returns after
+ * enqueueing only if stats == NULL; with stats it synchronises the stream.
+ * Concurrent calls on one index from different streams are allowed. */
+int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t mode,
+                 void* stream, int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
+
+void messi_free(messi_index* index); /* NULL-safe; synchronises the device */
+
+int messi_index_info(const messi_index* index, messi_info* out);
+
+/* Words in input order: host_words[n][segments], segment 0 first. */
+int messi_export_words(const messi_index* index, uint8_t* host_words);
+
+/* Leaves in depth-first order (root key ascending, bit 0 before bit 1) and the
+ * position array: host_leaves[n_leaves], host_pos[n]; leaf l's members are
+ * host_pos[start .. start + count), ascending series index. */
+int messi_export_leaves(const messi_index* index, messi_leaf* host_leaves, uint32_t* host_pos);
+
+/* ---- building blocks ---------------------------------------------------- */
+
+/* z-normalise series[n][len] in place (paper, Preliminaries: mean 0, standard
+ * deviation 1).  Mean and population variance in fp64, summed in fold-halving
+ * order (pad to a power of two with zeros, add the upper half onto the lower
+ * half until one value is left); z = fl32((x - mean) / sigma); sigma = 0 gives
+ * zeros.  Synchronous when stream == NULL, else stream-ordered. */
+int messi_znorm(float* series, int64_t n, int32_t len, void* stream);
+
+/* The iSAX breakpoints of card_bits bits: host_out[j - 1] = fl32(Phi^-1(j / 2^b)),
+ * j = 1 .. 2^b - 1.  Host-only; needs no GPU. */
+int messi_breakpoints(int32_t card_bits, float* host_out);
+
+/* Code and message of the calling thread's last error; returns the code. */
+int messi_last_error(char* buf, size_t len);
+
+/* ---- serving (continuous batching) -------------------------------------- */
+
+typedef struct messi_server messi_server;
+
+typedef struct {
+    uint64_t tag;        /* as submitted */
+    int32_t k;
+    int32_t status;      /* MESSI_OK or an error code */
+    double t_submit_ms;  /* server clock when submitted */
+    double t_done_ms;    /* server clock when the result was ready */
+    int64_t idx[MESSI_MAX_K];
+    float dist[MESSI_MAX_K];
+} messi_result;
+
+/* A request loop that keeps `index` on the device and answers exact k-NN
+ * queries with continuous batching: queries submitted while others run are
+ * admitted into free slots as soon as slots and device memory (budget_bytes)
+ * allow, and share batched launches with the queries already in flight.
+ * mode is MESSI_MODE_FP32 or MESSI_MODE_BF16.  The server owns a worker
+ * thread and its own stream. */
+messi_server* messi_server_create(const messi_index* index, size_t budget_bytes, int32_t max_slots, int32_t mode);
+
+/* Copy host_query[len] and enqueue it.  Non-blocking: returns MESSI_OK or
+ * MESSI_EINVAL (bad k). */
+int messi_server_submit(messi_server* server, const float* host_query, int32_t k, uint64_t tag);
+
+/* Move up to max_out finished results into out; returns how many (>= 0) or an error. */
+int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out);
+
+/* Milliseconds on the server clock (the one t_submit_ms / t_done_ms use). */
+double messi_server_clock_ms(const messi_server* server);
+
+/* Stop the worker (after finishing admitted queries) and free everything. */
+void messi_server_destroy(messi_server* server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MESSI_H */

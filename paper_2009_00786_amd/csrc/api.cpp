@@ -1,0 +1,241 @@
+// C ABI of the library (include/messi.h): argument checking, error state,
+// index lifecycle and host-side exports.  Device work lives in build.hip,
+// query.hip, bf16.hip and server.cpp.
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace messi {
+
+namespace {
+thread_local int t_code = MESSI_OK;
+thread_local std::string t_msg;
+}  // namespace
+
+void set_error(int code, const std::string& msg) {
+    t_code = code;
+    t_msg = msg;
+}
+void clear_error() {
+    t_code = MESSI_OK;
+    t_msg.clear();
+}
+int last_error_code() { return t_code; }
+
+int DevBuf::alloc(size_t n) {
+    release();
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        set_error(e == hipErrorOutOfMemory ? MESSI_ENOMEM : MESSI_EDEVICE,
+                  std::string("hipMalloc(") + std::to_string(n) + " bytes): " + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? MESSI_ENOMEM : MESSI_EDEVICE;
+    }
+    bytes = n;
+    return MESSI_OK;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+Index::~Index() {}
+
+bool is_device_pointer(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+int current_device_ok() {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        set_error(MESSI_ENODEV, "no HIP device available");
+        return MESSI_ENODEV;
+    }
+    return MESSI_OK;
+}
+
+static int fail(int code, const char* msg) {
+    set_error(code, msg);
+    return code;
+}
+
+}  // namespace messi
+
+using namespace messi;
+
+extern "C" {
+
+int messi_last_error(char* buf, size_t len) {
+    if (buf && len) {
+        std::snprintf(buf, len, "%s", t_msg.c_str());
+    }
+    return t_code;
+}
+
+int messi_breakpoints(int32_t card_bits, float* host_out) {
+    clear_error();
+    if (card_bits < 1 || card_bits > 8) return fail(MESSI_EINVAL, "card_bits must be in [1, 8]");
+    if (!host_out) return fail(MESSI_EINVAL, "host_out is null");
+    breakpoints_as241(card_bits, host_out);
+    return MESSI_OK;
+}
+
+static int check_series_args(const float* series, int64_t n, int32_t len) {
+    if (n < 1 || n >= (int64_t(1) << 32)) return fail(MESSI_EINVAL, "n must be in [1, 2^32)");
+    if (len < 1 || len > MESSI_MAX_LEN) return fail(MESSI_EINVAL, "len must be in [1, 1024]");
+    if (!series) return fail(MESSI_EINVAL, "series is null");
+    MESSI_TRY(current_device_ok());
+    if (!is_device_pointer(series)) return fail(MESSI_EINVAL, "series is not a device pointer");
+    return MESSI_OK;
+}
+
+int messi_znorm(float* series, int64_t n, int32_t len, void* stream) {
+    clear_error();
+    MESSI_TRY(check_series_args(series, n, len));
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf flag;
+    MESSI_TRY(flag.alloc(sizeof(int)));
+    MESSI_HIP_TRY(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    MESSI_TRY(znorm_device(series, n, len, s, flag.as<int>()));
+    int h = 0;
+    MESSI_HIP_TRY(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    if (h) return fail(MESSI_EINVAL, "series contain non-finite values");
+    return MESSI_OK;
+}
+
+messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
+                            int32_t leaf_cap, const messi_build_opts* opts) {
+    clear_error();
+    if (check_series_args(series, n, len) != MESSI_OK) return nullptr;
+    if (segments < 1 || segments > MESSI_MAX_SEGMENTS) {
+        fail(MESSI_EINVAL, "segments must be in [1, 16]");
+        return nullptr;
+    }
+    if (len % segments != 0) {
+        fail(MESSI_EINVAL, "len must be a multiple of segments");
+        return nullptr;
+    }
+    if (card_bits < 1 || card_bits > 8) {
+        fail(MESSI_EINVAL, "card_bits must be in [1, 8]");
+        return nullptr;
+    }
+    if (leaf_cap < 1) {
+        fail(MESSI_EINVAL, "leaf_cap must be >= 1");
+        return nullptr;
+    }
+    messi_build_opts o{};
+    if (opts) o = *opts;
+    Index* ix = new Index();
+    if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
+    int rc = build_index(ix, series, n, len, segments, card_bits, leaf_cap, o);
+    if (rc == MESSI_OK && o.bf16_shadow) rc = build_bf16_shadow(ix, (hipStream_t)o.stream);
+    if (rc != MESSI_OK) {
+        const int code = t_code;
+        const std::string msg = t_msg;
+        (void)hipDeviceSynchronize();
+        delete ix;
+        set_error(code, msg);
+        return nullptr;
+    }
+    messi_info& in = ix->info;
+    in.n = n;
+    in.len = len;
+    in.segments = segments;
+    in.card_bits = card_bits;
+    in.leaf_cap = leaf_cap;
+    in.n_leaves = ix->n_leaves;
+    in.max_leaf = ix->max_leaf;
+    in.levels = ix->levels;
+    in.has_bf16 = ix->shadow.p != nullptr;
+    in.device_bytes = ix->device_bytes();
+    in.data_absmax = ix->absmax;
+    return reinterpret_cast<messi_index*>(ix);
+}
+
+messi_index* messi_build(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
+                         int32_t leaf_cap) {
+    return messi_build_ex(series, n, len, segments, card_bits, leaf_cap, nullptr);
+}
+
+void messi_free(messi_index* index) {
+    if (!index) return;
+    Index* ix = reinterpret_cast<Index*>(index);
+    (void)hipDeviceSynchronize();
+    release_workspaces(ix);
+    release_bf16(ix);
+    delete ix;
+}
+
+int messi_index_info(const messi_index* index, messi_info* out) {
+    clear_error();
+    if (!index || !out) return fail(MESSI_EINVAL, "null argument");
+    *out = reinterpret_cast<const Index*>(index)->info;
+    return MESSI_OK;
+}
+
+int messi_export_words(const messi_index* index, uint8_t* host_words) {
+    clear_error();
+    if (!index || !host_words) return fail(MESSI_EINVAL, "null argument");
+    const Index* ix = reinterpret_cast<const Index*>(index);
+    std::vector<uint8_t> w(16 * (size_t)ix->n);
+    std::vector<uint32_t> p((size_t)ix->n);
+    MESSI_HIP_TRY(hipMemcpy(w.data(), ix->words.p, w.size(), hipMemcpyDeviceToHost));
+    MESSI_HIP_TRY(hipMemcpy(p.data(), ix->pos.p, sizeof(uint32_t) * p.size(), hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < ix->n; ++j)
+        std::memcpy(host_words + (size_t)p[j] * ix->w, &w[16 * (size_t)j], (size_t)ix->w);
+    return MESSI_OK;
+}
+
+int messi_export_leaves(const messi_index* index, messi_leaf* host_leaves, uint32_t* host_pos) {
+    clear_error();
+    if (!index || !host_leaves || !host_pos) return fail(MESSI_EINVAL, "null argument");
+    const Index* ix = reinterpret_cast<const Index*>(index);
+    static_assert(sizeof(messi_leaf) == sizeof(Leaf), "leaf layout");
+    MESSI_HIP_TRY(hipMemcpy(host_leaves, ix->leaves.p, sizeof(Leaf) * (size_t)ix->n_leaves, hipMemcpyDeviceToHost));
+    MESSI_HIP_TRY(hipMemcpy(host_pos, ix->pos.p, sizeof(uint32_t) * (size_t)ix->n, hipMemcpyDeviceToHost));
+    return MESSI_OK;
+}
+
+int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t mode, void* stream,
+                 int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    clear_error();
+    if (!index) return fail(MESSI_EINVAL, "index is null");
+    const Index* ix = reinterpret_cast<const Index*>(index);
+    if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
+    if (k < 1 || k > MESSI_MAX_K || (int64_t)k > ix->n) return fail(MESSI_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16) return fail(MESSI_EINVAL, "unknown mode");
+    if (mode == MESSI_MODE_BF16 && !ix->shadow.p)
+        return fail(MESSI_EINVAL, "BF16 mode needs an index built with bf16_shadow = 1");
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (nq == 0) return MESSI_OK;
+    if (!queries || !out_idx || !out_dist) return fail(MESSI_EINVAL, "null pointer argument");
+    if (!is_device_pointer(queries) || !is_device_pointer(out_idx) || !is_device_pointer(out_dist))
+        return fail(MESSI_EINVAL, "queries / out_idx / out_dist must be device pointers");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ix->device)
+        return fail(MESSI_EINVAL, "the index lives on another device");
+    if (mode == MESSI_MODE_BF16) return knn_bf16(ix, queries, nq, k, (hipStream_t)stream, out_idx, out_dist, stats);
+    return knn_device(ix, queries, nq, k, mode, (hipStream_t)stream, out_idx, out_dist, stats);
+}
+
+int messi_knn(const messi_index* index, const float* queries, int32_t nq, int32_t k, int64_t* out_idx,
+              float* out_dist) {
+    return messi_knn_ex(index, queries, nq, k, MESSI_MODE_FP32, nullptr, out_idx, out_dist, nullptr);
+}
+
+}  // extern "C"

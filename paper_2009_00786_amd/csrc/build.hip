@@ -1,0 +1,912 @@
+// Index construction on gfx950 (paper: Index Construction -- CalculateiSAXSummaries,
+// then TreeConstruction / SplitNode), re-planned for a GPU:
+//
+//  1. summarise: one wave streams a 1 KB row (float4 per lane) and produces the
+//     row's iSAX word and root key; z-normalisation can be fused into the same
+//     pass (fp64 statistics).                                      HBM-bound.
+//  2. bucket by root key: stable LSD radix sort of (key, word, pos), 8-bit
+//     digits, per-tile histograms + device scan + stable scatter ranked with
+//     wave ballots.  Its output is the paper's iSAX buffers, one contiguous run
+//     per root child.
+//  3. split levels: every node over capacity counts, per refinable segment,
+//     the members whose next symbol bit is 1 (tiles of 4096 members, LDS
+//     reduction, one atomic per tile and segment), picks the most balanced
+//     segment, and stable-partitions its range into the 0 and 1 children
+//     (ballot ranks + device scan).  A node's range is split in place, so the
+//     final member order is the depth-first leaf order with members in
+//     ascending series index -- the canonical layout.
+//  4. finalise: ranges that ended in the second buffer are copied back, and
+//     the leaf records are ordered by start through a bitmap rank.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+#include "scan.h"
+
+namespace messi {
+namespace {
+
+constexpr int kTile = 4096;
+constexpr int kBlk = 256;
+constexpr int kRounds = kTile / kBlk;
+
+// ---------------------------------------------------------------------------
+// Fold-halving sums across the lanes of one series group (width T lanes, E
+// consecutive elements per lane): pairs (i, i + h) for h = P/2 .. 1.  Strides
+// of at least E elements are lane offsets h/E; smaller strides are inside the
+// lane.  The full sum ends in the group's first lane, element 0.
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ __forceinline__ double fold_halving64(double (&v)[E], int T) {
+    for (int off = T >> 1; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) v[k] = __dadd_rn(v[k], __shfl_down(v[k], off, T));
+    }
+#pragma unroll
+    for (int h = E >> 1; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int k = 0; k < h; ++k) v[k] = __dadd_rn(v[k], v[k + h]);
+    }
+    return v[0];
+}
+
+struct SumArgs {
+    const float* in;
+    float* zout;          // z-normalised rows (may equal in); null when not normalising
+    int64_t n;
+    int32_t L, P, T, G;   // length, padded length, lanes per series, series per wave
+    int32_t w, m, M, b;   // segments, segment length, padded segment length, bits
+    const float* bp;      // 2^b - 1 breakpoints
+    uint4* words;         // [n] input order
+    uint16_t* keys;       // [n]
+    uint32_t* absmax;     // float bits, atomicMax
+    int* nonfinite;
+};
+
+// One kernel for: z-normalise only (SUM = false), summarise only (ZN = false),
+// or both fused (read once, write z once).
+template <int E, bool ZN, bool SUM>
+__global__ void __launch_bounds__(256) summarize_kernel(SumArgs a) {
+    __shared__ float s_bp[256];
+    __shared__ float s_row[4][64 * E];     // general PAA path: z values of the wave's series
+    __shared__ uint8_t s_sym[4][64 * 16];  // symbols of the wave's series
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (SUM) {
+        const int nb = (1 << a.b) - 1;
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) s_bp[i] = (i < nb) ? a.bp[i] : 0.f;
+        __syncthreads();
+    }
+    const int T = a.T, G = a.G, L = a.L;
+    const int g = lane / T, t = lane % T;
+    const bool fast_paa = SUM && ((a.m & (a.m - 1)) == 0) && (a.m % E == 0) && (L == a.P);
+    const bool vec = (L == a.P) && (E % 4 == 0);
+    const int64_t n_groups = (a.n + G - 1) / G;
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    float amax = 0.f;
+    bool bad = false;
+    for (int64_t grp = wave_id; grp < n_groups; grp += n_waves) {
+        const int64_t row = grp * G + g;
+        const bool live = row < a.n;
+        float x[E];
+        const float* src = a.in + (size_t)(live ? row : 0) * (size_t)L;
+        if (vec) {
+#pragma unroll
+            for (int k = 0; k < E; k += 4) {
+                float4 q = live ? *reinterpret_cast<const float4*>(src + t * E + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+                x[k] = q.x; x[k + 1] = q.y; x[k + 2] = q.z; x[k + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int j = t * E + k;
+                x[k] = (live && j < L) ? src[j] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) bad |= !isfinite(x[k]);
+        if (ZN) {
+            double v[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) v[k] = (double)x[k];
+            double s1 = fold_halving64<E>(v, T);
+            s1 = __shfl(s1, g * T, 64);
+            const double mu = __ddiv_rn(s1, (double)L);
+            double c[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int j = t * E + k;
+                c[k] = (j < L) ? __dsub_rn((double)x[k], mu) : 0.0;
+                v[k] = (j < L) ? __dmul_rn(c[k], c[k]) : 0.0;
+            }
+            double s2 = fold_halving64<E>(v, T);
+            s2 = __shfl(s2, g * T, 64);
+            const double var = __ddiv_rn(s2, (double)L);
+            const double sigma = __dsqrt_rn(var);
+#pragma unroll
+            for (int k = 0; k < E; ++k) x[k] = (var == 0.0) ? 0.f : (float)__ddiv_rn(c[k], sigma);
+            if (live) {
+                float* dst = a.zout + (size_t)row * (size_t)L;
+                if (vec) {
+#pragma unroll
+                    for (int k = 0; k < E; k += 4)
+                        *reinterpret_cast<float4*>(dst + t * E + k) = make_float4(x[k], x[k + 1], x[k + 2], x[k + 3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < E; ++k)
+                        if (t * E + k < L) dst[t * E + k] = x[k];
+                }
+            }
+        }
+        if (!SUM) continue;
+#pragma unroll
+        for (int k = 0; k < E; ++k) amax = fmaxf(amax, live ? fabsf(x[k]) : 0.f);
+
+        // ---- PAA: fold-halving sum of each segment, then one division by m.
+        const int w = a.w, m = a.m;
+        const float inv_m_exact = 1.0f / (float)m;  // used only when m is a power of two
+        if (fast_paa) {
+            float v[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) v[k] = x[k];
+            const int seg_lanes = m / E;
+            for (int off = seg_lanes >> 1; off >= 1; off >>= 1) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) v[k] = __fadd_rn(v[k], __shfl_down(v[k], off, T));
+            }
+#pragma unroll
+            for (int h = E >> 1; h >= 1; h >>= 1) {
+#pragma unroll
+                for (int k = 0; k < h; ++k) v[k] = __fadd_rn(v[k], v[k + h]);
+            }
+            // lane t holds segment t / seg_lanes when t % seg_lanes == 0
+            if (t % seg_lanes == 0) {
+                const int seg = t / seg_lanes;
+                const float p = __fmul_rn(v[0], inv_m_exact);
+                int s = 0;
+                for (int step = 1 << (a.b - 1); step >= 1; step >>= 1)
+                    if (s_bp[s + step - 1] <= p) s += step;
+                s_sym[wave][g * 16 + seg] = (uint8_t)s;
+            }
+        } else {
+            // general path: z values to LDS, one lane per (series, segment) sums the
+            // padded segment by fold-halving (pairwise over bit-reversed order).
+#pragma unroll
+            for (int k = 0; k < E; ++k) s_row[wave][g * a.P + t * E + k] = x[k];
+            dev::wave_sync();
+            for (int p = lane; p < G * w; p += 64) {
+                const int gg = p / w, seg = p % w;
+                const float* z = &s_row[wave][gg * a.P + seg * m];
+                // binary-counter pairwise sum over indices in bit-reversed order
+                float stack[11];
+                int depth = 0;
+                int lg = 0;
+                while ((1 << lg) < a.M) ++lg;
+                for (int r = 0; r < a.M; ++r) {
+                    int j = 0;
+                    for (int bit = 0; bit < lg; ++bit) j |= ((r >> bit) & 1) << (lg - 1 - bit);
+                    float val = (j < m) ? z[j] : 0.f;
+                    int cnt = r + 1;
+                    // merge while the count's low bits are zero
+                    stack[depth++] = val;
+                    while ((cnt & 1) == 0) {
+                        float hi = stack[--depth];
+                        float lo = stack[--depth];
+                        stack[depth++] = __fadd_rn(lo, hi);
+                        cnt >>= 1;
+                    }
+                }
+                const float sum = stack[0];
+                const float pval = __fdiv_rn(sum, (float)m);
+                int s = 0;
+                for (int step = 1 << (a.b - 1); step >= 1; step >>= 1)
+                    if (s_bp[s + step - 1] <= pval) s += step;
+                s_sym[wave][gg * 16 + seg] = (uint8_t)s;
+            }
+        }
+        dev::wave_sync();
+        // ---- word + root key: one lane per series
+        if (lane < G) {
+            const int64_t r2 = grp * G + lane;
+            if (r2 < a.n) {
+                uint32_t wd[4] = {0u, 0u, 0u, 0u};
+                uint32_t key = 0;
+                for (int i = 0; i < w; ++i) {
+                    const uint32_t s = s_sym[wave][lane * 16 + i];
+                    wd[i >> 2] |= s << (8 * (i & 3));
+                    key |= ((s >> (a.b - 1)) & 1u) << (w - 1 - i);
+                }
+                a.words[r2] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                a.keys[r2] = (uint16_t)key;
+            }
+        }
+        dev::wave_sync();
+    }
+    if (bad) atomicOr(a.nonfinite, 1);
+    if (SUM) {
+        amax = dev::wave_max(amax);
+        if (lane == 0) atomicMax(a.absmax, __float_as_uint(amax));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix pass over (key, word, pos), 8-bit digit at `shift`.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlk) radix_hist_kernel(const uint16_t* __restrict__ keys, int64_t n, int shift,
+                                                          uint32_t* __restrict__ hist, int64_t n_tiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t i = base + (int64_t)r * kBlk + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBlk) radix_scatter_kernel(const uint16_t* __restrict__ kin,
+                                                             const uint4* __restrict__ win,
+                                                             const uint32_t* __restrict__ pin, int64_t n, int shift,
+                                                             const uint32_t* __restrict__ offs, int64_t n_tiles,
+                                                             uint16_t* __restrict__ kout, uint4* __restrict__ wout,
+                                                             uint32_t* __restrict__ pout) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t woff[4][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    base[tid] = offs[(int64_t)tid * n_tiles + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+    uint32_t run = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kTile;
+    const uint64_t lt = dev::lanemask_lt();
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t i = t0 + (int64_t)r * kBlk + tid;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = dev::ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t m = dev::ballot(valid && on);
+            peers &= on ? m : ~m;
+        }
+        const int rank = dev::popc64(peers & lt);
+        if (valid && (peers & lt) == 0) wcnt[wave][d] = (uint32_t)dev::popc64(peers);
+        __syncthreads();
+        uint32_t acc = run;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t c = wcnt[w][tid];
+            woff[w][tid] = acc;
+            acc += c;
+            wcnt[w][tid] = 0;
+        }
+        run = acc;
+        __syncthreads();
+        if (valid) {
+            const uint32_t dst = base[d] + woff[wave][d] + (uint32_t)rank;
+            if (dst >= (uint64_t)n) continue;  // cannot happen with consistent offsets
+            kout[dst] = (uint16_t)key;
+            wout[dst] = win[i];
+            pout[dst] = pin ? pin[i] : (uint32_t)i;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Root children: runs of equal keys in the sorted key array.
+// ---------------------------------------------------------------------------
+__global__ void root_runs_kernel(const uint16_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ run_start,
+                                 uint32_t* __restrict__ run_end) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) run_start[k] = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) run_end[k] = (uint32_t)i + 1;
+}
+
+struct Lists {
+    Leaf* leaves;
+    uint8_t* leaf_buf;
+    uint32_t* n_leaves;  // counter
+    Leaf* next;
+    uint32_t* n_next;    // counter
+    uint32_t* max_leaf;
+};
+
+__device__ void emit_child(const Leaf& c, int w, int b, int cap, int buf, Lists L) {
+    if (c.count == 0) return;
+    bool refinable = false;
+    for (int i = 0; i < w; ++i) refinable |= c.card[i] < b;
+    if (c.count <= (uint32_t)cap || !refinable) {
+        const uint32_t id = atomicAdd(L.n_leaves, 1u);
+        L.leaves[id] = c;
+        L.leaf_buf[id] = (uint8_t)buf;
+        atomicMax(L.max_leaf, c.count);
+    } else {
+        const uint32_t id = atomicAdd(L.n_next, 1u);
+        L.next[id] = c;
+    }
+}
+
+__global__ void root_nodes_kernel(const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_end,
+                                  int w, int b, int cap, int buf, Lists L) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (1u << w)) return;
+    const uint32_t e = run_end[k];
+    if (e == 0) return;
+    Leaf c;
+    for (int i = 0; i < 16; ++i) {
+        c.card[i] = (i < w) ? 1 : 0;
+        c.prefix[i] = (i < w) ? (uint8_t)((k >> (w - 1 - i)) & 1u) : 0;
+    }
+    c.start = run_start[k];
+    c.count = e - run_start[k];
+    emit_child(c, w, b, cap, buf, L);
+}
+
+// ---------------------------------------------------------------------------
+// Split levels.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) node_tiles_kernel(const Leaf* __restrict__ nodes, int n_nodes,
+                                                          uint32_t* __restrict__ tile_first,
+                                                          uint32_t* __restrict__ total) {
+    __shared__ uint32_t wt[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int per = (n_nodes + 1023) / 1024;
+    const int b0 = t * per;
+    uint32_t acc = 0;
+    for (int i = b0; i < b0 + per && i < n_nodes; ++i) acc += (nodes[i].count + kTile - 1) / kTile;
+    uint32_t x = acc;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wt[wave] = x;
+    __syncthreads();
+    uint32_t wo = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) wo += wt[w];
+        tot += wt[w];
+    }
+    uint32_t run = wo + x - acc;
+    for (int i = b0; i < b0 + per && i < n_nodes; ++i) {
+        tile_first[i] = run;
+        run += (nodes[i].count + kTile - 1) / kTile;
+    }
+    if (t == 0) {
+        tile_first[n_nodes] = tot;
+        *total = tot;
+    }
+}
+
+__global__ void tile_node_kernel(const uint32_t* __restrict__ tile_first, int n_nodes, uint32_t n_tiles,
+                                 uint32_t* __restrict__ tile_node) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    int lo = 0, hi = n_nodes - 1;  // last node with tile_first <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_first[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    tile_node[t] = (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint32_t word_byte(const uint4& wd, int i) {
+    const uint32_t v = (i < 4) ? wd.x : (i < 8) ? wd.y : (i < 12) ? wd.z : wd.w;
+    return (v >> (8 * (i & 3))) & 0xFFu;
+}
+
+__global__ void __launch_bounds__(kBlk) level_count_kernel(const Leaf* __restrict__ nodes,
+                                                           const uint32_t* __restrict__ tile_first,
+                                                           const uint32_t* __restrict__ tile_node,
+                                                           const uint4* __restrict__ words, int w, int b,
+                                                           uint32_t* __restrict__ tile_cnt,
+                                                           uint32_t* __restrict__ node_cnt) {
+    __shared__ uint32_t part[4][16];
+    const int tile = blockIdx.x;
+    const uint32_t nd = tile_node[tile];
+    const Leaf node = nodes[nd];
+    const uint32_t start = node.start + (tile - tile_first[nd]) * kTile;
+    const uint32_t end = min(start + (uint32_t)kTile, node.start + node.count);
+    int shift[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) shift[i] = (i < w && node.card[i] < b) ? (b - 1 - node.card[i]) : -1;
+    uint32_t cnt[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) cnt[i] = 0;
+    for (uint32_t j = start + threadIdx.x; j < end; j += kBlk) {
+        const uint4 wd = words[j];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (shift[i] >= 0) cnt[i] += (word_byte(wd, i) >> shift[i]) & 1u;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t s = dev::wave_sum_u32(cnt[i]);
+        if (lane == 0) part[wave][i] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        const int i = threadIdx.x;
+        const uint32_t s = part[0][i] + part[1][i] + part[2][i] + part[3][i];
+        tile_cnt[(size_t)tile * 16 + i] = s;
+        if (shift[i] >= 0 && s) atomicAdd(&node_cnt[(size_t)nd * 16 + i], s);
+    }
+}
+
+__global__ void level_choose_kernel(const Leaf* __restrict__ nodes, int n_nodes, const uint32_t* __restrict__ node_cnt,
+                                    int w, int b, int cap, int dst_buf, uint8_t* __restrict__ node_seg,
+                                    uint32_t* __restrict__ node_n0, Lists L) {
+    const int nd = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nd >= n_nodes) return;
+    const Leaf node = nodes[nd];
+    int best = -1;
+    uint32_t best_gap = 0, best_n1 = 0;
+    for (int i = 0; i < w; ++i) {
+        if (node.card[i] >= b) continue;
+        const uint32_t n1 = node_cnt[(size_t)nd * 16 + i];
+        const uint32_t n0 = node.count - n1;
+        const uint32_t gap = n0 > n1 ? n0 - n1 : n1 - n0;
+        if (best < 0 || gap < best_gap) {
+            best = i;
+            best_gap = gap;
+            best_n1 = n1;
+        }
+    }
+    if (best < 0) {  // nodes on the list always have a refinable segment; keep the node whole
+        node_seg[nd] = 0;
+        node_n0[nd] = node.count;
+        emit_child(node, w, b, 0x7fffffff, dst_buf, L);
+        return;
+    }
+    const uint32_t n0 = node.count - best_n1;
+    node_seg[nd] = (uint8_t)best;
+    node_n0[nd] = n0;
+    Leaf c0 = node, c1 = node;
+    c0.card[best] = c1.card[best] = (uint8_t)(node.card[best] + 1);
+    c0.prefix[best] = (uint8_t)(node.prefix[best] * 2);
+    c1.prefix[best] = (uint8_t)(node.prefix[best] * 2 + 1);
+    c0.count = n0;
+    c1.start = node.start + n0;
+    c1.count = best_n1;
+    emit_child(c0, w, b, cap, dst_buf, L);
+    emit_child(c1, w, b, cap, dst_buf, L);
+}
+
+__global__ void level_zeros_kernel(const Leaf* __restrict__ nodes, const uint32_t* __restrict__ tile_first,
+                                   const uint32_t* __restrict__ tile_node, uint32_t n_tiles,
+                                   const uint32_t* __restrict__ tile_cnt, const uint8_t* __restrict__ node_seg,
+                                   uint32_t* __restrict__ zeros) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t nd = tile_node[t];
+    const Leaf node = nodes[nd];
+    const uint32_t start = node.start + (t - tile_first[nd]) * kTile;
+    const uint32_t end = min(start + (uint32_t)kTile, node.start + node.count);
+    zeros[t] = (end - start) - tile_cnt[(size_t)t * 16 + node_seg[nd]];
+}
+
+__global__ void __launch_bounds__(kBlk) level_scatter_kernel(const Leaf* __restrict__ nodes,
+                                                             const uint32_t* __restrict__ tile_first,
+                                                             const uint32_t* __restrict__ tile_node,
+                                                             const uint32_t* __restrict__ zscan,
+                                                             const uint8_t* __restrict__ node_seg,
+                                                             const uint32_t* __restrict__ node_n0, int b,
+                                                             const uint4* __restrict__ win,
+                                                             const uint32_t* __restrict__ pin,
+                                                             uint4* __restrict__ wout, uint32_t* __restrict__ pout) {
+    __shared__ uint32_t c0[4], c1[4];
+    const int tile = blockIdx.x;
+    const uint32_t nd = tile_node[tile];
+    const Leaf node = nodes[nd];
+    const uint32_t ft = tile_first[nd];
+    const uint32_t start = node.start + (tile - ft) * kTile;
+    const uint32_t end = min(start + (uint32_t)kTile, node.start + node.count);
+    const int seg = node_seg[nd];
+    const int shift = b - 1 - node.card[seg];
+    const uint32_t zb = zscan[tile] - zscan[ft];           // zeros before this tile in the node
+    const uint32_t ob = (tile - ft) * kTile - zb;          // ones before
+    uint32_t base0 = node.start + zb;
+    uint32_t base1 = node.start + node_n0[nd] + ob;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt = dev::lanemask_lt();
+    for (uint32_t r0 = start; r0 < end; r0 += kBlk) {
+        const uint32_t j = r0 + threadIdx.x;
+        const bool valid = j < end;
+        uint4 wd = make_uint4(0, 0, 0, 0);
+        uint32_t p = 0;
+        if (valid) {
+            wd = win[j];
+            p = pin[j];
+        }
+        const bool one = valid && ((word_byte(wd, seg) >> shift) & 1u);
+        const uint64_t m1 = dev::ballot(one);
+        const uint64_t m0 = dev::ballot(valid && !one);
+        if (lane == 0) {
+            c1[wave] = (uint32_t)dev::popc64(m1);
+            c0[wave] = (uint32_t)dev::popc64(m0);
+        }
+        __syncthreads();
+        uint32_t b0w = 0, b1w = 0, t0 = 0, t1 = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (w < wave) {
+                b0w += c0[w];
+                b1w += c1[w];
+            }
+            t0 += c0[w];
+            t1 += c1[w];
+        }
+        if (valid) {
+            const uint32_t dst = one ? base1 + b1w + (uint32_t)dev::popc64(m1 & lt)
+                                     : base0 + b0w + (uint32_t)dev::popc64(m0 & lt);
+            if (dst >= node.start && dst < node.start + node.count) {  // always true for consistent counts
+                wout[dst] = wd;
+                pout[dst] = p;
+            }
+        }
+        base0 += t0;
+        base1 += t1;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalise.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlk) copy_back_kernel(const Leaf* __restrict__ leaves,
+                                                         const uint8_t* __restrict__ leaf_buf, uint32_t n_leaves,
+                                                         const uint4* __restrict__ wsrc,
+                                                         const uint32_t* __restrict__ psrc, uint4* __restrict__ wdst,
+                                                         uint32_t* __restrict__ pdst, int src_buf) {
+    for (uint32_t l = blockIdx.x; l < n_leaves; l += gridDim.x) {
+        if (leaf_buf[l] != src_buf) continue;
+        const Leaf lf = leaves[l];
+        for (uint32_t j = lf.start + threadIdx.x; j < lf.start + lf.count; j += kBlk) {
+            wdst[j] = wsrc[j];
+            pdst[j] = psrc[j];
+        }
+    }
+}
+
+__global__ void leaf_bitmap_kernel(const Leaf* __restrict__ leaves, uint32_t n_leaves, uint32_t* __restrict__ bm) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_leaves) return;
+    const uint32_t s = leaves[l].start;
+    atomicOr(&bm[s >> 5], 1u << (s & 31));
+}
+
+__global__ void popc_kernel(const uint32_t* __restrict__ bm, int64_t nw, uint32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) cnt[i] = __popc(bm[i]);
+}
+
+__global__ void leaf_order_kernel(const Leaf* __restrict__ leaves, uint32_t n_leaves, const uint32_t* __restrict__ bm,
+                                  const uint32_t* __restrict__ rank_scan, Leaf* __restrict__ out) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_leaves) return;
+    const Leaf lf = leaves[l];
+    const uint32_t s = lf.start;
+    const uint32_t below = (s & 31) ? (bm[s >> 5] & ((1u << (s & 31)) - 1u)) : 0u;
+    const uint32_t r = rank_scan[s >> 5] + __popc(below);
+    if (r < n_leaves) out[r] = lf;
+}
+
+int launch_blocks(int64_t work, int per_block, int cap_blocks) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap_blocks) b = cap_blocks;
+    return (int)b;
+}
+
+// Lane layout of a row: E consecutive elements per lane, T lanes per series.
+struct RowLayout {
+    int P, E, T, G;
+};
+
+RowLayout row_layout(int L) {
+    RowLayout r;
+    r.P = 1;
+    while (r.P < L) r.P <<= 1;
+    r.E = std::min(r.P, std::max(4, r.P / 64));
+    r.T = r.P / r.E;
+    r.G = 64 / r.T;
+    return r;
+}
+
+template <bool ZN, bool SUM>
+int launch_summarize(const SumArgs& a, int E, hipStream_t s) {
+    const int64_t n_groups = (a.n + a.G - 1) / a.G;
+    const int blocks = launch_blocks(n_groups, 4, 256 * 16);
+    switch (E) {
+#define MESSI_SUM_CASE(EE)                                                                          \
+    case EE:                                                                                        \
+        hipLaunchKernelGGL((summarize_kernel<EE, ZN, SUM>), dim3(blocks), dim3(256), 0, s, a);      \
+        break;
+        MESSI_SUM_CASE(1)
+        MESSI_SUM_CASE(2)
+        MESSI_SUM_CASE(4)
+        MESSI_SUM_CASE(8)
+        MESSI_SUM_CASE(16)
+#undef MESSI_SUM_CASE
+        default:
+            set_error(MESSI_EINVAL, "unsupported series length");
+            return MESSI_EINVAL;
+    }
+    MESSI_LAUNCH_CHECK("summarize");
+    return MESSI_OK;
+}
+
+struct Timer {
+    hipStream_t s;
+    hipEvent_t e[2];
+    bool ok = false;
+    explicit Timer(hipStream_t st) : s(st) {
+        ok = hipEventCreate(&e[0]) == hipSuccess && hipEventCreate(&e[1]) == hipSuccess;
+    }
+    void start() { if (ok) (void)hipEventRecord(e[0], s); }
+    double stop_ms() {
+        if (!ok) return 0.0;
+        float ms = 0.f;
+        if (hipEventRecord(e[1], s) != hipSuccess || hipEventSynchronize(e[1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess)
+            return 0.0;
+        return ms;
+    }
+    ~Timer() {
+        if (ok) {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_flag) {
+    RowLayout r = row_layout(len);
+    SumArgs a{};
+    a.in = series;
+    a.zout = series;
+    a.n = n;
+    a.L = len;
+    a.P = r.P;
+    a.T = r.T;
+    a.G = r.G;
+    a.nonfinite = d_flag;
+    return launch_summarize<true, false>(a, r.E, s);
+}
+
+int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t w, int32_t b, int32_t cap,
+                const messi_build_opts& opts) {
+    hipStream_t s = (hipStream_t)opts.stream;
+    ix->series = series;
+    ix->n = n;
+    ix->len = len;
+    ix->w = w;
+    ix->b = b;
+    ix->cap = cap;
+    breakpoints_as241(b, ix->bp_host);
+    const int nb = (1 << b) - 1;
+    MESSI_TRY(ix->bp.alloc(sizeof(float) * 256));
+    MESSI_HIP_TRY(hipMemcpyAsync(ix->bp.p, ix->bp_host, sizeof(float) * nb, hipMemcpyHostToDevice, s));
+
+    const auto t_begin = std::chrono::steady_clock::now();
+    Timer tm(s);
+
+    // ---- buffers
+    DevBuf W[2], P[2], K[2], misc;
+    for (int i = 0; i < 2; ++i) {
+        MESSI_TRY(W[i].alloc(sizeof(uint4) * (size_t)n));
+        MESSI_TRY(P[i].alloc(sizeof(uint32_t) * (size_t)n));
+        MESSI_TRY(K[i].alloc(sizeof(uint16_t) * (size_t)n));
+    }
+    // misc: [0] nonfinite, [1] absmax bits, [2] n_leaves, [3] n_next, [4] max_leaf, [5] total tiles
+    MESSI_TRY(misc.alloc(64));
+    uint32_t* cnt = misc.as<uint32_t>();
+    MESSI_HIP_TRY(hipMemsetAsync(misc.p, 0, 64, s));
+
+    // ---- 1. summarise (optionally fused with z-normalisation)
+    RowLayout r = row_layout(len);
+    SumArgs a{};
+    a.in = series;
+    a.zout = opts.znorm ? const_cast<float*>(series) : nullptr;
+    a.n = n;
+    a.L = len;
+    a.P = r.P;
+    a.T = r.T;
+    a.G = r.G;
+    a.w = w;
+    a.m = len / w;
+    a.M = 1;
+    while (a.M < a.m) a.M <<= 1;
+    a.b = b;
+    a.bp = ix->bp.as<float>();
+    a.words = W[0].as<uint4>();
+    a.keys = K[0].as<uint16_t>();
+    a.absmax = cnt + 1;
+    a.nonfinite = reinterpret_cast<int*>(cnt + 0);
+    tm.start();
+    if (opts.znorm)
+        MESSI_TRY((launch_summarize<true, true>(a, r.E, s)));
+    else
+        MESSI_TRY((launch_summarize<false, true>(a, r.E, s)));
+    ix->info.ms_summarize = tm.stop_ms();
+    uint32_t flags[2];
+    MESSI_HIP_TRY(hipMemcpyAsync(flags, cnt, sizeof(flags), hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    if (flags[0]) {
+        set_error(MESSI_EINVAL, "series contain non-finite values");
+        return MESSI_EINVAL;
+    }
+    memcpy(&ix->absmax, &flags[1], sizeof(float));
+
+    // ---- 2. bucket by root key (stable LSD radix, 8-bit digits)
+    tm.start();
+    const int64_t n_tiles = (n + kTile - 1) / kTile;
+    DevBuf hist, scr;
+    MESSI_TRY(hist.alloc(sizeof(uint32_t) * 256 * (size_t)n_tiles));
+    int cur = 0;
+    const int passes = (w + 7) / 8;
+    {
+        const int64_t hn = 256 * n_tiles;
+        const size_t need = std::max(scan_scratch_words(hn), scan_scratch_words((n + 31) / 32)) + 16;
+        MESSI_TRY(scr.alloc(sizeof(uint32_t) * need));
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)n_tiles), dim3(kBlk), 0, s, K[cur].as<uint16_t>(), n,
+                           shift, hist.as<uint32_t>(), n_tiles);
+        MESSI_LAUNCH_CHECK("radix_hist");
+        MESSI_TRY(scan_exclusive(hist.as<uint32_t>(), hist.as<uint32_t>(), 256 * n_tiles, scr.as<uint32_t>(), nullptr,
+                                 s));
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)n_tiles), dim3(kBlk), 0, s, K[cur].as<uint16_t>(),
+                           W[cur].as<uint4>(), pass == 0 ? nullptr : P[cur].as<uint32_t>(), n, shift,
+                           hist.as<uint32_t>(), n_tiles, K[cur ^ 1].as<uint16_t>(), W[cur ^ 1].as<uint4>(),
+                           P[cur ^ 1].as<uint32_t>());
+        MESSI_LAUNCH_CHECK("radix_scatter");
+        cur ^= 1;
+    }
+    hist.release();
+
+    // root runs -> first nodes / leaves
+    const uint32_t n_keys = 1u << w;
+    DevBuf runs, leaves_raw, leaf_buf, nodes[2], node_cnt, node_seg, node_n0, tile_first, tile_node, tile_cnt, zeros;
+    MESSI_TRY(runs.alloc(sizeof(uint32_t) * 2 * n_keys));
+    MESSI_HIP_TRY(hipMemsetAsync(runs.p, 0, sizeof(uint32_t) * 2 * n_keys, s));
+    hipLaunchKernelGGL(root_runs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, K[cur].as<uint16_t>(), n,
+                       runs.as<uint32_t>(), runs.as<uint32_t>() + n_keys);
+    MESSI_LAUNCH_CHECK("root_runs");
+    // Leaves: at most n.  Nodes per level: at most n / (cap + 1) + 1 (each holds > cap).
+    MESSI_TRY(leaves_raw.alloc(sizeof(Leaf) * (size_t)n));
+    MESSI_TRY(leaf_buf.alloc((size_t)n));
+    const int64_t max_nodes = n / ((int64_t)cap + 1) + 2;
+    for (int i = 0; i < 2; ++i) MESSI_TRY(nodes[i].alloc(sizeof(Leaf) * (size_t)max_nodes));
+    Lists lists;
+    lists.leaves = leaves_raw.as<Leaf>();
+    lists.leaf_buf = leaf_buf.as<uint8_t>();
+    lists.n_leaves = cnt + 2;
+    lists.n_next = cnt + 3;
+    lists.max_leaf = cnt + 4;
+    lists.next = nodes[0].as<Leaf>();
+    hipLaunchKernelGGL(root_nodes_kernel, dim3((n_keys + 255) / 256), dim3(256), 0, s, runs.as<uint32_t>(),
+                       runs.as<uint32_t>() + n_keys, w, b, cap, cur, lists);
+    MESSI_LAUNCH_CHECK("root_nodes");
+    uint32_t n_nodes = 0;
+    MESSI_HIP_TRY(hipMemcpyAsync(&n_nodes, cnt + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    runs.release();
+    ix->info.ms_bucket = tm.stop_ms();
+
+    // ---- 3. split levels
+    tm.start();
+    const int64_t max_tiles = n_tiles + max_nodes + 1;
+    MESSI_TRY(node_cnt.alloc(sizeof(uint32_t) * 16 * (size_t)max_nodes));
+    MESSI_TRY(node_seg.alloc((size_t)max_nodes));
+    MESSI_TRY(node_n0.alloc(sizeof(uint32_t) * (size_t)max_nodes));
+    MESSI_TRY(tile_first.alloc(sizeof(uint32_t) * ((size_t)max_nodes + 1)));
+    MESSI_TRY(tile_node.alloc(sizeof(uint32_t) * (size_t)max_tiles));
+    MESSI_TRY(tile_cnt.alloc(sizeof(uint32_t) * 16 * (size_t)max_tiles));
+    MESSI_TRY(zeros.alloc(sizeof(uint32_t) * (size_t)max_tiles));
+    int levels = 0;
+    int nsel = 0;  // nodes[nsel] holds the current level
+    while (n_nodes > 0) {
+        Leaf* cur_nodes = nodes[nsel].as<Leaf>();
+        hipLaunchKernelGGL(node_tiles_kernel, dim3(1), dim3(1024), 0, s, cur_nodes, (int)n_nodes,
+                           tile_first.as<uint32_t>(), cnt + 5);
+        MESSI_LAUNCH_CHECK("node_tiles");
+        uint32_t tiles = 0;
+        MESSI_HIP_TRY(hipMemcpyAsync(&tiles, cnt + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipMemsetAsync(node_cnt.p, 0, sizeof(uint32_t) * 16 * (size_t)n_nodes, s));
+        MESSI_HIP_TRY(hipMemsetAsync(cnt + 3, 0, sizeof(uint32_t), s));
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        hipLaunchKernelGGL(tile_node_kernel, dim3((tiles + 255) / 256), dim3(256), 0, s, tile_first.as<uint32_t>(),
+                           (int)n_nodes, tiles, tile_node.as<uint32_t>());
+        MESSI_LAUNCH_CHECK("tile_node");
+        hipLaunchKernelGGL(level_count_kernel, dim3(tiles), dim3(kBlk), 0, s, cur_nodes, tile_first.as<uint32_t>(),
+                           tile_node.as<uint32_t>(), W[cur].as<uint4>(), w, b, tile_cnt.as<uint32_t>(),
+                           node_cnt.as<uint32_t>());
+        MESSI_LAUNCH_CHECK("level_count");
+        lists.next = nodes[nsel ^ 1].as<Leaf>();
+        hipLaunchKernelGGL(level_choose_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, s, cur_nodes,
+                           (int)n_nodes, node_cnt.as<uint32_t>(), w, b, cap, cur ^ 1, node_seg.as<uint8_t>(),
+                           node_n0.as<uint32_t>(), lists);
+        MESSI_LAUNCH_CHECK("level_choose");
+        hipLaunchKernelGGL(level_zeros_kernel, dim3((tiles + 255) / 256), dim3(256), 0, s, cur_nodes,
+                           tile_first.as<uint32_t>(), tile_node.as<uint32_t>(), tiles, tile_cnt.as<uint32_t>(),
+                           node_seg.as<uint8_t>(), zeros.as<uint32_t>());
+        MESSI_LAUNCH_CHECK("level_zeros");
+        MESSI_TRY(scan_exclusive(zeros.as<uint32_t>(), zeros.as<uint32_t>(), tiles, scr.as<uint32_t>(), nullptr, s));
+        hipLaunchKernelGGL(level_scatter_kernel, dim3(tiles), dim3(kBlk), 0, s, cur_nodes, tile_first.as<uint32_t>(),
+                           tile_node.as<uint32_t>(), zeros.as<uint32_t>(), node_seg.as<uint8_t>(),
+                           node_n0.as<uint32_t>(), b, W[cur].as<uint4>(), P[cur].as<uint32_t>(),
+                           W[cur ^ 1].as<uint4>(), P[cur ^ 1].as<uint32_t>());
+        MESSI_LAUNCH_CHECK("level_scatter");
+        MESSI_HIP_TRY(hipMemcpyAsync(&n_nodes, cnt + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        cur ^= 1;
+        nsel ^= 1;
+        ++levels;
+        if (levels > 16 * 8 + 2) {
+            set_error(MESSI_EDEVICE, "leaf partition did not terminate");
+            return MESSI_EDEVICE;
+        }
+    }
+    ix->info.ms_split = tm.stop_ms();
+    node_cnt.release(); node_seg.release(); node_n0.release(); tile_first.release(); tile_node.release();
+    tile_cnt.release(); zeros.release(); nodes[0].release(); nodes[1].release();
+
+    // ---- 4. finalise: all ranges into one buffer, leaves ordered by start
+    tm.start();
+    uint32_t hc[3];
+    MESSI_HIP_TRY(hipMemcpyAsync(hc, cnt + 2, sizeof(hc), hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t n_leaves = hc[0];
+    ix->max_leaf = hc[2];
+    const int fin = 0;  // final buffer index
+    hipLaunchKernelGGL(copy_back_kernel, dim3(launch_blocks(n_leaves, 1, 65536)), dim3(kBlk), 0, s,
+                       leaves_raw.as<Leaf>(), leaf_buf.as<uint8_t>(), n_leaves, W[1 - fin].as<uint4>(),
+                       P[1 - fin].as<uint32_t>(), W[fin].as<uint4>(), P[fin].as<uint32_t>(), 1 - fin);
+    MESSI_LAUNCH_CHECK("copy_back");
+    const int64_t nw = (n + 31) / 32;
+    DevBuf bm, rank;
+    MESSI_TRY(bm.alloc(sizeof(uint32_t) * (size_t)nw));
+    MESSI_TRY(rank.alloc(sizeof(uint32_t) * (size_t)nw));
+    MESSI_HIP_TRY(hipMemsetAsync(bm.p, 0, sizeof(uint32_t) * (size_t)nw, s));
+    hipLaunchKernelGGL(leaf_bitmap_kernel, dim3((n_leaves + 255) / 256), dim3(256), 0, s, leaves_raw.as<Leaf>(),
+                       n_leaves, bm.as<uint32_t>());
+    MESSI_LAUNCH_CHECK("leaf_bitmap");
+    hipLaunchKernelGGL(popc_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, bm.as<uint32_t>(), nw,
+                       rank.as<uint32_t>());
+    MESSI_LAUNCH_CHECK("popc");
+    MESSI_TRY(scan_exclusive(rank.as<uint32_t>(), rank.as<uint32_t>(), nw, scr.as<uint32_t>(), nullptr, s));
+    MESSI_TRY(ix->leaves.alloc(sizeof(Leaf) * (size_t)n_leaves));
+    hipLaunchKernelGGL(leaf_order_kernel, dim3((n_leaves + 255) / 256), dim3(256), 0, s, leaves_raw.as<Leaf>(),
+                       n_leaves, bm.as<uint32_t>(), rank.as<uint32_t>(), ix->leaves.as<Leaf>());
+    MESSI_LAUNCH_CHECK("leaf_order");
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    ix->info.ms_finalize = tm.stop_ms();
+
+    // keep the final arrays, drop the rest
+    ix->words = std::move(W[fin]);
+    ix->pos = std::move(P[fin]);
+    ix->n_leaves = n_leaves;
+    ix->levels = levels;
+    const auto t_end = std::chrono::steady_clock::now();
+    ix->info.ms_total = std::chrono::duration<double, std::milli>(t_end - t_begin).count();
+    return MESSI_OK;
+}
+
+}  // namespace messi

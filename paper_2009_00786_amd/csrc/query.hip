@@ -1,0 +1,863 @@
+// Exact k-NN search on gfx950 (paper: Query Answering -- ExactSearch, approxSearch,
+// SearchWorker, TraverseRootSubtree, ProcessQueue, CalculateRealDistance),
+// re-planned for a GPU:
+//
+//  prep        query PAA, norm, region widening, state reset          (1 block / query)
+//  leaf_lb     lower bound of every leaf against the query PAA, from per-segment
+//              tables in LDS; the argmin leaf is the approximate-search leaf
+//  approx      squared distances to that leaf's members -> first upper bound U
+//              on the k-th distance (the paper's initial BSF)
+//  order       the leaves whose bound does not exceed U, counting-sorted into
+//              1024 bound bins: the ascending order the priority queues deliver
+//  scan        persistent blocks take leaves from that order with an atomic
+//              ticket; a leaf whose bound exceeds the current U is skipped and,
+//              once a whole bin lies above U, the query stops; inside a leaf each
+//              member's own word gives a second bound (LDS table lookups) and only
+//              the survivors' rows are read, 16 lanes per row, abandoning a
+//              distance as soon as its partial sum exceeds U; U lives in device
+//              memory (atomicMin for k = 1, a k-th-smallest refresh for k > 1)
+//  final       candidates within the final U get the canonical fp64 distance and
+//              are ordered by (distance, index); the first k are the answer
+//
+// Exactness: every prune compares a quantity that is provably below the true
+// squared distance with an upper bound on the k-th true squared distance.
+//  * Regions are widened by delta = 2 (lg m + 1) 2^-24 A_data + 2 (m + 1) 2^-24 A_q,
+//    which covers the fp32 PAA error of both the data words (fold-halving sums)
+//    and the query (sequential sums), so the bound stays below the exact
+//    distance (Keogh's PAA bound + containment of the exact segment mean).
+//  * fp32 distances d have relative error below 2^-16 (at most a few dozen
+//    roundings of non-negative terms), so U = up(d_k (1 + 2^-15)) exceeds the
+//    true k-th distance; a candidate is kept iff d (1 - 2^-16) <= U, a partial
+//    sum abandons iff p (1 - 2^-16) > U, a bound prunes iff b (1 - 2^-12) > U.
+//  * The final order uses the canonical fp64 distance, so the returned indices
+//    are those of the brute-force definition whatever the visiting order.
+#include <cmath>
+#include <map>
+#include <mutex>
+
+#include "query.h"
+#include "scan.h"
+
+namespace messi {
+namespace {
+
+constexpr int kScanThreads = 256;
+
+__device__ __forceinline__ uint32_t vload(const uint32_t* p) {
+    return __atomic_load_n(p, __ATOMIC_RELAXED);
+}
+
+__device__ __forceinline__ float upper_u(float d) { return d * (1.0f + 2.0f * kRhoEd); }
+
+// --------------------------------------------------------------------------
+// prep
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, uint32_t kstride) {
+    __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ float s_red[2][4];
+    __shared__ int s_bad;
+    const int q = blockIdx.x;
+    const float* row = a.queries + (size_t)q * a.L;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    float n2 = 0.f, amax = 0.f;
+    bool bad = false;
+    for (int j = threadIdx.x; j < a.L; j += 256) {
+        const float v = row[j];
+        s_q[j] = v;
+        bad |= !isfinite(v);
+        n2 = fmaf(v, v, n2);
+        amax = fmaxf(amax, fabsf(v));
+    }
+    if (bad) s_bad = 1;
+    n2 = dev::wave_sum(n2);
+    amax = dev::wave_max(amax);
+    if ((threadIdx.x & 63) == 0) {
+        s_red[0][threadIdx.x >> 6] = n2;
+        s_red[1][threadIdx.x >> 6] = amax;
+    }
+    __syncthreads();
+    QState& st = a.qs[q];
+    if (threadIdx.x < a.w) {
+        const int i = threadIdx.x;
+        float s = 0.f;
+        for (int j = 0; j < a.m; ++j) s += s_q[i * a.m + j];
+        st.paa[i] = s / (float)a.m;
+    } else if (threadIdx.x < 16) {
+        st.paa[threadIdx.x] = 0.f;
+    }
+    if (threadIdx.x == 0) {
+        const float aq = fmaxf(fmaxf(s_red[1][0], s_red[1][1]), fmaxf(s_red[1][2], s_red[1][3]));
+        st.norm2 = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+        const float u = 5.9604644775390625e-08f;  // 2^-24
+        st.delta = 1.01f * (2.f * (float)(a.lg_m + 1) * u * a.absmax_data + 2.f * (float)(a.m + 1) * u * aq);
+        st.U = 0x7f800000u;  // +inf
+        st.ncand = 0;
+        st.ticket = 0;
+        st.nsurv = 0;
+        st.done = 0;
+        st.lbmax = 0;
+        st.argmin = ~0ull;
+        st.approx_leaf = 0;
+        st.approx_full = 0;
+        st.range = 0.f;
+        st.k = k;
+        st.err = s_bad ? 1u : 0u;
+        st.active = 1;
+        st.kstride = kstride;
+        if (s_bad) atomicOr(a.err_any, 1u);
+    }
+}
+
+// --------------------------------------------------------------------------
+// leaf lower bounds
+// --------------------------------------------------------------------------
+constexpr int kLeavesPerThread = 4;
+constexpr int kLeafBlock = 256 * kLeavesPerThread;
+
+__global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a) {
+    __shared__ float s_lo[16 * 257];
+    __shared__ float s_hi[16 * 257];
+    __shared__ unsigned long long s_min[4];
+    __shared__ uint32_t s_max[4];
+    const int q = blockIdx.y;
+    const QState& st = a.qs[q];
+    const int A = 1 << a.b;
+    const float delta = st.delta;
+    for (int idx = threadIdx.x; idx < a.w * (A + 1); idx += 256) {
+        const int i = idx / (A + 1), c = idx % (A + 1);
+        const float p = st.paa[i];
+        float tl = 0.f, th = 0.f;
+        if (c > 0 && c < A) {
+            const float lo = a.bp[c - 1] - delta;
+            const float hi = a.bp[c - 1] + delta;
+            if (p < lo) tl = (lo - p) * (lo - p);
+            if (p > hi) th = (p - hi) * (p - hi);
+        }
+        s_lo[i * 257 + c] = tl;
+        s_hi[i * 257 + c] = th;
+    }
+    __syncthreads();
+    unsigned long long best = ~0ull;
+    uint32_t mx = 0;
+    const float mf = (float)a.m;
+    for (int j = 0; j < kLeavesPerThread; ++j) {
+        const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
+        if (l >= a.nL) break;
+        const Leaf lf = a.leaves[l];
+        float s = 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < a.w) {
+                const int sh = a.b - lf.card[i];
+                const int lo = (int)lf.prefix[i] << sh;
+                const int hi = ((int)lf.prefix[i] + 1) << sh;
+                s += s_lo[i * 257 + lo] + s_hi[i * 257 + hi];
+            }
+        }
+        const float lbv = s * mf;
+        a.lb[(size_t)q * a.nL + l] = lbv;
+        const unsigned long long key = ((unsigned long long)__float_as_uint(lbv) << 32) | (uint32_t)l;
+        best = key < best ? key : best;
+        mx = max(mx, __float_as_uint(lbv));
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o < best ? o : best;
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_min[threadIdx.x >> 6] = best;
+        s_max[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b0 = s_min[0];
+        uint32_t m0 = s_max[0];
+        for (int w = 1; w < 4; ++w) {
+            b0 = s_min[w] < b0 ? s_min[w] : b0;
+            m0 = max(m0, s_max[w]);
+        }
+        atomicMin(&a.qs[q].argmin, b0);
+        atomicMax(&a.qs[q].lbmax, m0);
+    }
+}
+
+// --------------------------------------------------------------------------
+// approximate search: distances to the members of the smallest-bound leaf
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a) {
+    __shared__ float s_q[MESSI_MAX_LEN];
+    const int q = blockIdx.y;
+    const QState& st = a.qs[q];
+    if (st.err) return;
+    for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
+    __syncthreads();
+    const uint32_t leaf = (uint32_t)(st.argmin & 0xffffffffull);
+    const Leaf lf = a.leaves[leaf];
+    const uint32_t cnt = min(lf.count, (uint32_t)kApproxMax);
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (uint32_t r = gw; r < cnt; r += kApproxBlocks * 4) {
+        const float* x = a.series + (size_t)a.pos[lf.start + r] * a.L;
+        float s = 0.f;
+        for (int j = lane; j < a.L; j += 64) {
+            const float d = s_q[j] - x[j];
+            s = fmaf(d, d, s);
+        }
+        s = dev::wave_sum(s);
+        if (lane == 0) a.approx_d[(size_t)q * kApproxMax + r] = s;
+    }
+}
+
+// k-th smallest (1-based) of n non-negative floats by a 4-pass radix select
+// (block of 256 threads).  Returns +inf when n < k.
+template <class Getter>
+__device__ float block_kth(Getter get, uint32_t n, uint32_t k, uint32_t* s_hist, uint32_t* s_bcast) {
+    if (n < k) return __uint_as_float(0x7f800000u);
+    uint32_t prefix = 0, mask = 0, kk = k;
+    for (int pass = 3; pass >= 0; --pass) {
+        const int shift = 8 * pass;
+        s_hist[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += 256) {
+            const uint32_t key = __float_as_uint(get(i));
+            if ((key & mask) == prefix) atomicAdd(&s_hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0, d = 0;
+            for (d = 0; d < 256; ++d) {
+                if (acc + s_hist[d] >= kk) break;
+                acc += s_hist[d];
+            }
+            s_bcast[0] = d;
+            s_bcast[1] = kk - acc;
+        }
+        __syncthreads();
+        prefix |= s_bcast[0] << shift;
+        mask |= 255u << shift;
+        kk = s_bcast[1];
+        __syncthreads();
+    }
+    return __uint_as_float(prefix);
+}
+
+__global__ void __launch_bounds__(256) approx_select_kernel(QArgs a) {
+    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_b[2];
+    const int q = blockIdx.x;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    const uint32_t leaf = (uint32_t)(st.argmin & 0xffffffffull);
+    const Leaf lf = a.leaves[leaf];
+    const uint32_t cnt = min(lf.count, (uint32_t)kApproxMax);
+    const float* d = a.approx_d + (size_t)q * kApproxMax;
+    const float kth = block_kth([&](uint32_t i) { return d[i]; }, cnt, (uint32_t)st.k, s_hist, s_b);
+    const float U0 = isinf(kth) ? kth : upper_u(kth);
+    for (uint32_t r = threadIdx.x; r < cnt; r += 256) {
+        if (d[r] * (1.0f - kRhoEd) <= U0) {
+            const uint32_t slot = atomicAdd(&st.ncand, 1u);
+            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d[r], a.pos[lf.start + r]};
+        }
+    }
+    if (threadIdx.x == 0) {
+        st.U = __float_as_uint(U0);
+        st.approx_leaf = leaf;
+        st.approx_full = lf.count <= (uint32_t)kApproxMax;
+        float range = isinf(U0) ? __uint_as_float(st.lbmax) : U0;
+        st.range = range > 0.f ? range : 1e-30f;
+    }
+}
+
+// --------------------------------------------------------------------------
+// order: counting sort of the surviving leaves into bound bins
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int bin_of(float lbv, float range) {
+    const float f = lbv / range * (float)kNB;
+    if (!(f >= 0.f)) return 0;
+    return f >= (float)(kNB - 1) ? kNB - 1 : (int)f;
+}
+
+__device__ __forceinline__ bool leaf_kept(const QState& st, float lbv, uint32_t l, float U0) {
+    if (lbv * (1.0f - kRhoLb) > U0) return false;
+    return !(l == st.approx_leaf && st.approx_full);
+}
+
+__global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
+    __shared__ uint32_t h[kNB];
+    const int q = blockIdx.y;
+    const QState& st = a.qs[q];
+    if (st.err) return;
+    for (int i = threadIdx.x; i < kNB; i += 256) h[i] = 0;
+    __syncthreads();
+    const float U0 = __uint_as_float(st.U), range = st.range;
+    for (int j = 0; j < kLeavesPerThread; ++j) {
+        const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
+        if (l >= a.nL) break;
+        const float lbv = a.lb[(size_t)q * a.nL + l];
+        if (leaf_kept(st, lbv, (uint32_t)l, U0)) atomicAdd(&h[bin_of(lbv, range)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNB; i += 256)
+        if (h[i]) atomicAdd(&a.bins[(size_t)q * kNB + i], h[i]);
+}
+
+__global__ void __launch_bounds__(kNB) bin_scan_kernel(QArgs a) {
+    __shared__ uint32_t wt[kNB / 64];
+    const int q = blockIdx.x;
+    QState& st = a.qs[q];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t v = a.bins[(size_t)q * kNB + t];
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wt[wave] = x;
+    __syncthreads();
+    uint32_t wo = 0, tot = 0;
+    for (int w = 0; w < kNB / 64; ++w) {
+        if (w < wave) wo += wt[w];
+        tot += wt[w];
+    }
+    const uint32_t ex = wo + x - v;
+    a.bins[(size_t)q * kNB + t] = ex;
+    a.cursor[(size_t)q * kNB + t] = ex;
+    if (t == 0) {
+        st.nsurv = st.err ? 0u : tot;
+        if (a.counters) atomicAdd(&a.counters->kept, (unsigned long long)tot);
+    }
+}
+
+__global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
+    const int q = blockIdx.y;
+    const QState& st = a.qs[q];
+    if (st.err) return;
+    const float U0 = __uint_as_float(st.U), range = st.range;
+    for (int j = 0; j < kLeavesPerThread; ++j) {
+        const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
+        if (l >= a.nL) break;
+        const float lbv = a.lb[(size_t)q * a.nL + l];
+        if (leaf_kept(st, lbv, (uint32_t)l, U0)) {
+            const uint32_t slot = atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], 1u);
+            if (slot < (uint32_t)a.nL) a.order[(size_t)q * a.nL + slot] = (uint32_t)l;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// scan: persistent blocks over (query, leaf) tickets
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t word_byte(const uint4& wd, int i) {
+    const uint32_t v = (i < 4) ? wd.x : (i < 8) ? wd.y : (i < 12) ? wd.z : wd.w;
+    return (v >> (8 * (i & 3))) & 0xFFu;
+}
+
+// Refresh U of a query from its candidates (k > 1): U <= up(kth (1 + 2 rho)).
+// Other blocks may have reserved a slot (ncand) without having written it yet;
+// the buffer is pre-filled with an all-ones pattern (a NaN whose bits order
+// above every distance), so such a slot can only raise the k-th value.
+__device__ void refresh_u(QArgs& a, int q, QState& st, uint32_t* s_hist, uint32_t* s_b) {
+    if (threadIdx.x == 0) s_b[0] = min(vload(&st.ncand), a.cap);
+    __syncthreads();
+    const uint32_t n = s_b[0];
+    __syncthreads();
+    const Cand* c = a.cand + (size_t)q * a.cap;
+    const float kth = block_kth(
+        [&](uint32_t i) { return __uint_as_float(vload(reinterpret_cast<const uint32_t*>(&c[i].d))); }, n,
+        (uint32_t)st.k, s_hist, s_b);
+    if (threadIdx.x == 0 && !isinf(kth) && !isnan(kth)) atomicMin(&st.U, __float_as_uint(upper_u(kth)));
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
+    __shared__ float s_D[16 * 256];
+    __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ uint32_t s_surv[kChunk];
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_b[2];
+    __shared__ int s_sel[2];
+    __shared__ float s_ctl[2];
+    __shared__ uint32_t s_nsv, s_app;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int quarter = lane >> 4, ql = lane & 15;
+    const int nq = a.nq;
+    const int L = a.L;
+    const int nchunk = (L + 63) / 64;
+    int q = blockIdx.x % nq;
+    int loaded = -1;
+    unsigned long long c_scanned = 0, c_bounded = 0, c_dist = 0, c_abandon = 0, c_bytes = 0;
+    for (;;) {
+        if (tid == 0) {
+            int found = -1;
+            uint32_t tsel = 0;
+            for (int tries = 0; tries < nq; ++tries) {
+                const int qq = (q + tries) % nq;
+                QState& s2 = a.qs[qq];
+                if (vload(&s2.done) == 0) {
+                    const uint32_t t = atomicAdd(&s2.ticket, 1u);
+                    if (t < s2.nsurv) {
+                        found = qq;
+                        tsel = t;
+                        break;
+                    }
+                    s2.done = 1;
+                }
+            }
+            s_sel[0] = found;
+            s_sel[1] = (int)tsel;
+            if (found >= 0) {
+                const QState& s3 = a.qs[found];
+                const uint32_t leaf = a.order[(size_t)found * a.nL + tsel];
+                s_sel[1] = (int)leaf;
+                s_ctl[0] = a.lb[(size_t)found * a.nL + leaf];
+                s_ctl[1] = __uint_as_float(vload(&s3.U));
+            }
+        }
+        __syncthreads();
+        const int qq = s_sel[0];
+        if (qq < 0) break;
+        const uint32_t leaf = (uint32_t)s_sel[1];
+        const float lbv = s_ctl[0], U0 = s_ctl[1];
+        q = qq;
+        QState& st = a.qs[q];
+        if (lbv * (1.0f - kRhoLb) > U0) {
+            // bins ascend: once a bin's lower edge is above U, the rest of the list is too
+            if (tid == 0) {
+                const float low = (float)bin_of(lbv, st.range) * (st.range / (float)kNB);
+                if (low * (1.0f - 2.0f * kRhoLb) > U0) st.done = 1;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (q != loaded) {
+            const int A = 1 << a.b;
+            const float delta = st.delta;
+            const float mf = (float)a.m;
+            for (int idx = tid; idx < a.w * A; idx += kScanThreads) {
+                const int i = idx / A, c = idx % A;
+                const float p = st.paa[i];
+                float d = 0.f;
+                if (c > 0) {
+                    const float lo = a.bp[c - 1] - delta;
+                    if (p < lo) d = lo - p;
+                }
+                if (c < A - 1) {
+                    const float hi = a.bp[c] + delta;
+                    if (p > hi) d = p - hi;
+                }
+                s_D[i * 256 + c] = mf * (d * d);
+            }
+            for (int j = tid; j < L; j += kScanThreads) s_q[j] = a.queries[(size_t)q * L + j];
+            loaded = q;
+        }
+        if (tid == 0) s_app = 0;
+        __syncthreads();
+        const Leaf lf = a.leaves[leaf];
+        const int k = st.k;
+        uint32_t appended = 0;
+        for (uint32_t c0 = 0; c0 < lf.count; c0 += kChunk) {
+            // ---- second filter: lower bound from each member's own word
+            const float Uf = __uint_as_float(vload(&st.U));
+            if (tid == 0) s_nsv = 0;
+            __syncthreads();
+            const uint32_t cend = min(lf.count, c0 + (uint32_t)kChunk);
+            for (uint32_t r0 = c0; r0 < cend; r0 += kScanThreads) {
+                const uint32_t mi = r0 + tid;
+                bool keep = false;
+                if (mi < cend) {
+                    const uint4 wd = a.words[lf.start + mi];
+                    float s = 0.f;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (i < a.w) s += s_D[i * 256 + word_byte(wd, i)];
+                    keep = !(s * (1.0f - kRhoLb) > Uf);
+                    ++c_bounded;
+                }
+                const uint64_t m = dev::ballot(keep);
+                if (lane == 0) s_w[wave] = (uint32_t)dev::popc64(m);
+                __syncthreads();
+                uint32_t before = 0, tot = 0;
+                for (int w = 0; w < 4; ++w) {
+                    if (w < wave) before += s_w[w];
+                    tot += s_w[w];
+                }
+                if (keep) s_surv[s_nsv + before + dev::popc64(m & dev::lanemask_lt())] = mi;
+                __syncthreads();
+                if (tid == 0) s_nsv += tot;
+                __syncthreads();
+            }
+            const uint32_t nsv = s_nsv;
+            // ---- real distances: 16 lanes per row, 4 rows per wave, abandon per 512 B
+            for (uint32_t base = wave * 4; base < nsv; base += 16) {
+                const uint32_t si = base + quarter;
+                const bool act = si < nsv;
+                uint32_t gidx = 0;
+                if (act) gidx = a.pos[lf.start + s_surv[si]];
+                const float* row = a.series + (size_t)gidx * L;
+                float acc = 0.f;
+                bool alive = act;
+                for (int ch = 0; ch < nchunk; ch += 2) {
+                    if (alive) {
+#pragma unroll
+                        for (int cc = 0; cc < 2; ++cc) {
+                            const int c = ch + cc;
+                            if (c < nchunk) {
+                                const int j0 = c * 64 + ql * 4;
+                                if (VEC) {
+                                    if (j0 < L) {
+                                        const float4 x = *reinterpret_cast<const float4*>(row + j0);
+                                        const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
+                                        float d0 = y.x - x.x, d1 = y.y - x.y, d2 = y.z - x.z, d3 = y.w - x.w;
+                                        acc = fmaf(d0, d0, acc);
+                                        acc = fmaf(d1, d1, acc);
+                                        acc = fmaf(d2, d2, acc);
+                                        acc = fmaf(d3, d3, acc);
+                                    }
+                                } else {
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e) {
+                                        const int j = j0 + e;
+                                        if (j < L) {
+                                            const float d = s_q[j] - row[j];
+                                            acc = fmaf(d, d, acc);
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    float p = acc;
+                    p += __shfl_xor(p, 8, 16);
+                    p += __shfl_xor(p, 4, 16);
+                    p += __shfl_xor(p, 2, 16);
+                    p += __shfl_xor(p, 1, 16);
+                    p = __shfl(p, quarter * 16, 64);  // one value per row for every lane of the row
+                    if (alive) c_bytes += (uint64_t)min(2, nchunk - ch) * 256u;
+                    if (ch + 2 < nchunk) {
+                        const float Un = __uint_as_float((uint32_t)__builtin_amdgcn_readfirstlane((int)vload(&st.U)));
+                        if (alive && p * (1.0f - kRhoEd) > Un) {
+                            alive = false;
+                            if (ql == 0) ++c_abandon;
+                        }
+                    }
+                    if (ch + 2 >= nchunk) acc = p;  // full distance on every lane of the row
+                }
+                if (act && ql == 0) ++c_dist;
+                if (alive && ql == 0) {
+                    const float d = acc;
+                    const float Un = __uint_as_float(vload(&st.U));
+                    if (d * (1.0f - kRhoEd) <= Un) {
+                        const uint32_t slot = atomicAdd(&st.ncand, 1u);
+                        if (slot < a.cap) {
+                            a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx};
+                        } else {
+                            st.err = 2;
+                            atomicOr(a.err_any, 2u);
+                        }
+                        ++appended;
+                        if (k == 1) atomicMin(&st.U, __float_as_uint(upper_u(d)));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        ++c_scanned;
+        if (k > 1) {
+            if (appended) atomicAdd(&s_app, appended);
+            __syncthreads();
+            if (s_app) refresh_u(a, q, st, s_hist, s_b);
+        }
+        __syncthreads();
+    }
+    if (a.counters) {
+        // per-thread counts -> one atomic per wave
+        unsigned long long v[5] = {c_scanned, c_bounded, c_dist, c_abandon, c_bytes};
+        for (int i = 0; i < 5; ++i)
+            for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
+        if (lane == 0) {
+            if (wave == 0) atomicAdd(&a.counters->scanned, v[0] / 64);  // c_scanned counted by every thread
+            atomicAdd(&a.counters->bounded, v[1]);
+            atomicAdd(&a.counters->distance, v[2]);
+            atomicAdd(&a.counters->abandoned, v[3]);
+            atomicAdd(&a.counters->bytes, v[4] / 16 + v[1] * 16ull);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// final: canonical fp64 distance of the candidates within U, ordered by (D, idx)
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) final_kernel(QArgs a) {
+    __shared__ double s_d[kMaxFinal];
+    __shared__ uint32_t s_i[kMaxFinal];
+    __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ uint32_t s_kept;
+    const int q = blockIdx.x;
+    QState& st = a.qs[q];
+    if (threadIdx.x == 0) s_kept = 0;
+    for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
+    __syncthreads();
+    if (st.err) return;
+    const float U = __uint_as_float(st.U);
+    const uint32_t nc = st.ncand;
+    if (nc > a.cap) {
+        if (threadIdx.x == 0) {
+            st.err = 2;
+            atomicOr(a.err_any, 2u);
+        }
+        return;
+    }
+    const Cand* c = a.cand + (size_t)q * a.cap;
+    for (uint32_t i = threadIdx.x; i < nc; i += 256) {
+        const Cand e = c[i];
+        if (e.d * (1.0f - kRhoEd) <= U) {
+            const uint32_t slot = atomicAdd(&s_kept, 1u);
+            if (slot < (uint32_t)kMaxFinal) s_i[slot] = e.idx;
+        }
+    }
+    __syncthreads();
+    const uint32_t kept = s_kept;
+    const int k = st.k;
+    if (kept > (uint32_t)kMaxFinal || kept < (uint32_t)k) {
+        if (threadIdx.x == 0) {
+            st.err = kept > (uint32_t)kMaxFinal ? 3u : 4u;
+            atomicOr(a.err_any, kept > (uint32_t)kMaxFinal ? 4u : 8u);
+        }
+        return;
+    }
+    for (uint32_t j = threadIdx.x; j < kept; j += 256) {
+        const float* x = a.series + (size_t)s_i[j] * a.L;
+        double s = 0.0;
+        for (int t = 0; t < a.L; ++t) {
+            const double d = __dsub_rn((double)s_q[t], (double)x[t]);
+            s = __dadd_rn(s, __dmul_rn(d, d));
+        }
+        s_d[j] = s;
+    }
+    uint32_t P = 1;
+    while (P < kept) P <<= 1;
+    for (uint32_t j = kept + threadIdx.x; j < P; j += 256) {
+        s_d[j] = __longlong_as_double(0x7ff0000000000000ll);
+        s_i[j] = 0xffffffffu;
+    }
+    __syncthreads();
+    // bitonic sort by (distance, index)
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += 256) {
+                const uint32_t lo = 2 * t - (t & (stride - 1));
+                const uint32_t hi = lo + stride;
+                const bool up = ((lo & size) == 0);
+                const double dl = s_d[lo], dh = s_d[hi];
+                const uint32_t il = s_i[lo], ih = s_i[hi];
+                const bool gt = (dl > dh) || (dl == dh && il > ih);
+                if (gt == up) {
+                    s_d[lo] = dh;
+                    s_d[hi] = dl;
+                    s_i[lo] = ih;
+                    s_i[hi] = il;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t ks = st.kstride;
+    for (int j = threadIdx.x; j < k; j += 256) {
+        a.out_idx[(size_t)q * ks + j] = (int64_t)s_i[j];
+        a.out_dist[(size_t)q * ks + j] = (float)__dsqrt_rn(s_d[j]);
+    }
+    if (threadIdx.x == 0 && a.counters) atomicAdd(&a.counters->final_cands, (unsigned long long)kept);
+}
+
+// --------------------------------------------------------------------------
+// host side
+// --------------------------------------------------------------------------
+struct Workspace {
+    int32_t nq = 0, nL = 0;
+    uint32_t cap = 0;
+    DevBuf qs, lb, order, bins, cursor, approx_d, cand, counters, err;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<const Index*, hipStream_t>, Workspace*> g_ws;
+
+int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Workspace** out) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace*& ws = g_ws[{ix, s}];
+    if (!ws) ws = new Workspace();
+    if (ws->nq < nq || ws->cap < cap || ws->nL != ix->n_leaves) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        const int32_t nqa = std::max(nq, ws->nq);
+        const uint32_t capa = std::max(cap, ws->cap);
+        const size_t nL = (size_t)ix->n_leaves;
+        MESSI_TRY(ws->qs.alloc(sizeof(QState) * nqa));
+        MESSI_TRY(ws->lb.alloc(sizeof(float) * nL * nqa));
+        MESSI_TRY(ws->order.alloc(sizeof(uint32_t) * nL * nqa));
+        MESSI_TRY(ws->bins.alloc(sizeof(uint32_t) * kNB * nqa));
+        MESSI_TRY(ws->cursor.alloc(sizeof(uint32_t) * kNB * nqa));
+        MESSI_TRY(ws->approx_d.alloc(sizeof(float) * kApproxMax * nqa));
+        MESSI_TRY(ws->cand.alloc(sizeof(Cand) * (size_t)capa * nqa));
+        MESSI_TRY(ws->counters.alloc(sizeof(QCounters)));
+        MESSI_TRY(ws->err.alloc(sizeof(uint32_t) * 4));
+        ws->nq = nqa;
+        ws->cap = capa;
+        ws->nL = (int32_t)nL;
+    }
+    *out = ws;
+    return MESSI_OK;
+}
+
+int scan_grid() {
+    static int blocks = 0;
+    if (!blocks) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t p;
+            if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        }
+        blocks = cus * 4;
+    }
+    return blocks;
+}
+
+}  // namespace
+
+void release_workspaces(const Index* ix) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        if (it->first.first == ix) {
+            delete it->second;
+            it = g_ws.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
+               int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    (void)mode;
+    const uint32_t cap = nq == 1 ? (1u << 20) : std::max<uint32_t>(1u << 14, 64u * (uint32_t)k);
+    Workspace* ws = nullptr;
+    MESSI_TRY(get_workspace(ix, s, nq, cap, &ws));
+    QArgs a{};
+    a.series = ix->series;
+    a.n = ix->n;
+    a.L = ix->len;
+    a.w = ix->w;
+    a.m = ix->len / ix->w;
+    a.b = ix->b;
+    a.words = ix->words.as<uint4>();
+    a.pos = ix->pos.as<uint32_t>();
+    a.leaves = ix->leaves.as<Leaf>();
+    a.nL = (int32_t)ix->n_leaves;
+    a.bp = ix->bp.as<float>();
+    a.queries = queries;
+    a.nq = nq;
+    a.qs = ws->qs.as<QState>();
+    a.lb = ws->lb.as<float>();
+    a.order = ws->order.as<uint32_t>();
+    a.bins = ws->bins.as<uint32_t>();
+    a.cursor = ws->cursor.as<uint32_t>();
+    a.approx_d = ws->approx_d.as<float>();
+    a.cand = ws->cand.as<Cand>();
+    a.cap = cap;
+    a.absmax_data = ix->absmax;
+    int lg = 0;
+    while ((1 << lg) < a.m) ++lg;
+    a.lg_m = lg;
+    a.counters = stats ? ws->counters.as<QCounters>() : nullptr;
+    a.err_any = ws->err.as<uint32_t>();
+    a.out_idx = out_idx;
+    a.out_dist = out_dist;
+
+    hipEvent_t ev[8];
+    const bool timing = stats != nullptr;
+    if (timing)
+        for (auto& e : ev) MESSI_HIP_TRY(hipEventCreate(&e));
+    auto mark = [&](int i) -> int {
+        if (timing) MESSI_HIP_TRY(hipEventRecord(ev[i], s));
+        return MESSI_OK;
+    };
+    MESSI_HIP_TRY(hipMemsetAsync(a.err_any, 0, sizeof(uint32_t) * 4, s));
+    if (a.counters) MESSI_HIP_TRY(hipMemsetAsync(a.counters, 0, sizeof(QCounters), s));
+    MESSI_HIP_TRY(hipMemsetAsync(a.bins, 0, sizeof(uint32_t) * kNB * (size_t)nq, s));
+    MESSI_HIP_TRY(hipMemsetAsync(a.cand, 0xFF, sizeof(Cand) * (size_t)cap * nq, s));
+    MESSI_TRY(mark(0));
+    hipLaunchKernelGGL(prep_kernel, dim3(nq), dim3(256), 0, s, a, k, (uint32_t)k);
+    MESSI_LAUNCH_CHECK("prep");
+    MESSI_TRY(mark(1));
+    const unsigned lb_blocks = (unsigned)((a.nL + kLeafBlock - 1) / kLeafBlock);
+    hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("leaf_lb");
+    MESSI_TRY(mark(2));
+    hipLaunchKernelGGL(approx_ed_kernel, dim3(kApproxBlocks, nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("approx_ed");
+    hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("approx_select");
+    MESSI_TRY(mark(3));
+    hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("bin_hist");
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(nq), dim3(kNB), 0, s, a);
+    MESSI_LAUNCH_CHECK("bin_scan");
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("bin_scatter");
+    MESSI_TRY(mark(4));
+    const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
+    if (vec)
+        hipLaunchKernelGGL(scan_kernel<true>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(scan_kernel<false>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
+    MESSI_LAUNCH_CHECK("scan");
+    MESSI_TRY(mark(5));
+    hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("final");
+    MESSI_TRY(mark(6));
+    uint32_t err = 0;
+    MESSI_HIP_TRY(hipMemcpyAsync(&err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    QCounters hc{};
+    if (a.counters) MESSI_HIP_TRY(hipMemcpyAsync(&hc, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    if (timing) {
+        float ms[6];
+        for (int i = 0; i < 6; ++i) MESSI_HIP_TRY(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+        float tot = 0.f;
+        MESSI_HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev[6]));
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        stats->ms_prep = ms[0];
+        stats->ms_leaf_lb = ms[1];
+        stats->ms_approx = ms[2];
+        stats->ms_order = ms[3];
+        stats->ms_scan = ms[4];
+        stats->ms_final = ms[5];
+        stats->ms_total = tot;
+        stats->leaves_total = (int64_t)ix->n_leaves * nq;
+        stats->leaves_kept = (int64_t)hc.kept;
+        stats->leaves_scanned = (int64_t)hc.scanned;
+        stats->series_bounded = (int64_t)hc.bounded;
+        stats->series_distance = (int64_t)hc.distance;
+        stats->series_abandoned = (int64_t)hc.abandoned;
+        stats->series_recheck = (int64_t)hc.recheck;
+        stats->candidates = (int64_t)hc.final_cands;
+        stats->bytes_scan = (int64_t)hc.bytes;
+        stats->scan_launches = 1;
+    }
+    if (err & 1u) {
+        set_error(MESSI_EINVAL, "queries contain non-finite values");
+        return MESSI_EINVAL;
+    }
+    if (err & 6u) {
+        set_error(MESSI_EOVERFLOW, "too many tied candidates for the candidate buffer");
+        return MESSI_EOVERFLOW;
+    }
+    if (err & 8u) {
+        set_error(MESSI_EDEVICE, "internal error: fewer than k candidates");
+        return MESSI_EDEVICE;
+    }
+    return MESSI_OK;
+}
+
+}  // namespace messi

@@ -1,0 +1,279 @@
+"""ctypes binding of libmessi.so (include/messi.h).
+
+Argument marshalling only: every step of the index build and the search runs
+in the library's HIP kernels.  Device memory and streams come from torch.
+Loading fails loudly if the library has not been built; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmessi.so")
+
+MESSI_OK = 0
+MESSI_EINVAL = -1
+MESSI_ENOMEM = -2
+MESSI_EDEVICE = -3
+MESSI_ENODEV = -4
+MESSI_EBUSY = -5
+MESSI_EOVERFLOW = -6
+MODE_FP32 = 0
+MODE_BF16 = 1
+MAX_K = 1024
+
+EXPORTED = [
+    "messi_build", "messi_build_ex", "messi_knn", "messi_knn_ex", "messi_free", "messi_index_info",
+    "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_breakpoints", "messi_last_error",
+    "messi_server_create", "messi_server_submit", "messi_server_poll", "messi_server_clock_ms",
+    "messi_server_destroy",
+]
+
+
+class MessiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("messi error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Leaf(ctypes.Structure):
+    _fields_ = [("card", ctypes.c_uint8 * 16), ("prefix", ctypes.c_uint8 * 16),
+                ("start", ctypes.c_uint32), ("count", ctypes.c_uint32)]
+
+
+LEAF_DTYPE = np.dtype([("card", np.uint8, (16,)), ("prefix", np.uint8, (16,)),
+                       ("start", np.uint32), ("count", np.uint32)])
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("znorm", ctypes.c_int32), ("bf16_shadow", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("len", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("card_bits", ctypes.c_int32), ("leaf_cap", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
+                ("max_leaf", ctypes.c_int64), ("levels", ctypes.c_int32), ("has_bf16", ctypes.c_int32),
+                ("device_bytes", ctypes.c_uint64), ("data_absmax", ctypes.c_float),
+                ("ms_znorm", ctypes.c_double), ("ms_summarize", ctypes.c_double), ("ms_bucket", ctypes.c_double),
+                ("ms_split", ctypes.c_double), ("ms_finalize", ctypes.c_double), ("ms_shadow", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
+class KnnStats(ctypes.Structure):
+    _fields_ = [("leaves_total", ctypes.c_int64), ("leaves_kept", ctypes.c_int64),
+                ("leaves_scanned", ctypes.c_int64), ("series_bounded", ctypes.c_int64),
+                ("series_distance", ctypes.c_int64), ("series_abandoned", ctypes.c_int64),
+                ("series_recheck", ctypes.c_int64), ("candidates", ctypes.c_int64), ("bytes_scan", ctypes.c_int64),
+                ("ms_total", ctypes.c_double), ("ms_prep", ctypes.c_double), ("ms_leaf_lb", ctypes.c_double),
+                ("ms_approx", ctypes.c_double), ("ms_order", ctypes.c_double), ("ms_scan", ctypes.c_double),
+                ("ms_final", ctypes.c_double), ("scan_launches", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("k", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("t_submit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+                ("idx", ctypes.c_int64 * MAX_K), ("dist", ctypes.c_float * MAX_K)]
+
+
+_lib = None
+
+
+def load():
+    """Load libmessi.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmessi.so is not built: run python -m paper_2009_00786_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        lib.messi_build.argtypes = [vp, i64, i32, i32, i32, i32]
+        lib.messi_build.restype = vp
+        lib.messi_build_ex.argtypes = [vp, i64, i32, i32, i32, i32, ctypes.POINTER(BuildOpts)]
+        lib.messi_build_ex.restype = vp
+        lib.messi_knn.argtypes = [vp, vp, i32, i32, vp, vp]
+        lib.messi_knn.restype = ctypes.c_int
+        lib.messi_knn_ex.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, ctypes.POINTER(KnnStats)]
+        lib.messi_knn_ex.restype = ctypes.c_int
+        lib.messi_free.argtypes = [vp]
+        lib.messi_free.restype = None
+        lib.messi_index_info.argtypes = [vp, ctypes.POINTER(Info)]
+        lib.messi_index_info.restype = ctypes.c_int
+        lib.messi_export_words.argtypes = [vp, vp]
+        lib.messi_export_words.restype = ctypes.c_int
+        lib.messi_export_leaves.argtypes = [vp, vp, vp]
+        lib.messi_export_leaves.restype = ctypes.c_int
+        lib.messi_znorm.argtypes = [vp, i64, i32, vp]
+        lib.messi_znorm.restype = ctypes.c_int
+        lib.messi_breakpoints.argtypes = [i32, vp]
+        lib.messi_breakpoints.restype = ctypes.c_int
+        lib.messi_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        lib.messi_last_error.restype = ctypes.c_int
+        lib.messi_server_create.argtypes = [vp, ctypes.c_size_t, i32, i32]
+        lib.messi_server_create.restype = vp
+        lib.messi_server_submit.argtypes = [vp, vp, i32, ctypes.c_uint64]
+        lib.messi_server_submit.restype = ctypes.c_int
+        lib.messi_server_poll.argtypes = [vp, ctypes.POINTER(Result), i32]
+        lib.messi_server_poll.restype = ctypes.c_int
+        lib.messi_server_clock_ms.argtypes = [vp]
+        lib.messi_server_clock_ms.restype = ctypes.c_double
+        lib.messi_server_destroy.argtypes = [vp]
+        lib.messi_server_destroy.restype = None
+        _lib = lib
+    return _lib
+
+
+def last_error():
+    buf = ctypes.create_string_buffer(512)
+    code = load().messi_last_error(buf, 512)
+    return code, buf.value.decode(errors="replace")
+
+
+def _check(rc):
+    if rc != MESSI_OK:
+        code, msg = last_error()
+        raise MessiError(rc, msg)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def breakpoints(card_bits: int) -> np.ndarray:
+    out = np.zeros(255, dtype=np.float32)
+    _check(load().messi_breakpoints(card_bits, out.ctypes.data))
+    return out[:(1 << card_bits) - 1].copy()
+
+
+def znorm_(series, stream=None):
+    """z-normalise a CUDA fp32 tensor [n, len] in place (fp64 statistics)."""
+    assert series.is_cuda and series.dtype.is_floating_point and series.is_contiguous()
+    n, length = series.shape
+    _check(load().messi_znorm(ctypes.c_void_p(series.data_ptr()), n, length, _stream_ptr(stream)))
+    return series
+
+
+class Index:
+    """An iSAX index over a CUDA fp32 tensor [n, len]; the tensor is borrowed."""
+
+    def __init__(self, series, segments=16, card_bits=8, leaf_cap=2000, znorm=False, bf16_shadow=False,
+                 stream=None):
+        lib = load()
+        if series.is_cuda:
+            assert series.is_contiguous()
+            n, length = series.shape
+            ptr = series.data_ptr()
+        else:
+            n, length, ptr = 0, 0, 0
+        opts = BuildOpts(int(bool(znorm)), int(bool(bf16_shadow)), _stream_ptr(stream))
+        h = lib.messi_build_ex(ctypes.c_void_p(ptr) if ptr else None, n if series.is_cuda else series.shape[0],
+                               length if series.is_cuda else series.shape[1], segments, card_bits, leaf_cap,
+                               ctypes.byref(opts))
+        if not h:
+            code, msg = last_error()
+            raise MessiError(code, msg)
+        self._h = ctypes.c_void_p(h)
+        self.series = series  # keep the borrowed tensor alive
+        self.segments = segments
+        self.card_bits = card_bits
+        self.leaf_cap = leaf_cap
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().messi_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(load().messi_index_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def export_words(self) -> np.ndarray:
+        n = self.series.shape[0]
+        out = np.zeros((n, self.segments), dtype=np.uint8)
+        _check(load().messi_export_words(self._h, out.ctypes.data))
+        return out
+
+    def export_leaves(self):
+        inf = self.info()
+        leaves = np.zeros(inf["n_leaves"], dtype=LEAF_DTYPE)
+        pos = np.zeros(inf["n"], dtype=np.uint32)
+        _check(load().messi_export_leaves(self._h, leaves.ctypes.data, pos.ctypes.data))
+        return leaves, pos
+
+    def knn(self, queries, k: int, mode: int = MODE_FP32, stream=None, stats: bool = False, out=None):
+        """Exact k-NN of CUDA fp32 queries [nq, len] -> (idx int64 [nq, k], dist fp32 [nq, k]) on the GPU."""
+        import torch
+        assert queries.is_cuda and queries.dtype == torch.float32 and queries.is_contiguous()
+        nq = queries.shape[0]
+        if out is None:
+            out_idx = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
+            out_dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+        else:
+            out_idx, out_dist = out
+        st = KnnStats() if stats else None
+        rc = load().messi_knn_ex(self._h, ctypes.c_void_p(queries.data_ptr()), nq, k, mode, _stream_ptr(stream),
+                                 ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_dist.data_ptr()),
+                                 ctypes.byref(st) if st is not None else None)
+        _check(rc)
+        if stats:
+            return out_idx, out_dist, {f: getattr(st, f) for f, _ in KnnStats._fields_}
+        return out_idx, out_dist
+
+
+class Server:
+    """Continuous-batching request loop over a resident index (messi_server_*)."""
+
+    def __init__(self, index: Index, budget_bytes: int, max_slots: int = 256, mode: int = MODE_BF16):
+        h = load().messi_server_create(index.handle, budget_bytes, max_slots, mode)
+        if not h:
+            code, msg = last_error()
+            raise MessiError(code, msg)
+        self._h = ctypes.c_void_p(h)
+        self.index = index
+        self._buf = (Result * 64)()
+
+    def submit(self, query: np.ndarray, k: int, tag: int):
+        q = np.ascontiguousarray(query, dtype=np.float32)
+        rc = load().messi_server_submit(self._h, q.ctypes.data, k, tag)
+        _check(rc)
+
+    def poll(self):
+        n = load().messi_server_poll(self._h, self._buf, len(self._buf))
+        if n < 0:
+            _check(n)
+        out = []
+        for i in range(n):
+            r = self._buf[i]
+            out.append({"tag": r.tag, "k": r.k, "status": r.status, "t_submit_ms": r.t_submit_ms,
+                        "t_done_ms": r.t_done_ms, "idx": np.ctypeslib.as_array(r.idx)[:r.k].copy(),
+                        "dist": np.ctypeslib.as_array(r.dist)[:r.k].copy()})
+        return out
+
+    def clock_ms(self) -> float:
+        return load().messi_server_clock_ms(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().messi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

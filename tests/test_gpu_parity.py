@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Bars: iSAX words, leaf records, member order and neighbour indices bit-exact;
+z-normalised values bit-exact (same fp64 statistics in the same order);
+distances within 1e-5 relative of the oracle's fp64 distance.
+All calls go through the C ABI (ctypes binding)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def messi():
+    from paper_2009_00786_amd import messi as m
+    m.load()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def gpu_walks(torch, dg, n, length, seed, stream, row0=0):
+    t = torch.empty((n, length), dtype=torch.float32, device="cuda")
+    dg.gpu_random_walks(t, seed=seed, stream=stream, row0=row0)
+    return t
+
+
+# ---------------------------------------------------------------------------
+# generator and z-normalisation
+# ---------------------------------------------------------------------------
+
+def test_gpu_generator_matches_host(torch_cuda, datagen_mod):
+    torch = torch_cuda
+    _say("generator: walks 20000x256, mixture 3000x128")
+    g = gpu_walks(torch, datagen_mod, 20000, 256, 2009, 0).cpu().numpy()
+    h = datagen_mod.random_walks(20000, 256, seed=2009, stream=0)
+    np.testing.assert_array_equal(g, h)
+    cen = datagen_mod.mixture_centres(1000, 128)
+    gm = torch.empty((3000, 128), dtype=torch.float32, device="cuda")
+    datagen_mod.gpu_mixture(gm, torch.from_numpy(cen).cuda(), row0=12345)
+    hm = datagen_mod.mixture(3000, 128, cen, row0=12345)
+    np.testing.assert_array_equal(gm.cpu().numpy(), hm)
+
+
+@pytest.mark.parametrize("n,length", [(100_000, 256), (4097, 128), (3001, 96), (1000, 100), (777, 1000),
+                                      (500, 16), (33, 3), (1, 64)])
+def test_znorm_bitwise(torch_cuda, messi, datagen_mod, oracle_mod, n, length):
+    torch = torch_cuda
+    _say("znorm n=%d len=%d" % (n, length))
+    x = datagen_mod.random_walks(n, length, seed=77, stream=0)
+    x[n // 2] = 3.5  # a constant series -> zeros
+    t = torch.from_numpy(x).cuda()
+    messi.znorm_(t)
+    np.testing.assert_array_equal(t.cpu().numpy(), oracle_mod.znorm(x))
+
+
+# ---------------------------------------------------------------------------
+# index build: words, leaves, member order
+# ---------------------------------------------------------------------------
+
+BUILD_CASES = [
+    # n, len, segments, bits, cap
+    (100_000, 256, 16, 8, 2000),   # the tiny workload of the paper's setup
+    (12289, 128, 16, 8, 100),      # ragged last tile, two series per wave
+    (4097, 64, 8, 8, 10),
+    (3000, 96, 16, 8, 50),         # segment length 6: padded fold-halving path
+    (2000, 100, 4, 4, 20),         # length not a power of two, segment length 25
+    (5000, 256, 4, 1, 50),         # one bit per symbol: no splits possible
+    (3000, 1024, 16, 8, 300),      # longest supported rows
+    (50, 32, 2, 8, 1000),          # capacity above n: leaves = root children
+    (7, 16, 16, 3, 1),
+    (1, 16, 4, 8, 10),
+]
+
+
+def _oracle_index(oracle_mod, z, w, b, cap):
+    words = oracle_mod.words(z, w, b)
+    leaves, pos = oracle_mod.build_leaves(words, b, cap)
+    return words, leaves, pos
+
+
+@pytest.mark.parametrize("n,length,w,b,cap", BUILD_CASES)
+def test_build_bitwise(torch_cuda, messi, datagen_mod, oracle_mod, n, length, w, b, cap):
+    torch = torch_cuda
+    _say("build n=%d len=%d w=%d b=%d cap=%d" % (n, length, w, b, cap))
+    x = datagen_mod.random_walks(n, length, seed=2009, stream=0)
+    z = oracle_mod.znorm(x)
+    t = torch.from_numpy(x).cuda()
+    ix = messi.Index(t, segments=w, card_bits=b, leaf_cap=cap, znorm=True)
+    # the fused z-normalisation wrote the same values as the oracle
+    np.testing.assert_array_equal(t.cpu().numpy(), z)
+    ow, ol, op = _oracle_index(oracle_mod, z, w, b, cap)
+    np.testing.assert_array_equal(ix.export_words(), ow)
+    gl, gp = ix.export_leaves()
+    assert len(gl) == len(ol)
+    np.testing.assert_array_equal(gl["card"], ol["card"])
+    np.testing.assert_array_equal(gl["prefix"], ol["prefix"])
+    np.testing.assert_array_equal(gl["start"], ol["start"])
+    np.testing.assert_array_equal(gl["count"], ol["count"])
+    np.testing.assert_array_equal(gp, op)
+    info = ix.info()
+    assert info["n_leaves"] == len(ol) and info["max_leaf"] == int(ol["count"].max())
+    ix.close()
+
+
+def test_build_with_duplicates_and_overflow_leaves(torch_cuda, messi, oracle_mod):
+    torch = torch_cuda
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((3000, 64)).astype(np.float32)
+    x[100:1200] = x[5]            # > cap identical series -> an overflow leaf
+    x[2000:2010] = 1.0            # constant series
+    z = oracle_mod.znorm(x)
+    t = torch.from_numpy(z.copy()).cuda()
+    ix = messi.Index(t, segments=8, card_bits=8, leaf_cap=100)
+    ow, ol, op = _oracle_index(oracle_mod, z, 8, 8, 100)
+    np.testing.assert_array_equal(ix.export_words(), ow)
+    gl, gp = ix.export_leaves()
+    np.testing.assert_array_equal(gl["start"], ol["start"])
+    np.testing.assert_array_equal(gl["count"], ol["count"])
+    np.testing.assert_array_equal(gl["card"], ol["card"])
+    np.testing.assert_array_equal(gp, op)
+    assert ol["count"].max() > 100
+
+
+# ---------------------------------------------------------------------------
+# exact k-NN
+# ---------------------------------------------------------------------------
+
+def _check_answers(gidx, gdist, oidx, od64):
+    np.testing.assert_array_equal(gidx, oidx)
+    ref = np.sqrt(od64)
+    err = np.abs(gdist.astype(np.float64) - ref) / np.maximum(ref, 1e-30)
+    assert np.all((err <= REL_TOL) | (ref == 0) & (gdist == 0)), float(err.max())
+
+
+@pytest.fixture(scope="module")
+def tiny_workload(torch_cuda, messi, datagen_mod, oracle_mod):
+    """100,000 z-normalised random walks of length 256 (16 segments, 8 bits,
+    leaf capacity 2000) and 10 fresh walks as queries."""
+    torch = torch_cuda
+    x = datagen_mod.random_walks(100_000, 256)
+    z = oracle_mod.znorm(x)
+    t = torch.from_numpy(x).cuda()
+    ix = messi.Index(t, 16, 8, 2000, znorm=True)
+    qr = datagen_mod.random_walks(10, 256, seed=datagen_mod.SEED_QUERY, stream=datagen_mod.STREAM_QUERY)
+    qz = oracle_mod.znorm(qr)
+    qt = torch.from_numpy(qr).cuda()
+    messi.znorm_(qt)
+    np.testing.assert_array_equal(qt.cpu().numpy(), qz)
+    yield {"z": z, "ix": ix, "qz": qz, "qt": qt}
+    ix.close()
+
+
+def test_knn_single_queries_k1(tiny_workload, oracle_mod):
+    w = tiny_workload
+    _say("knn tiny workload, single queries, k=1")
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], w["qz"], 1, nthreads=8)
+    for i in range(10):
+        gi, gd = w["ix"].knn(w["qt"][i:i + 1], 1)
+        _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx[i:i + 1], od[i:i + 1])
+
+
+@pytest.mark.parametrize("k", [1, 2, 10, 100])
+def test_knn_batched(tiny_workload, oracle_mod, datagen_mod, torch_cuda, k):
+    torch = torch_cuda
+    w = tiny_workload
+    _say("knn tiny workload, batched, k=%d" % k)
+    rows = datagen_mod.uniform_ints(6, 100_000, 9, 5)
+    qn = datagen_mod.add_noise(w["z"][rows], [0.01, 0.1, 1.0, 0.01, 0.1, 1.0])
+    q = np.concatenate([w["qz"], qn])
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], q, k, nthreads=8)
+    gi, gd, st = w["ix"].knn(torch.from_numpy(q).cuda(), k, stats=True)
+    _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    assert st["series_distance"] < 100_000 * len(q)  # pruning happened
+    _say("  stats", st)
+
+
+def test_knn_matches_oracle_isax_counts(tiny_workload, oracle_mod):
+    """The oracle's pruned search and the GPU give the same answers."""
+    w = tiny_workload
+    words = oracle_mod.words(w["z"], 16, 8)
+    leaves, pos = oracle_mod.build_leaves(words, 8, 2000)
+    oi, od, _ = oracle_mod.knn_isax(w["z"], words, 8, leaves, pos, w["qz"][:3], 5)
+    gi, gd = w["ix"].knn(w["qt"][:3].contiguous(), 5)
+    _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oi, od)
+
+
+KNN_EDGE = [
+    # n, len, w, b, cap, k
+    (1, 16, 4, 8, 10, 1),
+    (7, 16, 16, 3, 1, 7),          # k = n
+    (64, 32, 8, 8, 4, 64),
+    (4097, 64, 8, 8, 10, 3),
+    (3000, 96, 16, 8, 50, 5),
+    (2000, 100, 4, 4, 20, 4),      # scalar row path
+    (5000, 256, 4, 1, 50, 2),
+    (3000, 1024, 16, 8, 300, 1),
+    (12289, 128, 16, 8, 2000, 17),
+]
+
+
+@pytest.mark.parametrize("n,length,w,b,cap,k", KNN_EDGE)
+def test_knn_shapes(torch_cuda, messi, datagen_mod, oracle_mod, n, length, w, b, cap, k):
+    torch = torch_cuda
+    _say("knn n=%d len=%d w=%d b=%d cap=%d k=%d" % (n, length, w, b, cap, k))
+    z = oracle_mod.znorm(datagen_mod.random_walks(n, length, seed=31, stream=0))
+    q = oracle_mod.znorm(datagen_mod.random_walks(4, length, seed=32, stream=1))
+    q = np.concatenate([q, z[[0, n - 1]]])
+    t = torch.from_numpy(z).cuda()
+    ix = messi.Index(t, w, b, cap)
+    oidx, od, _ = oracle_mod.knn_brute(z, q, k, nthreads=8)
+    gi, gd = ix.knn(torch.from_numpy(q).cuda(), k)
+    _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    for i in range(len(q)):  # one query at a time, too
+        gi1, gd1 = ix.knn(torch.from_numpy(q[i:i + 1]).cuda(), k)
+        _check_answers(gi1.cpu().numpy(), gd1.cpu().numpy(), oidx[i:i + 1], od[i:i + 1])
+    ix.close()
+
+
+def test_knn_ties_and_degenerate(torch_cuda, messi, oracle_mod):
+    torch = torch_cuda
+    _say("knn ties and degenerate series")
+    rng = np.random.default_rng(7)
+    z = oracle_mod.znorm(rng.standard_normal((3000, 64)).astype(np.float32))
+    z[100:400] = z[7]             # 301 identical rows (overflow leaf at cap 50)
+    z[500:520] = 0.0              # constant series
+    q = np.concatenate([z[[7, 500, 2999]], rng.standard_normal((2, 64)).astype(np.float32)])
+    t = torch.from_numpy(z).cuda()
+    ix = messi.Index(t, 8, 8, 50)
+    for k in (1, 5, 40, 350):
+        oidx, od, _ = oracle_mod.knn_brute(z, q, k, nthreads=8)
+        gi, gd = ix.knn(torch.from_numpy(q).cuda(), k)
+        _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    gi, gd = ix.knn(torch.from_numpy(z[150:151].copy()).cuda(), 3)
+    assert list(gi.cpu().numpy()[0]) == [7, 100, 101]
+
+
+def test_knn_nq_zero_and_errors(torch_cuda, messi):
+    torch = torch_cuda
+    z = torch.randn((100, 32), device="cuda")
+    messi.znorm_(z)
+    ix = messi.Index(z, 4, 8, 10)
+    empty = torch.empty((0, 32), device="cuda")
+    gi, gd = ix.knn(empty, 1)
+    assert gi.shape == (0, 1)
+    with pytest.raises(messi.MessiError) as e:
+        ix.knn(z[:1].contiguous(), 101)
+    assert e.value.code == messi.MESSI_EINVAL
+    bad = z[:1].clone()
+    bad[0, 3] = float("nan")
+    with pytest.raises(messi.MessiError) as e:
+        ix.knn(bad, 1)
+    assert e.value.code == messi.MESSI_EINVAL
+    import ctypes
+    host = np.zeros((1, 32), dtype=np.float32)
+    out_i = torch.empty((1, 1), dtype=torch.int64, device="cuda")
+    out_d = torch.empty((1, 1), dtype=torch.float32, device="cuda")
+    rc = messi.load().messi_knn(ix.handle, ctypes.c_void_p(host.ctypes.data), 1, 1,
+                                ctypes.c_void_p(out_i.data_ptr()), ctypes.c_void_p(out_d.data_ptr()))
+    assert rc == messi.MESSI_EINVAL
+    x = torch.randn((50, 32), device="cuda")
+    x[3, 3] = float("inf")
+    with pytest.raises(messi.MessiError) as e:
+        messi.Index(x, 4, 8, 10)
+    assert e.value.code == messi.MESSI_EINVAL
+    with pytest.raises(messi.MessiError):
+        messi.Index(x, 5, 8, 10)   # 32 % 5 != 0
+    ix.close()
