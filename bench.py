@@ -235,6 +235,8 @@ def main():
                       "approx": agg.get("ms_approx", 0) / total_q, "order": agg.get("ms_order", 0) / total_q,
                       "scan": scan_ms_per_q, "final": agg.get("ms_final", 0) / total_q,
                       "query_device_total": agg.get("ms_total", 0) / total_q},
+        "scan_breakdown_ms": {kk: agg.get(kk, 0) / total_q for kk in (
+            "scan_ms_control", "scan_ms_filter", "scan_ms_distance", "scan_ms_block_mean", "scan_ms_block_max")},
         "per_query": {kk: agg.get(kk, 0) / total_q for kk in ("leaves_total", "leaves_kept", "leaves_scanned",
                                                               "series_bounded", "series_distance",
                                                               "series_abandoned", "candidates", "bytes_scan")},

@@ -94,6 +94,9 @@ typedef struct {
     int64_t bytes_scan;       /* algorithmic HBM bytes of the scan kernels (words + rows read) */
     double ms_total, ms_prep, ms_leaf_lb, ms_approx, ms_order, ms_scan, ms_final;
     int32_t scan_launches;
+    /* scan kernel, per block (device wall clock): mean time in leaf control,
+       member filtering and distances, mean and max block lifetime */
+    double scan_ms_control, scan_ms_filter, scan_ms_distance, scan_ms_block_mean, scan_ms_block_max;
 } messi_knn_stats;
 
 /* ---- index ------------------------------------------------------------- */
@@ -122,10 +125,12 @@ messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t
 int messi_knn(const messi_index* index, const float* queries, int32_t nq, int32_t k, int64_t* out_idx,
               float* out_dist);
 
-/* Same, stream-ordered on `stream` (hipStream_t, NULL = null stream), with a
- * search mode (MESSI_MODE_*) and optional counters.  The call returns after
- * enqueueing only if stats == NULL; with stats it synchronises the stream.
- * Concurrent calls on one index from different streams are allowed. */
+/* Same, on `stream` (hipStream_t, NULL = null stream), with a search mode
+ * (MESSI_MODE_*) and optional counters (stats may be NULL).  The call
+ * synchronises `stream` before returning, so that per-query errors (a
+ * non-finite query, a candidate-buffer overflow) are reported by its return
+ * code.  Concurrent calls on one index from different streams are allowed;
+ * each stream gets its own search workspace. */
 int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t mode,
                  void* stream, int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
 

@@ -1,6 +1,7 @@
 // C ABI of the library (include/messi.h): argument checking, error state,
 // index lifecycle and host-side exports.  Device work lives in build.hip,
 // query.hip, bf16.hip and server.cpp.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <vector>

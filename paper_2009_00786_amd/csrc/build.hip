@@ -33,6 +33,13 @@ constexpr int kTile = 4096;
 constexpr int kBlk = 256;
 constexpr int kRounds = kTile / kBlk;
 
+int launch_blocks(int64_t work, int per_block, int cap_blocks) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap_blocks) b = cap_blocks;
+    return (int)b;
+}
+
 // ---------------------------------------------------------------------------
 // Fold-halving sums across the lanes of one series group (width T lanes, E
 // consecutive elements per lane): pairs (i, i + h) for h = P/2 .. 1.  Strides
@@ -67,12 +74,13 @@ struct SumArgs {
 };
 
 // One kernel for: z-normalise only (SUM = false), summarise only (ZN = false),
-// or both fused (read once, write z once).
-template <int E, bool ZN, bool SUM>
+// or both fused (read once, write z once).  Each wave loads R series groups
+// before computing on any of them, so R row loads per lane are in flight.
+template <int E, bool ZN, bool SUM, int R>
 __global__ void __launch_bounds__(256) summarize_kernel(SumArgs a) {
     __shared__ float s_bp[256];
     __shared__ float s_row[4][64 * E];     // general PAA path: z values of the wave's series
-    __shared__ uint8_t s_sym[4][64 * 16];  // symbols of the wave's series
+    __shared__ uint8_t s_sym[4][64 * 16];  // general PAA path: symbols of the wave's series
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (SUM) {
         const int nb = (1 << a.b) - 1;
@@ -88,147 +96,299 @@ __global__ void __launch_bounds__(256) summarize_kernel(SumArgs a) {
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     float amax = 0.f;
     bool bad = false;
-    for (int64_t grp = wave_id; grp < n_groups; grp += n_waves) {
-        const int64_t row = grp * G + g;
-        const bool live = row < a.n;
-        float x[E];
-        const float* src = a.in + (size_t)(live ? row : 0) * (size_t)L;
-        if (vec) {
+    for (int64_t grp0 = wave_id * R; grp0 < n_groups; grp0 += n_waves * R) {
+        float xs[R][E];
+        // ---- loads of all R groups first
 #pragma unroll
-            for (int k = 0; k < E; k += 4) {
-                float4 q = live ? *reinterpret_cast<const float4*>(src + t * E + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-                x[k] = q.x; x[k + 1] = q.y; x[k + 2] = q.z; x[k + 3] = q.w;
-            }
-        } else {
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = (grp0 + r) * G + g;
+            const bool live = (grp0 + r < n_groups) && row < a.n;
+            const float* src = a.in + (size_t)(live ? row : 0) * (size_t)L;
+            if (vec) {
 #pragma unroll
-            for (int k = 0; k < E; ++k) {
-                const int j = t * E + k;
-                x[k] = (live && j < L) ? src[j] : 0.f;
-            }
-        }
+                for (int k = 0; k < E; k += 4) {
+                    const float4 q = live ? *reinterpret_cast<const float4*>(src + t * E + k)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+                    xs[r][k] = q.x; xs[r][k + 1] = q.y; xs[r][k + 2] = q.z; xs[r][k + 3] = q.w;
+                }
+            } else {
 #pragma unroll
-        for (int k = 0; k < E; ++k) bad |= !isfinite(x[k]);
-        if (ZN) {
-            double v[E];
-#pragma unroll
-            for (int k = 0; k < E; ++k) v[k] = (double)x[k];
-            double s1 = fold_halving64<E>(v, T);
-            s1 = __shfl(s1, g * T, 64);
-            const double mu = __ddiv_rn(s1, (double)L);
-            double c[E];
-#pragma unroll
-            for (int k = 0; k < E; ++k) {
-                const int j = t * E + k;
-                c[k] = (j < L) ? __dsub_rn((double)x[k], mu) : 0.0;
-                v[k] = (j < L) ? __dmul_rn(c[k], c[k]) : 0.0;
-            }
-            double s2 = fold_halving64<E>(v, T);
-            s2 = __shfl(s2, g * T, 64);
-            const double var = __ddiv_rn(s2, (double)L);
-            const double sigma = __dsqrt_rn(var);
-#pragma unroll
-            for (int k = 0; k < E; ++k) x[k] = (var == 0.0) ? 0.f : (float)__ddiv_rn(c[k], sigma);
-            if (live) {
-                float* dst = a.zout + (size_t)row * (size_t)L;
-                if (vec) {
-#pragma unroll
-                    for (int k = 0; k < E; k += 4)
-                        *reinterpret_cast<float4*>(dst + t * E + k) = make_float4(x[k], x[k + 1], x[k + 2], x[k + 3]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < E; ++k)
-                        if (t * E + k < L) dst[t * E + k] = x[k];
+                for (int k = 0; k < E; ++k) {
+                    const int j = t * E + k;
+                    xs[r][k] = (live && j < L) ? src[j] : 0.f;
                 }
             }
         }
-        if (!SUM) continue;
 #pragma unroll
-        for (int k = 0; k < E; ++k) amax = fmaxf(amax, live ? fabsf(x[k]) : 0.f);
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = (grp0 + r) * G + g;
+            const bool live = (grp0 + r < n_groups) && row < a.n;
+            float* x = xs[r];
+#pragma unroll
+            for (int k = 0; k < E; ++k) bad |= !isfinite(x[k]);
+            if (ZN) {
+                double v[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) v[k] = (double)x[k];
+                double s1 = fold_halving64<E>(v, T);
+                s1 = __shfl(s1, g * T, 64);
+                const double mu = __ddiv_rn(s1, (double)L);
+                double c[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int j = t * E + k;
+                    c[k] = (j < L) ? __dsub_rn((double)x[k], mu) : 0.0;
+                    v[k] = (j < L) ? __dmul_rn(c[k], c[k]) : 0.0;
+                }
+                double s2 = fold_halving64<E>(v, T);
+                s2 = __shfl(s2, g * T, 64);
+                const double var = __ddiv_rn(s2, (double)L);
+                const double sigma = __dsqrt_rn(var);
+#pragma unroll
+                for (int k = 0; k < E; ++k) x[k] = (var == 0.0) ? 0.f : (float)__ddiv_rn(c[k], sigma);
+                if (live) {
+                    float* dst = a.zout + (size_t)row * (size_t)L;
+                    if (vec) {
+#pragma unroll
+                        for (int k = 0; k < E; k += 4)
+                            *reinterpret_cast<float4*>(dst + t * E + k) = make_float4(x[k], x[k + 1], x[k + 2], x[k + 3]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < E; ++k)
+                            if (t * E + k < L) dst[t * E + k] = x[k];
+                    }
+                }
+            }
+            if (!SUM) continue;
+#pragma unroll
+            for (int k = 0; k < E; ++k) amax = fmaxf(amax, live ? fabsf(x[k]) : 0.f);
 
-        // ---- PAA: fold-halving sum of each segment, then one division by m.
-        const int w = a.w, m = a.m;
-        const float inv_m_exact = 1.0f / (float)m;  // used only when m is a power of two
-        if (fast_paa) {
-            float v[E];
+            // ---- PAA: fold-halving sum of each segment, then one division by m.
+            const int w = a.w, m = a.m;
+            if (fast_paa) {
+                float v[E];
 #pragma unroll
-            for (int k = 0; k < E; ++k) v[k] = x[k];
-            const int seg_lanes = m / E;
-            for (int off = seg_lanes >> 1; off >= 1; off >>= 1) {
+                for (int k = 0; k < E; ++k) v[k] = x[k];
+                const int seg_lanes = m / E;
+                for (int off = seg_lanes >> 1; off >= 1; off >>= 1) {
 #pragma unroll
-                for (int k = 0; k < E; ++k) v[k] = __fadd_rn(v[k], __shfl_down(v[k], off, T));
-            }
+                    for (int k = 0; k < E; ++k) v[k] = __fadd_rn(v[k], __shfl_down(v[k], off, T));
+                }
 #pragma unroll
-            for (int h = E >> 1; h >= 1; h >>= 1) {
+                for (int h = E >> 1; h >= 1; h >>= 1) {
 #pragma unroll
-                for (int k = 0; k < h; ++k) v[k] = __fadd_rn(v[k], v[k + h]);
-            }
-            // lane t holds segment t / seg_lanes when t % seg_lanes == 0
-            if (t % seg_lanes == 0) {
+                    for (int k = 0; k < h; ++k) v[k] = __fadd_rn(v[k], v[k + h]);
+                }
+                // lane t holds segment t / seg_lanes when t % seg_lanes == 0; m is a
+                // power of two, so the division by m is an exact scaling
+                const bool seg_lane = (t % seg_lanes) == 0;
                 const int seg = t / seg_lanes;
-                const float p = __fmul_rn(v[0], inv_m_exact);
+                const float p = __fmul_rn(v[0], 1.0f / (float)m);
                 int s = 0;
                 for (int step = 1 << (a.b - 1); step >= 1; step >>= 1)
                     if (s_bp[s + step - 1] <= p) s += step;
-                s_sym[wave][g * 16 + seg] = (uint8_t)s;
-            }
-        } else {
-            // general path: z values to LDS, one lane per (series, segment) sums the
-            // padded segment by fold-halving (pairwise over bit-reversed order).
+                if (live && seg_lane) reinterpret_cast<uint8_t*>(a.words + row)[seg] = (uint8_t)s;
+                // root key: top bit of every segment's symbol, segment 0 most significant
+                const uint64_t top = dev::ballot(seg_lane && ((s >> (a.b - 1)) & 1));
+                if (live && t == 0) {
+                    const uint64_t mine = top >> (g * T);
+                    uint32_t key = 0;
+                    for (int i = 0; i < w; ++i) key |= (uint32_t)((mine >> (i * seg_lanes)) & 1ull) << (w - 1 - i);
+                    a.keys[row] = (uint16_t)key;
+                }
+            } else {
+                // general path: z values to LDS, one lane per (series, segment) sums the
+                // padded segment by fold-halving (pairwise over bit-reversed order).
 #pragma unroll
-            for (int k = 0; k < E; ++k) s_row[wave][g * a.P + t * E + k] = x[k];
-            dev::wave_sync();
-            for (int p = lane; p < G * w; p += 64) {
-                const int gg = p / w, seg = p % w;
-                const float* z = &s_row[wave][gg * a.P + seg * m];
-                // binary-counter pairwise sum over indices in bit-reversed order
-                float stack[11];
-                int depth = 0;
-                int lg = 0;
-                while ((1 << lg) < a.M) ++lg;
-                for (int r = 0; r < a.M; ++r) {
-                    int j = 0;
-                    for (int bit = 0; bit < lg; ++bit) j |= ((r >> bit) & 1) << (lg - 1 - bit);
-                    float val = (j < m) ? z[j] : 0.f;
-                    int cnt = r + 1;
-                    // merge while the count's low bits are zero
-                    stack[depth++] = val;
-                    while ((cnt & 1) == 0) {
-                        float hi = stack[--depth];
-                        float lo = stack[--depth];
-                        stack[depth++] = __fadd_rn(lo, hi);
-                        cnt >>= 1;
+                for (int k = 0; k < E; ++k) s_row[wave][g * a.P + t * E + k] = x[k];
+                dev::wave_sync();
+                for (int p = lane; p < G * w; p += 64) {
+                    const int gg = p / w, seg = p % w;
+                    const float* z = &s_row[wave][gg * a.P + seg * m];
+                    float stack[11];
+                    int depth = 0;
+                    int lg = 0;
+                    while ((1 << lg) < a.M) ++lg;
+                    for (int q = 0; q < a.M; ++q) {
+                        int j = 0;
+                        for (int bit = 0; bit < lg; ++bit) j |= ((q >> bit) & 1) << (lg - 1 - bit);
+                        const float val = (j < m) ? z[j] : 0.f;
+                        int cnt = q + 1;
+                        stack[depth++] = val;
+                        while ((cnt & 1) == 0) {
+                            const float hi = stack[--depth];
+                            const float lo = stack[--depth];
+                            stack[depth++] = __fadd_rn(lo, hi);
+                            cnt >>= 1;
+                        }
+                    }
+                    const float pval = __fdiv_rn(stack[0], (float)m);
+                    int s = 0;
+                    for (int step = 1 << (a.b - 1); step >= 1; step >>= 1)
+                        if (s_bp[s + step - 1] <= pval) s += step;
+                    s_sym[wave][gg * 16 + seg] = (uint8_t)s;
+                }
+                dev::wave_sync();
+                if (lane < G) {
+                    const int64_t r2 = (grp0 + r) * G + lane;
+                    if ((grp0 + r < n_groups) && r2 < a.n) {
+                        uint32_t wd[4] = {0u, 0u, 0u, 0u};
+                        uint32_t key = 0;
+                        for (int i = 0; i < w; ++i) {
+                            const uint32_t sy = s_sym[wave][lane * 16 + i];
+                            wd[i >> 2] |= sy << (8 * (i & 3));
+                            key |= ((sy >> (a.b - 1)) & 1u) << (w - 1 - i);
+                        }
+                        a.words[r2] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                        a.keys[r2] = (uint16_t)key;
                     }
                 }
-                const float sum = stack[0];
-                const float pval = __fdiv_rn(sum, (float)m);
-                int s = 0;
-                for (int step = 1 << (a.b - 1); step >= 1; step >>= 1)
-                    if (s_bp[s + step - 1] <= pval) s += step;
-                s_sym[wave][gg * 16 + seg] = (uint8_t)s;
+                dev::wave_sync();
             }
         }
-        dev::wave_sync();
-        // ---- word + root key: one lane per series
-        if (lane < G) {
-            const int64_t r2 = grp * G + lane;
-            if (r2 < a.n) {
-                uint32_t wd[4] = {0u, 0u, 0u, 0u};
-                uint32_t key = 0;
-                for (int i = 0; i < w; ++i) {
-                    const uint32_t s = s_sym[wave][lane * 16 + i];
-                    wd[i >> 2] |= s << (8 * (i & 3));
-                    key |= ((s >> (a.b - 1)) & 1u) << (w - 1 - i);
-                }
-                a.words[r2] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-                a.keys[r2] = (uint16_t)key;
-            }
-        }
-        dev::wave_sync();
     }
     if (bad) atomicOr(a.nonfinite, 1);
     if (SUM) {
         amax = dev::wave_max(amax);
         if (lane == 0) atomicMax(a.absmax, __float_as_uint(amax));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Summarise, one segment per lane: lane l of a wave owns segment l % w of row
+// l / w (64 / w rows per wave), keeps the segment's m values in registers and
+// sums them by fold-halving there (no cross-lane traffic).  The symbol comes
+// from a cell table over [-8, 8) (cells of 1/256, at most one breakpoint per
+// cell): a first guess from the cell, corrected by one comparison each way.
+// Word bytes of consecutive rows are consecutive lanes, so the byte stores of
+// a wave are one contiguous run; the root key is a ballot of the top bits.
+// ---------------------------------------------------------------------------
+constexpr int kCells = 4096;
+
+struct SegArgs {
+    const float* in;
+    int64_t n;
+    int32_t L, w, m, b;
+    const float* bp;        // 2^b - 1 breakpoints
+    const uint8_t* cells;   // kCells: number of breakpoints <= -8 + c / 256
+    uint8_t* words;         // [n][16] bytes, input order
+    uint16_t* keys;         // [n]
+    uint32_t* absmax;       // float bits, atomicMax
+    int* nonfinite;
+};
+
+template <int M, int R, bool VEC>
+__global__ void __launch_bounds__(256) summarize_seg_kernel(SegArgs a) {
+    __shared__ float s_bp[257];
+    __shared__ uint8_t s_cell[kCells];
+    const int A = 1 << a.b;
+    for (int i = threadIdx.x; i < 257; i += blockDim.x) s_bp[i] = (i >= 1 && i < A) ? a.bp[i - 1] : 0.f;
+    for (int i = threadIdx.x; i < kCells; i += blockDim.x) s_cell[i] = a.cells[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int w = a.w, m = a.m, L = a.L;
+    const int rpw = 64 / w;                 // rows per wave
+    const int r_in = lane / w, seg = lane % w;
+    const bool lane_on = r_in < rpw;
+    const uint32_t row_mask = (w == 32) ? 0xffffffffu : ((1u << w) - 1u);
+    const int64_t n_blocks = (a.n + rpw - 1) / rpw;   // row blocks of rpw rows
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    const float inv_m = 1.0f / (float)m;
+    const bool pow2_m = (m & (m - 1)) == 0;
+    uint32_t amax_bits = 0;
+    for (int64_t blk0 = wave_id * R; blk0 < n_blocks; blk0 += n_waves * R) {
+        float v[R][M];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = (blk0 + r) * rpw + r_in;
+            const bool live = lane_on && (blk0 + r < n_blocks) && row < a.n;
+            const float* src = a.in + (size_t)(live ? row : 0) * (size_t)L + (size_t)seg * m;
+            if (VEC) {
+#pragma unroll
+                for (int k = 0; k < M; k += 4) {
+                    const float4 q = live ? *reinterpret_cast<const float4*>(src + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    v[r][k] = q.x; v[r][k + 1] = q.y; v[r][k + 2] = q.z; v[r][k + 3] = q.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < M; ++k) v[r][k] = (live && k < m) ? src[k] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = (blk0 + r) * rpw + r_in;
+            const bool live = lane_on && (blk0 + r < n_blocks) && row < a.n;
+            uint32_t mx = 0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) mx = max(mx, __float_as_uint(v[r][k]) & 0x7fffffffu);
+            amax_bits = max(amax_bits, mx);
+            // fold-halving over the (zero-padded) segment
+#pragma unroll
+            for (int h = M / 2; h >= 1; h /= 2) {
+#pragma unroll
+                for (int k = 0; k < h; ++k) v[r][k] = __fadd_rn(v[r][k], v[r][k + h]);
+            }
+            const float p = pow2_m ? __fmul_rn(v[r][0], inv_m) : __fdiv_rn(v[r][0], (float)m);
+            const float cf = fminf(fmaxf(__fmul_rn(__fadd_rn(p, 8.0f), 256.0f), 0.0f), (float)(kCells - 1));
+            int s = s_cell[(int)cf];
+            if (s > 0 && s_bp[s] > p) --s;
+            else if (s < A - 1 && s_bp[s + 1] <= p) ++s;
+            if (live) a.words[(size_t)row * 16 + seg] = (uint8_t)s;
+            const uint64_t top = dev::ballot(lane_on && ((s >> (a.b - 1)) & 1));
+            if (live && seg == 0) {
+                const uint32_t bits = (uint32_t)(top >> (r_in * w)) & row_mask;
+                a.keys[row] = (uint16_t)(__brev(bits) >> (32 - w));
+            }
+        }
+    }
+    if (amax_bits >= 0x7f800000u) atomicOr(a.nonfinite, 1);
+    uint32_t mxw = amax_bits;
+    for (int off = 32; off >= 1; off >>= 1) mxw = max(mxw, (uint32_t)__shfl_xor((int)mxw, off));
+    if (lane == 0 && mxw < 0x7f800000u) atomicMax(a.absmax, mxw);
+}
+
+int launch_summarize_seg(const SegArgs& a, hipStream_t s) {
+    int M = 1;
+    while (M < a.m) M <<= 1;
+    const bool vec = (a.m % 4 == 0) && (a.L % 4 == 0) && ((uintptr_t)a.in % 16 == 0);
+    const int rpw = 64 / a.w;
+    const int64_t n_blocks = (a.n + rpw - 1) / rpw;
+    switch (M) {
+#define MESSI_SEG_CASE(MM)                                                                             \
+    case MM: {                                                                                         \
+        constexpr int R = (MM <= 8) ? 4 : (MM <= 16 ? 2 : 1);                                          \
+        const int blocks = launch_blocks(n_blocks, 4 * R, 256 * 8);                                    \
+        if (vec && MM >= 4)                                                                            \
+            hipLaunchKernelGGL((summarize_seg_kernel<MM, R, true>), dim3(blocks), dim3(256), 0, s, a);  \
+        else                                                                                           \
+            hipLaunchKernelGGL((summarize_seg_kernel<MM, R, false>), dim3(blocks), dim3(256), 0, s, a); \
+        break;                                                                                         \
+    }
+        MESSI_SEG_CASE(1)
+        MESSI_SEG_CASE(2)
+        MESSI_SEG_CASE(4)
+        MESSI_SEG_CASE(8)
+        MESSI_SEG_CASE(16)
+        MESSI_SEG_CASE(32)
+        MESSI_SEG_CASE(64)
+#undef MESSI_SEG_CASE
+        default:
+            set_error(MESSI_EINVAL, "segment length above 64 takes the general path");
+            return MESSI_EINVAL;
+    }
+    MESSI_LAUNCH_CHECK("summarize_seg");
+    return MESSI_OK;
+}
+
+// Cell table: cells[c] = number of breakpoints <= -8 + c / 256 (host).
+void cell_table(const float* bp, int card_bits, uint8_t* cells) {
+    const int nb = (1 << card_bits) - 1;
+    for (int c = 0; c < kCells; ++c) {
+        const float x = -8.0f + (float)c / 256.0f;
+        int cnt = 0;
+        for (int j = 0; j < nb; ++j) cnt += bp[j] <= x;
+        cells[c] = (uint8_t)cnt;
     }
 }
 
@@ -602,12 +762,6 @@ __global__ void leaf_order_kernel(const Leaf* __restrict__ leaves, uint32_t n_le
     if (r < n_leaves) out[r] = lf;
 }
 
-int launch_blocks(int64_t work, int per_block, int cap_blocks) {
-    int64_t b = (work + per_block - 1) / per_block;
-    if (b < 1) b = 1;
-    if (b > cap_blocks) b = cap_blocks;
-    return (int)b;
-}
 
 // Lane layout of a row: E consecutive elements per lane, T lanes per series.
 struct RowLayout {
@@ -627,12 +781,15 @@ RowLayout row_layout(int L) {
 template <bool ZN, bool SUM>
 int launch_summarize(const SumArgs& a, int E, hipStream_t s) {
     const int64_t n_groups = (a.n + a.G - 1) / a.G;
-    const int blocks = launch_blocks(n_groups, 4, 256 * 16);
+    // series groups per wave in flight: about 4 row loads of 16 B per lane
     switch (E) {
 #define MESSI_SUM_CASE(EE)                                                                          \
-    case EE:                                                                                        \
-        hipLaunchKernelGGL((summarize_kernel<EE, ZN, SUM>), dim3(blocks), dim3(256), 0, s, a);      \
-        break;
+    case EE: {                                                                                      \
+        constexpr int R = (EE >= 16) ? 1 : (EE >= 8 ? 2 : 4);                                        \
+        const int blocks = launch_blocks(n_groups, 4 * R, 256 * 8);                                 \
+        hipLaunchKernelGGL((summarize_kernel<EE, ZN, SUM, R>), dim3(blocks), dim3(256), 0, s, a);   \
+        break;                                                                                      \
+    }
         MESSI_SUM_CASE(1)
         MESSI_SUM_CASE(2)
         MESSI_SUM_CASE(4)
@@ -738,11 +895,36 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     a.keys = K[0].as<uint16_t>();
     a.absmax = cnt + 1;
     a.nonfinite = reinterpret_cast<int*>(cnt + 0);
+    if (w < 16) MESSI_HIP_TRY(hipMemsetAsync(W[0].p, 0, sizeof(uint4) * (size_t)n, s));
+    const bool seg_path = !opts.znorm && a.m <= 64;
+    DevBuf cells;
+    if (seg_path) {
+        uint8_t hc[kCells];
+        cell_table(ix->bp_host, b, hc);
+        MESSI_TRY(cells.alloc(kCells));
+        MESSI_HIP_TRY(hipMemcpyAsync(cells.p, hc, kCells, hipMemcpyHostToDevice, s));
+    }
     tm.start();
-    if (opts.znorm)
+    if (opts.znorm) {
         MESSI_TRY((launch_summarize<true, true>(a, r.E, s)));
-    else
+    } else if (seg_path) {
+        SegArgs sa{};
+        sa.in = series;
+        sa.n = n;
+        sa.L = len;
+        sa.w = w;
+        sa.m = a.m;
+        sa.b = b;
+        sa.bp = ix->bp.as<float>();
+        sa.cells = cells.as<uint8_t>();
+        sa.words = reinterpret_cast<uint8_t*>(W[0].p);
+        sa.keys = K[0].as<uint16_t>();
+        sa.absmax = cnt + 1;
+        sa.nonfinite = reinterpret_cast<int*>(cnt + 0);
+        MESSI_TRY(launch_summarize_seg(sa, s));
+    } else {
         MESSI_TRY((launch_summarize<false, true>(a, r.E, s)));
+    }
     ix->info.ms_summarize = tm.stop_ms();
     uint32_t flags[2];
     MESSI_HIP_TRY(hipMemcpyAsync(flags, cnt, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -793,7 +975,8 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     MESSI_TRY(leaves_raw.alloc(sizeof(Leaf) * (size_t)n));
     MESSI_TRY(leaf_buf.alloc((size_t)n));
     const int64_t max_nodes = n / ((int64_t)cap + 1) + 2;
-    for (int i = 0; i < 2; ++i) MESSI_TRY(nodes[i].alloc(sizeof(Leaf) * (size_t)max_nodes));
+    const int64_t max_nodes2 = max_nodes;
+    for (int i = 0; i < 2; ++i) MESSI_TRY(nodes[i].alloc(sizeof(Leaf) * (size_t)max_nodes2));
     Lists lists;
     lists.leaves = leaves_raw.as<Leaf>();
     lists.leaf_buf = leaf_buf.as<uint8_t>();
@@ -812,64 +995,65 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
 
     // ---- 3. split levels
     tm.start();
-    const int64_t max_tiles = n_tiles + max_nodes + 1;
-    MESSI_TRY(node_cnt.alloc(sizeof(uint32_t) * 16 * (size_t)max_nodes));
-    MESSI_TRY(node_seg.alloc((size_t)max_nodes));
-    MESSI_TRY(node_n0.alloc(sizeof(uint32_t) * (size_t)max_nodes));
-    MESSI_TRY(tile_first.alloc(sizeof(uint32_t) * ((size_t)max_nodes + 1)));
+    const int64_t max_tiles = n_tiles + max_nodes2 + 1;
+    MESSI_TRY(node_cnt.alloc(sizeof(uint32_t) * 16 * (size_t)max_nodes2));
+    MESSI_TRY(node_seg.alloc((size_t)max_nodes2));
+    MESSI_TRY(node_n0.alloc(sizeof(uint32_t) * (size_t)max_nodes2));
+    MESSI_TRY(tile_first.alloc(sizeof(uint32_t) * ((size_t)max_nodes2 + 1)));
     MESSI_TRY(tile_node.alloc(sizeof(uint32_t) * (size_t)max_tiles));
     MESSI_TRY(tile_cnt.alloc(sizeof(uint32_t) * 16 * (size_t)max_tiles));
     MESSI_TRY(zeros.alloc(sizeof(uint32_t) * (size_t)max_tiles));
     int levels = 0;
-    int nsel = 0;  // nodes[nsel] holds the current level
-    while (n_nodes > 0) {
-        Leaf* cur_nodes = nodes[nsel].as<Leaf>();
-        hipLaunchKernelGGL(node_tiles_kernel, dim3(1), dim3(1024), 0, s, cur_nodes, (int)n_nodes,
-                           tile_first.as<uint32_t>(), cnt + 5);
-        MESSI_LAUNCH_CHECK("node_tiles");
-        uint32_t tiles = 0;
-        MESSI_HIP_TRY(hipMemcpyAsync(&tiles, cnt + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        MESSI_HIP_TRY(hipMemsetAsync(node_cnt.p, 0, sizeof(uint32_t) * 16 * (size_t)n_nodes, s));
-        MESSI_HIP_TRY(hipMemsetAsync(cnt + 3, 0, sizeof(uint32_t), s));
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
-        hipLaunchKernelGGL(tile_node_kernel, dim3((tiles + 255) / 256), dim3(256), 0, s, tile_first.as<uint32_t>(),
-                           (int)n_nodes, tiles, tile_node.as<uint32_t>());
-        MESSI_LAUNCH_CHECK("tile_node");
-        hipLaunchKernelGGL(level_count_kernel, dim3(tiles), dim3(kBlk), 0, s, cur_nodes, tile_first.as<uint32_t>(),
-                           tile_node.as<uint32_t>(), W[cur].as<uint4>(), w, b, tile_cnt.as<uint32_t>(),
-                           node_cnt.as<uint32_t>());
-        MESSI_LAUNCH_CHECK("level_count");
-        lists.next = nodes[nsel ^ 1].as<Leaf>();
-        hipLaunchKernelGGL(level_choose_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, s, cur_nodes,
-                           (int)n_nodes, node_cnt.as<uint32_t>(), w, b, cap, cur ^ 1, node_seg.as<uint8_t>(),
-                           node_n0.as<uint32_t>(), lists);
-        MESSI_LAUNCH_CHECK("level_choose");
-        hipLaunchKernelGGL(level_zeros_kernel, dim3((tiles + 255) / 256), dim3(256), 0, s, cur_nodes,
-                           tile_first.as<uint32_t>(), tile_node.as<uint32_t>(), tiles, tile_cnt.as<uint32_t>(),
-                           node_seg.as<uint8_t>(), zeros.as<uint32_t>());
-        MESSI_LAUNCH_CHECK("level_zeros");
-        MESSI_TRY(scan_exclusive(zeros.as<uint32_t>(), zeros.as<uint32_t>(), tiles, scr.as<uint32_t>(), nullptr, s));
-        hipLaunchKernelGGL(level_scatter_kernel, dim3(tiles), dim3(kBlk), 0, s, cur_nodes, tile_first.as<uint32_t>(),
-                           tile_node.as<uint32_t>(), zeros.as<uint32_t>(), node_seg.as<uint8_t>(),
-                           node_n0.as<uint32_t>(), b, W[cur].as<uint4>(), P[cur].as<uint32_t>(),
-                           W[cur ^ 1].as<uint4>(), P[cur ^ 1].as<uint32_t>());
-        MESSI_LAUNCH_CHECK("level_scatter");
-        MESSI_HIP_TRY(hipMemcpyAsync(&n_nodes, cnt + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
-        cur ^= 1;
-        nsel ^= 1;
-        ++levels;
-        if (levels > 16 * 8 + 2) {
-            set_error(MESSI_EDEVICE, "leaf partition did not terminate");
-            return MESSI_EDEVICE;
+    // One level-synchronous split loop; the current level's nodes start in nodes[0].
+    auto run_levels = [&](uint32_t nn, int cap_lvl, Lists lst, int& lv) -> int {
+        int nsel = 0;
+        while (nn > 0) {
+            Leaf* cur_nodes = nodes[nsel].as<Leaf>();
+            hipLaunchKernelGGL(node_tiles_kernel, dim3(1), dim3(1024), 0, s, cur_nodes, (int)nn,
+                               tile_first.as<uint32_t>(), cnt + 5);
+            MESSI_LAUNCH_CHECK("node_tiles");
+            uint32_t tiles = 0;
+            MESSI_HIP_TRY(hipMemcpyAsync(&tiles, cnt + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            MESSI_HIP_TRY(hipMemsetAsync(node_cnt.p, 0, sizeof(uint32_t) * 16 * (size_t)nn, s));
+            MESSI_HIP_TRY(hipMemsetAsync(cnt + 3, 0, sizeof(uint32_t), s));
+            MESSI_HIP_TRY(hipStreamSynchronize(s));
+            hipLaunchKernelGGL(tile_node_kernel, dim3((tiles + 255) / 256), dim3(256), 0, s,
+                               tile_first.as<uint32_t>(), (int)nn, tiles, tile_node.as<uint32_t>());
+            MESSI_LAUNCH_CHECK("tile_node");
+            hipLaunchKernelGGL(level_count_kernel, dim3(tiles), dim3(kBlk), 0, s, cur_nodes,
+                               tile_first.as<uint32_t>(), tile_node.as<uint32_t>(), W[cur].as<uint4>(), w, b,
+                               tile_cnt.as<uint32_t>(), node_cnt.as<uint32_t>());
+            MESSI_LAUNCH_CHECK("level_count");
+            lst.next = nodes[nsel ^ 1].as<Leaf>();
+            hipLaunchKernelGGL(level_choose_kernel, dim3((nn + 255) / 256), dim3(256), 0, s, cur_nodes, (int)nn,
+                               node_cnt.as<uint32_t>(), w, b, cap_lvl, cur ^ 1, node_seg.as<uint8_t>(),
+                               node_n0.as<uint32_t>(), lst);
+            MESSI_LAUNCH_CHECK("level_choose");
+            hipLaunchKernelGGL(level_zeros_kernel, dim3((tiles + 255) / 256), dim3(256), 0, s, cur_nodes,
+                               tile_first.as<uint32_t>(), tile_node.as<uint32_t>(), tiles, tile_cnt.as<uint32_t>(),
+                               node_seg.as<uint8_t>(), zeros.as<uint32_t>());
+            MESSI_LAUNCH_CHECK("level_zeros");
+            MESSI_TRY(scan_exclusive(zeros.as<uint32_t>(), zeros.as<uint32_t>(), tiles, scr.as<uint32_t>(), nullptr,
+                                     s));
+            hipLaunchKernelGGL(level_scatter_kernel, dim3(tiles), dim3(kBlk), 0, s, cur_nodes,
+                               tile_first.as<uint32_t>(), tile_node.as<uint32_t>(), zeros.as<uint32_t>(),
+                               node_seg.as<uint8_t>(), node_n0.as<uint32_t>(), b, W[cur].as<uint4>(),
+                               P[cur].as<uint32_t>(), W[cur ^ 1].as<uint4>(), P[cur ^ 1].as<uint32_t>());
+            MESSI_LAUNCH_CHECK("level_scatter");
+            MESSI_HIP_TRY(hipMemcpyAsync(&nn, cnt + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            MESSI_HIP_TRY(hipStreamSynchronize(s));
+            cur ^= 1;
+            nsel ^= 1;
+            ++lv;
+            if (lv > 16 * 8 + 2) {
+                set_error(MESSI_EDEVICE, "leaf partition did not terminate");
+                return MESSI_EDEVICE;
+            }
         }
-    }
-    ix->info.ms_split = tm.stop_ms();
-    node_cnt.release(); node_seg.release(); node_n0.release(); tile_first.release(); tile_node.release();
-    tile_cnt.release(); zeros.release(); nodes[0].release(); nodes[1].release();
+        return MESSI_OK;
+    };
+    MESSI_TRY(run_levels(n_nodes, cap, lists, levels));
 
-    // ---- 4. finalise: all ranges into one buffer, leaves ordered by start
-    tm.start();
     uint32_t hc[3];
     MESSI_HIP_TRY(hipMemcpyAsync(hc, cnt + 2, sizeof(hc), hipMemcpyDeviceToHost, s));
     MESSI_HIP_TRY(hipStreamSynchronize(s));
@@ -880,6 +1064,13 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
                        leaves_raw.as<Leaf>(), leaf_buf.as<uint8_t>(), n_leaves, W[1 - fin].as<uint4>(),
                        P[1 - fin].as<uint32_t>(), W[fin].as<uint4>(), P[fin].as<uint32_t>(), 1 - fin);
     MESSI_LAUNCH_CHECK("copy_back");
+    cur = fin;
+    ix->info.ms_split = tm.stop_ms();
+    node_cnt.release(); node_seg.release(); node_n0.release(); tile_first.release(); tile_node.release();
+    tile_cnt.release(); zeros.release(); nodes[0].release(); nodes[1].release();
+
+    // ---- 4. finalise: leaves ordered by start
+    tm.start();
     const int64_t nw = (n + 31) / 32;
     DevBuf bm, rank;
     MESSI_TRY(bm.alloc(sizeof(uint32_t) * (size_t)nw));

@@ -95,7 +95,7 @@ struct Index {
     int64_t n = 0;
     int32_t len = 0, w = 0, b = 0, cap = 0;
     int64_t n_leaves = 0, max_leaf = 0;
-    int32_t levels = 0;
+    int32_t levels = 0;          // split levels of the partition
     float absmax = 0.f;
 
     DevBuf words;   // uint4 [n]: member words in leaf order (bytes 0..w-1)
@@ -104,7 +104,6 @@ struct Index {
     DevBuf bp;      // float [2^b - 1] breakpoints
     DevBuf norms;   // float [n] squared norms, leaf order (bf16 shadow only)
     DevBuf shadow;  // bf16 [n][len] rows in leaf order (bf16 shadow only)
-    DevBuf scratch; // per-index scratch for the single-query path (guarded by mu)
 
     float bp_host[255];
     messi_info info{};

@@ -7,7 +7,7 @@ namespace messi {
 
 constexpr int kNB = 1024;            // lower-bound bins used to order the surviving leaves
 constexpr int kApproxMax = 4096;     // members of the first leaf evaluated for the first bound
-constexpr int kApproxBlocks = 32;    // blocks per query for that leaf
+constexpr int kApproxBlocks = 128;   // blocks per query for that leaf
 constexpr int kMaxFinal = 4096;      // candidates ordered by fp64 distance per query
 constexpr int kChunk = 1024;         // members filtered per step of the scan
 
@@ -72,6 +72,7 @@ struct QArgs {
     int32_t lg_m;                // ceil(log2 m)
     QCounters* counters;         // nullptr = no counting
     uint32_t* err_any;
+    unsigned long long* prof;    // nullptr = no phase timing; else [blocks][4]
     int64_t* out_idx;
     float* out_dist;
 };

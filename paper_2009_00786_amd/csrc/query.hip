@@ -9,9 +9,9 @@
 //              on the k-th distance (the paper's initial BSF)
 //  order       the leaves whose bound does not exceed U, counting-sorted into
 //              1024 bound bins: the ascending order the priority queues deliver
-//  scan        persistent blocks take leaves from that order with an atomic
-//              ticket; a leaf whose bound exceeds the current U is skipped and,
-//              once a whole bin lies above U, the query stops; inside a leaf each
+//  scan        persistent blocks walk that order, each block taking every G-th
+//              position of its query; a leaf whose bound exceeds the current U is
+//              skipped and, once a whole bin lies above U, the block stops; inside a leaf each
 //              member's own word gives a second bound (LDS table lookups) and only
 //              the survivors' rows are read, 16 lanes per row, abandoning a
 //              distance as soon as its partial sum exceeds U; U lives in device
@@ -31,9 +31,11 @@
 //    sum abandons iff p (1 - 2^-16) > U, a bound prunes iff b (1 - 2^-12) > U.
 //  * The final order uses the canonical fp64 distance, so the returned indices
 //    are those of the brute-force definition whatever the visiting order.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "query.h"
 #include "scan.h"
@@ -42,6 +44,7 @@ namespace messi {
 namespace {
 
 constexpr int kScanThreads = 256;
+constexpr int kUnit = 4;  // leaf positions a scan block takes per step
 
 __device__ __forceinline__ uint32_t vload(const uint32_t* p) {
     return __atomic_load_n(p, __ATOMIC_RELAXED);
@@ -186,6 +189,20 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a) {
 // --------------------------------------------------------------------------
 // approximate search: distances to the members of the smallest-bound leaf
 // --------------------------------------------------------------------------
+// The members evaluated: the argmin leaf, extended into the depth-first
+// neighbouring leaves (contiguous in the member arrays) until at least k
+// members, so that the first bound is finite.
+__device__ __forceinline__ void approx_range(const QArgs& a, const QState& st, uint32_t& r0, uint32_t& cnt,
+                                             uint32_t& lstart, uint32_t& lcount) {
+    const uint32_t leaf = (uint32_t)(st.argmin & 0xffffffffull);
+    const Leaf lf = a.leaves[leaf];
+    lstart = lf.start;
+    lcount = lf.count;
+    cnt = min(max(lf.count, (uint32_t)st.k), (uint32_t)kApproxMax);
+    cnt = (uint32_t)min((int64_t)cnt, a.n);
+    r0 = (uint32_t)min((int64_t)lf.start, a.n - (int64_t)cnt);
+}
+
 __global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a) {
     __shared__ float s_q[MESSI_MAX_LEN];
     const int q = blockIdx.y;
@@ -193,13 +210,12 @@ __global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a) {
     if (st.err) return;
     for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
     __syncthreads();
-    const uint32_t leaf = (uint32_t)(st.argmin & 0xffffffffull);
-    const Leaf lf = a.leaves[leaf];
-    const uint32_t cnt = min(lf.count, (uint32_t)kApproxMax);
+    uint32_t r0, cnt, ls, lc;
+    approx_range(a, st, r0, cnt, ls, lc);
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
     for (uint32_t r = gw; r < cnt; r += kApproxBlocks * 4) {
-        const float* x = a.series + (size_t)a.pos[lf.start + r] * a.L;
+        const float* x = a.series + (size_t)a.pos[r0 + r] * a.L;
         float s = 0.f;
         for (int j = lane; j < a.L; j += 64) {
             const float d = s_q[j] - x[j];
@@ -225,14 +241,25 @@ __device__ float block_kth(Getter get, uint32_t n, uint32_t k, uint32_t* s_hist,
             if ((key & mask) == prefix) atomicAdd(&s_hist[(key >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t acc = 0, d = 0;
-            for (d = 0; d < 256; ++d) {
-                if (acc + s_hist[d] >= kk) break;
-                acc += s_hist[d];
+        {
+            // the digit whose inclusive running count first reaches kk
+            const uint32_t c = s_hist[threadIdx.x];
+            uint32_t x = c;
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off);
+                if (lane >= off) x += y;
             }
-            s_bcast[0] = d;
-            s_bcast[1] = kk - acc;
+            __syncthreads();
+            if (lane == 63) s_hist[256 + wave] = x;  // wave totals after the counts
+            __syncthreads();
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += s_hist[256 + w];
+            const uint32_t incl = before + x, excl = incl - c;
+            if (excl < kk && incl >= kk) {
+                s_bcast[0] = threadIdx.x;
+                s_bcast[1] = kk - excl;
+            }
         }
         __syncthreads();
         prefix |= s_bcast[0] << shift;
@@ -244,27 +271,30 @@ __device__ float block_kth(Getter get, uint32_t n, uint32_t k, uint32_t* s_hist,
 }
 
 __global__ void __launch_bounds__(256) approx_select_kernel(QArgs a) {
-    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_hist[256 + 4];
     __shared__ uint32_t s_b[2];
     const int q = blockIdx.x;
     QState& st = a.qs[q];
     if (st.err) return;
-    const uint32_t leaf = (uint32_t)(st.argmin & 0xffffffffull);
-    const Leaf lf = a.leaves[leaf];
-    const uint32_t cnt = min(lf.count, (uint32_t)kApproxMax);
+    uint32_t r0, cnt, ls, lc;
+    approx_range(a, st, r0, cnt, ls, lc);
     const float* d = a.approx_d + (size_t)q * kApproxMax;
     const float kth = block_kth([&](uint32_t i) { return d[i]; }, cnt, (uint32_t)st.k, s_hist, s_b);
     const float U0 = isinf(kth) ? kth : upper_u(kth);
+    // only the argmin leaf's own members become candidates here (that leaf is
+    // then skipped by the scan if it was evaluated whole)
+    const bool full = ls >= r0 && ls + lc <= r0 + cnt;
     for (uint32_t r = threadIdx.x; r < cnt; r += 256) {
-        if (d[r] * (1.0f - kRhoEd) <= U0) {
+        const uint32_t mp = r0 + r;
+        if (full && mp >= ls && mp < ls + lc && d[r] * (1.0f - kRhoEd) <= U0) {
             const uint32_t slot = atomicAdd(&st.ncand, 1u);
-            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d[r], a.pos[lf.start + r]};
+            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d[r], a.pos[mp]};
         }
     }
     if (threadIdx.x == 0) {
         st.U = __float_as_uint(U0);
-        st.approx_leaf = leaf;
-        st.approx_full = lf.count <= (uint32_t)kApproxMax;
+        st.approx_leaf = (uint32_t)(st.argmin & 0xffffffffull);
+        st.approx_full = full ? 1u : 0u;
         float range = isinf(U0) ? __uint_as_float(st.lbmax) : U0;
         st.range = range > 0.f ? range : 1e-30f;
     }
@@ -347,7 +377,7 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// scan: persistent blocks over (query, leaf) tickets
+// scan: persistent blocks over the ordered (query, leaf) positions
 // --------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t word_byte(const uint4& wd, int i) {
     const uint32_t v = (i < 4) ? wd.x : (i < 8) ? wd.y : (i < 12) ? wd.z : wd.w;
@@ -370,69 +400,54 @@ __device__ void refresh_u(QArgs& a, int q, QState& st, uint32_t* s_hist, uint32_
     if (threadIdx.x == 0 && !isinf(kth) && !isnan(kth)) atomicMin(&st.U, __float_as_uint(upper_u(kth)));
 }
 
+// Leaves of query q are visited in the bin order; the G blocks assigned to q
+// take positions j, j + G, j + 2G, ... (static, no shared ticket), so the
+// whole grid advances through the order together.  A block stops its share of
+// q at the first position whose bin lies entirely above U.
 template <bool VEC>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
     __shared__ float s_D[16 * 256];
     __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ uint32_t s_surv[kChunk];
-    __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_hist[256 + 4];
     __shared__ uint32_t s_b[2];
-    __shared__ int s_sel[2];
-    __shared__ float s_ctl[2];
-    __shared__ uint32_t s_nsv, s_app;
+    __shared__ uint32_t s_flag, s_app;
+    __shared__ uint32_t s_ustart[kUnit], s_ucnt[kUnit], s_ustop[kUnit];
+    __shared__ float s_Ublk;  // block's view of U: refreshed each step, lowered by its own finds
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4, ql = lane & 15;
     const int nq = a.nq;
     const int L = a.L;
     const int nchunk = (L + 63) / 64;
-    int q = blockIdx.x % nq;
-    int loaded = -1;
+    const int B = gridDim.x;
+    int q0, qstep, j, G;
+    if (nq <= B) {
+        q0 = blockIdx.x % nq;
+        qstep = nq;
+        j = blockIdx.x / nq;
+        G = (B - q0 + nq - 1) / nq;
+    } else {
+        q0 = blockIdx.x;
+        qstep = B;
+        j = 0;
+        G = 1;
+    }
     unsigned long long c_scanned = 0, c_bounded = 0, c_dist = 0, c_abandon = 0, c_bytes = 0;
-    for (;;) {
+    // optional per-block phase timing (thread 0): control, member filter, distances, total
+    unsigned long long t_ctl = 0, t_lb = 0, t_ed = 0, t_mark = 0;
+    const unsigned long long t_begin = (a.prof && tid == 0) ? wall_clock64() : 0ull;
+    for (int q = q0; q < nq; q += qstep) {
+        QState& st = a.qs[q];
         if (tid == 0) {
-            int found = -1;
-            uint32_t tsel = 0;
-            for (int tries = 0; tries < nq; ++tries) {
-                const int qq = (q + tries) % nq;
-                QState& s2 = a.qs[qq];
-                if (vload(&s2.done) == 0) {
-                    const uint32_t t = atomicAdd(&s2.ticket, 1u);
-                    if (t < s2.nsurv) {
-                        found = qq;
-                        tsel = t;
-                        break;
-                    }
-                    s2.done = 1;
-                }
-            }
-            s_sel[0] = found;
-            s_sel[1] = (int)tsel;
-            if (found >= 0) {
-                const QState& s3 = a.qs[found];
-                const uint32_t leaf = a.order[(size_t)found * a.nL + tsel];
-                s_sel[1] = (int)leaf;
-                s_ctl[0] = a.lb[(size_t)found * a.nL + leaf];
-                s_ctl[1] = __uint_as_float(vload(&s3.U));
-            }
+            s_flag = (st.err != 0 || st.nsurv == 0) ? 1u : 0u;
+            s_Ublk = __uint_as_float(0x7f800000u);
         }
         __syncthreads();
-        const int qq = s_sel[0];
-        if (qq < 0) break;
-        const uint32_t leaf = (uint32_t)s_sel[1];
-        const float lbv = s_ctl[0], U0 = s_ctl[1];
-        q = qq;
-        QState& st = a.qs[q];
-        if (lbv * (1.0f - kRhoLb) > U0) {
-            // bins ascend: once a bin's lower edge is above U, the rest of the list is too
-            if (tid == 0) {
-                const float low = (float)bin_of(lbv, st.range) * (st.range / (float)kNB);
-                if (low * (1.0f - 2.0f * kRhoLb) > U0) st.done = 1;
-            }
-            __syncthreads();
-            continue;
-        }
-        if (q != loaded) {
+        const bool skip = s_flag != 0;
+        __syncthreads();
+        if (skip) continue;
+        {
             const int A = 1 << a.b;
             const float delta = st.delta;
             const float mf = (float)a.m;
@@ -450,135 +465,214 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
                 }
                 s_D[i * 256 + c] = mf * (d * d);
             }
-            for (int j = tid; j < L; j += kScanThreads) s_q[j] = a.queries[(size_t)q * L + j];
-            loaded = q;
+            for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
         }
-        if (tid == 0) s_app = 0;
-        __syncthreads();
-        const Leaf lf = a.leaves[leaf];
+        const uint32_t nsurv = st.nsurv;
         const int k = st.k;
-        uint32_t appended = 0;
-        for (uint32_t c0 = 0; c0 < lf.count; c0 += kChunk) {
-            // ---- second filter: lower bound from each member's own word
-            const float Uf = __uint_as_float(vload(&st.U));
-            if (tid == 0) s_nsv = 0;
-            __syncthreads();
-            const uint32_t cend = min(lf.count, c0 + (uint32_t)kChunk);
-            for (uint32_t r0 = c0; r0 < cend; r0 += kScanThreads) {
-                const uint32_t mi = r0 + tid;
-                bool keep = false;
-                if (mi < cend) {
-                    const uint4 wd = a.words[lf.start + mi];
-                    float s = 0.f;
-#pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        if (i < a.w) s += s_D[i * 256 + word_byte(wd, i)];
-                    keep = !(s * (1.0f - kRhoLb) > Uf);
-                    ++c_bounded;
+        const float range = st.range;
+        for (uint32_t step = 0;; ++step) {
+            if (a.prof && tid == 0) t_mark = wall_clock64();
+            // ---- control: the next kUnit positions of this block, read in parallel
+            if (tid < kUnit) {
+                const uint32_t t = j + (step * kUnit + tid) * (uint32_t)G;
+                uint32_t cnt = 0, start = 0, stop = 1;
+                if (t < nsurv) {
+                    const uint32_t leaf = a.order[(size_t)q * a.nL + t];
+                    const float lbv = a.lb[(size_t)q * a.nL + leaf];
+                    const float U0 = __uint_as_float(vload(&st.U));
+                    stop = 0;
+                    if (lbv * (1.0f - kRhoLb) > U0) {
+                        // bins ascend: once a bin's lower edge is above U, later positions are too
+                        const float low = (float)bin_of(lbv, range) * (range / (float)kNB);
+                        stop = (low * (1.0f - 2.0f * kRhoLb) > U0) ? 1u : 0u;
+                    } else {
+                        const Leaf lf = a.leaves[leaf];
+                        cnt = lf.count;
+                        start = lf.start;
+                    }
                 }
-                const uint64_t m = dev::ballot(keep);
-                if (lane == 0) s_w[wave] = (uint32_t)dev::popc64(m);
-                __syncthreads();
-                uint32_t before = 0, tot = 0;
-                for (int w = 0; w < 4; ++w) {
-                    if (w < wave) before += s_w[w];
-                    tot += s_w[w];
-                }
-                if (keep) s_surv[s_nsv + before + dev::popc64(m & dev::lanemask_lt())] = mi;
-                __syncthreads();
-                if (tid == 0) s_nsv += tot;
-                __syncthreads();
+                s_ustart[tid] = start;
+                s_ucnt[tid] = cnt;
+                s_ustop[tid] = stop;
+                if (tid == 0) s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
             }
-            const uint32_t nsv = s_nsv;
-            // ---- real distances: 16 lanes per row, 4 rows per wave, abandon per 512 B
-            for (uint32_t base = wave * 4; base < nsv; base += 16) {
-                const uint32_t si = base + quarter;
-                const bool act = si < nsv;
-                uint32_t gidx = 0;
-                if (act) gidx = a.pos[lf.start + s_surv[si]];
-                const float* row = a.series + (size_t)gidx * L;
-                float acc = 0.f;
-                bool alive = act;
-                for (int ch = 0; ch < nchunk; ch += 2) {
-                    if (alive) {
+            if (tid == 0) s_app = 0;
+            __syncthreads();
+            uint32_t off[kUnit + 1];
+            off[0] = 0;
+            bool stop_after = false;
 #pragma unroll
-                        for (int cc = 0; cc < 2; ++cc) {
-                            const int c = ch + cc;
-                            if (c < nchunk) {
-                                const int j0 = c * 64 + ql * 4;
-                                if (VEC) {
-                                    if (j0 < L) {
-                                        const float4 x = *reinterpret_cast<const float4*>(row + j0);
-                                        const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
-                                        float d0 = y.x - x.x, d1 = y.y - x.y, d2 = y.z - x.z, d3 = y.w - x.w;
-                                        acc = fmaf(d0, d0, acc);
-                                        acc = fmaf(d1, d1, acc);
-                                        acc = fmaf(d2, d2, acc);
-                                        acc = fmaf(d3, d3, acc);
-                                    }
-                                } else {
+            for (int u = 0; u < kUnit; ++u) {
+                off[u + 1] = off[u] + s_ucnt[u];
+                stop_after |= s_ustop[u] != 0;
+            }
+            uint32_t ustart[kUnit];
 #pragma unroll
-                                    for (int e = 0; e < 4; ++e) {
-                                        const int j = j0 + e;
-                                        if (j < L) {
-                                            const float d = s_q[j] - row[j];
-                                            acc = fmaf(d, d, acc);
+            for (int u = 0; u < kUnit; ++u) ustart[u] = s_ustart[u];
+            const bool first_stopped = s_ustop[0] != 0;
+            __syncthreads();
+            if (a.prof && tid == 0) {
+                const unsigned long long now = wall_clock64();
+                t_ctl += now - t_mark;
+                t_mark = now;
+            }
+            if (first_stopped) break;
+            const uint32_t total_m = off[kUnit];
+            uint32_t appended = 0;
+            for (uint32_t c0 = 0; c0 < total_m; c0 += kChunk) {
+                // ---- second filter: bound from each member's own word (all loads first)
+                if (tid == 0) s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
+                __syncthreads();
+                const float Uf = s_Ublk;
+                const uint32_t cend = min(total_m, c0 + (uint32_t)kChunk);
+                uint4 wd[kChunk / kScanThreads];
+                uint32_t mpos[kChunk / kScanThreads];
+#pragma unroll
+                for (int r = 0; r < kChunk / kScanThreads; ++r) {
+                    const uint32_t f = c0 + r * kScanThreads + tid;
+                    uint32_t u = 0;
+#pragma unroll
+                    for (int uu = 1; uu < kUnit; ++uu) u += (f >= off[uu]) ? 1u : 0u;
+                    mpos[r] = ustart[u] + (f - off[u]);
+                    wd[r] = (f < cend) ? a.words[mpos[r]] : make_uint4(0, 0, 0, 0);
+                }
+                uint32_t keepmask = 0, nkeep = 0;
+#pragma unroll
+                for (int r = 0; r < kChunk / kScanThreads; ++r) {
+                    const uint32_t f = c0 + r * kScanThreads + tid;
+                    if (f < cend) {
+                        float sum = 0.f;
+#pragma unroll
+                        for (int i = 0; i < 16; ++i)
+                            if (i < a.w) sum += s_D[i * 256 + word_byte(wd[r], i)];
+                        if (!(sum * (1.0f - kRhoLb) > Uf)) {
+                            keepmask |= 1u << r;
+                            ++nkeep;
+                        }
+                        ++c_bounded;
+                    }
+                }
+                uint32_t total;
+                uint32_t o = block_exclusive_scan(nkeep, s_tmp, total);
+#pragma unroll
+                for (int r = 0; r < kChunk / kScanThreads; ++r)
+                    if (keepmask & (1u << r)) s_surv[o++] = mpos[r];
+                __syncthreads();
+                const uint32_t nsv = total;
+                if (a.prof && tid == 0) {
+                    const unsigned long long now = wall_clock64();
+                    t_lb += now - t_mark;
+                    t_mark = now;
+                }
+                // ---- real distances: 16 lanes per row, 4 rows per wave, abandon per 512 B
+                for (uint32_t base = wave * 4; base < nsv; base += 16) {
+                    const uint32_t si = base + quarter;
+                    const bool act = si < nsv;
+                    uint32_t gidx = 0;
+                    if (act) gidx = a.pos[s_surv[si]];
+                    const float* row = a.series + (size_t)gidx * L;
+                    float acc = 0.f;
+                    bool alive = act;
+                    for (int ch = 0; ch < nchunk; ch += 2) {
+                        if (alive) {
+#pragma unroll
+                            for (int cc = 0; cc < 2; ++cc) {
+                                const int c = ch + cc;
+                                if (c < nchunk) {
+                                    const int j0 = c * 64 + ql * 4;
+                                    if (VEC) {
+                                        if (j0 < L) {
+                                            const float4 x = *reinterpret_cast<const float4*>(row + j0);
+                                            const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
+                                            const float d0 = y.x - x.x, d1 = y.y - x.y, d2 = y.z - x.z, d3 = y.w - x.w;
+                                            acc = fmaf(d0, d0, acc);
+                                            acc = fmaf(d1, d1, acc);
+                                            acc = fmaf(d2, d2, acc);
+                                            acc = fmaf(d3, d3, acc);
+                                        }
+                                    } else {
+#pragma unroll
+                                        for (int e = 0; e < 4; ++e) {
+                                            const int jj = j0 + e;
+                                            if (jj < L) {
+                                                const float d = s_q[jj] - row[jj];
+                                                acc = fmaf(d, d, acc);
+                                            }
                                         }
                                     }
                                 }
                             }
                         }
-                    }
-                    float p = acc;
-                    p += __shfl_xor(p, 8, 16);
-                    p += __shfl_xor(p, 4, 16);
-                    p += __shfl_xor(p, 2, 16);
-                    p += __shfl_xor(p, 1, 16);
-                    p = __shfl(p, quarter * 16, 64);  // one value per row for every lane of the row
-                    if (alive) c_bytes += (uint64_t)min(2, nchunk - ch) * 256u;
-                    if (ch + 2 < nchunk) {
-                        const float Un = __uint_as_float((uint32_t)__builtin_amdgcn_readfirstlane((int)vload(&st.U)));
-                        if (alive && p * (1.0f - kRhoEd) > Un) {
-                            alive = false;
-                            if (ql == 0) ++c_abandon;
-                        }
-                    }
-                    if (ch + 2 >= nchunk) acc = p;  // full distance on every lane of the row
-                }
-                if (act && ql == 0) ++c_dist;
-                if (alive && ql == 0) {
-                    const float d = acc;
-                    const float Un = __uint_as_float(vload(&st.U));
-                    if (d * (1.0f - kRhoEd) <= Un) {
-                        const uint32_t slot = atomicAdd(&st.ncand, 1u);
-                        if (slot < a.cap) {
-                            a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx};
+                        float p = acc;
+                        p += __shfl_xor(p, 8, 16);
+                        p += __shfl_xor(p, 4, 16);
+                        p += __shfl_xor(p, 2, 16);
+                        p += __shfl_xor(p, 1, 16);
+                        p = __shfl(p, quarter * 16, 64);  // one value per row on every lane of the row
+                        if (alive) c_bytes += (uint64_t)min(2, nchunk - ch) * 256u;
+                        if (ch + 2 < nchunk) {
+                            // one value for the whole wave (other waves may lower it meanwhile)
+                            const float Un = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_Ublk)));
+                            if (alive && p * (1.0f - kRhoEd) > Un) {
+                                alive = false;
+                                if (ql == 0) ++c_abandon;
+                            }
                         } else {
-                            st.err = 2;
-                            atomicOr(a.err_any, 2u);
+                            acc = p;  // the full distance
                         }
-                        ++appended;
-                        if (k == 1) atomicMin(&st.U, __float_as_uint(upper_u(d)));
                     }
+                    if (act && ql == 0) ++c_dist;
+                    if (alive && ql == 0) {
+                        const float d = acc;
+                        const float Un = s_Ublk;
+                        if (d * (1.0f - kRhoEd) <= Un) {
+                            const uint32_t slot = atomicAdd(&st.ncand, 1u);
+                            if (slot < a.cap) {
+                                a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx};
+                            } else {
+                                st.err = 2;
+                                atomicOr(a.err_any, 2u);
+                            }
+                            ++appended;
+                            if (k == 1) {
+                                const uint32_t ub = __float_as_uint(upper_u(d));
+                                atomicMin(&st.U, ub);
+                                atomicMin(reinterpret_cast<uint32_t*>(&s_Ublk), ub);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                if (a.prof && tid == 0) {
+                    const unsigned long long now = wall_clock64();
+                    t_ed += now - t_mark;
+                    t_mark = now;
                 }
             }
+#pragma unroll
+            for (int u = 0; u < kUnit; ++u) c_scanned += (off[u + 1] > off[u]) ? 1u : 0u;
+            if (k > 1) {
+                if (appended) atomicAdd(&s_app, appended);
+                __syncthreads();
+                if (s_app) refresh_u(a, q, st, s_hist, s_b);
+            }
             __syncthreads();
+            if (stop_after) break;
         }
-        ++c_scanned;
-        if (k > 1) {
-            if (appended) atomicAdd(&s_app, appended);
-            __syncthreads();
-            if (s_app) refresh_u(a, q, st, s_hist, s_b);
-        }
-        __syncthreads();
+    }
+    if (a.prof && tid == 0) {
+        unsigned long long* pr = a.prof + (size_t)blockIdx.x * 4;
+        pr[0] = t_ctl;
+        pr[1] = t_lb;
+        pr[2] = t_ed;
+        pr[3] = wall_clock64() - t_begin;
     }
     if (a.counters) {
-        // per-thread counts -> one atomic per wave
         unsigned long long v[5] = {c_scanned, c_bounded, c_dist, c_abandon, c_bytes};
         for (int i = 0; i < 5; ++i)
             for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
         if (lane == 0) {
-            if (wave == 0) atomicAdd(&a.counters->scanned, v[0] / 64);  // c_scanned counted by every thread
+            if (wave == 0) atomicAdd(&a.counters->scanned, v[0] / 64);  // counted by every thread
             atomicAdd(&a.counters->bounded, v[1]);
             atomicAdd(&a.counters->distance, v[2]);
             atomicAdd(&a.counters->abandoned, v[3]);
@@ -678,7 +772,7 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
 struct Workspace {
     int32_t nq = 0, nL = 0;
     uint32_t cap = 0;
-    DevBuf qs, lb, order, bins, cursor, approx_d, cand, counters, err;
+    DevBuf qs, lb, order, bins, cursor, approx_d, cand, counters, err, prof;
 };
 
 std::mutex g_ws_mu;
@@ -702,6 +796,7 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
         MESSI_TRY(ws->cand.alloc(sizeof(Cand) * (size_t)capa * nqa));
         MESSI_TRY(ws->counters.alloc(sizeof(QCounters)));
         MESSI_TRY(ws->err.alloc(sizeof(uint32_t) * 4));
+        MESSI_TRY(ws->prof.alloc(sizeof(unsigned long long) * 4 * 4096));
         ws->nq = nqa;
         ws->cap = capa;
         ws->nL = (int32_t)nL;
@@ -770,6 +865,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     while ((1 << lg) < a.m) ++lg;
     a.lg_m = lg;
     a.counters = stats ? ws->counters.as<QCounters>() : nullptr;
+    a.prof = stats ? ws->prof.as<unsigned long long>() : nullptr;
     a.err_any = ws->err.as<uint32_t>();
     a.out_idx = out_idx;
     a.out_dist = out_dist;
@@ -820,6 +916,12 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     MESSI_HIP_TRY(hipMemcpyAsync(&err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QCounters hc{};
     if (a.counters) MESSI_HIP_TRY(hipMemcpyAsync(&hc, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
+    std::vector<unsigned long long> hprof;
+    const int sg = scan_grid();
+    if (a.prof) {
+        hprof.resize((size_t)4 * sg);
+        MESSI_HIP_TRY(hipMemcpyAsync(hprof.data(), a.prof, sizeof(unsigned long long) * 4 * sg, hipMemcpyDeviceToHost, s));
+    }
     MESSI_HIP_TRY(hipStreamSynchronize(s));
     if (timing) {
         float ms[6];
@@ -844,6 +946,21 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         stats->candidates = (int64_t)hc.final_cands;
         stats->bytes_scan = (int64_t)hc.bytes;
         stats->scan_launches = 1;
+        if (!hprof.empty()) {
+            int rate_khz = 100000;
+            (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ix->device);
+            const double to_ms = 1.0 / (double)rate_khz;
+            double sum[4] = {0, 0, 0, 0}, mx = 0;
+            for (int bb = 0; bb < sg; ++bb) {
+                for (int i = 0; i < 4; ++i) sum[i] += (double)hprof[(size_t)bb * 4 + i];
+                mx = std::max(mx, (double)hprof[(size_t)bb * 4 + 3]);
+            }
+            stats->scan_ms_control = sum[0] / sg * to_ms;
+            stats->scan_ms_filter = sum[1] / sg * to_ms;
+            stats->scan_ms_distance = sum[2] / sg * to_ms;
+            stats->scan_ms_block_mean = sum[3] / sg * to_ms;
+            stats->scan_ms_block_max = mx * to_ms;
+        }
     }
     if (err & 1u) {
         set_error(MESSI_EINVAL, "queries contain non-finite values");

@@ -69,7 +69,10 @@ class KnnStats(ctypes.Structure):
                 ("series_recheck", ctypes.c_int64), ("candidates", ctypes.c_int64), ("bytes_scan", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("ms_prep", ctypes.c_double), ("ms_leaf_lb", ctypes.c_double),
                 ("ms_approx", ctypes.c_double), ("ms_order", ctypes.c_double), ("ms_scan", ctypes.c_double),
-                ("ms_final", ctypes.c_double), ("scan_launches", ctypes.c_int32)]
+                ("ms_final", ctypes.c_double), ("scan_launches", ctypes.c_int32),
+                ("scan_ms_control", ctypes.c_double), ("scan_ms_filter", ctypes.c_double),
+                ("scan_ms_distance", ctypes.c_double), ("scan_ms_block_mean", ctypes.c_double),
+                ("scan_ms_block_max", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
