@@ -230,7 +230,6 @@ int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev != ix->device)
         return fail(MESSI_EINVAL, "the index lives on another device");
-    if (mode == MESSI_MODE_BF16) return knn_bf16(ix, queries, nq, k, (hipStream_t)stream, out_idx, out_dist, stats);
     return knn_device(ix, queries, nq, k, mode, (hipStream_t)stream, out_idx, out_dist, stats);
 }
 

@@ -130,8 +130,6 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
 
 // bf16.hip
 int build_bf16_shadow(Index* ix, hipStream_t s);
-int knn_bf16(const Index* ix, const float* queries, int32_t nq, int32_t k, hipStream_t s, int64_t* out_idx,
-             float* out_dist, messi_knn_stats* stats);
 void release_bf16(const Index* ix);
 void release_workspaces(const Index* ix);
 

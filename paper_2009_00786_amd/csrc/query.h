@@ -77,4 +77,23 @@ struct QArgs {
     float* out_dist;
 };
 
+// Per-(index, stream) search workspace, grown on demand.
+struct Workspace {
+    int32_t nq = 0, nL = 0;
+    uint32_t cap = 0;
+    DevBuf qs, lb, order, bins, cursor, approx_d, cand, counters, err, prof;
+    // BF16 path
+    int32_t bf_nq = 0;
+    size_t bf_pairs_cap = 0, bf_leafq_cap = 0;
+    DevBuf qb, qnorm, leaf_cnt, leaf_off, leaf_cur, leaf_q, pairs, npairs, scan_scr;
+};
+
+// The batched BF16 filter + compensated fp32 recheck (bf16.hip); runs after the
+// shared prefix (prep, leaf bounds, first bound, leaf order) and before the
+// shared fp64 final ordering.
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s);
+
+// For k > 1, lower every query's bound to its current k-th candidate distance.
+int refresh_bounds(QArgs& a, hipStream_t s);
+
 }  // namespace messi

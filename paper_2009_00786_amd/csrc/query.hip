@@ -404,6 +404,39 @@ __device__ void refresh_u(QArgs& a, int q, QState& st, uint32_t* s_hist, uint32_
 // take positions j, j + G, j + 2G, ... (static, no shared ticket), so the
 // whole grid advances through the order together.  A block stops its share of
 // q at the first position whose bin lies entirely above U.
+// One block per query, between kernels: for k > 1, lower U to the k-th
+// candidate distance; then drop the candidates that can no longer be answers
+// (d (1 - rho) > U), compacting the list in place (order kept).
+__global__ void __launch_bounds__(256) refresh_kernel(QArgs a) {
+    __shared__ uint32_t s_hist[256 + 4];
+    __shared__ uint32_t s_b[2];
+    __shared__ uint32_t s_tmp[4];
+    const int q = blockIdx.x;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    if (st.k > 1) refresh_u(a, q, st, s_hist, s_b);
+    __syncthreads();
+    const float U = __uint_as_float(st.U);
+    const uint32_t n = min(st.ncand, a.cap);
+    Cand* c = a.cand + (size_t)q * a.cap;
+    uint32_t out = 0;
+    for (uint32_t r0 = 0; r0 < n; r0 += 256) {
+        const uint32_t i = r0 + threadIdx.x;
+        Cand e{0.f, 0u};
+        bool keep = false;
+        if (i < n) {
+            e = c[i];
+            keep = e.d * (1.0f - kRhoEd) <= U;
+        }
+        uint32_t total;
+        const uint32_t o = block_exclusive_scan(keep ? 1u : 0u, s_tmp, total);  // all reads of this chunk done
+        if (keep) c[out + o] = e;
+        out += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && st.ncand <= a.cap) st.ncand = out;
+}
+
 template <bool VEC>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
     __shared__ float s_D[16 * 256];
@@ -769,12 +802,6 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
 // --------------------------------------------------------------------------
 // host side
 // --------------------------------------------------------------------------
-struct Workspace {
-    int32_t nq = 0, nL = 0;
-    uint32_t cap = 0;
-    DevBuf qs, lb, order, bins, cursor, approx_d, cand, counters, err, prof;
-};
-
 std::mutex g_ws_mu;
 std::map<std::pair<const Index*, hipStream_t>, Workspace*> g_ws;
 
@@ -820,6 +847,12 @@ int scan_grid() {
 
 }  // namespace
 
+int refresh_bounds(QArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(refresh_kernel, dim3(a.nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("refresh");
+    return MESSI_OK;
+}
+
 void release_workspaces(const Index* ix) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     for (auto it = g_ws.begin(); it != g_ws.end();) {
@@ -834,7 +867,6 @@ void release_workspaces(const Index* ix) {
 
 int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
                int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
-    (void)mode;
     const uint32_t cap = nq == 1 ? (1u << 20) : std::max<uint32_t>(1u << 14, 64u * (uint32_t)k);
     Workspace* ws = nullptr;
     MESSI_TRY(get_workspace(ix, s, nq, cap, &ws));
@@ -902,12 +934,16 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_scatter");
     MESSI_TRY(mark(4));
-    const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
-    if (vec)
-        hipLaunchKernelGGL(scan_kernel<true>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(scan_kernel<false>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
-    MESSI_LAUNCH_CHECK("scan");
+    if (mode == MESSI_MODE_BF16) {
+        MESSI_TRY(bf16_scan(ix, a, ws, s));
+    } else {
+        const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
+        if (vec)
+            hipLaunchKernelGGL(scan_kernel<true>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL(scan_kernel<false>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
+        MESSI_LAUNCH_CHECK("scan");
+    }
     MESSI_TRY(mark(5));
     hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("final");
@@ -968,6 +1004,10 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     }
     if (err & 6u) {
         set_error(MESSI_EOVERFLOW, "too many tied candidates for the candidate buffer");
+        return MESSI_EOVERFLOW;
+    }
+    if (err & 16u) {
+        set_error(MESSI_EOVERFLOW, "BF16 filter: more surviving (query, series) pairs than the pair buffer holds");
         return MESSI_EOVERFLOW;
     }
     if (err & 8u) {

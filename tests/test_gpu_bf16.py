@@ -1,0 +1,120 @@
+"""GPU parity of the batched BF16 matrix-core filter + compensated fp32 recheck.
+
+The filter may only discard a series whose exact distance provably exceeds
+the current bound, so the answers must equal the oracle's brute force
+(indices bit-exact, distances within 1e-5 relative)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def messi():
+    from paper_2009_00786_amd import messi as m
+    m.load()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _check(gidx, gdist, oidx, od64):
+    np.testing.assert_array_equal(gidx, oidx)
+    ref = np.sqrt(od64)
+    err = np.abs(gdist.astype(np.float64) - ref) / np.maximum(ref, 1e-30)
+    assert np.all((err <= REL_TOL) | ((ref == 0) & (gdist == 0))), float(err.max())
+
+
+@pytest.fixture(scope="module")
+def tiny_bf16(torch_cuda, messi, datagen_mod, oracle_mod):
+    torch = torch_cuda
+    x = datagen_mod.random_walks(100_000, 256)
+    z = oracle_mod.znorm(x)
+    t = torch.from_numpy(x).cuda()
+    ix = messi.Index(t, 16, 8, 2000, znorm=True, bf16_shadow=True)
+    fresh = oracle_mod.znorm(datagen_mod.random_walks(8, 256, seed=datagen_mod.SEED_QUERY,
+                                                      stream=datagen_mod.STREAM_QUERY))
+    rows = datagen_mod.uniform_ints(8, 100_000, 21, 7)
+    noisy = datagen_mod.add_noise(z[rows], [0.01, 0.1, 1.0, 0.01, 0.1, 1.0, 0.01, 0.1])
+    q = np.concatenate([fresh, noisy])
+    yield {"z": z, "ix": ix, "q": q}
+    ix.close()
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_bf16_batched_matches_oracle(tiny_bf16, oracle_mod, torch_cuda, messi, k):
+    w = tiny_bf16
+    _say("bf16 batched k=%d" % k)
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"], k, nthreads=8)
+    gi, gd, st = w["ix"].knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=messi.MODE_BF16, stats=True)
+    _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    _say("  stats", {kk: st[kk] for kk in ("series_distance", "series_recheck", "candidates", "leaves_kept")})
+    assert st["series_recheck"] < st["series_distance"]
+
+
+def test_bf16_equals_fp32_mode(tiny_bf16, torch_cuda, messi):
+    w = tiny_bf16
+    q = torch_cuda.from_numpy(w["q"]).cuda()
+    a = w["ix"].knn(q, 5, mode=messi.MODE_BF16)
+    b = w["ix"].knn(q, 5, mode=messi.MODE_FP32)
+    assert torch_cuda.equal(a[0], b[0]) and torch_cuda.equal(a[1], b[1])
+
+
+BF16_SHAPES = [
+    # n, len, w, b, cap, k
+    (4097, 128, 16, 8, 100, 3),
+    (3000, 96, 16, 8, 50, 5),      # 3 k-steps of 32
+    (2000, 100, 4, 4, 20, 4),      # padded to 128
+    (3000, 1024, 16, 8, 300, 2),   # rows longer than the register-resident tile
+    (7, 16, 16, 3, 1, 7),          # k = n, padded to 32
+    (64, 32, 8, 8, 4, 64),
+]
+
+
+@pytest.mark.parametrize("n,length,w,b,cap,k", BF16_SHAPES)
+def test_bf16_shapes(torch_cuda, messi, datagen_mod, oracle_mod, n, length, w, b, cap, k):
+    torch = torch_cuda
+    _say("bf16 n=%d len=%d w=%d b=%d cap=%d k=%d" % (n, length, w, b, cap, k))
+    z = oracle_mod.znorm(datagen_mod.random_walks(n, length, seed=41, stream=0))
+    q = oracle_mod.znorm(datagen_mod.random_walks(5, length, seed=42, stream=1))
+    q = np.concatenate([q, z[[0, n - 1]]])
+    ix = messi.Index(torch.from_numpy(z).cuda(), w, b, cap, bf16_shadow=True)
+    oidx, od, _ = oracle_mod.knn_brute(z, q, k, nthreads=8)
+    gi, gd = ix.knn(torch.from_numpy(q).cuda(), k, mode=messi.MODE_BF16)
+    _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    ix.close()
+
+
+def test_bf16_ties_and_unnormalised(torch_cuda, messi, oracle_mod):
+    torch = torch_cuda
+    rng = np.random.default_rng(11)
+    z = (rng.standard_normal((4000, 64)) * 30.0 + 100.0).astype(np.float32)   # not z-normalised, large norms
+    z[50:400] = z[9]
+    z[700:710] = 0.0
+    q = np.concatenate([z[[9, 700, 3999]], (rng.standard_normal((3, 64)) * 30 + 100).astype(np.float32)])
+    ix = messi.Index(torch.from_numpy(z).cuda(), 8, 8, 60, bf16_shadow=True)
+    for k in (1, 7, 360):
+        oidx, od, _ = oracle_mod.knn_brute(z, q, k, nthreads=8)
+        gi, gd = ix.knn(torch.from_numpy(q).cuda(), k, mode=messi.MODE_BF16)
+        _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    ix.close()
+
+
+def test_bf16_needs_shadow(torch_cuda, messi):
+    z = torch_cuda.randn((100, 32), device="cuda")
+    ix = messi.Index(z, 4, 8, 10)
+    with pytest.raises(messi.MessiError) as e:
+        ix.knn(z[:2].contiguous(), 1, mode=messi.MODE_BF16)
+    assert e.value.code == messi.MESSI_EINVAL
+    ix.close()
