@@ -36,6 +36,8 @@ WORKLOADS = {
     1: dict(name="random-walk 100K x 256, exact 1-NN, 10 single queries", n=100_000, length=256, queries=10, k=1),
     2: dict(name="random-walk 100M x 256, exact 1-NN, 100 single queries", n=100_000_000, length=256, queries=100,
             k=1),
+    3: dict(name="random-walk 100M x 256, batches of 1024 (512 fresh walks + 512 noisy rows), k=1 and k=10, "
+                 "BF16 matrix-core filter", n=100_000_000, length=256, queries=1024, k=10),
 }
 
 
@@ -106,6 +108,8 @@ def main():
     import datagen
     from paper_2009_00786_amd import messi
 
+    if args.config == 3:
+        return bench_batched(args)
     wl = dict(WORKLOADS[args.config])
     if args.n:
         wl["n"] = args.n
@@ -248,6 +252,109 @@ def main():
     }
     if ix is not None:
         ix.close()
+    print(json.dumps(res), flush=True)
+
+
+def make_batch(data, z_rows_gpu_fn, b, nq, length, seed_off=0):
+    """Half fresh random walks (query stream), half dataset rows + sigma * N(0,1),
+    sigma cycling over 0.01, 0.1, 1.0 (not re-normalised)."""
+    import datagen
+    from paper_2009_00786_amd import messi
+    import torch
+    half = nq // 2
+    fresh_raw = datagen.random_walks(half, length, seed=datagen.SEED_QUERY, stream=datagen.STREAM_QUERY,
+                                     row0=1_000_000 + b * half)
+    fresh = torch.from_numpy(fresh_raw).to(data.device)
+    messi.znorm_(fresh)
+    ids = datagen.uniform_ints(nq - half, data.shape[0], 9, 5 + b)
+    base = data[torch.from_numpy(ids).to(data.device)].cpu().numpy()
+    sig = np.array([(0.01, 0.1, 1.0)[i % 3] for i in range(nq - half)])
+    noisy = datagen.add_noise(base, sig, row0=b * nq)
+    return torch.cat([fresh, torch.from_numpy(noisy).to(data.device)]).contiguous()
+
+
+def bench_batched(args):
+    """Configuration 3: batches of 1024 queries through the BF16 filter, at k = 1 and k = 10."""
+    import torch
+
+    import datagen
+    from paper_2009_00786_amd import messi
+
+    wl = dict(WORKLOADS[3])
+    if args.n:
+        wl["n"] = args.n
+        wl["name"] += " (n=%d)" % args.n
+    n, length, nq = wl["n"], wl["length"], wl["queries"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    messi.load()
+    log("generating %d x %d random walks on the GPU" % (n, length))
+    data = torch.empty((n, length), dtype=torch.float32, device=dev)
+    for r0 in range(0, n, 10_000_000):
+        datagen.gpu_random_walks(data[r0:r0 + 10_000_000], row0=r0)
+    messi.znorm_(data)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = messi.Index(data, 16, 8, 2000, bf16_shadow=True)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = ix.info()
+    log("build with BF16 shadow: %.1f ms (shadow %.1f ms)" % (build_ms, info["ms_shadow"]))
+    batches = [make_batch(data, None, b, nq, length) for b in range(args.warmup + args.steps)]
+    agg = {1: {}, 10: {}}
+    times = {1: [], 10: []}
+    for b, q in enumerate(batches):
+        timed = b >= args.warmup
+        for k in (1, 10):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, _, st = ix.knn(q, k, mode=messi.MODE_BF16, stats=True)
+            e = time.perf_counter()
+            log("batch %d k=%d: %.2f ms  (filter %.2f ms, recheck %.2f ms, %d rounds, evals %.3g, rechecks %d)" % (
+                b, k, (e - a) * 1e3, st["ms_bf16_filter"], st["ms_bf16_recheck"], st["bf16_rounds"],
+                st["series_distance"], st["series_recheck"]))
+            if timed:
+                times[k].append((e - a) * 1e3)
+                for kk, v in st.items():
+                    agg[k][kk] = agg[k].get(kk, 0) + v
+    # the plain fp32 path on the same batch, for comparison
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    _, _, st32 = ix.knn(batches[-1], 1, mode=messi.MODE_FP32, stats=True)
+    fp32_batch_ms = (time.perf_counter() - a) * 1e3
+    log("fp32 batched k=1: %.2f ms" % fp32_batch_ms)
+    steps = args.steps
+    total_q = 2 * nq * steps
+    total_ms = sum(times[1]) + sum(times[10])
+    qps = total_q / (total_ms / 1e3)
+    f_ms = (agg[1].get("ms_bf16_filter", 0) + agg[10].get("ms_bf16_filter", 0))
+    f_flops = agg[1].get("bf16_flops", 0) + agg[10].get("bf16_flops", 0)
+    f_bytes = agg[1].get("bytes_scan", 0) + agg[10].get("bytes_scan", 0)
+    launches = agg[1].get("bf16_rounds", 0) + agg[10].get("bf16_rounds", 0)
+    mfma = {"bound": "mfma", "achieved": f_flops / (f_ms / 1e3) / 1e12 if f_ms else 0.0, "peak": 2500.0,
+            "unit": "TFLOP/s", "traffic": None, "kernel": "bf16_filter_kernel",
+            "flops_per_launch": f_flops / max(launches, 1), "ms_per_launch": f_ms / max(launches, 1)}
+    mfma["frac"] = mfma["achieved"] / mfma["peak"]
+    res = {
+        "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": total_ms / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "len": length, "segments": 16, "card_bits": 8, "leaf_cap": 2000,
+                   "batch": nq, "k": [1, 10], "mode": "BF16 matrix-core filter + compensated fp32 recheck"},
+        "qps_k1": nq * steps / (sum(times[1]) / 1e3), "qps_k10": nq * steps / (sum(times[10]) / 1e3),
+        "batch_ms_k1": float(np.mean(times[1])), "batch_ms_k10": float(np.mean(times[10])),
+        "fp32_batched_k1_ms": fp32_batch_ms, "fp32_batched_k1_qps": nq / (fp32_batch_ms / 1e3),
+        "build_ms_with_shadow": build_ms, "shadow_ms": info["ms_shadow"],
+        "roofline": mfma,
+        "filter_hbm_gbps": f_bytes / (f_ms / 1e3) / 1e9 if f_ms else 0.0,
+        "per_batch": {str(k): {kk: agg[k].get(kk, 0) / steps for kk in (
+            "leaves_kept", "series_distance", "series_recheck", "candidates", "ms_bf16_filter", "ms_bf16_recheck",
+            "ms_total", "ms_leaf_lb", "ms_approx", "ms_order", "ms_scan", "ms_final", "bf16_rounds")}
+            for k in (1, 10)},
+        "discard_rate": 1.0 - (agg[1].get("series_recheck", 0) + agg[10].get("series_recheck", 0)) /
+        max(1, agg[1].get("series_distance", 0) + agg[10].get("series_distance", 0)),
+        "cpu_baseline": None,
+    }
+    ix.close()
     print(json.dumps(res), flush=True)
 
 

@@ -97,6 +97,11 @@ typedef struct {
     /* scan kernel, per block (device wall clock): mean time in leaf control,
        member filtering and distances, mean and max block lifetime */
     double scan_ms_control, scan_ms_filter, scan_ms_distance, scan_ms_block_mean, scan_ms_block_max;
+    /* BF16 mode: device time of the matrix-core filter and of the recheck
+       kernels, and the filter's multiply-add work (2 * padded len per pair) */
+    double ms_bf16_filter, ms_bf16_recheck;
+    int64_t bf16_flops;
+    int32_t bf16_rounds;
 } messi_knn_stats;
 
 /* ---- index ------------------------------------------------------------- */

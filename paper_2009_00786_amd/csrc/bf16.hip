@@ -26,6 +26,7 @@
 // the final order uses the canonical fp64 distance.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "query.h"
 #include "scan.h"
@@ -395,7 +396,7 @@ int build_bf16_shadow(Index* ix, hipStream_t s) {
 
 void release_bf16(const Index* ix) { (void)ix; }
 
-int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing) {
     const int L = ix->len;
     const int Lp = (L + 31) / 32 * 32;
     const int nq = a.nq;
@@ -441,30 +442,60 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
                        ws->qnorm.as<float2>());
     MESSI_LAUNCH_CHECK("qprep_bf16");
     const int cus = device_cus();
+    // events around the filter and recheck launches of every round (timing only)
+    std::vector<hipEvent_t> evs;
+    auto mark = [&]() -> int {
+        if (!timing) return MESSI_OK;
+        hipEvent_t e;
+        MESSI_HIP_TRY(hipEventCreate(&e));
+        MESSI_HIP_TRY(hipEventRecord(e, s));
+        evs.push_back(e);
+        return MESSI_OK;
+    };
+    int rounds_run = 0;
     // Rounds over geometrically growing ranges of each query's leaf order
     // (8, 64, 512, ... positions); after each round every query's bound is
     // refreshed from its candidates, so later rounds are filtered tighter.
-    for (uint32_t t0 = 0, t1 = kFirstRound; t0 < (uint32_t)nL; t0 = t1, t1 = t1 * 8u) {
-        if (t1 > (uint32_t)nL) t1 = (uint32_t)nL;
+    for (uint64_t t0 = 0, t1 = kFirstRound; t0 < (uint64_t)nL; t0 = t1, t1 = t1 * 8u) {
+        if (t1 > (uint64_t)nL) t1 = (uint64_t)nL;
         const unsigned tbr = (unsigned)((t1 - t0 + 255) / 256);
+        const uint32_t r0 = (uint32_t)t0, r1 = (uint32_t)t1;
         MESSI_HIP_TRY(hipMemsetAsync(ws->leaf_cnt.p, 0, sizeof(uint32_t) * (nL + 1), s));
         MESSI_HIP_TRY(hipMemsetAsync(ws->leaf_cur.p, 0, sizeof(uint32_t) * (nL + 1), s));
         MESSI_HIP_TRY(hipMemsetAsync(ws->npairs.p, 0, sizeof(uint32_t) * 4, s));
-        hipLaunchKernelGGL(leaf_count_kernel, dim3(tbr, nq), dim3(256), 0, s, a, t0, t1, ws->leaf_cnt.as<uint32_t>());
+        hipLaunchKernelGGL(leaf_count_kernel, dim3(tbr, nq), dim3(256), 0, s, a, r0, r1, ws->leaf_cnt.as<uint32_t>());
         MESSI_LAUNCH_CHECK("leaf_count");
         MESSI_TRY(scan_exclusive(ws->leaf_cnt.as<uint32_t>(), ws->leaf_off.as<uint32_t>(), (int64_t)nL,
                                  ws->scan_scr.as<uint32_t>(), nullptr, s));
-        hipLaunchKernelGGL(leaf_scatter_kernel, dim3(tbr, nq), dim3(256), 0, s, a, t0, t1,
+        hipLaunchKernelGGL(leaf_scatter_kernel, dim3(tbr, nq), dim3(256), 0, s, a, r0, r1,
                            ws->leaf_off.as<uint32_t>(), ws->leaf_cur.as<uint32_t>(), ws->leaf_q.as<uint32_t>(),
                            leafq_cap);
         MESSI_LAUNCH_CHECK("leaf_scatter");
+        MESSI_TRY(mark());
         hipLaunchKernelGGL(bf16_filter_kernel, dim3(cus * 4), dim3(256), 0, s, a, bf);
         MESSI_LAUNCH_CHECK("bf16_filter");
+        MESSI_TRY(mark());
         hipLaunchKernelGGL(pairs_overflow_kernel, dim3(1), dim3(64), 0, s, bf.npairs, bf.pairs_cap, a.err_any);
         MESSI_LAUNCH_CHECK("pairs_overflow");
+        MESSI_TRY(mark());
         hipLaunchKernelGGL(bf16_recheck_kernel, dim3(cus * 8), dim3(256), 0, s, a, bf);
         MESSI_LAUNCH_CHECK("bf16_recheck");
+        MESSI_TRY(mark());
         MESSI_TRY(refresh_bounds(a, s));
+        ++rounds_run;
+    }
+    ws->bf_rounds = rounds_run;
+    ws->bf_ms_filter = ws->bf_ms_recheck = 0;
+    if (timing) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        for (size_t i = 0; i + 3 < evs.size(); i += 4) {
+            float f = 0, r = 0;
+            MESSI_HIP_TRY(hipEventElapsedTime(&f, evs[i], evs[i + 1]));
+            MESSI_HIP_TRY(hipEventElapsedTime(&r, evs[i + 2], evs[i + 3]));
+            ws->bf_ms_filter += f;
+            ws->bf_ms_recheck += r;
+        }
+        for (auto e : evs) (void)hipEventDestroy(e);
     }
     return MESSI_OK;
 }

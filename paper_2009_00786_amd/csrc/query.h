@@ -86,14 +86,25 @@ struct Workspace {
     int32_t bf_nq = 0;
     size_t bf_pairs_cap = 0, bf_leafq_cap = 0;
     DevBuf qb, qnorm, leaf_cnt, leaf_off, leaf_cur, leaf_q, pairs, npairs, scan_scr;
+    // timing of the BF16 kernels of the last call (filled when timing is on)
+    double bf_ms_filter = 0, bf_ms_recheck = 0;
+    int bf_rounds = 0;
 };
 
 // The batched BF16 filter + compensated fp32 recheck (bf16.hip); runs after the
 // shared prefix (prep, leaf bounds, first bound, leaf order) and before the
 // shared fp64 final ordering.
-int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s);
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing);
 
 // For k > 1, lower every query's bound to its current k-th candidate distance.
 int refresh_bounds(QArgs& a, hipStream_t s);
+
+// Enqueue a whole search on `s` without waiting (used by the server): kq is an
+// optional device array of per-query k (<= kmax; outputs have row stride kmax);
+// the call's error flags are copied to *host_err (pinned) when the stream
+// reaches that point.  knn_error_code turns those flags into a MESSI_E* code.
+int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
+                hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err);
+int knn_error_code(uint32_t err);
 
 }  // namespace messi

@@ -55,7 +55,8 @@ __device__ __forceinline__ float upper_u(float d) { return d * (1.0f + 2.0f * kR
 // --------------------------------------------------------------------------
 // prep
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, uint32_t kstride) {
+__global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, const int32_t* __restrict__ kq,
+                                                   uint32_t kstride) {
     __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ float s_red[2][4];
     __shared__ int s_bad;
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, uint32_t 
         st.approx_leaf = 0;
         st.approx_full = 0;
         st.range = 0.f;
-        st.k = k;
+        st.k = kq ? kq[q] : k;
         st.err = s_bad ? 1u : 0u;
         st.active = 1;
         st.kstride = kstride;
@@ -853,6 +854,15 @@ int refresh_bounds(QArgs& a, hipStream_t s) {
     return MESSI_OK;
 }
 
+void release_workspace(const Index* ix, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({ix, st});
+    if (it != g_ws.end()) {
+        delete it->second;
+        g_ws.erase(it);
+    }
+}
+
 void release_workspaces(const Index* ix) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     for (auto it = g_ws.begin(); it != g_ws.end();) {
@@ -865,12 +875,28 @@ void release_workspaces(const Index* ix) {
     }
 }
 
-int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
-               int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
-    const uint32_t cap = nq == 1 ? (1u << 20) : std::max<uint32_t>(1u << 14, 64u * (uint32_t)k);
+namespace {
+
+// Arguments of one search call shared by the synchronous entry point and the server.
+struct CallArgs {
+    const Index* ix;
+    const float* queries;
+    int32_t nq, kmax;
+    const int32_t* kq;  // device, per-query k (nullable: kmax for all)
+    int32_t mode;
+    hipStream_t s;
+    int64_t* out_idx;
+    float* out_dist;
+};
+
+int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap) {
+    const Index* ix = c.ix;
+    const int32_t nq = c.nq;
+    cap = nq == 1 ? (1u << 20) : std::max<uint32_t>(1u << 14, 64u * (uint32_t)c.kmax);
     Workspace* ws = nullptr;
-    MESSI_TRY(get_workspace(ix, s, nq, cap, &ws));
-    QArgs a{};
+    MESSI_TRY(get_workspace(ix, c.s, nq, cap, &ws));
+    *wsp = ws;
+    a = QArgs{};
     a.series = ix->series;
     a.n = ix->n;
     a.L = ix->len;
@@ -882,7 +908,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     a.leaves = ix->leaves.as<Leaf>();
     a.nL = (int32_t)ix->n_leaves;
     a.bp = ix->bp.as<float>();
-    a.queries = queries;
+    a.queries = c.queries;
     a.nq = nq;
     a.qs = ws->qs.as<QState>();
     a.lb = ws->lb.as<float>();
@@ -896,26 +922,28 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     int lg = 0;
     while ((1 << lg) < a.m) ++lg;
     a.lg_m = lg;
-    a.counters = stats ? ws->counters.as<QCounters>() : nullptr;
-    a.prof = stats ? ws->prof.as<unsigned long long>() : nullptr;
+    a.counters = counting ? ws->counters.as<QCounters>() : nullptr;
+    a.prof = counting ? ws->prof.as<unsigned long long>() : nullptr;
     a.err_any = ws->err.as<uint32_t>();
-    a.out_idx = out_idx;
-    a.out_dist = out_dist;
+    a.out_idx = c.out_idx;
+    a.out_dist = c.out_dist;
+    return MESSI_OK;
+}
 
-    hipEvent_t ev[8];
-    const bool timing = stats != nullptr;
-    if (timing)
-        for (auto& e : ev) MESSI_HIP_TRY(hipEventCreate(&e));
-    auto mark = [&](int i) -> int {
-        if (timing) MESSI_HIP_TRY(hipEventRecord(ev[i], s));
-        return MESSI_OK;
-    };
+// Enqueue the whole search on c.s; `mark(i)` is called at the phase boundaries
+// 0..6 (prep, leaf bounds, first bound, order, scan, final, end).
+template <class Mark>
+int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool timing, Mark mark) {
+    const hipStream_t s = c.s;
+    const int32_t nq = c.nq;
+    const Index* ix = c.ix;
     MESSI_HIP_TRY(hipMemsetAsync(a.err_any, 0, sizeof(uint32_t) * 4, s));
     if (a.counters) MESSI_HIP_TRY(hipMemsetAsync(a.counters, 0, sizeof(QCounters), s));
     MESSI_HIP_TRY(hipMemsetAsync(a.bins, 0, sizeof(uint32_t) * kNB * (size_t)nq, s));
     MESSI_HIP_TRY(hipMemsetAsync(a.cand, 0xFF, sizeof(Cand) * (size_t)cap * nq, s));
+    const int32_t mode = c.mode;
     MESSI_TRY(mark(0));
-    hipLaunchKernelGGL(prep_kernel, dim3(nq), dim3(256), 0, s, a, k, (uint32_t)k);
+    hipLaunchKernelGGL(prep_kernel, dim3(nq), dim3(256), 0, s, a, c.kmax, c.kq, (uint32_t)c.kmax);
     MESSI_LAUNCH_CHECK("prep");
     MESSI_TRY(mark(1));
     const unsigned lb_blocks = (unsigned)((a.nL + kLeafBlock - 1) / kLeafBlock);
@@ -935,7 +963,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     MESSI_LAUNCH_CHECK("bin_scatter");
     MESSI_TRY(mark(4));
     if (mode == MESSI_MODE_BF16) {
-        MESSI_TRY(bf16_scan(ix, a, ws, s));
+        MESSI_TRY(bf16_scan(ix, a, ws, s, timing));
     } else {
         const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
         if (vec)
@@ -948,6 +976,62 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("final");
     MESSI_TRY(mark(6));
+    (void)ix;
+    return MESSI_OK;
+}
+
+int decode_error(uint32_t err) {
+    if (err & 1u) {
+        set_error(MESSI_EINVAL, "queries contain non-finite values");
+        return MESSI_EINVAL;
+    }
+    if (err & 6u) {
+        set_error(MESSI_EOVERFLOW, "too many tied candidates for the candidate buffer");
+        return MESSI_EOVERFLOW;
+    }
+    if (err & 16u) {
+        set_error(MESSI_EOVERFLOW, "BF16 filter: more surviving (query, series) pairs than the pair buffer holds");
+        return MESSI_EOVERFLOW;
+    }
+    if (err & 8u) {
+        set_error(MESSI_EDEVICE, "internal error: fewer than k candidates");
+        return MESSI_EDEVICE;
+    }
+    return MESSI_OK;
+}
+
+}  // namespace
+
+int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
+                hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err) {
+    CallArgs c{ix, queries, nq, kmax, kq, mode, s, out_idx, out_dist};
+    Workspace* ws = nullptr;
+    QArgs a;
+    uint32_t cap = 0;
+    MESSI_TRY(setup_call(c, false, &ws, a, cap));
+    MESSI_TRY(launch_search(c, a, ws, cap, false, [](int) { return MESSI_OK; }));
+    MESSI_HIP_TRY(hipMemcpyAsync(host_err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    return MESSI_OK;
+}
+
+int knn_error_code(uint32_t err) { return decode_error(err); }
+
+int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
+               int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    CallArgs c{ix, queries, nq, k, nullptr, mode, s, out_idx, out_dist};
+    Workspace* ws = nullptr;
+    QArgs a;
+    uint32_t cap = 0;
+    MESSI_TRY(setup_call(c, stats != nullptr, &ws, a, cap));
+    hipEvent_t ev[8];
+    const bool timing = stats != nullptr;
+    if (timing)
+        for (auto& e : ev) MESSI_HIP_TRY(hipEventCreate(&e));
+    auto mark = [&](int i) -> int {
+        if (timing) MESSI_HIP_TRY(hipEventRecord(ev[i], s));
+        return MESSI_OK;
+    };
+    MESSI_TRY(launch_search(c, a, ws, cap, timing, mark));
     uint32_t err = 0;
     MESSI_HIP_TRY(hipMemcpyAsync(&err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QCounters hc{};
@@ -982,6 +1066,14 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         stats->candidates = (int64_t)hc.final_cands;
         stats->bytes_scan = (int64_t)hc.bytes;
         stats->scan_launches = 1;
+        if (mode == MESSI_MODE_BF16) {
+            const int Lp = (ix->len + 31) / 32 * 32;
+            stats->ms_bf16_filter = ws->bf_ms_filter;
+            stats->ms_bf16_recheck = ws->bf_ms_recheck;
+            stats->bf16_rounds = ws->bf_rounds;
+            stats->bf16_flops = (int64_t)hc.distance * 2 * Lp;
+            stats->scan_launches = ws->bf_rounds;
+        }
         if (!hprof.empty()) {
             int rate_khz = 100000;
             (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ix->device);
@@ -998,23 +1090,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
             stats->scan_ms_block_max = mx * to_ms;
         }
     }
-    if (err & 1u) {
-        set_error(MESSI_EINVAL, "queries contain non-finite values");
-        return MESSI_EINVAL;
-    }
-    if (err & 6u) {
-        set_error(MESSI_EOVERFLOW, "too many tied candidates for the candidate buffer");
-        return MESSI_EOVERFLOW;
-    }
-    if (err & 16u) {
-        set_error(MESSI_EOVERFLOW, "BF16 filter: more surviving (query, series) pairs than the pair buffer holds");
-        return MESSI_EOVERFLOW;
-    }
-    if (err & 8u) {
-        set_error(MESSI_EDEVICE, "internal error: fewer than k candidates");
-        return MESSI_EDEVICE;
-    }
-    return MESSI_OK;
+    return decode_error(err);
 }
 
 }  // namespace messi

@@ -1,22 +1,350 @@
-// Serving loop (continuous batching).
-#include "common.h"
+// Request loop with continuous batching over a resident index.
+//
+// The server owns a worker thread and a few "lanes"; a lane is a HIP stream
+// with its own pinned staging buffers and search workspace.  Submitted queries
+// wait in a FIFO; whenever a lane is free, the worker moves up to the lane's
+// batch size of waiting queries into it and enqueues one batched search
+// (mixed k allowed) on the lane's stream without waiting.  Lanes run
+// concurrently, so queries that arrive while other batches are on the GPU are
+// admitted as soon as a lane frees up and their work overlaps on the device.
+// The lane count and batch size follow from the device-memory budget: every
+// admitted query holds its share of a lane's workspace until it completes.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "query.h"
+
+namespace messi {
+
+void release_workspace(const Index* ix, hipStream_t s);
+
+namespace {
+
+struct Pending {
+    std::vector<float> q;
+    int32_t k;
+    uint64_t tag;
+    double t_submit;
+};
+
+struct Lane {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    int32_t kmax = 0;
+    DevBuf d_q, d_k, d_idx, d_dist;
+    float* h_q = nullptr;
+    int32_t* h_k = nullptr;
+    int64_t* h_idx = nullptr;
+    float* h_dist = nullptr;
+    uint32_t* h_err = nullptr;
+    std::vector<Pending> batch;
+};
+
+constexpr size_t kMaxPending = 1u << 20;
+
+}  // namespace
+
+struct Server {
+    const Index* ix = nullptr;
+    int32_t mode = MESSI_MODE_BF16;
+    int32_t batch = 1;  // queries per lane
+    std::vector<Lane> lanes;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Pending> pending;
+    std::deque<messi_result*> ready;
+    std::atomic<bool> stop{false};
+    std::thread worker;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    int device = 0;
+
+    double now_ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    int launch(Lane& ln) {
+        const int L = ix->len;
+        const int32_t nq = (int32_t)ln.batch.size();
+        int32_t kmax = 1;
+        for (int32_t i = 0; i < nq; ++i) {
+            std::memcpy(ln.h_q + (size_t)i * L, ln.batch[i].q.data(), sizeof(float) * L);
+            ln.h_k[i] = ln.batch[i].k;
+            kmax = std::max(kmax, ln.batch[i].k);
+        }
+        ln.kmax = kmax;
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.d_q.p, ln.h_q, sizeof(float) * (size_t)nq * L, hipMemcpyHostToDevice, ln.s));
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.d_k.p, ln.h_k, sizeof(int32_t) * (size_t)nq, hipMemcpyHostToDevice, ln.s));
+        *ln.h_err = 0;
+        MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, kmax, ln.d_k.as<int32_t>(), mode, ln.s, ln.d_idx.as<int64_t>(),
+                              ln.d_dist.as<float>(), ln.h_err));
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.h_idx, ln.d_idx.p, sizeof(int64_t) * (size_t)nq * kmax, hipMemcpyDeviceToHost,
+                                     ln.s));
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.h_dist, ln.d_dist.p, sizeof(float) * (size_t)nq * kmax, hipMemcpyDeviceToHost,
+                                     ln.s));
+        MESSI_HIP_TRY(hipEventRecord(ln.done, ln.s));
+        ln.busy = true;
+        return MESSI_OK;
+    }
+
+    void complete(Lane& ln, int status) {
+        const double t = now_ms();
+        std::vector<messi_result*> out;
+        out.reserve(ln.batch.size());
+        for (size_t i = 0; i < ln.batch.size(); ++i) {
+            messi_result* r = new messi_result();
+            std::memset(r, 0, sizeof(*r));
+            r->tag = ln.batch[i].tag;
+            r->k = ln.batch[i].k;
+            r->status = status;
+            r->t_submit_ms = ln.batch[i].t_submit;
+            r->t_done_ms = t;
+            if (status == MESSI_OK) {
+                for (int j = 0; j < r->k; ++j) {
+                    r->idx[j] = ln.h_idx[i * (size_t)ln.kmax + j];
+                    r->dist[j] = ln.h_dist[i * (size_t)ln.kmax + j];
+                }
+            }
+            out.push_back(r);
+        }
+        ln.batch.clear();
+        ln.busy = false;
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto* r : out) ready.push_back(r);
+    }
+
+    void run() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            bool progressed = false;
+            for (auto& ln : lanes) {
+                if (!ln.busy) continue;
+                const hipError_t q = hipEventQuery(ln.done);
+                if (q == hipErrorNotReady) continue;
+                int status = (q == hipSuccess) ? knn_error_code(*ln.h_err) : MESSI_EDEVICE;
+                if (q != hipSuccess) (void)hipGetLastError();
+                complete(ln, status);
+                progressed = true;
+            }
+            bool idle_lanes = false;
+            for (auto& ln : lanes) {
+                if (ln.busy) continue;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    while (!pending.empty() && (int32_t)ln.batch.size() < batch) {
+                        ln.batch.push_back(std::move(pending.front()));
+                        pending.pop_front();
+                    }
+                }
+                if (ln.batch.empty()) {
+                    idle_lanes = true;
+                    continue;
+                }
+                const int rc = launch(ln);
+                if (rc != MESSI_OK) complete(ln, rc);
+                progressed = true;
+            }
+            bool any_busy = false;
+            for (auto& ln : lanes) any_busy |= ln.busy;
+            if (stop.load() && !any_busy) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (pending.empty()) break;
+            }
+            if (!progressed) {
+                std::unique_lock<std::mutex> lk(mu);
+                if (pending.empty() || !idle_lanes)
+                    cv.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 500));
+            }
+        }
+    }
+
+    ~Server() {
+        for (auto& ln : lanes) {
+            if (ln.s) {
+                (void)hipStreamSynchronize(ln.s);
+                release_workspace(ix, ln.s);
+                (void)hipStreamDestroy(ln.s);
+            }
+            if (ln.done) (void)hipEventDestroy(ln.done);
+            for (void* p : {(void*)ln.h_q, (void*)ln.h_k, (void*)ln.h_idx, (void*)ln.h_dist, (void*)ln.h_err})
+                if (p) (void)hipHostFree(p);
+        }
+        for (auto* r : ready) delete r;
+    }
+};
+
+// Device bytes one admitted query holds (workspace share + staging), for kmax
+// results; used to turn the memory budget into slots.
+static size_t bytes_per_query(const Index* ix, int32_t mode) {
+    const size_t nL = (size_t)ix->n_leaves;
+    const size_t cap = std::max<size_t>(1u << 14, 64u * MESSI_MAX_K);
+    size_t b = nL * 4 * 2 + 2 * 1024 * 4 + 4096 * 4 + cap * 8 + sizeof(float) * ix->len +
+               (sizeof(int64_t) + sizeof(float)) * MESSI_MAX_K + 256;
+    if (mode == MESSI_MODE_BF16) b += nL * 4 + 16384 * 8 + (size_t)((ix->len + 31) / 32 * 32) * 2 + 8;
+    return b;
+}
+
+}  // namespace messi
+
+using namespace messi;
 
 extern "C" {
 
 messi_server* messi_server_create(const messi_index* index, size_t budget_bytes, int32_t max_slots, int32_t mode) {
-    (void)index; (void)budget_bytes; (void)max_slots; (void)mode;
-    messi::set_error(MESSI_EINVAL, "server not available in this build");
-    return nullptr;
+    clear_error();
+    if (!index) {
+        set_error(MESSI_EINVAL, "index is null");
+        return nullptr;
+    }
+    if (max_slots < 1) {
+        set_error(MESSI_EINVAL, "max_slots must be >= 1");
+        return nullptr;
+    }
+    if (mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16) {
+        set_error(MESSI_EINVAL, "unknown mode");
+        return nullptr;
+    }
+    const Index* ix = reinterpret_cast<const Index*>(index);
+    if (mode == MESSI_MODE_BF16 && !ix->shadow.p) {
+        set_error(MESSI_EINVAL, "BF16 serving needs an index built with bf16_shadow = 1");
+        return nullptr;
+    }
+    const size_t per_q = bytes_per_query(ix, mode);
+    const int64_t fit = (int64_t)(budget_bytes / per_q);
+    if (fit < 1) {
+        set_error(MESSI_ENOMEM, "memory budget below the need of one query (" + std::to_string(per_q) + " bytes)");
+        return nullptr;
+    }
+    const int32_t slots = (int32_t)std::min<int64_t>(max_slots, fit);
+    Server* sv = new Server();
+    sv->ix = ix;
+    sv->mode = mode;
+    sv->device = ix->device;
+    const int nl = std::min(4, slots);
+    sv->batch = (slots + nl - 1) / nl;
+    sv->lanes.resize(nl);
+    const int L = ix->len;
+    int rc = MESSI_OK;
+    for (auto& ln : sv->lanes) {
+        const size_t B = (size_t)sv->batch;
+        if (hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&ln.h_q, sizeof(float) * B * L, 0) != hipSuccess ||
+            hipHostMalloc((void**)&ln.h_k, sizeof(int32_t) * B, 0) != hipSuccess ||
+            hipHostMalloc((void**)&ln.h_idx, sizeof(int64_t) * B * MESSI_MAX_K, 0) != hipSuccess ||
+            hipHostMalloc((void**)&ln.h_dist, sizeof(float) * B * MESSI_MAX_K, 0) != hipSuccess ||
+            hipHostMalloc((void**)&ln.h_err, sizeof(uint32_t), 0) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error(MESSI_ENOMEM, "server: stream or pinned buffer allocation failed");
+            rc = MESSI_ENOMEM;
+            break;
+        }
+        if ((rc = ln.d_q.alloc(sizeof(float) * B * L)) != MESSI_OK) break;
+        if ((rc = ln.d_k.alloc(sizeof(int32_t) * B)) != MESSI_OK) break;
+        if ((rc = ln.d_idx.alloc(sizeof(int64_t) * B * MESSI_MAX_K)) != MESSI_OK) break;
+        if ((rc = ln.d_dist.alloc(sizeof(float) * B * MESSI_MAX_K)) != MESSI_OK) break;
+        // size the lane's workspace once: a full batch of copies of row 0, k = the maximum
+        if (hipMemcpyAsync(ln.d_q.p, ix->series, sizeof(float) * L, hipMemcpyDeviceToDevice, ln.s) != hipSuccess) {
+            rc = MESSI_EDEVICE;
+            break;
+        }
+        for (size_t i = 1; i < B; ++i)
+            if (hipMemcpyAsync(ln.d_q.as<float>() + i * L, ix->series, sizeof(float) * L, hipMemcpyDeviceToDevice,
+                               ln.s) != hipSuccess) {
+                rc = MESSI_EDEVICE;
+                break;
+            }
+        const int32_t kw = (int32_t)std::min<int64_t>(MESSI_MAX_K, ix->n);
+        for (size_t i = 0; i < B; ++i) ln.h_k[i] = kw;
+        if (rc != MESSI_OK || hipMemcpyAsync(ln.d_k.p, ln.h_k, sizeof(int32_t) * B, hipMemcpyHostToDevice, ln.s) != hipSuccess) {
+            rc = MESSI_EDEVICE;
+            break;
+        }
+        *ln.h_err = 0;
+        if ((rc = knn_enqueue(ix, ln.d_q.as<float>(), (int32_t)B, kw, ln.d_k.as<int32_t>(), mode, ln.s,
+                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err)) != MESSI_OK)
+            break;
+        if (hipStreamSynchronize(ln.s) != hipSuccess) {
+            rc = MESSI_EDEVICE;
+            break;
+        }
+    }
+    if (rc != MESSI_OK) {
+        const int code = last_error_code();
+        delete sv;
+        if (code == MESSI_OK) set_error(rc, "server creation failed");
+        return nullptr;
+    }
+    sv->t0 = std::chrono::steady_clock::now();
+    sv->worker = std::thread([sv] { sv->run(); });
+    return reinterpret_cast<messi_server*>(sv);
 }
-int messi_server_submit(messi_server* server, const float* host_query, int32_t k, uint64_t tag) {
-    (void)server; (void)host_query; (void)k; (void)tag;
-    return MESSI_EINVAL;
-}
-int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out) {
-    (void)server; (void)out; (void)max_out;
-    return MESSI_EINVAL;
-}
-double messi_server_clock_ms(const messi_server* server) { (void)server; return 0.0; }
-void messi_server_destroy(messi_server* server) { (void)server; }
 
+int messi_server_submit(messi_server* server, const float* host_query, int32_t k, uint64_t tag) {
+    clear_error();
+    if (!server || !host_query) {
+        set_error(MESSI_EINVAL, "null argument");
+        return MESSI_EINVAL;
+    }
+    Server* sv = reinterpret_cast<Server*>(server);
+    if (k < 1 || k > MESSI_MAX_K || (int64_t)k > sv->ix->n) {
+        set_error(MESSI_EINVAL, "k must be in [1, min(n, 1024)]");
+        return MESSI_EINVAL;
+    }
+    Pending p;
+    p.q.assign(host_query, host_query + sv->ix->len);
+    p.k = k;
+    p.tag = tag;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->pending.size() >= kMaxPending) {
+            set_error(MESSI_EBUSY, "too many queries waiting");
+            return MESSI_EBUSY;
+        }
+        p.t_submit = sv->now_ms();
+        sv->pending.push_back(std::move(p));
+    }
+    sv->cv.notify_one();
+    return MESSI_OK;
 }
+
+int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out) {
+    clear_error();
+    if (!server || (!out && max_out > 0) || max_out < 0) {
+        set_error(MESSI_EINVAL, "bad argument");
+        return MESSI_EINVAL;
+    }
+    Server* sv = reinterpret_cast<Server*>(server);
+    int32_t n = 0;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    while (n < max_out && !sv->ready.empty()) {
+        messi_result* r = sv->ready.front();
+        sv->ready.pop_front();
+        out[n++] = *r;
+        delete r;
+    }
+    return n;
+}
+
+double messi_server_clock_ms(const messi_server* server) {
+    if (!server) return 0.0;
+    return reinterpret_cast<const Server*>(server)->now_ms();
+}
+
+void messi_server_destroy(messi_server* server) {
+    if (!server) return;
+    Server* sv = reinterpret_cast<Server*>(server);
+    sv->stop.store(true);
+    sv->cv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    delete sv;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+"""Serving with continuous batching: each result is the same alone and in the mix.
+
+Queries of mixed k and difficulty are submitted while earlier ones are still
+on the GPU; every answer must equal the answer of the same query run alone
+(indices and distances bit-identical, since both are exact and the final
+order uses the canonical fp64 distance) and the oracle's brute force."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def messi():
+    from paper_2009_00786_amd import messi as m
+    m.load()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def served(torch_cuda, messi, datagen_mod, oracle_mod):
+    torch = torch_cuda
+    n = 50_000
+    x = datagen_mod.random_walks(n, 256, seed=123)
+    z = oracle_mod.znorm(x)
+    t = torch.from_numpy(x).cuda()
+    ix = messi.Index(t, 16, 8, 2000, znorm=True, bf16_shadow=True)
+    nqueries = 120
+    rows = datagen_mod.uniform_ints(nqueries, n, 31, 3)
+    sig = np.array([(0.01, 0.1, 1.0)[i % 3] for i in range(nqueries)])
+    q = datagen_mod.add_noise(z[rows], sig)
+    ks = np.array([(1, 10, 100)[(i // 3) % 3] for i in range(nqueries)], dtype=np.int32)
+    yield {"z": z, "ix": ix, "q": q, "ks": ks, "n": n}
+    ix.close()
+
+
+def _serve(messi, ix, q, ks, mode, budget, slots, pause):
+    sv = messi.Server(ix, budget, slots, mode)
+    got = {}
+    try:
+        rng = np.random.default_rng(5)
+        for i in range(len(q)):
+            sv.submit(q[i], int(ks[i]), i)
+            if pause and rng.random() < 0.3:
+                time.sleep(rng.random() * pause)
+            for r in sv.poll():
+                got[r["tag"]] = r
+        t_end = time.time() + 120
+        while len(got) < len(q) and time.time() < t_end:
+            for r in sv.poll():
+                got[r["tag"]] = r
+            time.sleep(0.001)
+    finally:
+        sv.close()
+    return got
+
+
+@pytest.mark.parametrize("mode_name,slots", [("BF16", 48), ("FP32", 1)])
+def test_results_alone_and_in_the_mix(served, messi, torch_cuda, oracle_mod, mode_name, slots):
+    w = served
+    mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
+    _say("serving %s, %d slots, %d queries" % (mode_name, slots, len(w["q"])))
+    got = _serve(messi, w["ix"], w["q"], w["ks"], mode, 4 << 30, slots, 0.002)
+    assert len(got) == len(w["q"])
+    for i in range(len(w["q"])):
+        r = got[i]
+        assert r["status"] == messi.MESSI_OK
+        k = int(w["ks"][i])
+        ai, ad = w["ix"].knn(torch_cuda.from_numpy(w["q"][i:i + 1].copy()).cuda(), k)
+        np.testing.assert_array_equal(r["idx"], ai.cpu().numpy()[0])
+        np.testing.assert_array_equal(r["dist"], ad.cpu().numpy()[0])
+        assert r["t_done_ms"] >= r["t_submit_ms"]
+    for i in range(0, len(w["q"]), 7):   # and against the oracle
+        k = int(w["ks"][i])
+        oi, od, _ = oracle_mod.knn_brute(w["z"], w["q"][i:i + 1], k, nthreads=8)
+        np.testing.assert_array_equal(got[i]["idx"], oi[0])
+
+
+def test_budget_and_argument_errors(served, messi):
+    w = served
+    with pytest.raises(messi.MessiError) as e:
+        messi.Server(w["ix"], 1024, 8, messi.MODE_BF16)
+    assert e.value.code == messi.MESSI_ENOMEM
+    sv = messi.Server(w["ix"], 1 << 30, 4, messi.MODE_BF16)
+    with pytest.raises(messi.MessiError) as e:
+        sv.submit(w["q"][0], 0, 1)
+    assert e.value.code == messi.MESSI_EINVAL
+    with pytest.raises(messi.MessiError) as e:
+        sv.submit(w["q"][0], 2000, 1)
+    assert e.value.code == messi.MESSI_EINVAL
+    sv.close()
+
+
+def test_bf16_server_needs_shadow(torch_cuda, messi):
+    z = torch_cuda.randn((200, 32), device="cuda")
+    ix = messi.Index(z, 4, 8, 10)
+    with pytest.raises(messi.MessiError) as e:
+        messi.Server(ix, 1 << 28, 4, messi.MODE_BF16)
+    assert e.value.code == messi.MESSI_EINVAL
+    ix.close()
