@@ -38,6 +38,14 @@ WORKLOADS = {
             k=1),
     3: dict(name="random-walk 100M x 256, batches of 1024 (512 fresh walks + 512 noisy rows), k=1 and k=10, "
                  "BF16 matrix-core filter", n=100_000_000, length=256, queries=1024, k=10),
+    4: dict(name="random-walk 100M x 256, open-loop Poisson arrivals at 200, 1000, 5000 queries/s; per query "
+                 "k in {1, 10, 100} and a dataset row + sigma*N(0,1), sigma in {0.01, 0.1, 1}; BF16 continuous-batching "
+                 "server vs fp32 single-query FIFO", n=100_000_000, length=256, data="walk", rates=(200, 1000, 5000),
+            headline_rate=1000),
+    5: dict(name="Gaussian mixture 200M x 128 (1000 centres U[0,255], sigma 20, integers clipped to [0,255]), "
+                 "z-normalised; open-loop Poisson at 200, 1000, 5000 queries/s, k=10, half noisy dataset rows and "
+                 "half fresh mixture draws; BF16 continuous-batching server vs fp32 single-query FIFO",
+            n=200_000_000, length=128, data="mixture", rates=(200, 1000, 5000), headline_rate=1000),
 }
 
 
@@ -97,6 +105,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=4_000_000)
     ap.add_argument("--cpu-queries", type=int, default=8)
+    ap.add_argument("--duration", type=float, default=10.0, help="seconds of arrivals per rate (configs 4, 5)")
+    ap.add_argument("--rates", type=str, default=None, help="comma-separated arrival rates (configs 4, 5)")
+    ap.add_argument("--no-fifo", action="store_true", help="skip the fp32 FIFO comparison (configs 4, 5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus %d is not supported "
@@ -110,6 +121,8 @@ def main():
 
     if args.config == 3:
         return bench_batched(args)
+    if args.config in (4, 5):
+        return bench_serving(args)
     wl = dict(WORKLOADS[args.config])
     if args.n:
         wl["n"] = args.n
@@ -353,6 +366,198 @@ def bench_batched(args):
         "discard_rate": 1.0 - (agg[1].get("series_recheck", 0) + agg[10].get("series_recheck", 0)) /
         max(1, agg[1].get("series_distance", 0) + agg[10].get("series_distance", 0)),
         "cpu_baseline": None,
+    }
+    ix.close()
+    print(json.dumps(res), flush=True)
+
+
+def serving_queries(data, wl, total, centres_dev=None):
+    """Per arrival: a query vector, its k, and where it came from.  Dataset rows
+    (uniform ids) + sigma * N(0,1), not re-normalised; for the mixture half of
+    the arrivals are fresh mixture draws instead (z-normalised)."""
+    import torch
+
+    import datagen
+    from paper_2009_00786_amd import messi
+    n, length = data.shape
+    sig_choice = datagen.uniform_ints(total, 3, datagen.SEED_QUERY, 12)
+    sig = np.array([0.01, 0.1, 1.0])[sig_choice]
+    if wl["data"] == "walk":
+        ks = np.array([1, 10, 100])[datagen.uniform_ints(total, 3, datagen.SEED_QUERY, 11)].astype(np.int32)
+        ids = datagen.uniform_ints(total, n, datagen.SEED_QUERY, 10)
+        base = data[torch.from_numpy(ids).to(data.device)].cpu().numpy()
+        return datagen.add_noise(base, sig), ks
+    ks = np.full(total, 10, dtype=np.int32)
+    n_fresh, n_noisy = (total + 1) // 2, total // 2
+    ids = datagen.uniform_ints(n_noisy, n, datagen.SEED_QUERY, 10)
+    base = data[torch.from_numpy(ids).to(data.device)].cpu().numpy()
+    noisy = datagen.add_noise(base, sig[:n_noisy])
+    fresh = torch.empty((n_fresh, length), dtype=torch.float32, device=data.device)
+    datagen.gpu_mixture(fresh, centres_dev, seed=datagen.SEED_QUERY, stream=datagen.STREAM_QUERY)
+    messi.znorm_(fresh)
+    q = np.empty((total, length), dtype=np.float32)
+    q[0::2] = fresh.cpu().numpy()
+    q[1::2] = noisy
+    return q, ks
+
+
+def open_loop(sv, qs, ks, arrivals, drain_s):
+    """Submit query i at arrivals[i] seconds after the start (open loop: the
+    schedule never waits for the server), collect results, and return
+    per-query latency = completion - scheduled arrival (ms), NaN if unfinished."""
+    n = len(arrivals)
+    got = {}
+    base_ms = sv.clock_ms()
+    t_start = time.perf_counter()
+    i = 0
+    while i < n:
+        now = time.perf_counter() - t_start
+        if now >= arrivals[i]:
+            sv.submit(qs[i], int(ks[i]), i)
+            i += 1
+            continue
+        for r in sv.poll():
+            got[r["tag"]] = r
+        rem = arrivals[i] - (time.perf_counter() - t_start)
+        if rem > 0.0004:
+            time.sleep(rem - 0.0002)
+    t_last = arrivals[-1]
+    while len(got) < n and time.perf_counter() - t_start < t_last + drain_s:
+        for r in sv.poll():
+            got[r["tag"]] = r
+        time.sleep(0.0005)
+    lat = np.full(n, np.nan)
+    bad = {}
+    for tag, r in got.items():
+        lat[tag] = r["t_done_ms"] - (base_ms + arrivals[tag] * 1e3)
+        if r["status"] != 0:
+            bad[str(r["status"])] = bad.get(str(r["status"]), 0) + 1
+    in_window = sum(1 for tag, r in got.items() if r["t_done_ms"] - base_ms <= t_last * 1e3)
+    return lat, got, in_window, bad
+
+
+def latency_summary(lat, window_s, in_window):
+    done = np.isfinite(lat)
+    frac = float(done.mean())
+    # an unfinished query has unbounded latency: a percentile that falls on one is reported as null
+    srt = np.sort(np.where(done, lat, np.inf))
+
+    def pct(p):
+        v = srt[min(len(srt) - 1, int(np.ceil(p / 100.0 * len(srt))) - 1)]
+        return float(v) if np.isfinite(v) else None
+    return {"arrivals": int(len(lat)), "completed_frac": frac, "sustained_qps": in_window / window_s,
+            "p50_ms": pct(50), "p99_ms": pct(99), "saturated": frac < 0.99}
+
+
+def bench_serving(args):
+    """Configurations 4 and 5: open-loop Poisson arrivals against a resident
+    index; the BF16 continuous-batching server vs the fp32 single-query FIFO."""
+    import torch
+
+    import datagen
+    from paper_2009_00786_amd import messi
+
+    wl = dict(WORKLOADS[args.config])
+    if args.n:
+        wl["n"] = args.n
+        wl["name"] += " (n=%d)" % args.n
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else list(wl["rates"])
+    n, length = wl["n"], wl["length"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    messi.load()
+    data = torch.empty((n, length), dtype=torch.float32, device=dev)
+    centres_dev = None
+    if wl["data"] == "walk":
+        log("generating %d x %d random walks on the GPU" % (n, length))
+        for r0 in range(0, n, 10_000_000):
+            datagen.gpu_random_walks(data[r0:r0 + 10_000_000], row0=r0)
+    else:
+        log("generating %d x %d mixture rows on the GPU" % (n, length))
+        centres_dev = torch.from_numpy(datagen.mixture_centres(1000, length)).to(dev)
+        for r0 in range(0, n, 10_000_000):
+            datagen.gpu_mixture(data[r0:r0 + 10_000_000], centres_dev, row0=r0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    messi.znorm_(data)
+    torch.cuda.synchronize()
+    znorm_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    ix = messi.Index(data, 16, 8, 2000, bf16_shadow=True)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = ix.info()
+    log("build %.1f ms (shadow %.1f ms), %d leaves" % (build_ms, info["ms_shadow"], info["n_leaves"]))
+
+    schedules = {}
+    total = 0
+    for r in rates:
+        m = int(np.ceil(r * args.duration))
+        a = datagen.poisson_arrivals(m + 1, r)
+        a = a[a <= args.duration][:m]
+        schedules[r] = (total, a)
+        total += len(a)
+    qs, ks = serving_queries(data, wl, total, centres_dev)
+    log("%d arrivals over %s /s, %.0f s each" % (total, rates, args.duration))
+
+    budget = 8 << 30
+    out = {}
+    results = {}
+    modes = [("bf16_server", messi.MODE_BF16, 256)] + ([] if args.no_fifo else [("fp32_fifo", messi.MODE_FP32, 1)])
+    for name, mode, slots in modes:
+        out[name] = {}
+        for r in rates:
+            off, a = schedules[r]
+            sv = messi.Server(ix, budget, slots, mode)
+            try:
+                lat, got, in_window, bad = open_loop(sv, qs[off:off + len(a)], ks[off:off + len(a)], a, 5.0)
+            finally:
+                sv.close()
+            summ = latency_summary(lat, float(a[-1]), in_window)
+            summ["errors"] = bad
+            out[name][str(int(r))] = summ
+            results[(name, r)] = got
+            log("%s at %g/s: %s" % (name, r, summ))
+
+    # exactness: the same query must get the same answer from both servers and
+    # when run alone (a fixed sample); every answer is exact, so bit-identical
+    mism_modes, compared = 0, 0
+    if not args.no_fifo:
+        for r in rates:
+            g1, g2 = results[("bf16_server", r)], results[("fp32_fifo", r)]
+            for tag in set(g1) & set(g2):
+                compared += 1
+                if not (np.array_equal(g1[tag]["idx"], g2[tag]["idx"]) and
+                        np.array_equal(g1[tag]["dist"], g2[tag]["dist"])):
+                    mism_modes += 1
+    r_head = float(wl["headline_rate"]) if float(wl["headline_rate"]) in schedules else rates[0]
+    off, a = schedules[r_head]
+    g = results[("bf16_server", r_head)]
+    sample = sorted(g)[:: max(1, len(g) // 200)][:200]
+    mism_alone = 0
+    for tag in sample:
+        qi = torch.from_numpy(qs[off + tag:off + tag + 1].copy()).to(dev)
+        ai, ad = ix.knn(qi, int(ks[off + tag]))
+        if not (np.array_equal(ai.cpu().numpy()[0], g[tag]["idx"]) and
+                np.array_equal(ad.cpu().numpy()[0], g[tag]["dist"])):
+            mism_alone += 1
+    log("alone vs mix: %d/%d mismatches; bf16 server vs fp32 fifo: %d/%d" % (mism_alone, len(sample), mism_modes,
+                                                                            compared))
+    head = out["bf16_server"][str(int(r_head))]
+    res = {
+        "metric": METRIC, "value": head["sustained_qps"], "unit": "queries/s", "n_gpus": 1, "steps": len(rates),
+        "warmup": 0, "ms_per_step": args.duration * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "len": length, "segments": 16, "card_bits": 8, "leaf_cap": 2000,
+                   "rates": rates, "duration_s": args.duration, "headline_rate": r_head, "budget_bytes": budget,
+                   "mode": "BF16 continuous-batching server (256 slots over 4 streams)"},
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "serving": out,
+        "alone_vs_mix": {"sample": len(sample), "mismatches": mism_alone},
+        "bf16_vs_fp32": {"compared": compared, "mismatches": mism_modes},
+        "build_ms_with_shadow": build_ms, "znorm_ms": znorm_ms, "build_gbps": n * length * 4 / (build_ms / 1e3) / 1e9,
+        "index": {"n_leaves": info["n_leaves"], "max_leaf": info["max_leaf"], "levels": info["levels"],
+                  "device_bytes": info["device_bytes"]},
+        "roofline": None, "cpu_baseline": None,
     }
     ix.close()
     print(json.dumps(res), flush=True)

@@ -39,7 +39,7 @@ extern "C" {
 #define MESSI_EDEVICE -3   /* a HIP runtime call or kernel launch failed */
 #define MESSI_ENODEV -4    /* no usable GPU */
 #define MESSI_EBUSY -5     /* server has no free slot (non-blocking submit) */
-#define MESSI_EOVERFLOW -6 /* a query has more tied candidates than the candidate buffer holds */
+#define MESSI_EOVERFLOW -6 /* more candidates tie within rounding of a query's k-th distance than its buffer holds */
 
 #define MESSI_MAX_SEGMENTS 16
 #define MESSI_MAX_LEN 1024
@@ -102,6 +102,12 @@ typedef struct {
     double ms_bf16_filter, ms_bf16_recheck;
     int64_t bf16_flops;
     int32_t bf16_rounds;
+    /* FP32 mode: queries whose candidate buffer overflowed and whose scan was
+       run a second time from the k-th buffered distance */
+    int32_t reruns;
+    /* BF16 mode: queries answered again by the FP32 path because their
+       candidate or filter-pair buffer overflowed */
+    int32_t fallbacks;
 } messi_knn_stats;
 
 /* ---- index ------------------------------------------------------------- */
@@ -135,7 +141,16 @@ int messi_knn(const messi_index* index, const float* queries, int32_t nq, int32_
  * synchronises `stream` before returning, so that per-query errors (a
  * non-finite query, a candidate-buffer overflow) are reported by its return
  * code.  Concurrent calls on one index from different streams are allowed;
- * each stream gets its own search workspace. */
+ * each stream gets its own search workspace.
+ * Every query keeps a buffer of candidate distances (2^20 slots for a single
+ * query, 64 k per query of a batch; the environment variable
+ * MESSI_CANDIDATE_CAP overrides this for testing).  If a query's buffer
+ * overflows, its scan reruns from the k-th buffered distance; if that
+ * overflows too, the call (FP32 mode) retries with a buffer 16 times larger,
+ * twice at most.  In BF16 mode a query whose candidates or filter pairs
+ * overflow their buffers is answered again, alone, in FP32 mode.
+ * MESSI_EOVERFLOW remains only for inputs with more exact ties at the k-th
+ * distance than the buffer can hold. */
 int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t mode,
                  void* stream, int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
 
@@ -182,24 +197,36 @@ typedef struct {
 } messi_result;
 
 /* A request loop that keeps `index` on the device and answers exact k-NN
- * queries with continuous batching: queries submitted while others run are
- * admitted into free slots as soon as slots and device memory (budget_bytes)
- * allow, and share batched launches with the queries already in flight.
- * mode is MESSI_MODE_FP32 or MESSI_MODE_BF16.  The server owns a worker
- * thread and its own stream. */
+ * queries with continuous batching (an extension beyond the paper, which
+ * answers queries one after another, Section 5).  Queries submitted while
+ * others run are admitted into free slots as soon as a slot frees up and
+ * share batched launches; the slots are spread over up to four lanes, each a
+ * HIP stream with its own workspace, that run concurrently.  A result never
+ * depends on which queries shared its batch: each query carries its own
+ * status, and a query whose BF16 buffers overflow is answered again, alone,
+ * in FP32 mode before its result is posted.
+ *   budget_bytes  device memory the server may use for per-query state; the
+ *                 slot count is min(max_slots, budget_bytes / per-query need)
+ *   mode          MESSI_MODE_FP32 or MESSI_MODE_BF16 (needs the BF16 shadow)
+ * Returns NULL on error: MESSI_EINVAL (null index, max_slots < 1, bad mode,
+ * BF16 without a shadow), MESSI_ENOMEM (budget below one query's need, or an
+ * allocation failed), MESSI_EDEVICE.  The index must outlive the server. */
 messi_server* messi_server_create(const messi_index* index, size_t budget_bytes, int32_t max_slots, int32_t mode);
 
-/* Copy host_query[len] and enqueue it.  Non-blocking: returns MESSI_OK or
- * MESSI_EINVAL (bad k). */
+/* Copy host_query[len] (host memory, the index's length) and enqueue it.
+ * Non-blocking: returns MESSI_OK, MESSI_EINVAL (null pointer, k outside
+ * [1, min(n, MESSI_MAX_K)]) or MESSI_EBUSY (2^20 queries already waiting). */
 int messi_server_submit(messi_server* server, const float* host_query, int32_t k, uint64_t tag);
 
-/* Move up to max_out finished results into out; returns how many (>= 0) or an error. */
+/* Move up to max_out finished results into out (host array, caller-owned);
+ * returns how many (>= 0) or MESSI_EINVAL.  Results come in completion order. */
 int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out);
 
 /* Milliseconds on the server clock (the one t_submit_ms / t_done_ms use). */
 double messi_server_clock_ms(const messi_server* server);
 
-/* Stop the worker (after finishing admitted queries) and free everything. */
+/* Drop the queries still waiting for a slot (they get no result), finish the
+ * admitted ones, stop the worker and free everything.  NULL-safe. */
 void messi_server_destroy(messi_server* server);
 
 #ifdef __cplusplus

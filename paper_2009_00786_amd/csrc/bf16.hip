@@ -253,7 +253,13 @@ __global__ void __launch_bounds__(256) bf16_filter_kernel(QArgs a, BfArgs bf) {
                         const float margin = __fsub_rn(f, E);
                         if (!(margin * (1.0f - 2.384185791015625e-07f) > s_U[r])) {
                             const uint32_t slot = atomicAdd(bf.npairs, 1u);
-                            if (slot < bf.pairs_cap) bf.pairs[slot] = make_uint2(q, mpos);
+                            if (slot < bf.pairs_cap) {
+                                bf.pairs[slot] = make_uint2(q, mpos);
+                            } else {
+                                // this query lost a pair: its answer is redone by the fp32 path
+                                a.qs[q].err = 5;
+                                atomicOr(a.err_any, 16u);
+                            }
                             ++c_pass;
                         }
                     }
@@ -348,10 +354,6 @@ __global__ void __launch_bounds__(256) bf16_recheck_kernel(QArgs a, BfArgs bf) {
             atomicAdd(&a.counters->bytes, c_bytes);
         }
     }
-}
-
-__global__ void pairs_overflow_kernel(const uint32_t* npairs, uint32_t cap, uint32_t* err_any) {
-    if (threadIdx.x == 0 && *npairs > cap) atomicOr(err_any, 16u);
 }
 
 int device_cus() {
@@ -475,9 +477,6 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         hipLaunchKernelGGL(bf16_filter_kernel, dim3(cus * 4), dim3(256), 0, s, a, bf);
         MESSI_LAUNCH_CHECK("bf16_filter");
         MESSI_TRY(mark());
-        hipLaunchKernelGGL(pairs_overflow_kernel, dim3(1), dim3(64), 0, s, bf.npairs, bf.pairs_cap, a.err_any);
-        MESSI_LAUNCH_CHECK("pairs_overflow");
-        MESSI_TRY(mark());
         hipLaunchKernelGGL(bf16_recheck_kernel, dim3(cus * 8), dim3(256), 0, s, a, bf);
         MESSI_LAUNCH_CHECK("bf16_recheck");
         MESSI_TRY(mark());
@@ -488,10 +487,10 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     ws->bf_ms_filter = ws->bf_ms_recheck = 0;
     if (timing) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        for (size_t i = 0; i + 3 < evs.size(); i += 4) {
+        for (size_t i = 0; i + 2 < evs.size(); i += 3) {
             float f = 0, r = 0;
             MESSI_HIP_TRY(hipEventElapsedTime(&f, evs[i], evs[i + 1]));
-            MESSI_HIP_TRY(hipEventElapsedTime(&r, evs[i + 2], evs[i + 3]));
+            MESSI_HIP_TRY(hipEventElapsedTime(&r, evs[i + 1], evs[i + 2]));
             ws->bf_ms_filter += f;
             ws->bf_ms_recheck += r;
         }

@@ -9,7 +9,8 @@ constexpr int kNB = 1024;            // lower-bound bins used to order the survi
 constexpr int kApproxMax = 4096;     // members of the first leaf evaluated for the first bound
 constexpr int kApproxBlocks = 128;   // blocks per query for that leaf
 constexpr int kMaxFinal = 4096;      // candidates ordered by fp64 distance per query
-constexpr int kChunk = 1024;         // members filtered per step of the scan
+constexpr int kChunk = 1024;         // members per scan work unit
+constexpr int kHistBins = 4096;      // candidate-distance histogram (k > 1 bound)
 
 // Relative error margins (see the exactness notes in query.hip).
 constexpr float kRhoEd = 1.52587890625e-05f;  // 2^-16, fp32 squared-distance error margin
@@ -20,6 +21,14 @@ struct Cand {
     uint32_t idx;  // series index
 };
 
+// One surviving leaf at its place in the bound order.
+struct OrdRec {
+    uint32_t start;  // first member (leaf order)
+    uint32_t count;  // members
+    float lb;        // lower bound of the leaf
+    uint32_t moff;   // members of all earlier leaves in the order
+};
+
 // Per-query search state (device).
 struct QState {
     float paa[16];
@@ -27,24 +36,24 @@ struct QState {
     float delta;             // widening of every region (covers fp32 PAA error of data and query)
     uint32_t U;              // current upper bound on the k-th squared distance (float bits)
     uint32_t ncand;          // candidates appended
-    uint32_t ticket;         // next position in the ordered leaf list
+    uint32_t nmemb;          // members of the ordered leaves
     uint32_t nsurv;          // leaves in the ordered list
-    uint32_t done;           // no more leaves can improve the answer
+    uint32_t ovf;            // the candidate buffer overflowed in this pass
     uint32_t lbmax;          // max leaf bound (float bits)
     unsigned long long argmin;  // (bound bits << 32) | leaf of the smallest bound
-    uint32_t approx_leaf;
-    uint32_t approx_full;    // the first leaf was evaluated completely
     float range;             // bound range mapped onto the bins
     int32_t k;
     uint32_t err;            // 0 ok, 1 non-finite query, 2 candidate overflow, 3 final overflow, 4 too few
     uint32_t active;         // slot in use (server); 1 for plain calls
     uint32_t kstride;        // output row stride
+    int32_t hbase;           // histogram bin of a distance = (float bits >> 16) - hbase, clamped
+    uint32_t rerun;          // the scan runs a second pass from a tightened bound
     uint32_t pad0;
 };
 
 // Counters accumulated over a call (device).
 struct QCounters {
-    unsigned long long kept, scanned, bounded, distance, abandoned, recheck, final_cands, bytes;
+    unsigned long long kept, scanned, bounded, distance, abandoned, recheck, final_cands, bytes, reruns;
 };
 
 struct QArgs {
@@ -62,9 +71,14 @@ struct QArgs {
     int32_t nq;
     QState* qs;
     float* lb;                   // [nq][nL]
-    uint32_t* order;             // [nq][nL]
-    uint32_t* bins;              // [nq][kNB]
-    uint32_t* cursor;            // [nq][kNB]
+    uint32_t* order;             // [nq][nL] leaf ids in bound order
+    OrdRec* rec;                 // [nq][nL] the same leaves with start, count, bound, member offset
+    uint32_t* chunk_first;       // [nq][max_chunks] order position holding the first member of each chunk
+    uint32_t max_chunks;
+    uint32_t* bins;              // [nq][kNB] leaves per bound bin, then their exclusive prefix
+    uint32_t* mbins;             // [nq][kNB] members per bound bin
+    unsigned long long* cursor;  // [nq][kNB] (position << 32 | member offset) fill cursors
+    uint32_t* hist;              // [nq][kHistBins] candidate-distance histogram
     float* approx_d;             // [nq][kApproxMax]
     Cand* cand;                  // [nq][cap]
     uint32_t cap;
@@ -73,6 +87,7 @@ struct QArgs {
     QCounters* counters;         // nullptr = no counting
     uint32_t* err_any;
     unsigned long long* prof;    // nullptr = no phase timing; else [blocks][4]
+    unsigned long long* blk_cnt; // scan counters per block [blocks][5] (with counters)
     int64_t* out_idx;
     float* out_dist;
 };
@@ -80,8 +95,10 @@ struct QArgs {
 // Per-(index, stream) search workspace, grown on demand.
 struct Workspace {
     int32_t nq = 0, nL = 0;
-    uint32_t cap = 0;
-    DevBuf qs, lb, order, bins, cursor, approx_d, cand, counters, err, prof;
+    size_t cand_slots = 0;  // candidate slots over all queries (a call uses nq * cap of them)
+    uint32_t max_chunks = 0;
+    DevBuf qs, lb, order, rec, chunk_first, bins, mbins, cursor, hist, approx_d, cand, counters, err, prof, blk_cnt,
+        status;
     // BF16 path
     int32_t bf_nq = 0;
     size_t bf_pairs_cap = 0, bf_leafq_cap = 0;
@@ -89,6 +106,13 @@ struct Workspace {
     // timing of the BF16 kernels of the last call (filled when timing is on)
     double bf_ms_filter = 0, bf_ms_recheck = 0;
     int bf_rounds = 0;
+    // statistics read-back: phase events and pinned staging, made on first use
+    hipEvent_t ev[8] = {};
+    QCounters* h_counters = nullptr;
+    unsigned long long* h_prof = nullptr;    // [4096][4]
+    unsigned long long* h_blk_cnt = nullptr; // [4096][5]
+    int ensure_stats();
+    ~Workspace();
 };
 
 // The batched BF16 filter + compensated fp32 recheck (bf16.hip); runs after the
@@ -101,10 +125,20 @@ int refresh_bounds(QArgs& a, hipStream_t s);
 
 // Enqueue a whole search on `s` without waiting (used by the server): kq is an
 // optional device array of per-query k (<= kmax; outputs have row stride kmax);
-// the call's error flags are copied to *host_err (pinned) when the stream
-// reaches that point.  knn_error_code turns those flags into a MESSI_E* code.
+// the call's error flags are copied to *host_err (pinned) and, if host_status
+// is given, every query's own status to host_status[nq] (pinned) when the
+// stream reaches that point.  knn_error_code turns the flags into a MESSI_E*
+// code, query_error_code a query's status.
+// cap_min raises the per-query candidate buffer above its default.
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
-                hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err);
+                hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
+                uint32_t cap_min = 0);
+// Default candidate slots per query for a call of nq queries with k <= kmax.
+uint32_t default_cap(int32_t nq, int32_t kmax);
 int knn_error_code(uint32_t err);
+int query_error_code(uint32_t status);
+
+// Device bytes of search workspace one query needs (for a memory budget).
+size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap);
 
 }  // namespace messi

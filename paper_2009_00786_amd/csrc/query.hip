@@ -9,13 +9,19 @@
 //              on the k-th distance (the paper's initial BSF)
 //  order       the leaves whose bound does not exceed U, counting-sorted into
 //              1024 bound bins: the ascending order the priority queues deliver
-//  scan        persistent blocks walk that order, each block taking every G-th
-//              position of its query; a leaf whose bound exceeds the current U is
-//              skipped and, once a whole bin lies above U, the block stops; inside a leaf each
-//              member's own word gives a second bound (LDS table lookups) and only
-//              the survivors' rows are read, 16 lanes per row, abandoning a
-//              distance as soon as its partial sum exceeds U; U lives in device
-//              memory (atomicMin for k = 1, a k-th-smallest refresh for k > 1)
+//  scan        the members of the ordered leaves, as one list cut into chunks
+//              of 1024, are shared out evenly over the query's blocks (block j
+//              takes chunks j, j + G, ...), so the grid advances through the
+//              order together; a leaf whose bound exceeds the current U is
+//              skipped and, once a chunk starts in a bin wholly above U, the
+//              block stops; inside a leaf each member's own word gives a
+//              second bound (LDS table lookups) and only the survivors' rows
+//              are read, 16 lanes per row, abandoning a distance as soon as
+//              its partial sum exceeds U; U lives in device memory (atomicMin
+//              for k = 1; for k > 1 from a histogram of candidate distances)
+//  fixup       k > 1: U from the exact k-th candidate, candidates compacted;
+//              if the candidate buffer overflowed, its k-th becomes U and the
+//              scan runs once more from that bound
 //  final       candidates within the final U get the canonical fp64 distance and
 //              are ordered by (distance, index); the first k are the answer
 //
@@ -32,6 +38,7 @@
 //  * The final order uses the canonical fp64 distance, so the returned indices
 //    are those of the brute-force definition whatever the visiting order.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -44,7 +51,6 @@ namespace messi {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kUnit = 4;  // leaf positions a scan block takes per step
 
 __device__ __forceinline__ uint32_t vload(const uint32_t* p) {
     return __atomic_load_n(p, __ATOMIC_RELAXED);
@@ -97,13 +103,13 @@ __global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, const int
         st.delta = 1.01f * (2.f * (float)(a.lg_m + 1) * u * a.absmax_data + 2.f * (float)(a.m + 1) * u * aq);
         st.U = 0x7f800000u;  // +inf
         st.ncand = 0;
-        st.ticket = 0;
+        st.nmemb = 0;
         st.nsurv = 0;
-        st.done = 0;
+        st.ovf = 0;
+        st.rerun = 0;
+        st.hbase = 0;
         st.lbmax = 0;
         st.argmin = ~0ull;
-        st.approx_leaf = 0;
-        st.approx_full = 0;
         st.range = 0.f;
         st.k = kq ? kq[q] : k;
         st.err = s_bad ? 1u : 0u;
@@ -111,6 +117,11 @@ __global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, const int
         st.kstride = kstride;
         if (s_bad) atomicOr(a.err_any, 1u);
     }
+    for (int i = threadIdx.x; i < kNB; i += 256) {
+        a.bins[(size_t)q * kNB + i] = 0;
+        a.mbins[(size_t)q * kNB + i] = 0;
+    }
+    for (int i = threadIdx.x; i < kHistBins; i += 256) a.hist[(size_t)q * kHistBins + i] = 0;
 }
 
 // --------------------------------------------------------------------------
@@ -282,20 +293,12 @@ __global__ void __launch_bounds__(256) approx_select_kernel(QArgs a) {
     const float* d = a.approx_d + (size_t)q * kApproxMax;
     const float kth = block_kth([&](uint32_t i) { return d[i]; }, cnt, (uint32_t)st.k, s_hist, s_b);
     const float U0 = isinf(kth) ? kth : upper_u(kth);
-    // only the argmin leaf's own members become candidates here (that leaf is
-    // then skipped by the scan if it was evaluated whole)
-    const bool full = ls >= r0 && ls + lc <= r0 + cnt;
-    for (uint32_t r = threadIdx.x; r < cnt; r += 256) {
-        const uint32_t mp = r0 + r;
-        if (full && mp >= ls && mp < ls + lc && d[r] * (1.0f - kRhoEd) <= U0) {
-            const uint32_t slot = atomicAdd(&st.ncand, 1u);
-            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d[r], a.pos[mp]};
-        }
-    }
+    // The members evaluated here only set the first bound; the leaf stays in
+    // the order and is scanned like any other, so every candidate is appended
+    // exactly once per pass.
     if (threadIdx.x == 0) {
         st.U = __float_as_uint(U0);
-        st.approx_leaf = (uint32_t)(st.argmin & 0xffffffffull);
-        st.approx_full = full ? 1u : 0u;
+        st.hbase = (int32_t)(__float_as_uint(U0) >> 16) - (kHistBins - 2);
         float range = isinf(U0) ? __uint_as_float(st.lbmax) : U0;
         st.range = range > 0.f ? range : 1e-30f;
     }
@@ -310,57 +313,84 @@ __device__ __forceinline__ int bin_of(float lbv, float range) {
     return f >= (float)(kNB - 1) ? kNB - 1 : (int)f;
 }
 
-__device__ __forceinline__ bool leaf_kept(const QState& st, float lbv, uint32_t l, float U0) {
-    if (lbv * (1.0f - kRhoLb) > U0) return false;
-    return !(l == st.approx_leaf && st.approx_full);
-}
+__device__ __forceinline__ bool leaf_kept(float lbv, float U0) { return !(lbv * (1.0f - kRhoLb) > U0); }
 
 __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
     __shared__ uint32_t h[kNB];
+    __shared__ uint32_t hm[kNB];
     const int q = blockIdx.y;
     const QState& st = a.qs[q];
     if (st.err) return;
-    for (int i = threadIdx.x; i < kNB; i += 256) h[i] = 0;
+    for (int i = threadIdx.x; i < kNB; i += 256) {
+        h[i] = 0;
+        hm[i] = 0;
+    }
     __syncthreads();
     const float U0 = __uint_as_float(st.U), range = st.range;
     for (int j = 0; j < kLeavesPerThread; ++j) {
         const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
         if (l >= a.nL) break;
         const float lbv = a.lb[(size_t)q * a.nL + l];
-        if (leaf_kept(st, lbv, (uint32_t)l, U0)) atomicAdd(&h[bin_of(lbv, range)], 1u);
+        if (leaf_kept(lbv, U0)) {
+            const int bn = bin_of(lbv, range);
+            atomicAdd(&h[bn], 1u);
+            atomicAdd(&hm[bn], a.leaves[l].count);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kNB; i += 256)
-        if (h[i]) atomicAdd(&a.bins[(size_t)q * kNB + i], h[i]);
+        if (h[i]) {
+            atomicAdd(&a.bins[(size_t)q * kNB + i], h[i]);
+            atomicAdd(&a.mbins[(size_t)q * kNB + i], hm[i]);
+        }
 }
 
+// Exclusive prefix sums of the leaf and member counts per bin: the fill
+// cursors of the scatter, the number of ordered leaves and of their members.
 __global__ void __launch_bounds__(kNB) bin_scan_kernel(QArgs a) {
-    __shared__ uint32_t wt[kNB / 64];
+    __shared__ uint32_t wt[2][kNB / 64];
     const int q = blockIdx.x;
     QState& st = a.qs[q];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint32_t v = a.bins[(size_t)q * kNB + t];
-    uint32_t x = v;
+    const uint32_t vm = a.mbins[(size_t)q * kNB + t];
+    uint32_t x = v, xm = vm;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
+        const uint32_t ym = __shfl_up(xm, off);
+        if (lane >= off) {
+            x += y;
+            xm += ym;
+        }
     }
-    if (lane == 63) wt[wave] = x;
+    if (lane == 63) {
+        wt[0][wave] = x;
+        wt[1][wave] = xm;
+    }
     __syncthreads();
-    uint32_t wo = 0, tot = 0;
+    uint32_t wo = 0, tot = 0, wom = 0, totm = 0;
     for (int w = 0; w < kNB / 64; ++w) {
-        if (w < wave) wo += wt[w];
-        tot += wt[w];
+        if (w < wave) {
+            wo += wt[0][w];
+            wom += wt[1][w];
+        }
+        tot += wt[0][w];
+        totm += wt[1][w];
     }
-    const uint32_t ex = wo + x - v;
+    const uint32_t ex = wo + x - v, exm = wom + xm - vm;
     a.bins[(size_t)q * kNB + t] = ex;
-    a.cursor[(size_t)q * kNB + t] = ex;
+    a.cursor[(size_t)q * kNB + t] = ((unsigned long long)ex << 32) | exm;
     if (t == 0) {
         st.nsurv = st.err ? 0u : tot;
+        st.nmemb = st.err ? 0u : totm;
         if (a.counters) atomicAdd(&a.counters->kept, (unsigned long long)tot);
     }
 }
 
+// Place every kept leaf at its position in the bin order.  One 64-bit atomic
+// hands out the position and the member offset together, so member offsets
+// increase with the position; the leaf whose member range holds the first
+// member of a scan chunk records itself as that chunk's first position.
 __global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
     const int q = blockIdx.y;
     const QState& st = a.qs[q];
@@ -370,9 +400,18 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
         const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
         if (l >= a.nL) break;
         const float lbv = a.lb[(size_t)q * a.nL + l];
-        if (leaf_kept(st, lbv, (uint32_t)l, U0)) {
-            const uint32_t slot = atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], 1u);
-            if (slot < (uint32_t)a.nL) a.order[(size_t)q * a.nL + slot] = (uint32_t)l;
+        if (leaf_kept(lbv, U0)) {
+            const Leaf lf = a.leaves[l];
+            const unsigned long long old =
+                atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], (1ull << 32) | lf.count);
+            const uint32_t t = (uint32_t)(old >> 32), moff = (uint32_t)old;
+            if (t < (uint32_t)a.nL) {
+                a.order[(size_t)q * a.nL + t] = (uint32_t)l;
+                a.rec[(size_t)q * a.nL + t] = OrdRec{lf.start, lf.count, lbv, moff};
+                const uint64_t end = (uint64_t)moff + lf.count;
+                for (uint64_t c = ((uint64_t)moff + kChunk - 1) / kChunk; c * kChunk < end; ++c)
+                    if (c < a.max_chunks) a.chunk_first[(size_t)q * a.max_chunks + c] = t;
+            }
         }
     }
 }
@@ -385,41 +424,61 @@ __device__ __forceinline__ uint32_t word_byte(const uint4& wd, int i) {
     return (v >> (8 * (i & 3))) & 0xFFu;
 }
 
-// Refresh U of a query from its candidates (k > 1): U <= up(kth (1 + 2 rho)).
-// Other blocks may have reserved a slot (ncand) without having written it yet;
-// the buffer is pre-filled with an all-ones pattern (a NaN whose bits order
-// above every distance), so such a slot can only raise the k-th value.
-__device__ void refresh_u(QArgs& a, int q, QState& st, uint32_t* s_hist, uint32_t* s_b) {
-    if (threadIdx.x == 0) s_b[0] = min(vload(&st.ncand), a.cap);
-    __syncthreads();
-    const uint32_t n = s_b[0];
-    __syncthreads();
-    const Cand* c = a.cand + (size_t)q * a.cap;
-    const float kth = block_kth(
-        [&](uint32_t i) { return __uint_as_float(vload(reinterpret_cast<const uint32_t*>(&c[i].d))); }, n,
-        (uint32_t)st.k, s_hist, s_b);
-    if (threadIdx.x == 0 && !isinf(kth) && !isnan(kth)) atomicMin(&st.U, __float_as_uint(upper_u(kth)));
+// ---- candidate bookkeeping -------------------------------------------------
+// For k > 1 the bound is the k-th smallest candidate distance.  During the scan
+// it comes from a histogram of the candidate distances binned by their top 16
+// float bits (128 bins per octave below the first bound): every candidate in
+// the bins up to the one where the running count reaches k lies below that
+// bin's upper edge, so the edge bounds the k-th distance from above.  Between
+// kernels the exact k-th is taken from the candidate buffer itself.
+__device__ __forceinline__ uint32_t hist_bin(float d, int32_t hbase) {
+    const int32_t b = (int32_t)(__float_as_uint(d) >> 16) - hbase;
+    return (uint32_t)min(max(b, 0), kHistBins - 1);
 }
 
-// Leaves of query q are visited in the bin order; the G blocks assigned to q
-// take positions j, j + G, j + 2G, ... (static, no shared ticket), so the
-// whole grid advances through the order together.  A block stops its share of
-// q at the first position whose bin lies entirely above U.
-// One block per query, between kernels: for k > 1, lower U to the k-th
-// candidate distance; then drop the candidates that can no longer be answers
-// (d (1 - rho) > U), compacting the list in place (order kept).
-__global__ void __launch_bounds__(256) refresh_kernel(QArgs a) {
-    __shared__ uint32_t s_hist[256 + 4];
-    __shared__ uint32_t s_b[2];
-    __shared__ uint32_t s_tmp[4];
-    const int q = blockIdx.x;
-    QState& st = a.qs[q];
-    if (st.err) return;
-    if (st.k > 1) refresh_u(a, q, st, s_hist, s_b);
-    __syncthreads();
-    const float U = __uint_as_float(st.U);
+// Lower U from the histogram (block-wide; call from every thread).
+__device__ void hist_refresh(const QArgs& a, int q, QState& st, uint32_t* s_tmp, float* s_Ublk) {
+    const uint32_t* h = a.hist + (size_t)q * kHistBins;
+    constexpr int kPer = kHistBins / 256;
+    const int t = threadIdx.x;
+    uint32_t v[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        v[i] = vload(h + t * kPer + i);
+        sum += v[i];
+    }
+    uint32_t total;
+    const uint32_t excl = block_exclusive_scan(sum, s_tmp, total);
+    const uint32_t k = (uint32_t)st.k;
+    if (total >= k && excl < k && excl + sum >= k) {
+        uint32_t c = excl, b = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            if (c < k && c + v[i] >= k) b = t * kPer + i;
+            c += v[i];
+        }
+        const int32_t e = (int32_t)b + 1 + st.hbase;  // upper edge of bin b, as float bits >> 16
+        if (b < (uint32_t)(kHistBins - 1) && e > 0 && e < 0x7f80) {
+            const uint32_t ub = __float_as_uint(upper_u(__uint_as_float((uint32_t)e << 16)));
+            atomicMin(&st.U, ub);
+            atomicMin(reinterpret_cast<uint32_t*>(s_Ublk), ub);
+        }
+    }
+}
+
+// Between kernels (every slot written): for k > 1 set U from the exact k-th
+// candidate distance, then drop the candidates that can no longer be answers
+// (d (1 - rho) > U), compacting the list in place.  One block per query.
+__device__ void refresh_compact(QArgs& a, int q, QState& st, uint32_t* s_hist, uint32_t* s_b, uint32_t* s_tmp) {
     const uint32_t n = min(st.ncand, a.cap);
     Cand* c = a.cand + (size_t)q * a.cap;
+    if (st.k > 1) {
+        const float kth = block_kth([&](uint32_t i) { return c[i].d; }, n, (uint32_t)st.k, s_hist, s_b);
+        if (threadIdx.x == 0 && !isinf(kth) && !isnan(kth)) atomicMin(&st.U, __float_as_uint(upper_u(kth)));
+    }
+    __syncthreads();
+    const float U = __uint_as_float(st.U);
     uint32_t out = 0;
     for (uint32_t r0 = 0; r0 < n; r0 += 256) {
         const uint32_t i = r0 + threadIdx.x;
@@ -438,17 +497,78 @@ __global__ void __launch_bounds__(256) refresh_kernel(QArgs a) {
     if (threadIdx.x == 0 && st.ncand <= a.cap) st.ncand = out;
 }
 
+__global__ void __launch_bounds__(256) refresh_kernel(QArgs a) {
+    __shared__ uint32_t s_hist[256 + 4];
+    __shared__ uint32_t s_b[2];
+    __shared__ uint32_t s_tmp[4];
+    const int q = blockIdx.x;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    refresh_compact(a, q, st, s_hist, s_b, s_tmp);
+}
+
+// After scan pass `pass`.  If the candidate buffer overflowed, the cap
+// candidates it holds are exact distances of distinct series, so their k-th is
+// a valid bound: take it, empty the buffer and the histogram, and let the
+// second pass rescan from that much tighter bound.  A second overflow means
+// more than cap candidates lie within rounding of the k-th distance (massive
+// duplication) and is reported.  Otherwise (k > 1) tighten and compact.
+__global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
+    __shared__ uint32_t s_hist[256 + 4];
+    __shared__ uint32_t s_b[2];
+    __shared__ uint32_t s_tmp[4];
+    const int q = blockIdx.x;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    if (pass == 1 && !st.rerun) return;
+    if (st.ovf) {
+        if (pass == 1) {
+            if (threadIdx.x == 0) {
+                st.err = 2;
+                atomicOr(a.err_any, 2u);
+            }
+            return;
+        }
+        const Cand* c = a.cand + (size_t)q * a.cap;
+        const float kth = block_kth([&](uint32_t i) { return c[i].d; }, a.cap, (uint32_t)st.k, s_hist, s_b);
+        for (int i = threadIdx.x; i < kHistBins; i += 256) a.hist[(size_t)q * kHistBins + i] = 0;
+        if (threadIdx.x == 0) {
+            if (!isinf(kth) && !isnan(kth)) atomicMin(&st.U, __float_as_uint(upper_u(kth)));
+            st.ncand = 0;
+            st.ovf = 0;
+            st.rerun = 1;
+            if (a.counters) atomicAdd(&a.counters->reruns, 1ull);
+        }
+        return;
+    }
+    if (st.k > 1) refresh_compact(a, q, st, s_hist, s_b, s_tmp);
+}
+
+// ---- the ordered scan --------------------------------------------------------
+// The members of the ordered leaves form one list (leaf after leaf in bound
+// order); it is cut into chunks of kChunk members and the G blocks of a query
+// take chunks j, j + G, j + 2G, ...  Every block does the same amount of
+// member work, and the grid still advances through the order together, so
+// the best leaves are scanned first and U tightens early.  Per chunk:
+//   control   the chunk's leaves (start, bound, member offset) into LDS; stop
+//             once the chunk's first leaf lies in a bin wholly above U
+//   filter    per member: leaf bound, then the member's own word bound from
+//             the LDS table; survivors compacted into LDS
+//   distance  16 lanes per row, two rows per 16 lanes in flight, abandoning
+//             a row once half of it already exceeds U
+//   bound     k = 1: atomicMin of U; k > 1: histogram, then U from it
+// Pass 1 runs only for queries whose candidate buffer overflowed in pass 0.
 template <bool VEC>
-__global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
+__global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a, int pass) {
     __shared__ float s_D[16 * 256];
     __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ uint32_t s_surv[kChunk];
+    __shared__ uint32_t s_pbase[kChunk];  // word index of the chunk's member 0 if it were in this leaf
+    __shared__ float s_plb[kChunk];
+    __shared__ uint16_t s_pm[kChunk];     // first chunk-relative member of each leaf (0 for the first)
     __shared__ uint32_t s_tmp[4];
-    __shared__ uint32_t s_hist[256 + 4];
-    __shared__ uint32_t s_b[2];
-    __shared__ uint32_t s_flag, s_app;
-    __shared__ uint32_t s_ustart[kUnit], s_ucnt[kUnit], s_ustop[kUnit];
-    __shared__ float s_Ublk;  // block's view of U: refreshed each step, lowered by its own finds
+    __shared__ uint32_t s_flag, s_app, s_stop;
+    __shared__ float s_Ublk;  // block's view of U: refreshed each chunk, lowered by its own finds
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4, ql = lane & 15;
     const int nq = a.nq;
@@ -471,16 +591,18 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
     // optional per-block phase timing (thread 0): control, member filter, distances, total
     unsigned long long t_ctl = 0, t_lb = 0, t_ed = 0, t_mark = 0;
     const unsigned long long t_begin = (a.prof && tid == 0) ? wall_clock64() : 0ull;
+    bool worked = false;
     for (int q = q0; q < nq; q += qstep) {
         QState& st = a.qs[q];
         if (tid == 0) {
-            s_flag = (st.err != 0 || st.nsurv == 0) ? 1u : 0u;
+            s_flag = (st.err != 0 || st.nsurv == 0 || (pass == 1 && st.rerun == 0)) ? 1u : 0u;
             s_Ublk = __uint_as_float(0x7f800000u);
         }
         __syncthreads();
         const bool skip = s_flag != 0;
         __syncthreads();
         if (skip) continue;
+        worked = true;
         {
             const int A = 1 << a.b;
             const float delta = st.delta;
@@ -502,217 +624,236 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
             for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
         }
         const uint32_t nsurv = st.nsurv;
+        const uint64_t nmemb = st.nmemb;
         const int k = st.k;
         const float range = st.range;
-        for (uint32_t step = 0;; ++step) {
+        const uint64_t nch = (nmemb + kChunk - 1) / kChunk;
+        for (uint64_t c = j; c < nch; c += G) {
             if (a.prof && tid == 0) t_mark = wall_clock64();
-            // ---- control: the next kUnit positions of this block, read in parallel
-            if (tid < kUnit) {
-                const uint32_t t = j + (step * kUnit + tid) * (uint32_t)G;
-                uint32_t cnt = 0, start = 0, stop = 1;
+            // ---- control
+            if (tid == 0) {
+                s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
+                s_stop = vload(&st.ovf);
+                s_app = 0;
+            }
+            const uint64_t cbeg = c * kChunk;
+            const uint32_t clen = (uint32_t)min((uint64_t)kChunk, nmemb - cbeg);
+            const uint32_t t0 = a.chunk_first[(size_t)q * a.max_chunks + c];
+            __syncthreads();
+            if (s_stop) break;  // this pass overflowed; it is redone from a tighter bound
+            const float Uc = s_Ublk;
+            uint32_t np = 0;
+            for (uint32_t b0 = 0; b0 < (uint32_t)kChunk; b0 += kScanThreads) {
+                const uint32_t t = t0 + b0 + tid;
+                bool inc = false;
                 if (t < nsurv) {
-                    const uint32_t leaf = a.order[(size_t)q * a.nL + t];
-                    const float lbv = a.lb[(size_t)q * a.nL + leaf];
-                    const float U0 = __uint_as_float(vload(&st.U));
-                    stop = 0;
-                    if (lbv * (1.0f - kRhoLb) > U0) {
-                        // bins ascend: once a bin's lower edge is above U, later positions are too
-                        const float low = (float)bin_of(lbv, range) * (range / (float)kNB);
-                        stop = (low * (1.0f - 2.0f * kRhoLb) > U0) ? 1u : 0u;
-                    } else {
-                        const Leaf lf = a.leaves[leaf];
-                        cnt = lf.count;
-                        start = lf.start;
+                    const OrdRec r = a.rec[(size_t)q * a.nL + t];
+                    inc = (uint64_t)r.moff < cbeg + kChunk;
+                    if (inc) {
+                        const uint32_t p = b0 + tid;
+                        s_pbase[p] = r.start + (uint32_t)cbeg - r.moff;  // modulo 2^32
+                        s_pm[p] = (uint64_t)r.moff > cbeg ? (uint16_t)(r.moff - (uint32_t)cbeg) : (uint16_t)0;
+                        s_plb[p] = r.lb;
+                        if ((uint64_t)r.moff >= cbeg && !(r.lb * (1.0f - kRhoLb) > Uc)) ++c_scanned;
                     }
                 }
-                s_ustart[tid] = start;
-                s_ucnt[tid] = cnt;
-                s_ustop[tid] = stop;
-                if (tid == 0) s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
+                // the included leaves are a prefix of the positions from t0
+                const int cnt = __syncthreads_count(inc);
+                np += (uint32_t)cnt;
+                if (cnt < kScanThreads) break;
             }
-            if (tid == 0) s_app = 0;
-            __syncthreads();
-            uint32_t off[kUnit + 1];
-            off[0] = 0;
-            bool stop_after = false;
-#pragma unroll
-            for (int u = 0; u < kUnit; ++u) {
-                off[u + 1] = off[u] + s_ucnt[u];
-                stop_after |= s_ustop[u] != 0;
+            if (np == 0) break;
+            {
+                // bins ascend along the order: once the chunk's first leaf lies
+                // in a bin wholly above U, so does every later chunk
+                const float lb0 = s_plb[0];
+                const float low = (float)bin_of(lb0, range) * (range / (float)kNB);
+                if (lb0 * (1.0f - kRhoLb) > Uc && low * (1.0f - 2.0f * kRhoLb) > Uc) break;
             }
-            uint32_t ustart[kUnit];
-#pragma unroll
-            for (int u = 0; u < kUnit; ++u) ustart[u] = s_ustart[u];
-            const bool first_stopped = s_ustop[0] != 0;
-            __syncthreads();
             if (a.prof && tid == 0) {
                 const unsigned long long now = wall_clock64();
                 t_ctl += now - t_mark;
                 t_mark = now;
             }
-            if (first_stopped) break;
-            const uint32_t total_m = off[kUnit];
-            uint32_t appended = 0;
-            for (uint32_t c0 = 0; c0 < total_m; c0 += kChunk) {
-                // ---- second filter: bound from each member's own word (all loads first)
-                if (tid == 0) s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
-                __syncthreads();
-                const float Uf = s_Ublk;
-                const uint32_t cend = min(total_m, c0 + (uint32_t)kChunk);
-                uint4 wd[kChunk / kScanThreads];
-                uint32_t mpos[kChunk / kScanThreads];
+            // ---- filter: leaf bound, then the member's own word (all loads first)
+            constexpr int kPer = kChunk / kScanThreads;
+            uint4 wd[kPer];
+            uint32_t mpos[kPer];
+            uint32_t live = 0;
 #pragma unroll
-                for (int r = 0; r < kChunk / kScanThreads; ++r) {
-                    const uint32_t f = c0 + r * kScanThreads + tid;
-                    uint32_t u = 0;
-#pragma unroll
-                    for (int uu = 1; uu < kUnit; ++uu) u += (f >= off[uu]) ? 1u : 0u;
-                    mpos[r] = ustart[u] + (f - off[u]);
-                    wd[r] = (f < cend) ? a.words[mpos[r]] : make_uint4(0, 0, 0, 0);
-                }
-                uint32_t keepmask = 0, nkeep = 0;
-#pragma unroll
-                for (int r = 0; r < kChunk / kScanThreads; ++r) {
-                    const uint32_t f = c0 + r * kScanThreads + tid;
-                    if (f < cend) {
-                        float sum = 0.f;
-#pragma unroll
-                        for (int i = 0; i < 16; ++i)
-                            if (i < a.w) sum += s_D[i * 256 + word_byte(wd[r], i)];
-                        if (!(sum * (1.0f - kRhoLb) > Uf)) {
-                            keepmask |= 1u << r;
-                            ++nkeep;
-                        }
-                        ++c_bounded;
+            for (int r = 0; r < kPer; ++r) {
+                const uint32_t f = r * kScanThreads + tid;
+                mpos[r] = 0;
+                if (f < clen) {
+                    int lo = 0, hi = (int)np - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if ((uint32_t)s_pm[mid] <= f) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    if (!(s_plb[lo] * (1.0f - kRhoLb) > Uc)) {
+                        live |= 1u << r;
+                        mpos[r] = s_pbase[lo] + f;
                     }
                 }
-                uint32_t total;
-                uint32_t o = block_exclusive_scan(nkeep, s_tmp, total);
+                wd[r] = (live & (1u << r)) ? a.words[mpos[r]] : make_uint4(0, 0, 0, 0);
+            }
+            const float Uf = s_Ublk;
+            uint32_t keepmask = 0, nkeep = 0;
 #pragma unroll
-                for (int r = 0; r < kChunk / kScanThreads; ++r)
-                    if (keepmask & (1u << r)) s_surv[o++] = mpos[r];
-                __syncthreads();
-                const uint32_t nsv = total;
-                if (a.prof && tid == 0) {
-                    const unsigned long long now = wall_clock64();
-                    t_lb += now - t_mark;
-                    t_mark = now;
+            for (int r = 0; r < kPer; ++r) {
+                if (live & (1u << r)) {
+                    float sum = 0.f;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (i < a.w) sum += s_D[i * 256 + word_byte(wd[r], i)];
+                    if (!(sum * (1.0f - kRhoLb) > Uf)) {
+                        keepmask |= 1u << r;
+                        ++nkeep;
+                    }
+                    ++c_bounded;
                 }
-                // ---- real distances: 16 lanes per row, 4 rows per wave, abandon per 512 B
-                for (uint32_t base = wave * 4; base < nsv; base += 16) {
-                    const uint32_t si = base + quarter;
-                    const bool act = si < nsv;
-                    uint32_t gidx = 0;
-                    if (act) gidx = a.pos[s_surv[si]];
-                    const float* row = a.series + (size_t)gidx * L;
-                    float acc = 0.f;
-                    bool alive = act;
-                    for (int ch = 0; ch < nchunk; ch += 2) {
-                        if (alive) {
+            }
+            uint32_t total;
+            uint32_t o = block_exclusive_scan(nkeep, s_tmp, total);
 #pragma unroll
-                            for (int cc = 0; cc < 2; ++cc) {
-                                const int c = ch + cc;
-                                if (c < nchunk) {
-                                    const int j0 = c * 64 + ql * 4;
-                                    if (VEC) {
-                                        if (j0 < L) {
-                                            const float4 x = *reinterpret_cast<const float4*>(row + j0);
-                                            const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
-                                            const float d0 = y.x - x.x, d1 = y.y - x.y, d2 = y.z - x.z, d3 = y.w - x.w;
-                                            acc = fmaf(d0, d0, acc);
-                                            acc = fmaf(d1, d1, acc);
-                                            acc = fmaf(d2, d2, acc);
-                                            acc = fmaf(d3, d3, acc);
-                                        }
-                                    } else {
+            for (int r = 0; r < kPer; ++r)
+                if (keepmask & (1u << r)) s_surv[o++] = mpos[r];
+            __syncthreads();
+            const uint32_t nsv = total;
+            if (a.prof && tid == 0) {
+                const unsigned long long now = wall_clock64();
+                t_lb += now - t_mark;
+                t_mark = now;
+            }
+            // ---- distances: 16 lanes per row, 8 rows per wave, abandon per 512 B
+            uint32_t appended = 0;
+            for (uint32_t base = wave * 8; base < nsv; base += 32) {
+                uint32_t gidx[2];
+                bool act[2], alive[2];
+                float acc[2];
 #pragma unroll
-                                        for (int e = 0; e < 4; ++e) {
-                                            const int jj = j0 + e;
-                                            if (jj < L) {
-                                                const float d = s_q[jj] - row[jj];
-                                                acc = fmaf(d, d, acc);
-                                            }
+                for (int rr = 0; rr < 2; ++rr) {
+                    const uint32_t si = base + rr * 4 + quarter;
+                    act[rr] = si < nsv;
+                    gidx[rr] = act[rr] ? a.pos[s_surv[si]] : 0u;
+                    alive[rr] = act[rr];
+                    acc[rr] = 0.f;
+                }
+                for (int ch = 0; ch < nchunk; ch += 2) {
+#pragma unroll
+                    for (int rr = 0; rr < 2; ++rr) {
+                        if (!alive[rr]) continue;
+                        const float* row = a.series + (size_t)gidx[rr] * L;
+#pragma unroll
+                        for (int cc = 0; cc < 2; ++cc) {
+                            const int cix = ch + cc;
+                            if (cix < nchunk) {
+                                const int j0 = cix * 64 + ql * 4;
+                                if (VEC) {
+                                    if (j0 < L) {
+                                        const float4 x = *reinterpret_cast<const float4*>(row + j0);
+                                        const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
+                                        const float d0 = y.x - x.x, d1 = y.y - x.y, d2 = y.z - x.z, d3 = y.w - x.w;
+                                        acc[rr] = fmaf(d0, d0, acc[rr]);
+                                        acc[rr] = fmaf(d1, d1, acc[rr]);
+                                        acc[rr] = fmaf(d2, d2, acc[rr]);
+                                        acc[rr] = fmaf(d3, d3, acc[rr]);
+                                    }
+                                } else {
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e) {
+                                        const int jj = j0 + e;
+                                        if (jj < L) {
+                                            const float d = s_q[jj] - row[jj];
+                                            acc[rr] = fmaf(d, d, acc[rr]);
                                         }
                                     }
                                 }
                             }
                         }
-                        float p = acc;
+                    }
+                    const float Un = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_Ublk)));
+#pragma unroll
+                    for (int rr = 0; rr < 2; ++rr) {
+                        float p = acc[rr];
                         p += __shfl_xor(p, 8, 16);
                         p += __shfl_xor(p, 4, 16);
                         p += __shfl_xor(p, 2, 16);
                         p += __shfl_xor(p, 1, 16);
                         p = __shfl(p, quarter * 16, 64);  // one value per row on every lane of the row
-                        if (alive) c_bytes += (uint64_t)min(2, nchunk - ch) * 256u;
+                        if (alive[rr]) c_bytes += (uint64_t)min(2, nchunk - ch) * 256u;
                         if (ch + 2 < nchunk) {
-                            // one value for the whole wave (other waves may lower it meanwhile)
-                            const float Un = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_Ublk)));
-                            if (alive && p * (1.0f - kRhoEd) > Un) {
-                                alive = false;
+                            // one U for the whole wave (other waves may lower it meanwhile)
+                            if (alive[rr] && p * (1.0f - kRhoEd) > Un) {
+                                alive[rr] = false;
                                 if (ql == 0) ++c_abandon;
                             }
                         } else {
-                            acc = p;  // the full distance
-                        }
-                    }
-                    if (act && ql == 0) ++c_dist;
-                    if (alive && ql == 0) {
-                        const float d = acc;
-                        const float Un = s_Ublk;
-                        if (d * (1.0f - kRhoEd) <= Un) {
-                            const uint32_t slot = atomicAdd(&st.ncand, 1u);
-                            if (slot < a.cap) {
-                                a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx};
-                            } else {
-                                st.err = 2;
-                                atomicOr(a.err_any, 2u);
-                            }
-                            ++appended;
-                            if (k == 1) {
-                                const uint32_t ub = __float_as_uint(upper_u(d));
-                                atomicMin(&st.U, ub);
-                                atomicMin(reinterpret_cast<uint32_t*>(&s_Ublk), ub);
-                            }
+                            acc[rr] = p;  // the full distance
                         }
                     }
                 }
-                __syncthreads();
-                if (a.prof && tid == 0) {
-                    const unsigned long long now = wall_clock64();
-                    t_ed += now - t_mark;
-                    t_mark = now;
-                }
-            }
 #pragma unroll
-            for (int u = 0; u < kUnit; ++u) c_scanned += (off[u + 1] > off[u]) ? 1u : 0u;
-            if (k > 1) {
-                if (appended) atomicAdd(&s_app, appended);
-                __syncthreads();
-                if (s_app) refresh_u(a, q, st, s_hist, s_b);
+                for (int rr = 0; rr < 2; ++rr) {
+                    if (act[rr] && ql == 0) ++c_dist;
+                    if (!(alive[rr] && ql == 0)) continue;
+                    const float d = acc[rr];
+                    if (d * (1.0f - kRhoEd) <= s_Ublk) {
+                        const uint32_t slot = atomicAdd(&st.ncand, 1u);
+                        if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx[rr]};
+                        else st.ovf = 1;
+                        ++appended;
+                        if (k == 1) {
+                            const uint32_t ub = __float_as_uint(upper_u(d));
+                            atomicMin(&st.U, ub);
+                            atomicMin(reinterpret_cast<uint32_t*>(&s_Ublk), ub);
+                        } else {
+                            atomicAdd(&a.hist[(size_t)q * kHistBins + hist_bin(d, st.hbase)], 1u);
+                        }
+                    }
+                }
             }
+            if (k > 1 && appended) atomicAdd(&s_app, appended);
             __syncthreads();
-            if (stop_after) break;
+            if (a.prof && tid == 0) {
+                const unsigned long long now = wall_clock64();
+                t_ed += now - t_mark;
+                t_mark = now;
+            }
+            if (k > 1 && s_app) hist_refresh(a, q, st, s_tmp, &s_Ublk);
+            __syncthreads();
         }
+        __syncthreads();
     }
-    if (a.prof && tid == 0) {
+    if (a.prof && tid == 0 && (pass == 0 || worked)) {
+        // pass 0 writes the block's times; a second pass adds its own
         unsigned long long* pr = a.prof + (size_t)blockIdx.x * 4;
-        pr[0] = t_ctl;
-        pr[1] = t_lb;
-        pr[2] = t_ed;
-        pr[3] = wall_clock64() - t_begin;
+        const unsigned long long v[4] = {t_ctl, t_lb, t_ed, wall_clock64() - t_begin};
+        for (int i = 0; i < 4; ++i) pr[i] = (pass == 0 ? 0ull : pr[i]) + v[i];
     }
-    if (a.counters) {
-        unsigned long long v[5] = {c_scanned, c_bounded, c_dist, c_abandon, c_bytes};
+    if (a.blk_cnt) {
+        // per-block totals in plain stores (the host adds them up): same-address
+        // atomics from every block at once would serialise at the end of the grid
+        __shared__ unsigned long long s_cnt[4][5];
+        unsigned long long v[5] = {c_scanned, c_bounded, c_dist, c_abandon, c_bytes / 16 + c_bounded * 16ull};
         for (int i = 0; i < 5; ++i)
             for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
-        if (lane == 0) {
-            if (wave == 0) atomicAdd(&a.counters->scanned, v[0] / 64);  // counted by every thread
-            atomicAdd(&a.counters->bounded, v[1]);
-            atomicAdd(&a.counters->distance, v[2]);
-            atomicAdd(&a.counters->abandoned, v[3]);
-            atomicAdd(&a.counters->bytes, v[4] / 16 + v[1] * 16ull);
+        if (lane == 0)
+            for (int i = 0; i < 5; ++i) s_cnt[wave][i] = v[i];
+        __syncthreads();
+        if (tid < 5 && (pass == 0 || worked)) {
+            const unsigned long long t = s_cnt[0][tid] + s_cnt[1][tid] + s_cnt[2][tid] + s_cnt[3][tid];
+            unsigned long long* p = a.blk_cnt + (size_t)blockIdx.x * 5 + tid;
+            *p = (pass == 0 ? 0ull : *p) + t;
         }
     }
+}
+
+// Every query's own status (QState::err) for the caller.
+__global__ void status_kernel(QArgs a, uint32_t* out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < a.nq) out[q] = a.qs[q].err;
 }
 
 // --------------------------------------------------------------------------
@@ -806,28 +947,73 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
 std::mutex g_ws_mu;
 std::map<std::pair<const Index*, hipStream_t>, Workspace*> g_ws;
 
+}  // namespace
+
+// Candidate slots per query: 2^20 for a single query, 64 k (at least 2^14)
+// per query of a batch.  MESSI_CANDIDATE_CAP in the environment overrides the
+// default (at least 2 k), to exercise the overflow paths in tests.
+uint32_t default_cap(int32_t nq, int32_t kmax) {
+    const uint32_t floor_k = 2u * (uint32_t)kmax;
+    if (const char* v = std::getenv("MESSI_CANDIDATE_CAP")) {
+        const long long x = std::atoll(v);
+        if (x > 0) return std::max<uint32_t>(floor_k, (uint32_t)std::min<long long>(x, 1ll << 30));
+    }
+    return nq == 1 ? (1u << 20) : std::max<uint32_t>(1u << 14, 64u * (uint32_t)kmax);
+}
+
+int Workspace::ensure_stats() {
+    if (ev[0]) return MESSI_OK;
+    for (auto& e : ev) MESSI_HIP_TRY(hipEventCreate(&e));
+    MESSI_HIP_TRY(hipHostMalloc((void**)&h_counters, sizeof(QCounters), 0));
+    MESSI_HIP_TRY(hipHostMalloc((void**)&h_prof, sizeof(unsigned long long) * 4 * 4096, 0));
+    MESSI_HIP_TRY(hipHostMalloc((void**)&h_blk_cnt, sizeof(unsigned long long) * 5 * 4096, 0));
+    return MESSI_OK;
+}
+
+Workspace::~Workspace() {
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    for (void* p : {(void*)h_counters, (void*)h_prof, (void*)h_blk_cnt})
+        if (p) (void)hipHostFree(p);
+}
+
+namespace {
+
+uint32_t max_chunks_of(const Index* ix) { return (uint32_t)((ix->n + kChunk - 1) / kChunk + 1); }
+
 int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Workspace** out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace*& ws = g_ws[{ix, s}];
     if (!ws) ws = new Workspace();
-    if (ws->nq < nq || ws->cap < cap || ws->nL != ix->n_leaves) {
+    const size_t slots = (size_t)cap * (size_t)nq;
+    if (ws->nq < nq || ws->nL != ix->n_leaves) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         const int32_t nqa = std::max(nq, ws->nq);
-        const uint32_t capa = std::max(cap, ws->cap);
         const size_t nL = (size_t)ix->n_leaves;
+        const uint32_t mc = max_chunks_of(ix);
         MESSI_TRY(ws->qs.alloc(sizeof(QState) * nqa));
         MESSI_TRY(ws->lb.alloc(sizeof(float) * nL * nqa));
         MESSI_TRY(ws->order.alloc(sizeof(uint32_t) * nL * nqa));
+        MESSI_TRY(ws->rec.alloc(sizeof(OrdRec) * nL * nqa));
+        MESSI_TRY(ws->chunk_first.alloc(sizeof(uint32_t) * (size_t)mc * nqa));
         MESSI_TRY(ws->bins.alloc(sizeof(uint32_t) * kNB * nqa));
-        MESSI_TRY(ws->cursor.alloc(sizeof(uint32_t) * kNB * nqa));
+        MESSI_TRY(ws->mbins.alloc(sizeof(uint32_t) * kNB * nqa));
+        MESSI_TRY(ws->cursor.alloc(sizeof(unsigned long long) * kNB * nqa));
+        MESSI_TRY(ws->hist.alloc(sizeof(uint32_t) * kHistBins * nqa));
         MESSI_TRY(ws->approx_d.alloc(sizeof(float) * kApproxMax * nqa));
-        MESSI_TRY(ws->cand.alloc(sizeof(Cand) * (size_t)capa * nqa));
+        MESSI_TRY(ws->status.alloc(sizeof(uint32_t) * nqa));
         MESSI_TRY(ws->counters.alloc(sizeof(QCounters)));
         MESSI_TRY(ws->err.alloc(sizeof(uint32_t) * 4));
         MESSI_TRY(ws->prof.alloc(sizeof(unsigned long long) * 4 * 4096));
+        MESSI_TRY(ws->blk_cnt.alloc(sizeof(unsigned long long) * 5 * 4096));
         ws->nq = nqa;
-        ws->cap = capa;
         ws->nL = (int32_t)nL;
+        ws->max_chunks = mc;
+    }
+    if (ws->cand_slots < slots) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(ws->cand.alloc(sizeof(Cand) * slots));
+        ws->cand_slots = slots;
     }
     *out = ws;
     return MESSI_OK;
@@ -889,10 +1075,10 @@ struct CallArgs {
     float* out_dist;
 };
 
-int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap) {
+int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap, uint32_t cap_min = 0) {
     const Index* ix = c.ix;
     const int32_t nq = c.nq;
-    cap = nq == 1 ? (1u << 20) : std::max<uint32_t>(1u << 14, 64u * (uint32_t)c.kmax);
+    cap = std::max(default_cap(nq, c.kmax), cap_min);
     Workspace* ws = nullptr;
     MESSI_TRY(get_workspace(ix, c.s, nq, cap, &ws));
     *wsp = ws;
@@ -913,8 +1099,13 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.qs = ws->qs.as<QState>();
     a.lb = ws->lb.as<float>();
     a.order = ws->order.as<uint32_t>();
+    a.rec = ws->rec.as<OrdRec>();
+    a.chunk_first = ws->chunk_first.as<uint32_t>();
+    a.max_chunks = ws->max_chunks;
     a.bins = ws->bins.as<uint32_t>();
-    a.cursor = ws->cursor.as<uint32_t>();
+    a.mbins = ws->mbins.as<uint32_t>();
+    a.cursor = ws->cursor.as<unsigned long long>();
+    a.hist = ws->hist.as<uint32_t>();
     a.approx_d = ws->approx_d.as<float>();
     a.cand = ws->cand.as<Cand>();
     a.cap = cap;
@@ -925,6 +1116,7 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.counters = counting ? ws->counters.as<QCounters>() : nullptr;
     a.prof = counting ? ws->prof.as<unsigned long long>() : nullptr;
     a.err_any = ws->err.as<uint32_t>();
+    a.blk_cnt = counting ? ws->blk_cnt.as<unsigned long long>() : nullptr;
     a.out_idx = c.out_idx;
     a.out_dist = c.out_dist;
     return MESSI_OK;
@@ -939,8 +1131,6 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     const Index* ix = c.ix;
     MESSI_HIP_TRY(hipMemsetAsync(a.err_any, 0, sizeof(uint32_t) * 4, s));
     if (a.counters) MESSI_HIP_TRY(hipMemsetAsync(a.counters, 0, sizeof(QCounters), s));
-    MESSI_HIP_TRY(hipMemsetAsync(a.bins, 0, sizeof(uint32_t) * kNB * (size_t)nq, s));
-    MESSI_HIP_TRY(hipMemsetAsync(a.cand, 0xFF, sizeof(Cand) * (size_t)cap * nq, s));
     const int32_t mode = c.mode;
     MESSI_TRY(mark(0));
     hipLaunchKernelGGL(prep_kernel, dim3(nq), dim3(256), 0, s, a, c.kmax, c.kq, (uint32_t)c.kmax);
@@ -966,11 +1156,15 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
         MESSI_TRY(bf16_scan(ix, a, ws, s, timing));
     } else {
         const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
-        if (vec)
-            hipLaunchKernelGGL(scan_kernel<true>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
-        else
-            hipLaunchKernelGGL(scan_kernel<false>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a);
-        MESSI_LAUNCH_CHECK("scan");
+        for (int pass = 0; pass < 2; ++pass) {
+            if (vec)
+                hipLaunchKernelGGL(scan_kernel<true>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a, pass);
+            else
+                hipLaunchKernelGGL(scan_kernel<false>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a, pass);
+            MESSI_LAUNCH_CHECK("scan");
+            hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, pass);
+            MESSI_LAUNCH_CHECK("fixup");
+        }
     }
     MESSI_TRY(mark(5));
     hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
@@ -1003,18 +1197,44 @@ int decode_error(uint32_t err) {
 }  // namespace
 
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
-                hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err) {
+                hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
+                uint32_t cap_min) {
     CallArgs c{ix, queries, nq, kmax, kq, mode, s, out_idx, out_dist};
     Workspace* ws = nullptr;
     QArgs a;
     uint32_t cap = 0;
-    MESSI_TRY(setup_call(c, false, &ws, a, cap));
+    MESSI_TRY(setup_call(c, false, &ws, a, cap, cap_min));
     MESSI_TRY(launch_search(c, a, ws, cap, false, [](int) { return MESSI_OK; }));
     MESSI_HIP_TRY(hipMemcpyAsync(host_err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (host_status) {
+        hipLaunchKernelGGL(status_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, a, ws->status.as<uint32_t>());
+        MESSI_LAUNCH_CHECK("status");
+        MESSI_HIP_TRY(hipMemcpyAsync(host_status, ws->status.p, sizeof(uint32_t) * nq, hipMemcpyDeviceToHost, s));
+    }
     return MESSI_OK;
 }
 
+int query_error_code(uint32_t st) {
+    switch (st) {
+        case 0: return MESSI_OK;
+        case 1: return MESSI_EINVAL;
+        case 2:
+        case 3:
+        case 5: return MESSI_EOVERFLOW;
+        default: return MESSI_EDEVICE;
+    }
+}
+
 int knn_error_code(uint32_t err) { return decode_error(err); }
+
+size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap) {
+    const size_t nL = (size_t)ix->n_leaves;
+    size_t b = sizeof(QState) + nL * (sizeof(float) + sizeof(uint32_t) + sizeof(OrdRec)) +
+               sizeof(uint32_t) * (size_t)max_chunks_of(ix) + kNB * (2 * sizeof(uint32_t) + sizeof(unsigned long long)) +
+               sizeof(uint32_t) * kHistBins + sizeof(float) * kApproxMax + sizeof(Cand) * (size_t)cap;
+    if (mode == MESSI_MODE_BF16) b += nL * 4 + 16384 * 8 + (size_t)((ix->len + 31) / 32 * 32) * 2 + 8;
+    return b;
+}
 
 int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
                int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
@@ -1023,32 +1243,78 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     QArgs a;
     uint32_t cap = 0;
     MESSI_TRY(setup_call(c, stats != nullptr, &ws, a, cap));
-    hipEvent_t ev[8];
     const bool timing = stats != nullptr;
-    if (timing)
-        for (auto& e : ev) MESSI_HIP_TRY(hipEventCreate(&e));
+    if (timing) MESSI_TRY(ws->ensure_stats());
+    hipEvent_t* ev = ws->ev;
     auto mark = [&](int i) -> int {
         if (timing) MESSI_HIP_TRY(hipEventRecord(ev[i], s));
         return MESSI_OK;
     };
-    MESSI_TRY(launch_search(c, a, ws, cap, timing, mark));
     uint32_t err = 0;
-    MESSI_HIP_TRY(hipMemcpyAsync(&err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QCounters hc{};
-    if (a.counters) MESSI_HIP_TRY(hipMemcpyAsync(&hc, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
-    std::vector<unsigned long long> hprof;
     const int sg = scan_grid();
-    if (a.prof) {
-        hprof.resize((size_t)4 * sg);
-        MESSI_HIP_TRY(hipMemcpyAsync(hprof.data(), a.prof, sizeof(unsigned long long) * 4 * sg, hipMemcpyDeviceToHost, s));
+    const bool fp32 = mode == MESSI_MODE_FP32;
+    const unsigned long long* hprof = nullptr;
+    const unsigned long long* hcnt = nullptr;
+    int32_t retries = 0;
+    for (;;) {
+        MESSI_TRY(launch_search(c, a, ws, cap, timing, mark));
+        MESSI_HIP_TRY(hipMemcpyAsync(&err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (a.counters)
+            MESSI_HIP_TRY(hipMemcpyAsync(ws->h_counters, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
+        if (a.prof && fp32) {
+            MESSI_HIP_TRY(hipMemcpyAsync(ws->h_prof, a.prof, sizeof(unsigned long long) * 4 * sg,
+                                         hipMemcpyDeviceToHost, s));
+            MESSI_HIP_TRY(hipMemcpyAsync(ws->h_blk_cnt, a.blk_cnt, sizeof(unsigned long long) * 5 * sg,
+                                         hipMemcpyDeviceToHost, s));
+            hprof = ws->h_prof;
+            hcnt = ws->h_blk_cnt;
+        }
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        if (a.counters) hc = *ws->h_counters;
+        // The FP32 scan's own second pass was not enough (more than cap
+        // candidates below the k-th buffered distance): search again with a
+        // 16 times larger candidate buffer.
+        if (fp32 && (err & 2u) && !(err & 1u) && retries < 2 && cap <= (1u << 26)) {
+            ++retries;
+            MESSI_TRY(setup_call(c, stats != nullptr, &ws, a, cap, cap * 16));
+            continue;
+        }
+        break;
     }
-    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    for (int bb = 0; hcnt && bb < sg; ++bb) {
+        hc.scanned += hcnt[(size_t)bb * 5 + 0];
+        hc.bounded += hcnt[(size_t)bb * 5 + 1];
+        hc.distance += hcnt[(size_t)bb * 5 + 2];
+        hc.abandoned += hcnt[(size_t)bb * 5 + 3];
+        hc.bytes += hcnt[(size_t)bb * 5 + 4];
+    }
+    // BF16 mode: a query whose candidates or filter pairs overflowed their
+    // buffers is answered again, alone, by the FP32 path (which reruns and
+    // grows its own buffer as needed).
+    int32_t fallbacks = 0;
+    if (!fp32 && (err & (2u | 4u | 16u)) && !(err & 1u)) {
+        std::vector<uint32_t> st(nq);
+        hipLaunchKernelGGL(status_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, a, ws->status.as<uint32_t>());
+        MESSI_LAUNCH_CHECK("status");
+        MESSI_HIP_TRY(hipMemcpyAsync(st.data(), ws->status.p, sizeof(uint32_t) * nq, hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        uint32_t rest = err & ~(2u | 4u | 16u);
+        for (int32_t q = 0; q < nq; ++q) {
+            if (query_error_code(st[q]) != MESSI_EOVERFLOW) continue;
+            ++fallbacks;
+            const int rc = knn_device(ix, queries + (size_t)q * ix->len, 1, k, MESSI_MODE_FP32, s,
+                                      out_idx + (size_t)q * k, out_dist + (size_t)q * k, nullptr);
+            if (rc == MESSI_EOVERFLOW) rest |= 2u;
+            else if (rc != MESSI_OK) return rc;
+        }
+        err = rest;
+    }
     if (timing) {
         float ms[6];
         for (int i = 0; i < 6; ++i) MESSI_HIP_TRY(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
         float tot = 0.f;
         MESSI_HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev[6]));
-        for (auto& e : ev) (void)hipEventDestroy(e);
         stats->ms_prep = ms[0];
         stats->ms_leaf_lb = ms[1];
         stats->ms_approx = ms[2];
@@ -1065,7 +1331,9 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         stats->series_recheck = (int64_t)hc.recheck;
         stats->candidates = (int64_t)hc.final_cands;
         stats->bytes_scan = (int64_t)hc.bytes;
-        stats->scan_launches = 1;
+        stats->scan_launches = (hc.reruns ? 2 : 1) + 2 * retries;
+        stats->reruns = (int32_t)hc.reruns + retries;
+        stats->fallbacks = fallbacks;
         if (mode == MESSI_MODE_BF16) {
             const int Lp = (ix->len + 31) / 32 * 32;
             stats->ms_bf16_filter = ws->bf_ms_filter;
@@ -1074,7 +1342,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
             stats->bf16_flops = (int64_t)hc.distance * 2 * Lp;
             stats->scan_launches = ws->bf_rounds;
         }
-        if (!hprof.empty()) {
+        if (hprof) {
             int rate_khz = 100000;
             (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ix->device);
             const double to_ms = 1.0 / (double)rate_khz;

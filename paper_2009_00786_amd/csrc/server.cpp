@@ -32,6 +32,8 @@ struct Pending {
     int32_t k;
     uint64_t tag;
     double t_submit;
+    bool fp32 = false;  // answered alone in FP32 mode (after a buffer overflow)
+    int grow = 0;       // its candidate buffer is 16^grow times the default
 };
 
 struct Lane {
@@ -39,12 +41,14 @@ struct Lane {
     hipEvent_t done = nullptr;
     bool busy = false;
     int32_t kmax = 0;
+    int32_t mode = MESSI_MODE_BF16;  // of the batch in flight
     DevBuf d_q, d_k, d_idx, d_dist;
     float* h_q = nullptr;
     int32_t* h_k = nullptr;
     int64_t* h_idx = nullptr;
     float* h_dist = nullptr;
     uint32_t* h_err = nullptr;
+    uint32_t* h_status = nullptr;  // per query of the batch in flight
     std::vector<Pending> batch;
 };
 
@@ -80,11 +84,15 @@ struct Server {
             kmax = std::max(kmax, ln.batch[i].k);
         }
         ln.kmax = kmax;
+        ln.mode = ln.batch[0].fp32 ? MESSI_MODE_FP32 : mode;
         MESSI_HIP_TRY(hipMemcpyAsync(ln.d_q.p, ln.h_q, sizeof(float) * (size_t)nq * L, hipMemcpyHostToDevice, ln.s));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.d_k.p, ln.h_k, sizeof(int32_t) * (size_t)nq, hipMemcpyHostToDevice, ln.s));
         *ln.h_err = 0;
-        MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, kmax, ln.d_k.as<int32_t>(), mode, ln.s, ln.d_idx.as<int64_t>(),
-                              ln.d_dist.as<float>(), ln.h_err));
+        uint32_t cap_min = 0;
+        if (ln.batch[0].fp32)
+            cap_min = default_cap(1, kmax) << (4 * ln.batch[0].grow);
+        MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, kmax, ln.d_k.as<int32_t>(), ln.mode, ln.s,
+                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, cap_min));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.h_idx, ln.d_idx.p, sizeof(int64_t) * (size_t)nq * kmax, hipMemcpyDeviceToHost,
                                      ln.s));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.h_dist, ln.d_dist.p, sizeof(float) * (size_t)nq * kmax, hipMemcpyDeviceToHost,
@@ -94,11 +102,29 @@ struct Server {
         return MESSI_OK;
     }
 
-    void complete(Lane& ln, int status) {
+    // A finished batch: per query, its own status decides.  A query whose
+    // buffers overflowed goes back to the head of the queue to be answered
+    // alone in FP32 mode (from a BF16 batch), or alone with a 16 times larger
+    // candidate buffer (twice at most); every other query gets its result.
+    // launch_status != MESSI_OK (the launch or the stream failed) applies to all.
+    void complete(Lane& ln, int launch_status) {
         const double t = now_ms();
         std::vector<messi_result*> out;
+        std::vector<Pending> redo;
         out.reserve(ln.batch.size());
         for (size_t i = 0; i < ln.batch.size(); ++i) {
+            const int status = launch_status != MESSI_OK ? launch_status : query_error_code(ln.h_status[i]);
+            if (status == MESSI_EOVERFLOW && (!ln.batch[i].fp32 || ln.batch[i].grow < 2)) {
+                Pending p = std::move(ln.batch[i]);
+                if (!p.fp32) {
+                    p.fp32 = true;
+                    p.grow = ln.mode == MESSI_MODE_FP32 ? 1 : 0;
+                } else {
+                    ++p.grow;
+                }
+                redo.push_back(std::move(p));
+                continue;
+            }
             messi_result* r = new messi_result();
             std::memset(r, 0, sizeof(*r));
             r->tag = ln.batch[i].tag;
@@ -118,6 +144,7 @@ struct Server {
         ln.busy = false;
         std::lock_guard<std::mutex> lk(mu);
         for (auto* r : out) ready.push_back(r);
+        for (auto it = redo.rbegin(); it != redo.rend(); ++it) pending.push_front(std::move(*it));
     }
 
     void run() {
@@ -128,19 +155,22 @@ struct Server {
                 if (!ln.busy) continue;
                 const hipError_t q = hipEventQuery(ln.done);
                 if (q == hipErrorNotReady) continue;
-                int status = (q == hipSuccess) ? knn_error_code(*ln.h_err) : MESSI_EDEVICE;
                 if (q != hipSuccess) (void)hipGetLastError();
-                complete(ln, status);
+                complete(ln, q == hipSuccess ? MESSI_OK : MESSI_EDEVICE);
                 progressed = true;
             }
             bool idle_lanes = false;
             for (auto& ln : lanes) {
                 if (ln.busy) continue;
                 {
+                    // a batch of BF16 queries, or one FP32 query on its own
                     std::lock_guard<std::mutex> lk(mu);
                     while (!pending.empty() && (int32_t)ln.batch.size() < batch) {
+                        const bool alone = pending.front().fp32;
+                        if (alone && !ln.batch.empty()) break;
                         ln.batch.push_back(std::move(pending.front()));
                         pending.pop_front();
+                        if (alone) break;
                     }
                 }
                 if (ln.batch.empty()) {
@@ -173,7 +203,8 @@ struct Server {
                 (void)hipStreamDestroy(ln.s);
             }
             if (ln.done) (void)hipEventDestroy(ln.done);
-            for (void* p : {(void*)ln.h_q, (void*)ln.h_k, (void*)ln.h_idx, (void*)ln.h_dist, (void*)ln.h_err})
+            for (void* p : {(void*)ln.h_q, (void*)ln.h_k, (void*)ln.h_idx, (void*)ln.h_dist, (void*)ln.h_err,
+                            (void*)ln.h_status})
                 if (p) (void)hipHostFree(p);
         }
         for (auto* r : ready) delete r;
@@ -183,12 +214,9 @@ struct Server {
 // Device bytes one admitted query holds (workspace share + staging), for kmax
 // results; used to turn the memory budget into slots.
 static size_t bytes_per_query(const Index* ix, int32_t mode) {
-    const size_t nL = (size_t)ix->n_leaves;
-    const size_t cap = std::max<size_t>(1u << 14, 64u * MESSI_MAX_K);
-    size_t b = nL * 4 * 2 + 2 * 1024 * 4 + 4096 * 4 + cap * 8 + sizeof(float) * ix->len +
-               (sizeof(int64_t) + sizeof(float)) * MESSI_MAX_K + 256;
-    if (mode == MESSI_MODE_BF16) b += nL * 4 + 16384 * 8 + (size_t)((ix->len + 31) / 32 * 32) * 2 + 8;
-    return b;
+    const uint32_t cap = std::max<uint32_t>(1u << 14, 64u * MESSI_MAX_K);
+    return workspace_bytes_per_query(ix, mode, cap) + sizeof(float) * ix->len +
+           (sizeof(int64_t) + sizeof(float)) * MESSI_MAX_K + 256;
 }
 
 }  // namespace messi
@@ -240,7 +268,8 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
             hipHostMalloc((void**)&ln.h_k, sizeof(int32_t) * B, 0) != hipSuccess ||
             hipHostMalloc((void**)&ln.h_idx, sizeof(int64_t) * B * MESSI_MAX_K, 0) != hipSuccess ||
             hipHostMalloc((void**)&ln.h_dist, sizeof(float) * B * MESSI_MAX_K, 0) != hipSuccess ||
-            hipHostMalloc((void**)&ln.h_err, sizeof(uint32_t), 0) != hipSuccess) {
+            hipHostMalloc((void**)&ln.h_err, sizeof(uint32_t), 0) != hipSuccess ||
+            hipHostMalloc((void**)&ln.h_status, sizeof(uint32_t) * B, 0) != hipSuccess) {
             (void)hipGetLastError();
             set_error(MESSI_ENOMEM, "server: stream or pinned buffer allocation failed");
             rc = MESSI_ENOMEM;
@@ -269,7 +298,7 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
         }
         *ln.h_err = 0;
         if ((rc = knn_enqueue(ix, ln.d_q.as<float>(), (int32_t)B, kw, ln.d_k.as<int32_t>(), mode, ln.s,
-                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err)) != MESSI_OK)
+                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status)) != MESSI_OK)
             break;
         if (hipStreamSynchronize(ln.s) != hipSuccess) {
             rc = MESSI_EDEVICE;
@@ -341,6 +370,10 @@ double messi_server_clock_ms(const messi_server* server) {
 void messi_server_destroy(messi_server* server) {
     if (!server) return;
     Server* sv = reinterpret_cast<Server*>(server);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->pending.clear();
+    }
     sv->stop.store(true);
     sv->cv.notify_all();
     if (sv->worker.joinable()) sv->worker.join();

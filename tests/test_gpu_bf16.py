@@ -63,6 +63,20 @@ def test_bf16_batched_matches_oracle(tiny_bf16, oracle_mod, torch_cuda, messi, k
     assert st["series_recheck"] < st["series_distance"]
 
 
+def test_bf16_overflow_falls_back_to_fp32(tiny_bf16, oracle_mod, torch_cuda, messi, monkeypatch):
+    """Candidate buffers far too small for the BF16 rounds: the queries that
+    overflow are answered again by the FP32 path, and every answer is exact."""
+    w = tiny_bf16
+    monkeypatch.setenv("MESSI_CANDIDATE_CAP", "16")
+    k = 30
+    _say("bf16 overflow fallback k=%d" % k)
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"], k, nthreads=8)
+    gi, gd, st = w["ix"].knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=messi.MODE_BF16, stats=True)
+    _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    _say("  fallbacks", st["fallbacks"])
+    assert st["fallbacks"] > 0
+
+
 def test_bf16_equals_fp32_mode(tiny_bf16, torch_cuda, messi):
     w = tiny_bf16
     q = torch_cuda.from_numpy(w["q"]).cuda()

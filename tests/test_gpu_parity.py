@@ -246,6 +246,29 @@ def test_knn_ties_and_degenerate(torch_cuda, messi, oracle_mod):
     assert list(gi.cpu().numpy()[0]) == [7, 100, 101]
 
 
+def test_knn_candidate_overflow_recovers(torch_cuda, messi, datagen_mod, oracle_mod, monkeypatch):
+    """A candidate buffer far smaller than what a loose first bound lets
+    through: the scan reruns from the k-th buffered distance (and the call
+    retries with a larger buffer if even that overflows); answers stay exact."""
+    torch = torch_cuda
+    z = oracle_mod.znorm(datagen_mod.random_walks(30_000, 64, seed=77, stream=0))
+    q = datagen_mod.add_noise(z[[5, 17_000, 29_999]], [1.0, 1.0, 0.5])
+    ix = messi.Index(torch.from_numpy(z).cuda(), 16, 8, 200)
+    monkeypatch.setenv("MESSI_CANDIDATE_CAP", "64")
+    reruns = 0
+    for k in (1, 8, 30):
+        _say("overflow recovery k=%d" % k)
+        oidx, od, _ = oracle_mod.knn_brute(z, q, k, nthreads=8)
+        gi, gd, st = ix.knn(torch.from_numpy(q).cuda(), k, stats=True)
+        _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+        reruns += st["reruns"]
+        gi, gd, st = ix.knn(torch.from_numpy(q[:1].copy()).cuda(), k, stats=True)
+        _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx[:1], od[:1])
+        reruns += st["reruns"]
+    assert reruns > 0
+    ix.close()
+
+
 def test_knn_nq_zero_and_errors(torch_cuda, messi):
     torch = torch_cuda
     z = torch.randn((100, 32), device="cuda")

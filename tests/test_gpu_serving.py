@@ -68,11 +68,16 @@ def _serve(messi, ix, q, ks, mode, budget, slots, pause):
     return got
 
 
-@pytest.mark.parametrize("mode_name,slots", [("BF16", 48), ("FP32", 1)])
-def test_results_alone_and_in_the_mix(served, messi, torch_cuda, oracle_mod, mode_name, slots):
+@pytest.mark.parametrize("mode_name,slots,small_cap", [("BF16", 48, False), ("FP32", 1, False), ("BF16", 48, True)])
+def test_results_alone_and_in_the_mix(served, messi, torch_cuda, oracle_mod, monkeypatch, mode_name, slots,
+                                      small_cap):
+    """small_cap: candidate buffers so small that BF16 batches overflow; those
+    queries must come back exact through the FP32 fallback."""
     w = served
     mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
-    _say("serving %s, %d slots, %d queries" % (mode_name, slots, len(w["q"])))
+    if small_cap:
+        monkeypatch.setenv("MESSI_CANDIDATE_CAP", "16")
+    _say("serving %s, %d slots, %d queries, small buffers %s" % (mode_name, slots, len(w["q"]), small_cap))
     got = _serve(messi, w["ix"], w["q"], w["ks"], mode, 4 << 30, slots, 0.002)
     assert len(got) == len(w["q"])
     for i in range(len(w["q"])):
