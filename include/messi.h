@@ -108,6 +108,9 @@ typedef struct {
     /* BF16 mode: queries answered again by the FP32 path because their
        candidate or filter-pair buffer overflowed */
     int32_t fallbacks;
+    /* FP32 mode: device time after the first scan pass (candidate fix-up,
+       the second pass when needed); ms_scan is then the first pass alone */
+    double ms_fixup;
 } messi_knn_stats;
 
 /* ---- index ------------------------------------------------------------- */

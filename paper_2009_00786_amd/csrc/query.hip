@@ -558,8 +558,8 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
 //             a row once half of it already exceeds U
 //   bound     k = 1: atomicMin of U; k > 1: histogram, then U from it
 // Pass 1 runs only for queries whose candidate buffer overflowed in pass 0.
-template <bool VEC>
-__global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a, int pass) {
+template <bool VEC, int pass>
+__global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
     __shared__ float s_D[16 * 256];
     __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ uint32_t s_surv[kChunk];
@@ -1123,7 +1123,8 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
 }
 
 // Enqueue the whole search on c.s; `mark(i)` is called at the phase boundaries
-// 0..6 (prep, leaf bounds, first bound, order, scan, final, end).
+// 0..6 (prep, leaf bounds, first bound, order, scan, final, end) and 7 (after the
+// first FP32 scan pass).
 template <class Mark>
 int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool timing, Mark mark) {
     const hipStream_t s = c.s;
@@ -1156,15 +1157,19 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
         MESSI_TRY(bf16_scan(ix, a, ws, s, timing));
     } else {
         const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
-        for (int pass = 0; pass < 2; ++pass) {
-            if (vec)
-                hipLaunchKernelGGL(scan_kernel<true>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a, pass);
-            else
-                hipLaunchKernelGGL(scan_kernel<false>, dim3(scan_grid()), dim3(kScanThreads), 0, s, a, pass);
-            MESSI_LAUNCH_CHECK("scan");
-            hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, pass);
-            MESSI_LAUNCH_CHECK("fixup");
-        }
+        const dim3 g(scan_grid()), b(kScanThreads);
+        if (vec) hipLaunchKernelGGL((scan_kernel<true, 0>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((scan_kernel<false, 0>), g, b, 0, s, a);
+        MESSI_LAUNCH_CHECK("scan");
+        MESSI_TRY(mark(7));
+        hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 0);
+        MESSI_LAUNCH_CHECK("fixup");
+        // the second pass exits at once unless a query's buffer overflowed
+        if (vec) hipLaunchKernelGGL((scan_kernel<true, 1>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((scan_kernel<false, 1>), g, b, 0, s, a);
+        MESSI_LAUNCH_CHECK("rescan");
+        hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 1);
+        MESSI_LAUNCH_CHECK("fixup");
     }
     MESSI_TRY(mark(5));
     hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
@@ -1319,7 +1324,14 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         stats->ms_leaf_lb = ms[1];
         stats->ms_approx = ms[2];
         stats->ms_order = ms[3];
-        stats->ms_scan = ms[4];
+        if (fp32) {
+            float scan_only = 0.f;
+            MESSI_HIP_TRY(hipEventElapsedTime(&scan_only, ev[4], ev[7]));
+            stats->ms_scan = scan_only;
+            stats->ms_fixup = ms[4] - scan_only;
+        } else {
+            stats->ms_scan = ms[4];
+        }
         stats->ms_final = ms[5];
         stats->ms_total = tot;
         stats->leaves_total = (int64_t)ix->n_leaves * nq;
