@@ -51,6 +51,7 @@ namespace messi {
 namespace {
 
 constexpr int kScanThreads = 256;
+constexpr int kEdBatch = 32;  // survivors gathered before a round of distances
 
 __device__ __forceinline__ uint32_t vload(const uint32_t* p) {
     return __atomic_load_n(p, __ATOMIC_RELAXED);
@@ -550,22 +551,29 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
 // take chunks j, j + G, j + 2G, ...  Every block does the same amount of
 // member work, and the grid still advances through the order together, so
 // the best leaves are scanned first and U tightens early.  Per chunk:
-//   control   the chunk's leaves (start, bound, member offset) into LDS; stop
-//             once the chunk's first leaf lies in a bin wholly above U
-//   filter    per member: leaf bound, then the member's own word bound from
-//             the LDS table; survivors compacted into LDS
-//   distance  16 lanes per row, two rows per 16 lanes in flight, abandoning
-//             a row once half of it already exceeds U
-//   bound     k = 1: atomicMin of U; k > 1: histogram, then U from it
+//   positions  the chunk's leaves (start, bound, member offset) into LDS
+//   words      per member: leaf bound against U, then its 16-byte word
+//   filter     the member's own word bound from the LDS table; survivors
+//              compacted into LDS
+//   distances  16 lanes per row, each row read whole (1 KB per pass)
+//   bound      k = 1: atomicMin of U; k > 1: histogram, then U from it
+// The steps are software-pipelined one chunk deep: the next chunk's leaf
+// records load while this chunk's words are filtered, and its words load
+// while this chunk's distances are computed, so a chunk costs about two
+// dependent memory round trips (row index, row) instead of six.  The stop
+// test (the chunk's first leaf lies in a bin wholly above U) is taken when
+// a chunk is prefetched.
 // Pass 1 runs only for queries whose candidate buffer overflowed in pass 0.
 template <bool VEC, int pass>
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
+    constexpr int kPer = kChunk / kScanThreads;
     __shared__ float s_D[16 * 256];
     __shared__ float s_q[MESSI_MAX_LEN];
-    __shared__ uint32_t s_surv[kChunk];
+    __shared__ uint32_t s_surv[kChunk + kEdBatch];  // series indices waiting for their distance
     __shared__ uint32_t s_pbase[kChunk];  // word index of the chunk's member 0 if it were in this leaf
     __shared__ float s_plb[kChunk];
     __shared__ uint16_t s_pm[kChunk];     // first chunk-relative member of each leaf (0 for the first)
+    __shared__ uint32_t s_cf[64];         // first order position of this block's next 64 chunks
     __shared__ uint32_t s_tmp[4];
     __shared__ uint32_t s_flag, s_app, s_stop;
     __shared__ float s_Ublk;  // block's view of U: refreshed each chunk, lowered by its own finds
@@ -587,10 +595,22 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
         j = 0;
         G = 1;
     }
-    unsigned long long c_scanned = 0, c_bounded = 0, c_dist = 0, c_abandon = 0, c_bytes = 0;
-    // optional per-block phase timing (thread 0): control, member filter, distances, total
-    unsigned long long t_ctl = 0, t_lb = 0, t_ed = 0, t_mark = 0;
-    const unsigned long long t_begin = (a.prof && tid == 0) ? wall_clock64() : 0ull;
+    uint32_t c_scanned = 0, c_bounded = 0, c_dist = 0, c_abandon = 0, c_bytes = 0;  // this thread's share
+    // optional per-block phase timing, kept by thread 0 in LDS: control,
+    // member filter, distances, last mark, start
+    __shared__ unsigned long long s_t[5];
+    const bool timing = a.prof != nullptr;
+    if (timing && tid == 0) {
+        s_t[0] = s_t[1] = s_t[2] = 0;
+        s_t[4] = s_t[3] = wall_clock64();
+    }
+    auto tick = [&](int slot) {
+        if (timing && tid == 0) {
+            const unsigned long long now = wall_clock64();
+            s_t[slot] += now - s_t[3];
+            s_t[3] = now;
+        }
+    };
     bool worked = false;
     for (int q = q0; q < nq; q += qstep) {
         QState& st = a.qs[q];
@@ -603,6 +623,14 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
         __syncthreads();
         if (skip) continue;
         worked = true;
+        const uint32_t nsurv = st.nsurv;
+        const uint64_t nmemb = st.nmemb;
+        const int k = st.k;
+        const float range = st.range;
+        const uint64_t nch = (nmemb + kChunk - 1) / kChunk;
+        const uint32_t ncb = nch > (uint64_t)j ? (uint32_t)((nch - (uint64_t)j + G - 1) / G) : 0u;
+        if (ncb == 0) continue;
+        if (timing && tid == 0) s_t[3] = wall_clock64();
         {
             const int A = 1 << a.b;
             const float delta = st.delta;
@@ -623,81 +651,112 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
             }
             for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
         }
-        const uint32_t nsurv = st.nsurv;
-        const uint64_t nmemb = st.nmemb;
-        const int k = st.k;
-        const float range = st.range;
-        const uint64_t nch = (nmemb + kChunk - 1) / kChunk;
-        for (uint64_t c = j; c < nch; c += G) {
-            if (a.prof && tid == 0) t_mark = wall_clock64();
-            // ---- control
-            if (tid == 0) {
-                s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
-                s_stop = vload(&st.ovf);
-                s_app = 0;
-            }
-            const uint64_t cbeg = c * kChunk;
-            const uint32_t clen = (uint32_t)min((uint64_t)kChunk, nmemb - cbeg);
-            const uint32_t t0 = a.chunk_first[(size_t)q * a.max_chunks + c];
+        const uint32_t* cfq = a.chunk_first + (size_t)q * a.max_chunks;
+        const OrdRec* recq = a.rec + (size_t)q * a.nL;
+        // chunk starts of chunks i0 .. i0 + 63 of this block (call from every thread)
+        auto load_cf = [&](uint32_t i0) {
+            if (tid < 64 && i0 + tid < ncb) s_cf[tid] = cfq[(uint64_t)j + (uint64_t)(i0 + tid) * G];
             __syncthreads();
-            if (s_stop) break;  // this pass overflowed; it is redone from a tighter bound
-            const float Uc = s_Ublk;
-            uint32_t np = 0;
-            for (uint32_t b0 = 0; b0 < (uint32_t)kChunk; b0 += kScanThreads) {
+        };
+        // The leaves of chunk c, from the order record `r` this thread loaded
+        // (position t0 + tid, valid if r_ok), into the LDS position arrays;
+        // returns how many leaves the chunk spans.  Call from every thread.
+        auto commit_positions = [&](uint64_t c, uint32_t t0, const OrdRec& r, bool r_ok, float Uc) -> uint32_t {
+            const uint64_t cbeg = c * kChunk;
+            auto put = [&](uint32_t p, const OrdRec& rr) {
+                s_pbase[p] = rr.start + (uint32_t)cbeg - rr.moff;  // modulo 2^32
+                s_pm[p] = (uint64_t)rr.moff > cbeg ? (uint16_t)(rr.moff - (uint32_t)cbeg) : (uint16_t)0;
+                s_plb[p] = rr.lb;
+                if ((uint64_t)rr.moff >= cbeg && !(rr.lb * (1.0f - kRhoLb) > Uc)) ++c_scanned;
+            };
+            bool inc = r_ok && (uint64_t)r.moff < cbeg + kChunk;
+            if (inc) put(tid, r);
+            int cnt = __syncthreads_count(inc);
+            uint32_t np = (uint32_t)cnt;
+            // the included leaves are a prefix of the positions from t0; a chunk
+            // of many small leaves needs more than one round of records
+            for (uint32_t b0 = kScanThreads; cnt == kScanThreads && b0 < (uint32_t)kChunk; b0 += kScanThreads) {
                 const uint32_t t = t0 + b0 + tid;
-                bool inc = false;
+                inc = false;
                 if (t < nsurv) {
-                    const OrdRec r = a.rec[(size_t)q * a.nL + t];
-                    inc = (uint64_t)r.moff < cbeg + kChunk;
-                    if (inc) {
-                        const uint32_t p = b0 + tid;
-                        s_pbase[p] = r.start + (uint32_t)cbeg - r.moff;  // modulo 2^32
-                        s_pm[p] = (uint64_t)r.moff > cbeg ? (uint16_t)(r.moff - (uint32_t)cbeg) : (uint16_t)0;
-                        s_plb[p] = r.lb;
-                        if ((uint64_t)r.moff >= cbeg && !(r.lb * (1.0f - kRhoLb) > Uc)) ++c_scanned;
-                    }
+                    const OrdRec r2 = recq[t];
+                    inc = (uint64_t)r2.moff < cbeg + kChunk;
+                    if (inc) put(b0 + tid, r2);
                 }
-                // the included leaves are a prefix of the positions from t0
-                const int cnt = __syncthreads_count(inc);
+                cnt = __syncthreads_count(inc);
                 np += (uint32_t)cnt;
-                if (cnt < kScanThreads) break;
             }
-            if (np == 0) break;
-            {
-                // bins ascend along the order: once the chunk's first leaf lies
-                // in a bin wholly above U, so does every later chunk
-                const float lb0 = s_plb[0];
-                const float low = (float)bin_of(lb0, range) * (range / (float)kNB);
-                if (lb0 * (1.0f - kRhoLb) > Uc && low * (1.0f - 2.0f * kRhoLb) > Uc) break;
+            return np;
+        };
+        // bins ascend along the order: once a chunk's first leaf lies in a bin
+        // wholly above U, so does every later chunk
+        auto chunk_stops = [&](float Uc) -> bool {
+            const float lb0 = s_plb[0];
+            const float low = (float)bin_of(lb0, range) * (range / (float)kNB);
+            return lb0 * (1.0f - kRhoLb) > Uc && low * (1.0f - 2.0f * kRhoLb) > Uc;
+        };
+        // Member f of the chunk whose leaves are in the LDS position arrays:
+        // its leaf (the last one starting at or before f) and word index.
+        auto member_leaf = [&](uint32_t np, uint32_t f) -> int {
+            int lo = 0, hi = (int)np - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((uint32_t)s_pm[mid] <= f) lo = mid;
+                else hi = mid - 1;
             }
-            if (a.prof && tid == 0) {
-                const unsigned long long now = wall_clock64();
-                t_ctl += now - t_mark;
-                t_mark = now;
-            }
-            // ---- filter: leaf bound, then the member's own word (all loads first)
-            constexpr int kPer = kChunk / kScanThreads;
-            uint4 wd[kPer];
-            uint32_t mpos[kPer];
+            return lo;
+        };
+        // This thread's members of a chunk: leaf bound against U, then the word.
+        auto issue_words = [&](uint32_t np, uint32_t clen, float Uc, uint4* wd) -> uint32_t {
             uint32_t live = 0;
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
                 const uint32_t f = r * kScanThreads + tid;
-                mpos[r] = 0;
+                uint32_t mp = 0;
                 if (f < clen) {
-                    int lo = 0, hi = (int)np - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if ((uint32_t)s_pm[mid] <= f) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    if (!(s_plb[lo] * (1.0f - kRhoLb) > Uc)) {
+                    const int lf = member_leaf(np, f);
+                    if (!(s_plb[lf] * (1.0f - kRhoLb) > Uc)) {
                         live |= 1u << r;
-                        mpos[r] = s_pbase[lo] + f;
+                        mp = s_pbase[lf] + f;
                     }
                 }
-                wd[r] = (live & (1u << r)) ? a.words[mpos[r]] : make_uint4(0, 0, 0, 0);
+                wd[r] = (live & (1u << r)) ? a.words[mp] : make_uint4(0, 0, 0, 0);
             }
+            return live;
+        };
+        auto chunk_len = [&](uint64_t c) -> uint32_t {
+            return (uint32_t)min((uint64_t)kChunk, nmemb - c * kChunk);
+        };
+
+        // ---- prologue: chunk 0 of this block
+        uint32_t nacc = 0;  // survivors gathered in s_surv (the same in every thread)
+        load_cf(0);
+        if (tid == 0) {
+            s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
+            s_stop = vload(&st.ovf);
+        }
+        uint32_t t0n = s_cf[0];
+        OrdRec rn{0u, 0u, 0.f, 0u};
+        bool rn_ok = t0n + tid < nsurv;
+        if (rn_ok) rn = recq[t0n + tid];
+        __syncthreads();
+        float Uc = s_Ublk;
+        uint32_t np = commit_positions((uint64_t)j, t0n, rn, rn_ok, Uc);
+        if (np == 0 || s_stop || chunk_stops(Uc)) continue;
+        uint4 wd[kPer];
+        uint32_t live = issue_words(np, chunk_len((uint64_t)j), Uc, wd);
+        tick(0);
+        for (uint32_t i = 0;; ++i) {
+            const uint64_t c = (uint64_t)j + (uint64_t)i * G;
+            bool more = i + 1 < ncb;
+            // ---- next chunk's leaf records, in flight during this chunk's filter
+            if (more && ((i + 1) & 63u) == 0) load_cf(i + 1);
+            if (more) {
+                t0n = s_cf[(i + 1) & 63u];
+                rn_ok = t0n + tid < nsurv;
+                if (rn_ok) rn = recq[t0n + tid];
+            }
+            // ---- filter this chunk: each member's own word bound
             const float Uf = s_Ublk;
             uint32_t keepmask = 0, nkeep = 0;
 #pragma unroll
@@ -705,8 +764,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
                 if (live & (1u << r)) {
                     float sum = 0.f;
 #pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        if (i < a.w) sum += s_D[i * 256 + word_byte(wd[r], i)];
+                    for (int i2 = 0; i2 < 16; ++i2)
+                        if (i2 < a.w) sum += s_D[i2 * 256 + word_byte(wd[r], i2)];
                     if (!(sum * (1.0f - kRhoLb) > Uf)) {
                         keepmask |= 1u << r;
                         ++nkeep;
@@ -714,94 +773,121 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
                     ++c_bounded;
                 }
             }
+            // series index of every survivor, in flight during the compaction
+            uint32_t gi[kPer];
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                gi[r] = 0;
+                if (keepmask & (1u << r)) {
+                    // the chunk's leaves are still in LDS (the next chunk's are committed below)
+                    const uint32_t f = r * kScanThreads + tid;
+                    gi[r] = a.pos[s_pbase[member_leaf(np, f)] + f];
+                }
+            }
             uint32_t total;
-            uint32_t o = block_exclusive_scan(nkeep, s_tmp, total);
+            uint32_t o = nacc + block_exclusive_scan(nkeep, s_tmp, total);
 #pragma unroll
             for (int r = 0; r < kPer; ++r)
-                if (keepmask & (1u << r)) s_surv[o++] = mpos[r];
+                if (keepmask & (1u << r)) s_surv[o++] = gi[r];
+            nacc += total;
+            tick(1);
+            // every thread has placed its survivors (reading this chunk's
+            // leaves) before the next chunk's leaves overwrite them
             __syncthreads();
-            const uint32_t nsv = total;
-            if (a.prof && tid == 0) {
-                const unsigned long long now = wall_clock64();
-                t_lb += now - t_mark;
-                t_mark = now;
+            // ---- next chunk's positions (the barrier also publishes s_surv)
+            if (tid == 0) {
+                s_Ublk = fminf(s_Ublk, __uint_as_float(vload(&st.U)));
+                s_stop = vload(&st.ovf);
+                s_app = 0;
             }
-            // ---- distances: 16 lanes per row, 8 rows per wave, abandon per 512 B
+            uint32_t npn = 0;
+            if (more) npn = commit_positions(c + G, t0n, rn, rn_ok, s_Ublk);
+            else __syncthreads();
+            Uc = s_Ublk;
+            // this pass overflowed (it is redone from a tighter bound), or the
+            // next chunk lies wholly above U
+            if (s_stop) break;
+            if (more && (npn == 0 || chunk_stops(Uc))) more = false;
+            uint4 wdn[kPer];
+            uint32_t liven = 0;
+            if (more) liven = issue_words(npn, chunk_len(c + G), Uc, wdn);
+            tick(0);
+            // distances wait until a batch of survivors has gathered (or the
+            // block's last chunk), so each round of row loads is well filled
+            const bool run_ed = !more || nacc >= (uint32_t)kEdBatch;
+            if (run_ed) {
+            // ---- distances: 16 lanes per row, the whole row per pass
+            const uint32_t nsv = nacc;
+            nacc = 0;
             uint32_t appended = 0;
-            for (uint32_t base = wave * 8; base < nsv; base += 32) {
-                uint32_t gidx[2];
-                bool act[2], alive[2];
-                float acc[2];
+            for (uint32_t base = wave * 4; base < nsv; base += 16) {
+                const uint32_t si = base + quarter;
+                const bool act = si < nsv;
+                const uint32_t gidx = act ? s_surv[si] : 0u;
+                const float* row = a.series + (size_t)gidx * L;
+                float acc = 0.f;
+                bool alive = act;
+                for (int g = 0; g < nchunk; g += 4) {
+                    if (alive) {
+                        if (VEC) {
+                            float4 x[4];
 #pragma unroll
-                for (int rr = 0; rr < 2; ++rr) {
-                    const uint32_t si = base + rr * 4 + quarter;
-                    act[rr] = si < nsv;
-                    gidx[rr] = act[rr] ? a.pos[s_surv[si]] : 0u;
-                    alive[rr] = act[rr];
-                    acc[rr] = 0.f;
-                }
-                for (int ch = 0; ch < nchunk; ch += 2) {
+                            for (int cc = 0; cc < 4; ++cc) {
+                                const int j0 = (g + cc) * 64 + ql * 4;
+                                x[cc] = (g + cc < nchunk && j0 < L) ? *reinterpret_cast<const float4*>(row + j0)
+                                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+                            }
 #pragma unroll
-                    for (int rr = 0; rr < 2; ++rr) {
-                        if (!alive[rr]) continue;
-                        const float* row = a.series + (size_t)gidx[rr] * L;
+                            for (int cc = 0; cc < 4; ++cc) {
+                                const int j0 = (g + cc) * 64 + ql * 4;
+                                if (g + cc < nchunk && j0 < L) {
+                                    const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
+                                    const float d0 = y.x - x[cc].x, d1 = y.y - x[cc].y, d2 = y.z - x[cc].z,
+                                                d3 = y.w - x[cc].w;
+                                    acc = fmaf(d0, d0, acc);
+                                    acc = fmaf(d1, d1, acc);
+                                    acc = fmaf(d2, d2, acc);
+                                    acc = fmaf(d3, d3, acc);
+                                }
+                            }
+                        } else {
 #pragma unroll
-                        for (int cc = 0; cc < 2; ++cc) {
-                            const int cix = ch + cc;
-                            if (cix < nchunk) {
-                                const int j0 = cix * 64 + ql * 4;
-                                if (VEC) {
-                                    if (j0 < L) {
-                                        const float4 x = *reinterpret_cast<const float4*>(row + j0);
-                                        const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
-                                        const float d0 = y.x - x.x, d1 = y.y - x.y, d2 = y.z - x.z, d3 = y.w - x.w;
-                                        acc[rr] = fmaf(d0, d0, acc[rr]);
-                                        acc[rr] = fmaf(d1, d1, acc[rr]);
-                                        acc[rr] = fmaf(d2, d2, acc[rr]);
-                                        acc[rr] = fmaf(d3, d3, acc[rr]);
-                                    }
-                                } else {
+                            for (int cc = 0; cc < 4; ++cc) {
 #pragma unroll
-                                    for (int e = 0; e < 4; ++e) {
-                                        const int jj = j0 + e;
-                                        if (jj < L) {
-                                            const float d = s_q[jj] - row[jj];
-                                            acc[rr] = fmaf(d, d, acc[rr]);
-                                        }
+                                for (int e = 0; e < 4; ++e) {
+                                    const int jj = (g + cc) * 64 + ql * 4 + e;
+                                    if (g + cc < nchunk && jj < L) {
+                                        const float d = s_q[jj] - row[jj];
+                                        acc = fmaf(d, d, acc);
                                     }
                                 }
                             }
                         }
                     }
-                    const float Un = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_Ublk)));
-#pragma unroll
-                    for (int rr = 0; rr < 2; ++rr) {
-                        float p = acc[rr];
-                        p += __shfl_xor(p, 8, 16);
-                        p += __shfl_xor(p, 4, 16);
-                        p += __shfl_xor(p, 2, 16);
-                        p += __shfl_xor(p, 1, 16);
-                        p = __shfl(p, quarter * 16, 64);  // one value per row on every lane of the row
-                        if (alive[rr]) c_bytes += (uint64_t)min(2, nchunk - ch) * 256u;
-                        if (ch + 2 < nchunk) {
-                            // one U for the whole wave (other waves may lower it meanwhile)
-                            if (alive[rr] && p * (1.0f - kRhoEd) > Un) {
-                                alive[rr] = false;
-                                if (ql == 0) ++c_abandon;
-                            }
-                        } else {
-                            acc[rr] = p;  // the full distance
+                    float p = acc;
+                    p += __shfl_xor(p, 8, 16);
+                    p += __shfl_xor(p, 4, 16);
+                    p += __shfl_xor(p, 2, 16);
+                    p += __shfl_xor(p, 1, 16);
+                    p = __shfl(p, quarter * 16, 64);  // one value per row on every lane of the row
+                    if (alive) c_bytes += (uint64_t)min(4, nchunk - g) * 256u;
+                    if (g + 4 < nchunk) {
+                        // one U for the whole wave (other waves may lower it meanwhile)
+                        const float Un = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_Ublk)));
+                        if (alive && p * (1.0f - kRhoEd) > Un) {
+                            alive = false;
+                            if (ql == 0) ++c_abandon;
                         }
+                    } else {
+                        acc = p;  // the full distance
                     }
                 }
-#pragma unroll
-                for (int rr = 0; rr < 2; ++rr) {
-                    if (act[rr] && ql == 0) ++c_dist;
-                    if (!(alive[rr] && ql == 0)) continue;
-                    const float d = acc[rr];
+                if (act && ql == 0) ++c_dist;
+                if (alive && ql == 0) {
+                    const float d = acc;
                     if (d * (1.0f - kRhoEd) <= s_Ublk) {
                         const uint32_t slot = atomicAdd(&st.ncand, 1u);
-                        if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx[rr]};
+                        if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx};
                         else st.ovf = 1;
                         ++appended;
                         if (k == 1) {
@@ -816,27 +902,30 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
             }
             if (k > 1 && appended) atomicAdd(&s_app, appended);
             __syncthreads();
-            if (a.prof && tid == 0) {
-                const unsigned long long now = wall_clock64();
-                t_ed += now - t_mark;
-                t_mark = now;
-            }
+            tick(2);
             if (k > 1 && s_app) hist_refresh(a, q, st, s_tmp, &s_Ublk);
             __syncthreads();
+            }
+            if (!more) break;
+            np = npn;
+            live = liven;
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) wd[r] = wdn[r];
         }
         __syncthreads();
     }
-    if (a.prof && tid == 0 && (pass == 0 || worked)) {
+    if (timing && tid == 0 && (pass == 0 || worked)) {
         // pass 0 writes the block's times; a second pass adds its own
         unsigned long long* pr = a.prof + (size_t)blockIdx.x * 4;
-        const unsigned long long v[4] = {t_ctl, t_lb, t_ed, wall_clock64() - t_begin};
+        const unsigned long long v[4] = {s_t[0], s_t[1], s_t[2], wall_clock64() - s_t[4]};
         for (int i = 0; i < 4; ++i) pr[i] = (pass == 0 ? 0ull : pr[i]) + v[i];
     }
     if (a.blk_cnt) {
         // per-block totals in plain stores (the host adds them up): same-address
         // atomics from every block at once would serialise at the end of the grid
         __shared__ unsigned long long s_cnt[4][5];
-        unsigned long long v[5] = {c_scanned, c_bounded, c_dist, c_abandon, c_bytes / 16 + c_bounded * 16ull};
+        unsigned long long v[5] = {c_scanned, c_bounded, c_dist, c_abandon,
+                                   (unsigned long long)c_bytes / 16 + (unsigned long long)c_bounded * 16ull};
         for (int i = 0; i < 5; ++i)
             for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
         if (lane == 0)
@@ -1019,6 +1108,8 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
     return MESSI_OK;
 }
 
+// Scan blocks: as many as can be resident at once (all instances of the scan
+// kernel share one grid, so the per-block statistics line up across passes).
 int scan_grid() {
     static int blocks = 0;
     if (!blocks) {
@@ -1027,7 +1118,15 @@ int scan_grid() {
             hipDeviceProp_t p;
             if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
         }
-        blocks = cus * 4;
+        int per = 4;
+        const void* fns[] = {(const void*)scan_kernel<true, 0>, (const void*)scan_kernel<true, 1>,
+                             (const void*)scan_kernel<false, 0>, (const void*)scan_kernel<false, 1>};
+        for (const void* f : fns) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kScanThreads, 0) == hipSuccess && nb > 0)
+                per = std::min(per, nb);
+        }
+        blocks = std::min(cus * std::max(per, 1), 4096);
     }
     return blocks;
 }
