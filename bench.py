@@ -187,7 +187,9 @@ def main():
     ix = None
     ans_i = torch.empty((nq, k), dtype=torch.int64, device=dev)
     ans_d = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    ans_i2, ans_d2 = torch.empty_like(ans_i), torch.empty_like(ans_d)
     answers = None
+    same_instrumented = True
     for step in range(args.warmup + args.steps):
         timed = step >= args.warmup
         if ix is not None:
@@ -199,21 +201,29 @@ def main():
         t1 = time.perf_counter()
         for qi in range(nq):
             a = time.perf_counter()
-            _, _, st = ix.knn(queries[qi:qi + 1], k, stats=True, out=(ans_i[qi:qi + 1], ans_d[qi:qi + 1]))
+            ix.knn(queries[qi:qi + 1], k, out=(ans_i[qi:qi + 1], ans_d[qi:qi + 1]))
             e = time.perf_counter()
             if timed:
                 lat.append((e - a) * 1e3)
+        t2 = time.perf_counter()
+        # the same queries again with the library's HIP-event phase timing and
+        # counters (the events themselves cost device time, so this pass is
+        # kept out of the throughput and latency figures)
+        for qi in range(nq):
+            _, _, st = ix.knn(queries[qi:qi + 1], k, stats=True, out=(ans_i2[qi:qi + 1], ans_d2[qi:qi + 1]))
+            if timed:
                 for key, v in st.items():
                     agg[key] = agg.get(key, 0) + v
-        t2 = time.perf_counter()
+        t3 = time.perf_counter()
         answers = (ans_i.cpu().numpy(), ans_d.cpu().numpy())
+        same_instrumented &= bool(torch.equal(ans_i, ans_i2) and torch.equal(ans_d, ans_d2))
         info = ix.info()
         log("step %d%s: build %.1f ms (summarize %.2f, bucket %.2f, split %.2f, finalize %.2f; %d leaves, %d levels), "
             "queries %.1f ms" % (step, "" if timed else " (warmup)", (t1 - t0) * 1e3, info["ms_summarize"],
                                  info["ms_bucket"], info["ms_split"], info["ms_finalize"], info["n_leaves"],
                                  info["levels"], (t2 - t1) * 1e3))
         if timed:
-            step_ms.append((t2 - t0) * 1e3)
+            step_ms.append((t3 - t0) * 1e3)
             build_ms.append((t1 - t0) * 1e3)
             query_ms.append((t2 - t1) * 1e3)
             infos.append(info)
@@ -285,6 +295,10 @@ def main():
         "cpu_baseline": cpu,
         "vs_baseline_note": "paper: ~50 ms per exact 1-NN query at 100 GB on 2x Xeon E5-2650 v4 (context only)",
         "answers_sha": hashlib.sha256(answers[0].tobytes()).hexdigest()[:16],
+        "instrumented_pass_same_answers": same_instrumented,
+        "measurement": "a step = index build + the queries answered one at a time (timed: value, p50, p99) + "
+                       "the same queries again with the library's HIP-event phase timing and counters (phases, "
+                       "roofline: the scan kernel's own event pair on its stream)",
     }
     if ix is not None:
         ix.close()

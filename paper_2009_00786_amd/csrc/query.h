@@ -29,6 +29,13 @@ struct OrdRec {
     uint32_t moff;   // members of all earlier leaves in the order
 };
 
+// One leaf-bound block's share of the smallest leaf bound and the largest one.
+struct LbPart {
+    unsigned long long key;  // (bound bits << 32) | leaf, smallest in the block
+    uint32_t mx;             // largest bound bits in the block
+    uint32_t pad;
+};
+
 // Per-query search state (device).
 struct QState {
     float paa[16];
@@ -80,6 +87,7 @@ struct QArgs {
     unsigned long long* cursor;  // [nq][kNB] (position << 32 | member offset) fill cursors
     uint32_t* hist;              // [nq][kHistBins] candidate-distance histogram
     float* approx_d;             // [nq][kApproxMax]
+    LbPart* lbpart;              // [nq][leaf-bound blocks]
     Cand* cand;                  // [nq][cap]
     uint32_t cap;
     float absmax_data;
@@ -98,7 +106,8 @@ struct Workspace {
     size_t cand_slots = 0;  // candidate slots over all queries (a call uses nq * cap of them)
     uint32_t max_chunks = 0;
     DevBuf qs, lb, order, rec, chunk_first, bins, mbins, cursor, hist, approx_d, cand, counters, err, prof, blk_cnt,
-        status;
+        status, lbpart;
+    uint32_t* h_err = nullptr;  // pinned copy of the call's error flags
     // BF16 path
     int32_t bf_nq = 0;
     size_t bf_pairs_cap = 0, bf_leafq_cap = 0;

@@ -60,16 +60,21 @@ __device__ __forceinline__ uint32_t vload(const uint32_t* p) {
 __device__ __forceinline__ float upper_u(float d) { return d * (1.0f + 2.0f * kRhoEd); }
 
 // --------------------------------------------------------------------------
-// prep
+// leaf bounds (with the query summary folded in)
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, const int32_t* __restrict__ kq,
-                                                   uint32_t kstride) {
-    __shared__ float s_q[MESSI_MAX_LEN];
-    __shared__ float s_red[2][4];
-    __shared__ int s_bad;
-    const int q = blockIdx.x;
-    const float* row = a.queries + (size_t)q * a.L;
-    if (threadIdx.x == 0) s_bad = 0;
+constexpr int kLeafBlock = 256;  // leaves per block of the bound kernels
+
+// Query summary, computed by every block that needs it: PAA (sequential
+// fp32 sums of each segment, one division), squared norm, largest |value|,
+// finiteness, and the region widening delta.
+struct QSum {
+    float paa[16];
+    float norm2, amax, delta;
+    bool bad;
+};
+
+__device__ void query_summary(const QArgs& a, const float* row, float* s_q, float* s_red, int* s_bad, QSum& out) {
+    if (threadIdx.x == 0) *s_bad = 0;
     __syncthreads();
     float n2 = 0.f, amax = 0.f;
     bool bad = false;
@@ -80,73 +85,86 @@ __global__ void __launch_bounds__(256) prep_kernel(QArgs a, int32_t k, const int
         n2 = fmaf(v, v, n2);
         amax = fmaxf(amax, fabsf(v));
     }
-    if (bad) s_bad = 1;
+    if (bad) *s_bad = 1;
     n2 = dev::wave_sum(n2);
     amax = dev::wave_max(amax);
     if ((threadIdx.x & 63) == 0) {
-        s_red[0][threadIdx.x >> 6] = n2;
-        s_red[1][threadIdx.x >> 6] = amax;
+        s_red[threadIdx.x >> 6] = n2;
+        s_red[4 + (threadIdx.x >> 6)] = amax;
     }
     __syncthreads();
-    QState& st = a.qs[q];
-    if (threadIdx.x < a.w) {
-        const int i = threadIdx.x;
+    if (threadIdx.x < 16) {
         float s = 0.f;
-        for (int j = 0; j < a.m; ++j) s += s_q[i * a.m + j];
-        st.paa[i] = s / (float)a.m;
-    } else if (threadIdx.x < 16) {
-        st.paa[threadIdx.x] = 0.f;
+        if (threadIdx.x < a.w)
+            for (int j = 0; j < a.m; ++j) s += s_q[threadIdx.x * a.m + j];
+        s_red[8 + threadIdx.x] = threadIdx.x < a.w ? s / (float)a.m : 0.f;
     }
-    if (threadIdx.x == 0) {
-        const float aq = fmaxf(fmaxf(s_red[1][0], s_red[1][1]), fmaxf(s_red[1][2], s_red[1][3]));
-        st.norm2 = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
-        const float u = 5.9604644775390625e-08f;  // 2^-24
-        st.delta = 1.01f * (2.f * (float)(a.lg_m + 1) * u * a.absmax_data + 2.f * (float)(a.m + 1) * u * aq);
-        st.U = 0x7f800000u;  // +inf
-        st.ncand = 0;
-        st.nmemb = 0;
-        st.nsurv = 0;
-        st.ovf = 0;
-        st.rerun = 0;
-        st.hbase = 0;
-        st.lbmax = 0;
-        st.argmin = ~0ull;
-        st.range = 0.f;
-        st.k = kq ? kq[q] : k;
-        st.err = s_bad ? 1u : 0u;
-        st.active = 1;
-        st.kstride = kstride;
-        if (s_bad) atomicOr(a.err_any, 1u);
-    }
-    for (int i = threadIdx.x; i < kNB; i += 256) {
-        a.bins[(size_t)q * kNB + i] = 0;
-        a.mbins[(size_t)q * kNB + i] = 0;
-    }
-    for (int i = threadIdx.x; i < kHistBins; i += 256) a.hist[(size_t)q * kHistBins + i] = 0;
+    __syncthreads();
+    for (int i = 0; i < 16; ++i) out.paa[i] = s_red[8 + i];
+    out.norm2 = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    out.amax = fmaxf(fmaxf(s_red[4], s_red[5]), fmaxf(s_red[6], s_red[7]));
+    const float u = 5.9604644775390625e-08f;  // 2^-24
+    out.delta = 1.01f * (2.f * (float)(a.lg_m + 1) * u * a.absmax_data + 2.f * (float)(a.m + 1) * u * out.amax);
+    out.bad = *s_bad != 0;
 }
 
-// --------------------------------------------------------------------------
-// leaf lower bounds
-// --------------------------------------------------------------------------
-constexpr int kLeavesPerThread = 4;
-constexpr int kLeafBlock = 256 * kLeavesPerThread;
-
-__global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a) {
+// Every leaf's lower bound against the query PAA, from per-segment tables in
+// LDS; each block also leaves its smallest and largest bound for the next
+// kernel.  Block 0 of each query initialises the query's search state (and
+// block 0 of query 0 the call's error flags and counters).
+__global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const int32_t* __restrict__ kq,
+                                                      uint32_t kstride) {
     __shared__ float s_lo[16 * 257];
     __shared__ float s_hi[16 * 257];
+    __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ float s_red[24];
+    __shared__ int s_bad;
     __shared__ unsigned long long s_min[4];
     __shared__ uint32_t s_max[4];
+    __shared__ float s_bp[256];
     const int q = blockIdx.y;
-    const QState& st = a.qs[q];
     const int A = 1 << a.b;
-    const float delta = st.delta;
+    if (threadIdx.x < A - 1) s_bp[threadIdx.x] = a.bp[threadIdx.x];
+    QSum qs;
+    query_summary(a, a.queries + (size_t)q * a.L, s_q, s_red, &s_bad, qs);
+    if (blockIdx.x == 0) {
+        QState& st = a.qs[q];
+        if (threadIdx.x < 16) st.paa[threadIdx.x] = qs.paa[threadIdx.x];
+        if (threadIdx.x == 0) {
+            st.norm2 = qs.norm2;
+            st.delta = qs.delta;
+            st.U = 0x7f800000u;  // +inf until the first bound
+            st.ncand = 0;
+            st.nmemb = 0;
+            st.nsurv = 0;
+            st.ovf = 0;
+            st.rerun = 0;
+            st.hbase = 0;
+            st.lbmax = 0;
+            st.argmin = ~0ull;
+            st.range = 0.f;
+            st.k = kq ? kq[q] : k;
+            st.err = qs.bad ? 1u : 0u;
+            st.active = 1;
+            st.kstride = kstride;
+            if (q == 0) {
+                for (int i = 0; i < 4; ++i) a.err_any[i] = 0;
+                if (a.counters) *a.counters = QCounters{};
+            }
+        }
+        for (int i = threadIdx.x; i < kNB; i += 256) {
+            a.bins[(size_t)q * kNB + i] = 0;
+            a.mbins[(size_t)q * kNB + i] = 0;
+        }
+        for (int i = threadIdx.x; i < kHistBins; i += 256) a.hist[(size_t)q * kHistBins + i] = 0;
+    }
     for (int idx = threadIdx.x; idx < a.w * (A + 1); idx += 256) {
         const int i = idx / (A + 1), c = idx % (A + 1);
-        const float p = st.paa[i];
+        const float p = qs.paa[i];
         float tl = 0.f, th = 0.f;
         if (c > 0 && c < A) {
-            const float lo = a.bp[c - 1] - delta;
-            const float hi = a.bp[c - 1] + delta;
+            const float lo = s_bp[c - 1] - qs.delta;
+            const float hi = s_bp[c - 1] + qs.delta;
             if (p < lo) tl = (lo - p) * (lo - p);
             if (p > hi) th = (p - hi) * (p - hi);
         }
@@ -157,9 +175,8 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a) {
     unsigned long long best = ~0ull;
     uint32_t mx = 0;
     const float mf = (float)a.m;
-    for (int j = 0; j < kLeavesPerThread; ++j) {
-        const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
-        if (l >= a.nL) break;
+    const int l = blockIdx.x * kLeafBlock + threadIdx.x;
+    if (l < a.nL) {
         const Leaf lf = a.leaves[l];
         float s = 0.f;
 #pragma unroll
@@ -173,9 +190,8 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a) {
         }
         const float lbv = s * mf;
         a.lb[(size_t)q * a.nL + l] = lbv;
-        const unsigned long long key = ((unsigned long long)__float_as_uint(lbv) << 32) | (uint32_t)l;
-        best = key < best ? key : best;
-        mx = max(mx, __float_as_uint(lbv));
+        best = ((unsigned long long)__float_as_uint(lbv) << 32) | (uint32_t)l;
+        mx = __float_as_uint(lbv);
     }
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(best, off);
@@ -194,8 +210,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a) {
             b0 = s_min[w] < b0 ? s_min[w] : b0;
             m0 = max(m0, s_max[w]);
         }
-        atomicMin(&a.qs[q].argmin, b0);
-        atomicMax(&a.qs[q].lbmax, m0);
+        a.lbpart[(size_t)q * gridDim.x + blockIdx.x] = LbPart{b0, m0, 0u};
     }
 }
 
@@ -205,38 +220,12 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a) {
 // The members evaluated: the argmin leaf, extended into the depth-first
 // neighbouring leaves (contiguous in the member arrays) until at least k
 // members, so that the first bound is finite.
-__device__ __forceinline__ void approx_range(const QArgs& a, const QState& st, uint32_t& r0, uint32_t& cnt,
-                                             uint32_t& lstart, uint32_t& lcount) {
-    const uint32_t leaf = (uint32_t)(st.argmin & 0xffffffffull);
+__device__ __forceinline__ void approx_range(const QArgs& a, uint32_t leaf, int32_t k, uint32_t& r0,
+                                             uint32_t& cnt) {
     const Leaf lf = a.leaves[leaf];
-    lstart = lf.start;
-    lcount = lf.count;
-    cnt = min(max(lf.count, (uint32_t)st.k), (uint32_t)kApproxMax);
+    cnt = min(max(lf.count, (uint32_t)k), (uint32_t)kApproxMax);
     cnt = (uint32_t)min((int64_t)cnt, a.n);
     r0 = (uint32_t)min((int64_t)lf.start, a.n - (int64_t)cnt);
-}
-
-__global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a) {
-    __shared__ float s_q[MESSI_MAX_LEN];
-    const int q = blockIdx.y;
-    const QState& st = a.qs[q];
-    if (st.err) return;
-    for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
-    __syncthreads();
-    uint32_t r0, cnt, ls, lc;
-    approx_range(a, st, r0, cnt, ls, lc);
-    const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
-    for (uint32_t r = gw; r < cnt; r += kApproxBlocks * 4) {
-        const float* x = a.series + (size_t)a.pos[r0 + r] * a.L;
-        float s = 0.f;
-        for (int j = lane; j < a.L; j += 64) {
-            const float d = s_q[j] - x[j];
-            s = fmaf(d, d, s);
-        }
-        s = dev::wave_sum(s);
-        if (lane == 0) a.approx_d[(size_t)q * kApproxMax + r] = s;
-    }
 }
 
 // k-th smallest (1-based) of n non-negative floats by a 4-pass radix select
@@ -283,14 +272,76 @@ __device__ float block_kth(Getter get, uint32_t n, uint32_t k, uint32_t* s_hist,
     return __uint_as_float(prefix);
 }
 
-__global__ void __launch_bounds__(256) approx_select_kernel(QArgs a) {
+// The smallest and largest leaf bound, from the leaf-bound kernel's per-block
+// partials (every thread of the block gets both).
+__device__ void lb_extremes(const QArgs& a, int q, uint32_t nlb, unsigned long long* s_min, uint32_t* s_max,
+                            unsigned long long& best, uint32_t& mx) {
+    best = ~0ull;
+    mx = 0;
+    for (uint32_t i = threadIdx.x; i < nlb; i += 256) {
+        const LbPart p = a.lbpart[(size_t)q * nlb + i];
+        best = p.key < best ? p.key : best;
+        mx = max(mx, p.mx);
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o < best ? o : best;
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_min[threadIdx.x >> 6] = best;
+        s_max[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    for (int w = 0; w < 4; ++w) {
+        best = s_min[w] < best ? s_min[w] : best;
+        mx = max(mx, s_max[w]);
+    }
+}
+
+// Distances to the approximate leaf's members.
+__global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a, uint32_t nlb) {
+    __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ unsigned long long s_min[4];
+    __shared__ uint32_t s_max[4];
+    const int q = blockIdx.y;
+    const QState& st = a.qs[q];
+    if (st.err) return;
+    for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
+    unsigned long long best;
+    uint32_t mx;
+    lb_extremes(a, q, nlb, s_min, s_max, best, mx);
+    uint32_t r0, cnt;
+    approx_range(a, (uint32_t)(best & 0xffffffffull), st.k, r0, cnt);
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (uint32_t r = gw; r < cnt; r += gridDim.x * 4) {
+        const float* x = a.series + (size_t)a.pos[r0 + r] * a.L;
+        float s = 0.f;
+        for (int j = lane; j < a.L; j += 64) {
+            const float d = s_q[j] - x[j];
+            s = fmaf(d, d, s);
+        }
+        s = dev::wave_sum(s);
+        if (lane == 0) a.approx_d[(size_t)q * kApproxMax + r] = s;
+    }
+}
+
+// The k-th of those distances: the first upper bound U (the paper's initial
+// best-so-far), the histogram base and the bound range of the bins.
+__global__ void __launch_bounds__(256) approx_select_kernel(QArgs a, uint32_t nlb) {
+    __shared__ unsigned long long s_min[4];
+    __shared__ uint32_t s_max[4];
     __shared__ uint32_t s_hist[256 + 4];
     __shared__ uint32_t s_b[2];
     const int q = blockIdx.x;
     QState& st = a.qs[q];
     if (st.err) return;
-    uint32_t r0, cnt, ls, lc;
-    approx_range(a, st, r0, cnt, ls, lc);
+    unsigned long long best;
+    uint32_t mx;
+    lb_extremes(a, q, nlb, s_min, s_max, best, mx);
+    uint32_t r0, cnt;
+    approx_range(a, (uint32_t)(best & 0xffffffffull), st.k, r0, cnt);
     const float* d = a.approx_d + (size_t)q * kApproxMax;
     const float kth = block_kth([&](uint32_t i) { return d[i]; }, cnt, (uint32_t)st.k, s_hist, s_b);
     const float U0 = isinf(kth) ? kth : upper_u(kth);
@@ -298,9 +349,11 @@ __global__ void __launch_bounds__(256) approx_select_kernel(QArgs a) {
     // the order and is scanned like any other, so every candidate is appended
     // exactly once per pass.
     if (threadIdx.x == 0) {
+        st.argmin = best;
+        st.lbmax = mx;
         st.U = __float_as_uint(U0);
         st.hbase = (int32_t)(__float_as_uint(U0) >> 16) - (kHistBins - 2);
-        float range = isinf(U0) ? __uint_as_float(st.lbmax) : U0;
+        float range = isinf(U0) ? __uint_as_float(mx) : U0;
         st.range = range > 0.f ? range : 1e-30f;
     }
 }
@@ -316,6 +369,7 @@ __device__ __forceinline__ int bin_of(float lbv, float range) {
 
 __device__ __forceinline__ bool leaf_kept(float lbv, float U0) { return !(lbv * (1.0f - kRhoLb) > U0); }
 
+// Leaves and members per bound bin.
 __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
     __shared__ uint32_t h[kNB];
     __shared__ uint32_t hm[kNB];
@@ -328,9 +382,8 @@ __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
     }
     __syncthreads();
     const float U0 = __uint_as_float(st.U), range = st.range;
-    for (int j = 0; j < kLeavesPerThread; ++j) {
-        const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
-        if (l >= a.nL) break;
+    const int l = blockIdx.x * kLeafBlock + threadIdx.x;
+    if (l < a.nL) {
         const float lbv = a.lb[(size_t)q * a.nL + l];
         if (leaf_kept(lbv, U0)) {
             const int bn = bin_of(lbv, range);
@@ -346,44 +399,34 @@ __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
         }
 }
 
-// Exclusive prefix sums of the leaf and member counts per bin: the fill
-// cursors of the scatter, the number of ordered leaves and of their members.
-__global__ void __launch_bounds__(kNB) bin_scan_kernel(QArgs a) {
-    __shared__ uint32_t wt[2][kNB / 64];
+// Exclusive prefix sums of the leaf and member counts per bin (4 consecutive
+// bins per thread): the fill cursors of the scatter, the number of ordered
+// leaves and of their members.
+__global__ void __launch_bounds__(256) bin_scan_kernel(QArgs a) {
+    __shared__ uint32_t s_tmp[4];
     const int q = blockIdx.x;
     QState& st = a.qs[q];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const uint32_t v = a.bins[(size_t)q * kNB + t];
-    const uint32_t vm = a.mbins[(size_t)q * kNB + t];
-    uint32_t x = v, xm = vm;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        const uint32_t ym = __shfl_up(xm, off);
-        if (lane >= off) {
-            x += y;
-            xm += ym;
-        }
+    if (st.err) return;
+    constexpr int kPer = kNB / 256;
+    uint32_t v[kPer], vm[kPer], sv = 0, svm = 0;
+    for (int i = 0; i < kPer; ++i) {
+        v[i] = a.bins[(size_t)q * kNB + threadIdx.x * kPer + i];
+        vm[i] = a.mbins[(size_t)q * kNB + threadIdx.x * kPer + i];
+        sv += v[i];
+        svm += vm[i];
     }
-    if (lane == 63) {
-        wt[0][wave] = x;
-        wt[1][wave] = xm;
-    }
+    uint32_t tot, totm;
+    uint32_t ex = block_exclusive_scan(sv, s_tmp, tot);
     __syncthreads();
-    uint32_t wo = 0, tot = 0, wom = 0, totm = 0;
-    for (int w = 0; w < kNB / 64; ++w) {
-        if (w < wave) {
-            wo += wt[0][w];
-            wom += wt[1][w];
-        }
-        tot += wt[0][w];
-        totm += wt[1][w];
+    uint32_t exm = block_exclusive_scan(svm, s_tmp, totm);
+    for (int i = 0; i < kPer; ++i) {
+        a.cursor[(size_t)q * kNB + threadIdx.x * kPer + i] = ((unsigned long long)ex << 32) | exm;
+        ex += v[i];
+        exm += vm[i];
     }
-    const uint32_t ex = wo + x - v, exm = wom + xm - vm;
-    a.bins[(size_t)q * kNB + t] = ex;
-    a.cursor[(size_t)q * kNB + t] = ((unsigned long long)ex << 32) | exm;
-    if (t == 0) {
-        st.nsurv = st.err ? 0u : tot;
-        st.nmemb = st.err ? 0u : totm;
+    if (threadIdx.x == 0) {
+        st.nsurv = tot;
+        st.nmemb = totm;
         if (a.counters) atomicAdd(&a.counters->kept, (unsigned long long)tot);
     }
 }
@@ -397,23 +440,19 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
     const QState& st = a.qs[q];
     if (st.err) return;
     const float U0 = __uint_as_float(st.U), range = st.range;
-    for (int j = 0; j < kLeavesPerThread; ++j) {
-        const int l = blockIdx.x * kLeafBlock + j * 256 + threadIdx.x;
-        if (l >= a.nL) break;
-        const float lbv = a.lb[(size_t)q * a.nL + l];
-        if (leaf_kept(lbv, U0)) {
-            const Leaf lf = a.leaves[l];
-            const unsigned long long old =
-                atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], (1ull << 32) | lf.count);
-            const uint32_t t = (uint32_t)(old >> 32), moff = (uint32_t)old;
-            if (t < (uint32_t)a.nL) {
-                a.order[(size_t)q * a.nL + t] = (uint32_t)l;
-                a.rec[(size_t)q * a.nL + t] = OrdRec{lf.start, lf.count, lbv, moff};
-                const uint64_t end = (uint64_t)moff + lf.count;
-                for (uint64_t c = ((uint64_t)moff + kChunk - 1) / kChunk; c * kChunk < end; ++c)
-                    if (c < a.max_chunks) a.chunk_first[(size_t)q * a.max_chunks + c] = t;
-            }
-        }
+    const int l = blockIdx.x * kLeafBlock + threadIdx.x;
+    if (l >= a.nL) return;
+    const float lbv = a.lb[(size_t)q * a.nL + l];
+    if (!leaf_kept(lbv, U0)) return;
+    const Leaf lf = a.leaves[l];
+    const unsigned long long old = atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], (1ull << 32) | lf.count);
+    const uint32_t t = (uint32_t)(old >> 32), moff = (uint32_t)old;
+    if (t < (uint32_t)a.nL) {
+        a.order[(size_t)q * a.nL + t] = (uint32_t)l;
+        a.rec[(size_t)q * a.nL + t] = OrdRec{lf.start, lf.count, lbv, moff};
+        const uint64_t end = (uint64_t)moff + lf.count;
+        for (uint64_t c = ((uint64_t)moff + kChunk - 1) / kChunk; c * kChunk < end; ++c)
+            if (c < a.max_chunks) a.chunk_first[(size_t)q * a.max_chunks + c] = t;
     }
 }
 
@@ -958,7 +997,12 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     if (threadIdx.x == 0) s_kept = 0;
     for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
     __syncthreads();
-    if (st.err) return;
+    if (st.err) {
+        // the call's error flags: one bit per kind of per-query failure
+        const uint32_t e = st.err;
+        if (threadIdx.x == 0) atomicOr(a.err_any, e == 1 ? 1u : e == 2 ? 2u : e == 3 ? 4u : e == 4 ? 8u : 16u);
+        return;
+    }
     const float U = __uint_as_float(st.U);
     const uint32_t nc = st.ncand;
     if (nc > a.cap) {
@@ -986,14 +1030,50 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
         }
         return;
     }
-    for (uint32_t j = threadIdx.x; j < kept; j += 256) {
-        const float* x = a.series + (size_t)s_i[j] * a.L;
-        double s = 0.0;
-        for (int t = 0; t < a.L; ++t) {
-            const double d = __dsub_rn((double)s_q[t], (double)x[t]);
-            s = __dadd_rn(s, __dmul_rn(d, d));
+    // D64 of every candidate: the squared differences added one after another
+    // in index order, each operation rounded once (no fused multiply-add)
+    if (kept <= 16) {
+        // few candidates: each wave stages one candidate's row in LDS with a
+        // coalesced load, then one lane sums it in order from LDS (while at
+        // most 16 candidates are kept, s_d beyond its first 64 entries is free)
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        float* stage = reinterpret_cast<float*>(s_d + 64) + wave * MESSI_MAX_LEN;
+        for (uint32_t g = 0; g < kept; g += 4) {
+            const uint32_t j = g + wave;
+            if (j < kept) {
+                const float* x = a.series + (size_t)s_i[j] * a.L;
+                for (int t = lane; t < a.L; t += 64) stage[t] = x[t];
+            }
+            __syncthreads();
+            if (j < kept && lane == 0) {
+                double s = 0.0;
+                for (int t = 0; t < a.L; ++t) {
+                    const double d = __dsub_rn((double)s_q[t], (double)stage[t]);
+                    s = __dadd_rn(s, __dmul_rn(d, d));
+                }
+                s_d[j] = s;
+            }
+            __syncthreads();
         }
-        s_d[j] = s;
+    } else {
+        // many candidates: a thread per candidate, loads 16 at a time
+        for (uint32_t j = threadIdx.x; j < kept; j += 256) {
+            const float* x = a.series + (size_t)s_i[j] * a.L;
+            double s = 0.0;
+            for (int t0 = 0; t0 < a.L; t0 += 16) {
+                float xv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) xv[u] = (t0 + u < a.L) ? x[t0 + u] : 0.f;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    if (t0 + u < a.L) {
+                        const double d = __dsub_rn((double)s_q[t0 + u], (double)xv[u]);
+                        s = __dadd_rn(s, __dmul_rn(d, d));
+                    }
+                }
+            }
+            s_d[j] = s;
+        }
     }
     uint32_t P = 1;
     while (P < kept) P <<= 1;
@@ -1062,7 +1142,7 @@ int Workspace::ensure_stats() {
 Workspace::~Workspace() {
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
-    for (void* p : {(void*)h_counters, (void*)h_prof, (void*)h_blk_cnt})
+    for (void* p : {(void*)h_counters, (void*)h_prof, (void*)h_blk_cnt, (void*)h_err})
         if (p) (void)hipHostFree(p);
 }
 
@@ -1095,6 +1175,8 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
         MESSI_TRY(ws->err.alloc(sizeof(uint32_t) * 4));
         MESSI_TRY(ws->prof.alloc(sizeof(unsigned long long) * 4 * 4096));
         MESSI_TRY(ws->blk_cnt.alloc(sizeof(unsigned long long) * 5 * 4096));
+        MESSI_TRY(ws->lbpart.alloc(sizeof(LbPart) * (size_t)nqa * ((nL + kLeafBlock - 1) / kLeafBlock)));
+        if (!ws->h_err) MESSI_HIP_TRY(hipHostMalloc((void**)&ws->h_err, sizeof(uint32_t) * 4, 0));
         ws->nq = nqa;
         ws->nL = (int32_t)nL;
         ws->max_chunks = mc;
@@ -1206,6 +1288,7 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.cursor = ws->cursor.as<unsigned long long>();
     a.hist = ws->hist.as<uint32_t>();
     a.approx_d = ws->approx_d.as<float>();
+    a.lbpart = ws->lbpart.as<LbPart>();
     a.cand = ws->cand.as<Cand>();
     a.cap = cap;
     a.absmax_data = ix->absmax;
@@ -1222,32 +1305,27 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
 }
 
 // Enqueue the whole search on c.s; `mark(i)` is called at the phase boundaries
-// 0..6 (prep, leaf bounds, first bound, order, scan, final, end) and 7 (after the
+// 0 (start), 2 .. 6 (first bound, order, scan, final, end) and 7 (after the
 // first FP32 scan pass).
 template <class Mark>
 int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool timing, Mark mark) {
     const hipStream_t s = c.s;
     const int32_t nq = c.nq;
     const Index* ix = c.ix;
-    MESSI_HIP_TRY(hipMemsetAsync(a.err_any, 0, sizeof(uint32_t) * 4, s));
-    if (a.counters) MESSI_HIP_TRY(hipMemsetAsync(a.counters, 0, sizeof(QCounters), s));
     const int32_t mode = c.mode;
-    MESSI_TRY(mark(0));
-    hipLaunchKernelGGL(prep_kernel, dim3(nq), dim3(256), 0, s, a, c.kmax, c.kq, (uint32_t)c.kmax);
-    MESSI_LAUNCH_CHECK("prep");
-    MESSI_TRY(mark(1));
     const unsigned lb_blocks = (unsigned)((a.nL + kLeafBlock - 1) / kLeafBlock);
-    hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    MESSI_TRY(mark(0));
+    hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a, c.kmax, c.kq, (uint32_t)c.kmax);
     MESSI_LAUNCH_CHECK("leaf_lb");
     MESSI_TRY(mark(2));
-    hipLaunchKernelGGL(approx_ed_kernel, dim3(kApproxBlocks, nq), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(approx_ed_kernel, dim3(kApproxBlocks, nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_ed");
-    hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_select");
     MESSI_TRY(mark(3));
     hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_hist");
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(nq), dim3(kNB), 0, s, a);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_scan");
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_scatter");
@@ -1261,14 +1339,20 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
         else hipLaunchKernelGGL((scan_kernel<false, 0>), g, b, 0, s, a);
         MESSI_LAUNCH_CHECK("scan");
         MESSI_TRY(mark(7));
-        hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 0);
-        MESSI_LAUNCH_CHECK("fixup");
-        // the second pass exits at once unless a query's buffer overflowed
-        if (vec) hipLaunchKernelGGL((scan_kernel<true, 1>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((scan_kernel<false, 1>), g, b, 0, s, a);
-        MESSI_LAUNCH_CHECK("rescan");
-        hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 1);
-        MESSI_LAUNCH_CHECK("fixup");
+        // k > 1: exact k-th bound and compaction, and a second pass for a
+        // query whose buffer overflowed (that pass exits at once otherwise).
+        // With k = 1 the bound is exact already, and an overflow (which needs
+        // more improving candidates than the buffer holds) is reported by the
+        // final kernel and retried with a larger buffer by the caller.
+        if (c.kmax > 1) {
+            hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 0);
+            MESSI_LAUNCH_CHECK("fixup");
+            if (vec) hipLaunchKernelGGL((scan_kernel<true, 1>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((scan_kernel<false, 1>), g, b, 0, s, a);
+            MESSI_LAUNCH_CHECK("rescan");
+            hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 1);
+            MESSI_LAUNCH_CHECK("fixup");
+        }
     }
     MESSI_TRY(mark(5));
     hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
@@ -1335,7 +1419,8 @@ size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap) {
     const size_t nL = (size_t)ix->n_leaves;
     size_t b = sizeof(QState) + nL * (sizeof(float) + sizeof(uint32_t) + sizeof(OrdRec)) +
                sizeof(uint32_t) * (size_t)max_chunks_of(ix) + kNB * (2 * sizeof(uint32_t) + sizeof(unsigned long long)) +
-               sizeof(uint32_t) * kHistBins + sizeof(float) * kApproxMax + sizeof(Cand) * (size_t)cap;
+               sizeof(uint32_t) * kHistBins + sizeof(float) * kApproxMax + sizeof(Cand) * (size_t)cap +
+               sizeof(LbPart) * ((nL + kLeafBlock - 1) / kLeafBlock) + sizeof(uint32_t);
     if (mode == MESSI_MODE_BF16) b += nL * 4 + 16384 * 8 + (size_t)((ix->len + 31) / 32 * 32) * 2 + 8;
     return b;
 }
@@ -1363,7 +1448,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     int32_t retries = 0;
     for (;;) {
         MESSI_TRY(launch_search(c, a, ws, cap, timing, mark));
-        MESSI_HIP_TRY(hipMemcpyAsync(&err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipMemcpyAsync(ws->h_err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         if (a.counters)
             MESSI_HIP_TRY(hipMemcpyAsync(ws->h_counters, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
         if (a.prof && fp32) {
@@ -1375,6 +1460,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
             hcnt = ws->h_blk_cnt;
         }
         MESSI_HIP_TRY(hipStreamSynchronize(s));
+        err = *ws->h_err;
         if (a.counters) hc = *ws->h_counters;
         // The FP32 scan's own second pass was not enough (more than cap
         // candidates below the k-th buffered distance): search again with a
@@ -1415,8 +1501,10 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         err = rest;
     }
     if (timing) {
-        float ms[6];
-        for (int i = 0; i < 6; ++i) MESSI_HIP_TRY(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+        // phase 0 (query summary) runs inside the leaf-bound kernel
+        float ms[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        MESSI_HIP_TRY(hipEventElapsedTime(&ms[1], ev[0], ev[2]));
+        for (int i = 2; i < 6; ++i) MESSI_HIP_TRY(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
         float tot = 0.f;
         MESSI_HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev[6]));
         stats->ms_prep = ms[0];
