@@ -255,6 +255,97 @@ __global__ void __launch_bounds__(256) summarize_kernel(SumArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// z-normalisation only, for rows of more than 32 values (padded length P =
+// 64 EP).  Lane l of a wave holds elements l, l + 64, ..., l + 64 (EP - 1) of
+// its row, so the fold-halving levels with strides of 64 and more are
+// additions inside the lane and only the last six (strides 32 .. 1) cross
+// lanes, on one value.  Same fp64 statistics and the same order of additions
+// as the general kernel; the quotient c / sigma is formed as c * (1 / sigma)
+// and rounded to fp32 directly unless that product lies within a few fp64
+// ulps of an fp32 rounding midpoint, where the correctly rounded fp64
+// quotient is computed instead -- so the fp32 result is fl32(fl64(c / sigma))
+// in every case.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float quotient_f32(double c, double sigma, double rs) {
+    const double q1 = __dmul_rn(c, rs);  // within 2 fp64 ulps of the exact quotient
+    const uint64_t bits = (uint64_t)__double_as_longlong(q1);
+    const int e = (int)((bits >> 52) & 0x7ff);
+    const uint32_t low = (uint32_t)(bits & ((1ull << 29) - 1));  // the bits below fp32 precision
+    const uint32_t half = 1u << 28;
+    // normal fp32 range, and not near the point where fp32 rounding flips
+    if (e >= 1023 - 126 && e <= 1023 + 127 && (low > half + 8u || low + 8u < half)) return (float)q1;
+    return (float)__ddiv_rn(c, sigma);
+}
+
+template <int EP, int R>
+__global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, float* out, int64_t n, int L,
+                                                            int* nonfinite) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    bool bad = false;
+    for (int64_t row0 = wave_id * R; row0 < n; row0 += n_waves * R) {
+        float x[R][EP];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = row0 + r;
+            const float* src = in + (size_t)(row < n ? row : 0) * (size_t)L;
+#pragma unroll
+            for (int k = 0; k < EP; ++k) {
+                const int j = lane + 64 * k;
+                x[r][k] = (row < n && j < L) ? src[j] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = row0 + r;
+            double v[EP];
+#pragma unroll
+            for (int k = 0; k < EP; ++k) {
+                bad |= !isfinite(x[r][k]);
+                v[k] = (double)x[r][k];
+            }
+#pragma unroll
+            for (int h = EP >> 1; h >= 1; h >>= 1)
+#pragma unroll
+                for (int k = 0; k < h; ++k) v[k] = __dadd_rn(v[k], v[k + h]);
+            double s1 = v[0];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) s1 = __dadd_rn(s1, __shfl_down(s1, off, 64));
+            s1 = __shfl(s1, 0, 64);
+            const double mu = __ddiv_rn(s1, (double)L);
+            double c[EP];
+#pragma unroll
+            for (int k = 0; k < EP; ++k) {
+                const bool in_row = lane + 64 * k < L;
+                c[k] = in_row ? __dsub_rn((double)x[r][k], mu) : 0.0;
+                v[k] = in_row ? __dmul_rn(c[k], c[k]) : 0.0;
+            }
+#pragma unroll
+            for (int h = EP >> 1; h >= 1; h >>= 1)
+#pragma unroll
+                for (int k = 0; k < h; ++k) v[k] = __dadd_rn(v[k], v[k + h]);
+            double s2 = v[0];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) s2 = __dadd_rn(s2, __shfl_down(s2, off, 64));
+            s2 = __shfl(s2, 0, 64);
+            const double var = __ddiv_rn(s2, (double)L);
+            const double sigma = __dsqrt_rn(var);
+            const double rs = var == 0.0 ? 0.0 : __ddiv_rn(1.0, sigma);
+            if (row < n) {
+                float* dst = out + (size_t)row * (size_t)L;
+#pragma unroll
+                for (int k = 0; k < EP; ++k) {
+                    const int j = lane + 64 * k;
+                    if (j < L) dst[j] = var == 0.0 ? 0.f : quotient_f32(c[k], sigma, rs);
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(nonfinite, 1);
+}
+
+// ---------------------------------------------------------------------------
 // Summarise, one segment per lane: lane l of a wave owns segment l % w of row
 // l / w (64 / w rows per wave), keeps the segment's m values in registers and
 // sums them by fold-halving there (no cross-lane traffic).  The symbol comes
@@ -833,6 +924,28 @@ struct Timer {
 // ---------------------------------------------------------------------------
 
 int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_flag) {
+    if (len > 32) {
+        int P = 64;
+        while (P < len) P <<= 1;
+        const int64_t waves = (n + 3) / 4;  // about 4 rows per wave
+        const int blocks = launch_blocks(waves, 4, 256 * 16);
+        switch (P / 64) {
+#define MESSI_ZN_CASE(EP, R)                                                                                  \
+    case EP:                                                                                                  \
+        hipLaunchKernelGGL((znorm_strided_kernel<EP, R>), dim3(blocks), dim3(256), 0, s, series, series, n, len, \
+                           d_flag);                                                                           \
+        break;
+            MESSI_ZN_CASE(1, 8)
+            MESSI_ZN_CASE(2, 4)
+            MESSI_ZN_CASE(4, 4)
+            MESSI_ZN_CASE(8, 2)
+            MESSI_ZN_CASE(16, 1)
+#undef MESSI_ZN_CASE
+            default: break;
+        }
+        MESSI_LAUNCH_CHECK("znorm");
+        return MESSI_OK;
+    }
     RowLayout r = row_layout(len);
     SumArgs a{};
     a.in = series;

@@ -53,8 +53,10 @@ def test_gpu_generator_matches_host(torch_cuda, datagen_mod):
     np.testing.assert_array_equal(gm.cpu().numpy(), hm)
 
 
-@pytest.mark.parametrize("n,length", [(100_000, 256), (4097, 128), (3001, 96), (1000, 100), (777, 1000),
-                                      (500, 16), (33, 3), (1, 64)])
+# 1M x 256 makes the fp64 quotient land near an fp32 rounding midpoint a few
+# times, so both ways of forming the fp32 quotient are exercised
+@pytest.mark.parametrize("n,length", [(1_000_000, 256), (100_000, 256), (4097, 128), (3001, 96), (1000, 100),
+                                      (777, 1000), (300, 512), (200, 33), (500, 16), (33, 3), (1, 64)])
 def test_znorm_bitwise(torch_cuda, messi, datagen_mod, oracle_mod, n, length):
     torch = torch_cuda
     _say("znorm n=%d len=%d" % (n, length))
