@@ -37,8 +37,11 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kKS = 8;             // K-steps of 32 held in registers (rows up to 256)
-constexpr uint32_t kFirstRound = 8;  // leaf positions per query in the first round
+// Ends of the filter rounds in each query's leaf order: a first bound from the
+// query's best leaves, a tighter one over the next few hundred, then the rest.
+// With a batch of queries nearly every leaf is visited in every later round,
+// so a round costs a pass over most of the BF16 rows: few rounds.
+constexpr uint32_t kRoundEnds[] = {16u, 0xffffffffu, 0xffffffffu};
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -95,7 +98,10 @@ struct BfArgs {
     uint2* pairs;           // (query, member position)
     uint32_t* npairs;
     uint32_t pairs_cap;
-    float c1;               // coefficient of |q||x| in E (rounded up)
+    uint32_t* work;         // next leaf of the filter (zero at the start of a round)
+    int32_t qc;             // queries of a leaf staged in LDS at a time (multiple of 16)
+    float c1;               // c1 (1 + 2^-18), rounded up: coefficient of |q||x| in the test
+    float one_minus_g;      // 1 - (7 u32 + 2^-18), rounded down
 };
 
 __global__ void __launch_bounds__(256) qprep_bf16_kernel(const float* __restrict__ queries, int L, int Lp,
@@ -149,118 +155,188 @@ __global__ void __launch_bounds__(256) leaf_scatter_kernel(QArgs a, uint32_t t0,
     }
 }
 
-// One block per leaf at a time (persistent, static stride over leaves); wave w
-// owns members w*16 .. w*16+15 of every 64-member tile of the leaf.
-__global__ void __launch_bounds__(256) bf16_filter_kernel(QArgs a, BfArgs bf) {
-    constexpr int kMaxLp = MESSI_MAX_LEN;
-    __shared__ uint16_t s_a[16 * (kMaxLp + 8)];
-    __shared__ float s_U[16], s_nq[16], s_rq[16];
-    __shared__ uint32_t s_qid[16];
+// ---------------------------------------------------------------------------
+// The filter.  With s the MFMA sum of the BF16 products and
+//   c1 = 4 u_b + 2 u_b^2 + 2 gamma_{Lp-1} (1 + u_b)^2,
+// the exact squared distance satisfies (bound above, using
+// (|q| + |x|)^2 <= 2 (|q|^2 + |x|^2) for the last term)
+//   D >= |q|^2 + |x|^2 - 2 s - c1 |q||x| - 7 u32 (|q|^2 + |x|^2),
+// so a member may be dropped for a query when
+//   2 s + c1' |q||x| < (1 - g) |q|^2 + (1 - g) |x|^2 - U'
+// with c1' = c1 (1 + 2^-18), g = 7 u32 + 2^-18 and U' = U (1 + 2^-20).  The
+// extra 2^-18 terms cover the fp32 roundings (to nearest) of this test
+// itself: the left side is at least -(|q|^2 + |x|^2) (1 + eps), so a drop
+// needs U' below about 2 (|q|^2 + |x|^2), every operand is then at most a few
+// times |q|^2 + |x|^2 in size, and the six roundings of 2^-24 each stay below
+// 2^-21 (|q|^2 + |x|^2); the two roundings of the c1' |q||x| product are
+// covered by the factor 1 + 2^-18 in c1'.  Per (query, member) that is one multiply, one
+// fused multiply-add, one add and a compare, on per-query terms
+// (c1' |q|, alpha = (1 - g) |q|^2 - U') and per-member terms (|x|,
+// beta = (1 - g) |x|^2).
+//
+// Work: blocks of kFWaves waves take leaves from a shared counter.  For a
+// leaf, up to QC of its queries (BF16 rows) are staged in LDS once; each wave
+// holds the BF16 rows of 32 members in registers (two 16-member B fragments
+// per 32-wide k-step) and streams 16-query A fragments from LDS, every A
+// fragment feeding two mfma_f32_16x16x32_bf16.  Rows longer than 256 values
+// are taken 8 k-steps of B at a time, with the accumulators of up to four
+// query tiles kept across them.
+// ---------------------------------------------------------------------------
+constexpr int kFWaves = 8;
+constexpr int kFThreads = 64 * kFWaves;
+constexpr int kFMem = 32;                  // members per wave
+constexpr int kFTile = kFWaves * kFMem;    // members per block step
+constexpr int kFKC = 8;                    // k-steps of B held at a time
+
+__global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs bf) {
+    extern __shared__ __align__(16) uint8_t s_raw[];
+    const int QC = bf.qc, Lp = bf.Lp, ks = bf.ksteps, lda = Lp + 8;
+    uint16_t* s_a = reinterpret_cast<uint16_t*>(s_raw);
+    float* s_alpha = reinterpret_cast<float*>(s_raw + (size_t)QC * lda * 2);
+    float* s_c1rq = s_alpha + QC;
+    uint32_t* s_qid = reinterpret_cast<uint32_t*>(s_c1rq + QC);
+    __shared__ uint32_t s_leaf;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, kb = lane >> 4;
-    const int Lp = bf.Lp, ks = bf.ksteps, lda = Lp + 8;
-    const bool resident = ks <= kKS;
-    const float u32 = 5.9604644775390625e-08f;
-    unsigned long long c_eval = 0, c_pass = 0, c_bytes = 0;
-    for (int leaf = blockIdx.x; leaf < a.nL; leaf += gridDim.x) {
+    const float c1p = bf.c1;
+    const float g1 = bf.one_minus_g;
+    unsigned long long c_eval = 0, c_bytes = 0;
+    for (;;) {
+        __syncthreads();  // every wave is done with the previous leaf's LDS
+        if (tid == 0) s_leaf = atomicAdd(bf.work, 1u);
+        __syncthreads();
+        const uint32_t leaf = s_leaf;
+        if (leaf >= (uint32_t)a.nL) break;
         const uint32_t cntq = bf.leaf_cnt[leaf];
         if (cntq == 0) continue;
         const Leaf lf = a.leaves[leaf];
         const uint32_t qoff = bf.leaf_off[leaf];
-        for (uint32_t mt0 = 0; mt0 < lf.count; mt0 += 64) {
-            const uint32_t mi = mt0 + wave * 16 + col;
-            const bool mvalid = mi < lf.count;
-            const uint32_t mpos = lf.start + (mvalid ? mi : 0u);
-            const uint16_t* brow = bf.shadow + (size_t)mpos * Lp;
-            bf16x8 bfrag[kKS];
-            if (resident) {
-#pragma unroll
-                for (int st = 0; st < kKS; ++st) {
-                    uint4 v = make_uint4(0, 0, 0, 0);
-                    if (st < ks && mvalid) v = *reinterpret_cast<const uint4*>(brow + 32 * st + 8 * kb);
-                    bfrag[st] = __builtin_bit_cast(bf16x8, v);
+        for (uint32_t qc0 = 0; qc0 < cntq; qc0 += QC) {
+            const int nqc = (int)min((uint32_t)QC, cntq - qc0);
+            const int nrows = (nqc + 15) & ~15;
+            if (qc0 > 0) __syncthreads();
+            // ---- stage the chunk's queries: ids and per-query terms, then the
+            // BF16 rows (rows past nqc are zero), eight 16-byte loads in flight
+            // per thread
+            for (int r = tid; r < nrows; r += kFThreads) {
+                if (r < nqc) {
+                    const uint32_t q = bf.leaf_q[qoff + qc0 + r];
+                    const float2 qn = bf.qnorm[q];
+                    const float U = __uint_as_float(vload(&a.qs[q].U));
+                    s_qid[r] = q;
+                    s_c1rq[r] = __fmul_rn(c1p, qn.y);
+                    s_alpha[r] = __fsub_rn(__fmul_rn(g1, qn.x), __fmul_rn(U, 1.00000095367431640625f));
+                } else {
+                    s_qid[r] = 0xffffffffu;
+                    s_c1rq[r] = 0.f;
+                    s_alpha[r] = -__uint_as_float(0x7f800000u);
                 }
             }
-            const float2 xn = mvalid ? bf.norms[mpos] : make_float2(0.f, 0.f);
-            if (mvalid && kb == 0) c_bytes += (uint64_t)Lp * 2 + 8;
-            for (uint32_t qt0 = 0; qt0 < cntq; qt0 += 16) {
-                __syncthreads();  // previous tile's readers are done
-                const int chunks = Lp / 8;  // 16-byte chunks per row
-                for (int idx = tid; idx < 16 * chunks; idx += 256) {
-                    const int r = idx / chunks, c = idx % chunks;
-                    const uint32_t qi = qt0 + r;
-                    uint4 v = make_uint4(0, 0, 0, 0);
-                    if (qi < cntq) {
-                        const uint32_t q = bf.leaf_q[qoff + qi];
-                        v = *reinterpret_cast<const uint4*>(bf.qb + (size_t)q * Lp + 8 * c);
-                    }
-                    *reinterpret_cast<uint4*>(&s_a[r * lda + 8 * c]) = v;
-                }
-                if (tid < 16) {
-                    const uint32_t qi = qt0 + tid;
-                    if (qi < cntq) {
-                        const uint32_t q = bf.leaf_q[qoff + qi];
-                        const float2 qn = bf.qnorm[q];
-                        s_qid[tid] = q;
-                        s_nq[tid] = qn.x;
-                        s_rq[tid] = qn.y;
-                        s_U[tid] = __uint_as_float(vload(&a.qs[q].U));
-                    } else {
-                        s_qid[tid] = 0xffffffffu;
+            __syncthreads();
+            const int chunks = Lp / 8;  // 16-byte pieces per row
+            const int total = nrows * chunks;
+            for (int base = 0; base < total; base += 8 * kFThreads) {
+                uint4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = base + u * kFThreads + tid;
+                    v[u] = make_uint4(0, 0, 0, 0);
+                    if (idx < total) {
+                        const uint32_t q = s_qid[idx / chunks];
+                        if (q != 0xffffffffu)
+                            v[u] = *reinterpret_cast<const uint4*>(bf.qb + (size_t)q * Lp + 8 * (idx % chunks));
                     }
                 }
-                __syncthreads();
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                if (resident) {
 #pragma unroll
-                    for (int st = 0; st < kKS; ++st) {
-                        if (st < ks) {
-                            const bf16x8 af =
-                                __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_a[col * lda + 32 * st + 8 * kb]));
-                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfrag[st], acc, 0, 0, 0);
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = base + u * kFThreads + tid;
+                    if (idx < total) *reinterpret_cast<uint4*>(&s_a[(idx / chunks) * lda + 8 * (idx % chunks)]) = v[u];
+                }
+            }
+            __syncthreads();
+            // ---- members: each wave 32 of every kFTile
+            for (uint32_t mt0 = 0; mt0 < lf.count; mt0 += kFTile) {
+                const uint32_t mb = mt0 + wave * kFMem;
+                if (mb >= lf.count) continue;  // this wave has no members in the tile
+                uint32_t mpos[2];
+                bool mval[2];
+                float rx[2], beta[2];
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    const uint32_t mi = mb + f * 16 + col;
+                    mval[f] = mi < lf.count;
+                    mpos[f] = lf.start + (mval[f] ? mi : 0u);
+                    const float2 xn = mval[f] ? bf.norms[mpos[f]] : make_float2(0.f, 0.f);
+                    rx[f] = xn.y;
+                    beta[f] = __fmul_rn(g1, xn.x);
+                    if (mval[f] && kb == 0) c_bytes += (uint64_t)Lp * 2 + 8;
+                }
+                bf16x8 bfrag[2][kFKC];
+                for (int qg0 = 0; qg0 < nqc; qg0 += 64) {
+                    const int ntile = min(4, (nqc - qg0 + 15) / 16);
+                    floatx4 acc[4][2];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int f = 0; f < 2; ++f) acc[t][f] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    for (int kc = 0; kc < ks; kc += kFKC) {
+                        // B for these k-steps (rows of at most 8 k-steps keep it across query groups)
+                        if (ks > kFKC || qg0 == 0) {
+#pragma unroll
+                            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                                for (int st = 0; st < kFKC; ++st) {
+                                    uint4 v = make_uint4(0, 0, 0, 0);
+                                    if (kc + st < ks && mval[f])
+                                        v = *reinterpret_cast<const uint4*>(bf.shadow + (size_t)mpos[f] * Lp +
+                                                                            32 * (kc + st) + 8 * kb);
+                                    bfrag[f][st] = __builtin_bit_cast(bf16x8, v);
+                                }
                         }
-                    }
-                } else {
-                    for (int s0 = 0; s0 < ks; s0 += kKS) {
 #pragma unroll
-                        for (int st = 0; st < kKS; ++st) {
-                            uint4 v = make_uint4(0, 0, 0, 0);
-                            if (s0 + st < ks && mvalid) v = *reinterpret_cast<const uint4*>(brow + 32 * (s0 + st) + 8 * kb);
-                            bfrag[st] = __builtin_bit_cast(bf16x8, v);
-                        }
+                        for (int t = 0; t < 4; ++t) {
+                            if (t < ntile) {
+                                const uint16_t* arow = &s_a[(qg0 + 16 * t + col) * lda + 8 * kb];
 #pragma unroll
-                        for (int st = 0; st < kKS; ++st) {
-                            if (s0 + st < ks) {
-                                const bf16x8 af = __builtin_bit_cast(
-                                    bf16x8, *reinterpret_cast<const uint4*>(&s_a[col * lda + 32 * (s0 + st) + 8 * kb]));
-                                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfrag[st], acc, 0, 0, 0);
+                                for (int st = 0; st < kFKC; ++st) {
+                                    if (kc + st < ks) {
+                                        const bf16x8 af = __builtin_bit_cast(
+                                            bf16x8, *reinterpret_cast<const uint4*>(arow + 32 * (kc + st)));
+                                        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfrag[0][st], acc[t][0],
+                                                                                            0, 0, 0);
+                                        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfrag[1][st], acc[t][1],
+                                                                                            0, 0, 0);
+                                    }
+                                }
                             }
                         }
                     }
-                }
-                // acc[i] = s for query row 4 kb + i and member col
+                    // ---- the test; acc[t][f][i] is query row qg0 + 16 t + 4 kb + i, member col of fragment f
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 4 * kb + i;
-                    const uint32_t q = s_qid[r];
-                    if (q != 0xffffffffu && mvalid) {
-                        ++c_eval;
-                        const float nq = s_nq[r], rq = s_rq[r];
-                        const float f = __fsub_rn(__fadd_rn(nq, xn.x), __fmul_rn(2.0f, acc[i]));
-                        const float rs = __fadd_rn(rq, xn.y);
-                        const float E = (bf.c1 * (rq * xn.y) + 3.0f * u32 * (nq + xn.x) + 2.0f * u32 * (rs * rs)) *
-                                        (1.0f + 9.5367431640625e-07f);
-                        const float margin = __fsub_rn(f, E);
-                        if (!(margin * (1.0f - 2.384185791015625e-07f) > s_U[r])) {
-                            const uint32_t slot = atomicAdd(bf.npairs, 1u);
-                            if (slot < bf.pairs_cap) {
-                                bf.pairs[slot] = make_uint2(q, mpos);
-                            } else {
-                                // this query lost a pair: its answer is redone by the fp32 path
-                                a.qs[q].err = 5;
-                                atomicOr(a.err_any, 16u);
+                    for (int t = 0; t < 4; ++t) {
+                        if (t >= ntile) continue;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int r = qg0 + 16 * t + 4 * kb + i;
+                            if (r >= nqc) continue;
+                            const float al = s_alpha[r], cq = s_c1rq[r];
+#pragma unroll
+                            for (int f = 0; f < 2; ++f) {
+                                if (!mval[f]) continue;
+                                ++c_eval;
+                                const float lhs = __fmaf_rn(2.0f, acc[t][f][i], __fmul_rn(cq, rx[f]));
+                                if (!(lhs < __fadd_rn(al, beta[f]))) {
+                                    const uint32_t slot = atomicAdd(bf.npairs, 1u);
+                                    const uint32_t q = s_qid[r];
+                                    if (slot < bf.pairs_cap) {
+                                        bf.pairs[slot] = make_uint2(q, mpos[f]);
+                                    } else {
+                                        // this query lost a pair: its answer is redone by the fp32 path
+                                        a.qs[q].err = 5;
+                                        atomicOr(a.err_any, 16u);
+                                    }
+                                }
                             }
-                            ++c_pass;
                         }
                     }
                 }
@@ -270,7 +346,6 @@ __global__ void __launch_bounds__(256) bf16_filter_kernel(QArgs a, BfArgs bf) {
     if (a.counters) {
         for (int off = 32; off >= 1; off >>= 1) {
             c_eval += __shfl_xor(c_eval, off);
-            c_pass += __shfl_xor(c_pass, off);
             c_bytes += __shfl_xor(c_bytes, off);
         }
         if (lane == 0) {
@@ -425,6 +500,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     const double nu = (double)(Lp - 1) * u;
     const double gamma = nu / (1.0 - nu);
     const double c1 = 4.0 * ub + 2.0 * ub * ub + 2.0 * gamma * (1.0 + ub) * (1.0 + ub);
+    const double g = 7.0 * std::ldexp(1.0, -24) + std::ldexp(1.0, -18);
     BfArgs bf{};
     bf.Lp = Lp;
     bf.ksteps = Lp / 32;
@@ -438,7 +514,19 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     bf.pairs = ws->pairs.as<uint2>();
     bf.npairs = ws->npairs.as<uint32_t>();
     bf.pairs_cap = (uint32_t)pairs_cap;
-    bf.c1 = (float)(c1 * (1.0 + 1e-6));
+    bf.c1 = std::nextafter((float)(c1 * (1.0 + std::ldexp(1.0, -18))), 1.0f);
+    bf.one_minus_g = std::nextafter((float)(1.0 - g), 0.0f);
+    bf.work = ws->npairs.as<uint32_t>() + 1;
+    // queries staged per leaf: as many as the LDS of one block holds (at most 256)
+    int lds_max = 65536;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device);
+    const size_t row_bytes = (size_t)(Lp + 8) * 2 + 12;
+    int qc = (int)std::min<size_t>(256, (size_t)(lds_max - 1024) / row_bytes) / 16 * 16;
+    if (qc < 16) qc = 16;
+    bf.qc = qc;
+    const size_t filter_lds = (size_t)qc * row_bytes;
+    MESSI_HIP_TRY(hipFuncSetAttribute((const void*)bf16_filter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)filter_lds));
 
     hipLaunchKernelGGL(qprep_bf16_kernel, dim3(nq), dim3(256), 0, s, a.queries, L, Lp, ws->qb.as<uint16_t>(),
                        ws->qnorm.as<float2>());
@@ -455,11 +543,13 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         return MESSI_OK;
     };
     int rounds_run = 0;
-    // Rounds over geometrically growing ranges of each query's leaf order
-    // (8, 64, 512, ... positions); after each round every query's bound is
-    // refreshed from its candidates, so later rounds are filtered tighter.
-    for (uint64_t t0 = 0, t1 = kFirstRound; t0 < (uint64_t)nL; t0 = t1, t1 = t1 * 8u) {
-        if (t1 > (uint64_t)nL) t1 = (uint64_t)nL;
+    // Rounds over ranges of each query's leaf order (kRoundEnds); after each
+    // round every query's bound is refreshed from its candidates, so later
+    // rounds are filtered tighter.
+    uint64_t t1 = 0;
+    for (int round = 0; t1 < (uint64_t)nL; ++round) {
+        const uint64_t t0 = t1;
+        t1 = std::min<uint64_t>(kRoundEnds[std::min(round, 2)], (uint64_t)nL);
         const unsigned tbr = (unsigned)((t1 - t0 + 255) / 256);
         const uint32_t r0 = (uint32_t)t0, r1 = (uint32_t)t1;
         MESSI_HIP_TRY(hipMemsetAsync(ws->leaf_cnt.p, 0, sizeof(uint32_t) * (nL + 1), s));
@@ -474,7 +564,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
                            leafq_cap);
         MESSI_LAUNCH_CHECK("leaf_scatter");
         MESSI_TRY(mark());
-        hipLaunchKernelGGL(bf16_filter_kernel, dim3(cus * 4), dim3(256), 0, s, a, bf);
+        hipLaunchKernelGGL(bf16_filter_kernel, dim3(cus), dim3(kFThreads), filter_lds, s, a, bf);
         MESSI_LAUNCH_CHECK("bf16_filter");
         MESSI_TRY(mark());
         hipLaunchKernelGGL(bf16_recheck_kernel, dim3(cus * 8), dim3(256), 0, s, a, bf);
