@@ -403,7 +403,8 @@ def bench_batched(args):
         "filter_hbm_gbps": f_bytes / (f_ms / 1e3) / 1e9 if f_ms else 0.0,
         "per_batch": {str(k): {kk: agg[k].get(kk, 0) / steps for kk in (
             "leaves_kept", "series_distance", "series_recheck", "candidates", "ms_bf16_filter", "ms_bf16_recheck",
-            "ms_total", "ms_leaf_lb", "ms_approx", "ms_order", "ms_scan", "ms_final", "bf16_rounds")}
+            "ms_total", "ms_leaf_lb", "ms_approx", "ms_order", "ms_scan", "ms_final", "bf16_rounds",
+            "bf16_stage_queries")}
             for k in (1, 10)},
         "discard_rate": 1.0 - (agg[1].get("series_recheck", 0) + agg[10].get("series_recheck", 0)) /
         max(1, agg[1].get("series_distance", 0) + agg[10].get("series_distance", 0)),

@@ -111,6 +111,8 @@ typedef struct {
     /* FP32 mode: device time after the first scan pass (candidate fix-up,
        the second pass when needed); ms_scan is then the first pass alone */
     double ms_fixup;
+    /* BF16 mode: queries of a leaf staged in LDS at a time by the filter */
+    int32_t bf16_stage_queries;
 } messi_knn_stats;
 
 /* ---- index ------------------------------------------------------------- */

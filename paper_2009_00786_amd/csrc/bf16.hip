@@ -51,13 +51,49 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 
 __device__ __forceinline__ uint32_t vload(const uint32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
 
+// Directed roundings for non-negative values: largest fp32 / BF16 value not
+// above x, smallest BF16 value not below x.
+__device__ __forceinline__ float f32_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = __uint_as_float(__float_as_uint(f) - 1u);
+    return f;
+}
+__device__ __forceinline__ uint16_t bf16_down(float x) { return (uint16_t)(__float_as_uint(x) >> 16); }
+__device__ __forceinline__ uint16_t bf16_up(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u >> 16) + ((u & 0xFFFFu) ? 1u : 0u));
+}
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+constexpr uint16_t kBf16MinusOne = 0xBF80u;
+
+// The constants of the filter's test for rows padded to Lp (see the filter).
+struct BfConsts {
+    double c1p;  // coefficient of |q||x|
+    double g;    // member-side slack
+    double h;    // query-side slack
+};
+
+BfConsts bf_consts(int Lp) {
+    const double ub = std::ldexp(1.0, -8), u = std::ldexp(1.0, -23);
+    const double nu = (double)(Lp + 32 - 1) * u;  // terms accumulated: Lp products + the extra k-step
+    const double gamma = nu / (1.0 - nu);
+    const double c1 = 4.0 * ub + 2.0 * ub * ub + 2.0 * gamma * (1.0 + ub) * (1.0 + ub);
+    BfConsts k;
+    k.c1p = c1 * (1.0 + 2.0 * gamma + std::ldexp(1.0, -18));
+    k.g = gamma + std::ldexp(1.0, -20) + std::ldexp(1.0, -22);
+    k.h = std::ldexp(1.0, -20) + std::ldexp(1.0, -22);
+    return k;
+}
+
 // ---------------------------------------------------------------------------
-// build: BF16 rows in leaf order (zero-padded to a multiple of 32) and the
-// fp32 squared norm and norm of every member, from fp64 sums.
+// build: BF16 rows in leaf order (zero-padded to a multiple of 32) and, per
+// member, the BF16 terms of the filter's extra k-step: |x| rounded up and
+// beta = (1 - g) |x|^2 as a sum of two BF16 values rounded down (|x|^2 summed
+// in fp64).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) shadow_kernel(const float* __restrict__ series, const uint32_t* __restrict__ pos,
-                                                     int64_t n, int L, int Lp, uint16_t* __restrict__ shadow,
-                                                     float2* __restrict__ norms) {
+                                                     int64_t n, int L, int Lp, double one_minus_g,
+                                                     uint16_t* __restrict__ shadow, uint2* __restrict__ sx) {
     const int lane = threadIdx.x & 63;
     const bool vec = (L % 4) == 0;
     for (int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); j < n; j += (int64_t)gridDim.x * 4) {
@@ -79,7 +115,13 @@ __global__ void __launch_bounds__(256) shadow_kernel(const float* __restrict__ s
             *reinterpret_cast<uint2*>(shadow + (size_t)j * Lp + e0) = make_uint2(lo, hi);
         }
         for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) norms[j] = make_float2((float)acc, (float)sqrt(acc));
+        if (lane == 0) {
+            const uint16_t rx = bf16_up((float)sqrt(acc) * 1.0000001192092896f);  // |x|, from above
+            const double beta = one_minus_g * acc;
+            const uint16_t bh = bf16_down(f32_down(beta));
+            const uint16_t bl = bf16_down(f32_down(beta - (double)bf16_value(bh)));
+            sx[j] = make_uint2((uint32_t)rx | ((uint32_t)bh << 16), (uint32_t)bl);
+        }
     }
 }
 
@@ -89,9 +131,10 @@ __global__ void __launch_bounds__(256) shadow_kernel(const float* __restrict__ s
 struct BfArgs {
     int32_t Lp, ksteps;
     const uint16_t* shadow;
-    const float2* norms;
-    const uint16_t* qb;     // [nq][Lp] bf16 queries
+    const uint2* sx;        // [n] member terms of the extra k-step
+    const uint16_t* qb;     // [nq][Lp] bf16 queries, doubled
     const float2* qnorm;    // [nq] (|q|^2, |q|)
+    const uint4* qx;        // [nq] query terms of the extra k-step
     const uint32_t* leaf_cnt;
     const uint32_t* leaf_off;
     const uint32_t* leaf_q;
@@ -100,12 +143,15 @@ struct BfArgs {
     uint32_t pairs_cap;
     uint32_t* work;         // next leaf of the filter (zero at the start of a round)
     int32_t qc;             // queries of a leaf staged in LDS at a time (multiple of 16)
-    float c1;               // c1 (1 + 2^-18), rounded up: coefficient of |q||x| in the test
-    float one_minus_g;      // 1 - (7 u32 + 2^-18), rounded down
+    float one_minus_h;      // 1 - h, rounded down
 };
 
-__global__ void __launch_bounds__(256) qprep_bf16_kernel(const float* __restrict__ queries, int L, int Lp,
-                                                         uint16_t* __restrict__ qb, float2* __restrict__ qnorm) {
+// Per query: 2 q in BF16 (an exact doubling of the rounded q), |q|^2 and |q|
+// from fp64, and the extra k-step (c1' |q| rounded up, -1, -1, 0, ...) that
+// meets the member's (|x|, beta_hi, beta_lo, 0, ...).
+__global__ void __launch_bounds__(256) qprep_bf16_kernel(const float* __restrict__ queries, int L, int Lp, float c1p,
+                                                         uint16_t* __restrict__ qb, float2* __restrict__ qnorm,
+                                                         uint4* __restrict__ qx) {
     __shared__ double s_part[4];
     const int q = blockIdx.x;
     const float* row = queries + (size_t)q * L;
@@ -113,14 +159,18 @@ __global__ void __launch_bounds__(256) qprep_bf16_kernel(const float* __restrict
     for (int e = threadIdx.x; e < Lp; e += 256) {
         const float v = (e < L) ? row[e] : 0.f;
         acc += (double)v * (double)v;
-        qb[(size_t)q * Lp + e] = bf16_rne(v);
+        qb[(size_t)q * Lp + e] = bf16_rne(2.0f * v);
     }
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
     if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         const double t = s_part[0] + s_part[1] + s_part[2] + s_part[3];
-        qnorm[q] = make_float2((float)t, (float)sqrt(t));
+        const float rq = (float)sqrt(t);
+        qnorm[q] = make_float2((float)t, rq);
+        // c1' |q| from above: one ulp over the rounded product, then BF16 up
+        const float cq = __uint_as_float(__float_as_uint(c1p * (rq * 1.0000001192092896f)) + 1u);
+        qx[q] = make_uint4((uint32_t)bf16_up(cq) | ((uint32_t)kBf16MinusOne << 16), (uint32_t)kBf16MinusOne, 0u, 0u);
     }
 }
 
@@ -156,31 +206,33 @@ __global__ void __launch_bounds__(256) leaf_scatter_kernel(QArgs a, uint32_t t0,
 }
 
 // ---------------------------------------------------------------------------
-// The filter.  With s the MFMA sum of the BF16 products and
-//   c1 = 4 u_b + 2 u_b^2 + 2 gamma_{Lp-1} (1 + u_b)^2,
-// the exact squared distance satisfies (bound above, using
-// (|q| + |x|)^2 <= 2 (|q|^2 + |x|^2) for the last term)
-//   D >= |q|^2 + |x|^2 - 2 s - c1 |q||x| - 7 u32 (|q|^2 + |x|^2),
-// so a member may be dropped for a query when
-//   2 s + c1' |q||x| < (1 - g) |q|^2 + (1 - g) |x|^2 - U'
-// with c1' = c1 (1 + 2^-18), g = 7 u32 + 2^-18 and U' = U (1 + 2^-20).  The
-// extra 2^-18 terms cover the fp32 roundings (to nearest) of this test
-// itself: the left side is at least -(|q|^2 + |x|^2) (1 + eps), so a drop
-// needs U' below about 2 (|q|^2 + |x|^2), every operand is then at most a few
-// times |q|^2 + |x|^2 in size, and the six roundings of 2^-24 each stay below
-// 2^-21 (|q|^2 + |x|^2); the two roundings of the c1' |q||x| product are
-// covered by the factor 1 + 2^-18 in c1'.  Per (query, member) that is one multiply, one
-// fused multiply-add, one add and a compare, on per-query terms
-// (c1' |q|, alpha = (1 - g) |q|^2 - U') and per-member terms (|x|,
-// beta = (1 - g) |x|^2).
+// The filter.  s = MFMA sum of BF16 products, with the fp32 accumulation of
+// K = Lp + 32 terms in any order and rounding (u = 2^-23, gamma = gamma_{K-1})
+// covered; |q~.x~ - q.x| <= (2 u_b + u_b^2) |q||x| for the BF16-rounded rows.
+// The query's A row is 2 q~ followed by the extra k-step (c~, -1, -1, 0, ...),
+// the member's B row is x~ followed by (r~x, b_hi, b_lo, 0, ...), where
+//   c~ >= c1' |q|,  r~x >= |x|,  b_hi + b_lo <= beta = (1 - g) |x|^2,
+//   c1 = 4 u_b + 2 u_b^2 + 2 gamma (1 + u_b)^2,  c1' = c1 (1 + 2 gamma + 2^-18),
+//   g = gamma + 2^-20 + 2^-22,
+// so one MFMA chain yields acc ~ 2 q~.x~ + c~ r~x - b_hi - b_lo.  A member is
+// dropped for a query iff acc < alpha = fl(fl((1 - h) |q|^2) - fl(U (1 + 2^-20))),
+// h = 2^-20 + 2^-22.  That drop is exact: with the accumulation error at most
+// gamma (2 (1 + u_b)^2 |q||x| + c~ r~x + beta),
+//   D = |q|^2 + |x|^2 - 2 q.x  >=  |q|^2 + |x|^2 - acc + c~ r~x (1 - gamma)
+//       - c1 |q||x| - (1 - g) |x|^2 - gamma beta
+//     >  U (1 + 2^-20) + (h - 2^-23) |q|^2 + (g - gamma - 2^-23) |x|^2 - err(alpha)
+//     >= U,
+// because c~ r~x (1 - gamma) covers c1 |q||x| (norms are fp32 roundings of
+// fp64 sums, within 2^-23), and a drop needs acc > -(|q|^2 + 2|x|^2) (1.01),
+// so U < 2.02 (|q|^2 + |x|^2) and the roundings of alpha stay below the 2^-20
+// slacks.  The test costs one compare per (query, member).
 //
 // Work: blocks of kFWaves waves take leaves from a shared counter.  For a
 // leaf, up to QC of its queries (BF16 rows) are staged in LDS once; each wave
 // holds the BF16 rows of 32 members in registers (two 16-member B fragments
 // per 32-wide k-step) and streams 16-query A fragments from LDS, every A
-// fragment feeding two mfma_f32_16x16x32_bf16.  Rows longer than 256 values
-// are taken 8 k-steps of B at a time, with the accumulators of up to four
-// query tiles kept across them.
+// fragment feeding two mfma_f32_16x16x32_bf16, four query tiles interleaved.
+// Rows longer than 256 values are taken 8 k-steps of B at a time.
 // ---------------------------------------------------------------------------
 constexpr int kFWaves = 8;
 constexpr int kFThreads = 64 * kFWaves;
@@ -188,18 +240,26 @@ constexpr int kFMem = 32;                  // members per wave
 constexpr int kFTile = kFWaves * kFMem;    // members per block step
 constexpr int kFKC = 8;                    // k-steps of B held at a time
 
+__device__ __forceinline__ bf16x8 member_extra(const uint2* sx, uint32_t pos, bool valid, int kb) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (valid && kb == 0) {
+        const uint2 t = sx[pos];
+        v = make_uint4(t.x, t.y, 0u, 0u);
+    }
+    return __builtin_bit_cast(bf16x8, v);
+}
+
 __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs bf) {
     extern __shared__ __align__(16) uint8_t s_raw[];
     const int QC = bf.qc, Lp = bf.Lp, ks = bf.ksteps, lda = Lp + 8;
     uint16_t* s_a = reinterpret_cast<uint16_t*>(s_raw);
     float* s_alpha = reinterpret_cast<float*>(s_raw + (size_t)QC * lda * 2);
-    float* s_c1rq = s_alpha + QC;
-    uint32_t* s_qid = reinterpret_cast<uint32_t*>(s_c1rq + QC);
+    uint4* s_qx = reinterpret_cast<uint4*>(s_alpha + QC);
+    uint32_t* s_qid = reinterpret_cast<uint32_t*>(s_qx + QC);
     __shared__ uint32_t s_leaf;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, kb = lane >> 4;
-    const float c1p = bf.c1;
-    const float g1 = bf.one_minus_g;
+    const float h1 = bf.one_minus_h;
     unsigned long long c_eval = 0, c_bytes = 0;
     for (;;) {
         __syncthreads();  // every wave is done with the previous leaf's LDS
@@ -224,11 +284,11 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                     const float2 qn = bf.qnorm[q];
                     const float U = __uint_as_float(vload(&a.qs[q].U));
                     s_qid[r] = q;
-                    s_c1rq[r] = __fmul_rn(c1p, qn.y);
-                    s_alpha[r] = __fsub_rn(__fmul_rn(g1, qn.x), __fmul_rn(U, 1.00000095367431640625f));
+                    s_qx[r] = bf.qx[q];
+                    s_alpha[r] = __fsub_rn(__fmul_rn(h1, qn.x), __fmul_rn(U, 1.00000095367431640625f));
                 } else {
                     s_qid[r] = 0xffffffffu;
-                    s_c1rq[r] = 0.f;
+                    s_qx[r] = make_uint4(0, 0, 0, 0);
                     s_alpha[r] = -__uint_as_float(0x7f800000u);
                 }
             }
@@ -255,23 +315,30 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
             }
             __syncthreads();
             // ---- members: each wave 32 of every kFTile
+            const bool pf = ks <= kFKC;  // the whole row fits the B registers
             for (uint32_t mt0 = 0; mt0 < lf.count; mt0 += kFTile) {
                 const uint32_t mb = mt0 + wave * kFMem;
                 if (mb >= lf.count) continue;  // this wave has no members in the tile
                 uint32_t mpos[2];
                 bool mval[2];
-                float rx[2], beta[2];
+                bf16x8 bfrag[2][kFKC], bx[2];
 #pragma unroll
                 for (int f = 0; f < 2; ++f) {
                     const uint32_t mi = mb + f * 16 + col;
                     mval[f] = mi < lf.count;
                     mpos[f] = lf.start + (mval[f] ? mi : 0u);
-                    const float2 xn = mval[f] ? bf.norms[mpos[f]] : make_float2(0.f, 0.f);
-                    rx[f] = xn.y;
-                    beta[f] = __fmul_rn(g1, xn.x);
                     if (mval[f] && kb == 0) c_bytes += (uint64_t)Lp * 2 + 8;
+                    bx[f] = member_extra(bf.sx, mpos[f], mval[f], kb);
+                    if (pf) {
+#pragma unroll
+                        for (int st = 0; st < kFKC; ++st) {
+                            uint4 v = make_uint4(0, 0, 0, 0);
+                            if (st < ks && mval[f])
+                                v = *reinterpret_cast<const uint4*>(bf.shadow + (size_t)mpos[f] * Lp + 32 * st + 8 * kb);
+                            bfrag[f][st] = __builtin_bit_cast(bf16x8, v);
+                        }
+                    }
                 }
-                bf16x8 bfrag[2][kFKC];
                 for (int qg0 = 0; qg0 < nqc; qg0 += 64) {
                     const int ntile = min(4, (nqc - qg0 + 15) / 16);
                     floatx4 acc[4][2];
@@ -279,9 +346,10 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                     for (int t = 0; t < 4; ++t)
 #pragma unroll
                         for (int f = 0; f < 2; ++f) acc[t][f] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    const uint16_t* arow = &s_a[(qg0 + col) * lda + 8 * kb];
                     for (int kc = 0; kc < ks; kc += kFKC) {
-                        // B for these k-steps (rows of at most 8 k-steps keep it across query groups)
-                        if (ks > kFKC || qg0 == 0) {
+                        // B for these k-steps (rows of at most kFKC k-steps have it already)
+                        if (!pf) {
 #pragma unroll
                             for (int f = 0; f < 2; ++f)
 #pragma unroll
@@ -293,21 +361,41 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                                     bfrag[f][st] = __builtin_bit_cast(bf16x8, v);
                                 }
                         }
+                        // k-step by k-step over the query tiles, so that eight
+                        // independent accumulations interleave on the matrix unit
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            if (t < ntile) {
-                                const uint16_t* arow = &s_a[(qg0 + 16 * t + col) * lda + 8 * kb];
+                        for (int st = 0; st < kFKC; ++st) {
+                            if (kc + st < ks) {
+                                bf16x8 af[4];
 #pragma unroll
-                                for (int st = 0; st < kFKC; ++st) {
-                                    if (kc + st < ks) {
-                                        const bf16x8 af = __builtin_bit_cast(
-                                            bf16x8, *reinterpret_cast<const uint4*>(arow + 32 * (kc + st)));
-                                        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfrag[0][st], acc[t][0],
+                                for (int t = 0; t < 4; ++t)
+                                    if (t < ntile)
+                                        af[t] = __builtin_bit_cast(
+                                            bf16x8, *reinterpret_cast<const uint4*>(arow + 16 * t * lda + 32 * (kc + st)));
+#pragma unroll
+                                for (int t = 0; t < 4; ++t) {
+                                    if (t < ntile) {
+                                        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bfrag[0][st], acc[t][0],
                                                                                             0, 0, 0);
-                                        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfrag[1][st], acc[t][1],
+                                        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bfrag[1][st], acc[t][1],
                                                                                             0, 0, 0);
                                     }
                                 }
+                            }
+                        }
+                    }
+                    // the extra k-step: c~ r~x - b_hi - b_lo
+                    {
+                        bf16x8 ax[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            if (t < ntile)
+                                ax[t] = __builtin_bit_cast(bf16x8, kb == 0 ? s_qx[qg0 + 16 * t + col] : make_uint4(0, 0, 0, 0));
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            if (t < ntile) {
+                                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax[t], bx[0], acc[t][0], 0, 0, 0);
+                                acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax[t], bx[1], acc[t][1], 0, 0, 0);
                             }
                         }
                     }
@@ -315,19 +403,18 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         if (t >= ntile) continue;
+                        const int r0 = qg0 + 16 * t + 4 * kb;  // this lane's 4 query rows
+                        const float4 al4 = *reinterpret_cast<const float4*>(&s_alpha[r0]);
+                        const float alv[4] = {al4.x, al4.y, al4.z, al4.w};
+                        c_eval += (uint32_t)(min(4, max(0, nqc - r0)) * ((int)mval[0] + (int)mval[1]));
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const int r = qg0 + 16 * t + 4 * kb + i;
-                            if (r >= nqc) continue;
-                            const float al = s_alpha[r], cq = s_c1rq[r];
+                            if (r0 + i >= nqc) continue;  // padding rows of the last tile
 #pragma unroll
                             for (int f = 0; f < 2; ++f) {
-                                if (!mval[f]) continue;
-                                ++c_eval;
-                                const float lhs = __fmaf_rn(2.0f, acc[t][f][i], __fmul_rn(cq, rx[f]));
-                                if (!(lhs < __fadd_rn(al, beta[f]))) {
+                                if (mval[f] && !(acc[t][f][i] < alv[i])) {
                                     const uint32_t slot = atomicAdd(bf.npairs, 1u);
-                                    const uint32_t q = s_qid[r];
+                                    const uint32_t q = s_qid[r0 + i];
                                     if (slot < bf.pairs_cap) {
                                         bf.pairs[slot] = make_uint2(q, mpos[f]);
                                     } else {
@@ -383,9 +470,11 @@ __global__ void __launch_bounds__(256) bf16_recheck_kernel(QArgs a, BfArgs bf) {
     const uint32_t stride = gridDim.x * 16;
     for (uint32_t base = (blockIdx.x * 4 + wave) * 4; base < np; base += stride) {
         const uint32_t pi = base + quarter;
-        const bool act = pi < np;
         uint2 pr = make_uint2(0, 0);
-        if (act) pr = bf.pairs[pi];
+        if (pi < np) pr = bf.pairs[pi];
+        // a pair outside the call's queries or the collection is never followed
+        const bool act = pi < np && pr.x < (uint32_t)a.nq && (int64_t)pr.y < a.n;
+        if (!act) pr = make_uint2(0, 0);
         const uint32_t gidx = a.pos[pr.y];
         const float* x = a.series + (size_t)gidx * L;
         const float* qr = a.queries + (size_t)pr.x * L;
@@ -451,15 +540,16 @@ int device_cus() {
 int build_bf16_shadow(Index* ix, hipStream_t s) {
     const int Lp = (ix->len + 31) / 32 * 32;
     MESSI_TRY(ix->shadow.alloc(sizeof(uint16_t) * (size_t)ix->n * Lp));
-    MESSI_TRY(ix->norms.alloc(sizeof(float2) * (size_t)ix->n));
+    MESSI_TRY(ix->sx.alloc(sizeof(uint2) * (size_t)ix->n));
     hipEvent_t e0, e1;
     MESSI_HIP_TRY(hipEventCreate(&e0));
     MESSI_HIP_TRY(hipEventCreate(&e1));
     MESSI_HIP_TRY(hipEventRecord(e0, s));
     const int64_t waves = (ix->n + 3) / 4;
     const unsigned blocks = (unsigned)std::min<int64_t>(waves, (int64_t)device_cus() * 16);
+    const BfConsts kc = bf_consts(Lp);
     hipLaunchKernelGGL(shadow_kernel, dim3(blocks), dim3(256), 0, s, ix->series, ix->pos.as<uint32_t>(), ix->n,
-                       ix->len, Lp, ix->shadow.as<uint16_t>(), ix->norms.as<float2>());
+                       ix->len, Lp, 1.0 - kc.g, ix->shadow.as<uint16_t>(), ix->sx.as<uint2>());
     MESSI_LAUNCH_CHECK("shadow");
     MESSI_HIP_TRY(hipEventRecord(e1, s));
     MESSI_HIP_TRY(hipEventSynchronize(e1));
@@ -484,6 +574,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         MESSI_TRY(ws->qb.alloc(sizeof(uint16_t) * (size_t)nq * Lp));
         MESSI_TRY(ws->qnorm.alloc(sizeof(float2) * (size_t)nq));
+        MESSI_TRY(ws->qx.alloc(sizeof(uint4) * (size_t)nq));
         MESSI_TRY(ws->leaf_cnt.alloc(sizeof(uint32_t) * (nL + 1)));
         MESSI_TRY(ws->leaf_off.alloc(sizeof(uint32_t) * (nL + 1)));
         MESSI_TRY(ws->leaf_cur.alloc(sizeof(uint32_t) * (nL + 1)));
@@ -495,41 +586,38 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         ws->bf_pairs_cap = pairs_cap;
         ws->bf_leafq_cap = leafq_cap;
     }
-    // coefficient of |q||x| in the bound, rounded up
-    const double ub = std::ldexp(1.0, -8), u = std::ldexp(1.0, -23);
-    const double nu = (double)(Lp - 1) * u;
-    const double gamma = nu / (1.0 - nu);
-    const double c1 = 4.0 * ub + 2.0 * ub * ub + 2.0 * gamma * (1.0 + ub) * (1.0 + ub);
-    const double g = 7.0 * std::ldexp(1.0, -24) + std::ldexp(1.0, -18);
+    const BfConsts kc = bf_consts(Lp);
     BfArgs bf{};
     bf.Lp = Lp;
     bf.ksteps = Lp / 32;
     bf.shadow = ix->shadow.as<uint16_t>();
-    bf.norms = ix->norms.as<float2>();
+    bf.sx = ix->sx.as<uint2>();
     bf.qb = ws->qb.as<uint16_t>();
     bf.qnorm = ws->qnorm.as<float2>();
+    bf.qx = ws->qx.as<uint4>();
     bf.leaf_cnt = ws->leaf_cnt.as<uint32_t>();
     bf.leaf_off = ws->leaf_off.as<uint32_t>();
     bf.leaf_q = ws->leaf_q.as<uint32_t>();
     bf.pairs = ws->pairs.as<uint2>();
     bf.npairs = ws->npairs.as<uint32_t>();
     bf.pairs_cap = (uint32_t)pairs_cap;
-    bf.c1 = std::nextafter((float)(c1 * (1.0 + std::ldexp(1.0, -18))), 1.0f);
-    bf.one_minus_g = std::nextafter((float)(1.0 - g), 0.0f);
+    bf.one_minus_h = std::nextafter((float)(1.0 - kc.h), 0.0f);
     bf.work = ws->npairs.as<uint32_t>() + 1;
     // queries staged per leaf: as many as the LDS of one block holds (at most 256)
     int lds_max = 65536;
     (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device);
-    const size_t row_bytes = (size_t)(Lp + 8) * 2 + 12;
+    const size_t row_bytes = (size_t)(Lp + 8) * 2 + 24;  // row, alpha, extra k-step, id
     int qc = (int)std::min<size_t>(256, (size_t)(lds_max - 1024) / row_bytes) / 16 * 16;
     if (qc < 16) qc = 16;
     bf.qc = qc;
+    ws->bf_stage_queries = qc;
     const size_t filter_lds = (size_t)qc * row_bytes;
     MESSI_HIP_TRY(hipFuncSetAttribute((const void*)bf16_filter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)filter_lds));
 
-    hipLaunchKernelGGL(qprep_bf16_kernel, dim3(nq), dim3(256), 0, s, a.queries, L, Lp, ws->qb.as<uint16_t>(),
-                       ws->qnorm.as<float2>());
+    hipLaunchKernelGGL(qprep_bf16_kernel, dim3(nq), dim3(256), 0, s, a.queries, L, Lp,
+                       std::nextafter((float)kc.c1p, 1.0f), ws->qb.as<uint16_t>(), ws->qnorm.as<float2>(),
+                       ws->qx.as<uint4>());
     MESSI_LAUNCH_CHECK("qprep_bf16");
     const int cus = device_cus();
     // events around the filter and recheck launches of every round (timing only)

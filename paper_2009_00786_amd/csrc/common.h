@@ -102,14 +102,14 @@ struct Index {
     DevBuf pos;     // uint32 [n]: series index of each member, leaf order
     DevBuf leaves;  // Leaf [n_leaves], depth-first order
     DevBuf bp;      // float [2^b - 1] breakpoints
-    DevBuf norms;   // float [n] squared norms, leaf order (bf16 shadow only)
+    DevBuf sx;      // uint2 [n]: BF16 (|x| up, beta high, beta low, 0) per member, leaf order (bf16 shadow only)
     DevBuf shadow;  // bf16 [n][len] rows in leaf order (bf16 shadow only)
 
     float bp_host[255];
     messi_info info{};
 
     uint64_t device_bytes() const {
-        return words.bytes + pos.bytes + leaves.bytes + bp.bytes + norms.bytes + shadow.bytes;
+        return words.bytes + pos.bytes + leaves.bytes + bp.bytes + sx.bytes + shadow.bytes;
     }
     ~Index();
 };

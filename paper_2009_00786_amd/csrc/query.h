@@ -72,7 +72,6 @@ struct QArgs {
     const Leaf* leaves;
     int32_t nL;
     const float* bp;
-    const float* norms;          // bf16 path: squared norms in leaf order
     const uint16_t* shadow;      // bf16 path: bf16 rows in leaf order
     const float* queries;        // [nq][L]
     int32_t nq;
@@ -111,10 +110,10 @@ struct Workspace {
     // BF16 path
     int32_t bf_nq = 0;
     size_t bf_pairs_cap = 0, bf_leafq_cap = 0;
-    DevBuf qb, qnorm, leaf_cnt, leaf_off, leaf_cur, leaf_q, pairs, npairs, scan_scr;
+    DevBuf qb, qnorm, qx, leaf_cnt, leaf_off, leaf_cur, leaf_q, pairs, npairs, scan_scr;
     // timing of the BF16 kernels of the last call (filled when timing is on)
     double bf_ms_filter = 0, bf_ms_recheck = 0;
-    int bf_rounds = 0;
+    int bf_rounds = 0, bf_stage_queries = 0;
     // statistics read-back: phase events and pinned staging, made on first use
     hipEvent_t ev[8] = {};
     QCounters* h_counters = nullptr;

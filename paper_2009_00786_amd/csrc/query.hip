@@ -175,8 +175,8 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     unsigned long long best = ~0ull;
     uint32_t mx = 0;
     const float mf = (float)a.m;
-    const int l = blockIdx.x * kLeafBlock + threadIdx.x;
-    if (l < a.nL) {
+    // leaves blockIdx.x * 256 + threadIdx.x, stepping over the query's blocks
+    for (int l = blockIdx.x * kLeafBlock + threadIdx.x; l < a.nL; l += gridDim.x * kLeafBlock) {
         const Leaf lf = a.leaves[l];
         float s = 0.f;
 #pragma unroll
@@ -190,8 +190,9 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
         }
         const float lbv = s * mf;
         a.lb[(size_t)q * a.nL + l] = lbv;
-        best = ((unsigned long long)__float_as_uint(lbv) << 32) | (uint32_t)l;
-        mx = __float_as_uint(lbv);
+        const unsigned long long key = ((unsigned long long)__float_as_uint(lbv) << 32) | (uint32_t)l;
+        best = key < best ? key : best;
+        mx = max(mx, __float_as_uint(lbv));
     }
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(best, off);
@@ -382,8 +383,7 @@ __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
     }
     __syncthreads();
     const float U0 = __uint_as_float(st.U), range = st.range;
-    const int l = blockIdx.x * kLeafBlock + threadIdx.x;
-    if (l < a.nL) {
+    for (int l = blockIdx.x * kLeafBlock + threadIdx.x; l < a.nL; l += gridDim.x * kLeafBlock) {
         const float lbv = a.lb[(size_t)q * a.nL + l];
         if (leaf_kept(lbv, U0)) {
             const int bn = bin_of(lbv, range);
@@ -440,19 +440,20 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
     const QState& st = a.qs[q];
     if (st.err) return;
     const float U0 = __uint_as_float(st.U), range = st.range;
-    const int l = blockIdx.x * kLeafBlock + threadIdx.x;
-    if (l >= a.nL) return;
-    const float lbv = a.lb[(size_t)q * a.nL + l];
-    if (!leaf_kept(lbv, U0)) return;
-    const Leaf lf = a.leaves[l];
-    const unsigned long long old = atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], (1ull << 32) | lf.count);
-    const uint32_t t = (uint32_t)(old >> 32), moff = (uint32_t)old;
-    if (t < (uint32_t)a.nL) {
-        a.order[(size_t)q * a.nL + t] = (uint32_t)l;
-        a.rec[(size_t)q * a.nL + t] = OrdRec{lf.start, lf.count, lbv, moff};
-        const uint64_t end = (uint64_t)moff + lf.count;
-        for (uint64_t c = ((uint64_t)moff + kChunk - 1) / kChunk; c * kChunk < end; ++c)
-            if (c < a.max_chunks) a.chunk_first[(size_t)q * a.max_chunks + c] = t;
+    for (int l = blockIdx.x * kLeafBlock + threadIdx.x; l < a.nL; l += gridDim.x * kLeafBlock) {
+        const float lbv = a.lb[(size_t)q * a.nL + l];
+        if (!leaf_kept(lbv, U0)) continue;
+        const Leaf lf = a.leaves[l];
+        const unsigned long long old =
+            atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], (1ull << 32) | lf.count);
+        const uint32_t t = (uint32_t)(old >> 32), moff = (uint32_t)old;
+        if (t < (uint32_t)a.nL) {
+            a.order[(size_t)q * a.nL + t] = (uint32_t)l;
+            a.rec[(size_t)q * a.nL + t] = OrdRec{lf.start, lf.count, lbv, moff};
+            const uint64_t end = (uint64_t)moff + lf.count;
+            for (uint64_t c = ((uint64_t)moff + kChunk - 1) / kChunk; c * kChunk < end; ++c)
+                if (c < a.max_chunks) a.chunk_first[(size_t)q * a.max_chunks + c] = t;
+        }
     }
 }
 
@@ -1313,7 +1314,11 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     const int32_t nq = c.nq;
     const Index* ix = c.ix;
     const int32_t mode = c.mode;
-    const unsigned lb_blocks = (unsigned)((a.nL + kLeafBlock - 1) / kLeafBlock);
+    // blocks per query over the leaves: one per 256 leaves for a few queries;
+    // for a large batch fewer, so that the query tables each block builds are
+    // not rebuilt more often than needed (about 8K blocks in all)
+    const unsigned lb_blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((a.nL + kLeafBlock - 1) / kLeafBlock, (8192 + nq - 1) / nq));
     MESSI_TRY(mark(0));
     hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a, c.kmax, c.kq, (uint32_t)c.kmax);
     MESSI_LAUNCH_CHECK("leaf_lb");
@@ -1538,6 +1543,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
             stats->ms_bf16_filter = ws->bf_ms_filter;
             stats->ms_bf16_recheck = ws->bf_ms_recheck;
             stats->bf16_rounds = ws->bf_rounds;
+            stats->bf16_stage_queries = ws->bf_stage_queries;
             stats->bf16_flops = (int64_t)hc.distance * 2 * Lp;
             stats->scan_launches = ws->bf_rounds;
         }

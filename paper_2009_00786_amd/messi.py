@@ -74,7 +74,8 @@ class KnnStats(ctypes.Structure):
                 ("scan_ms_distance", ctypes.c_double), ("scan_ms_block_mean", ctypes.c_double),
                 ("scan_ms_block_max", ctypes.c_double), ("ms_bf16_filter", ctypes.c_double),
                 ("ms_bf16_recheck", ctypes.c_double), ("bf16_flops", ctypes.c_int64), ("bf16_rounds", ctypes.c_int32),
-                ("reruns", ctypes.c_int32), ("fallbacks", ctypes.c_int32), ("ms_fixup", ctypes.c_double)]
+                ("reruns", ctypes.c_int32), ("fallbacks", ctypes.c_int32), ("ms_fixup", ctypes.c_double),
+                ("bf16_stage_queries", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
