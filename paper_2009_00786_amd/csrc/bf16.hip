@@ -229,14 +229,16 @@ __global__ void __launch_bounds__(256) leaf_scatter_kernel(QArgs a, uint32_t t0,
 //
 // Work: blocks of kFWaves waves take leaves from a shared counter.  For a
 // leaf, up to QC of its queries (BF16 rows) are staged in LDS once; each wave
-// holds the BF16 rows of 32 members in registers (two 16-member B fragments
+// holds the BF16 rows of 64 members in registers (four 16-member B fragments
 // per 32-wide k-step) and streams 16-query A fragments from LDS, every A
-// fragment feeding two mfma_f32_16x16x32_bf16, four query tiles interleaved.
+// fragment feeding four mfma_f32_16x16x32_bf16, two query tiles interleaved.
 // Rows longer than 256 values are taken 8 k-steps of B at a time.
 // ---------------------------------------------------------------------------
 constexpr int kFWaves = 8;
 constexpr int kFThreads = 64 * kFWaves;
-constexpr int kFMem = 32;                  // members per wave
+constexpr int kFFrags = 4;                 // 16-member B fragments per wave
+constexpr int kFQT = 2;                    // 16-query A tiles per step
+constexpr int kFMem = 16 * kFFrags;        // members per wave
 constexpr int kFTile = kFWaves * kFMem;    // members per block step
 constexpr int kFKC = 8;                    // k-steps of B held at a time
 
@@ -319,11 +321,11 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
             for (uint32_t mt0 = 0; mt0 < lf.count; mt0 += kFTile) {
                 const uint32_t mb = mt0 + wave * kFMem;
                 if (mb >= lf.count) continue;  // this wave has no members in the tile
-                uint32_t mpos[2];
-                bool mval[2];
-                bf16x8 bfrag[2][kFKC], bx[2];
+                uint32_t mpos[kFFrags];
+                bool mval[kFFrags];
+                bf16x8 bfrag[kFFrags][kFKC], bx[kFFrags];
 #pragma unroll
-                for (int f = 0; f < 2; ++f) {
+                for (int f = 0; f < kFFrags; ++f) {
                     const uint32_t mi = mb + f * 16 + col;
                     mval[f] = mi < lf.count;
                     mpos[f] = lf.start + (mval[f] ? mi : 0u);
@@ -339,19 +341,19 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                         }
                     }
                 }
-                for (int qg0 = 0; qg0 < nqc; qg0 += 64) {
-                    const int ntile = min(4, (nqc - qg0 + 15) / 16);
-                    floatx4 acc[4][2];
+                for (int qg0 = 0; qg0 < nqc; qg0 += 16 * kFQT) {
+                    const int ntile = min(kFQT, (nqc - qg0 + 15) / 16);
+                    floatx4 acc[kFQT][kFFrags];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t)
+                    for (int t = 0; t < kFQT; ++t)
 #pragma unroll
-                        for (int f = 0; f < 2; ++f) acc[t][f] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        for (int f = 0; f < kFFrags; ++f) acc[t][f] = floatx4{0.f, 0.f, 0.f, 0.f};
                     const uint16_t* arow = &s_a[(qg0 + col) * lda + 8 * kb];
                     for (int kc = 0; kc < ks; kc += kFKC) {
                         // B for these k-steps (rows of at most kFKC k-steps have it already)
                         if (!pf) {
 #pragma unroll
-                            for (int f = 0; f < 2; ++f)
+                            for (int f = 0; f < kFFrags; ++f)
 #pragma unroll
                                 for (int st = 0; st < kFKC; ++st) {
                                     uint4 v = make_uint4(0, 0, 0, 0);
@@ -361,24 +363,24 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                                     bfrag[f][st] = __builtin_bit_cast(bf16x8, v);
                                 }
                         }
-                        // k-step by k-step over the query tiles, so that eight
-                        // independent accumulations interleave on the matrix unit
+                        // k-step by k-step over the query tiles: every A fragment
+                        // feeds kFFrags MFMAs, kFQT * kFFrags chains interleave
 #pragma unroll
                         for (int st = 0; st < kFKC; ++st) {
                             if (kc + st < ks) {
-                                bf16x8 af[4];
+                                bf16x8 af[kFQT];
 #pragma unroll
-                                for (int t = 0; t < 4; ++t)
+                                for (int t = 0; t < kFQT; ++t)
                                     if (t < ntile)
                                         af[t] = __builtin_bit_cast(
                                             bf16x8, *reinterpret_cast<const uint4*>(arow + 16 * t * lda + 32 * (kc + st)));
 #pragma unroll
-                                for (int t = 0; t < 4; ++t) {
+                                for (int t = 0; t < kFQT; ++t) {
                                     if (t < ntile) {
-                                        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bfrag[0][st], acc[t][0],
-                                                                                            0, 0, 0);
-                                        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bfrag[1][st], acc[t][1],
-                                                                                            0, 0, 0);
+#pragma unroll
+                                        for (int f = 0; f < kFFrags; ++f)
+                                            acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bfrag[f][st],
+                                                                                                acc[t][f], 0, 0, 0);
                                     }
                                 }
                             }
@@ -386,32 +388,36 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                     }
                     // the extra k-step: c~ r~x - b_hi - b_lo
                     {
-                        bf16x8 ax[4];
+                        bf16x8 ax[kFQT];
 #pragma unroll
-                        for (int t = 0; t < 4; ++t)
+                        for (int t = 0; t < kFQT; ++t)
                             if (t < ntile)
                                 ax[t] = __builtin_bit_cast(bf16x8, kb == 0 ? s_qx[qg0 + 16 * t + col] : make_uint4(0, 0, 0, 0));
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) {
+                        for (int t = 0; t < kFQT; ++t) {
                             if (t < ntile) {
-                                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax[t], bx[0], acc[t][0], 0, 0, 0);
-                                acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax[t], bx[1], acc[t][1], 0, 0, 0);
+#pragma unroll
+                                for (int f = 0; f < kFFrags; ++f)
+                                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax[t], bx[f], acc[t][f], 0, 0, 0);
                             }
                         }
                     }
                     // ---- the test; acc[t][f][i] is query row qg0 + 16 t + 4 kb + i, member col of fragment f
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
+                    for (int t = 0; t < kFQT; ++t) {
                         if (t >= ntile) continue;
                         const int r0 = qg0 + 16 * t + 4 * kb;  // this lane's 4 query rows
                         const float4 al4 = *reinterpret_cast<const float4*>(&s_alpha[r0]);
                         const float alv[4] = {al4.x, al4.y, al4.z, al4.w};
-                        c_eval += (uint32_t)(min(4, max(0, nqc - r0)) * ((int)mval[0] + (int)mval[1]));
+                        int nvalid = 0;
+#pragma unroll
+                        for (int f = 0; f < kFFrags; ++f) nvalid += (int)mval[f];
+                        c_eval += (uint32_t)(min(4, max(0, nqc - r0)) * nvalid);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             if (r0 + i >= nqc) continue;  // padding rows of the last tile
 #pragma unroll
-                            for (int f = 0; f < 2; ++f) {
+                            for (int f = 0; f < kFFrags; ++f) {
                                 if (mval[f] && !(acc[t][f][i] < alv[i])) {
                                     const uint32_t slot = atomicAdd(bf.npairs, 1u);
                                     const uint32_t q = s_qid[r0 + i];
