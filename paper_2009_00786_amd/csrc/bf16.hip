@@ -424,9 +424,9 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                                     if (slot < bf.pairs_cap) {
                                         bf.pairs[slot] = make_uint2(q, mpos[f]);
                                     } else {
-                                        // this query lost a pair: its answer is redone by the fp32 path
-                                        a.qs[q].err = 5;
-                                        atomicOr(a.err_any, 16u);
+                                        // this query lost a pair: its answer is redone by the fp32
+                                        // path (the final kernel raises the call's flag)
+                                        if (a.qs[q].err == 0) a.qs[q].err = 5;
                                     }
                                 }
                             }
@@ -507,8 +507,7 @@ __global__ void __launch_bounds__(256) bf16_recheck_kernel(QArgs a, BfArgs bf) {
                 if (slot < a.cap) {
                     a.cand[(size_t)pr.x * a.cap + slot] = Cand{d, gidx};
                 } else {
-                    st.err = 2;
-                    atomicOr(a.err_any, 2u);
+                    if (st.err == 0) st.err = 2;  // the final kernel raises the call's flag
                 }
                 if (st.k == 1) atomicMin(&st.U, __float_as_uint(d * (1.0f + 2.0f * kRhoEd)));
             }
@@ -575,7 +574,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     const int nq = a.nq;
     const size_t nL = (size_t)ix->n_leaves;
     const size_t leafq_cap = (size_t)nq * nL;
-    const size_t pairs_cap = std::min<size_t>((size_t)nq * 16384, (size_t)1 << 28);
+    const size_t pairs_cap = std::min<size_t>((size_t)nq * 65536, (size_t)1 << 28);
     if (ws->bf_nq < nq || ws->bf_pairs_cap < pairs_cap || ws->bf_leafq_cap < leafq_cap) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         MESSI_TRY(ws->qb.alloc(sizeof(uint16_t) * (size_t)nq * Lp));

@@ -142,7 +142,7 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
                 uint32_t cap_min = 0);
 // Default candidate slots per query for a call of nq queries with k <= kmax.
-uint32_t default_cap(int32_t nq, int32_t kmax);
+uint32_t default_cap(int32_t nq, int32_t kmax, int32_t mode);
 int knn_error_code(uint32_t err);
 int query_error_code(uint32_t status);
 

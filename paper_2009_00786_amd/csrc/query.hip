@@ -1119,16 +1119,19 @@ std::map<std::pair<const Index*, hipStream_t>, Workspace*> g_ws;
 
 }  // namespace
 
-// Candidate slots per query: 2^20 for a single query, 64 k (at least 2^14)
-// per query of a batch.  MESSI_CANDIDATE_CAP in the environment overrides the
-// default (at least 2 k), to exercise the overflow paths in tests.
-uint32_t default_cap(int32_t nq, int32_t kmax) {
+// Candidate slots per query: 2^20 for a single query, 64 k (at least 2^14;
+// 2^16 in BF16 mode, whose rounds append all rechecked survivors within the
+// round's bound) per query of a batch.  MESSI_CANDIDATE_CAP in the environment
+// overrides the default (at least 2 k), to exercise the overflow paths in tests.
+uint32_t default_cap(int32_t nq, int32_t kmax, int32_t mode) {
     const uint32_t floor_k = 2u * (uint32_t)kmax;
     if (const char* v = std::getenv("MESSI_CANDIDATE_CAP")) {
         const long long x = std::atoll(v);
         if (x > 0) return std::max<uint32_t>(floor_k, (uint32_t)std::min<long long>(x, 1ll << 30));
     }
-    return nq == 1 ? (1u << 20) : std::max<uint32_t>(1u << 14, 64u * (uint32_t)kmax);
+    if (nq == 1) return 1u << 20;
+    const uint32_t lo = mode == MESSI_MODE_BF16 ? (1u << 16) : (1u << 14);
+    return std::max<uint32_t>(lo, 64u * (uint32_t)kmax);
 }
 
 int Workspace::ensure_stats() {
@@ -1260,7 +1263,7 @@ struct CallArgs {
 int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap, uint32_t cap_min = 0) {
     const Index* ix = c.ix;
     const int32_t nq = c.nq;
-    cap = std::max(default_cap(nq, c.kmax), cap_min);
+    cap = std::max(default_cap(nq, c.kmax, c.mode), cap_min);
     Workspace* ws = nullptr;
     MESSI_TRY(get_workspace(ix, c.s, nq, cap, &ws));
     *wsp = ws;

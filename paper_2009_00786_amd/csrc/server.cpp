@@ -90,7 +90,7 @@ struct Server {
         *ln.h_err = 0;
         uint32_t cap_min = 0;
         if (ln.batch[0].fp32)
-            cap_min = default_cap(1, kmax) << (4 * ln.batch[0].grow);
+            cap_min = default_cap(1, kmax, MESSI_MODE_FP32) << (4 * ln.batch[0].grow);
         MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, kmax, ln.d_k.as<int32_t>(), ln.mode, ln.s,
                               ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, cap_min));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.h_idx, ln.d_idx.p, sizeof(int64_t) * (size_t)nq * kmax, hipMemcpyDeviceToHost,
