@@ -62,6 +62,10 @@ def _load():
         lib.oracle_knn_brute.restype = ctypes.c_int
         lib.oracle_knn_isax.argtypes = [vp, i64, i32, vp, i32, i32, vp, i64, vp, vp, i32, i32, vp, vp, vp]
         lib.oracle_knn_isax.restype = ctypes.c_int
+        lib.oracle_bf16_round_array.argtypes = [vp, i64, vp]
+        lib.oracle_bf16_filter_values.argtypes = [vp, vp, i64, i32, vp]
+        lib.oracle_bf16_error_bound.argtypes = [d, d, i32, vp]
+        lib.oracle_bf16_error_bound.restype = d
         _lib = lib
     return _lib
 
@@ -191,3 +195,31 @@ def knn_isax(data, words_, card_bits, leaves, pos, queries, k: int, return_stats
         raise ValueError("bad arguments to knn_isax")
     out = (idx, dd, np.sqrt(dd).astype(np.float32))
     return out + (stats,) if return_stats else out
+
+
+def bf16_round(v) -> np.ndarray:
+    """Round fp32 values to BF16 (nearest, ties to even), returned as fp32."""
+    a = _f32(v)
+    out = np.empty_like(a)
+    _load().oracle_bf16_round_array(a.ctypes.data, a.size, out.ctypes.data)
+    return out
+
+
+def bf16_filter_values(q, x) -> np.ndarray:
+    """Filtered squared distance of each row pair (q[i], x[i]) as the BF16
+    filter of the batched search defines it: fl32(fl32(|q|^2 + |x|^2) - 2 s),
+    s the fp32 sum in index order of the exact BF16 products."""
+    q2, x2 = _f32(q), _f32(x)
+    assert q2.shape == x2.shape and q2.ndim == 2
+    out = np.empty(q2.shape[0], dtype=np.float32)
+    _load().oracle_bf16_filter_values(q2.ctypes.data, x2.ctypes.data, q2.shape[0], q2.shape[1], out.ctypes.data)
+    return out
+
+
+def bf16_error_bound(norm2_q: float, norm2_x: float, length: int, terms: bool = False):
+    """Bound E on |f - D| for the BF16 filter (any order and rounding of its
+    fp32 accumulation).  With terms=True also returns the five parts:
+    operands, accumulation, norms, first add, final subtraction."""
+    t = np.zeros(5, dtype=np.float64)
+    e = _load().oracle_bf16_error_bound(float(norm2_q), float(norm2_x), int(length), t.ctypes.data)
+    return (e, t) if terms else e

@@ -26,6 +26,9 @@
  *     region, per segment; MINDIST^2 = m * sum_i d_i^2.
  *   - k-NN answer: the k smallest (D64, index) pairs, D64 the canonical
  *     sequential fp64 squared distance of oracle_d64.
+ *   - BF16 filter of the batched search (beyond the paper): the filtered
+ *     value and its rounding bound E, derived term by term at
+ *     oracle_bf16_error_bound; a member may be discarded only if f - E > U.
  *
  * Parity pins live in tests/ (they compare against the paper's worked word,
  * textbook quantiles, closed forms, invariants and brute force).  Functions
@@ -545,4 +548,86 @@ int oracle_knn_isax(const float* data, int64_t n, int32_t len, const uint8_t* wo
     }
     free(order);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* BF16 filter of the batched search (an extension beyond the paper, whose   */
+/* search computes real distances only).  The filtered squared distance of a */
+/* pair is                                                                   */
+/*   f = fl32(fl32(nq + nx) - 2 s),                                          */
+/*   s = fp32 sum over j = 0 .. len-1, in that order, of the exact products  */
+/*       bf16(q_j) * bf16(x_j)  (8-bit significands: the product is exact    */
+/*       in fp32),                                                           */
+/*   nq = fl32(|q|^2), nx = fl32(|x|^2), each from a sequential fp64 sum,    */
+/* with bf16() rounding to nearest, ties to even.                            */
+/* ------------------------------------------------------------------------ */
+
+float oracle_bf16_round(float v) {
+    uint32_t u;
+    memcpy(&u, &v, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+void oracle_bf16_round_array(const float* in, int64_t n, float* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = oracle_bf16_round(in[i]);
+}
+
+void oracle_bf16_filter_values(const float* q, const float* x, int64_t npairs, int32_t len, float* out) {
+    for (int64_t p = 0; p < npairs; ++p) {
+        const float* qp = q + (size_t)p * (size_t)len;
+        const float* xp = x + (size_t)p * (size_t)len;
+        double a2 = 0.0, b2 = 0.0;
+        float s = 0.0f;
+        for (int j = 0; j < len; ++j) {
+            a2 = a2 + (double)qp[j] * (double)qp[j];
+            b2 = b2 + (double)xp[j] * (double)xp[j];
+            float prod = oracle_bf16_round(qp[j]) * oracle_bf16_round(xp[j]);
+            s = s + prod;
+        }
+        float nsum = (float)a2 + (float)b2;
+        out[p] = nsum - 2.0f * s;
+    }
+}
+
+/* Bound E on |f - D|, D = |q - x|^2 exact, for ANY order and ANY rounding    */
+/* (nearest or directed) of the fp32 accumulation of s.  With a = |q|,        */
+/* b = |x|, u_b = 2^-8 (BF16 unit roundoff), u32 = 2^-24, and               */
+/* gamma_n = n u / (1 - n u) for u = 2^-23 (a directed fp32 rounding has      */
+/* relative error below 2^-23):                                              */
+/*   [0] operands:   2 (2 u_b + u_b^2) a b.  bf16(q_j) bf16(x_j) differs     */
+/*       from q_j x_j by at most (2 u_b + u_b^2) |q_j x_j|; summed, and by   */
+/*       Cauchy-Schwarz sum |q_j x_j| <= a b; doubled by the factor 2 of s.  */
+/*   [1] accumulation: 2 gamma_{len-1} (1 + u_b)^2 a b.  Summing len terms in */
+/*       any order errs by at most gamma_{len-1} sum |p_j| (the standard     */
+/*       recursive-summation bound), and sum |p_j| <= |bf16(q)| |bf16(x)|     */
+/*       <= (1 + u_b)^2 a b; doubled likewise.                              */
+/*   [2] norms:      2 u32 (a^2 + b^2): one rounding of each fp64 norm to    */
+/*       fp32, plus as much again covering the fp64 sums' own error.         */
+/*   [3] first add:  u32 (a^2 + b^2) (1 + 2 u32).                            */
+/*   [4] final subtraction: 2 u32 (a + b)^2, since |nq + nx - 2 s| is at most */
+/*       (a + b)^2 times a factor below 2.                                   */
+/* E = [0] + [1] + [2] + [3] + [4] in fp64, i.e.                              */
+/*   (4 u_b + 2 u_b^2 + 2 gamma (1 + u_b)^2) a b + 3 u32 (a^2 + b^2)          */
+/*   + 2 u32 (a + b)^2  (to first order).                                    */
+double oracle_bf16_error_bound(double a2, double b2, int32_t len, double* terms) {
+    const double ub = ldexp(1.0, -8), u32 = ldexp(1.0, -24), u = ldexp(1.0, -23);
+    const double nu = (double)(len > 1 ? len - 1 : 0) * u;
+    const double gamma = nu / (1.0 - nu);
+    const double a = sqrt(a2), b = sqrt(b2);
+    double t[5];
+    t[0] = 2.0 * (2.0 * ub + ub * ub) * a * b;
+    t[1] = 2.0 * gamma * (1.0 + ub) * (1.0 + ub) * a * b;
+    t[2] = 2.0 * u32 * (a2 + b2);
+    t[3] = u32 * (a2 + b2) * (1.0 + 2.0 * u32);
+    t[4] = 2.0 * u32 * (a + b) * (a + b);
+    double e = 0.0;
+    for (int i = 0; i < 5; ++i) {
+        if (terms) terms[i] = t[i];
+        e = e + t[i];
+    }
+    return e;
 }

@@ -2,28 +2,26 @@
 // search exact, then a compensated fp32 recheck of the survivors.
 //
 // For a batch of queries, the (query, leaf) pairs that survive the leaf bound
-// are grouped by leaf.  A wave holds the BF16 rows of 16 members of a leaf in
-// registers (the B operand) and streams 16-query tiles of the leaf's queries
-// from LDS (the A operand) through mfma_f32_16x16x32_bf16, so a member row is
-// read from HBM once per leaf whatever the number of queries that visit it.
-// For every (query q, member x) it forms
-//     f = fl(fl(|q|^2 + |x|^2) - 2 s),   s = sum_j bf16(q_j) bf16(x_j) (fp32 accumulation)
-// and discards x for q only if f - E(q, x) > U_q, where E bounds |f - D| for the
-// exact squared distance D = |q - x|^2:
-//   - operand rounding to BF16 (unit roundoff u_b = 2^-8):
-//       |sum bf16(q_j) bf16(x_j) - q.x| <= (2 u_b + u_b^2) |q| |x|   (Cauchy-Schwarz)
-//   - fp32 accumulation of L exact products in any order, u = 2^-23 so that
-//     non-nearest or unknown rounding inside the unit is covered:
-//       <= gamma_{L-1} (1 + u_b)^2 |q| |x|,   gamma_n = n u / (1 - n u)
-//   - the squared norms are fp32 roundings of fp64 sums (u32 = 2^-24 each), and
-//     the final add and subtract round once each:
-//       <= 3 u32 (|q|^2 + |x|^2) + 2 u32 (|q| + |x|)^2
-//   so E = (4 u_b + 2 u_b^2 + 2 gamma_{L-1} (1 + u_b)^2) |q||x| + 3 u32 (|q|^2 + |x|^2)
-//          + 2 u32 (|q| + |x|)^2, evaluated in fp32 and scaled by (1 + 2^-20).
-// A discarded member has D >= f - E > U_q >= the k-th true distance, so it is
-// not an answer.  Survivors get a Neumaier-compensated fp32 distance (relative
-// error ~3 u32), which feeds the same candidate/bound logic as the fp32 scan;
-// the final order uses the canonical fp64 distance.
+// are grouped by leaf.  A block stages a leaf's queries in LDS as BF16 rows
+// (the A operand); each of its waves holds the BF16 rows of 64 of the leaf's
+// members in registers (the B operand), so a member row is read from HBM once
+// per leaf and round whatever the number of queries that visit the leaf.
+// For every (query q, member x) the filter evaluates
+//     f = |q|^2 + |x|^2 - 2 s,   s = sum_j bf16(q_j) bf16(x_j)  (fp32 accumulation)
+// and may discard x for q only if f - E(q, x) > U_q, where E bounds |f - D| for
+// the exact squared distance D = |q - x|^2:
+//   - operand rounding to BF16 (unit roundoff u_b = 2^-8), by Cauchy-Schwarz:
+//       |sum bf16(q_j) bf16(x_j) - q.x| <= (2 u_b + u_b^2) |q| |x|
+//   - fp32 accumulation in any order and rounding (u = 2^-23):
+//       <= gamma_{K-1} (1 + u_b)^2 |q| |x|,   gamma_n = n u / (1 - n u)
+//   - the norms are fp32 roundings of fp64 sums, and the remaining operations
+//     round once each: covered by relative slacks of 2^-20 on |q|^2, |x|^2, U.
+// The filter kernel folds this test into its MFMA chain (one extra k-step, see
+// there), so the whole drop decision is one compare per (query, member).  A
+// discarded member has D > U_q >= the k-th true distance, so it is not an
+// answer.  Survivors get a Neumaier-compensated fp32 distance (relative error
+// ~3 u32), which feeds the same candidate/bound logic as the fp32 scan; the
+// final order uses the canonical fp64 distance.
 #include <algorithm>
 #include <cmath>
 #include <vector>
