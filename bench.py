@@ -121,11 +121,13 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=None, help="override the collection size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=4_000_000)
-    ap.add_argument("--cpu-queries", type=int, default=8)
+    ap.add_argument("--cpu-rows", type=int, default=12_000_000)
+    ap.add_argument("--cpu-queries", type=int, default=100)
     ap.add_argument("--duration", type=float, default=10.0, help="seconds of arrivals per rate (configs 4, 5)")
     ap.add_argument("--rates", type=str, default=None, help="comma-separated arrival rates (configs 4, 5)")
     ap.add_argument("--no-fifo", action="store_true", help="skip the fp32 FIFO comparison (configs 4, 5)")
+    ap.add_argument("--variants", action="store_true",
+                    help="also serve with BF16 batches only, and without HIP graphs (configs 4, 5)")
     ap.add_argument("--no-fp32-batch", action="store_true",
                     help="skip the fp32 batched comparison call (config 3), e.g. under a profiler")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -545,7 +547,13 @@ def bench_serving(args):
     budget = 8 << 30
     out = {}
     results = {}
-    modes = [("bf16_server", messi.MODE_BF16, 256)] + ([] if args.no_fifo else [("fp32_fifo", messi.MODE_FP32, 1)])
+    modes = [("bf16_server", messi.MODE_BF16, 256)]
+    if args.variants:
+        # the same server with one of its two latency devices switched off
+        modes += [("bf16_batch_only", messi.MODE_BF16 | messi.SERVER_BATCH_ONLY, 256),
+                  ("bf16_no_graphs", messi.MODE_BF16 | messi.SERVER_NO_GRAPHS, 256)]
+    if not args.no_fifo:
+        modes += [("fp32_fifo", messi.MODE_FP32, 1)]
     for name, mode, slots in modes:
         out[name] = {}
         for r in rates:
@@ -553,10 +561,12 @@ def bench_serving(args):
             sv = messi.Server(ix, budget, slots, mode)
             try:
                 lat, got, in_window, bad = open_loop(sv, qs[off:off + len(a)], ks[off:off + len(a)], a, 5.0)
+                sst = sv.stats()
             finally:
                 sv.close()
             summ = latency_summary(lat, float(a[-1]), in_window)
             summ["errors"] = bad
+            summ["server"] = sst
             out[name][str(int(r))] = summ
             results[(name, r)] = got
             log("%s at %g/s: %s" % (name, r, summ))
@@ -592,7 +602,8 @@ def bench_serving(args):
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "len": length, "segments": 16, "card_bits": 8, "leaf_cap": 2000,
                    "rates": rates, "duration_s": args.duration, "headline_rate": r_head, "budget_bytes": budget,
-                   "mode": "BF16 continuous-batching server (256 slots over 4 streams)"},
+                   "mode": "BF16 continuous-batching server (256 slots over 4 streams; batches replayed as HIP "
+                           "graphs; a lone waiting query runs alone in FP32 mode)"},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "serving": out,
         "alone_vs_mix": {"sample": len(sample), "mismatches": mism_alone},

@@ -201,21 +201,31 @@ typedef struct {
     float dist[MESSI_MAX_K];
 } messi_result;
 
+/* Server mode flags, OR-ed into `mode` of messi_server_create. */
+#define MESSI_SERVER_BATCH_ONLY 0x100 /* BF16: never answer a lone waiting query alone in FP32 mode */
+#define MESSI_SERVER_NO_GRAPHS 0x200  /* enqueue every launch eagerly instead of replaying HIP graphs */
+
 /* A request loop that keeps `index` on the device and answers exact k-NN
  * queries with continuous batching (an extension beyond the paper, which
  * answers queries one after another, Section 5).  Queries submitted while
  * others run are admitted into free slots as soon as a slot frees up and
  * share batched launches; the slots are spread over up to four lanes, each a
- * HIP stream with its own workspace, that run concurrently.  A result never
+ * HIP stream with its own workspace, that run concurrently.  A lane's launch
+ * is recorded once per batch shape into a HIP graph and replayed afterwards.
+ * In BF16 mode, a query that is alone in the queue when a lane frees up is
+ * answered by itself in FP32 mode (unless MESSI_SERVER_BATCH_ONLY), since a
+ * batch of one gains nothing from the matrix-core filter.  A result never
  * depends on which queries shared its batch: each query carries its own
  * status, and a query whose BF16 buffers overflow is answered again, alone,
  * in FP32 mode before its result is posted.
  *   budget_bytes  device memory the server may use for per-query state; the
  *                 slot count is min(max_slots, budget_bytes / per-query need)
- *   mode          MESSI_MODE_FP32 or MESSI_MODE_BF16 (needs the BF16 shadow)
- * Returns NULL on error: MESSI_EINVAL (null index, max_slots < 1, bad mode,
- * BF16 without a shadow), MESSI_ENOMEM (budget below one query's need, or an
- * allocation failed), MESSI_EDEVICE.  The index must outlive the server. */
+ *   mode          MESSI_MODE_FP32 or MESSI_MODE_BF16 (needs the BF16 shadow),
+ *                 optionally OR-ed with MESSI_SERVER_* flags
+ * Returns NULL on error: MESSI_EINVAL (null index, max_slots < 1, bad mode or
+ * flags, BF16 without a shadow), MESSI_ENOMEM (budget below one query's need,
+ * or an allocation failed), MESSI_EDEVICE.  The index must outlive the
+ * server. */
 messi_server* messi_server_create(const messi_index* index, size_t budget_bytes, int32_t max_slots, int32_t mode);
 
 /* Copy host_query[len] (host memory, the index's length) and enqueue it.
@@ -226,6 +236,21 @@ int messi_server_submit(messi_server* server, const float* host_query, int32_t k
 /* Move up to max_out finished results into out (host array, caller-owned);
  * returns how many (>= 0) or MESSI_EINVAL.  Results come in completion order. */
 int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out);
+
+typedef struct {
+    int64_t batches;          /* launches (a batch, or one query alone) */
+    int64_t bf16_batches;     /* of which in BF16 mode */
+    int64_t solo_fp32;        /* lone queries answered alone in FP32 mode */
+    int64_t requeued;         /* queries re-queued after a buffer overflow */
+    int64_t eager_launches;   /* launches enqueued operation by operation */
+    int64_t graphs_recorded;  /* launches recorded into a new HIP graph (then replayed) */
+    int64_t graph_replays;    /* launches that replayed a recorded graph */
+    int32_t lanes, batch;     /* lanes and queries per lane */
+} messi_server_counters;
+
+/* Counters of the server so far (host struct, caller-owned).  MESSI_OK or
+ * MESSI_EINVAL (null argument). */
+int messi_server_stats(messi_server* server, messi_server_counters* out);
 
 /* Milliseconds on the server clock (the one t_submit_ms / t_done_ms use). */
 double messi_server_clock_ms(const messi_server* server);

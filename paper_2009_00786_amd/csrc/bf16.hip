@@ -27,7 +27,6 @@
 #include <vector>
 
 #include "query.h"
-#include "scan.h"
 
 namespace messi {
 namespace {
@@ -136,10 +135,10 @@ struct BfArgs {
     const uint32_t* leaf_cnt;
     const uint32_t* leaf_off;
     const uint32_t* leaf_q;
+    const uint32_t* leaf_act;  // the round's leaves with at least one query
     uint2* pairs;           // (query, member position)
-    uint32_t* npairs;
+    uint32_t* npairs;       // round counters: survivors, next active leaf, active leaves, slots
     uint32_t pairs_cap;
-    uint32_t* work;         // next leaf of the filter (zero at the start of a round)
     int32_t qc;             // queries of a leaf staged in LDS at a time (multiple of 16)
     float one_minus_h;      // 1 - h, rounded down
 };
@@ -182,12 +181,39 @@ __device__ __forceinline__ bool round_leaf(const QArgs& a, int q, uint32_t t, ui
     return !(a.lb[(size_t)q * a.nL + leaf] * (1.0f - kRhoLb) > U);
 }
 
+// The round's counters: [0] filter survivors, [1] next active leaf of the
+// filter, [2] active leaves, [3] query slots handed out.  Words, not a memset,
+// so that the whole round can be recorded in a graph.
+__global__ void __launch_bounds__(256) round_reset_kernel(uint32_t* __restrict__ leaf_cnt, uint32_t nL,
+                                                          uint32_t* __restrict__ ctr) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nL; i += gridDim.x * 256) leaf_cnt[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 4) ctr[threadIdx.x] = 0;
+}
+
+// Count the queries of every leaf; the first query to reach a leaf appends it
+// to the round's list of active leaves.
 __global__ void __launch_bounds__(256) leaf_count_kernel(QArgs a, uint32_t t0, uint32_t t1,
-                                                         uint32_t* __restrict__ leaf_cnt) {
+                                                         uint32_t* __restrict__ leaf_cnt,
+                                                         uint32_t* __restrict__ leaf_act, uint32_t* __restrict__ ctr) {
     const int q = blockIdx.y;
     const uint32_t t = t0 + blockIdx.x * 256 + threadIdx.x;
     uint32_t leaf;
-    if (round_leaf(a, q, t, t1, leaf)) atomicAdd(&leaf_cnt[leaf], 1u);
+    if (round_leaf(a, q, t, t1, leaf) && atomicAdd(&leaf_cnt[leaf], 1u) == 0u)
+        leaf_act[atomicAdd(&ctr[2], 1u)] = leaf;
+}
+
+// Each active leaf takes a contiguous run of query slots (runs in no
+// particular order) and resets its fill cursor.
+__global__ void __launch_bounds__(256) leaf_offsets_kernel(const uint32_t* __restrict__ leaf_cnt,
+                                                           const uint32_t* __restrict__ leaf_act,
+                                                           uint32_t* __restrict__ leaf_off,
+                                                           uint32_t* __restrict__ leaf_cur, uint32_t* __restrict__ ctr) {
+    const uint32_t nact = ctr[2];
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nact; i += gridDim.x * 256) {
+        const uint32_t leaf = leaf_act[i];
+        leaf_off[leaf] = atomicAdd(&ctr[3], leaf_cnt[leaf]);
+        leaf_cur[leaf] = 0;
+    }
 }
 
 __global__ void __launch_bounds__(256) leaf_scatter_kernel(QArgs a, uint32_t t0, uint32_t t1,
@@ -261,14 +287,15 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
     const int col = lane & 15, kb = lane >> 4;
     const float h1 = bf.one_minus_h;
     unsigned long long c_eval = 0, c_bytes = 0;
+    const uint32_t nact = bf.npairs[2];
     for (;;) {
         __syncthreads();  // every wave is done with the previous leaf's LDS
-        if (tid == 0) s_leaf = atomicAdd(bf.work, 1u);
+        if (tid == 0) s_leaf = atomicAdd(&bf.npairs[1], 1u);
         __syncthreads();
-        const uint32_t leaf = s_leaf;
-        if (leaf >= (uint32_t)a.nL) break;
+        const uint32_t li = s_leaf;
+        if (li >= nact) break;
+        const uint32_t leaf = bf.leaf_act[li];
         const uint32_t cntq = bf.leaf_cnt[leaf];
-        if (cntq == 0) continue;
         const Leaf lf = a.leaves[leaf];
         const uint32_t qoff = bf.leaf_off[leaf];
         for (uint32_t qc0 = 0; qc0 < cntq; qc0 += QC) {
@@ -439,7 +466,7 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
             c_eval += __shfl_xor(c_eval, off);
             c_bytes += __shfl_xor(c_bytes, off);
         }
-        if (lane == 0) {
+        if (lane == 0 && c_eval) {
             atomicAdd(&a.counters->distance, c_eval);
             atomicAdd(&a.counters->bytes, c_bytes);
         }
@@ -516,7 +543,7 @@ __global__ void __launch_bounds__(256) bf16_recheck_kernel(QArgs a, BfArgs bf) {
             c_re += __shfl_xor(c_re, off);
             c_bytes += __shfl_xor(c_bytes, off);
         }
-        if (lane == 0) {
+        if (lane == 0 && c_re) {
             atomicAdd(&a.counters->recheck, c_re);
             atomicAdd(&a.counters->bytes, c_bytes);
         }
@@ -584,8 +611,9 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         MESSI_TRY(ws->leaf_q.alloc(sizeof(uint32_t) * leafq_cap));
         MESSI_TRY(ws->pairs.alloc(sizeof(uint2) * pairs_cap));
         MESSI_TRY(ws->npairs.alloc(sizeof(uint32_t) * 4));
-        MESSI_TRY(ws->scan_scr.alloc(sizeof(uint32_t) * scan_scratch_words((int64_t)nL + 1)));
+        MESSI_TRY(ws->leaf_act.alloc(sizeof(uint32_t) * (nL + 1)));
         ws->bf_nq = nq;
+        ++ws->gen;
         ws->bf_pairs_cap = pairs_cap;
         ws->bf_leafq_cap = leafq_cap;
     }
@@ -605,7 +633,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     bf.npairs = ws->npairs.as<uint32_t>();
     bf.pairs_cap = (uint32_t)pairs_cap;
     bf.one_minus_h = std::nextafter((float)(1.0 - kc.h), 0.0f);
-    bf.work = ws->npairs.as<uint32_t>() + 1;
+    bf.leaf_act = ws->leaf_act.as<uint32_t>();
     // queries staged per leaf: as many as the LDS of one block holds (at most 256)
     int lds_max = 65536;
     (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device);
@@ -643,13 +671,16 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         t1 = std::min<uint64_t>(kRoundEnds[std::min(round, 2)], (uint64_t)nL);
         const unsigned tbr = (unsigned)((t1 - t0 + 255) / 256);
         const uint32_t r0 = (uint32_t)t0, r1 = (uint32_t)t1;
-        MESSI_HIP_TRY(hipMemsetAsync(ws->leaf_cnt.p, 0, sizeof(uint32_t) * (nL + 1), s));
-        MESSI_HIP_TRY(hipMemsetAsync(ws->leaf_cur.p, 0, sizeof(uint32_t) * (nL + 1), s));
-        MESSI_HIP_TRY(hipMemsetAsync(ws->npairs.p, 0, sizeof(uint32_t) * 4, s));
-        hipLaunchKernelGGL(leaf_count_kernel, dim3(tbr, nq), dim3(256), 0, s, a, r0, r1, ws->leaf_cnt.as<uint32_t>());
+        hipLaunchKernelGGL(round_reset_kernel, dim3((unsigned)std::min<size_t>((nL + 255) / 256, 1024)), dim3(256), 0,
+                           s, ws->leaf_cnt.as<uint32_t>(), (uint32_t)nL, ws->npairs.as<uint32_t>());
+        MESSI_LAUNCH_CHECK("round_reset");
+        hipLaunchKernelGGL(leaf_count_kernel, dim3(tbr, nq), dim3(256), 0, s, a, r0, r1, ws->leaf_cnt.as<uint32_t>(),
+                           ws->leaf_act.as<uint32_t>(), ws->npairs.as<uint32_t>());
         MESSI_LAUNCH_CHECK("leaf_count");
-        MESSI_TRY(scan_exclusive(ws->leaf_cnt.as<uint32_t>(), ws->leaf_off.as<uint32_t>(), (int64_t)nL,
-                                 ws->scan_scr.as<uint32_t>(), nullptr, s));
+        hipLaunchKernelGGL(leaf_offsets_kernel, dim3((unsigned)std::min<size_t>((nL + 255) / 256, 256)), dim3(256), 0,
+                           s, ws->leaf_cnt.as<uint32_t>(), ws->leaf_act.as<uint32_t>(), ws->leaf_off.as<uint32_t>(),
+                           ws->leaf_cur.as<uint32_t>(), ws->npairs.as<uint32_t>());
+        MESSI_LAUNCH_CHECK("leaf_offsets");
         hipLaunchKernelGGL(leaf_scatter_kernel, dim3(tbr, nq), dim3(256), 0, s, a, r0, r1,
                            ws->leaf_off.as<uint32_t>(), ws->leaf_cur.as<uint32_t>(), ws->leaf_q.as<uint32_t>(),
                            leafq_cap);

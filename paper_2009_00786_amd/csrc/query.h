@@ -101,6 +101,7 @@ struct QArgs {
 
 // Per-(index, stream) search workspace, grown on demand.
 struct Workspace {
+    uint64_t gen = 0;  // bumped whenever a buffer is reallocated (recorded graphs hold the old addresses)
     int32_t nq = 0, nL = 0;
     size_t cand_slots = 0;  // candidate slots over all queries (a call uses nq * cap of them)
     uint32_t max_chunks = 0;
@@ -110,7 +111,7 @@ struct Workspace {
     // BF16 path
     int32_t bf_nq = 0;
     size_t bf_pairs_cap = 0, bf_leafq_cap = 0;
-    DevBuf qb, qnorm, qx, leaf_cnt, leaf_off, leaf_cur, leaf_q, pairs, npairs, scan_scr;
+    DevBuf qb, qnorm, qx, leaf_cnt, leaf_off, leaf_cur, leaf_q, leaf_act, pairs, npairs;
     // timing of the BF16 kernels of the last call (filled when timing is on)
     double bf_ms_filter = 0, bf_ms_recheck = 0;
     int bf_rounds = 0, bf_stage_queries = 0;
@@ -148,5 +149,8 @@ int query_error_code(uint32_t status);
 
 // Device bytes of search workspace one query needs (for a memory budget).
 size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap);
+
+// Generation of the (index, stream) workspace, 0 if there is none yet.
+uint64_t workspace_generation(const Index* ix, hipStream_t s);
 
 }  // namespace messi

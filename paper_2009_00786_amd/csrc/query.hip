@@ -1184,11 +1184,13 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
         ws->nq = nqa;
         ws->nL = (int32_t)nL;
         ws->max_chunks = mc;
+        ++ws->gen;
     }
     if (ws->cand_slots < slots) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         MESSI_TRY(ws->cand.alloc(sizeof(Cand) * slots));
         ws->cand_slots = slots;
+        ++ws->gen;
     }
     *out = ws;
     return MESSI_OK;
@@ -1223,6 +1225,12 @@ int refresh_bounds(QArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(refresh_kernel, dim3(a.nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("refresh");
     return MESSI_OK;
+}
+
+uint64_t workspace_generation(const Index* ix, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({ix, s});
+    return it == g_ws.end() ? 0 : it->second->gen;
 }
 
 void release_workspace(const Index* ix, hipStream_t st) {

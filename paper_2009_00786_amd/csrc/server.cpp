@@ -9,13 +9,28 @@
 // admitted as soon as a lane frees up and their work overlaps on the device.
 // The lane count and batch size follow from the device-memory budget: every
 // admitted query holds its share of a lane's workspace until it completes.
+//
+// In BF16 mode a lone waiting query (the queue holds at most one when a lane
+// frees up) is answered by itself in FP32 mode: a batch of one gains nothing
+// from the matrix-core filter, whose cost is a pass over the BF16 rows of
+// every leaf the query visits, while the FP32 scan bounds each member by its
+// word first.  As soon as queries queue up they go in BF16 batches.
+//
+// A lane's whole launch (copies in, the search, copies out) is recorded once
+// per batch shape (query count, largest k, mode, buffer size) into a HIP graph
+// and replayed afterwards: the first batch of a shape runs eagerly, which
+// also sizes the workspace, the second records the graph.  A graph is dropped
+// when the workspace it points into is reallocated.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
+#include <set>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -36,12 +51,26 @@ struct Pending {
     int grow = 0;       // its candidate buffer is 16^grow times the default
 };
 
+// A recorded launch: the shape it was recorded for decides everything the
+// launch does (grids, buffer sizes); the lane's buffers are fixed.
+typedef std::tuple<int32_t, int32_t, int32_t, uint32_t> Shape;  // nq, kmax, mode, cap_min
+
+struct Recorded {
+    hipGraphExec_t exec = nullptr;
+    uint64_t gen = 0;  // workspace generation it was recorded against
+};
+
+constexpr size_t kMaxGraphsPerLane = 256;
+
 struct Lane {
     hipStream_t s = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
+    bool solo = false;               // the batch is one query answered in FP32 mode
     int32_t kmax = 0;
     int32_t mode = MESSI_MODE_BF16;  // of the batch in flight
+    std::set<Shape> seen;            // shapes run eagerly once
+    std::map<Shape, Recorded> graphs;
     DevBuf d_q, d_k, d_idx, d_dist;
     float* h_q = nullptr;
     int32_t* h_k = nullptr;
@@ -59,7 +88,10 @@ constexpr size_t kMaxPending = 1u << 20;
 struct Server {
     const Index* ix = nullptr;
     int32_t mode = MESSI_MODE_BF16;
+    bool solo_fp32 = true;  // BF16 mode: a lone waiting query runs alone in FP32 mode
+    bool use_graphs = true;
     int32_t batch = 1;  // queries per lane
+    messi_server_counters stats{};  // guarded by mu
     std::vector<Lane> lanes;
     std::mutex mu;
     std::condition_variable cv;
@@ -74,6 +106,50 @@ struct Server {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
 
+    // The lane's launch as stream operations: copies in, the search, copies out.
+    int enqueue(Lane& ln, int32_t nq, uint32_t cap_min) {
+        const int L = ix->len;
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.d_q.p, ln.h_q, sizeof(float) * (size_t)nq * L, hipMemcpyHostToDevice, ln.s));
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.d_k.p, ln.h_k, sizeof(int32_t) * (size_t)nq, hipMemcpyHostToDevice, ln.s));
+        MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, ln.kmax, ln.d_k.as<int32_t>(), ln.mode, ln.s,
+                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, cap_min));
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.h_idx, ln.d_idx.p, sizeof(int64_t) * (size_t)nq * ln.kmax,
+                                     hipMemcpyDeviceToHost, ln.s));
+        MESSI_HIP_TRY(hipMemcpyAsync(ln.h_dist, ln.d_dist.p, sizeof(float) * (size_t)nq * ln.kmax,
+                                     hipMemcpyDeviceToHost, ln.s));
+        return MESSI_OK;
+    }
+
+    static void drop_graph(Recorded& r) {
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        r.exec = nullptr;
+    }
+
+    // Record the lane's launch for this shape; false (and the stream left as it
+    // was) if recording is not possible, then the caller runs it eagerly.
+    bool record(Lane& ln, int32_t nq, uint32_t cap_min, Recorded& out) {
+        if (hipStreamBeginCapture(ln.s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        const int rc = enqueue(ln, nq, cap_min);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ln.s, &g);
+        hipGraphExec_t exec = nullptr;
+        bool ok = rc == MESSI_OK && ec == hipSuccess && g &&
+                  hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+            (void)hipGetLastError();
+            clear_error();
+            if (exec) (void)hipGraphExecDestroy(exec);
+            return false;
+        }
+        out.exec = exec;
+        out.gen = workspace_generation(ix, ln.s);
+        return true;
+    }
+
     int launch(Lane& ln) {
         const int L = ix->len;
         const int32_t nq = (int32_t)ln.batch.size();
@@ -84,21 +160,49 @@ struct Server {
             kmax = std::max(kmax, ln.batch[i].k);
         }
         ln.kmax = kmax;
-        ln.mode = ln.batch[0].fp32 ? MESSI_MODE_FP32 : mode;
-        MESSI_HIP_TRY(hipMemcpyAsync(ln.d_q.p, ln.h_q, sizeof(float) * (size_t)nq * L, hipMemcpyHostToDevice, ln.s));
-        MESSI_HIP_TRY(hipMemcpyAsync(ln.d_k.p, ln.h_k, sizeof(int32_t) * (size_t)nq, hipMemcpyHostToDevice, ln.s));
+        ln.mode = (ln.batch[0].fp32 || ln.solo) ? MESSI_MODE_FP32 : mode;
         *ln.h_err = 0;
         uint32_t cap_min = 0;
         if (ln.batch[0].fp32)
             cap_min = default_cap(1, kmax, MESSI_MODE_FP32) << (4 * ln.batch[0].grow);
-        MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, kmax, ln.d_k.as<int32_t>(), ln.mode, ln.s,
-                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, cap_min));
-        MESSI_HIP_TRY(hipMemcpyAsync(ln.h_idx, ln.d_idx.p, sizeof(int64_t) * (size_t)nq * kmax, hipMemcpyDeviceToHost,
-                                     ln.s));
-        MESSI_HIP_TRY(hipMemcpyAsync(ln.h_dist, ln.d_dist.p, sizeof(float) * (size_t)nq * kmax, hipMemcpyDeviceToHost,
-                                     ln.s));
+        const Shape shape{nq, kmax, ln.mode, cap_min};
+        bool replayed = false, recorded = false;
+        if (use_graphs) {
+            auto it = ln.graphs.find(shape);
+            if (it != ln.graphs.end() && it->second.gen != workspace_generation(ix, ln.s)) {
+                // the workspace moved since the recording: drop every graph of the lane
+                for (auto& kv : ln.graphs) drop_graph(kv.second);
+                ln.graphs.clear();
+                ln.seen.clear();
+                it = ln.graphs.end();
+            }
+            if (it == ln.graphs.end() && ln.seen.count(shape) && ln.graphs.size() < kMaxGraphsPerLane) {
+                Recorded r;
+                if (record(ln, nq, cap_min, r)) {
+                    it = ln.graphs.emplace(shape, r).first;
+                    recorded = true;
+                }
+            }
+            if (it != ln.graphs.end()) {
+                MESSI_HIP_TRY(hipGraphLaunch(it->second.exec, ln.s));
+                replayed = !recorded;
+            }
+        }
+        if (!replayed && !recorded) {
+            MESSI_TRY(enqueue(ln, nq, cap_min));
+            ln.seen.insert(shape);
+        }
         MESSI_HIP_TRY(hipEventRecord(ln.done, ln.s));
         ln.busy = true;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stats.batches += 1;
+            if (ln.mode == MESSI_MODE_BF16) stats.bf16_batches += 1;
+            if (ln.solo) stats.solo_fp32 += 1;
+            if (recorded) stats.graphs_recorded += 1;
+            if (replayed) stats.graph_replays += 1;
+            if (!recorded && !replayed) stats.eager_launches += 1;
+        }
         return MESSI_OK;
     }
 
@@ -111,11 +215,13 @@ struct Server {
         const double t = now_ms();
         std::vector<messi_result*> out;
         std::vector<Pending> redo;
+        int64_t fallbacks = 0;
         out.reserve(ln.batch.size());
         for (size_t i = 0; i < ln.batch.size(); ++i) {
             const int status = launch_status != MESSI_OK ? launch_status : query_error_code(ln.h_status[i]);
             if (status == MESSI_EOVERFLOW && (!ln.batch[i].fp32 || ln.batch[i].grow < 2)) {
                 Pending p = std::move(ln.batch[i]);
+                fallbacks += 1;
                 if (!p.fp32) {
                     p.fp32 = true;
                     p.grow = ln.mode == MESSI_MODE_FP32 ? 1 : 0;
@@ -143,6 +249,7 @@ struct Server {
         ln.batch.clear();
         ln.busy = false;
         std::lock_guard<std::mutex> lk(mu);
+        stats.requeued += fallbacks;
         for (auto* r : out) ready.push_back(r);
         for (auto it = redo.rbegin(); it != redo.rend(); ++it) pending.push_front(std::move(*it));
     }
@@ -163,14 +270,16 @@ struct Server {
             for (auto& ln : lanes) {
                 if (ln.busy) continue;
                 {
-                    // a batch of BF16 queries, or one FP32 query on its own
+                    // a batch, or one query on its own in FP32 mode: a re-queued
+                    // one, or (BF16 mode) the only query waiting
                     std::lock_guard<std::mutex> lk(mu);
+                    ln.solo = solo_fp32 && pending.size() == 1 && !pending.front().fp32;
                     while (!pending.empty() && (int32_t)ln.batch.size() < batch) {
                         const bool alone = pending.front().fp32;
                         if (alone && !ln.batch.empty()) break;
                         ln.batch.push_back(std::move(pending.front()));
                         pending.pop_front();
-                        if (alone) break;
+                        if (alone || ln.solo) break;
                     }
                 }
                 if (ln.batch.empty()) {
@@ -197,6 +306,7 @@ struct Server {
 
     ~Server() {
         for (auto& ln : lanes) {
+            for (auto& kv : ln.graphs) drop_graph(kv.second);
             if (ln.s) {
                 (void)hipStreamSynchronize(ln.s);
                 release_workspace(ix, ln.s);
@@ -235,7 +345,10 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
         set_error(MESSI_EINVAL, "max_slots must be >= 1");
         return nullptr;
     }
-    if (mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16) {
+    const int32_t flags = mode & ~0xff;
+    mode &= 0xff;
+    if ((mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16) ||
+        (flags & ~(MESSI_SERVER_BATCH_ONLY | MESSI_SERVER_NO_GRAPHS))) {
         set_error(MESSI_EINVAL, "unknown mode");
         return nullptr;
     }
@@ -254,6 +367,8 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     Server* sv = new Server();
     sv->ix = ix;
     sv->mode = mode;
+    sv->solo_fp32 = mode == MESSI_MODE_BF16 && !(flags & MESSI_SERVER_BATCH_ONLY);
+    sv->use_graphs = !(flags & MESSI_SERVER_NO_GRAPHS);
     sv->device = ix->device;
     const int nl = std::min(4, slots);
     sv->batch = (slots + nl - 1) / nl;
@@ -360,6 +475,20 @@ int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out) 
         delete r;
     }
     return n;
+}
+
+int messi_server_stats(messi_server* server, messi_server_counters* out) {
+    clear_error();
+    if (!server || !out) {
+        set_error(MESSI_EINVAL, "null argument");
+        return MESSI_EINVAL;
+    }
+    Server* sv = reinterpret_cast<Server*>(server);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *out = sv->stats;
+    out->lanes = (int32_t)sv->lanes.size();
+    out->batch = sv->batch;
+    return MESSI_OK;
 }
 
 double messi_server_clock_ms(const messi_server* server) {

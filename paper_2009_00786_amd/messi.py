@@ -23,12 +23,14 @@ MESSI_EBUSY = -5
 MESSI_EOVERFLOW = -6
 MODE_FP32 = 0
 MODE_BF16 = 1
+SERVER_BATCH_ONLY = 0x100  # OR into a server mode: no lone FP32 queries in BF16 mode
+SERVER_NO_GRAPHS = 0x200   # OR into a server mode: eager launches, no HIP graphs
 MAX_K = 1024
 
 EXPORTED = [
     "messi_build", "messi_build_ex", "messi_knn", "messi_knn_ex", "messi_free", "messi_index_info",
     "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_breakpoints", "messi_last_error",
-    "messi_server_create", "messi_server_submit", "messi_server_poll", "messi_server_clock_ms",
+    "messi_server_create", "messi_server_submit", "messi_server_poll", "messi_server_stats", "messi_server_clock_ms",
     "messi_server_destroy",
 ]
 
@@ -78,6 +80,13 @@ class KnnStats(ctypes.Structure):
                 ("bf16_stage_queries", ctypes.c_int32)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("bf16_batches", ctypes.c_int64), ("solo_fp32", ctypes.c_int64),
+                ("requeued", ctypes.c_int64), ("eager_launches", ctypes.c_int64),
+                ("graphs_recorded", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
+                ("lanes", ctypes.c_int32), ("batch", ctypes.c_int32)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("k", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("t_submit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
@@ -123,6 +132,8 @@ def load():
         lib.messi_server_submit.restype = ctypes.c_int
         lib.messi_server_poll.argtypes = [vp, ctypes.POINTER(Result), i32]
         lib.messi_server_poll.restype = ctypes.c_int
+        lib.messi_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        lib.messi_server_stats.restype = ctypes.c_int
         lib.messi_server_clock_ms.argtypes = [vp]
         lib.messi_server_clock_ms.restype = ctypes.c_double
         lib.messi_server_destroy.argtypes = [vp]
@@ -272,6 +283,11 @@ class Server:
 
     def clock_ms(self) -> float:
         return load().messi_server_clock_ms(self._h)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().messi_server_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

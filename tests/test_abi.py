@@ -55,6 +55,13 @@ def test_breakpoints_bad_bits(lib):
     assert code == lib.MESSI_EINVAL and "null" in msg
 
 
+def test_server_stats_rejects_null(lib):
+    m = lib.load()
+    st = lib.ServerStats()
+    assert m.messi_server_stats(None, ctypes.byref(st)) == lib.MESSI_EINVAL
+    assert m.messi_server_stats(None, None) == lib.MESSI_EINVAL
+
+
 def test_argument_validation_without_device(lib):
     m = lib.load()
     # null series / bad sizes are rejected before any device call

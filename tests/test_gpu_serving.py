@@ -116,3 +116,59 @@ def test_bf16_server_needs_shadow(torch_cuda, messi):
         messi.Server(ix, 1 << 28, 4, messi.MODE_BF16)
     assert e.value.code == messi.MESSI_EINVAL
     ix.close()
+
+
+def _wave(sv, q, ks, tags):
+    for i, t in enumerate(tags):
+        sv.submit(q[i], int(ks[i]), t)
+    got = {}
+    t_end = time.time() + 60
+    while len(got) < len(tags) and time.time() < t_end:
+        for r in sv.poll():
+            got[r["tag"]] = r
+        time.sleep(0.0005)
+    return got
+
+
+@pytest.mark.parametrize("mode_name,flags", [("BF16", 0), ("BF16", "batch_only"), ("FP32", 0), ("BF16", "no_graphs")])
+def test_graph_replays_match_eager_answers(served, messi, torch_cuda, mode_name, flags):
+    """The same waves of queries again and again: batch shapes repeat, so the
+    lanes record HIP graphs and replay them; between waves the eager search
+    runs on another stream.  Every replayed answer must equal the eager one."""
+    w = served
+    mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
+    if flags == "batch_only":
+        mode |= messi.SERVER_BATCH_ONLY
+    elif flags == "no_graphs":
+        mode |= messi.SERVER_NO_GRAPHS
+    q = w["q"][:8]
+    ks = np.array([10, 10, 1, 1, 100, 100, 10, 10], dtype=np.int32)
+    want = {}
+    for i in range(8):
+        ai, ad = w["ix"].knn(torch_cuda.from_numpy(q[i:i + 1].copy()).cuda(), int(ks[i]))
+        want[i] = (ai.cpu().numpy()[0], ad.cpu().numpy()[0])
+    sv = messi.Server(w["ix"], 4 << 30, 8, mode)
+    try:
+        for wave in range(6):
+            _say("wave %d (%s, %s)" % (wave, mode_name, flags))
+            got = _wave(sv, q, ks, [wave * 100 + i for i in range(8)])
+            assert len(got) == 8
+            for i in range(8):
+                r = got[wave * 100 + i]
+                assert r["status"] == messi.MESSI_OK
+                np.testing.assert_array_equal(r["idx"], want[i][0])
+                np.testing.assert_array_equal(r["dist"], want[i][1])
+            # eager work on the default stream between replays
+            w["ix"].knn(torch_cuda.from_numpy(q[wave:wave + 1].copy()).cuda(), 10)
+            torch_cuda.cuda.synchronize()
+        st = sv.stats()
+    finally:
+        sv.close()
+    _say(st)
+    assert st["batches"] == st["eager_launches"] + st["graphs_recorded"] + st["graph_replays"]
+    if flags == "no_graphs":
+        assert st["graphs_recorded"] == 0 and st["graph_replays"] == 0
+    else:
+        assert st["graphs_recorded"] >= 1 and st["graph_replays"] >= 1
+    if flags == "batch_only" or mode_name == "FP32":
+        assert st["solo_fp32"] == 0
