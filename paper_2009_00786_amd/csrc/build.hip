@@ -40,6 +40,18 @@ int launch_blocks(int64_t work, int per_block, int cap_blocks) {
     return (int)b;
 }
 
+int device_cu_count() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+                  ? p.multiProcessorCount
+                  : 256;
+    }
+    return cus;
+}
+
 // ---------------------------------------------------------------------------
 // Fold-halving sums across the lanes of one series group (width T lanes, E
 // consecutive elements per lane): pairs (i, i + h) for h = P/2 .. 1.  Strides
@@ -445,11 +457,14 @@ int launch_summarize_seg(const SegArgs& a, hipStream_t s) {
     const bool vec = (a.m % 4 == 0) && (a.L % 4 == 0) && ((uintptr_t)a.in % 16 == 0);
     const int rpw = 64 / a.w;
     const int64_t n_blocks = (a.n + rpw - 1) / rpw;
+    // A streaming read: few waves (two blocks per CU), each with 128 values
+    // per lane (R row groups of M) in flight, beat many waves with few loads.
+    const int cap = 2 * device_cu_count();
     switch (M) {
 #define MESSI_SEG_CASE(MM)                                                                             \
     case MM: {                                                                                         \
-        constexpr int R = (MM <= 8) ? 4 : (MM <= 16 ? 2 : 1);                                          \
-        const int blocks = launch_blocks(n_blocks, 4 * R, 256 * 8);                                    \
+        constexpr int R = (MM <= 8) ? 16 : 128 / MM;                                                   \
+        const int blocks = launch_blocks(n_blocks, 4 * R, cap);                                        \
         if (vec && MM >= 4)                                                                            \
             hipLaunchKernelGGL((summarize_seg_kernel<MM, R, true>), dim3(blocks), dim3(256), 0, s, a);  \
         else                                                                                           \

@@ -604,8 +604,11 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
 // test (the chunk's first leaf lies in a bin wholly above U) is taken when
 // a chunk is prefetched.
 // Pass 1 runs only for queries whose candidate buffer overflowed in pass 0.
+// Four waves per SIMD (four blocks per CU, which the LDS also allows): the
+// scan is bound by memory latency, so resident waves matter more than the
+// couple of registers this spills.
 template <bool VEC, int pass>
-__global__ void __launch_bounds__(kScanThreads) scan_kernel(QArgs a) {
+__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) scan_kernel(QArgs a) {
     constexpr int kPer = kChunk / kScanThreads;
     __shared__ float s_D[16 * 256];
     __shared__ float s_q[MESSI_MAX_LEN];
