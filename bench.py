@@ -304,6 +304,27 @@ def main():
                        "the same queries again with the library's HIP-event phase timing and counters (phases, "
                        "roofline: the scan kernel's own event pair on its stream)",
     }
+    # the paper's approximate search on the same index and queries (the best
+    # leaf's members only): its own rate and how often it finds the exact answer
+    apx_i = torch.empty_like(ans_i)
+    apx_d = torch.empty_like(ans_d)
+    apx_lat = []
+    for rep in range(2):
+        for qi in range(nq):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            ix.knn(queries[qi:qi + 1], k, mode=messi.MODE_APPROX, out=(apx_i[qi:qi + 1], apx_d[qi:qi + 1]))
+            torch.cuda.synchronize()
+            if rep == 1:
+                apx_lat.append((time.perf_counter() - a) * 1e3)
+    apx_lat = np.array(apx_lat)
+    ai = apx_i.cpu().numpy()
+    res["approx_mode"] = {
+        "queries_per_s": len(apx_lat) / (apx_lat.sum() / 1e3), "p50_ms": float(np.percentile(apx_lat, 50)),
+        "p99_ms": float(np.percentile(apx_lat, 99)),
+        "recall_at_%d" % k: float(np.mean([len(set(ai[qi]) & set(answers[0][qi])) / k for qi in range(nq)])),
+        "distance_ratio_mean": float(np.mean(apx_d.cpu().numpy()[:, 0] / np.maximum(answers[1][:, 0], 1e-30))),
+    }
     if ix is not None:
         ix.close()
     print(json.dumps(res), flush=True)

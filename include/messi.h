@@ -48,6 +48,11 @@ extern "C" {
 /* Search modes of messi_knn_ex. */
 #define MESSI_MODE_FP32 0        /* ordered leaf scan, fp32 early-abandoning squared ED */
 #define MESSI_MODE_BF16 1        /* batched BF16 matrix-core filter with a rounding bound, fp32 recheck */
+#define MESSI_MODE_APPROX 2      /* the paper's approximate search (Section 4, approxSearch): the k best
+                                    of the members of the leaf with the smallest bound (extended to
+                                    the following leaves in depth-first order when it holds fewer
+                                    than k, at most 4096 members), ordered by the canonical fp64
+                                    distance.  Not exact: no other leaf is visited. */
 
 typedef struct messi_index messi_index;
 

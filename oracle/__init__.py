@@ -62,6 +62,9 @@ def _load():
         lib.oracle_knn_brute.restype = ctypes.c_int
         lib.oracle_knn_isax.argtypes = [vp, i64, i32, vp, i32, i32, vp, i64, vp, vp, i32, i32, vp, vp, vp]
         lib.oracle_knn_isax.restype = ctypes.c_int
+        lib.oracle_leaf_bounds.argtypes = [vp, i32, i32, i32, vp, i64, vp]
+        lib.oracle_knn_approx.argtypes = [vp, i64, i32, i32, i32, vp, i64, vp, vp, i32, i32, i64, vp, vp, vp]
+        lib.oracle_knn_approx.restype = ctypes.c_int
         lib.oracle_bf16_round_array.argtypes = [vp, i64, vp]
         lib.oracle_bf16_filter_values.argtypes = [vp, vp, i64, i32, vp]
         lib.oracle_bf16_error_bound.argtypes = [d, d, i32, vp]
@@ -195,6 +198,38 @@ def knn_isax(data, words_, card_bits, leaves, pos, queries, k: int, return_stats
         raise ValueError("bad arguments to knn_isax")
     out = (idx, dd, np.sqrt(dd).astype(np.float32))
     return out + (stats,) if return_stats else out
+
+
+def leaf_bounds(query, segments: int, card_bits: int, leaves) -> np.ndarray:
+    """MINDIST^2 (fp64, no widening) of one query's PAA to every leaf's regions."""
+    q = _f32(query).ravel()
+    leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+    out = np.zeros(leaves.size, dtype=np.float64)
+    _load().oracle_leaf_bounds(q.ctypes.data, q.size, segments, card_bits, leaves.ctypes.data, leaves.size,
+                               out.ctypes.data)
+    return out
+
+
+def knn_approx(data, segments: int, card_bits: int, leaves, pos, queries, k: int, leaf=None):
+    """The paper's approximate search (Section 4, approxSearch): the k best
+    members of the leaf with the smallest bound (or of `leaf`), extended in
+    depth-first order to at least k members, at most 4096.
+    Returns (leaf int64[nq], idx int64[nq, k], d64 float64[nq, k], dist float32[nq, k])."""
+    data, queries = _f32(data), _f32(queries)
+    n, length = data.shape
+    nq = queries.shape[0]
+    leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+    pos = np.ascontiguousarray(pos, dtype=np.uint32)
+    lf = np.zeros(nq, dtype=np.int64)
+    idx = np.zeros((nq, k), dtype=np.int64)
+    dd = np.zeros((nq, k), dtype=np.float64)
+    rc = _load().oracle_knn_approx(data.ctypes.data, n, length, segments, card_bits, leaves.ctypes.data,
+                                   leaves.size, pos.ctypes.data, queries.ctypes.data, nq, k,
+                                   -1 if leaf is None else int(leaf), lf.ctypes.data, idx.ctypes.data,
+                                   dd.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments to knn_approx")
+    return lf, idx, dd, np.sqrt(dd).astype(np.float32)
 
 
 def bf16_round(v) -> np.ndarray:

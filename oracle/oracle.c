@@ -631,3 +631,57 @@ double oracle_bf16_error_bound(double a2, double b2, int32_t len, double* terms)
     }
     return e;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Approximate search (Section 4, approxSearch): the leaf whose summary is   */
+/* closest to the query -- the smallest MINDIST of the query's PAA (fp64) to */
+/* the leaf's regions, ties to the lowest leaf id -- and the k best of its   */
+/* members by (D64, index).  A leaf with fewer than k members is extended to */
+/* the following members in depth-first leaf order (the member range moves   */
+/* back from the end of the collection), and at most 4096 members are taken. */
+/* Each query's chosen leaf goes to out_leaf; with leaf_override >= 0 that   */
+/* leaf is used instead of the argmin (to check a near-tie).                 */
+/* ------------------------------------------------------------------------ */
+
+void oracle_leaf_bounds(const float* query, int32_t len, int32_t w, int32_t card_bits, const oracle_leaf* leaves,
+                        int64_t n_leaves, double* out) {
+    int m = len / w;
+    float bp[255];
+    oracle_breakpoints(card_bits, bp);
+    double qp[16];
+    paa64(query, len, w, qp);
+    for (int64_t l = 0; l < n_leaves; ++l)
+        out[l] = oracle_mindist_sq(qp, w, m, leaves[l].card, leaves[l].prefix, card_bits, bp, 0.0);
+}
+
+int oracle_knn_approx(const float* data, int64_t n, int32_t len, int32_t w, int32_t card_bits,
+                      const oracle_leaf* leaves, int64_t n_leaves, const uint32_t* pos, const float* queries,
+                      int32_t nq, int32_t k, int64_t leaf_override, int64_t* out_leaf, int64_t* out_idx,
+                      double* out_d64) {
+    if (n < 1 || len < 1 || w < 1 || len % w || k < 1 || k > n || k > 4096) return -1;
+    double* lb = (double*)malloc(sizeof(double) * (size_t)n_leaves);
+    for (int32_t q = 0; q < nq; ++q) {
+        const float* qs = queries + (size_t)q * (size_t)len;
+        int64_t best = leaf_override;
+        if (best < 0) {
+            oracle_leaf_bounds(qs, len, w, card_bits, leaves, n_leaves, lb);
+            best = 0;
+            for (int64_t l = 1; l < n_leaves; ++l)
+                if (lb[l] < lb[best]) best = l;
+        }
+        out_leaf[q] = best;
+        int64_t cnt = leaves[best].count;
+        if (cnt < k) cnt = k;
+        if (cnt > 4096) cnt = 4096;
+        if (cnt > n) cnt = n;
+        int64_t r0 = leaves[best].start;
+        if (r0 > n - cnt) r0 = n - cnt;
+        topk_t t = {k, 0, out_d64 + (size_t)q * (size_t)k, out_idx + (size_t)q * (size_t)k};
+        for (int64_t r = r0; r < r0 + cnt; ++r) {
+            const uint32_t row = pos[r];
+            topk_insert(&t, oracle_d64(qs, data + (size_t)row * (size_t)len, len), (int64_t)row);
+        }
+    }
+    free(lb);
+    return 0;
+}

@@ -219,7 +219,8 @@ int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int
     const Index* ix = reinterpret_cast<const Index*>(index);
     if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
     if (k < 1 || k > MESSI_MAX_K || (int64_t)k > ix->n) return fail(MESSI_EINVAL, "k must be in [1, min(n, 1024)]");
-    if (mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16) return fail(MESSI_EINVAL, "unknown mode");
+    if (mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16 && mode != MESSI_MODE_APPROX)
+        return fail(MESSI_EINVAL, "unknown mode");
     if (mode == MESSI_MODE_BF16 && !ix->shadow.p)
         return fail(MESSI_EINVAL, "BF16 mode needs an index built with bf16_shadow = 1");
     if (stats) std::memset(stats, 0, sizeof(*stats));

@@ -359,6 +359,31 @@ __global__ void __launch_bounds__(256) approx_select_kernel(QArgs a, uint32_t nl
     }
 }
 
+// Approximate mode: the evaluated members of the first leaf whose distance is
+// within the first bound are the candidates; the final kernel orders them.
+__global__ void __launch_bounds__(256) approx_cands_kernel(QArgs a, uint32_t nlb) {
+    __shared__ unsigned long long s_min[4];
+    __shared__ uint32_t s_max[4];
+    const int q = blockIdx.x;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    unsigned long long best;
+    uint32_t mx;
+    lb_extremes(a, q, nlb, s_min, s_max, best, mx);
+    uint32_t r0, cnt;
+    approx_range(a, (uint32_t)(best & 0xffffffffull), st.k, r0, cnt);
+    const float U = __uint_as_float(st.U);
+    const float* d = a.approx_d + (size_t)q * kApproxMax;
+    for (uint32_t r = threadIdx.x; r < cnt; r += 256) {
+        const float dv = d[r];
+        if (dv * (1.0f - kRhoEd) <= U) {
+            const uint32_t slot = atomicAdd(&st.ncand, 1u);
+            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{dv, a.pos[r0 + r]};
+            else if (st.err == 0) st.err = 2;
+        }
+    }
+}
+
 // --------------------------------------------------------------------------
 // order: counting sort of the surviving leaves into bound bins
 // --------------------------------------------------------------------------
@@ -1275,6 +1300,8 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     const Index* ix = c.ix;
     const int32_t nq = c.nq;
     cap = std::max(default_cap(nq, c.kmax, c.mode), cap_min);
+    // the approximate mode's candidates are the evaluated members of one leaf
+    if (c.mode == MESSI_MODE_APPROX) cap = std::max<uint32_t>(cap, (uint32_t)kApproxMax);
     Workspace* ws = nullptr;
     MESSI_TRY(get_workspace(ix, c.s, nq, cap, &ws));
     *wsp = ws;
@@ -1342,6 +1369,17 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_select");
     MESSI_TRY(mark(3));
+    if (mode == MESSI_MODE_APPROX) {
+        hipLaunchKernelGGL(approx_cands_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
+        MESSI_LAUNCH_CHECK("approx_cands");
+        MESSI_TRY(mark(4));
+        MESSI_TRY(mark(7));
+        MESSI_TRY(mark(5));
+        hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
+        MESSI_LAUNCH_CHECK("final");
+        MESSI_TRY(mark(6));
+        return MESSI_OK;
+    }
     hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_hist");
     hipLaunchKernelGGL(bin_scan_kernel, dim3(nq), dim3(256), 0, s, a);
@@ -1502,7 +1540,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     // buffers is answered again, alone, by the FP32 path (which reruns and
     // grows its own buffer as needed).
     int32_t fallbacks = 0;
-    if (!fp32 && (err & (2u | 4u | 16u)) && !(err & 1u)) {
+    if (mode == MESSI_MODE_BF16 && (err & (2u | 4u | 16u)) && !(err & 1u)) {
         std::vector<uint32_t> st(nq);
         hipLaunchKernelGGL(status_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, a, ws->status.as<uint32_t>());
         MESSI_LAUNCH_CHECK("status");

@@ -23,6 +23,7 @@ MESSI_EBUSY = -5
 MESSI_EOVERFLOW = -6
 MODE_FP32 = 0
 MODE_BF16 = 1
+MODE_APPROX = 2  # approximate: the best leaf's members only (not exact)
 SERVER_BATCH_ONLY = 0x100  # OR into a server mode: no lone FP32 queries in BF16 mode
 SERVER_NO_GRAPHS = 0x200   # OR into a server mode: eager launches, no HIP graphs
 MAX_K = 1024

@@ -302,3 +302,54 @@ def test_knn_nq_zero_and_errors(torch_cuda, messi):
     with pytest.raises(messi.MessiError):
         messi.Index(x, 5, 8, 10)   # 32 % 5 != 0
     ix.close()
+
+
+# ---------------------------------------------------------------------------
+# approximate mode (the paper's approxSearch)
+# ---------------------------------------------------------------------------
+
+def _approx_matches(oracle_mod, z, leaves, pos, w, b, q, k, gi, gd):
+    """The GPU's approximate answer is the oracle's for the leaf of smallest
+    bound -- or, where bounds tie within the fp32 rounding the GPU decides
+    in, for another leaf of (nearly) the smallest bound."""
+    lf, oi, _, od = oracle_mod.knn_approx(z, w, b, leaves, pos, q[None, :], k)
+    if np.array_equal(gi, oi[0]) and np.array_equal(gd, od[0]):
+        return True
+    lb = oracle_mod.leaf_bounds(q, w, b, leaves)
+    near = np.nonzero(lb <= lb.min() + 1e-3 * (1.0 + lb.min()))[0]
+    for l in near:
+        _, oi, _, od = oracle_mod.knn_approx(z, w, b, leaves, pos, q[None, :], k, leaf=int(l))
+        if np.array_equal(gi, oi[0]) and np.array_equal(gd, od[0]):
+            return True
+    return False
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_approx_mode_matches_oracle(tiny_workload, oracle_mod, messi, torch_cuda, k):
+    w = tiny_workload
+    _say("approximate mode, tiny workload, k=%d (single and batched)" % k)
+    leaves, pos = w["ix"].export_leaves()
+    bi, bd = w["ix"].knn(w["qt"], k, mode=messi.MODE_APPROX)
+    bi, bd = bi.cpu().numpy(), bd.cpu().numpy()
+    ei, ed, _ = oracle_mod.knn_brute(w["z"], w["qz"], k, nthreads=8)
+    for i in range(len(w["qz"])):
+        si, sd = w["ix"].knn(w["qt"][i:i + 1], k, mode=messi.MODE_APPROX)
+        np.testing.assert_array_equal(si.cpu().numpy()[0], bi[i])
+        np.testing.assert_array_equal(sd.cpu().numpy()[0], bd[i])
+        assert _approx_matches(oracle_mod, w["z"], leaves, pos, 16, 8, w["qz"][i], k, bi[i], bd[i]), i
+        assert np.all(bd[i] >= np.sqrt(ed[i]).astype(np.float32))
+
+
+def test_approx_mode_shapes(torch_cuda, messi, datagen_mod, oracle_mod):
+    for (n, length, w, b, cap, k) in [(3000, 96, 8, 8, 50, 5), (500, 32, 16, 3, 7, 40), (64, 16, 4, 8, 1000, 64)]:
+        _say("approximate mode n=%d L=%d w=%d b=%d cap=%d k=%d" % (n, length, w, b, cap, k))
+        x = datagen_mod.random_walks(n, length, seed=n + 5)
+        z = oracle_mod.znorm(x)
+        q = oracle_mod.znorm(datagen_mod.random_walks(4, length, seed=n + 6, stream=1))
+        ix = messi.Index(torch_cuda.from_numpy(z).cuda(), w, b, cap)
+        leaves, pos = ix.export_leaves()
+        gi, gd = ix.knn(torch_cuda.from_numpy(q).cuda(), k, mode=messi.MODE_APPROX)
+        gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+        for i in range(len(q)):
+            assert _approx_matches(oracle_mod, z, leaves, pos, w, b, q[i], k, gi[i], gd[i]), (n, i)
+        ix.close()

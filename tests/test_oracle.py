@@ -458,3 +458,51 @@ def test_isax_search_tiny_config(oracle_mod, datagen_mod):
     q = oracle_mod.znorm(datagen_mod.random_walks(10, 256, seed=datagen_mod.SEED_QUERY,
                                                   stream=datagen_mod.STREAM_QUERY))
     _isax_vs_brute(oracle_mod, z, q, 16, 8, 2000, 1)
+
+
+# ---------------------------------------------------------------------------
+# approximate search (Section 4, approxSearch)
+# ---------------------------------------------------------------------------
+
+def test_approx_single_leaf_is_exact(oracle_mod):
+    """With one segment and every series above zero the collection falls in a
+    single root bucket; with the capacity above N that bucket is the only
+    leaf, so the approximate answer is the exact one."""
+    rng = np.random.default_rng(3)
+    x = (np.abs(rng.standard_normal((900, 8))) + 0.1).astype(np.float32)  # not z-normalised
+    q = (np.abs(rng.standard_normal((5, 8))) + 0.1).astype(np.float32)
+    words = oracle_mod.words(x, 1, 8)
+    leaves, pos = oracle_mod.build_leaves(words, 8, 10_000)
+    assert len(leaves) == 1
+    for k in (1, 7, 200):
+        lf, ia, da, _ = oracle_mod.knn_approx(x, 1, 8, leaves, pos, q, k)
+        ib, db, _ = oracle_mod.knn_brute(x, q, k)
+        assert np.all(lf == 0)
+        np.testing.assert_array_equal(ia, ib)
+        np.testing.assert_array_equal(da, db)
+
+
+def test_approx_picks_the_smallest_bound_and_never_beats_exact(oracle_mod, datagen_mod):
+    z = oracle_mod.znorm(datagen_mod.random_walks(8000, 64, seed=21))
+    q = np.concatenate([oracle_mod.znorm(datagen_mod.random_walks(6, 64, seed=786, stream=1)),
+                        datagen_mod.add_noise(z[[5, 4000]], [0.01, 0.5])]).astype(np.float32)
+    words = oracle_mod.words(z, 8, 8)
+    leaves, pos = oracle_mod.build_leaves(words, 8, 50)
+    for k in (1, 10, 120):
+        lf, ia, da, _ = oracle_mod.knn_approx(z, 8, 8, leaves, pos, q, k)
+        ib, db, _ = oracle_mod.knn_brute(z, q, k)
+        for i in range(len(q)):
+            lb = oracle_mod.leaf_bounds(q[i], 8, 8, leaves)
+            assert lf[i] == int(np.argmin(lb))                  # first of the smallest
+            assert np.all(da[i] >= db[i])                         # the j-th approximate is no better
+            # the answers lie in the chosen leaf or, when it holds fewer than
+            # k members, in the members that follow it in leaf order
+            start, count = int(leaves[lf[i]]["start"]), int(leaves[lf[i]]["count"])
+            cnt = min(max(count, k), 4096, len(z))
+            r0 = min(start, len(z) - cnt)
+            members = set(pos[r0:r0 + cnt].tolist())
+            assert set(ia[i].tolist()) <= members
+            assert len(set(ia[i].tolist())) == k
+    # a dataset row's own leaf has bound 0, and the row is its own answer
+    lf, ia, da, _ = oracle_mod.knn_approx(z, 8, 8, leaves, pos, z[[77, 6001]], 1)
+    assert list(ia[:, 0]) == [77, 6001] and np.all(da == 0)
