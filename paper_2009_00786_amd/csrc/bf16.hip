@@ -3,7 +3,7 @@
 //
 // For a batch of queries, the (query, leaf) pairs that survive the leaf bound
 // are grouped by leaf.  A block stages a leaf's queries in LDS as BF16 rows
-// (the A operand); each of its waves holds the BF16 rows of 64 of the leaf's
+// (the A operand); each of its waves holds the BF16 rows of 32 of the leaf's
 // members in registers (the B operand), so a member row is read from HBM once
 // per leaf and round whatever the number of queries that visit the leaf.
 // For every (query q, member x) the filter evaluates
@@ -251,16 +251,19 @@ __global__ void __launch_bounds__(256) leaf_scatter_kernel(QArgs a, uint32_t t0,
 // so U < 2.02 (|q|^2 + |x|^2) and the roundings of alpha stay below the 2^-20
 // slacks.  The test costs one compare per (query, member).
 //
-// Work: blocks of kFWaves waves take leaves from a shared counter.  For a
-// leaf, up to QC of its queries (BF16 rows) are staged in LDS once; each wave
-// holds the BF16 rows of 64 members in registers (four 16-member B fragments
-// per 32-wide k-step) and streams 16-query A fragments from LDS, every A
-// fragment feeding four mfma_f32_16x16x32_bf16, two query tiles interleaved.
+// Work: blocks of kFWaves waves (one block per CU) take leaves from a shared
+// counter.  For a leaf, up to QC of its queries (BF16 rows) are staged in LDS
+// once; each wave holds the BF16 rows of 32 members in registers (two
+// 16-member B fragments per 32-wide k-step) and streams 16-query A fragments
+// from LDS, every A fragment feeding two mfma_f32_16x16x32_bf16, two query
+// tiles interleaved.  Two fragments per wave keep a wave at about 150
+// registers, so twelve waves fit a CU: the filter waits on memory, and the
+// extra waves hide more of it than four fragments per wave save in LDS reads.
 // Rows longer than 256 values are taken 8 k-steps of B at a time.
 // ---------------------------------------------------------------------------
-constexpr int kFWaves = 8;
+constexpr int kFWaves = 12;
 constexpr int kFThreads = 64 * kFWaves;
-constexpr int kFFrags = 4;                 // 16-member B fragments per wave
+constexpr int kFFrags = 2;                 // 16-member B fragments per wave
 constexpr int kFQT = 2;                    // 16-query A tiles per step
 constexpr int kFMem = 16 * kFFrags;        // members per wave
 constexpr int kFTile = kFWaves * kFMem;    // members per block step
@@ -341,7 +344,7 @@ __global__ void __launch_bounds__(kFThreads) bf16_filter_kernel(QArgs a, BfArgs 
                 }
             }
             __syncthreads();
-            // ---- members: each wave 32 of every kFTile
+            // ---- members: each wave kFMem of every kFTile
             const bool pf = ks <= kFKC;  // the whole row fits the B registers
             for (uint32_t mt0 = 0; mt0 < lf.count; mt0 += kFTile) {
                 const uint32_t mb = mt0 + wave * kFMem;
