@@ -47,7 +47,10 @@ extern "C" {
 
 /* Search modes of messi_knn_ex. */
 #define MESSI_MODE_FP32 0        /* ordered leaf scan, fp32 early-abandoning squared ED */
-#define MESSI_MODE_BF16 1        /* batched BF16 matrix-core filter with a rounding bound, fp32 recheck */
+#define MESSI_MODE_BF16 1        /* BF16 filter with a rounding bound, then exact fp32 distances: a
+                                    batch runs the matrix-core filter; a call of one query runs the
+                                    FP32 mode's ordered scan, where each member whose word bound
+                                    survives is first tested on its BF16 row (half the bytes) */
 #define MESSI_MODE_APPROX 2      /* the paper's approximate search (Section 4, approxSearch): the k best
                                     of the members of the leaf with the smallest bound (extended to
                                     the following leaves in depth-first order when it holds fewer
@@ -207,7 +210,7 @@ typedef struct {
 } messi_result;
 
 /* Server mode flags, OR-ed into `mode` of messi_server_create. */
-#define MESSI_SERVER_BATCH_ONLY 0x100 /* BF16: never answer a lone waiting query alone in FP32 mode */
+#define MESSI_SERVER_BATCH_ONLY 0x100 /* BF16: launches of one query also take the matrix-core filter */
 #define MESSI_SERVER_NO_GRAPHS 0x200  /* enqueue every launch eagerly instead of replaying HIP graphs */
 
 /* A request loop that keeps `index` on the device and answers exact k-NN
@@ -217,9 +220,10 @@ typedef struct {
  * share batched launches; the slots are spread over up to four lanes, each a
  * HIP stream with its own workspace, that run concurrently.  A lane's launch
  * is recorded once per batch shape into a HIP graph and replayed afterwards.
- * In BF16 mode, a query that is alone in the queue when a lane frees up is
- * answered by itself in FP32 mode (unless MESSI_SERVER_BATCH_ONLY), since a
- * batch of one gains nothing from the matrix-core filter.  A result never
+ * In BF16 mode, a query that is alone in the queue when a lane frees up is a
+ * launch of one, answered by the ordered scan with the BF16 row filter (see
+ * messi_knn; unless MESSI_SERVER_BATCH_ONLY), since a batch of one gains
+ * nothing from the matrix-core filter.  A result never
  * depends on which queries shared its batch: each query carries its own
  * status, and a query whose BF16 buffers overflow is answered again, alone,
  * in FP32 mode before its result is posted.
@@ -245,7 +249,7 @@ int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out);
 typedef struct {
     int64_t batches;          /* launches (a batch, or one query alone) */
     int64_t bf16_batches;     /* of which in BF16 mode */
-    int64_t solo_fp32;        /* lone queries answered alone in FP32 mode */
+    int64_t row_filter;       /* BF16 launches of one query (the row-filtered scan) */
     int64_t requeued;         /* queries re-queued after a buffer overflow */
     int64_t eager_launches;   /* launches enqueued operation by operation */
     int64_t graphs_recorded;  /* launches recorded into a new HIP graph (then replayed) */

@@ -596,6 +596,34 @@ int build_bf16_shadow(Index* ix, hipStream_t s) {
 
 void release_bf16(const Index* ix) { (void)ix; }
 
+int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
+    const int L = ix->len;
+    const int Lp = (L + 31) / 32 * 32;
+    const int nq = a.nq;
+    if (ws->qb.bytes < sizeof(uint16_t) * (size_t)nq * Lp || ws->qnorm.bytes < sizeof(float2) * (size_t)nq ||
+        ws->qx.bytes < sizeof(uint4) * (size_t)nq) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(ws->qb.alloc(sizeof(uint16_t) * (size_t)nq * Lp));
+        MESSI_TRY(ws->qnorm.alloc(sizeof(float2) * (size_t)nq));
+        MESSI_TRY(ws->qx.alloc(sizeof(uint4) * (size_t)nq));
+        ws->bf_nq = 0;  // the batched filter's buffers are sized again on its next call
+        ++ws->gen;
+    }
+    const BfConsts kc = bf_consts(Lp);
+    a.shadow = ix->shadow.as<uint16_t>();
+    a.sx = ix->sx.as<uint2>();
+    a.qb = ws->qb.as<uint16_t>();
+    a.qnorm = ws->qnorm.as<float2>();
+    a.qx = ws->qx.as<uint4>();
+    a.Lp = Lp;
+    a.one_minus_h = std::nextafter((float)(1.0 - kc.h), 0.0f);
+    hipLaunchKernelGGL(qprep_bf16_kernel, dim3(nq), dim3(256), 0, s, a.queries, L, Lp,
+                       std::nextafter((float)kc.c1p, 1.0f), ws->qb.as<uint16_t>(), ws->qnorm.as<float2>(),
+                       ws->qx.as<uint4>());
+    MESSI_LAUNCH_CHECK("qprep_bf16");
+    return MESSI_OK;
+}
+
 int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing) {
     const int L = ix->len;
     const int Lp = (L + 31) / 32 * 32;

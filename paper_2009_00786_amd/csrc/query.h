@@ -36,6 +36,11 @@ struct LbPart {
     uint32_t pad;
 };
 
+// Scan statistics per block: scanned leaves, bounded members, members that
+// reached the distance stage, abandoned, bytes read x 16, fp32 distances after
+// a BF16 row test, BF16 rows tested.
+constexpr int kBlkCnt = 7;
+
 // Per-query search state (device).
 struct QState {
     float paa[16];
@@ -72,7 +77,15 @@ struct QArgs {
     const Leaf* leaves;
     int32_t nL;
     const float* bp;
-    const uint16_t* shadow;      // bf16 path: bf16 rows in leaf order
+    const uint16_t* shadow;      // bf16 path: bf16 rows in leaf order [n][Lp]
+    // BF16 row filter of the ordered scan (bf16_row_prep fills these)
+    const uint2* sx;             // [n] member terms of the filter's extra k-step
+    const uint16_t* qb;          // [nq][Lp] 2 q rounded to BF16
+    const float2* qnorm;         // [nq] (|q|^2, |q|) from fp64 sums
+    const uint4* qx;             // [nq] query terms of the extra k-step
+    int32_t Lp;                  // BF16 row length (L rounded up to 32)
+    float one_minus_h;           // 1 - h of the drop test, rounded down
+    float rf_tau;                // the row filter runs while U > rf_tau |q|^2
     const float* queries;        // [nq][L]
     int32_t nq;
     QState* qs;
@@ -129,6 +142,14 @@ struct Workspace {
 // shared fp64 final ordering.
 int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing);
 
+// The BF16 row filter of the ordered scan: per query 2 q in BF16, its norms
+// and the extra k-step terms (into the workspace), and the filter's fields of a.
+int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s);
+
+// Whether a BF16-mode call of nq queries runs the ordered scan with the BF16
+// row filter (few queries) instead of the batched matrix-core filter.
+bool row_filter_path(int32_t mode, int32_t nq, bool matrix_only);
+
 // For k > 1, lower every query's bound to its current k-th candidate distance.
 int refresh_bounds(QArgs& a, hipStream_t s);
 
@@ -139,9 +160,10 @@ int refresh_bounds(QArgs& a, hipStream_t s);
 // stream reaches that point.  knn_error_code turns the flags into a MESSI_E*
 // code, query_error_code a query's status.
 // cap_min raises the per-query candidate buffer above its default.
+// matrix_only keeps a BF16 call of few queries on the matrix-core filter.
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
-                uint32_t cap_min = 0);
+                uint32_t cap_min = 0, bool matrix_only = false);
 // Default candidate slots per query for a call of nq queries with k <= kmax.
 uint32_t default_cap(int32_t nq, int32_t kmax, int32_t mode);
 int knn_error_code(uint32_t err);

@@ -52,6 +52,12 @@ namespace {
 
 constexpr int kScanThreads = 256;
 constexpr int kEdBatch = 32;  // survivors gathered before a round of distances
+// BF16 calls of at most this many queries run the ordered scan with the BF16
+// row filter; larger batches share member rows on the matrix-core filter
+constexpr int32_t kRowFilterMaxQ = 1;
+// the row filter runs while U > kRowFilterTau |q|^2 (about twice its rounding
+// bound for |x| = |q|)
+constexpr float kRowFilterTau = 0.03f;
 
 __device__ __forceinline__ uint32_t vload(const uint32_t* p) {
     return __atomic_load_n(p, __ATOMIC_RELAXED);
@@ -497,6 +503,18 @@ __device__ __forceinline__ uint32_t word_byte(const uint4& wd, int i) {
 // the bins up to the one where the running count reaches k lies below that
 // bin's upper edge, so the edge bounds the k-th distance from above.  Between
 // kernels the exact k-th is taken from the candidate buffer itself.
+// acc + the dot product of 8 BF16 pairs, one fused multiply-add per pair (the
+// products of two BF16 values are exact in fp32, so each step rounds once).
+__device__ __forceinline__ float bf16_dot8(const uint4& x, const uint4& y, float acc) {
+    const uint32_t xv[4] = {x.x, x.y, x.z, x.w}, yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        acc = fmaf(__uint_as_float(xv[i] << 16), __uint_as_float(yv[i] << 16), acc);
+        acc = fmaf(__uint_as_float(xv[i] & 0xffff0000u), __uint_as_float(yv[i] & 0xffff0000u), acc);
+    }
+    return acc;
+}
+
 __device__ __forceinline__ uint32_t hist_bin(float d, int32_t hbase) {
     const int32_t b = (int32_t)(__float_as_uint(d) >> 16) - hbase;
     return (uint32_t)min(max(b, 0), kHistBins - 1);
@@ -629,14 +647,24 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
 // test (the chunk's first leaf lies in a bin wholly above U) is taken when
 // a chunk is prefetched.
 // Pass 1 runs only for queries whose candidate buffer overflowed in pass 0.
+// With SH (BF16 mode, few queries) a survivor's 512-byte BF16 row in leaf
+// order (L = 256) is tested first, with the same exact drop rule as the
+// matrix-core filter: the test is acc < alpha for
+//     acc = sum 2 q~_j x~_j + c~ r~x - b_hi - b_lo    (fp32, any order)
+//     alpha = fl(fl((1 - h) |q|^2) - fl(U (1 + 2^-20))),
+// which implies D > U, so a dropped member is not an answer.  Only the rows
+// that pass read their fp32 row for the distance the FP32 scan computes.  The
+// test runs while U exceeds rf_tau |q|^2: once U is of the order of the
+// rounding bound (about 4 |q||x| 2^-8) it would drop little.
 // Four waves per SIMD (four blocks per CU, which the LDS also allows): the
 // scan is bound by memory latency, so resident waves matter more than the
-// couple of registers this spills.
-template <bool VEC, int pass>
-__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) scan_kernel(QArgs a) {
+// couple of registers this spills.  The row-filtered variant runs three, with
+// no spills: its BF16 pass keeps twice the rows in flight per wave.
+template <bool VEC, int pass, bool SH>
+__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(SH ? 3 : 4))) scan_kernel(QArgs a) {
     constexpr int kPer = kChunk / kScanThreads;
     __shared__ float s_D[16 * 256];
-    __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ float s_q[SH ? 1 : MESSI_MAX_LEN];  // with SH the rare fp32 rows read the query from L2
     __shared__ uint32_t s_surv[kChunk + kEdBatch];  // series indices waiting for their distance
     __shared__ uint32_t s_pbase[kChunk];  // word index of the chunk's member 0 if it were in this leaf
     __shared__ float s_plb[kChunk];
@@ -645,6 +673,11 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
     __shared__ uint32_t s_tmp[4];
     __shared__ uint32_t s_flag, s_app, s_stop;
     __shared__ float s_Ublk;  // block's view of U: refreshed each chunk, lowered by its own finds
+    __shared__ uint4 s_qb[SH ? MESSI_MAX_LEN / 8 : 1];  // row filter: 2 q in BF16
+    __shared__ uint4 s_qx;                              // row filter: the query's extra k-step
+    __shared__ float s_q2h, s_tau;                      // row filter: fl((1 - h) |q|^2), rf_tau |q|^2
+    __shared__ uint32_t s_rck[SH ? kChunk + kEdBatch : 1];  // row filter: series indices that passed
+    __shared__ uint32_t s_nrck;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4, ql = lane & 15;
     const int nq = a.nq;
@@ -664,6 +697,8 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
         G = 1;
     }
     uint32_t c_scanned = 0, c_bounded = 0, c_dist = 0, c_abandon = 0, c_bytes = 0;  // this thread's share
+    uint32_t c_rck = 0, c_bft = 0;
+    const int npc = SH ? (a.Lp >> 3) : 0;  // 16-byte pieces of a BF16 row
     // optional per-block phase timing, kept by thread 0 in LDS: control,
     // member filter, distances, last mark, start
     __shared__ unsigned long long s_t[5];
@@ -685,6 +720,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
         if (tid == 0) {
             s_flag = (st.err != 0 || st.nsurv == 0 || (pass == 1 && st.rerun == 0)) ? 1u : 0u;
             s_Ublk = __uint_as_float(0x7f800000u);
+            s_nrck = 0;
         }
         __syncthreads();
         const bool skip = s_flag != 0;
@@ -717,7 +753,18 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                 }
                 s_D[i * 256 + c] = mf * (d * d);
             }
-            for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
+            if (!SH)
+                for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
+            if (SH) {
+                const uint4* qb4 = reinterpret_cast<const uint4*>(a.qb) + (size_t)q * npc;
+                for (int jj = tid; jj < npc; jj += kScanThreads) s_qb[jj] = qb4[jj];
+                if (tid == 0) {
+                    const float2 qn = a.qnorm[q];
+                    s_qx = a.qx[q];
+                    s_q2h = __fmul_rn(a.one_minus_h, qn.x);
+                    s_tau = a.rf_tau * qn.x;
+                }
+            }
         }
         const uint32_t* cfq = a.chunk_first + (size_t)q * a.max_chunks;
         const OrdRec* recq = a.rec + (size_t)q * a.nL;
@@ -842,6 +889,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                 }
             }
             // series index of every survivor, in flight during the compaction
+            // (with SH its leaf-order position: the BF16 row's index)
             uint32_t gi[kPer];
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
@@ -849,7 +897,8 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                 if (keepmask & (1u << r)) {
                     // the chunk's leaves are still in LDS (the next chunk's are committed below)
                     const uint32_t f = r * kScanThreads + tid;
-                    gi[r] = a.pos[s_pbase[member_leaf(np, f)] + f];
+                    const uint32_t mp = s_pbase[member_leaf(np, f)] + f;
+                    gi[r] = SH ? mp : a.pos[mp];
                 }
             }
             uint32_t total;
@@ -884,17 +933,70 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
             // block's last chunk), so each round of row loads is well filled
             const bool run_ed = !more || nacc >= (uint32_t)kEdBatch;
             if (run_ed) {
-            // ---- distances: 16 lanes per row, the whole row per pass
-            const uint32_t nsv = nacc;
+            uint32_t nsv = nacc;
             nacc = 0;
+            // With SH the list holds leaf-order positions.  While U is large
+            // their BF16 rows are tested first, 8 lanes per row and 8 rows per
+            // wave at a time (twice the rows in flight of the fp32 pass), and
+            // the series indices of the rows that pass go to s_rck.
+            bool from_rck = false;
+            if (SH && s_Ublk > s_tau) {
+                // nothing lowers s_Ublk before the distances below: one value for the block
+                const float alpha = __fsub_rn(s_q2h, __fmul_rn(s_Ublk, 1.00000095367431640625f));
+                const int g8 = lane >> 3, l8 = lane & 7;
+                for (uint32_t base = wave * 8; base < nsv; base += 32) {
+                    const uint32_t si = base + g8;
+                    const bool act = si < nsv;
+                    const uint32_t mp = act ? s_surv[si] : 0u;
+                    const uint4* xr = reinterpret_cast<const uint4*>(a.shadow) + (size_t)mp * npc;
+                    float bacc = 0.f;
+                    for (int c0 = 0; c0 < npc; c0 += 32) {
+                        uint4 xv[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int c = c0 + t * 8 + l8;
+                            xv[t] = (act && c < npc) ? xr[c] : make_uint4(0u, 0u, 0u, 0u);
+                        }
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int c = c0 + t * 8 + l8;
+                            if (c < npc) bacc = bf16_dot8(s_qb[c], xv[t], bacc);
+                        }
+                    }
+                    if (act && l8 == 0) {
+                        const uint2 e = a.sx[mp];
+                        bacc = bf16_dot8(s_qx, make_uint4(e.x, e.y, 0u, 0u), bacc);
+                    }
+                    bacc += __shfl_xor(bacc, 4, 8);
+                    bacc += __shfl_xor(bacc, 2, 8);
+                    bacc += __shfl_xor(bacc, 1, 8);
+                    if (act) {
+                        c_bytes += 2u * ((uint32_t)npc * 16u + 8u);  // 8 lanes of the row (the sum is taken / 16)
+                        if (l8 == 0) {
+                            ++c_dist;
+                            ++c_bft;
+                            if (!(bacc < alpha)) {
+                                ++c_rck;
+                                s_rck[atomicAdd(&s_nrck, 1u)] = a.pos[mp];
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                nsv = s_nrck;
+                from_rck = true;
+            }
+            // ---- distances: 16 lanes per row, the whole row per pass
+            const float* qv = SH ? a.queries + (size_t)q * L : s_q;
             uint32_t appended = 0;
             for (uint32_t base = wave * 4; base < nsv; base += 16) {
                 const uint32_t si = base + quarter;
                 const bool act = si < nsv;
-                const uint32_t gidx = act ? s_surv[si] : 0u;
+                uint32_t gidx = act ? (from_rck ? s_rck[si] : s_surv[si]) : 0u;
+                if (SH && !from_rck && act) gidx = a.pos[gidx];  // a leaf-order position
+                bool alive = act;
                 const float* row = a.series + (size_t)gidx * L;
                 float acc = 0.f;
-                bool alive = act;
                 for (int g = 0; g < nchunk; g += 4) {
                     if (alive) {
                         if (VEC) {
@@ -909,7 +1011,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                             for (int cc = 0; cc < 4; ++cc) {
                                 const int j0 = (g + cc) * 64 + ql * 4;
                                 if (g + cc < nchunk && j0 < L) {
-                                    const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
+                                    const float4 y = *reinterpret_cast<const float4*>(qv + j0);
                                     const float d0 = y.x - x[cc].x, d1 = y.y - x[cc].y, d2 = y.z - x[cc].z,
                                                 d3 = y.w - x[cc].w;
                                     acc = fmaf(d0, d0, acc);
@@ -925,7 +1027,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                                 for (int e = 0; e < 4; ++e) {
                                     const int jj = (g + cc) * 64 + ql * 4 + e;
                                     if (g + cc < nchunk && jj < L) {
-                                        const float d = s_q[jj] - row[jj];
+                                        const float d = qv[jj] - row[jj];
                                         acc = fmaf(d, d, acc);
                                     }
                                 }
@@ -950,7 +1052,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                         acc = p;  // the full distance
                     }
                 }
-                if (act && ql == 0) ++c_dist;
+                if (act && ql == 0 && !from_rck) ++c_dist;
                 if (alive && ql == 0) {
                     const float d = acc;
                     if (d * (1.0f - kRhoEd) <= s_Ublk) {
@@ -970,6 +1072,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
             }
             if (k > 1 && appended) atomicAdd(&s_app, appended);
             __syncthreads();
+            if (SH && tid == 0) s_nrck = 0;  // every thread has read it
             tick(2);
             if (k > 1 && s_app) hist_refresh(a, q, st, s_tmp, &s_Ublk);
             __syncthreads();
@@ -991,17 +1094,18 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
     if (a.blk_cnt) {
         // per-block totals in plain stores (the host adds them up): same-address
         // atomics from every block at once would serialise at the end of the grid
-        __shared__ unsigned long long s_cnt[4][5];
-        unsigned long long v[5] = {c_scanned, c_bounded, c_dist, c_abandon,
-                                   (unsigned long long)c_bytes / 16 + (unsigned long long)c_bounded * 16ull};
-        for (int i = 0; i < 5; ++i)
+        __shared__ unsigned long long s_cnt[4][kBlkCnt];
+        unsigned long long v[kBlkCnt] = {c_scanned, c_bounded, c_dist, c_abandon,
+                                         (unsigned long long)c_bytes / 16 + (unsigned long long)c_bounded * 16ull,
+                                         c_rck, c_bft};
+        for (int i = 0; i < kBlkCnt; ++i)
             for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
         if (lane == 0)
-            for (int i = 0; i < 5; ++i) s_cnt[wave][i] = v[i];
+            for (int i = 0; i < kBlkCnt; ++i) s_cnt[wave][i] = v[i];
         __syncthreads();
-        if (tid < 5 && (pass == 0 || worked)) {
+        if (tid < kBlkCnt && (pass == 0 || worked)) {
             const unsigned long long t = s_cnt[0][tid] + s_cnt[1][tid] + s_cnt[2][tid] + s_cnt[3][tid];
-            unsigned long long* p = a.blk_cnt + (size_t)blockIdx.x * 5 + tid;
+            unsigned long long* p = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
             *p = (pass == 0 ? 0ull : *p) + t;
         }
     }
@@ -1167,7 +1271,7 @@ int Workspace::ensure_stats() {
     for (auto& e : ev) MESSI_HIP_TRY(hipEventCreate(&e));
     MESSI_HIP_TRY(hipHostMalloc((void**)&h_counters, sizeof(QCounters), 0));
     MESSI_HIP_TRY(hipHostMalloc((void**)&h_prof, sizeof(unsigned long long) * 4 * 4096, 0));
-    MESSI_HIP_TRY(hipHostMalloc((void**)&h_blk_cnt, sizeof(unsigned long long) * 5 * 4096, 0));
+    MESSI_HIP_TRY(hipHostMalloc((void**)&h_blk_cnt, sizeof(unsigned long long) * kBlkCnt * 4096, 0));
     return MESSI_OK;
 }
 
@@ -1206,7 +1310,7 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
         MESSI_TRY(ws->counters.alloc(sizeof(QCounters)));
         MESSI_TRY(ws->err.alloc(sizeof(uint32_t) * 4));
         MESSI_TRY(ws->prof.alloc(sizeof(unsigned long long) * 4 * 4096));
-        MESSI_TRY(ws->blk_cnt.alloc(sizeof(unsigned long long) * 5 * 4096));
+        MESSI_TRY(ws->blk_cnt.alloc(sizeof(unsigned long long) * kBlkCnt * 4096));
         MESSI_TRY(ws->lbpart.alloc(sizeof(LbPart) * (size_t)nqa * ((nL + kLeafBlock - 1) / kLeafBlock)));
         if (!ws->h_err) MESSI_HIP_TRY(hipHostMalloc((void**)&ws->h_err, sizeof(uint32_t) * 4, 0));
         ws->nq = nqa;
@@ -1224,10 +1328,11 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
     return MESSI_OK;
 }
 
-// Scan blocks: as many as can be resident at once (all instances of the scan
-// kernel share one grid, so the per-block statistics line up across passes).
-int scan_grid() {
-    static int blocks = 0;
+// Scan blocks: as many as can be resident at once (the passes of a variant
+// share one grid, so the per-block statistics line up across passes).
+int scan_grid(bool sh) {
+    static int grid[2] = {0, 0};
+    int& blocks = grid[sh ? 1 : 0];
     if (!blocks) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
@@ -1235,9 +1340,12 @@ int scan_grid() {
             if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
         }
         int per = 4;
-        const void* fns[] = {(const void*)scan_kernel<true, 0>, (const void*)scan_kernel<true, 1>,
-                             (const void*)scan_kernel<false, 0>, (const void*)scan_kernel<false, 1>};
-        for (const void* f : fns) {
+        const void* fns[2][4] = {
+            {(const void*)scan_kernel<true, 0, false>, (const void*)scan_kernel<true, 1, false>,
+             (const void*)scan_kernel<false, 0, false>, (const void*)scan_kernel<false, 1, false>},
+            {(const void*)scan_kernel<true, 0, true>, (const void*)scan_kernel<true, 1, true>,
+             (const void*)scan_kernel<false, 0, true>, (const void*)scan_kernel<false, 1, true>}};
+        for (const void* f : fns[sh ? 1 : 0]) {
             int nb = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kScanThreads, 0) == hipSuccess && nb > 0)
                 per = std::min(per, nb);
@@ -1247,7 +1355,33 @@ int scan_grid() {
     return blocks;
 }
 
+// One pass of the ordered scan in the variant the call needs.
+int launch_scan(const QArgs& a, bool vec, int pass, bool sh, hipStream_t s) {
+    const dim3 g(scan_grid(sh)), b(kScanThreads);
+    const int v = (vec ? 4 : 0) | (pass ? 2 : 0) | (sh ? 1 : 0);
+    switch (v) {
+        case 0: hipLaunchKernelGGL((scan_kernel<false, 0, false>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((scan_kernel<false, 0, true>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((scan_kernel<false, 1, false>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((scan_kernel<false, 1, true>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((scan_kernel<true, 0, false>), g, b, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((scan_kernel<true, 0, true>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((scan_kernel<true, 1, false>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((scan_kernel<true, 1, true>), g, b, 0, s, a); break;
+    }
+    if (pass) MESSI_LAUNCH_CHECK("rescan");
+    else MESSI_LAUNCH_CHECK("scan");
+    return MESSI_OK;
+}
+
 }  // namespace
+
+bool row_filter_path(int32_t mode, int32_t nq, bool matrix_only) {
+    if (mode != MESSI_MODE_BF16 || matrix_only) return false;
+    int32_t max_q = kRowFilterMaxQ;
+    if (const char* v = std::getenv("MESSI_ROW_FILTER_MAX_Q")) max_q = std::atoi(v);
+    return nq <= max_q;
+}
 
 int refresh_bounds(QArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(refresh_kernel, dim3(a.nq), dim3(256), 0, s, a);
@@ -1294,6 +1428,7 @@ struct CallArgs {
     hipStream_t s;
     int64_t* out_idx;
     float* out_dist;
+    bool matrix_only = false;  // BF16: keep few queries on the matrix-core filter
 };
 
 int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap, uint32_t cap_min = 0) {
@@ -1387,14 +1522,16 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_scatter");
     MESSI_TRY(mark(4));
-    if (mode == MESSI_MODE_BF16) {
+    const bool rowf = row_filter_path(mode, nq, c.matrix_only);
+    if (mode == MESSI_MODE_BF16 && !rowf) {
         MESSI_TRY(bf16_scan(ix, a, ws, s, timing));
     } else {
         const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
-        const dim3 g(scan_grid()), b(kScanThreads);
-        if (vec) hipLaunchKernelGGL((scan_kernel<true, 0>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((scan_kernel<false, 0>), g, b, 0, s, a);
-        MESSI_LAUNCH_CHECK("scan");
+        if (rowf) {
+            MESSI_TRY(bf16_row_prep(ix, a, ws, s));
+            a.rf_tau = kRowFilterTau;
+        }
+        MESSI_TRY(launch_scan(a, vec, 0, rowf, s));
         MESSI_TRY(mark(7));
         // k > 1: exact k-th bound and compaction, and a second pass for a
         // query whose buffer overflowed (that pass exits at once otherwise).
@@ -1404,9 +1541,7 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
         if (c.kmax > 1) {
             hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 0);
             MESSI_LAUNCH_CHECK("fixup");
-            if (vec) hipLaunchKernelGGL((scan_kernel<true, 1>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((scan_kernel<false, 1>), g, b, 0, s, a);
-            MESSI_LAUNCH_CHECK("rescan");
+            MESSI_TRY(launch_scan(a, vec, 1, rowf, s));
             hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 1);
             MESSI_LAUNCH_CHECK("fixup");
         }
@@ -1443,8 +1578,8 @@ int decode_error(uint32_t err) {
 
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
-                uint32_t cap_min) {
-    CallArgs c{ix, queries, nq, kmax, kq, mode, s, out_idx, out_dist};
+                uint32_t cap_min, bool matrix_only) {
+    CallArgs c{ix, queries, nq, kmax, kq, mode, s, out_idx, out_dist, matrix_only};
     Workspace* ws = nullptr;
     QArgs a;
     uint32_t cap = 0;
@@ -1498,8 +1633,9 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     };
     uint32_t err = 0;
     QCounters hc{};
-    const int sg = scan_grid();
-    const bool fp32 = mode == MESSI_MODE_FP32;
+    const bool rowf = row_filter_path(mode, nq, false);
+    const int sg = scan_grid(rowf);
+    const bool fp32 = mode == MESSI_MODE_FP32 || rowf;  // the ordered scan runs
     const unsigned long long* hprof = nullptr;
     const unsigned long long* hcnt = nullptr;
     int32_t retries = 0;
@@ -1511,7 +1647,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         if (a.prof && fp32) {
             MESSI_HIP_TRY(hipMemcpyAsync(ws->h_prof, a.prof, sizeof(unsigned long long) * 4 * sg,
                                          hipMemcpyDeviceToHost, s));
-            MESSI_HIP_TRY(hipMemcpyAsync(ws->h_blk_cnt, a.blk_cnt, sizeof(unsigned long long) * 5 * sg,
+            MESSI_HIP_TRY(hipMemcpyAsync(ws->h_blk_cnt, a.blk_cnt, sizeof(unsigned long long) * kBlkCnt * sg,
                                          hipMemcpyDeviceToHost, s));
             hprof = ws->h_prof;
             hcnt = ws->h_blk_cnt;
@@ -1529,12 +1665,16 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         }
         break;
     }
+    unsigned long long bf_rows = 0;
     for (int bb = 0; hcnt && bb < sg; ++bb) {
-        hc.scanned += hcnt[(size_t)bb * 5 + 0];
-        hc.bounded += hcnt[(size_t)bb * 5 + 1];
-        hc.distance += hcnt[(size_t)bb * 5 + 2];
-        hc.abandoned += hcnt[(size_t)bb * 5 + 3];
-        hc.bytes += hcnt[(size_t)bb * 5 + 4];
+        const unsigned long long* h = hcnt + (size_t)bb * kBlkCnt;
+        hc.scanned += h[0];
+        hc.bounded += h[1];
+        hc.distance += h[2];
+        hc.abandoned += h[3];
+        hc.bytes += h[4];
+        hc.recheck += h[5];
+        bf_rows += h[6];
     }
     // BF16 mode: a query whose candidates or filter pairs overflowed their
     // buffers is answered again, alone, by the FP32 path (which reruns and
@@ -1590,7 +1730,10 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         stats->scan_launches = (hc.reruns ? 2 : 1) + 2 * retries;
         stats->reruns = (int32_t)hc.reruns + retries;
         stats->fallbacks = fallbacks;
-        if (mode == MESSI_MODE_BF16) {
+        if (rowf) {
+            const int Lp = (ix->len + 31) / 32 * 32;
+            stats->bf16_flops = (int64_t)bf_rows * 2 * Lp;
+        } else if (mode == MESSI_MODE_BF16) {
             const int Lp = (ix->len + 31) / 32 * 32;
             stats->ms_bf16_filter = ws->bf_ms_filter;
             stats->ms_bf16_recheck = ws->bf_ms_recheck;

@@ -11,10 +11,12 @@
 // admitted query holds its share of a lane's workspace until it completes.
 //
 // In BF16 mode a lone waiting query (the queue holds at most one when a lane
-// frees up) is answered by itself in FP32 mode: a batch of one gains nothing
-// from the matrix-core filter, whose cost is a pass over the BF16 rows of
-// every leaf the query visits, while the FP32 scan bounds each member by its
-// word first.  As soon as queries queue up they go in BF16 batches.
+// frees up) becomes a launch of one, which the search answers with the
+// ordered scan and its BF16 row filter: a batch of one gains nothing from the
+// matrix-core filter, whose cost is a pass over the BF16 rows of every leaf
+// the query visits, while the scan bounds each member by its word first and
+// then reads half a row for it.  As soon as queries queue up they go in
+// batches on the matrix-core filter.
 //
 // A lane's whole launch (copies in, the search, copies out) is recorded once
 // per batch shape (query count, largest k, mode, buffer size) into a HIP graph
@@ -66,7 +68,6 @@ struct Lane {
     hipStream_t s = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    bool solo = false;               // the batch is one query answered in FP32 mode
     int32_t kmax = 0;
     int32_t mode = MESSI_MODE_BF16;  // of the batch in flight
     std::set<Shape> seen;            // shapes run eagerly once
@@ -88,7 +89,7 @@ constexpr size_t kMaxPending = 1u << 20;
 struct Server {
     const Index* ix = nullptr;
     int32_t mode = MESSI_MODE_BF16;
-    bool solo_fp32 = true;  // BF16 mode: a lone waiting query runs alone in FP32 mode
+    bool row_filter = true;  // BF16 mode: a launch of one query takes the row-filtered scan
     bool use_graphs = true;
     int32_t batch = 1;  // queries per lane
     messi_server_counters stats{};  // guarded by mu
@@ -112,7 +113,8 @@ struct Server {
         MESSI_HIP_TRY(hipMemcpyAsync(ln.d_q.p, ln.h_q, sizeof(float) * (size_t)nq * L, hipMemcpyHostToDevice, ln.s));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.d_k.p, ln.h_k, sizeof(int32_t) * (size_t)nq, hipMemcpyHostToDevice, ln.s));
         MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, ln.kmax, ln.d_k.as<int32_t>(), ln.mode, ln.s,
-                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, cap_min));
+                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, cap_min,
+                              !row_filter));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.h_idx, ln.d_idx.p, sizeof(int64_t) * (size_t)nq * ln.kmax,
                                      hipMemcpyDeviceToHost, ln.s));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.h_dist, ln.d_dist.p, sizeof(float) * (size_t)nq * ln.kmax,
@@ -160,7 +162,7 @@ struct Server {
             kmax = std::max(kmax, ln.batch[i].k);
         }
         ln.kmax = kmax;
-        ln.mode = (ln.batch[0].fp32 || ln.solo) ? MESSI_MODE_FP32 : mode;
+        ln.mode = ln.batch[0].fp32 ? MESSI_MODE_FP32 : mode;
         *ln.h_err = 0;
         uint32_t cap_min = 0;
         if (ln.batch[0].fp32)
@@ -198,7 +200,7 @@ struct Server {
             std::lock_guard<std::mutex> lk(mu);
             stats.batches += 1;
             if (ln.mode == MESSI_MODE_BF16) stats.bf16_batches += 1;
-            if (ln.solo) stats.solo_fp32 += 1;
+            if (row_filter_path(ln.mode, nq, !row_filter)) stats.row_filter += 1;
             if (recorded) stats.graphs_recorded += 1;
             if (replayed) stats.graph_replays += 1;
             if (!recorded && !replayed) stats.eager_launches += 1;
@@ -270,16 +272,14 @@ struct Server {
             for (auto& ln : lanes) {
                 if (ln.busy) continue;
                 {
-                    // a batch, or one query on its own in FP32 mode: a re-queued
-                    // one, or (BF16 mode) the only query waiting
+                    // a batch, or a re-queued query on its own in FP32 mode
                     std::lock_guard<std::mutex> lk(mu);
-                    ln.solo = solo_fp32 && pending.size() == 1 && !pending.front().fp32;
                     while (!pending.empty() && (int32_t)ln.batch.size() < batch) {
                         const bool alone = pending.front().fp32;
                         if (alone && !ln.batch.empty()) break;
                         ln.batch.push_back(std::move(pending.front()));
                         pending.pop_front();
-                        if (alone || ln.solo) break;
+                        if (alone) break;
                     }
                 }
                 if (ln.batch.empty()) {
@@ -367,7 +367,7 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     Server* sv = new Server();
     sv->ix = ix;
     sv->mode = mode;
-    sv->solo_fp32 = mode == MESSI_MODE_BF16 && !(flags & MESSI_SERVER_BATCH_ONLY);
+    sv->row_filter = !(flags & MESSI_SERVER_BATCH_ONLY);
     sv->use_graphs = !(flags & MESSI_SERVER_NO_GRAPHS);
     sv->device = ix->device;
     const int nl = std::min(4, slots);

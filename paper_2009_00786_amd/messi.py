@@ -24,7 +24,7 @@ MESSI_EOVERFLOW = -6
 MODE_FP32 = 0
 MODE_BF16 = 1
 MODE_APPROX = 2  # approximate: the best leaf's members only (not exact)
-SERVER_BATCH_ONLY = 0x100  # OR into a server mode: no lone FP32 queries in BF16 mode
+SERVER_BATCH_ONLY = 0x100  # OR into a server mode: launches of one query also use the matrix-core filter
 SERVER_NO_GRAPHS = 0x200   # OR into a server mode: eager launches, no HIP graphs
 MAX_K = 1024
 
@@ -82,7 +82,7 @@ class KnnStats(ctypes.Structure):
 
 
 class ServerStats(ctypes.Structure):
-    _fields_ = [("batches", ctypes.c_int64), ("bf16_batches", ctypes.c_int64), ("solo_fp32", ctypes.c_int64),
+    _fields_ = [("batches", ctypes.c_int64), ("bf16_batches", ctypes.c_int64), ("row_filter", ctypes.c_int64),
                 ("requeued", ctypes.c_int64), ("eager_launches", ctypes.c_int64),
                 ("graphs_recorded", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
                 ("lanes", ctypes.c_int32), ("batch", ctypes.c_int32)]

@@ -1,6 +1,8 @@
-"""GPU parity of the batched BF16 matrix-core filter + compensated fp32 recheck.
+"""GPU parity of the BF16 mode: the batched matrix-core filter + compensated
+fp32 recheck, and (for a call of one query) the ordered scan whose survivors
+are first tested on their BF16 rows.
 
-The filter may only discard a series whose exact distance provably exceeds
+Either filter may only discard a series whose exact distance provably exceeds
 the current bound, so the answers must equal the oracle's brute force
 (indices bit-exact, distances within 1e-5 relative)."""
 import numpy as np
@@ -131,4 +133,88 @@ def test_bf16_needs_shadow(torch_cuda, messi):
     with pytest.raises(messi.MessiError) as e:
         ix.knn(z[:2].contiguous(), 1, mode=messi.MODE_BF16)
     assert e.value.code == messi.MESSI_EINVAL
+    ix.close()
+
+
+# ---- the row-filtered scan (BF16 mode, one query per call) -----------------
+
+def _one_by_one(ix, q, k, torch, mode):
+    idx = np.zeros((len(q), k), dtype=np.int64)
+    dist = np.zeros((len(q), k), dtype=np.float32)
+    stats = []
+    for i in range(len(q)):
+        gi, gd, st = ix.knn(torch.from_numpy(q[i:i + 1].copy()).cuda(), k, mode=mode, stats=True)
+        idx[i], dist[i] = gi.cpu().numpy()[0], gd.cpu().numpy()[0]
+        stats.append(st)
+    return idx, dist, stats
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_row_filter_single_queries_match_oracle(tiny_bf16, oracle_mod, torch_cuda, messi, k):
+    w = tiny_bf16
+    _say("row filter, single queries, k=%d" % k)
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"], k, nthreads=8)
+    gi, gd, stats = _one_by_one(w["ix"], w["q"], k, torch_cuda, messi.MODE_BF16)
+    _check(gi, gd, oidx, od)
+    # fresh walks (far from every row): the BF16 rows are tested and some are dropped
+    tested = sum(st["bf16_flops"] for st in stats[:8])
+    assert tested > 0
+    for st in stats[:8]:
+        assert st["series_recheck"] <= st["series_distance"]
+    assert sum(st["series_recheck"] for st in stats[:8]) < sum(st["series_distance"] for st in stats[:8])
+    # and equal to the FP32 mode bit for bit
+    fi, fd, _ = _one_by_one(w["ix"], w["q"], k, torch_cuda, messi.MODE_FP32)
+    np.testing.assert_array_equal(gi, fi)
+    np.testing.assert_array_equal(gd, fd)
+
+
+def test_row_filter_for_a_batch(tiny_bf16, oracle_mod, torch_cuda, messi, monkeypatch):
+    """The row-filtered scan over a batch (blocks share the grid across queries)."""
+    w = tiny_bf16
+    monkeypatch.setenv("MESSI_ROW_FILTER_MAX_Q", "64")
+    for k in (1, 10):
+        _say("row filter, batch of %d, k=%d" % (len(w["q"]), k))
+        oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"], k, nthreads=8)
+        gi, gd, st = w["ix"].knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=messi.MODE_BF16, stats=True)
+        _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+        assert st["bf16_flops"] > 0 and st["bf16_rounds"] == 0
+
+
+def test_row_filter_candidate_overflow_recovers(tiny_bf16, oracle_mod, torch_cuda, messi, monkeypatch):
+    w = tiny_bf16
+    monkeypatch.setenv("MESSI_CANDIDATE_CAP", "16")
+    k = 30
+    _say("row filter, candidate buffer of 16, k=%d" % k)
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"][:4], k, nthreads=8)
+    gi, gd, _ = _one_by_one(w["ix"], w["q"][:4], k, torch_cuda, messi.MODE_BF16)
+    _check(gi, gd, oidx, od)
+
+
+@pytest.mark.parametrize("n,length,w,b,cap,k", BF16_SHAPES)
+def test_row_filter_shapes(torch_cuda, messi, datagen_mod, oracle_mod, n, length, w, b, cap, k):
+    torch = torch_cuda
+    _say("row filter n=%d len=%d w=%d b=%d cap=%d k=%d" % (n, length, w, b, cap, k))
+    z = oracle_mod.znorm(datagen_mod.random_walks(n, length, seed=41, stream=0))
+    q = oracle_mod.znorm(datagen_mod.random_walks(3, length, seed=42, stream=1))
+    q = np.concatenate([q, z[[0, n - 1]]])
+    ix = messi.Index(torch.from_numpy(z).cuda(), w, b, cap, bf16_shadow=True)
+    oidx, od, _ = oracle_mod.knn_brute(z, q, k, nthreads=8)
+    gi, gd, _ = _one_by_one(ix, q, k, torch, messi.MODE_BF16)
+    _check(gi, gd, oidx, od)
+    ix.close()
+
+
+def test_row_filter_ties_and_unnormalised(torch_cuda, messi, oracle_mod):
+    torch = torch_cuda
+    rng = np.random.default_rng(12)
+    z = (rng.standard_normal((4000, 64)) * 30.0 + 100.0).astype(np.float32)
+    z[50:400] = z[9]
+    z[700:710] = 0.0
+    q = np.concatenate([z[[9, 700, 3999]], (rng.standard_normal((3, 64)) * 30 + 100).astype(np.float32)])
+    ix = messi.Index(torch.from_numpy(z).cuda(), 8, 8, 60, bf16_shadow=True)
+    for k in (1, 7, 360):
+        _say("row filter, unnormalised with ties, k=%d" % k)
+        oidx, od, _ = oracle_mod.knn_brute(z, q, k, nthreads=8)
+        gi, gd, _ = _one_by_one(ix, q, k, torch, messi.MODE_BF16)
+        _check(gi, gd, oidx, od)
     ix.close()

@@ -171,4 +171,4 @@ def test_graph_replays_match_eager_answers(served, messi, torch_cuda, mode_name,
     else:
         assert st["graphs_recorded"] >= 1 and st["graph_replays"] >= 1
     if flags == "batch_only" or mode_name == "FP32":
-        assert st["solo_fp32"] == 0
+        assert st["row_filter"] == 0
