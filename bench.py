@@ -46,6 +46,9 @@ WORKLOADS = {
                  "z-normalised; open-loop Poisson at 200, 1000, 5000 queries/s, k=10, half noisy dataset rows and "
                  "half fresh mixture draws; BF16 continuous-batching server vs fp32 single-query FIFO",
             n=200_000_000, length=128, data="mixture", rates=(200, 1000, 5000), headline_rate=1000),
+    6: dict(name="streaming series: one random walk of 100M + 255 points cut into its 100M sliding windows of 256 "
+                 "(step 1), z-normalised per window and indexed; exact 1-NN, 100 single queries",
+            n=100_000_000, length=256, queries=100, k=1),
 }
 
 
@@ -149,6 +152,8 @@ def main():
         return bench_batched(args)
     if args.config in (4, 5):
         return bench_serving(args)
+    if args.config == 6:
+        return bench_windows(args)
     wl = dict(WORKLOADS[args.config])
     if args.n:
         wl["n"] = args.n
@@ -346,6 +351,133 @@ def make_batch(data, z_rows_gpu_fn, b, nq, length, seed_off=0):
     sig = np.array([(0.01, 0.1, 1.0)[i % 3] for i in range(nq - half)])
     noisy = datagen.add_noise(base, sig, row0=b * nq)
     return torch.cat([fresh, torch.from_numpy(noisy).to(data.device)]).contiguous()
+
+
+def bench_windows(args):
+    """Config 6: the windows of one long random walk as the collection.  A
+    step is the windows pass (z-normalised per window), the index build over
+    the windows and the queries answered one at a time."""
+    import torch
+
+    import datagen
+    from paper_2009_00786_amd import messi
+    wl = dict(WORKLOADS[6])
+    if args.n:
+        wl["n"] = args.n
+        wl["name"] += " (n=%d)" % args.n
+    n, length, nq, k = wl["n"], wl["length"], wl["queries"], wl["k"]
+    w, b, cap = 16, 8, 2000
+    m = n + length - 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    messi.load()
+    piece = 4096
+    pieces = (m + piece - 1) // piece
+    log("generating one random walk of %d points on the GPU (%d pieces of %d, stitched)" % (m, pieces, piece))
+    walk = torch.empty((pieces, piece), dtype=torch.float32, device=dev)
+    for r0 in range(0, pieces, 1_000_000):
+        datagen.gpu_random_walks(walk[r0:r0 + 1_000_000], row0=r0)
+    # piece r continues from the last value of piece r - 1
+    ends = walk[:, -1].double()
+    walk += (torch.cumsum(ends, 0) - ends).float()[:, None]
+    long_series = walk.view(-1)[:m]
+    rows = torch.empty((n, length), dtype=torch.float32, device=dev)
+    qraw = datagen.random_walks(nq, length, seed=datagen.SEED_QUERY, stream=datagen.STREAM_QUERY)
+    queries = torch.from_numpy(qraw).to(dev)
+    messi.znorm_(queries)
+    torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        r = min(args.cpu_rows, n)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        messi.windows(long_series[:r + length - 1], length, 1, True, out=rows[:r])
+        torch.cuda.synchronize()
+        log("cpu baseline: oracle brute force, %d queries x %d windows, %d threads" % (args.cpu_queries, r, threads))
+        cpu = cpu_baseline(rows, qraw, k, length, n, r, min(args.cpu_queries, nq), threads)
+        log("  ", cpu)
+
+    win_ms, build_ms, query_ms, lat, infos = [], [], [], [], []
+    ans_i = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    ans_d = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    ix = None
+    self_ok = True
+    for step in range(args.warmup + args.steps):
+        timed = step >= args.warmup
+        if ix is not None:
+            ix.close()
+            ix = None
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        messi.windows(long_series, length, 1, True, out=rows)
+        ev1.record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ix = messi.Index(rows, w, b, cap)
+        t2 = time.perf_counter()
+        for qi in range(nq):
+            a = time.perf_counter()
+            ix.knn(queries[qi:qi + 1], k, out=(ans_i[qi:qi + 1], ans_d[qi:qi + 1]))
+            e = time.perf_counter()
+            if timed:
+                lat.append((e - a) * 1e3)
+        t3 = time.perf_counter()
+        # a window used as the query finds its own start at distance 0
+        probe = int(datagen.uniform_ints(1, n, 62 + step, 5)[0])
+        pi, pd = ix.knn(rows[probe:probe + 1].clone(), 1)
+        self_ok &= int(pi[0, 0]) == probe and float(pd[0, 0]) == 0.0
+        info = ix.info()
+        log("step %d%s: windows %.1f ms, build %.1f ms, queries %.1f ms" % (
+            step, "" if timed else " (warmup)", ev0.elapsed_time(ev1), (t2 - t1) * 1e3, (t3 - t2) * 1e3))
+        if timed:
+            win_ms.append(ev0.elapsed_time(ev1))
+            build_ms.append((t2 - t1) * 1e3)
+            query_ms.append((t3 - t2) * 1e3)
+            infos.append(info)
+    steps = args.steps
+    qps = nq * steps / (sum(query_ms) / 1e3)
+    lat_a = np.array(lat)
+    wms = float(np.mean(win_ms))
+    win_bytes = n * length * 4 + m * 4  # every window written, the long series read once
+    roof = {"bound": "hbm", "achieved": win_bytes / (wms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "traffic": traffic_from_profiles("znorm_strided_kernel<4, 4>")}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = "znorm_strided_kernel<4, 4> (windows)"
+    roof["bytes_per_launch"] = win_bytes
+    roof["ms_per_launch"] = wms
+    res = {
+        "metric": METRIC,
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean(win_ms) + np.mean(build_ms) + np.mean(query_ms)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "len": length, "long_series_points": m, "step": 1,
+                   "segments": w, "card_bits": b, "leaf_cap": cap, "queries": nq, "k": k,
+                   "mode": "fp32, one query per call"},
+        "p50_ms": float(np.percentile(lat_a, 50)),
+        "p99_ms": float(np.percentile(lat_a, 99)),
+        "windows_ms": wms,
+        "windows_gbps": roof["achieved"],
+        "build_ms": float(np.mean(build_ms)),
+        "build_gbps": n * length * 4 / (np.mean(build_ms) / 1e3) / 1e9,
+        "roofline": roof,
+        "self_match": self_ok,
+        "index": {"n_leaves": infos[-1]["n_leaves"], "max_leaf": infos[-1]["max_leaf"],
+                  "levels": infos[-1]["levels"]},
+        "cpu_baseline": cpu,
+        "measurement": "a step = the windows pass (HIP events on its stream) + the index build over the windows + "
+                       "the queries answered one at a time (value, p50, p99)",
+    }
+    print(json.dumps(res), flush=True)
 
 
 def bench_batched(args):

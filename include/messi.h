@@ -188,6 +188,21 @@ int messi_export_leaves(const messi_index* index, messi_leaf* host_leaves, uint3
  * zeros.  Synchronous when stream == NULL, else stream-ordered. */
 int messi_znorm(float* series, int64_t n, int32_t len, void* stream);
 
+/* The windows of a long series as a collection (paper, Preliminaries: a
+ * streaming series is cut into subsequences of the query length by a sliding
+ * window, and those are indexed).  Writes window r = long_series[r * step ..
+ * r * step + len) to out_rows[r][len] for r = 0 .. count - 1, where
+ * count = (m - len) / step + 1 (a tail shorter than a step is left out).  With
+ * znorm = 1 each window is z-normalised by its own statistics exactly as
+ * messi_znorm does (the same fp64 sums, bit for bit); with znorm = 0 it is
+ * copied.  long_series[m] and out_rows[count][len] are device memory and must
+ * not overlap.  The result is an ordinary collection for messi_build; a k-NN
+ * answer's index r is the window starting at r * step.  Limits: 1 <= len <=
+ * 1024, m >= len, step >= 1, count < 2^32, znorm in {0, 1}.  Non-finite values
+ * with znorm = 1 -> MESSI_EINVAL.  Synchronous. */
+int messi_windows(const float* long_series, int64_t m, int32_t len, int64_t step, int32_t znorm, float* out_rows,
+                  void* stream);
+
 /* The iSAX breakpoints of card_bits bits: host_out[j - 1] = fl32(Phi^-1(j / 2^b)),
  * j = 1 .. 2^b - 1.  Host-only; needs no GPU. */
 int messi_breakpoints(int32_t card_bits, float* host_out);

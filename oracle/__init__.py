@@ -95,6 +95,19 @@ def znorm(x) -> np.ndarray:
     return z
 
 
+def windows(long_series, length: int, step: int = 1, znorm_windows: bool = True) -> np.ndarray:
+    """Subsequences of a streaming series by a sliding window (Preliminaries:
+    the windows of the query length are what gets indexed): row r is
+    long_series[r*step : r*step + length], for every r whose window fits,
+    then z-normalised per window as any collection is."""
+    x = _f32(long_series).ravel()
+    if length < 1 or step < 1 or x.size < length:
+        raise ValueError("need 1 <= length <= len(long_series) and step >= 1")
+    count = (x.size - length) // step + 1
+    rows = np.stack([x[r * step:r * step + length] for r in range(count)])
+    return znorm(rows) if znorm_windows else rows
+
+
 def paa(z, segments: int) -> np.ndarray:
     """Segment means, fp32, fold-halving order (PAA, Preliminaries)."""
     z = _f32(z)

@@ -119,6 +119,34 @@ int messi_znorm(float* series, int64_t n, int32_t len, void* stream) {
     return MESSI_OK;
 }
 
+int messi_windows(const float* long_series, int64_t m, int32_t len, int64_t step, int32_t znorm, float* out_rows,
+                  void* stream) {
+    clear_error();
+    if (len < 1 || len > MESSI_MAX_LEN) return fail(MESSI_EINVAL, "len must be in [1, 1024]");
+    if (m < len) return fail(MESSI_EINVAL, "the long series is shorter than one window");
+    if (step < 1) return fail(MESSI_EINVAL, "step must be >= 1");
+    if (znorm != 0 && znorm != 1) return fail(MESSI_EINVAL, "znorm must be 0 or 1");
+    const int64_t count = (m - len) / step + 1;
+    if (count >= (int64_t(1) << 32)) return fail(MESSI_EINVAL, "more than 2^32 - 1 windows");
+    if (!long_series || !out_rows) return fail(MESSI_EINVAL, "null pointer");
+    MESSI_TRY(current_device_ok());
+    if (!is_device_pointer(long_series)) return fail(MESSI_EINVAL, "long_series is not a device pointer");
+    if (!is_device_pointer(out_rows)) return fail(MESSI_EINVAL, "out_rows is not a device pointer");
+    const uintptr_t a0 = (uintptr_t)long_series, a1 = a0 + (uintptr_t)m * sizeof(float);
+    const uintptr_t b0 = (uintptr_t)out_rows, b1 = b0 + (uintptr_t)count * (uintptr_t)len * sizeof(float);
+    if (a0 < b1 && b0 < a1) return fail(MESSI_EINVAL, "out_rows overlaps long_series");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf flag;
+    MESSI_TRY(flag.alloc(sizeof(int)));
+    MESSI_HIP_TRY(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    MESSI_TRY(windows_device(long_series, count, len, step, znorm == 1, out_rows, s, flag.as<int>()));
+    int h = 0;
+    MESSI_HIP_TRY(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    if (h) return fail(MESSI_EINVAL, "long_series contains non-finite values");
+    return MESSI_OK;
+}
+
 messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
                             int32_t leaf_cap, const messi_build_opts* opts) {
     clear_error();

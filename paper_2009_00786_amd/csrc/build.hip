@@ -289,9 +289,12 @@ __device__ __forceinline__ float quotient_f32(double c, double sigma, double rs)
     return (float)__ddiv_rn(c, sigma);
 }
 
+// Row r is read from in + r * in_stride (in_stride = L for a collection; the
+// window step for the windows of a long series, which overlap) and written to
+// out + r * L.
 template <int EP, int R>
 __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, float* out, int64_t n, int L,
-                                                            int* nonfinite) {
+                                                            int64_t in_stride, int* nonfinite) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
     const int64_t n_waves = (int64_t)gridDim.x * 4;
@@ -301,7 +304,7 @@ __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, flo
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t row = row0 + r;
-            const float* src = in + (size_t)(row < n ? row : 0) * (size_t)L;
+            const float* src = in + (size_t)(row < n ? row : 0) * (size_t)in_stride;
 #pragma unroll
             for (int k = 0; k < EP; ++k) {
                 const int j = lane + 64 * k;
@@ -355,6 +358,18 @@ __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, flo
         }
     }
     if (bad) atomicOr(nonfinite, 1);
+}
+
+// The windows of a long series copied as rows: row r = src[r * step ..
+// r * step + L), one wave per row at a time.
+__global__ void __launch_bounds__(256) windows_copy_kernel(const float* __restrict__ src, int64_t step, int64_t n,
+                                                           int L, float* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n; r += (int64_t)gridDim.x * 4) {
+        const float* a = src + (size_t)r * (size_t)step;
+        float* b = out + (size_t)r * (size_t)L;
+        for (int j = lane; j < L; j += 64) b[j] = a[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -938,6 +953,39 @@ struct Timer {
 
 // ---------------------------------------------------------------------------
 
+int windows_device(const float* src, int64_t count, int32_t len, int64_t step, bool znorm, float* out,
+                   hipStream_t s, int* d_flag) {
+    if (znorm && len > 32) {
+        // z-normalised straight from the long series: every window's values
+        // are read once from HBM and again from the caches for the overlaps
+        int P = 64;
+        while (P < len) P <<= 1;
+        const int blocks = launch_blocks((count + 3) / 4, 4, 256 * 16);
+        switch (P / 64) {
+#define MESSI_WN_CASE(EP, R)                                                                                      \
+    case EP:                                                                                                      \
+        hipLaunchKernelGGL((znorm_strided_kernel<EP, R>), dim3(blocks), dim3(256), 0, s, src, out, count, len, step, \
+                           d_flag);                                                                               \
+        break;
+            MESSI_WN_CASE(1, 8)
+            MESSI_WN_CASE(2, 4)
+            MESSI_WN_CASE(4, 4)
+            MESSI_WN_CASE(8, 2)
+            MESSI_WN_CASE(16, 1)
+#undef MESSI_WN_CASE
+            default: break;
+        }
+        MESSI_LAUNCH_CHECK("windows");
+        return MESSI_OK;
+    }
+    const int blocks = launch_blocks((count + 3) / 4, 4, 256 * 16);
+    hipLaunchKernelGGL(windows_copy_kernel, dim3(blocks), dim3(256), 0, s, src, step, count, len, out);
+    MESSI_LAUNCH_CHECK("windows_copy");
+    // short windows: z-normalised in place by the collection kernel
+    if (znorm) return znorm_device(out, count, len, s, d_flag);
+    return MESSI_OK;
+}
+
 int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_flag) {
     if (len > 32) {
         int P = 64;
@@ -948,7 +996,7 @@ int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_fl
 #define MESSI_ZN_CASE(EP, R)                                                                                  \
     case EP:                                                                                                  \
         hipLaunchKernelGGL((znorm_strided_kernel<EP, R>), dim3(blocks), dim3(256), 0, s, series, series, n, len, \
-                           d_flag);                                                                           \
+                           (int64_t)len, d_flag);                                                             \
         break;
             MESSI_ZN_CASE(1, 8)
             MESSI_ZN_CASE(2, 4)

@@ -121,6 +121,10 @@ void breakpoints_as241(int card_bits, float* out);
 
 // build.hip
 int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_flag);
+// Rows r = 0 .. count - 1 of out[count][len] from src[r * step ..], z-normalised
+// as znorm_device does when znorm is set.
+int windows_device(const float* src, int64_t count, int32_t len, int64_t step, bool znorm, float* out,
+                   hipStream_t s, int* d_flag);
 int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t w, int32_t b, int32_t cap,
                 const messi_build_opts& opts);
 

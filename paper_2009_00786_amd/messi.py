@@ -30,7 +30,8 @@ MAX_K = 1024
 
 EXPORTED = [
     "messi_build", "messi_build_ex", "messi_knn", "messi_knn_ex", "messi_free", "messi_index_info",
-    "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_breakpoints", "messi_last_error",
+    "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_windows", "messi_breakpoints",
+    "messi_last_error",
     "messi_server_create", "messi_server_submit", "messi_server_poll", "messi_server_stats", "messi_server_clock_ms",
     "messi_server_destroy",
 ]
@@ -123,6 +124,8 @@ def load():
         lib.messi_export_leaves.restype = ctypes.c_int
         lib.messi_znorm.argtypes = [vp, i64, i32, vp]
         lib.messi_znorm.restype = ctypes.c_int
+        lib.messi_windows.argtypes = [vp, i64, i32, i64, i32, vp, vp]
+        lib.messi_windows.restype = ctypes.c_int
         lib.messi_breakpoints.argtypes = [i32, vp]
         lib.messi_breakpoints.restype = ctypes.c_int
         lib.messi_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -165,6 +168,23 @@ def breakpoints(card_bits: int) -> np.ndarray:
     out = np.zeros(255, dtype=np.float32)
     _check(load().messi_breakpoints(card_bits, out.ctypes.data))
     return out[:(1 << card_bits) - 1].copy()
+
+
+def windows(long_series, length, step=1, znorm=True, out=None, stream=None):
+    """The windows of a 1-D CUDA fp32 tensor as a [count, length] collection:
+    row r is long_series[r * step : r * step + length], z-normalised per
+    window when znorm (count = (m - length) // step + 1)."""
+    assert long_series.is_cuda and long_series.dtype.is_floating_point and long_series.is_contiguous()
+    import torch
+    m = long_series.numel()
+    if m < length:
+        raise MessiError(MESSI_EINVAL, "the long series is shorter than one window")
+    count = (m - length) // step + 1 if step >= 1 else 0
+    if out is None:
+        out = torch.empty((max(count, 1), length), dtype=torch.float32, device=long_series.device)
+    _check(load().messi_windows(ctypes.c_void_p(long_series.data_ptr()), m, length, step, int(znorm),
+                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
 
 
 def znorm_(series, stream=None):

@@ -506,3 +506,53 @@ def test_approx_picks_the_smallest_bound_and_never_beats_exact(oracle_mod, datag
     # a dataset row's own leaf has bound 0, and the row is its own answer
     lf, ia, da, _ = oracle_mod.knn_approx(z, 8, 8, leaves, pos, z[[77, 6001]], 1)
     assert list(ia[:, 0]) == [77, 6001] and np.all(da == 0)
+
+
+# ---- sliding windows of a streaming series (Preliminaries) -----------------
+
+def test_windows_closed_form(oracle_mod):
+    """1, 2, ..., 7 in windows of 3: every window is (c - 1, c, c + 1), whose
+    z-normalised form is (-sqrt(3/2), 0, sqrt(3/2)) (population sigma
+    sqrt(2/3)); with step 2 the windows start at 0, 2, 4, and of 0 .. 7 the
+    last value (a tail shorter than a step) starts no window."""
+    s = np.arange(1, 8, dtype=np.float32)
+    w = oracle_mod.windows(s, 3, 1)
+    assert w.shape == (5, 3)
+    want = np.array([-np.sqrt(1.5), 0.0, np.sqrt(1.5)], dtype=np.float32)
+    np.testing.assert_allclose(w, np.tile(want, (5, 1)), rtol=2e-7, atol=0)
+    raw = oracle_mod.windows(s, 3, 2, znorm_windows=False)
+    np.testing.assert_array_equal(raw, [[1, 2, 3], [3, 4, 5], [5, 6, 7]])
+    raw = oracle_mod.windows(np.arange(8, dtype=np.float32), 3, 2, znorm_windows=False)
+    np.testing.assert_array_equal(raw[:, 0], [0, 2, 4])  # the tail value 7 starts no window
+    assert oracle_mod.windows(s, 7, 1).shape == (1, 7)
+
+
+def test_windows_count_and_starts(oracle_mod):
+    ramp = np.arange(1000, dtype=np.float32)
+    for length, step in ((16, 1), (100, 7), (256, 256), (999, 1), (1000, 3)):
+        raw = oracle_mod.windows(ramp, length, step, znorm_windows=False)
+        assert raw.shape == ((1000 - length) // step + 1, length)
+        np.testing.assert_array_equal(raw[:, 0], np.arange(raw.shape[0]) * step)
+        np.testing.assert_array_equal(raw[:, -1] - raw[:, 0], length - 1)
+
+
+def test_windows_non_overlapping_equal_the_reshaped_collection(oracle_mod, datagen_mod):
+    walk = datagen_mod.random_walks(1, 64 * 40, seed=5)[0]
+    np.testing.assert_array_equal(oracle_mod.windows(walk, 64, 64), oracle_mod.znorm(walk.reshape(40, 64)))
+
+
+def test_windows_invariants(oracle_mod, datagen_mod):
+    """Each z-normalised window has mean 0 and population variance 1 within
+    the rounding of its fp64 statistics; a window is unchanged by an affine
+    change of the stream (z-normalisation forgets offset and scale, up to the
+    rounding of the scaled values); a constant stretch gives zeros."""
+    walk = datagen_mod.random_walks(1, 5000, seed=6)[0].astype(np.float64)
+    w = oracle_mod.windows(walk, 128, 3)
+    np.testing.assert_allclose(w.astype(np.float64).mean(axis=1), 0.0, atol=1e-5)
+    np.testing.assert_allclose(w.astype(np.float64).var(axis=1), 1.0, atol=1e-5)
+    w2 = oracle_mod.windows((walk * 4.0 - 1000.0).astype(np.float32), 128, 3)
+    np.testing.assert_allclose(w2, w, atol=2e-4)
+    s = walk.copy()
+    s[2000:2300] = 7.0
+    wz = oracle_mod.windows(s, 128, 1)
+    assert np.all(wz[2000:2300 - 127] == 0.0) and np.any(wz[1999] != 0.0)
