@@ -62,6 +62,17 @@ def _load():
         lib.oracle_knn_brute.restype = ctypes.c_int
         lib.oracle_knn_isax.argtypes = [vp, i64, i32, vp, i32, i32, vp, i64, vp, vp, i32, i32, vp, vp, vp]
         lib.oracle_knn_isax.restype = ctypes.c_int
+        lib.oracle_dtw64.argtypes = [vp, vp, i32, i32]
+        lib.oracle_dtw64.restype = d
+        lib.oracle_envelope.argtypes = [vp, i32, i32, vp, vp]
+        lib.oracle_lb_keogh.argtypes = [vp, vp, vp, i32]
+        lib.oracle_lb_keogh.restype = d
+        lib.oracle_mindist_dtw_sq.argtypes = [vp, vp, i32, i32, vp, vp, i32, vp, d]
+        lib.oracle_mindist_dtw_sq.restype = d
+        lib.oracle_knn_brute_dtw.argtypes = [vp, i64, i32, vp, i32, i32, i32, ctypes.c_int, vp, vp]
+        lib.oracle_knn_brute_dtw.restype = ctypes.c_int
+        lib.oracle_knn_isax_dtw.argtypes = [vp, i64, i32, vp, i32, i32, vp, i64, vp, vp, i32, i32, i32, vp, vp, vp]
+        lib.oracle_knn_isax_dtw.restype = ctypes.c_int
         lib.oracle_leaf_bounds.argtypes = [vp, i32, i32, i32, vp, i64, vp]
         lib.oracle_knn_approx.argtypes = [vp, i64, i32, i32, i32, vp, i64, vp, vp, i32, i32, i64, vp, vp, vp]
         lib.oracle_knn_approx.restype = ctypes.c_int
@@ -209,6 +220,81 @@ def knn_isax(data, words_, card_bits, leaves, pos, queries, k: int, return_stats
                                  dd.ctypes.data, stats.ctypes.data)
     if rc != 0:
         raise ValueError("bad arguments to knn_isax")
+    out = (idx, dd, np.sqrt(dd).astype(np.float32))
+    return out + (stats,) if return_stats else out
+
+
+def dtw64(q, x, band: int) -> float:
+    """Squared DTW under a Sakoe-Chiba band of half-width `band`, fp64, by the
+    textbook recurrence (the paper's DTW experiment; Berndt & Clifford)."""
+    q, x = _f32(q).ravel(), _f32(x).ravel()
+    assert q.size == x.size
+    return _load().oracle_dtw64(q.ctypes.data, x.ctypes.data, q.size, int(band))
+
+
+def envelope(q, band: int):
+    """LB_Keogh envelope of q over the band: (up, lo), fp32."""
+    q = _f32(q).ravel()
+    up, lo = np.empty_like(q), np.empty_like(q)
+    _load().oracle_envelope(q.ctypes.data, q.size, int(band), up.ctypes.data, lo.ctypes.data)
+    return up, lo
+
+
+def lb_keogh(q, x, band: int) -> float:
+    """LB_Keogh^2 of x against the envelope of q, fp64."""
+    up, lo = envelope(q, band)
+    x = _f32(x).ravel()
+    return _load().oracle_lb_keogh(up.ctypes.data, lo.ctypes.data, x.ctypes.data, x.size)
+
+
+def mindist_dtw_sq(q, band: int, card, prefix, card_bits: int, segments: int, slack: float = 0.0) -> float:
+    """The index bound under DTW: per segment the envelope's max / min against
+    the node's region (LB_PAA of the envelope), fp64."""
+    up, lo = envelope(q, band)
+    bp = np.zeros(255, dtype=np.float32)
+    b = breakpoints(card_bits)
+    bp[:b.size] = b
+    c = np.zeros(16, np.uint8)
+    p = np.zeros(16, np.uint8)
+    c[:segments] = card[:segments]
+    p[:segments] = prefix[:segments]
+    return _load().oracle_mindist_dtw_sq(up.ctypes.data, lo.ctypes.data, up.size, segments, c.ctypes.data,
+                                         p.ctypes.data, card_bits, bp.ctypes.data, float(slack))
+
+
+def knn_brute_dtw(data, queries, k: int, band: int, nthreads: int = 1):
+    """Exact k-NN under DTW by full scan: k smallest (DTW64, index).
+    Returns (idx, dtw64, fl32(sqrt(dtw64)))."""
+    data, queries = _f32(data), _f32(queries)
+    n, length = data.shape
+    nq = queries.shape[0]
+    idx = np.zeros((nq, k), dtype=np.int64)
+    dd = np.zeros((nq, k), dtype=np.float64)
+    rc = _load().oracle_knn_brute_dtw(data.ctypes.data, n, length, queries.ctypes.data, nq, k, int(band),
+                                      int(nthreads), idx.ctypes.data, dd.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments to knn_brute_dtw")
+    return idx, dd, np.sqrt(dd).astype(np.float32)
+
+
+def knn_isax_dtw(data, words_, card_bits, leaves, pos, queries, k: int, band: int, return_stats=False):
+    """DTW k-NN through the oracle's index with the envelope bounds and
+    LB_Keogh (must equal knn_brute_dtw)."""
+    data, queries = _f32(data), _f32(queries)
+    wd = np.ascontiguousarray(words_, dtype=np.uint8)
+    n, length = data.shape
+    w = wd.shape[1]
+    nq = queries.shape[0]
+    leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+    pos = np.ascontiguousarray(pos, dtype=np.uint32)
+    idx = np.zeros((nq, k), dtype=np.int64)
+    dd = np.zeros((nq, k), dtype=np.float64)
+    stats = np.zeros((nq, 4), dtype=np.int64)
+    rc = _load().oracle_knn_isax_dtw(data.ctypes.data, n, length, wd.ctypes.data, w, card_bits, leaves.ctypes.data,
+                                     leaves.size, pos.ctypes.data, queries.ctypes.data, nq, k, int(band),
+                                     idx.ctypes.data, dd.ctypes.data, stats.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments to knn_isax_dtw")
     out = (idx, dd, np.sqrt(dd).astype(np.float32))
     return out + (stats,) if return_stats else out
 

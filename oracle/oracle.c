@@ -29,6 +29,12 @@
  *   - BF16 filter of the batched search (beyond the paper): the filtered
  *     value and its rounding bound E, derived term by term at
  *     oracle_bf16_error_bound; a member may be discarded only if f - E > U.
+ *   - DTW search (the paper's closing experiment): a Sakoe-Chiba band of
+ *     half-width r around the diagonal (the caller picks r; the paper's
+ *     window of 10% of the length is r = floor(L / 10)), the squared DTW of
+ *     the textbook recurrence in fp64, the query's LB_Keogh envelope over
+ *     that band, and per segment its maximum / minimum against the node's
+ *     region as the index bound (oracle_mindist_dtw_sq).
  *
  * Parity pins live in tests/ (they compare against the paper's worked word,
  * textbook quantiles, closed forms, invariants and brute force).  Functions
@@ -402,12 +408,15 @@ static void topk_insert(topk_t* t, double d, int64_t idx) {
 /* Brute-force exact k-NN (the definition of the answer).                   */
 /* ------------------------------------------------------------------------ */
 
+double oracle_dtw64(const float* q, const float* x, int32_t len, int32_t r);
+
 typedef struct {
     const float* data;
     int64_t r0, r1;
     int32_t len;
     const float* queries;
     int32_t nq, k;
+    int32_t band;   /* < 0: Euclidean (D64); else DTW with this half-width */
     double* d;      /* [nq][k] */
     int64_t* idx;   /* [nq][k] */
     int32_t* size;  /* [nq] */
@@ -418,18 +427,35 @@ static void* brute_worker(void* arg) {
     for (int32_t q = 0; q < j->nq; ++q) {
         topk_t t = {j->k, 0, j->d + (size_t)q * (size_t)j->k, j->idx + (size_t)q * (size_t)j->k};
         const float* qs = j->queries + (size_t)q * (size_t)j->len;
-        for (int64_t r = j->r0; r < j->r1; ++r)
-            topk_insert(&t, oracle_d64(qs, j->data + (size_t)r * (size_t)j->len, j->len), r);
+        for (int64_t r = j->r0; r < j->r1; ++r) {
+            const float* x = j->data + (size_t)r * (size_t)j->len;
+            topk_insert(&t, j->band < 0 ? oracle_d64(qs, x, j->len) : oracle_dtw64(qs, x, j->len, j->band), r);
+        }
         j->size[q] = t.size;
     }
     return NULL;
 }
+
+static int knn_brute_any(const float* data, int64_t n, int32_t len, const float* queries, int32_t nq, int32_t k,
+                         int32_t band, int nthreads, int64_t row_offset, int64_t* out_idx, double* out_d64);
 
 /* out_d64 / out_idx: [nq][k], ascending (D64, index).  Rows are data[n][len].
  * Uses nthreads threads over contiguous row ranges, merged at the end.
  * row_offset is added to every returned index (for scans of a slice). */
 int oracle_knn_brute(const float* data, int64_t n, int32_t len, const float* queries, int32_t nq, int32_t k,
                      int nthreads, int64_t row_offset, int64_t* out_idx, double* out_d64) {
+    return knn_brute_any(data, n, len, queries, nq, k, -1, nthreads, row_offset, out_idx, out_d64);
+}
+
+/* The same under DTW with a band of half-width r (ascending (DTW64, index)). */
+int oracle_knn_brute_dtw(const float* data, int64_t n, int32_t len, const float* queries, int32_t nq, int32_t k,
+                         int32_t r, int nthreads, int64_t* out_idx, double* out_d) {
+    if (r < 0) return -1;
+    return knn_brute_any(data, n, len, queries, nq, k, r, nthreads, 0, out_idx, out_d);
+}
+
+static int knn_brute_any(const float* data, int64_t n, int32_t len, const float* queries, int32_t nq, int32_t k,
+                         int32_t band, int nthreads, int64_t row_offset, int64_t* out_idx, double* out_d64) {
     if (n < 1 || len < 1 || nq < 0 || k < 1 || k > n) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
@@ -438,7 +464,7 @@ int oracle_knn_brute(const float* data, int64_t n, int32_t len, const float* que
     pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
     for (int t = 0; t < nthreads; ++t) {
         brute_job* j = &jobs[t];
-        j->data = data; j->len = len; j->queries = queries; j->nq = nq; j->k = k;
+        j->data = data; j->len = len; j->queries = queries; j->nq = nq; j->k = k; j->band = band;
         j->r0 = n * t / nthreads; j->r1 = n * (t + 1) / nthreads;
         j->d = (double*)malloc(sizeof(double) * (size_t)nq * (size_t)k + 8);
         j->idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)nq * (size_t)k + 8);
@@ -683,5 +709,175 @@ int oracle_knn_approx(const float* data, int64_t n, int32_t len, int32_t w, int3
         }
     }
     free(lb);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dynamic time warping (the paper's closing experiment: the index is left   */
+/* as it is, and searched with the LB_Keogh envelope of the query).          */
+/*                                                                          */
+/* DTW^2(q, x) under a Sakoe-Chiba band of half-width r is the smallest sum  */
+/* of (q_i - x_j)^2 over the monotone warping paths from (0, 0) to           */
+/* (L-1, L-1) whose cells all satisfy |i - j| <= r.  It is computed by the   */
+/* textbook recurrence                                                       */
+/*   D(i, j) = c(i, j) + min(D(i-1, j), D(i, j-1), D(i-1, j-1)),  D(0,0) = c  */
+/* in fp64, c = fl64(d * d) with d = fl64(q_i - x_j), each sum rounded once.  */
+/* A cell's value is a fixed function of its three neighbours, so every      */
+/* order of evaluating the cells gives these same values.  r >= L - 1 is the */
+/* unconstrained DTW; r = 0 leaves only the diagonal, the squared Euclidean  */
+/* distance summed in index order (oracle_d64).                              */
+/* ------------------------------------------------------------------------ */
+double oracle_dtw64(const float* q, const float* x, int32_t len, int32_t r) {
+    if (r > len - 1) r = len - 1;
+    if (r < 0) r = 0;
+    double* prev = (double*)malloc(sizeof(double) * (size_t)len);
+    double* cur = (double*)malloc(sizeof(double) * (size_t)len);
+    for (int32_t i = 0; i < len; ++i) {
+        const int32_t lo = i - r > 0 ? i - r : 0, hi = i + r < len - 1 ? i + r : len - 1;
+        const int32_t plo = i - 1 - r > 0 ? i - 1 - r : 0, phi = i - 1 + r < len - 1 ? i - 1 + r : len - 1;
+        for (int32_t j = lo; j <= hi; ++j) {
+            const double d = (double)q[i] - (double)x[j];
+            const double c = d * d;
+            double best = INFINITY;
+            if (i == 0 && j == 0) best = 0.0;
+            if (i > 0 && j >= plo && j <= phi && prev[j] < best) best = prev[j];
+            if (i > 0 && j - 1 >= plo && j - 1 <= phi && prev[j - 1] < best) best = prev[j - 1];
+            if (j - 1 >= lo && cur[j - 1] < best) best = cur[j - 1];
+            cur[j] = c + best;
+        }
+        double* t = prev;
+        prev = cur;
+        cur = t;
+    }
+    const double out = prev[len - 1];
+    free(prev);
+    free(cur);
+    return out;
+}
+
+/* The query's envelope over the band (LB_Keogh): up[j] / lo[j] = the largest /
+ * smallest q_t with |t - j| <= r. */
+void oracle_envelope(const float* q, int32_t len, int32_t r, float* up, float* lo) {
+    for (int32_t j = 0; j < len; ++j) {
+        const int32_t a = j - r > 0 ? j - r : 0, b = j + r < len - 1 ? j + r : len - 1;
+        float u = q[a], l = q[a];
+        for (int32_t t = a + 1; t <= b; ++t) {
+            if (q[t] > u) u = q[t];
+            if (q[t] < l) l = q[t];
+        }
+        up[j] = u;
+        lo[j] = l;
+    }
+}
+
+/* LB_Keogh^2: the squared distance from x to the envelope (0 inside it),
+ * fp64, summed in index order.  Every warping path in the band matches each
+ * x_j with some q_t, |t - j| <= r, which lies inside [lo_j, up_j]. */
+double oracle_lb_keogh(const float* up, const float* lo, const float* x, int32_t len) {
+    double s = 0.0;
+    for (int32_t j = 0; j < len; ++j) {
+        double d = 0.0;
+        if (x[j] > up[j]) d = (double)x[j] - (double)up[j];
+        else if (x[j] < lo[j]) d = (double)lo[j] - (double)x[j];
+        s += d * d;
+    }
+    return s;
+}
+
+/* The index bound under DTW: per segment i, U_i = max of up and L_i = min of
+ * lo over the segment's m values; against the node's region [a, b] (widened
+ * by slack), d_i = a - U_i if U_i < a, L_i - b if L_i > b, else 0; bound =
+ * m sum_i d_i^2.  A series whose segment mean lies in [a, b] has at least m of
+ * (mean - U_i)^2 in its LB_Keogh terms over the segment (mean of the positive
+ * parts, Cauchy-Schwarz), so the bound is below LB_Keogh, hence below DTW. */
+double oracle_mindist_dtw_sq(const float* up, const float* lo, int32_t len, int32_t w, const uint8_t* card,
+                             const uint8_t* prefix, int32_t card_bits, const float* bp, double slack) {
+    const int32_t m = len / w;
+    double s = 0.0;
+    for (int32_t i = 0; i < w; ++i) {
+        double U = -INFINITY, L = INFINITY;
+        for (int32_t t = i * m; t < (i + 1) * m; ++t) {
+            if ((double)up[t] > U) U = (double)up[t];
+            if ((double)lo[t] < L) L = (double)lo[t];
+        }
+        double a, b;
+        region(bp, card_bits, card[i], prefix[i], &a, &b);
+        a -= slack;
+        b += slack;
+        double d = 0.0;
+        if (U < a) d = a - U;
+        else if (L > b) d = L - b;
+        s += d * d;
+    }
+    return (double)m * s;
+}
+
+/* Exact DTW k-NN through the index: leaves in ascending DTW bound, stop at
+ * the first whose bound exceeds the k-th distance; inside a leaf, skip a
+ * series whose word's bound or whose LB_Keogh exceeds it; else its DTW.  The
+ * slack and the (1 - 2^-40) scaling are those of oracle_knn_isax.  Must return
+ * exactly oracle_knn_brute_dtw's answer.  stats (may be NULL): [nq][4] =
+ * leaves visited, series bounded, LB_Keogh computed, DTW computed. */
+int oracle_knn_isax_dtw(const float* data, int64_t n, int32_t len, const uint8_t* words, int32_t w,
+                        int32_t card_bits, const oracle_leaf* leaves, int64_t n_leaves, const uint32_t* pos,
+                        const float* queries, int32_t nq, int32_t k, int32_t r, int64_t* out_idx, double* out_d,
+                        int64_t* stats) {
+    if (n < 1 || len < 1 || w < 1 || len % w || k < 1 || k > n || r < 0) return -1;
+    const int32_t m = len / w;
+    float bp[255];
+    oracle_breakpoints(card_bits, bp);
+    double amax = 0.0;
+    for (int64_t i = 0; i < n * (int64_t)len; ++i) {
+        double a = fabs((double)data[i]);
+        if (a > amax) amax = a;
+    }
+    int lg = 0;
+    while ((1 << lg) < m) lg++;
+    const double slack = (double)(lg + 2) * ldexp(1.0, -23) * amax;
+    const double shrink = 1.0 - ldexp(1.0, -40);
+    lb_item* order = (lb_item*)malloc(sizeof(lb_item) * (size_t)n_leaves);
+    float* up = (float*)malloc(sizeof(float) * (size_t)len);
+    float* lo = (float*)malloc(sizeof(float) * (size_t)len);
+    uint8_t full[16];
+    for (int i = 0; i < 16; ++i) full[i] = (uint8_t)card_bits;
+    for (int32_t q = 0; q < nq; ++q) {
+        const float* qs = queries + (size_t)q * (size_t)len;
+        oracle_envelope(qs, len, r, up, lo);
+        for (int64_t l = 0; l < n_leaves; ++l) {
+            order[l].lb = oracle_mindist_dtw_sq(up, lo, len, w, leaves[l].card, leaves[l].prefix, card_bits, bp, slack);
+            order[l].id = l;
+        }
+        qsort(order, (size_t)n_leaves, sizeof(lb_item), lb_cmp);
+        topk_t t = {k, 0, out_d + (size_t)q * (size_t)k, out_idx + (size_t)q * (size_t)k};
+        int64_t visited = 0, bounded = 0, keogh = 0, real = 0;
+        for (int64_t o = 0; o < n_leaves; ++o) {
+            double bsf = (t.size == k) ? t.d[k - 1] : INFINITY;
+            if (order[o].lb * shrink > bsf) break;
+            const oracle_leaf* lf = &leaves[order[o].id];
+            visited++;
+            for (uint32_t j = 0; j < lf->count; ++j) {
+                const uint32_t row = pos[lf->start + j];
+                const float* x = data + (size_t)row * (size_t)len;
+                bsf = (t.size == k) ? t.d[k - 1] : INFINITY;
+                bounded++;
+                if (oracle_mindist_dtw_sq(up, lo, len, w, full, words + (size_t)row * (size_t)w, card_bits, bp,
+                                          slack) * shrink > bsf)
+                    continue;
+                keogh++;
+                if (oracle_lb_keogh(up, lo, x, len) * shrink > bsf) continue;
+                real++;
+                topk_insert(&t, oracle_dtw64(qs, x, len, r), (int64_t)row);
+            }
+        }
+        if (stats) {
+            stats[(size_t)q * 4 + 0] = visited;
+            stats[(size_t)q * 4 + 1] = bounded;
+            stats[(size_t)q * 4 + 2] = keogh;
+            stats[(size_t)q * 4 + 3] = real;
+        }
+    }
+    free(order);
+    free(up);
+    free(lo);
     return 0;
 }
