@@ -43,6 +43,7 @@ extern "C" {
 
 #define MESSI_MAX_SEGMENTS 16
 #define MESSI_MAX_LEN 1024
+#define MESSI_MAX_DTW_BAND 27  /* largest Sakoe-Chiba half-width of messi_knn_dtw */
 #define MESSI_MAX_K 1024
 
 /* Search modes of messi_knn_ex. */
@@ -178,6 +179,24 @@ int messi_export_words(const messi_index* index, uint8_t* host_words);
  * position array: host_leaves[n_leaves], host_pos[n]; leaf l's members are
  * host_pos[start .. start + count), ascending series index. */
 int messi_export_leaves(const messi_index* index, messi_leaf* host_leaves, uint32_t* host_pos);
+
+/* Exact k-NN under dynamic time warping on the same index (paper, closing
+ * experiment: the index is unchanged; the query's LB_Keogh envelope is built
+ * and the index searched with it; warping window 10% of the length, i.e.
+ * band = len / 10).  DTW^2(q, x) is the smallest sum of (q_i - x_j)^2 over the
+ * monotone warping paths from (0, 0) to (len-1, len-1) whose cells satisfy
+ * |i - j| <= band (a Sakoe-Chiba band); band = 0 is the Euclidean distance.
+ * Leaves are visited in ascending envelope bound (per segment, the envelope's
+ * extreme values against the node's region), members are bounded by their
+ * words, then by LB_Keogh against the envelope, then get their DTW; the final
+ * order is the canonical fp64 DTW (every step rounded once, no fused
+ * multiply-add).  Outputs as messi_knn_ex: out_idx[nq][k], out_dist[nq][k] =
+ * fl32(sqrt(DTW^2)), ascending (distance, index).  Limits: 0 <= band <= 27,
+ * 1 <= k <= min(n, 1024).  Synchronous (stream-ordered work, then a wait).
+ * Errors as messi_knn_ex; stats (optional, host) as there, with
+ * series_distance = LB_Keogh computed and series_recheck = DTW computed. */
+int messi_knn_dtw(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t band,
+                  void* stream, int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
 
 /* ---- building blocks ---------------------------------------------------- */
 

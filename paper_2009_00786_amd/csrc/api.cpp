@@ -262,6 +262,25 @@ int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int
     return knn_device(ix, queries, nq, k, mode, (hipStream_t)stream, out_idx, out_dist, stats);
 }
 
+int messi_knn_dtw(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t band,
+                  void* stream, int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    clear_error();
+    if (!index) return fail(MESSI_EINVAL, "index is null");
+    const Index* ix = reinterpret_cast<const Index*>(index);
+    if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
+    if (k < 1 || k > MESSI_MAX_K || (int64_t)k > ix->n) return fail(MESSI_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (band < 0 || band > MESSI_MAX_DTW_BAND) return fail(MESSI_EINVAL, "band must be in [0, 27]");
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (nq == 0) return MESSI_OK;
+    if (!queries || !out_idx || !out_dist) return fail(MESSI_EINVAL, "null pointer argument");
+    if (!is_device_pointer(queries) || !is_device_pointer(out_idx) || !is_device_pointer(out_dist))
+        return fail(MESSI_EINVAL, "queries / out_idx / out_dist must be device pointers");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ix->device)
+        return fail(MESSI_EINVAL, "the index lives on another device");
+    return knn_dtw_device(ix, queries, nq, k, band, (hipStream_t)stream, out_idx, out_dist, stats);
+}
+
 int messi_knn(const messi_index* index, const float* queries, int32_t nq, int32_t k, int64_t* out_idx,
               float* out_dist) {
     return messi_knn_ex(index, queries, nq, k, MESSI_MODE_FP32, nullptr, out_idx, out_dist, nullptr);

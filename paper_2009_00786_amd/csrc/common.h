@@ -131,6 +131,9 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
 // query.hip
 int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
                int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
+// Exact k-NN under DTW with a Sakoe-Chiba band of half-width `band`.
+int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
+                   int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
 
 // bf16.hip
 int build_bf16_shadow(Index* ix, hipStream_t s);

@@ -15,6 +15,7 @@ constexpr int kHistBins = 4096;      // candidate-distance histogram (k > 1 boun
 // Relative error margins (see the exactness notes in query.hip).
 constexpr float kRhoEd = 1.52587890625e-05f;  // 2^-16, fp32 squared-distance error margin
 constexpr float kRhoLb = 2.44140625e-04f;     // 2^-12, lower-bound error margin
+constexpr float kRhoDtw = 2.44140625e-04f;    // 2^-12, fp32 banded-DTW error margin (L <= 1024)
 
 struct Cand {
     float d;       // fp32 squared distance
@@ -43,7 +44,8 @@ constexpr int kBlkCnt = 7;
 
 // Per-query search state (device).
 struct QState {
-    float paa[16];
+    float paa[16];           // ED: the query PAA; DTW: per segment the envelope's minimum
+    float paa_hi[16];        // ED: the query PAA; DTW: per segment the envelope's maximum
     float norm2;
     float delta;             // widening of every region (covers fp32 PAA error of data and query)
     uint32_t U;              // current upper bound on the k-th squared distance (float bits)
@@ -60,7 +62,7 @@ struct QState {
     uint32_t kstride;        // output row stride
     int32_t hbase;           // histogram bin of a distance = (float bits >> 16) - hbase, clamped
     uint32_t rerun;          // the scan runs a second pass from a tightened bound
-    uint32_t pad0;
+    uint32_t ntodo;          // DTW: series of this round waiting for their DTW
 };
 
 // Counters accumulated over a call (device).
@@ -86,6 +88,12 @@ struct QArgs {
     int32_t Lp;                  // BF16 row length (L rounded up to 32)
     float one_minus_h;           // 1 - h of the drop test, rounded down
     float rf_tau;                // the row filter runs while U > rf_tau |q|^2
+    // DTW search
+    int32_t band;                // Sakoe-Chiba half-width; < 0: Euclidean search
+    float rho_d;                 // relative error margin of the distances kept (ED or DTW)
+    uint32_t chunk_lo, chunk_hi; // the scan takes chunks [chunk_lo, chunk_hi) of each query's order
+    Cand* todo;                  // [nq][todo_cap] DTW: (LB_Keogh, series) waiting for their DTW
+    uint32_t todo_cap;
     const float* queries;        // [nq][L]
     int32_t nq;
     QState* qs;
@@ -120,6 +128,8 @@ struct Workspace {
     uint32_t max_chunks = 0;
     DevBuf qs, lb, order, rec, chunk_first, bins, mbins, cursor, hist, approx_d, cand, counters, err, prof, blk_cnt,
         status, lbpart;
+    DevBuf todo;  // DTW search
+    size_t todo_slots = 0;
     uint32_t* h_err = nullptr;  // pinned copy of the call's error flags
     // BF16 path
     int32_t bf_nq = 0;

@@ -51,6 +51,8 @@ namespace messi {
 namespace {
 
 constexpr int kScanThreads = 256;
+// scan variants: Euclidean; Euclidean with the BF16 row filter; LB_Keogh for DTW
+constexpr int kScanEd = 0, kScanRowFilter = 1, kScanDtw = 2;
 constexpr int kEdBatch = 32;  // survivors gathered before a round of distances
 // BF16 calls of at most this many queries run the ordered scan with the BF16
 // row filter; larger batches share member rows on the matrix-core filter
@@ -72,9 +74,12 @@ constexpr int kLeafBlock = 256;  // leaves per block of the bound kernels
 
 // Query summary, computed by every block that needs it: PAA (sequential
 // fp32 sums of each segment, one division), squared norm, largest |value|,
-// finiteness, and the region widening delta.
+// finiteness, and the region widening delta.  The bounds take per segment an
+// interval [plo, phi] of the query side: the PAA value for ED; under DTW the
+// smallest and largest value of the query's LB_Keogh envelope over the
+// segment (exact: minima and maxima of query values).
 struct QSum {
-    float paa[16];
+    float plo[16], phi[16];
     float norm2, amax, delta;
     bool bad;
 };
@@ -100,13 +105,29 @@ __device__ void query_summary(const QArgs& a, const float* row, float* s_q, floa
     }
     __syncthreads();
     if (threadIdx.x < 16) {
-        float s = 0.f;
-        if (threadIdx.x < a.w)
-            for (int j = 0; j < a.m; ++j) s += s_q[threadIdx.x * a.m + j];
-        s_red[8 + threadIdx.x] = threadIdx.x < a.w ? s / (float)a.m : 0.f;
+        const int i = threadIdx.x;
+        float lo = 0.f, hi = 0.f;
+        if (i < a.w && a.band < 0) {
+            float s = 0.f;
+            for (int j = 0; j < a.m; ++j) s += s_q[i * a.m + j];
+            lo = hi = s / (float)a.m;
+        } else if (i < a.w) {
+            // the envelope over segment i: every query value within band of it
+            const int t0 = max(0, i * a.m - a.band), t1 = min(a.L - 1, (i + 1) * a.m - 1 + a.band);
+            lo = hi = s_q[t0];
+            for (int t = t0 + 1; t <= t1; ++t) {
+                lo = fminf(lo, s_q[t]);
+                hi = fmaxf(hi, s_q[t]);
+            }
+        }
+        s_red[8 + i] = lo;
+        s_red[24 + i] = hi;
     }
     __syncthreads();
-    for (int i = 0; i < 16; ++i) out.paa[i] = s_red[8 + i];
+    for (int i = 0; i < 16; ++i) {
+        out.plo[i] = s_red[8 + i];
+        out.phi[i] = s_red[24 + i];
+    }
     out.norm2 = s_red[0] + s_red[1] + s_red[2] + s_red[3];
     out.amax = fmaxf(fmaxf(s_red[4], s_red[5]), fmaxf(s_red[6], s_red[7]));
     const float u = 5.9604644775390625e-08f;  // 2^-24
@@ -123,7 +144,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     __shared__ float s_lo[16 * 257];
     __shared__ float s_hi[16 * 257];
     __shared__ float s_q[MESSI_MAX_LEN];
-    __shared__ float s_red[24];
+    __shared__ float s_red[40];
     __shared__ int s_bad;
     __shared__ unsigned long long s_min[4];
     __shared__ uint32_t s_max[4];
@@ -135,7 +156,10 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     query_summary(a, a.queries + (size_t)q * a.L, s_q, s_red, &s_bad, qs);
     if (blockIdx.x == 0) {
         QState& st = a.qs[q];
-        if (threadIdx.x < 16) st.paa[threadIdx.x] = qs.paa[threadIdx.x];
+        if (threadIdx.x < 16) {
+            st.paa[threadIdx.x] = qs.plo[threadIdx.x];
+            st.paa_hi[threadIdx.x] = qs.phi[threadIdx.x];
+        }
         if (threadIdx.x == 0) {
             st.norm2 = qs.norm2;
             st.delta = qs.delta;
@@ -145,6 +169,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
             st.nsurv = 0;
             st.ovf = 0;
             st.rerun = 0;
+            st.ntodo = 0;
             st.hbase = 0;
             st.lbmax = 0;
             st.argmin = ~0ull;
@@ -166,13 +191,13 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     }
     for (int idx = threadIdx.x; idx < a.w * (A + 1); idx += 256) {
         const int i = idx / (A + 1), c = idx % (A + 1);
-        const float p = qs.paa[i];
+        const float pl = qs.plo[i], ph = qs.phi[i];
         float tl = 0.f, th = 0.f;
         if (c > 0 && c < A) {
             const float lo = s_bp[c - 1] - qs.delta;
             const float hi = s_bp[c - 1] + qs.delta;
-            if (p < lo) tl = (lo - p) * (lo - p);
-            if (p > hi) th = (p - hi) * (p - hi);
+            if (ph < lo) tl = (lo - ph) * (lo - ph);
+            if (pl > hi) th = (pl - hi) * (pl - hi);
         }
         s_lo[i * 257 + c] = tl;
         s_hi[i * 257 + c] = th;
@@ -503,6 +528,11 @@ __device__ __forceinline__ uint32_t word_byte(const uint4& wd, int i) {
 // the bins up to the one where the running count reaches k lies below that
 // bin's upper edge, so the edge bounds the k-th distance from above.  Between
 // kernels the exact k-th is taken from the candidate buffer itself.
+// Distance from x to the envelope [lo, up] (0 inside it): one LB_Keogh term.
+__device__ __forceinline__ float keogh_gap(float x, float up, float lo) {
+    return x > up ? x - up : (x < lo ? lo - x : 0.f);
+}
+
 // acc + the dot product of 8 BF16 pairs, one fused multiply-add per pair (the
 // products of two BF16 values are exact in fp32, so each step rounds once).
 __device__ __forceinline__ float bf16_dot8(const uint4& x, const uint4& y, float acc) {
@@ -559,7 +589,8 @@ __device__ void refresh_compact(QArgs& a, int q, QState& st, uint32_t* s_hist, u
     Cand* c = a.cand + (size_t)q * a.cap;
     if (st.k > 1) {
         const float kth = block_kth([&](uint32_t i) { return c[i].d; }, n, (uint32_t)st.k, s_hist, s_b);
-        if (threadIdx.x == 0 && !isinf(kth) && !isnan(kth)) atomicMin(&st.U, __float_as_uint(upper_u(kth)));
+        if (threadIdx.x == 0 && !isinf(kth) && !isnan(kth))
+            atomicMin(&st.U, __float_as_uint(kth * (1.0f + 2.0f * a.rho_d)));
     }
     __syncthreads();
     const float U = __uint_as_float(st.U);
@@ -570,7 +601,7 @@ __device__ void refresh_compact(QArgs& a, int q, QState& st, uint32_t* s_hist, u
         bool keep = false;
         if (i < n) {
             e = c[i];
-            keep = e.d * (1.0f - kRhoEd) <= U;
+            keep = e.d * (1.0f - a.rho_d) <= U;
         }
         uint32_t total;
         const uint32_t o = block_exclusive_scan(keep ? 1u : 0u, s_tmp, total);  // all reads of this chunk done
@@ -660,11 +691,16 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
 // scan is bound by memory latency, so resident waves matter more than the
 // couple of registers this spills.  The row-filtered variant runs three, with
 // no spills: its BF16 pass keeps twice the rows in flight per wave.
-template <bool VEC, int pass, bool SH>
-__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(SH ? 3 : 4))) scan_kernel(QArgs a) {
+template <bool VEC, int pass, int MODE>
+__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(MODE == kScanRowFilter ? 3 : 4)))
+scan_kernel(QArgs a) {
+    constexpr bool SH = MODE == kScanRowFilter;
+    constexpr bool DTW = MODE == kScanDtw;
     constexpr int kPer = kChunk / kScanThreads;
     __shared__ float s_D[16 * 256];
-    __shared__ float s_q[SH ? 1 : MESSI_MAX_LEN];  // with SH the rare fp32 rows read the query from L2
+    // the query; with SH none (the rare fp32 rows read it from L2); with DTW
+    // its envelope, upper then lower
+    __shared__ float s_q[SH ? 1 : DTW ? 2 * MESSI_MAX_LEN : MESSI_MAX_LEN];
     __shared__ uint32_t s_surv[kChunk + kEdBatch];  // series indices waiting for their distance
     __shared__ uint32_t s_pbase[kChunk];  // word index of the chunk's member 0 if it were in this leaf
     __shared__ float s_plb[kChunk];
@@ -731,8 +767,10 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
         const uint64_t nmemb = st.nmemb;
         const int k = st.k;
         const float range = st.range;
-        const uint64_t nch = (nmemb + kChunk - 1) / kChunk;
-        const uint32_t ncb = nch > (uint64_t)j ? (uint32_t)((nch - (uint64_t)j + G - 1) / G) : 0u;
+        // this call's chunks of the query's order: [chunk_lo, chunk_hi)
+        const uint64_t nch = min((nmemb + kChunk - 1) / kChunk, (uint64_t)a.chunk_hi);
+        const uint64_t jb = (uint64_t)a.chunk_lo + (uint64_t)j;
+        const uint32_t ncb = nch > jb ? (uint32_t)((nch - jb + G - 1) / G) : 0u;
         if (ncb == 0) continue;
         if (timing && tid == 0) s_t[3] = wall_clock64();
         {
@@ -741,20 +779,35 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
             const float mf = (float)a.m;
             for (int idx = tid; idx < a.w * A; idx += kScanThreads) {
                 const int i = idx / A, c = idx % A;
-                const float p = st.paa[i];
+                const float pl = st.paa[i], ph = st.paa_hi[i];
                 float d = 0.f;
                 if (c > 0) {
                     const float lo = a.bp[c - 1] - delta;
-                    if (p < lo) d = lo - p;
+                    if (ph < lo) d = lo - ph;
                 }
                 if (c < A - 1) {
                     const float hi = a.bp[c] + delta;
-                    if (p > hi) d = p - hi;
+                    if (pl > hi) d = pl - hi;
                 }
                 s_D[i * 256 + c] = mf * (d * d);
             }
-            if (!SH)
+            if (DTW) {
+                // LB_Keogh envelope: every query value within the band
+                const float* qg = a.queries + (size_t)q * L;
+                for (int jj = tid; jj < L; jj += kScanThreads) {
+                    const int t0 = max(0, jj - a.band), t1 = min(L - 1, jj + a.band);
+                    float u = qg[t0], l = u;
+                    for (int t = t0 + 1; t <= t1; ++t) {
+                        const float v = qg[t];
+                        u = fmaxf(u, v);
+                        l = fminf(l, v);
+                    }
+                    s_q[jj] = u;
+                    s_q[MESSI_MAX_LEN + jj] = l;
+                }
+            } else if (!SH) {
                 for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
+            }
             if (SH) {
                 const uint4* qb4 = reinterpret_cast<const uint4*>(a.qb) + (size_t)q * npc;
                 for (int jj = tid; jj < npc; jj += kScanThreads) s_qb[jj] = qb4[jj];
@@ -770,7 +823,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
         const OrdRec* recq = a.rec + (size_t)q * a.nL;
         // chunk starts of chunks i0 .. i0 + 63 of this block (call from every thread)
         auto load_cf = [&](uint32_t i0) {
-            if (tid < 64 && i0 + tid < ncb) s_cf[tid] = cfq[(uint64_t)j + (uint64_t)(i0 + tid) * G];
+            if (tid < 64 && i0 + tid < ncb) s_cf[tid] = cfq[jb + (uint64_t)(i0 + tid) * G];
             __syncthreads();
         };
         // The leaves of chunk c, from the order record `r` this thread loaded
@@ -856,13 +909,13 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
         if (rn_ok) rn = recq[t0n + tid];
         __syncthreads();
         float Uc = s_Ublk;
-        uint32_t np = commit_positions((uint64_t)j, t0n, rn, rn_ok, Uc);
+        uint32_t np = commit_positions(jb, t0n, rn, rn_ok, Uc);
         if (np == 0 || s_stop || chunk_stops(Uc)) continue;
         uint4 wd[kPer];
-        uint32_t live = issue_words(np, chunk_len((uint64_t)j), Uc, wd);
+        uint32_t live = issue_words(np, chunk_len(jb), Uc, wd);
         tick(0);
         for (uint32_t i = 0;; ++i) {
-            const uint64_t c = (uint64_t)j + (uint64_t)i * G;
+            const uint64_t c = jb + (uint64_t)i * G;
             bool more = i + 1 < ncb;
             // ---- next chunk's leaf records, in flight during this chunk's filter
             if (more && ((i + 1) & 63u) == 0) load_cf(i + 1);
@@ -1012,8 +1065,19 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                                 const int j0 = (g + cc) * 64 + ql * 4;
                                 if (g + cc < nchunk && j0 < L) {
                                     const float4 y = *reinterpret_cast<const float4*>(qv + j0);
-                                    const float d0 = y.x - x[cc].x, d1 = y.y - x[cc].y, d2 = y.z - x[cc].z,
-                                                d3 = y.w - x[cc].w;
+                                    float d0, d1, d2, d3;
+                                    if (DTW) {
+                                        const float4 lw = *reinterpret_cast<const float4*>(qv + MESSI_MAX_LEN + j0);
+                                        d0 = keogh_gap(x[cc].x, y.x, lw.x);
+                                        d1 = keogh_gap(x[cc].y, y.y, lw.y);
+                                        d2 = keogh_gap(x[cc].z, y.z, lw.z);
+                                        d3 = keogh_gap(x[cc].w, y.w, lw.w);
+                                    } else {
+                                        d0 = y.x - x[cc].x;
+                                        d1 = y.y - x[cc].y;
+                                        d2 = y.z - x[cc].z;
+                                        d3 = y.w - x[cc].w;
+                                    }
                                     acc = fmaf(d0, d0, acc);
                                     acc = fmaf(d1, d1, acc);
                                     acc = fmaf(d2, d2, acc);
@@ -1027,7 +1091,8 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                                 for (int e = 0; e < 4; ++e) {
                                     const int jj = (g + cc) * 64 + ql * 4 + e;
                                     if (g + cc < nchunk && jj < L) {
-                                        const float d = qv[jj] - row[jj];
+                                        const float d = DTW ? keogh_gap(row[jj], qv[jj], qv[MESSI_MAX_LEN + jj])
+                                                            : qv[jj] - row[jj];
                                         acc = fmaf(d, d, acc);
                                     }
                                 }
@@ -1053,7 +1118,14 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
                     }
                 }
                 if (act && ql == 0 && !from_rck) ++c_dist;
-                if (alive && ql == 0) {
+                if (DTW && alive && ql == 0) {
+                    // LB_Keogh within the bound: the series waits for its DTW
+                    if (acc * (1.0f - kRhoEd) <= s_Ublk) {
+                        const uint32_t slot = atomicAdd(&st.ntodo, 1u);
+                        if (slot < a.todo_cap) a.todo[(size_t)q * a.todo_cap + slot] = Cand{acc, gidx};
+                        else st.ovf = 1;
+                    }
+                } else if (alive && ql == 0) {
                     const float d = acc;
                     if (d * (1.0f - kRhoEd) <= s_Ublk) {
                         const uint32_t slot = atomicAdd(&st.ncand, 1u);
@@ -1089,7 +1161,9 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
         // pass 0 writes the block's times; a second pass adds its own
         unsigned long long* pr = a.prof + (size_t)blockIdx.x * 4;
         const unsigned long long v[4] = {s_t[0], s_t[1], s_t[2], wall_clock64() - s_t[4]};
-        for (int i = 0; i < 4; ++i) pr[i] = (pass == 0 ? 0ull : pr[i]) + v[i];
+        // pass 0 of a call starts the sums (DTW rounds after the first add to them)
+        const bool first = pass == 0 && a.chunk_lo == 0;
+        for (int i = 0; i < 4; ++i) pr[i] = (first ? 0ull : pr[i]) + v[i];
     }
     if (a.blk_cnt) {
         // per-block totals in plain stores (the host adds them up): same-address
@@ -1106,7 +1180,7 @@ __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_
         if (tid < kBlkCnt && (pass == 0 || worked)) {
             const unsigned long long t = s_cnt[0][tid] + s_cnt[1][tid] + s_cnt[2][tid] + s_cnt[3][tid];
             unsigned long long* p = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
-            *p = (pass == 0 ? 0ull : *p) + t;
+            *p = (pass == 0 && a.chunk_lo == 0 ? 0ull : *p) + t;
         }
     }
 }
@@ -1120,6 +1194,138 @@ __global__ void status_kernel(QArgs a, uint32_t* out) {
 // --------------------------------------------------------------------------
 // final: canonical fp64 distance of the candidates within U, ordered by (D, idx)
 // --------------------------------------------------------------------------
+// --------------------------------------------------------------------------
+// DTW: banded dynamic time warping in registers
+// --------------------------------------------------------------------------
+// Squared DTW of the query q (LDS) against the series x under a band of
+// half-width r (2r + 1 + 8 <= W), by the textbook recurrence
+//     D(i, j) = c(i, j) + min(D(i-1, j), D(i, j-1), D(i-1, j-1)).
+// Register slot t of row i holds cell (i, i - r + t); going down a row, slot t
+// reads the row above in slots t + 1 (same column) and t (one column left)
+// and its left neighbour from slot t - 1 of the new row, so the row is
+// updated in place in ascending t.  The x values of row i sit in xw[t] and
+// shift down one slot per row; the value entering the last slot is used at
+// least 8 rows later, which hides its load.
+// T = double: the canonical value, each subtraction, product and sum rounded
+// once in fp64 (no fused multiply-add), equal to the plain recurrence in any
+// evaluation order.  T = float: the search value, within a relative 2^-12 of
+// it for L <= 1024 (each path sum is a sequential sum of at most 2L - 1
+// non-negative terms, each term within 3 units of rounding); it stops, and
+// returns +inf, once a whole row of the band exceeds limit / (1 - 2^-12):
+// every path crosses that row, and sums only grow along a path.
+template <int W, typename T>
+__device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, int L, int r, float limit) {
+    constexpr bool F64 = sizeof(T) == 8;
+    const T inf = (T)__builtin_huge_valf();
+    T D[W];
+    float xw[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+        D[t] = t == r ? (T)0 : inf;  // the virtual cell (-1, -1) starts the path
+        const int j = t - r;
+        xw[t] = (j >= 0 && j < L) ? x[j] : 0.f;
+    }
+    for (int i = 0; i < L; ++i) {
+        const float qi = q[i];
+        T left = inf, rowmin = inf;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            const int j = i - r + t;
+            const T above = (t + 1 < W) ? D[t + 1] : inf;
+            T m = D[t] < above ? D[t] : above;
+            m = left < m ? left : m;
+            T v;
+            if (F64) {
+                const double d = __dsub_rn((double)qi, (double)xw[t]);
+                v = (T)__dadd_rn(__dmul_rn(d, d), (double)m);
+            } else {
+                const float d = qi - xw[t];
+                v = (T)(d * d + (float)m);
+            }
+            v = (t <= 2 * r && j >= 0 && j < L) ? v : inf;
+            D[t] = v;
+            left = v;
+            rowmin = v < rowmin ? v : rowmin;
+        }
+#pragma unroll
+        for (int t = 0; t + 1 < W; ++t) xw[t] = xw[t + 1];
+        const int jn = i + 1 - r + W - 1;
+        xw[W - 1] = jn < L ? x[jn] : 0.f;
+        if (!F64 && (float)rowmin * (1.0f - kRhoDtw) > limit) return inf;
+    }
+    T out = inf;
+#pragma unroll
+    for (int t = 0; t < W; ++t)
+        if (t == r) out = D[t];
+    return out;
+}
+
+// The series of a round whose LB_Keogh is within the bound get their fp32
+// DTW; those within the bound become candidates, and for k = 1 they lower U.
+template <int W>
+__global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
+    __shared__ float s_q[MESSI_MAX_LEN];
+    const int q = blockIdx.y;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
+    __syncthreads();
+    const uint32_t n = st.ntodo;
+    if (n > a.todo_cap) {
+        // a round left series out (cannot happen with rounds of at most
+        // todo_cap members, checked anyway)
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st.err = 2;
+            atomicOr(a.err_any, 2u);
+        }
+        return;
+    }
+    const Cand* td = a.todo + (size_t)q * a.todo_cap;
+    const float* series = a.series;
+    unsigned long long ndtw = 0;
+    for (uint32_t e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+        const Cand t = td[e];
+        if (t.d * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U))) continue;
+        ++ndtw;
+        const float d = dtw_band<W, float>(s_q, series + (size_t)t.idx * a.L, a.L, a.band,
+                                           __uint_as_float(vload(&st.U)));
+        if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
+            const uint32_t slot = atomicAdd(&st.ncand, 1u);
+            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, t.idx};
+            if (st.k == 1) atomicMin(&st.U, __float_as_uint(d * (1.0f + 2.0f * kRhoDtw)));
+        }
+    }
+    if (a.counters) {
+        for (int off = 32; off >= 1; off >>= 1) ndtw += __shfl_xor(ndtw, off);
+        if ((threadIdx.x & 63) == 0 && ndtw) atomicAdd(&a.counters->recheck, ndtw);
+    }
+}
+
+// Before a DTW round: empty every query's list of waiting series.
+__global__ void __launch_bounds__(256) todo_reset_kernel(QArgs a) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q < a.nq) a.qs[q].ntodo = 0;
+    if (q == 0) a.err_any[2] = 0;
+}
+
+// After a DTW round: count the queries whose order goes on past chunk c1 with
+// a chunk that the bound does not stop (the scan's own stop rule).
+__global__ void __launch_bounds__(256) dtw_active_kernel(QArgs a, uint32_t c1) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= a.nq) return;
+    const QState& st = a.qs[q];
+    if (st.err) return;
+    const uint64_t nch = ((uint64_t)st.nmemb + kChunk - 1) / kChunk;
+    if ((uint64_t)c1 >= nch) return;
+    const uint32_t t0 = a.chunk_first[(size_t)q * a.max_chunks + c1];
+    const float lb0 = a.rec[(size_t)q * a.nL + t0].lb;
+    const float U = __uint_as_float(st.U);
+    const float low = (float)bin_of(lb0, st.range) * (st.range / (float)kNB);
+    if (lb0 * (1.0f - kRhoLb) > U && low * (1.0f - 2.0f * kRhoLb) > U) return;
+    atomicAdd(&a.err_any[2], 1u);
+}
+
+template <int W>
 __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     __shared__ double s_d[kMaxFinal];
     __shared__ uint32_t s_i[kMaxFinal];
@@ -1148,7 +1354,7 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     const Cand* c = a.cand + (size_t)q * a.cap;
     for (uint32_t i = threadIdx.x; i < nc; i += 256) {
         const Cand e = c[i];
-        if (e.d * (1.0f - kRhoEd) <= U) {
+        if (e.d * (1.0f - a.rho_d) <= U) {
             const uint32_t slot = atomicAdd(&s_kept, 1u);
             if (slot < (uint32_t)kMaxFinal) s_i[slot] = e.idx;
         }
@@ -1163,9 +1369,14 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
         }
         return;
     }
-    // D64 of every candidate: the squared differences added one after another
-    // in index order, each operation rounded once (no fused multiply-add)
-    if (kept <= 16) {
+    if (W > 0) {
+        // DTW: the canonical fp64 value of every candidate, a thread each
+        for (uint32_t j = threadIdx.x; j < kept; j += 256)
+            s_d[j] = dtw_band<(W > 0 ? W : 16), double>(s_q, a.series + (size_t)s_i[j] * a.L, a.L, a.band, 0.f);
+    } else if (kept <= 16) {
+        // D64 of every candidate: the squared differences added one after
+        // another in index order, each operation rounded once (no fused
+        // multiply-add).
         // few candidates: each wave stages one candidate's row in LDS with a
         // coalesced load, then one lane sums it in order from LDS (while at
         // most 16 candidates are kept, s_d beyond its first 64 entries is free)
@@ -1330,9 +1541,9 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
 
 // Scan blocks: as many as can be resident at once (the passes of a variant
 // share one grid, so the per-block statistics line up across passes).
-int scan_grid(bool sh) {
-    static int grid[2] = {0, 0};
-    int& blocks = grid[sh ? 1 : 0];
+int scan_grid(int mode) {
+    static int grid[3] = {0, 0, 0};
+    int& blocks = grid[mode];
     if (!blocks) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
@@ -1340,14 +1551,16 @@ int scan_grid(bool sh) {
             if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
         }
         int per = 4;
-        const void* fns[2][4] = {
-            {(const void*)scan_kernel<true, 0, false>, (const void*)scan_kernel<true, 1, false>,
-             (const void*)scan_kernel<false, 0, false>, (const void*)scan_kernel<false, 1, false>},
-            {(const void*)scan_kernel<true, 0, true>, (const void*)scan_kernel<true, 1, true>,
-             (const void*)scan_kernel<false, 0, true>, (const void*)scan_kernel<false, 1, true>}};
-        for (const void* f : fns[sh ? 1 : 0]) {
+        const void* fns[3][4] = {
+            {(const void*)scan_kernel<true, 0, kScanEd>, (const void*)scan_kernel<true, 1, kScanEd>,
+             (const void*)scan_kernel<false, 0, kScanEd>, (const void*)scan_kernel<false, 1, kScanEd>},
+            {(const void*)scan_kernel<true, 0, kScanRowFilter>, (const void*)scan_kernel<true, 1, kScanRowFilter>,
+             (const void*)scan_kernel<false, 0, kScanRowFilter>, (const void*)scan_kernel<false, 1, kScanRowFilter>},
+            {(const void*)scan_kernel<true, 0, kScanDtw>, (const void*)scan_kernel<false, 0, kScanDtw>, nullptr,
+             nullptr}};
+        for (const void* f : fns[mode]) {
             int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kScanThreads, 0) == hipSuccess && nb > 0)
+            if (f && hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kScanThreads, 0) == hipSuccess && nb > 0)
                 per = std::min(per, nb);
         }
         blocks = std::min(cus * std::max(per, 1), 4096);
@@ -1355,19 +1568,27 @@ int scan_grid(bool sh) {
     return blocks;
 }
 
-// One pass of the ordered scan in the variant the call needs.
-int launch_scan(const QArgs& a, bool vec, int pass, bool sh, hipStream_t s) {
-    const dim3 g(scan_grid(sh)), b(kScanThreads);
+// One pass of the ordered scan in the variant the call needs (the DTW
+// variant has no second pass).
+int launch_scan(const QArgs& a, bool vec, int pass, int mode, hipStream_t s) {
+    const dim3 g(scan_grid(mode)), b(kScanThreads);
+    if (mode == kScanDtw) {
+        if (vec) hipLaunchKernelGGL((scan_kernel<true, 0, kScanDtw>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((scan_kernel<false, 0, kScanDtw>), g, b, 0, s, a);
+        MESSI_LAUNCH_CHECK("scan_dtw");
+        return MESSI_OK;
+    }
+    const bool sh = mode == kScanRowFilter;
     const int v = (vec ? 4 : 0) | (pass ? 2 : 0) | (sh ? 1 : 0);
     switch (v) {
-        case 0: hipLaunchKernelGGL((scan_kernel<false, 0, false>), g, b, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((scan_kernel<false, 0, true>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((scan_kernel<false, 1, false>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((scan_kernel<false, 1, true>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((scan_kernel<true, 0, false>), g, b, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((scan_kernel<true, 0, true>), g, b, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((scan_kernel<true, 1, false>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((scan_kernel<true, 1, true>), g, b, 0, s, a); break;
+        case 0: hipLaunchKernelGGL((scan_kernel<false, 0, kScanEd>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((scan_kernel<false, 0, kScanRowFilter>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((scan_kernel<false, 1, kScanEd>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((scan_kernel<false, 1, kScanRowFilter>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((scan_kernel<true, 0, kScanEd>), g, b, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((scan_kernel<true, 0, kScanRowFilter>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((scan_kernel<true, 1, kScanEd>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((scan_kernel<true, 1, kScanRowFilter>), g, b, 0, s, a); break;
     }
     if (pass) MESSI_LAUNCH_CHECK("rescan");
     else MESSI_LAUNCH_CHECK("scan");
@@ -1478,6 +1699,10 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.blk_cnt = counting ? ws->blk_cnt.as<unsigned long long>() : nullptr;
     a.out_idx = c.out_idx;
     a.out_dist = c.out_dist;
+    a.band = -1;
+    a.rho_d = kRhoEd;
+    a.chunk_lo = 0;
+    a.chunk_hi = 0xffffffffu;
     return MESSI_OK;
 }
 
@@ -1510,7 +1735,7 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
         MESSI_TRY(mark(4));
         MESSI_TRY(mark(7));
         MESSI_TRY(mark(5));
-        hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(final_kernel<0>, dim3(nq), dim3(256), 0, s, a);
         MESSI_LAUNCH_CHECK("final");
         MESSI_TRY(mark(6));
         return MESSI_OK;
@@ -1531,7 +1756,7 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
             MESSI_TRY(bf16_row_prep(ix, a, ws, s));
             a.rf_tau = kRowFilterTau;
         }
-        MESSI_TRY(launch_scan(a, vec, 0, rowf, s));
+        MESSI_TRY(launch_scan(a, vec, 0, rowf ? kScanRowFilter : kScanEd, s));
         MESSI_TRY(mark(7));
         // k > 1: exact k-th bound and compaction, and a second pass for a
         // query whose buffer overflowed (that pass exits at once otherwise).
@@ -1541,13 +1766,13 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
         if (c.kmax > 1) {
             hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 0);
             MESSI_LAUNCH_CHECK("fixup");
-            MESSI_TRY(launch_scan(a, vec, 1, rowf, s));
+            MESSI_TRY(launch_scan(a, vec, 1, rowf ? kScanRowFilter : kScanEd, s));
             hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 1);
             MESSI_LAUNCH_CHECK("fixup");
         }
     }
     MESSI_TRY(mark(5));
-    hipLaunchKernelGGL(final_kernel, dim3(nq), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(final_kernel<0>, dim3(nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("final");
     MESSI_TRY(mark(6));
     (void)ix;
@@ -1594,6 +1819,146 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
     return MESSI_OK;
 }
 
+// Rounds of the DTW search: the first takes each query's first 16 chunks of
+// its order (its best leaves, for a tight bound early), each later one twice
+// as many, up to kDtwRoundChunks; a round's waiting list holds every member
+// of its chunks at most once, so it cannot overflow.
+constexpr uint32_t kDtwRoundChunks = 1024;
+
+int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
+                   int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    CallArgs c{ix, queries, nq, k, nullptr, MESSI_MODE_FP32, s, out_idx, out_dist};
+    Workspace* ws = nullptr;
+    QArgs a;
+    uint32_t cap = 0;
+    MESSI_TRY(setup_call(c, stats != nullptr, &ws, a, cap));
+    const bool timing = stats != nullptr;
+    if (timing) MESSI_TRY(ws->ensure_stats());
+    a.band = band;
+    a.rho_d = kRhoDtw;
+    const uint32_t todo_cap = kDtwRoundChunks * (uint32_t)kChunk;
+    if (ws->todo_slots < (size_t)nq * todo_cap) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(ws->todo.alloc(sizeof(Cand) * (size_t)nq * todo_cap));
+        ws->todo_slots = (size_t)nq * todo_cap;
+        ++ws->gen;
+    }
+    a.todo = ws->todo.as<Cand>();
+    a.todo_cap = todo_cap;
+    hipEvent_t* ev = ws->ev;
+    auto mark = [&](int i) -> int {
+        if (timing) MESSI_HIP_TRY(hipEventRecord(ev[i], s));
+        return MESSI_OK;
+    };
+    const unsigned lb_blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((a.nL + kLeafBlock - 1) / kLeafBlock, (8192 + nq - 1) / nq));
+    MESSI_TRY(mark(0));
+    hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a, k, (const int32_t*)nullptr,
+                       (uint32_t)k);
+    MESSI_LAUNCH_CHECK("leaf_lb");
+    MESSI_TRY(mark(2));
+    // the first bound: Euclidean distances to the best leaf's members (the
+    // diagonal path lies in every band, so DTW <= ED)
+    hipLaunchKernelGGL(approx_ed_kernel, dim3(kApproxBlocks, nq), dim3(256), 0, s, a, lb_blocks);
+    MESSI_LAUNCH_CHECK("approx_ed");
+    hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
+    MESSI_LAUNCH_CHECK("approx_select");
+    MESSI_TRY(mark(3));
+    hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("bin_hist");
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("bin_scan");
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("bin_scatter");
+    MESSI_TRY(mark(4));
+    // plan the rounds from the longest order
+    std::vector<QState> hq(nq);
+    MESSI_HIP_TRY(hipMemcpyAsync(hq.data(), a.qs, sizeof(QState) * nq, hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    uint64_t max_nch = 0;
+    for (const QState& h : hq)
+        if (!h.err) max_nch = std::max<uint64_t>(max_nch, ((uint64_t)h.nmemb + kChunk - 1) / kChunk);
+    const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
+    const int W = 2 * band + 9 <= 16 ? 16 : 2 * band + 9 <= 32 ? 32 : 64;
+    const unsigned dtw_blocks = (unsigned)std::max(1, scan_grid(kScanDtw) / std::max(1, nq));
+    const unsigned nqb = (unsigned)((nq + 255) / 256);
+    int rounds = 0;
+    for (uint64_t c0 = 0, size = 16; c0 < max_nch;) {
+        const uint64_t c1 = std::min<uint64_t>(c0 + size, max_nch);
+        a.chunk_lo = (uint32_t)c0;
+        a.chunk_hi = (uint32_t)c1;
+        ++rounds;
+        hipLaunchKernelGGL(todo_reset_kernel, dim3(nqb), dim3(256), 0, s, a);
+        MESSI_LAUNCH_CHECK("todo_reset");
+        MESSI_TRY(launch_scan(a, vec, 0, kScanDtw, s));
+        if (W == 16) hipLaunchKernelGGL(dtw_kernel<16>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
+        else if (W == 32) hipLaunchKernelGGL(dtw_kernel<32>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(dtw_kernel<64>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
+        MESSI_LAUNCH_CHECK("dtw");
+        MESSI_TRY(refresh_bounds(a, s));
+        c0 = c1;
+        size = std::min<uint64_t>(2 * size, kDtwRoundChunks);
+        if (c0 >= max_nch) break;
+        // stop early once no query's order goes on below its bound
+        hipLaunchKernelGGL(dtw_active_kernel, dim3(nqb), dim3(256), 0, s, a, (uint32_t)c0);
+        MESSI_LAUNCH_CHECK("dtw_active");
+        MESSI_HIP_TRY(hipMemcpyAsync(ws->h_err, a.err_any + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        if (*ws->h_err == 0) break;
+    }
+    MESSI_TRY(mark(5));
+    if (W == 16) hipLaunchKernelGGL(final_kernel<16>, dim3(nq), dim3(256), 0, s, a);
+    else if (W == 32) hipLaunchKernelGGL(final_kernel<32>, dim3(nq), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(final_kernel<64>, dim3(nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("final_dtw");
+    MESSI_TRY(mark(6));
+    MESSI_HIP_TRY(hipMemcpyAsync(ws->h_err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    const int sg = scan_grid(kScanDtw);
+    if (timing) {
+        MESSI_HIP_TRY(hipMemcpyAsync(ws->h_counters, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipMemcpyAsync(ws->h_blk_cnt, a.blk_cnt, sizeof(unsigned long long) * kBlkCnt * sg,
+                                     hipMemcpyDeviceToHost, s));
+    }
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t err = *ws->h_err;
+    if (timing) {
+        QCounters hc = *ws->h_counters;
+        for (int bb = 0; bb < sg; ++bb) {
+            const unsigned long long* h = ws->h_blk_cnt + (size_t)bb * kBlkCnt;
+            hc.scanned += h[0];
+            hc.bounded += h[1];
+            hc.distance += h[2];
+            hc.abandoned += h[3];
+            hc.bytes += h[4];
+        }
+        float ms[7] = {0, 0, 0, 0, 0, 0, 0};
+        MESSI_HIP_TRY(hipEventElapsedTime(&ms[1], ev[0], ev[2]));
+        MESSI_HIP_TRY(hipEventElapsedTime(&ms[2], ev[2], ev[3]));
+        MESSI_HIP_TRY(hipEventElapsedTime(&ms[3], ev[3], ev[4]));
+        MESSI_HIP_TRY(hipEventElapsedTime(&ms[4], ev[4], ev[5]));
+        MESSI_HIP_TRY(hipEventElapsedTime(&ms[5], ev[5], ev[6]));
+        MESSI_HIP_TRY(hipEventElapsedTime(&ms[6], ev[0], ev[6]));
+        *stats = messi_knn_stats{};
+        stats->ms_leaf_lb = ms[1];
+        stats->ms_approx = ms[2];
+        stats->ms_order = ms[3];
+        stats->ms_scan = ms[4];
+        stats->ms_final = ms[5];
+        stats->ms_total = ms[6];
+        stats->leaves_total = (int64_t)ix->n_leaves * nq;
+        stats->leaves_kept = (int64_t)hc.kept;
+        stats->leaves_scanned = (int64_t)hc.scanned;
+        stats->series_bounded = (int64_t)hc.bounded;
+        stats->series_distance = (int64_t)hc.distance;
+        stats->series_abandoned = (int64_t)hc.abandoned;
+        stats->series_recheck = (int64_t)hc.recheck;
+        stats->candidates = (int64_t)hc.final_cands;
+        stats->bytes_scan = (int64_t)hc.bytes;
+        stats->scan_launches = rounds;
+    }
+    return decode_error(err);
+}
+
 int query_error_code(uint32_t st) {
     switch (st) {
         case 0: return MESSI_OK;
@@ -1634,7 +1999,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     uint32_t err = 0;
     QCounters hc{};
     const bool rowf = row_filter_path(mode, nq, false);
-    const int sg = scan_grid(rowf);
+    const int sg = scan_grid(rowf ? kScanRowFilter : kScanEd);
     const bool fp32 = mode == MESSI_MODE_FP32 || rowf;  // the ordered scan runs
     const unsigned long long* hprof = nullptr;
     const unsigned long long* hcnt = nullptr;

@@ -30,7 +30,7 @@ MAX_K = 1024
 
 EXPORTED = [
     "messi_build", "messi_build_ex", "messi_knn", "messi_knn_ex", "messi_free", "messi_index_info",
-    "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_windows", "messi_breakpoints",
+    "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_windows", "messi_knn_dtw", "messi_breakpoints",
     "messi_last_error",
     "messi_server_create", "messi_server_submit", "messi_server_poll", "messi_server_stats", "messi_server_clock_ms",
     "messi_server_destroy",
@@ -126,6 +126,8 @@ def load():
         lib.messi_znorm.restype = ctypes.c_int
         lib.messi_windows.argtypes = [vp, i64, i32, i64, i32, vp, vp]
         lib.messi_windows.restype = ctypes.c_int
+        lib.messi_knn_dtw.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, ctypes.POINTER(KnnStats)]
+        lib.messi_knn_dtw.restype = ctypes.c_int
         lib.messi_breakpoints.argtypes = [i32, vp]
         lib.messi_breakpoints.restype = ctypes.c_int
         lib.messi_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -267,6 +269,26 @@ class Index:
         rc = load().messi_knn_ex(self._h, ctypes.c_void_p(queries.data_ptr()), nq, k, mode, _stream_ptr(stream),
                                  ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_dist.data_ptr()),
                                  ctypes.byref(st) if st is not None else None)
+        _check(rc)
+        if stats:
+            return out_idx, out_dist, {f: getattr(st, f) for f, _ in KnnStats._fields_}
+        return out_idx, out_dist
+
+    def knn_dtw(self, queries, k: int, band: int, stream=None, stats: bool = False, out=None):
+        """Exact k-NN under DTW with a Sakoe-Chiba band of half-width `band`
+        (the paper's window of 10% of the length is band = len // 10)."""
+        import torch
+        assert queries.is_cuda and queries.dtype == torch.float32 and queries.is_contiguous()
+        nq = queries.shape[0]
+        if out is None:
+            out_idx = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
+            out_dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+        else:
+            out_idx, out_dist = out
+        st = KnnStats() if stats else None
+        rc = load().messi_knn_dtw(self._h, ctypes.c_void_p(queries.data_ptr()), nq, k, band, _stream_ptr(stream),
+                                  ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_dist.data_ptr()),
+                                  ctypes.byref(st) if st is not None else None)
         _check(rc)
         if stats:
             return out_idx, out_dist, {f: getattr(st, f) for f, _ in KnnStats._fields_}

@@ -1,0 +1,128 @@
+"""GPU parity of the DTW search (the paper's closing experiment: the same
+index searched with the query's LB_Keogh envelope): indices and distances
+equal the oracle's brute-force DTW (fp64 recurrence) bit for bit; band 0 gives
+the Euclidean search's answers."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def messi():
+    from paper_2009_00786_amd import messi as m
+    m.load()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _queries(datagen_mod, oracle_mod, z, length, seed):
+    fresh = oracle_mod.znorm(datagen_mod.random_walks(4, length, seed=datagen_mod.SEED_QUERY,
+                                                      stream=datagen_mod.STREAM_QUERY, row0=seed))
+    rows = datagen_mod.uniform_ints(4, len(z), seed, 7)
+    noisy = datagen_mod.add_noise(z[rows], [0.0, 0.01, 0.1, 1.0])
+    return np.concatenate([fresh, noisy]).astype(np.float32), rows
+
+
+@pytest.fixture(scope="module")
+def walks128(torch_cuda, messi, datagen_mod, oracle_mod):
+    z = oracle_mod.znorm(datagen_mod.random_walks(20_000, 128, seed=51))
+    ix = messi.Index(torch_cuda.from_numpy(z).cuda(), 16, 8, 200)
+    q, rows = _queries(datagen_mod, oracle_mod, z, 128, 52)
+    yield {"z": z, "ix": ix, "q": q, "rows": rows}
+    ix.close()
+
+
+@pytest.mark.parametrize("k", [1, 5, 50])
+def test_dtw_matches_oracle(walks128, oracle_mod, messi, torch_cuda, k):
+    w = walks128
+    band = 12  # 10% of 128
+    _say("dtw n=20000 len=128 band=%d k=%d" % (band, k))
+    oi, _, od = oracle_mod.knn_brute_dtw(w["z"], w["q"], k, band, nthreads=8)
+    gi, gd, st = w["ix"].knn_dtw(torch_cuda.from_numpy(w["q"]).cuda(), k, band, stats=True)
+    np.testing.assert_array_equal(gi.cpu().numpy(), oi)
+    np.testing.assert_array_equal(gd.cpu().numpy(), od)
+    assert gi.cpu().numpy()[4, 0] == w["rows"][0]  # an exact row finds itself
+    _say("  stats", {kk: st[kk] for kk in ("series_bounded", "series_distance", "series_recheck", "candidates",
+                                          "scan_launches")})
+    assert 0 < st["series_recheck"] < 8 * len(w["z"])
+
+
+def test_dtw_one_query_at_a_time(walks128, oracle_mod, messi, torch_cuda):
+    w = walks128
+    oi, _, od = oracle_mod.knn_brute_dtw(w["z"], w["q"], 3, 12, nthreads=8)
+    for i in range(len(w["q"])):
+        gi, gd = w["ix"].knn_dtw(torch_cuda.from_numpy(w["q"][i:i + 1].copy()).cuda(), 3, 12)
+        np.testing.assert_array_equal(gi.cpu().numpy()[0], oi[i])
+        np.testing.assert_array_equal(gd.cpu().numpy()[0], od[i])
+
+
+def test_dtw_band_zero_is_the_euclidean_search(walks128, messi, torch_cuda):
+    w = walks128
+    q = torch_cuda.from_numpy(w["q"]).cuda()
+    a = w["ix"].knn_dtw(q, 10, 0)
+    b = w["ix"].knn(q, 10)
+    assert torch_cuda.equal(a[0], b[0]) and torch_cuda.equal(a[1], b[1])
+
+
+DTW_SHAPES = [
+    # n, len, w, b, cap, band, k
+    (10_000, 256, 16, 8, 500, 25, 4),   # the paper's window: 10% of 256
+    (5_000, 90, 10, 8, 100, 9, 3),      # rows not a multiple of 4 values
+    (3_000, 64, 8, 4, 60, 27, 2),       # the widest band
+    (2_000, 16, 4, 8, 30, 20, 5),       # band beyond the length: unconstrained DTW
+    (500, 32, 16, 8, 10, 3, 500),       # k = n
+]
+
+
+@pytest.mark.parametrize("n,length,w,b,cap,band,k", DTW_SHAPES)
+def test_dtw_shapes(torch_cuda, messi, datagen_mod, oracle_mod, n, length, w, b, cap, band, k):
+    torch = torch_cuda
+    _say("dtw n=%d len=%d w=%d b=%d cap=%d band=%d k=%d" % (n, length, w, b, cap, band, k))
+    z = oracle_mod.znorm(datagen_mod.random_walks(n, length, seed=53))
+    q, _ = _queries(datagen_mod, oracle_mod, z, length, 54)
+    ix = messi.Index(torch.from_numpy(z).cuda(), w, b, cap)
+    oi, _, od = oracle_mod.knn_brute_dtw(z, q, k, band, nthreads=8)
+    gi, gd = ix.knn_dtw(torch.from_numpy(q).cuda(), k, band)
+    np.testing.assert_array_equal(gi.cpu().numpy(), oi)
+    np.testing.assert_array_equal(gd.cpu().numpy(), od)
+    ix.close()
+
+
+def test_dtw_ties_and_errors(torch_cuda, messi, oracle_mod):
+    torch = torch_cuda
+    rng = np.random.default_rng(5)
+    z = np.cumsum(rng.standard_normal((3000, 64)), axis=1).astype(np.float32)
+    z = oracle_mod.znorm(z)
+    z[100:140] = z[7]          # duplicates of row 7
+    z[500] = np.roll(z[7], 1)  # a shifted copy: close under DTW
+    ix = messi.Index(torch.from_numpy(z).cuda(), 8, 8, 20)
+    q = z[[7, 500, 2999]].copy()
+    for k in (1, 45):
+        oi, _, od = oracle_mod.knn_brute_dtw(z, q, k, 6, nthreads=8)
+        gi, gd = ix.knn_dtw(torch.from_numpy(q).cuda(), k, 6)
+        np.testing.assert_array_equal(gi.cpu().numpy(), oi)
+        np.testing.assert_array_equal(gd.cpu().numpy(), od)
+    qq = torch.from_numpy(q).cuda()
+    for band, k in ((28, 1), (-1, 1), (6, 3001), (6, 0)):
+        with pytest.raises(messi.MessiError) as e:
+            ix.knn_dtw(qq, k, band)
+        assert e.value.code == messi.MESSI_EINVAL
+    bad = qq.clone()
+    bad[1, 3] = float("nan")
+    with pytest.raises(messi.MessiError) as e:
+        ix.knn_dtw(bad, 1, 6)
+    assert e.value.code == messi.MESSI_EINVAL
+    empty = ix.knn_dtw(qq[:0], 1, 6)
+    assert empty[0].shape == (0, 1)
+    ix.close()
