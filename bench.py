@@ -330,9 +330,54 @@ def main():
         "recall_at_%d" % k: float(np.mean([len(set(ai[qi]) & set(answers[0][qi])) / k for qi in range(nq)])),
         "distance_ratio_mean": float(np.mean(apx_d.cpu().numpy()[:, 0] / np.maximum(answers[1][:, 0], 1e-30))),
     }
+    # the paper's DTW search on the same index and queries (warping window 10%
+    # of the length): its rate, its work, and DTW <= ED for every answer
+    band = length // 10
+    dtw_i = torch.empty_like(ans_i)
+    dtw_d = torch.empty_like(ans_d)
+    dtw_lat = []
+    for rep in range(2):
+        for qi in range(nq):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            ix.knn_dtw(queries[qi:qi + 1], k, band, out=(dtw_i[qi:qi + 1], dtw_d[qi:qi + 1]))
+            torch.cuda.synchronize()
+            if rep == 1:
+                dtw_lat.append((time.perf_counter() - a) * 1e3)
+    dagg = {}
+    for qi in range(nq):
+        _, _, st = ix.knn_dtw(queries[qi:qi + 1], k, band, stats=True)
+        for key in ("ms_total", "ms_scan", "ms_final", "series_bounded", "series_distance", "series_recheck",
+                    "scan_launches"):
+            dagg[key] = dagg.get(key, 0) + st[key] / nq
+    dtw_lat = np.array(dtw_lat)
+    res["dtw_mode"] = {
+        "band": band, "k": k, "queries_per_s": len(dtw_lat) / (dtw_lat.sum() / 1e3),
+        "p50_ms": float(np.percentile(dtw_lat, 50)), "p99_ms": float(np.percentile(dtw_lat, 99)),
+        "per_query": {"lb_keogh": dagg["series_distance"], "dtw": dagg["series_recheck"],
+                      "members_bounded": dagg["series_bounded"], "rounds": dagg["scan_launches"],
+                      "ms_device": dagg["ms_total"], "ms_rounds": dagg["ms_scan"], "ms_final": dagg["ms_final"]},
+        "dtw_le_ed": bool(np.all(dtw_d.cpu().numpy()[:, 0] <= answers[1][:, 0])),
+    }
+    if cpu is not None:
+        res["dtw_mode"]["cpu_baseline"] = cpu_baseline_dtw(data, qraw, k, length, band, n, threads=cpu["cores"])
     if ix is not None:
         ix.close()
     print(json.dumps(res), flush=True)
+
+
+def cpu_baseline_dtw(data_gpu, q_host_raw, k, length, band, n_total, rows=100_000, nq=10, threads=16):
+    """The CPU oracle's brute-force DTW k-NN timed on a bounded sample (nq
+    queries over the first `rows` rows), scaled to the full collection."""
+    import oracle
+    z = oracle.znorm(data_gpu[:rows].cpu().numpy())
+    qz = oracle.znorm(q_host_raw[:nq])
+    t0 = time.perf_counter()
+    oracle.knn_brute_dtw(z, qz, k, band, nthreads=threads)
+    t = time.perf_counter() - t0
+    return {"value": nq / (t * (n_total / rows)), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": "fp64 brute-force DTW k-NN (oracle, band %d) of %d queries over the first %d rows, %.1f s, "
+                      "scaled by %d/%d rows" % (band, nq, rows, t, n_total, rows)}
 
 
 def make_batch(data, z_rows_gpu_fn, b, nq, length, seed_off=0):

@@ -1210,11 +1210,18 @@ __global__ void status_kernel(QArgs a, uint32_t* out) {
 // once in fp64 (no fused multiply-add), equal to the plain recurrence in any
 // evaluation order.  T = float: the search value, within a relative 2^-12 of
 // it for L <= 1024 (each path sum is a sequential sum of at most 2L - 1
-// non-negative terms, each term within 3 units of rounding); it stops, and
-// returns +inf, once a whole row of the band exceeds limit / (1 - 2^-12):
-// every path crosses that row, and sums only grow along a path.
+// non-negative terms, each term within 3 units of rounding).  It stops, and
+// returns +inf, once a lower bound of the final value exceeds limit: after
+// row i every path still has to match each column j > i + r with some query
+// value inside the envelope [el_j, eu_j], so the final value is at least the
+// row's smallest cell plus the LB_Keogh terms of those columns, which are
+// lbk (the row's LB_Keogh, summed by the scan) less the terms of columns
+// <= i + r summed here.  Both sums are within 2^-13 lbk of their exact
+// values, covered by a slack of 2^-12 lbk.
 template <int W, typename T>
-__device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, int L, int r, float limit) {
+__device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, int L, int r, float limit,
+                      const float* __restrict__ eu = nullptr, const float* __restrict__ el = nullptr,
+                      float lbk = 0.f) {
     constexpr bool F64 = sizeof(T) == 8;
     const T inf = (T)__builtin_huge_valf();
     T D[W];
@@ -1225,9 +1232,18 @@ __device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, 
         const int j = t - r;
         xw[t] = (j >= 0 && j < L) ? x[j] : 0.f;
     }
+    // LB_Keogh terms of the columns below r (the first row reaches column r)
+    float pre = 0.f;
+    if (!F64)
+        for (int j = 0; j < r && j < L; ++j) pre += keogh_gap(x[j], eu[j], el[j]) * keogh_gap(x[j], eu[j], el[j]);
+    const float slack = lbk * 2.44140625e-04f;
     for (int i = 0; i < L; ++i) {
         const float qi = q[i];
         T left = inf, rowmin = inf;
+        if (!F64 && i + r < L) {
+            const float g = keogh_gap(x[i + r], eu[i + r], el[i + r]);
+            pre += g * g;
+        }
 #pragma unroll
         for (int t = 0; t < W; ++t) {
             const int j = i - r + t;
@@ -1251,7 +1267,10 @@ __device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, 
         for (int t = 0; t + 1 < W; ++t) xw[t] = xw[t + 1];
         const int jn = i + 1 - r + W - 1;
         xw[W - 1] = jn < L ? x[jn] : 0.f;
-        if (!F64 && (float)rowmin * (1.0f - kRhoDtw) > limit) return inf;
+        if (!F64) {
+            const float rest = fmaxf(0.f, lbk - pre - slack);
+            if (((float)rowmin * (1.0f - kRhoDtw) + rest) * (1.0f - 1.0e-6f) > limit) return inf;
+        }
     }
     T out = inf;
 #pragma unroll
@@ -1265,10 +1284,22 @@ __device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, 
 template <int W>
 __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
     __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ float s_eu[MESSI_MAX_LEN], s_el[MESSI_MAX_LEN];
     const int q = blockIdx.y;
     QState& st = a.qs[q];
     if (st.err) return;
-    for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
+    const float* qg = a.queries + (size_t)q * a.L;
+    for (int j = threadIdx.x; j < a.L; j += 256) {
+        s_q[j] = qg[j];
+        const int t0 = max(0, j - a.band), t1 = min(a.L - 1, j + a.band);
+        float u = qg[t0], l = u;
+        for (int t = t0 + 1; t <= t1; ++t) {
+            u = fmaxf(u, qg[t]);
+            l = fminf(l, qg[t]);
+        }
+        s_eu[j] = u;
+        s_el[j] = l;
+    }
     __syncthreads();
     const uint32_t n = st.ntodo;
     if (n > a.todo_cap) {
@@ -1288,7 +1319,7 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
         if (t.d * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U))) continue;
         ++ndtw;
         const float d = dtw_band<W, float>(s_q, series + (size_t)t.idx * a.L, a.L, a.band,
-                                           __uint_as_float(vload(&st.U)));
+                                           __uint_as_float(vload(&st.U)), s_eu, s_el, t.d);
         if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
             const uint32_t slot = atomicAdd(&st.ncand, 1u);
             if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, t.idx};
