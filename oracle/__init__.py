@@ -62,6 +62,8 @@ def _load():
         lib.oracle_knn_brute.restype = ctypes.c_int
         lib.oracle_knn_isax.argtypes = [vp, i64, i32, vp, i32, i32, vp, i64, vp, vp, i32, i32, vp, vp, vp]
         lib.oracle_knn_isax.restype = ctypes.c_int
+        lib.oracle_build_leaves_ex.argtypes = [vp, i64, i32, i32, i64, vp, i64, vp, vp, vp, vp]
+        lib.oracle_build_leaves_ex.restype = i64
         lib.oracle_dtw64.argtypes = [vp, vp, i32, i32]
         lib.oracle_dtw64.restype = d
         lib.oracle_envelope.argtypes = [vp, i32, i32, vp, vp]
@@ -154,19 +156,40 @@ def root_keys(words_, card_bits: int) -> np.ndarray:
     return out
 
 
-def build_leaves(words_, card_bits: int, leaf_cap: int):
+SPLIT_DTYPE = np.dtype([("card", np.uint8, (16,)), ("prefix", np.uint8, (16,)), ("seg", np.int32)])
+
+
+def build_leaves(words_, card_bits: int, leaf_cap: int, forced=None, return_inner=False):
     """Leaf partition by the order-free top-down rule (TreeConstruction/SplitNode).
 
-    Returns (leaves structured array in depth-first order, pos uint32[n])."""
+    forced: internal nodes (SPLIT_DTYPE) that must split on their segment --
+    appending series to an index is the partition of all its series with the
+    previous partition's internal nodes forced (see append_leaves).
+    Returns (leaves structured array in depth-first order, pos uint32[n])
+    and, with return_inner, the internal nodes with their segments."""
     wd = np.ascontiguousarray(words_, dtype=np.uint8)
     n, w = wd.shape
     leaves = np.zeros(n, dtype=LEAF_DTYPE)
     pos = np.zeros(n, dtype=np.uint32)
-    cnt = _load().oracle_build_leaves(wd.ctypes.data, n, w, card_bits, leaf_cap, leaves.ctypes.data,
-                                      pos.ctypes.data)
+    f = np.ascontiguousarray(forced if forced is not None else np.zeros(0, SPLIT_DTYPE), dtype=SPLIT_DTYPE)
+    inner = np.zeros((w * (card_bits - 1) + 2) * (n // (leaf_cap + 1) + 1), dtype=SPLIT_DTYPE)
+    n_inner = ctypes.c_int64(0)
+    cnt = _load().oracle_build_leaves_ex(wd.ctypes.data, n, w, card_bits, leaf_cap, f.ctypes.data, f.size,
+                                         leaves.ctypes.data, pos.ctypes.data, inner.ctypes.data,
+                                         ctypes.byref(n_inner))
     if cnt < 0:
         raise ValueError("bad arguments to build_leaves")
-    return leaves[:cnt].copy(), pos
+    out = (leaves[:cnt].copy(), pos)
+    return out + (inner[:n_inner.value].copy(),) if return_inner else out
+
+
+def append_leaves(words_all, card_bits: int, leaf_cap: int, inner_before):
+    """The index after appending series (Algorithm TreeConstruction's insert
+    and SplitNode): words_all holds the words of the old series followed by
+    the new ones; every node that was internal before splits on the same
+    segment, everything else follows the top-down rule.  Returns (leaves,
+    pos, inner) of the new index."""
+    return build_leaves(words_all, card_bits, leaf_cap, forced=inner_before, return_inner=True)
 
 
 def d64(q, x) -> float:

@@ -219,6 +219,13 @@ typedef struct {
     uint32_t count;
 } oracle_leaf;
 
+/* An internal node of the partition and the segment it split on. */
+typedef struct {
+    uint8_t card[16];
+    uint8_t prefix[16];
+    int32_t seg;
+} oracle_split;
+
 typedef struct {
     const uint8_t* words;
     int32_t w, b;
@@ -229,7 +236,21 @@ typedef struct {
     int64_t n_pos;
     /* per-depth scratch for the members of the two children */
     uint32_t* scratch;
+    /* appends: nodes that must split on a given segment (may be NULL) */
+    const oracle_split* forced;
+    int64_t n_forced;
+    /* every internal node with its segment, in the order met (may be NULL) */
+    oracle_split* inner;
+    int64_t n_inner;
 } build_ctx;
+
+static int forced_segment(const build_ctx* ctx, const uint8_t* card, const uint8_t* prefix) {
+    for (int64_t f = 0; f < ctx->n_forced; ++f)
+        if (memcmp(ctx->forced[f].card, card, (size_t)ctx->w) == 0 &&
+            memcmp(ctx->forced[f].prefix, prefix, (size_t)ctx->w) == 0)
+            return ctx->forced[f].seg;
+    return -1;
+}
 
 static void emit_leaf(build_ctx* ctx, const uint8_t* card, const uint8_t* prefix, const uint32_t* members,
                       int64_t cnt) {
@@ -248,24 +269,34 @@ static void split_node(build_ctx* ctx, const uint8_t* card, const uint8_t* prefi
         emit_leaf(ctx, card, prefix, members, cnt);
         return;
     }
-    int best = -1;
-    int64_t best_gap = 0;
-    for (int i = 0; i < w; ++i) {
-        if (card[i] >= b) continue;
-        int shift = b - 1 - card[i];
-        int64_t n1 = 0;
-        for (int64_t j = 0; j < cnt; ++j)
-            n1 += (ctx->words[(size_t)members[j] * (size_t)w + (size_t)i] >> shift) & 1;
-        int64_t n0 = cnt - n1;
-        int64_t gap = n0 > n1 ? n0 - n1 : n1 - n0;
-        if (best < 0 || gap < best_gap) {
-            best = i;
-            best_gap = gap;
+    /* a node that split before an append splits on the same segment again */
+    int best = forced_segment(ctx, card, prefix);
+    if (best < 0) {
+        int64_t best_gap = 0;
+        for (int i = 0; i < w; ++i) {
+            if (card[i] >= b) continue;
+            int shift = b - 1 - card[i];
+            int64_t n1 = 0;
+            for (int64_t j = 0; j < cnt; ++j)
+                n1 += (ctx->words[(size_t)members[j] * (size_t)w + (size_t)i] >> shift) & 1;
+            int64_t n0 = cnt - n1;
+            int64_t gap = n0 > n1 ? n0 - n1 : n1 - n0;
+            if (best < 0 || gap < best_gap) {
+                best = i;
+                best_gap = gap;
+            }
         }
     }
     if (best < 0) { /* every segment at full cardinality */
         emit_leaf(ctx, card, prefix, members, cnt);
         return;
+    }
+    if (ctx->inner) {
+        oracle_split* sp = &ctx->inner[ctx->n_inner++];
+        memset(sp, 0, sizeof *sp);
+        memcpy(sp->card, card, (size_t)w);
+        memcpy(sp->prefix, prefix, (size_t)w);
+        sp->seg = best;
     }
     int shift = b - 1 - card[best];
     uint32_t* tmp = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)cnt);
@@ -292,8 +323,29 @@ static void split_node(build_ctx* ctx, const uint8_t* card, const uint8_t* prefi
 
 /* Returns the number of leaves (<= n), or -1 on bad arguments.  leaves must
  * hold n entries and pos n entries. */
+int64_t oracle_build_leaves_ex(const uint8_t* words, int64_t n, int32_t w, int32_t card_bits, int64_t cap,
+                               const oracle_split* forced, int64_t n_forced, oracle_leaf* leaves, uint32_t* pos,
+                               oracle_split* inner, int64_t* n_inner);
+
 int64_t oracle_build_leaves(const uint8_t* words, int64_t n, int32_t w, int32_t card_bits, int64_t cap,
                             oracle_leaf* leaves, uint32_t* pos) {
+    return oracle_build_leaves_ex(words, n, w, card_bits, cap, NULL, 0, leaves, pos, NULL, NULL);
+}
+
+/* The same, and (inner may be NULL) every internal node with the segment it
+ * split on.  forced (n_forced entries, may be NULL) lists nodes that must
+ * split on a given segment: appending series to an index is this partition of
+ * all the series with the previous index's internal nodes as `forced`
+ * (Algorithm TreeConstruction inserts each new series into the leaf its word
+ * reaches and splits a leaf that gets too full; the existing splits stay, a
+ * leaf that gets no new series stays as it is, and an over-full one is split
+ * by the same balance rule).  inner must hold (w (card_bits - 1) + 2)
+ * (n / (cap + 1) + 1) entries: internal nodes hold more than cap series, the
+ * nodes of one depth are disjoint, and a path refines at most w (card_bits - 1)
+ * times below the root children. */
+int64_t oracle_build_leaves_ex(const uint8_t* words, int64_t n, int32_t w, int32_t card_bits, int64_t cap,
+                               const oracle_split* forced, int64_t n_forced, oracle_leaf* leaves, uint32_t* pos,
+                               oracle_split* inner, int64_t* n_inner) {
     if (n < 1 || w < 1 || w > 16 || card_bits < 1 || card_bits > 8 || cap < 1) return -1;
     uint32_t* keys = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
     oracle_root_keys(words, n, w, card_bits, keys);
@@ -309,6 +361,7 @@ int64_t oracle_build_leaves(const uint8_t* words, int64_t n, int32_t w, int32_t 
     build_ctx ctx;
     memset(&ctx, 0, sizeof ctx);
     ctx.words = words; ctx.w = w; ctx.b = card_bits; ctx.cap = cap; ctx.leaves = leaves; ctx.pos = pos;
+    ctx.forced = forced; ctx.n_forced = forced ? n_forced : 0; ctx.inner = inner;
     for (int64_t k = 0; k < nkeys; ++k) {
         int64_t cnt = start[k + 1] - start[k];
         if (cnt == 0) continue;
@@ -320,6 +373,7 @@ int64_t oracle_build_leaves(const uint8_t* words, int64_t n, int32_t w, int32_t 
         split_node(&ctx, card, prefix, order + start[k], cnt);
     }
     free(keys); free(start); free(order); free(fill);
+    if (n_inner) *n_inner = ctx.n_inner;
     return ctx.n_leaves;
 }
 
