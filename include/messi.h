@@ -175,6 +175,21 @@ int messi_index_info(const messi_index* index, messi_info* out);
 /* Words in input order: host_words[n][segments], segment 0 first. */
 int messi_export_words(const messi_index* index, uint8_t* host_words);
 
+/* Append series to a built index (paper: Algorithm TreeConstruction inserts
+ * each series into the leaf its word reaches and splits a leaf that becomes
+ * too full, SplitNode).  `series` is the collection with the new rows after
+ * the old ones: rows [0, n) must be the rows the index was built on (it may
+ * be a new allocation holding them), rows [n, new_n) are appended.  The new
+ * index is the top-down partition of all new_n series in which every node
+ * that split before splits on the same segment: the existing splits stay, a
+ * leaf that gets no new series keeps its members, a region that held no
+ * series gets a leaf, and a leaf over leaf_cap is split by the same balance
+ * rule as the build.  The index then borrows `series` (as messi_build does);
+ * its BF16 shadow, if any, is rebuilt.  Limits as messi_build (new_n < 2^32,
+ * new_n >= n).  Not to be called while searches or a server use the index.
+ * On error the index is unchanged.  Synchronous. */
+int messi_append(messi_index* index, const float* series, int64_t new_n, void* stream);
+
 /* Leaves in depth-first order (root key ascending, bit 0 before bit 1) and the
  * position array: host_leaves[n_leaves], host_pos[n]; leaf l's members are
  * host_pos[start .. start + count), ascending series index. */

@@ -74,6 +74,43 @@ static int fail(int code, const char* msg) {
     return code;
 }
 
+static void fill_info(Index* ix) {
+    messi_info& in = ix->info;
+    in.n = ix->n;
+    in.len = ix->len;
+    in.segments = ix->w;
+    in.card_bits = ix->b;
+    in.leaf_cap = ix->cap;
+    in.n_leaves = ix->n_leaves;
+    in.max_leaf = ix->max_leaf;
+    in.levels = ix->levels;
+    in.has_bf16 = ix->shadow.p != nullptr;
+    in.device_bytes = ix->device_bytes();
+    in.data_absmax = ix->absmax;
+}
+
+// Take over everything src holds (src keeps dst's old buffers, to be freed).
+static void adopt(Index* dst, Index* src) {
+    std::swap(dst->series, src->series);
+    std::swap(dst->n, src->n);
+    std::swap(dst->n_leaves, src->n_leaves);
+    std::swap(dst->max_leaf, src->max_leaf);
+    std::swap(dst->levels, src->levels);
+    std::swap(dst->absmax, src->absmax);
+    std::swap(dst->split_mask, src->split_mask);
+    std::swap(dst->n_inner, src->n_inner);
+    std::swap(dst->info, src->info);
+    DevBuf* a[] = {&dst->words, &dst->pos, &dst->leaves, &dst->bp, &dst->sx, &dst->shadow, &dst->split_keys,
+                   &dst->split_seg, &dst->split_claim};
+    DevBuf* b[] = {&src->words, &src->pos, &src->leaves, &src->bp, &src->sx, &src->shadow, &src->split_keys,
+                   &src->split_seg, &src->split_claim};
+    for (size_t i = 0; i < sizeof(a) / sizeof(a[0]); ++i) {
+        DevBuf t = std::move(*a[i]);
+        *a[i] = std::move(*b[i]);
+        *b[i] = std::move(t);
+    }
+}
+
 }  // namespace messi
 
 using namespace messi;
@@ -181,19 +218,44 @@ messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t
         set_error(code, msg);
         return nullptr;
     }
-    messi_info& in = ix->info;
-    in.n = n;
-    in.len = len;
-    in.segments = segments;
-    in.card_bits = card_bits;
-    in.leaf_cap = leaf_cap;
-    in.n_leaves = ix->n_leaves;
-    in.max_leaf = ix->max_leaf;
-    in.levels = ix->levels;
-    in.has_bf16 = ix->shadow.p != nullptr;
-    in.device_bytes = ix->device_bytes();
-    in.data_absmax = ix->absmax;
+    fill_info(ix);
     return reinterpret_cast<messi_index*>(ix);
+}
+
+int messi_append(messi_index* index, const float* series, int64_t new_n, void* stream) {
+    clear_error();
+    if (!index) return fail(MESSI_EINVAL, "index is null");
+    Index* ix = reinterpret_cast<Index*>(index);
+    if (new_n < ix->n) return fail(MESSI_EINVAL, "new_n is below the indexed count");
+    MESSI_TRY(check_series_args(series, new_n, ix->len));
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ix->device)
+        return fail(MESSI_EINVAL, "the index lives on another device");
+    hipStream_t s = (hipStream_t)stream;
+    MESSI_HIP_TRY(hipDeviceSynchronize());  // searches on other streams are done with the old arrays
+    Index* nx = new Index();
+    nx->device = ix->device;
+    messi_build_opts o{};
+    o.stream = stream;
+    const SplitTab tab{ix->split_keys.as<uint4>(), ix->split_seg.as<uint8_t>(), ix->split_claim.as<uint32_t>(),
+                       ix->split_mask};
+    int rc = build_index(nx, series, new_n, ix->len, ix->w, ix->b, ix->cap, o, &tab);
+    if (rc == MESSI_OK && ix->shadow.p) rc = build_bf16_shadow(nx, s);
+    if (rc != MESSI_OK) {
+        const int code = last_error_code();
+        char msg[512];
+        messi_last_error(msg, sizeof msg);
+        (void)hipDeviceSynchronize();
+        delete nx;
+        set_error(code, msg);
+        return code;
+    }
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    release_workspaces(ix);  // sized for the old leaf count
+    adopt(ix, nx);
+    fill_info(ix);
+    delete nx;  // the old arrays
+    return MESSI_OK;
 }
 
 messi_index* messi_build(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,

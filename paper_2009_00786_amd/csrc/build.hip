@@ -725,25 +725,99 @@ __global__ void __launch_bounds__(kBlk) level_count_kernel(const Leaf* __restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// The split table: (card, prefix) of every internal node -> its segment, in
+// open addressing with linear probing (at least twice as many slots as nodes).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void node_key(const Leaf& nd, uint4& k0, uint4& k1) {
+    uint32_t v[8];
+    memcpy(v, nd.card, 16);
+    memcpy(v + 4, nd.prefix, 16);
+    k0 = make_uint4(v[0], v[1], v[2], v[3]);
+    k1 = make_uint4(v[4], v[5], v[6], v[7]);
+}
+
+__device__ __forceinline__ uint32_t key_hash(const uint4& k0, const uint4& k1) {
+    const uint32_t v[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    for (int i = 0; i < 8; ++i) {
+        h ^= v[i];
+        h *= 0xff51afd7ed558ccdull;
+        h ^= h >> 33;
+    }
+    return (uint32_t)h;
+}
+
+__device__ int split_lookup(const SplitTab& t, const Leaf& nd) {
+    uint4 k0, k1;
+    node_key(nd, k0, k1);
+    uint32_t h = key_hash(k0, k1) & t.mask;
+    for (uint32_t probe = 0; probe <= t.mask; ++probe) {
+        if (t.claim[h] == 0u) return -1;
+        const uint4 a = t.keys[2 * (size_t)h], c = t.keys[2 * (size_t)h + 1];
+        if (a.x == k0.x && a.y == k0.y && a.z == k0.z && a.w == k0.w && c.x == k1.x && c.y == k1.y &&
+            c.z == k1.z && c.w == k1.w)
+            return t.seg[h];
+        h = (h + 1) & t.mask;
+    }
+    return -1;
+}
+
+// One thread per recorded internal node (its segment in `start`).
+__global__ void __launch_bounds__(256) split_insert_kernel(const Leaf* __restrict__ inner, uint32_t n,
+                                                           uint4* __restrict__ keys, uint8_t* __restrict__ seg,
+                                                           uint32_t* __restrict__ claim, uint32_t mask) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const Leaf nd = inner[i];
+    uint4 k0, k1;
+    node_key(nd, k0, k1);
+    uint32_t h = key_hash(k0, k1) & mask;
+    while (atomicCAS(&claim[h], 0u, 1u) != 0u) h = (h + 1) & mask;
+    keys[2 * (size_t)h] = k0;
+    keys[2 * (size_t)h + 1] = k1;
+    seg[h] = (uint8_t)nd.start;
+}
+
+// After a level's choice: every node that split, with its segment in `start`.
+__global__ void __launch_bounds__(256) record_inner_kernel(const Leaf* __restrict__ nodes, int n_nodes,
+                                                           const uint8_t* __restrict__ node_split,
+                                                           const uint8_t* __restrict__ node_seg,
+                                                           Leaf* __restrict__ inner, uint32_t* __restrict__ n_inner) {
+    const int nd = blockIdx.x * 256 + threadIdx.x;
+    if (nd >= n_nodes || !node_split[nd]) return;
+    Leaf r = nodes[nd];
+    r.start = node_seg[nd];
+    r.count = 0;
+    inner[atomicAdd(n_inner, 1u)] = r;
+}
+
 __global__ void level_choose_kernel(const Leaf* __restrict__ nodes, int n_nodes, const uint32_t* __restrict__ node_cnt,
                                     int w, int b, int cap, int dst_buf, uint8_t* __restrict__ node_seg,
-                                    uint32_t* __restrict__ node_n0, Lists L) {
+                                    uint32_t* __restrict__ node_n0, uint8_t* __restrict__ node_split, SplitTab forced,
+                                    Lists L) {
     const int nd = blockIdx.x * blockDim.x + threadIdx.x;
     if (nd >= n_nodes) return;
     const Leaf node = nodes[nd];
-    int best = -1;
+    // a node that split before (an append) keeps its segment
+    int best = forced.mask ? split_lookup(forced, node) : -1;
     uint32_t best_gap = 0, best_n1 = 0;
-    for (int i = 0; i < w; ++i) {
-        if (node.card[i] >= b) continue;
-        const uint32_t n1 = node_cnt[(size_t)nd * 16 + i];
-        const uint32_t n0 = node.count - n1;
-        const uint32_t gap = n0 > n1 ? n0 - n1 : n1 - n0;
-        if (best < 0 || gap < best_gap) {
-            best = i;
-            best_gap = gap;
-            best_n1 = n1;
+    if (best >= 0) {
+        best_n1 = node_cnt[(size_t)nd * 16 + best];
+    } else {
+        for (int i = 0; i < w; ++i) {
+            if (node.card[i] >= b) continue;
+            const uint32_t n1 = node_cnt[(size_t)nd * 16 + i];
+            const uint32_t n0 = node.count - n1;
+            const uint32_t gap = n0 > n1 ? n0 - n1 : n1 - n0;
+            if (best < 0 || gap < best_gap) {
+                best = i;
+                best_gap = gap;
+                best_n1 = n1;
+            }
         }
     }
+    node_split[nd] = best >= 0 ? 1 : 0;
     if (best < 0) {  // nodes on the list always have a refinable segment; keep the node whole
         node_seg[nd] = 0;
         node_n0[nd] = node.count;
@@ -1023,7 +1097,7 @@ int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_fl
 }
 
 int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t w, int32_t b, int32_t cap,
-                const messi_build_opts& opts) {
+                const messi_build_opts& opts, const SplitTab* forced) {
     hipStream_t s = (hipStream_t)opts.stream;
     ix->series = series;
     ix->n = n;
@@ -1046,7 +1120,8 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
         MESSI_TRY(P[i].alloc(sizeof(uint32_t) * (size_t)n));
         MESSI_TRY(K[i].alloc(sizeof(uint16_t) * (size_t)n));
     }
-    // misc: [0] nonfinite, [1] absmax bits, [2] n_leaves, [3] n_next, [4] max_leaf, [5] total tiles
+    // misc: [0] nonfinite, [1] absmax bits, [2] n_leaves, [3] n_next, [4] max_leaf, [5] total tiles,
+    // [6] internal nodes recorded
     MESSI_TRY(misc.alloc(64));
     uint32_t* cnt = misc.as<uint32_t>();
     MESSI_HIP_TRY(hipMemsetAsync(misc.p, 0, 64, s));
@@ -1142,6 +1217,10 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     // root runs -> first nodes / leaves
     const uint32_t n_keys = 1u << w;
     DevBuf runs, leaves_raw, leaf_buf, nodes[2], node_cnt, node_seg, node_n0, tile_first, tile_node, tile_cnt, zeros;
+    DevBuf node_split, inner;
+    size_t inner_cap = 0, inner_ub = 0;  // recorded internal nodes: capacity, upper bound so far
+    const SplitTab no_tab{nullptr, nullptr, nullptr, 0u};
+    const SplitTab ftab = forced ? *forced : no_tab;
     MESSI_TRY(runs.alloc(sizeof(uint32_t) * 2 * n_keys));
     MESSI_HIP_TRY(hipMemsetAsync(runs.p, 0, sizeof(uint32_t) * 2 * n_keys, s));
     hipLaunchKernelGGL(root_runs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, K[cur].as<uint16_t>(), n,
@@ -1175,6 +1254,7 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     MESSI_TRY(node_cnt.alloc(sizeof(uint32_t) * 16 * (size_t)max_nodes2));
     MESSI_TRY(node_seg.alloc((size_t)max_nodes2));
     MESSI_TRY(node_n0.alloc(sizeof(uint32_t) * (size_t)max_nodes2));
+    MESSI_TRY(node_split.alloc((size_t)max_nodes2));
     MESSI_TRY(tile_first.alloc(sizeof(uint32_t) * ((size_t)max_nodes2 + 1)));
     MESSI_TRY(tile_node.alloc(sizeof(uint32_t) * (size_t)max_tiles));
     MESSI_TRY(tile_cnt.alloc(sizeof(uint32_t) * 16 * (size_t)max_tiles));
@@ -1203,8 +1283,23 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
             lst.next = nodes[nsel ^ 1].as<Leaf>();
             hipLaunchKernelGGL(level_choose_kernel, dim3((nn + 255) / 256), dim3(256), 0, s, cur_nodes, (int)nn,
                                node_cnt.as<uint32_t>(), w, b, cap_lvl, cur ^ 1, node_seg.as<uint8_t>(),
-                               node_n0.as<uint32_t>(), lst);
+                               node_n0.as<uint32_t>(), node_split.as<uint8_t>(), ftab, lst);
             MESSI_LAUNCH_CHECK("level_choose");
+            // record the nodes that split (kept for later appends)
+            if (inner_ub + nn > inner_cap) {
+                size_t ncap = std::max<size_t>(1024, 2 * (inner_ub + nn));
+                DevBuf grown;
+                MESSI_TRY(grown.alloc(sizeof(Leaf) * ncap));
+                if (inner_ub) MESSI_HIP_TRY(hipMemcpyAsync(grown.p, inner.p, sizeof(Leaf) * inner_ub,
+                                                           hipMemcpyDeviceToDevice, s));
+                MESSI_HIP_TRY(hipStreamSynchronize(s));
+                inner = std::move(grown);
+                inner_cap = ncap;
+            }
+            hipLaunchKernelGGL(record_inner_kernel, dim3((nn + 255) / 256), dim3(256), 0, s, cur_nodes, (int)nn,
+                               node_split.as<uint8_t>(), node_seg.as<uint8_t>(), inner.as<Leaf>(), cnt + 6);
+            MESSI_LAUNCH_CHECK("record_inner");
+            inner_ub += nn;
             hipLaunchKernelGGL(level_zeros_kernel, dim3((tiles + 255) / 256), dim3(256), 0, s, cur_nodes,
                                tile_first.as<uint32_t>(), tile_node.as<uint32_t>(), tiles, tile_cnt.as<uint32_t>(),
                                node_seg.as<uint8_t>(), zeros.as<uint32_t>());
@@ -1243,7 +1338,28 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     cur = fin;
     ix->info.ms_split = tm.stop_ms();
     node_cnt.release(); node_seg.release(); node_n0.release(); tile_first.release(); tile_node.release();
-    tile_cnt.release(); zeros.release(); nodes[0].release(); nodes[1].release();
+    tile_cnt.release(); zeros.release(); nodes[0].release(); nodes[1].release(); node_split.release();
+
+    // the split table of the new index (read by the next append)
+    {
+        uint32_t n_inner = 0;
+        MESSI_HIP_TRY(hipMemcpyAsync(&n_inner, cnt + 6, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        uint32_t slots = 16;
+        while (slots < 2u * n_inner) slots <<= 1;
+        MESSI_TRY(ix->split_keys.alloc(sizeof(uint4) * 2 * (size_t)slots));
+        MESSI_TRY(ix->split_seg.alloc((size_t)slots));
+        MESSI_TRY(ix->split_claim.alloc(sizeof(uint32_t) * (size_t)slots));
+        MESSI_HIP_TRY(hipMemsetAsync(ix->split_claim.p, 0, sizeof(uint32_t) * (size_t)slots, s));
+        if (n_inner)
+            hipLaunchKernelGGL(split_insert_kernel, dim3((n_inner + 255) / 256), dim3(256), 0, s, inner.as<Leaf>(),
+                               n_inner, ix->split_keys.as<uint4>(), ix->split_seg.as<uint8_t>(),
+                               ix->split_claim.as<uint32_t>(), slots - 1);
+        MESSI_LAUNCH_CHECK("split_insert");
+        ix->split_mask = slots - 1;
+        ix->n_inner = n_inner;
+        inner.release();
+    }
 
     // ---- 4. finalise: leaves ordered by start
     tm.start();

@@ -104,6 +104,13 @@ struct Index {
     DevBuf bp;      // float [2^b - 1] breakpoints
     DevBuf sx;      // uint2 [n]: BF16 (|x| up, beta high, beta low, 0) per member, leaf order (bf16 shadow only)
     DevBuf shadow;  // bf16 [n][len] rows in leaf order (bf16 shadow only)
+    // the partition's internal nodes and their split segments, as an
+    // open-addressing table keyed by (card, prefix): appends keep these splits
+    DevBuf split_keys;   // uint4 [2][slots]: card bytes, prefix bytes
+    DevBuf split_seg;    // uint8 [slots]
+    DevBuf split_claim;  // uint32 [slots]: 1 = slot used
+    uint32_t split_mask = 0;  // slots - 1 (0: no table)
+    uint32_t n_inner = 0;
 
     float bp_host[255];
     messi_info info{};
@@ -125,8 +132,17 @@ int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_fl
 // as znorm_device does when znorm is set.
 int windows_device(const float* src, int64_t count, int32_t len, int64_t step, bool znorm, float* out,
                    hipStream_t s, int* d_flag);
+// The split table of an index, as the build reads it (mask 0: none).
+struct SplitTab {
+    const uint4* keys;
+    const uint8_t* seg;
+    const uint32_t* claim;
+    uint32_t mask;
+};
+// forced (may be null): nodes that split on a given segment whatever the
+// balance (an append keeps the previous index's splits).
 int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t w, int32_t b, int32_t cap,
-                const messi_build_opts& opts);
+                const messi_build_opts& opts, const SplitTab* forced = nullptr);
 
 // query.hip
 int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,

@@ -30,7 +30,8 @@ MAX_K = 1024
 
 EXPORTED = [
     "messi_build", "messi_build_ex", "messi_knn", "messi_knn_ex", "messi_free", "messi_index_info",
-    "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_windows", "messi_knn_dtw", "messi_breakpoints",
+    "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_windows", "messi_knn_dtw", "messi_append",
+    "messi_breakpoints",
     "messi_last_error",
     "messi_server_create", "messi_server_submit", "messi_server_poll", "messi_server_stats", "messi_server_clock_ms",
     "messi_server_destroy",
@@ -128,6 +129,8 @@ def load():
         lib.messi_windows.restype = ctypes.c_int
         lib.messi_knn_dtw.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, ctypes.POINTER(KnnStats)]
         lib.messi_knn_dtw.restype = ctypes.c_int
+        lib.messi_append.argtypes = [vp, vp, i64, vp]
+        lib.messi_append.restype = ctypes.c_int
         lib.messi_breakpoints.argtypes = [i32, vp]
         lib.messi_breakpoints.restype = ctypes.c_int
         lib.messi_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -236,6 +239,14 @@ class Index:
             self.close()
         except Exception:
             pass
+
+    def append(self, series, stream=None):
+        """Append rows: `series` is a CUDA tensor [new_n, len] whose first n
+        rows are the indexed ones; the index then borrows it."""
+        assert series.is_cuda and series.is_contiguous() and series.dim() == 2
+        _check(load().messi_append(self._h, ctypes.c_void_p(series.data_ptr()), series.shape[0],
+                                   _stream_ptr(stream)))
+        self.series = series
 
     def info(self) -> dict:
         inf = Info()
