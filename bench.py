@@ -363,6 +363,25 @@ def main():
         res["dtw_mode"]["cpu_baseline"] = cpu_baseline_dtw(data, qraw, k, length, band, n, threads=cpu["cores"])
     if ix is not None:
         ix.close()
+        ix = None
+    # appending the last 1% of the rows to an index of the first 99%
+    n0 = n - n // 100
+    ixa = messi.Index(data[:n0], w, b, cap)
+    app_ms = []
+    for rep in range(2):
+        if rep:
+            ixa.close()
+            ixa = messi.Index(data[:n0], w, b, cap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ixa.append(data)
+        torch.cuda.synchronize()
+        app_ms.append((time.perf_counter() - t0) * 1e3)
+    ai2, ad2 = ixa.knn(queries, k)
+    res["append"] = {"rows_before": n0, "rows_after": n, "ms": app_ms[-1],
+                     "gbps": n * length * 4 / (app_ms[-1] / 1e3) / 1e9, "n_leaves": ixa.info()["n_leaves"],
+                     "same_answers_as_full_build": bool(np.array_equal(ai2.cpu().numpy(), answers[0]))}
+    ixa.close()
     print(json.dumps(res), flush=True)
 
 
