@@ -296,19 +296,30 @@ template <int EP, int R>
 __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, float* out, int64_t n, int L,
                                                             int64_t in_stride, int* nonfinite) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
-    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
+    int64_t n_waves = (int64_t)gridDim.x * 4;
+    int64_t r_begin = 0, r_end = n;
+    if (in_stride < L && (gridDim.x & 7) == 0) {
+        // overlapping windows: blocks b, b + 8, ... run on one XCD; give each
+        // XCD one contiguous eighth of the rows, so that the values its
+        // windows share are read from HBM once into its own L2
+        const int64_t per = (n + 7) / 8;
+        r_begin = min(n, (int64_t)(blockIdx.x & 7) * per);
+        r_end = min(n, r_begin + per);
+        wave_id = (int64_t)(blockIdx.x >> 3) * 4 + wave;
+        n_waves = (int64_t)(gridDim.x >> 3) * 4;
+    }
     bool bad = false;
-    for (int64_t row0 = wave_id * R; row0 < n; row0 += n_waves * R) {
+    for (int64_t row0 = r_begin + wave_id * R; row0 < r_end; row0 += n_waves * R) {
         float x[R][EP];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t row = row0 + r;
-            const float* src = in + (size_t)(row < n ? row : 0) * (size_t)in_stride;
+            const float* src = in + (size_t)(row < r_end ? row : r_begin) * (size_t)in_stride;
 #pragma unroll
             for (int k = 0; k < EP; ++k) {
                 const int j = lane + 64 * k;
-                x[r][k] = (row < n && j < L) ? src[j] : 0.f;
+                x[r][k] = (row < r_end && j < L) ? src[j] : 0.f;
             }
         }
 #pragma unroll
@@ -347,7 +358,7 @@ __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, flo
             const double var = __ddiv_rn(s2, (double)L);
             const double sigma = __dsqrt_rn(var);
             const double rs = var == 0.0 ? 0.0 : __ddiv_rn(1.0, sigma);
-            if (row < n) {
+            if (row < r_end) {
                 float* dst = out + (size_t)row * (size_t)L;
 #pragma unroll
                 for (int k = 0; k < EP; ++k) {
