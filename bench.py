@@ -133,6 +133,8 @@ def main():
                     help="also serve with BF16 batches only, and without HIP graphs (configs 4, 5)")
     ap.add_argument("--no-fp32-batch", action="store_true",
                     help="skip the fp32 batched comparison call (config 3), e.g. under a profiler")
+    ap.add_argument("--core-only", action="store_true",
+                    help="config 2: skip the approximate, DTW and append measurements (e.g. under counters)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 4 GiB device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -309,6 +311,11 @@ def main():
                        "the same queries again with the library's HIP-event phase timing and counters (phases, "
                        "roofline: the scan kernel's own event pair on its stream)",
     }
+    if args.core_only:
+        if ix is not None:
+            ix.close()
+        print(json.dumps(res), flush=True)
+        return
     # the paper's approximate search on the same index and queries (the best
     # leaf's members only): its own rate and how often it finds the exact answer
     apx_i = torch.empty_like(ans_i)
