@@ -62,7 +62,7 @@ struct QState {
     uint32_t kstride;        // output row stride
     int32_t hbase;           // histogram bin of a distance = (float bits >> 16) - hbase, clamped
     uint32_t rerun;          // the scan runs a second pass from a tightened bound
-    uint32_t ntodo;          // DTW: series of this round waiting for their DTW
+    uint32_t pad1;
 };
 
 // Counters accumulated over a call (device).
@@ -92,8 +92,11 @@ struct QArgs {
     int32_t band;                // Sakoe-Chiba half-width; < 0: Euclidean search
     float rho_d;                 // relative error margin of the distances kept (ED or DTW)
     uint32_t chunk_lo, chunk_hi; // the scan takes chunks [chunk_lo, chunk_hi) of each query's order
-    Cand* todo;                  // [nq][todo_cap] DTW: (LB_Keogh, series) waiting for their DTW
-    uint32_t todo_cap;
+    Cand* todo;                  // [nq][todo_nseg][todo_seg] DTW: (LB_Keogh, series) waiting for their DTW,
+    uint32_t todo_cap;           //   a segment per scan block of the query; todo_cap = todo_nseg * todo_seg
+    uint32_t todo_seg, todo_nseg;
+    uint32_t* todo_cnt;          // [nq][todo_nseg] entries in each segment
+    float* env;                  // [nq][2][L] DTW: the query's envelope, upper then lower
     const float* queries;        // [nq][L]
     int32_t nq;
     QState* qs;
@@ -128,8 +131,8 @@ struct Workspace {
     uint32_t max_chunks = 0;
     DevBuf qs, lb, order, rec, chunk_first, bins, mbins, cursor, hist, approx_d, cand, counters, err, prof, blk_cnt,
         status, lbpart;
-    DevBuf todo;  // DTW search
-    size_t todo_slots = 0;
+    DevBuf todo, env, todo_cnt;  // DTW search
+    size_t todo_slots = 0, env_floats = 0, todo_cnt_n = 0;
     uint32_t* h_err = nullptr;  // pinned copy of the call's error flags
     // BF16 path
     int32_t bf_nq = 0;

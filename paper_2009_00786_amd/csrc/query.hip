@@ -169,7 +169,6 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
             st.nsurv = 0;
             st.ovf = 0;
             st.rerun = 0;
-            st.ntodo = 0;
             st.hbase = 0;
             st.lbmax = 0;
             st.argmin = ~0ull;
@@ -714,6 +713,7 @@ scan_kernel(QArgs a) {
     __shared__ float s_q2h, s_tau;                      // row filter: fl((1 - h) |q|^2), rf_tau |q|^2
     __shared__ uint32_t s_rck[SH ? kChunk + kEdBatch : 1];  // row filter: series indices that passed
     __shared__ uint32_t s_nrck;
+    __shared__ uint32_t s_ntodo;  // DTW: entries in this block's segment of the waiting list
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4, ql = lane & 15;
     const int nq = a.nq;
@@ -757,6 +757,7 @@ scan_kernel(QArgs a) {
             s_flag = (st.err != 0 || st.nsurv == 0 || (pass == 1 && st.rerun == 0)) ? 1u : 0u;
             s_Ublk = __uint_as_float(0x7f800000u);
             s_nrck = 0;
+            s_ntodo = 0;
         }
         __syncthreads();
         const bool skip = s_flag != 0;
@@ -792,18 +793,11 @@ scan_kernel(QArgs a) {
                 s_D[i * 256 + c] = mf * (d * d);
             }
             if (DTW) {
-                // LB_Keogh envelope: every query value within the band
-                const float* qg = a.queries + (size_t)q * L;
+                // the query's LB_Keogh envelope (dtw_env_kernel)
+                const float* eg = a.env + (size_t)q * 2 * L;
                 for (int jj = tid; jj < L; jj += kScanThreads) {
-                    const int t0 = max(0, jj - a.band), t1 = min(L - 1, jj + a.band);
-                    float u = qg[t0], l = u;
-                    for (int t = t0 + 1; t <= t1; ++t) {
-                        const float v = qg[t];
-                        u = fmaxf(u, v);
-                        l = fminf(l, v);
-                    }
-                    s_q[jj] = u;
-                    s_q[MESSI_MAX_LEN + jj] = l;
+                    s_q[jj] = eg[jj];
+                    s_q[MESSI_MAX_LEN + jj] = eg[L + jj];
                 }
             } else if (!SH) {
                 for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
@@ -1118,12 +1112,16 @@ scan_kernel(QArgs a) {
                     }
                 }
                 if (act && ql == 0 && !from_rck) ++c_dist;
-                if (DTW && alive && ql == 0) {
-                    // LB_Keogh within the bound: the series waits for its DTW
-                    if (acc * (1.0f - kRhoEd) <= s_Ublk) {
-                        const uint32_t slot = atomicAdd(&st.ntodo, 1u);
-                        if (slot < a.todo_cap) a.todo[(size_t)q * a.todo_cap + slot] = Cand{acc, gidx};
-                        else st.ovf = 1;
+                if (DTW) {
+                    // LB_Keogh within the bound: the series waits for its DTW, in
+                    // this block's own segment of the list (a counter in LDS: one
+                    // counter for the whole grid would serialise the appends)
+                    if (alive && ql == 0 && !(acc * (1.0f - kRhoEd) > s_Ublk)) {
+                        const uint32_t slot = atomicAdd(&s_ntodo, 1u);
+                        if (slot < a.todo_seg)
+                            a.todo[(size_t)q * a.todo_cap + (size_t)j * a.todo_seg + slot] = Cand{acc, gidx};
+                        else
+                            st.ovf = 1;
                     }
                 } else if (alive && ql == 0) {
                     const float d = acc;
@@ -1156,6 +1154,7 @@ scan_kernel(QArgs a) {
             for (int r = 0; r < kPer; ++r) wd[r] = wdn[r];
         }
         __syncthreads();
+        if (DTW && tid == 0) a.todo_cnt[(size_t)q * a.todo_nseg + j] = min(s_ntodo, a.todo_seg);
     }
     if (timing && tid == 0 && (pass == 0 || worked)) {
         // pass 0 writes the block's times; a second pass adds its own
@@ -1279,64 +1278,211 @@ __device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, 
     return out;
 }
 
-// The series of a round whose LB_Keogh is within the bound get their fp32
-// DTW; those within the bound become candidates, and for k = 1 they lower U.
+// Keep this wave's LDS accesses in program order for the compiler: the
+// hardware performs one wave's LDS operations in the order issued, so no wait
+// is needed (a wavefront-scope fence emits none).
+__device__ __forceinline__ void wave_order() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// LB_Keogh of the query against the candidate's envelope (the candidate-side
+// bound): every warping path in the band matches q_i with some x_j,
+// |i - j| <= r, and x_j lies inside [min, max] of x over [i - r, i + r], so
+// the sum over i of the squared distance from q_i to that interval is below
+// the DTW.  One wave computes it for one candidate: the row goes into LDS
+// padded with 32 values of -inf / +inf on each side, five in-place doubling
+// steps turn each padded position p into the max (min) of p .. p + 31, and
+// the window of position j (2r + 1 <= 55 values) is covered by the two spans
+// starting at j - r and j + r - 31.  For r < 16 the spans reach past the
+// window: a wider interval, so a smaller but still valid bound.  Within a
+// wave, LDS operations run in program order, so the reads of a step precede
+// its writes.
+__device__ float lb_keogh_ec_wave(const float* __restrict__ x, const float* __restrict__ q, float* tmax,
+                                  float* tmin, int L, int r, int lane) {
+    const float inf = __builtin_huge_valf();
+    const int P = L + 64;  // padded length; reads reach P + 31
+    for (int p = lane; p < P + 32; p += 64) {
+        const int j = p - 32;
+        const bool in = j >= 0 && j < L;
+        const float v = in ? x[j] : 0.f;
+        tmax[p] = in ? v : -inf;
+        tmin[p] = in ? v : inf;
+    }
+    wave_order();
+    for (int h = 1; h < 32; h <<= 1) {
+        for (int c0 = 0; c0 < P; c0 += 64) {
+            const int p = c0 + lane;
+            const float a0 = tmax[p], a1 = tmax[p + h], b0 = tmin[p], b1 = tmin[p + h];
+            wave_order();
+            tmax[p] = fmaxf(a0, a1);
+            tmin[p] = fminf(b0, b1);
+            wave_order();
+        }
+    }
+    float ec = 0.f;
+    for (int j = lane; j < L; j += 64) {
+        const int p0 = j - r + 32, p1 = j + r + 1;  // spans [p0, p0 + 31] and [p1, p1 + 31]
+        const float u = fmaxf(tmax[p0], tmax[p1]), l = fminf(tmin[p0], tmin[p1]);
+        const float g = keogh_gap(q[j], u, l);
+        ec = fmaf(g, g, ec);
+    }
+    wave_order();  // the tables are reused for the next candidate
+    return dev::wave_sum(ec);
+}
+
+// The series of a round whose LB_Keogh is within the bound: those whose
+// candidate-side bound is within it too go to a block queue, and the queue
+// is drained 256 at a time (a thread each, so that full waves run the DP) by
+// the fp32 banded DTW; those within the bound become candidates, and for
+// k = 1 they lower U.
 template <int W>
 __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
     __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ float s_eu[MESSI_MAX_LEN], s_el[MESSI_MAX_LEN];
+    __shared__ float s_tab[4][2][MESSI_MAX_LEN + 96];  // per wave: max and min tables
+    __shared__ Cand s_queue[512];
+    __shared__ uint32_t s_nq;
+    __shared__ uint32_t s_off[4097];  // the query's segments (at most 4096): exclusive prefix of their counts
+    __shared__ uint32_t s_tmp[4];
     const int q = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     QState& st = a.qs[q];
     if (st.err) return;
-    const float* qg = a.queries + (size_t)q * a.L;
-    for (int j = threadIdx.x; j < a.L; j += 256) {
+    const int L = a.L, r = a.band;
+    const float* qg = a.queries + (size_t)q * L;
+    const float* eg = a.env + (size_t)q * 2 * L;
+    for (int j = tid; j < L; j += 256) {
         s_q[j] = qg[j];
-        const int t0 = max(0, j - a.band), t1 = min(a.L - 1, j + a.band);
-        float u = qg[t0], l = u;
-        for (int t = t0 + 1; t <= t1; ++t) {
-            u = fmaxf(u, qg[t]);
-            l = fminf(l, qg[t]);
-        }
-        s_eu[j] = u;
-        s_el[j] = l;
+        s_eu[j] = eg[j];
+        s_el[j] = eg[L + j];
     }
+    if (tid == 0) s_nq = 0;
     __syncthreads();
-    const uint32_t n = st.ntodo;
-    if (n > a.todo_cap) {
-        // a round left series out (cannot happen with rounds of at most
-        // todo_cap members, checked anyway)
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (st.ovf) {
+        // a segment of the waiting list overflowed (cannot happen: a segment
+        // holds every member of its block's chunks of a round; checked anyway)
+        if (blockIdx.x == 0 && tid == 0) {
             st.err = 2;
             atomicOr(a.err_any, 2u);
         }
         return;
     }
-    const Cand* td = a.todo + (size_t)q * a.todo_cap;
-    const float* series = a.series;
+    float* tmax = s_tab[wave][0];
+    float* tmin = s_tab[wave][1];
     unsigned long long ndtw = 0;
-    for (uint32_t e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
-        const Cand t = td[e];
-        if (t.d * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U))) continue;
-        ++ndtw;
-        const float d = dtw_band<W, float>(s_q, series + (size_t)t.idx * a.L, a.L, a.band,
-                                           __uint_as_float(vload(&st.U)), s_eu, s_el, t.d);
-        if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
-            const uint32_t slot = atomicAdd(&st.ncand, 1u);
-            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, t.idx};
-            if (st.k == 1) atomicMin(&st.U, __float_as_uint(d * (1.0f + 2.0f * kRhoDtw)));
+    // DTW for the queued series, 256 at a time; with `all`, until the queue is empty
+    auto drain = [&](bool all) {
+        for (;;) {
+            const uint32_t nq = s_nq;
+            if (nq < 256 && !(all && nq > 0)) break;
+            const uint32_t take = min(nq, 256u);
+            if ((uint32_t)tid < take) {
+                const Cand c = s_queue[tid];
+                const float U = __uint_as_float(vload(&st.U));
+                if (!(c.d * (1.0f - kRhoEd) > U)) {
+                    ++ndtw;
+                    const float d = dtw_band<W, float>(s_q, a.series + (size_t)c.idx * L, L, r, U, s_eu, s_el, c.d);
+                    if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
+                        const uint32_t slot = atomicAdd(&st.ncand, 1u);
+                        if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, c.idx};
+                        if (st.k == 1) atomicMin(&st.U, __float_as_uint(d * (1.0f + 2.0f * kRhoDtw)));
+                    }
+                }
+            }
+            __syncthreads();
+            // move the rest to the front
+            const uint32_t rest = nq - take;
+            Cand keep{0.f, 0u};
+            if ((uint32_t)tid < rest) keep = s_queue[take + tid];
+            __syncthreads();
+            if ((uint32_t)tid < rest) s_queue[tid] = keep;
+            if (tid == 0) s_nq = rest;
+            __syncthreads();
         }
+    };
+    // the entries of all the query's segments as one list (prefix sums of the
+    // segment counts; a segment per scan block, at most 4096), spread evenly
+    // over the blocks
+    const uint32_t G = a.todo_nseg;
+    const int per = (int)((G + 255) / 256);
+    uint32_t loc[16], sum = 0;
+    for (int k2 = 0; k2 < per && k2 < 16; ++k2) {
+        const uint32_t i2 = (uint32_t)tid * per + k2;
+        loc[k2] = i2 < G ? a.todo_cnt[(size_t)q * G + i2] : 0u;
+        sum += loc[k2];
     }
+    uint32_t n = 0;
+    uint32_t ex = block_exclusive_scan(sum, s_tmp, n);
+    for (int k2 = 0; k2 < per && k2 < 16; ++k2) {
+        const uint32_t i2 = (uint32_t)tid * per + k2;
+        if (i2 < G) s_off[i2] = ex;
+        ex += loc[k2];
+    }
+    if (tid == 0) s_off[G] = n;
+    __syncthreads();
+    const uint32_t stride = gridDim.x * 256;
+    for (uint32_t base = blockIdx.x * 256; base < n; base += stride) {
+        // ---- the two lower bounds for this batch, a wave per candidate
+        const uint32_t e = base + tid;
+        Cand t{0.f, 0u};
+        bool act = e < n;
+        if (act) {
+            // the segment holding entry e: the last whose offset is <= e
+            uint32_t lo = 0, hi = G - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            t = a.todo[(size_t)q * a.todo_cap + (size_t)lo * a.todo_seg + (e - s_off[lo])];
+            act = !(t.d * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U)));
+        }
+        // a wave per candidate
+        float ec = 0.f;
+        uint64_t m = __ballot(act);
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const uint32_t idx = __shfl(t.idx, l);
+            const float v = lb_keogh_ec_wave(a.series + (size_t)idx * L, s_q, tmax, tmin, L, r, lane);
+            if (lane == l) ec = v;
+        }
+        if (act && !(ec * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U)))) s_queue[atomicAdd(&s_nq, 1u)] = t;
+        __syncthreads();
+        drain(false);
+    }
+    drain(true);
     if (a.counters) {
         for (int off = 32; off >= 1; off >>= 1) ndtw += __shfl_xor(ndtw, off);
-        if ((threadIdx.x & 63) == 0 && ndtw) atomicAdd(&a.counters->recheck, ndtw);
+        if (lane == 0 && ndtw) atomicAdd(&a.counters->recheck, ndtw);
+    }
+}
+
+// Once per DTW call: every query's LB_Keogh envelope, the largest and the
+// smallest query value within the band of each position.
+__global__ void __launch_bounds__(256) dtw_env_kernel(QArgs a) {
+    const int q = blockIdx.x;
+    const int L = a.L, r = a.band;
+    const float* qg = a.queries + (size_t)q * L;
+    float* eg = a.env + (size_t)q * 2 * L;
+    for (int j = threadIdx.x; j < L; j += 256) {
+        const int t0 = max(0, j - r), t1 = min(L - 1, j + r);
+        float u = qg[t0], l = u;
+        for (int t = t0 + 1; t <= t1; ++t) {
+            u = fmaxf(u, qg[t]);
+            l = fminf(l, qg[t]);
+        }
+        eg[j] = u;
+        eg[L + j] = l;
     }
 }
 
 // Before a DTW round: empty every query's list of waiting series.
 __global__ void __launch_bounds__(256) todo_reset_kernel(QArgs a) {
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q < a.nq) a.qs[q].ntodo = 0;
-    if (q == 0) a.err_any[2] = 0;
+    const size_t n = (size_t)a.nq * a.todo_nseg;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) a.todo_cnt[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.err_any[2] = 0;
 }
 
 // After a DTW round: count the queries whose order goes on past chunk c1 with
@@ -1851,10 +1997,12 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
 }
 
 // Rounds of the DTW search: the first takes each query's first 16 chunks of
-// its order (its best leaves, for a tight bound early), each later one twice
-// as many, up to kDtwRoundChunks; a round's waiting list holds every member
-// of its chunks at most once, so it cannot overflow.
-constexpr uint32_t kDtwRoundChunks = 1024;
+// its order (its best leaves, for a tight bound early), each later one four
+// times as many, up to kDtwRoundChunks / nq (at least 64).  A round costs a
+// launch of each kernel whatever its size, so the rounds grow fast.  The
+// waiting list has a segment per scan block of a query, large enough for
+// every member of that block's chunks of a round, so it cannot overflow.
+constexpr uint32_t kDtwRoundChunks = 8192;
 
 int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
                    int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
@@ -1867,15 +2015,37 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     if (timing) MESSI_TRY(ws->ensure_stats());
     a.band = band;
     a.rho_d = kRhoDtw;
-    const uint32_t todo_cap = kDtwRoundChunks * (uint32_t)kChunk;
+    // scan blocks per query (the scan's own split of its grid) and the segments
+    const int B = scan_grid(kScanDtw);
+    const uint32_t g_max = nq <= B ? (uint32_t)((B + nq - 1) / nq) : 1u;
+    const uint32_t g_min = nq <= B ? (uint32_t)(B / nq) : 1u;
+    const uint64_t round_max = std::max<uint64_t>(64, kDtwRoundChunks / (uint32_t)nq);
+    const uint32_t seg = (uint32_t)((round_max + g_min - 1) / g_min) * (uint32_t)kChunk;
+    const uint32_t todo_cap = g_max * seg;
     if (ws->todo_slots < (size_t)nq * todo_cap) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         MESSI_TRY(ws->todo.alloc(sizeof(Cand) * (size_t)nq * todo_cap));
         ws->todo_slots = (size_t)nq * todo_cap;
         ++ws->gen;
     }
+    if (ws->todo_cnt_n < (size_t)nq * g_max) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(ws->todo_cnt.alloc(sizeof(uint32_t) * (size_t)nq * g_max));
+        ws->todo_cnt_n = (size_t)nq * g_max;
+        ++ws->gen;
+    }
     a.todo = ws->todo.as<Cand>();
     a.todo_cap = todo_cap;
+    a.todo_seg = seg;
+    a.todo_nseg = g_max;
+    a.todo_cnt = ws->todo_cnt.as<uint32_t>();
+    if (ws->env_floats < (size_t)nq * 2 * ix->len) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(ws->env.alloc(sizeof(float) * (size_t)nq * 2 * ix->len));
+        ws->env_floats = (size_t)nq * 2 * ix->len;
+        ++ws->gen;
+    }
+    a.env = ws->env.as<float>();
     hipEvent_t* ev = ws->ev;
     auto mark = [&](int i) -> int {
         if (timing) MESSI_HIP_TRY(hipEventRecord(ev[i], s));
@@ -1884,6 +2054,8 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     const unsigned lb_blocks = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((a.nL + kLeafBlock - 1) / kLeafBlock, (8192 + nq - 1) / nq));
     MESSI_TRY(mark(0));
+    hipLaunchKernelGGL(dtw_env_kernel, dim3(nq), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("dtw_env");
     hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a, k, (const int32_t*)nullptr,
                        (uint32_t)k);
     MESSI_LAUNCH_CHECK("leaf_lb");
@@ -1914,12 +2086,13 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     const unsigned dtw_blocks = (unsigned)std::max(1, scan_grid(kScanDtw) / std::max(1, nq));
     const unsigned nqb = (unsigned)((nq + 255) / 256);
     int rounds = 0;
-    for (uint64_t c0 = 0, size = 16; c0 < max_nch;) {
+    for (uint64_t c0 = 0, size = std::min<uint64_t>(16, round_max); c0 < max_nch;) {
         const uint64_t c1 = std::min<uint64_t>(c0 + size, max_nch);
         a.chunk_lo = (uint32_t)c0;
         a.chunk_hi = (uint32_t)c1;
         ++rounds;
-        hipLaunchKernelGGL(todo_reset_kernel, dim3(nqb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(todo_reset_kernel, dim3((unsigned)std::min<size_t>(((size_t)nq * g_max + 255) / 256, 1024)),
+                           dim3(256), 0, s, a);
         MESSI_LAUNCH_CHECK("todo_reset");
         MESSI_TRY(launch_scan(a, vec, 0, kScanDtw, s));
         if (W == 16) hipLaunchKernelGGL(dtw_kernel<16>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
@@ -1928,7 +2101,7 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
         MESSI_LAUNCH_CHECK("dtw");
         MESSI_TRY(refresh_bounds(a, s));
         c0 = c1;
-        size = std::min<uint64_t>(2 * size, kDtwRoundChunks);
+        size = std::min<uint64_t>(4 * size, round_max);
         if (c0 >= max_nch) break;
         // stop early once no query's order goes on below its bound
         hipLaunchKernelGGL(dtw_active_kernel, dim3(nqb), dim3(256), 0, s, a, (uint32_t)c0);
