@@ -77,9 +77,10 @@ constexpr int kLeafBlock = 256;  // leaves per block of the bound kernels
 // finiteness, and the region widening delta.  The bounds take per segment an
 // interval [plo, phi] of the query side: the PAA value for ED; under DTW the
 // smallest and largest value of the query's LB_Keogh envelope over the
-// segment (exact: minima and maxima of query values).
+// segment (exact: minima and maxima of query values).  The intervals stay in
+// LDS (s_red[8 + i] and s_red[24 + i]): indexed by a run-time segment, a
+// register copy would live in scratch memory.
 struct QSum {
-    float plo[16], phi[16];
     float norm2, amax, delta;
     bool bad;
 };
@@ -124,10 +125,6 @@ __device__ void query_summary(const QArgs& a, const float* row, float* s_q, floa
         s_red[24 + i] = hi;
     }
     __syncthreads();
-    for (int i = 0; i < 16; ++i) {
-        out.plo[i] = s_red[8 + i];
-        out.phi[i] = s_red[24 + i];
-    }
     out.norm2 = s_red[0] + s_red[1] + s_red[2] + s_red[3];
     out.amax = fmaxf(fmaxf(s_red[4], s_red[5]), fmaxf(s_red[6], s_red[7]));
     const float u = 5.9604644775390625e-08f;  // 2^-24
@@ -157,8 +154,8 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     if (blockIdx.x == 0) {
         QState& st = a.qs[q];
         if (threadIdx.x < 16) {
-            st.paa[threadIdx.x] = qs.plo[threadIdx.x];
-            st.paa_hi[threadIdx.x] = qs.phi[threadIdx.x];
+            st.paa[threadIdx.x] = s_red[8 + threadIdx.x];
+            st.paa_hi[threadIdx.x] = s_red[24 + threadIdx.x];
         }
         if (threadIdx.x == 0) {
             st.norm2 = qs.norm2;
@@ -188,18 +185,19 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
         }
         for (int i = threadIdx.x; i < kHistBins; i += 256) a.hist[(size_t)q * kHistBins + i] = 0;
     }
-    for (int idx = threadIdx.x; idx < a.w * (A + 1); idx += 256) {
-        const int i = idx / (A + 1), c = idx % (A + 1);
-        const float pl = qs.plo[i], ph = qs.phi[i];
-        float tl = 0.f, th = 0.f;
-        if (c > 0 && c < A) {
-            const float lo = s_bp[c - 1] - qs.delta;
-            const float hi = s_bp[c - 1] + qs.delta;
-            if (ph < lo) tl = (lo - ph) * (lo - ph);
-            if (pl > hi) th = (pl - hi) * (pl - hi);
+    for (int i = 0; i < a.w; ++i) {
+        const float pl = s_red[8 + i], ph = s_red[24 + i];
+        for (int c = threadIdx.x; c <= A; c += 256) {
+            float tl = 0.f, th = 0.f;
+            if (c > 0 && c < A) {
+                const float lo = s_bp[c - 1] - qs.delta;
+                const float hi = s_bp[c - 1] + qs.delta;
+                if (ph < lo) tl = (lo - ph) * (lo - ph);
+                if (pl > hi) th = (pl - hi) * (pl - hi);
+            }
+            s_lo[i * 257 + c] = tl;
+            s_hi[i * 257 + c] = th;
         }
-        s_lo[i * 257 + c] = tl;
-        s_hi[i * 257 + c] = th;
     }
     __syncthreads();
     unsigned long long best = ~0ull;
@@ -264,6 +262,17 @@ __device__ __forceinline__ void approx_range(const QArgs& a, uint32_t leaf, int3
 template <class Getter>
 __device__ float block_kth(Getter get, uint32_t n, uint32_t k, uint32_t* s_hist, uint32_t* s_bcast) {
     if (n < k) return __uint_as_float(0x7f800000u);
+    if (k == 1) {
+        // the smallest key: one block reduction instead of four passes
+        uint32_t m = 0xffffffffu;
+        for (uint32_t i = threadIdx.x; i < n; i += 256) m = min(m, __float_as_uint(get(i)));
+        for (int off = 32; off >= 1; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off));
+        if ((threadIdx.x & 63) == 0) s_hist[threadIdx.x >> 6] = m;
+        __syncthreads();
+        m = min(min(s_hist[0], s_hist[1]), min(s_hist[2], s_hist[3]));
+        __syncthreads();
+        return __uint_as_float(m);
+    }
     uint32_t prefix = 0, mask = 0, kk = k;
     for (int pass = 3; pass >= 0; --pass) {
         const int shift = 8 * pass;
@@ -1567,9 +1576,25 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
             }
             __syncthreads();
             if (j < kept && lane == 0) {
+                // 16 values per round of LDS reads, so that the chain of
+                // additions does not wait on each read
                 double s = 0.0;
-                for (int t = 0; t < a.L; ++t) {
-                    const double d = __dsub_rn((double)s_q[t], (double)stage[t]);
+                int t0 = 0;
+                for (; t0 + 16 <= a.L; t0 += 16) {
+                    float xv[16], qv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        xv[u] = stage[t0 + u];
+                        qv[u] = s_q[t0 + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const double d = __dsub_rn((double)qv[u], (double)xv[u]);
+                        s = __dadd_rn(s, __dmul_rn(d, d));
+                    }
+                }
+                for (; t0 < a.L; ++t0) {
+                    const double d = __dsub_rn((double)s_q[t0], (double)stage[t0]);
                     s = __dadd_rn(s, __dmul_rn(d, d));
                 }
                 s_d[j] = s;
