@@ -7,7 +7,9 @@ namespace messi {
 
 constexpr int kNB = 1024;            // lower-bound bins used to order the surviving leaves
 constexpr int kApproxMax = 4096;     // members of the first leaf evaluated for the first bound
-constexpr int kApproxBlocks = 128;   // blocks per query for that leaf
+// blocks per query for that leaf: for one or two queries a wave per member
+// of a full leaf, so no wave waits on a second row
+inline int approx_blocks(int nq) { return nq <= 2 ? 512 : nq <= 8 ? 256 : 128; }
 constexpr int kMaxFinal = 4096;      // candidates ordered by fp64 distance per query
 constexpr int kChunk = 1024;         // members per scan work unit
 constexpr int kHistBins = 4096;      // candidate-distance histogram (k > 1 bound)

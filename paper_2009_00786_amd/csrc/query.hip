@@ -148,6 +148,10 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     __shared__ float s_bp[256];
     const int q = blockIdx.y;
     const int A = 1 << a.b;
+    // this thread's first leaf, in flight while the query summary is formed
+    const int l0 = blockIdx.x * kLeafBlock + threadIdx.x;
+    Leaf lf0{};
+    if (l0 < a.nL) lf0 = a.leaves[l0];
     if (threadIdx.x < A - 1) s_bp[threadIdx.x] = a.bp[threadIdx.x];
     QSum qs;
     query_summary(a, a.queries + (size_t)q * a.L, s_q, s_red, &s_bad, qs);
@@ -203,9 +207,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     unsigned long long best = ~0ull;
     uint32_t mx = 0;
     const float mf = (float)a.m;
-    // leaves blockIdx.x * 256 + threadIdx.x, stepping over the query's blocks
-    for (int l = blockIdx.x * kLeafBlock + threadIdx.x; l < a.nL; l += gridDim.x * kLeafBlock) {
-        const Leaf lf = a.leaves[l];
+    auto bound = [&](const Leaf& lf, int l) {
         float s = 0.f;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -221,7 +223,10 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
         const unsigned long long key = ((unsigned long long)__float_as_uint(lbv) << 32) | (uint32_t)l;
         best = key < best ? key : best;
         mx = max(mx, __float_as_uint(lbv));
-    }
+    };
+    // leaves blockIdx.x * 256 + threadIdx.x, stepping over the query's blocks
+    if (l0 < a.nL) bound(lf0, l0);
+    for (int l = l0 + gridDim.x * kLeafBlock; l < a.nL; l += gridDim.x * kLeafBlock) bound(a.leaves[l], l);
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(best, off);
         best = o < best ? o : best;
@@ -355,12 +360,24 @@ __global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a, uint32_t nlb) {
     approx_range(a, (uint32_t)(best & 0xffffffffull), st.k, r0, cnt);
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const bool vec = (a.L & 3) == 0 && ((uintptr_t)a.series & 15u) == 0;
     for (uint32_t r = gw; r < cnt; r += gridDim.x * 4) {
         const float* x = a.series + (size_t)a.pos[r0 + r] * a.L;
         float s = 0.f;
-        for (int j = lane; j < a.L; j += 64) {
-            const float d = s_q[j] - x[j];
-            s = fmaf(d, d, s);
+        if (vec) {
+            for (int j = lane * 4; j < a.L; j += 256) {
+                const float4 v = *reinterpret_cast<const float4*>(x + j);
+                const float d0 = s_q[j] - v.x, d1 = s_q[j + 1] - v.y, d2 = s_q[j + 2] - v.z, d3 = s_q[j + 3] - v.w;
+                s = fmaf(d0, d0, s);
+                s = fmaf(d1, d1, s);
+                s = fmaf(d2, d2, s);
+                s = fmaf(d3, d3, s);
+            }
+        } else {
+            for (int j = lane; j < a.L; j += 64) {
+                const float d = s_q[j] - x[j];
+                s = fmaf(d, d, s);
+            }
         }
         s = dev::wave_sum(s);
         if (lane == 0) a.approx_d[(size_t)q * kApproxMax + r] = s;
@@ -1926,7 +1943,7 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a, c.kmax, c.kq, (uint32_t)c.kmax);
     MESSI_LAUNCH_CHECK("leaf_lb");
     MESSI_TRY(mark(2));
-    hipLaunchKernelGGL(approx_ed_kernel, dim3(kApproxBlocks, nq), dim3(256), 0, s, a, lb_blocks);
+    hipLaunchKernelGGL(approx_ed_kernel, dim3(approx_blocks(nq), nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_ed");
     hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_select");
@@ -2087,7 +2104,7 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     MESSI_TRY(mark(2));
     // the first bound: Euclidean distances to the best leaf's members (the
     // diagonal path lies in every band, so DTW <= ED)
-    hipLaunchKernelGGL(approx_ed_kernel, dim3(kApproxBlocks, nq), dim3(256), 0, s, a, lb_blocks);
+    hipLaunchKernelGGL(approx_ed_kernel, dim3(approx_blocks(nq), nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_ed");
     hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_select");
