@@ -109,7 +109,7 @@ struct QArgs {
     uint32_t max_chunks;
     uint32_t* bins;              // [nq][kNB] leaves per bound bin, then their exclusive prefix
     uint32_t* mbins;             // [nq][kNB] members per bound bin
-    unsigned long long* cursor;  // [nq][kNB] (position << 32 | member offset) fill cursors
+    unsigned long long* cursor;  // [nq][kNB] per bin: (leaves placed << 32 | their members), zeroed per call
     uint32_t* hist;              // [nq][kHistBins] candidate-distance histogram
     float* approx_d;             // [nq][kApproxMax]
     LbPart* lbpart;              // [nq][leaf-bound blocks]

@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
         for (int i = threadIdx.x; i < kNB; i += 256) {
             a.bins[(size_t)q * kNB + i] = 0;
             a.mbins[(size_t)q * kNB + i] = 0;
+            a.cursor[(size_t)q * kNB + i] = 0;
         }
         for (int i = threadIdx.x; i < kHistBins; i += 256) a.hist[(size_t)q * kHistBins + i] = 0;
     }
@@ -384,35 +385,58 @@ __global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a, uint32_t nlb) {
     }
 }
 
-// The k-th of those distances: the first upper bound U (the paper's initial
-// best-so-far), the histogram base and the bound range of the bins.
+// The k-th of those distances: the first upper bound U0 (the paper's initial
+// best-so-far); with the smallest and largest leaf bound.  Block-wide: every
+// thread gets the result, and every block that computes it gets the same.
+struct FirstBound {
+    unsigned long long best;  // (bound bits << 32) | leaf of the smallest leaf bound
+    uint32_t mx;              // largest leaf bound (float bits)
+    float U0;
+    // the bound range mapped onto the order's bins
+    __device__ float range() const {
+        const float r = isinf(U0) ? __uint_as_float(mx) : U0;
+        return r > 0.f ? r : 1e-30f;
+    }
+};
+
+struct FirstBoundSmem {
+    unsigned long long s_min[4];
+    uint32_t s_max[4];
+    uint32_t s_hist[256 + 4];
+    uint32_t s_b[2];
+};
+
+__device__ FirstBound first_bound(const QArgs& a, int q, int32_t k, uint32_t nlb, FirstBoundSmem& sm) {
+    FirstBound f;
+    lb_extremes(a, q, nlb, sm.s_min, sm.s_max, f.best, f.mx);
+    uint32_t r0, cnt;
+    approx_range(a, (uint32_t)(f.best & 0xffffffffull), k, r0, cnt);
+    const float* d = a.approx_d + (size_t)q * kApproxMax;
+    const float kth = block_kth([&](uint32_t i) { return d[i]; }, cnt, (uint32_t)k, sm.s_hist, sm.s_b);
+    f.U0 = isinf(kth) ? kth : upper_u(kth);
+    return f;
+}
+
+// The members evaluated for the first bound only set it; their leaf stays in
+// the order and is scanned like any other, so every candidate is appended
+// exactly once per pass.
+__device__ void store_first_bound(QState& st, const FirstBound& f) {
+    st.argmin = f.best;
+    st.lbmax = f.mx;
+    st.U = __float_as_uint(f.U0);
+    st.hbase = (int32_t)(__float_as_uint(f.U0) >> 16) - (kHistBins - 2);
+    st.range = f.range();
+}
+
+// Approximate mode: the first bound into the query's state (the exact
+// searches form it inside the bin-histogram kernel instead).
 __global__ void __launch_bounds__(256) approx_select_kernel(QArgs a, uint32_t nlb) {
-    __shared__ unsigned long long s_min[4];
-    __shared__ uint32_t s_max[4];
-    __shared__ uint32_t s_hist[256 + 4];
-    __shared__ uint32_t s_b[2];
+    __shared__ FirstBoundSmem sm;
     const int q = blockIdx.x;
     QState& st = a.qs[q];
     if (st.err) return;
-    unsigned long long best;
-    uint32_t mx;
-    lb_extremes(a, q, nlb, s_min, s_max, best, mx);
-    uint32_t r0, cnt;
-    approx_range(a, (uint32_t)(best & 0xffffffffull), st.k, r0, cnt);
-    const float* d = a.approx_d + (size_t)q * kApproxMax;
-    const float kth = block_kth([&](uint32_t i) { return d[i]; }, cnt, (uint32_t)st.k, s_hist, s_b);
-    const float U0 = isinf(kth) ? kth : upper_u(kth);
-    // The members evaluated here only set the first bound; the leaf stays in
-    // the order and is scanned like any other, so every candidate is appended
-    // exactly once per pass.
-    if (threadIdx.x == 0) {
-        st.argmin = best;
-        st.lbmax = mx;
-        st.U = __float_as_uint(U0);
-        st.hbase = (int32_t)(__float_as_uint(U0) >> 16) - (kHistBins - 2);
-        float range = isinf(U0) ? __uint_as_float(mx) : U0;
-        st.range = range > 0.f ? range : 1e-30f;
-    }
+    const FirstBound f = first_bound(a, q, st.k, nlb, sm);
+    if (threadIdx.x == 0) store_first_bound(st, f);
 }
 
 // Approximate mode: the evaluated members of the first leaf whose distance is
@@ -451,19 +475,24 @@ __device__ __forceinline__ int bin_of(float lbv, float range) {
 
 __device__ __forceinline__ bool leaf_kept(float lbv, float U0) { return !(lbv * (1.0f - kRhoLb) > U0); }
 
-// Leaves and members per bound bin.
-__global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
+// Leaves and members per bound bin.  Every block first forms the first bound
+// (the same in each; block 0 stores it for the later kernels): one launch
+// fewer on the query's critical path.
+__global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a, uint32_t nlb) {
     __shared__ uint32_t h[kNB];
     __shared__ uint32_t hm[kNB];
+    __shared__ FirstBoundSmem sm;
     const int q = blockIdx.y;
-    const QState& st = a.qs[q];
+    QState& st = a.qs[q];
     if (st.err) return;
     for (int i = threadIdx.x; i < kNB; i += 256) {
         h[i] = 0;
         hm[i] = 0;
     }
+    const FirstBound f = first_bound(a, q, st.k, nlb, sm);
+    if (blockIdx.x == 0 && threadIdx.x == 0) store_first_bound(st, f);
     __syncthreads();
-    const float U0 = __uint_as_float(st.U), range = st.range;
+    const float U0 = f.U0, range = f.range();
     for (int l = blockIdx.x * kLeafBlock + threadIdx.x; l < a.nL; l += gridDim.x * kLeafBlock) {
         const float lbv = a.lb[(size_t)q * a.nL + l];
         if (leaf_kept(lbv, U0)) {
@@ -480,54 +509,54 @@ __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a) {
         }
 }
 
-// Exclusive prefix sums of the leaf and member counts per bin (4 consecutive
-// bins per thread): the fill cursors of the scatter, the number of ordered
-// leaves and of their members.
-__global__ void __launch_bounds__(256) bin_scan_kernel(QArgs a) {
+// Place every kept leaf at its position in the bin order.  Every block first
+// takes the exclusive prefix sums of the leaf and member counts per bin (4
+// consecutive bins per thread; the same in each block, and block 0 stores the
+// totals): the bins' first positions and member offsets.  Within a bin one
+// 64-bit atomic on its fill counter hands out the position and the member
+// offset together, so member offsets increase with the position; the leaf
+// whose member range holds the first member of a scan chunk records itself as
+// that chunk's first position.
+__global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
+    __shared__ uint32_t s_pos[kNB], s_moff[kNB];
     __shared__ uint32_t s_tmp[4];
-    const int q = blockIdx.x;
+    const int q = blockIdx.y;
     QState& st = a.qs[q];
     if (st.err) return;
-    constexpr int kPer = kNB / 256;
-    uint32_t v[kPer], vm[kPer], sv = 0, svm = 0;
-    for (int i = 0; i < kPer; ++i) {
-        v[i] = a.bins[(size_t)q * kNB + threadIdx.x * kPer + i];
-        vm[i] = a.mbins[(size_t)q * kNB + threadIdx.x * kPer + i];
-        sv += v[i];
-        svm += vm[i];
+    {
+        constexpr int kPer = kNB / 256;
+        uint32_t v[kPer], vm[kPer], sv = 0, svm = 0;
+        for (int i = 0; i < kPer; ++i) {
+            v[i] = a.bins[(size_t)q * kNB + threadIdx.x * kPer + i];
+            vm[i] = a.mbins[(size_t)q * kNB + threadIdx.x * kPer + i];
+            sv += v[i];
+            svm += vm[i];
+        }
+        uint32_t tot, totm;
+        uint32_t ex = block_exclusive_scan(sv, s_tmp, tot);
+        __syncthreads();
+        uint32_t exm = block_exclusive_scan(svm, s_tmp, totm);
+        for (int i = 0; i < kPer; ++i) {
+            s_pos[threadIdx.x * kPer + i] = ex;
+            s_moff[threadIdx.x * kPer + i] = exm;
+            ex += v[i];
+            exm += vm[i];
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st.nsurv = tot;
+            st.nmemb = totm;
+            if (a.counters) atomicAdd(&a.counters->kept, (unsigned long long)tot);
+        }
+        __syncthreads();
     }
-    uint32_t tot, totm;
-    uint32_t ex = block_exclusive_scan(sv, s_tmp, tot);
-    __syncthreads();
-    uint32_t exm = block_exclusive_scan(svm, s_tmp, totm);
-    for (int i = 0; i < kPer; ++i) {
-        a.cursor[(size_t)q * kNB + threadIdx.x * kPer + i] = ((unsigned long long)ex << 32) | exm;
-        ex += v[i];
-        exm += vm[i];
-    }
-    if (threadIdx.x == 0) {
-        st.nsurv = tot;
-        st.nmemb = totm;
-        if (a.counters) atomicAdd(&a.counters->kept, (unsigned long long)tot);
-    }
-}
-
-// Place every kept leaf at its position in the bin order.  One 64-bit atomic
-// hands out the position and the member offset together, so member offsets
-// increase with the position; the leaf whose member range holds the first
-// member of a scan chunk records itself as that chunk's first position.
-__global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
-    const int q = blockIdx.y;
-    const QState& st = a.qs[q];
-    if (st.err) return;
     const float U0 = __uint_as_float(st.U), range = st.range;
     for (int l = blockIdx.x * kLeafBlock + threadIdx.x; l < a.nL; l += gridDim.x * kLeafBlock) {
         const float lbv = a.lb[(size_t)q * a.nL + l];
         if (!leaf_kept(lbv, U0)) continue;
         const Leaf lf = a.leaves[l];
-        const unsigned long long old =
-            atomicAdd(&a.cursor[(size_t)q * kNB + bin_of(lbv, range)], (1ull << 32) | lf.count);
-        const uint32_t t = (uint32_t)(old >> 32), moff = (uint32_t)old;
+        const int bn = bin_of(lbv, range);
+        const unsigned long long old = atomicAdd(&a.cursor[(size_t)q * kNB + bn], (1ull << 32) | lf.count);
+        const uint32_t t = s_pos[bn] + (uint32_t)(old >> 32), moff = s_moff[bn] + (uint32_t)old;
         if (t < (uint32_t)a.nL) {
             a.order[(size_t)q * a.nL + t] = (uint32_t)l;
             a.rec[(size_t)q * a.nL + t] = OrdRec{lf.start, lf.count, lbv, moff};
@@ -1945,10 +1974,10 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     MESSI_TRY(mark(2));
     hipLaunchKernelGGL(approx_ed_kernel, dim3(approx_blocks(nq), nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_ed");
-    hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
-    MESSI_LAUNCH_CHECK("approx_select");
-    MESSI_TRY(mark(3));
     if (mode == MESSI_MODE_APPROX) {
+        hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
+        MESSI_LAUNCH_CHECK("approx_select");
+        MESSI_TRY(mark(3));
         hipLaunchKernelGGL(approx_cands_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
         MESSI_LAUNCH_CHECK("approx_cands");
         MESSI_TRY(mark(4));
@@ -1959,10 +1988,9 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
         MESSI_TRY(mark(6));
         return MESSI_OK;
     }
-    hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    MESSI_TRY(mark(3));
+    hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("bin_hist");
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(nq), dim3(256), 0, s, a);
-    MESSI_LAUNCH_CHECK("bin_scan");
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_scatter");
     MESSI_TRY(mark(4));
@@ -2106,13 +2134,9 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     // diagonal path lies in every band, so DTW <= ED)
     hipLaunchKernelGGL(approx_ed_kernel, dim3(approx_blocks(nq), nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("approx_ed");
-    hipLaunchKernelGGL(approx_select_kernel, dim3(nq), dim3(256), 0, s, a, lb_blocks);
-    MESSI_LAUNCH_CHECK("approx_select");
     MESSI_TRY(mark(3));
-    hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a, lb_blocks);
     MESSI_LAUNCH_CHECK("bin_hist");
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(nq), dim3(256), 0, s, a);
-    MESSI_LAUNCH_CHECK("bin_scan");
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_scatter");
     MESSI_TRY(mark(4));
