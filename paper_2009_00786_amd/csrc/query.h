@@ -99,6 +99,10 @@ struct QArgs {
     uint32_t todo_seg, todo_nseg;
     uint32_t* todo_cnt;          // [nq][todo_nseg] entries in each segment
     float* env;                  // [nq][2][L] DTW: the query's envelope, upper then lower
+    Cand* ec;                    // [nq][ec_nseg][ec_seg] DTW: waiting series within the candidate-side bound,
+    uint32_t ec_cap;             //   a segment per block of the bound kernel; ec_cap = ec_nseg * ec_seg
+    uint32_t ec_seg, ec_nseg;
+    uint32_t* ec_cnt;            // [nq][ec_nseg] entries in each segment
     const float* queries;        // [nq][L]
     int32_t nq;
     QState* qs;
@@ -133,8 +137,8 @@ struct Workspace {
     uint32_t max_chunks = 0;
     DevBuf qs, lb, order, rec, chunk_first, bins, mbins, cursor, hist, approx_d, cand, counters, err, prof, blk_cnt,
         status, lbpart;
-    DevBuf todo, env, todo_cnt;  // DTW search
-    size_t todo_slots = 0, env_floats = 0, todo_cnt_n = 0;
+    DevBuf todo, env, todo_cnt, ec, ec_cnt;  // DTW search
+    size_t todo_slots = 0, env_floats = 0, todo_cnt_n = 0, ec_slots = 0, ec_cnt_n = 0;
     uint32_t* h_err = nullptr;  // pinned copy of the call's error flags
     // BF16 path
     int32_t bf_nq = 0;

@@ -1386,85 +1386,16 @@ __device__ float lb_keogh_ec_wave(const float* __restrict__ x, const float* __re
     return dev::wave_sum(ec);
 }
 
-// The series of a round whose LB_Keogh is within the bound: those whose
-// candidate-side bound is within it too go to a block queue, and the queue
-// is drained 256 at a time (a thread each, so that full waves run the DP) by
-// the fp32 banded DTW; those within the bound become candidates, and for
-// k = 1 they lower U.
-template <int W>
-__global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
-    __shared__ float s_q[MESSI_MAX_LEN];
-    __shared__ float s_eu[MESSI_MAX_LEN], s_el[MESSI_MAX_LEN];
-    __shared__ float s_tab[4][2][MESSI_MAX_LEN + 96];  // per wave: max and min tables
-    __shared__ Cand s_queue[512];
-    __shared__ uint32_t s_nq;
-    __shared__ uint32_t s_off[4097];  // the query's segments (at most 4096): exclusive prefix of their counts
-    __shared__ uint32_t s_tmp[4];
-    const int q = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    QState& st = a.qs[q];
-    if (st.err) return;
-    const int L = a.L, r = a.band;
-    const float* qg = a.queries + (size_t)q * L;
-    const float* eg = a.env + (size_t)q * 2 * L;
-    for (int j = tid; j < L; j += 256) {
-        s_q[j] = qg[j];
-        s_eu[j] = eg[j];
-        s_el[j] = eg[L + j];
-    }
-    if (tid == 0) s_nq = 0;
-    __syncthreads();
-    if (st.ovf) {
-        // a segment of the waiting list overflowed (cannot happen: a segment
-        // holds every member of its block's chunks of a round; checked anyway)
-        if (blockIdx.x == 0 && tid == 0) {
-            st.err = 2;
-            atomicOr(a.err_any, 2u);
-        }
-        return;
-    }
-    float* tmax = s_tab[wave][0];
-    float* tmin = s_tab[wave][1];
-    unsigned long long ndtw = 0;
-    // DTW for the queued series, 256 at a time; with `all`, until the queue is empty
-    auto drain = [&](bool all) {
-        for (;;) {
-            const uint32_t nq = s_nq;
-            if (nq < 256 && !(all && nq > 0)) break;
-            const uint32_t take = min(nq, 256u);
-            if ((uint32_t)tid < take) {
-                const Cand c = s_queue[tid];
-                const float U = __uint_as_float(vload(&st.U));
-                if (!(c.d * (1.0f - kRhoEd) > U)) {
-                    ++ndtw;
-                    const float d = dtw_band<W, float>(s_q, a.series + (size_t)c.idx * L, L, r, U, s_eu, s_el, c.d);
-                    if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
-                        const uint32_t slot = atomicAdd(&st.ncand, 1u);
-                        if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, c.idx};
-                        if (st.k == 1) atomicMin(&st.U, __float_as_uint(d * (1.0f + 2.0f * kRhoDtw)));
-                    }
-                }
-            }
-            __syncthreads();
-            // move the rest to the front
-            const uint32_t rest = nq - take;
-            Cand keep{0.f, 0u};
-            if ((uint32_t)tid < rest) keep = s_queue[take + tid];
-            __syncthreads();
-            if ((uint32_t)tid < rest) s_queue[tid] = keep;
-            if (tid == 0) s_nq = rest;
-            __syncthreads();
-        }
-    };
-    // the entries of all the query's segments as one list (prefix sums of the
-    // segment counts; a segment per scan block, at most 4096), spread evenly
-    // over the blocks
-    const uint32_t G = a.todo_nseg;
+// Block-wide: the exclusive prefix sums of a query's G segment counts (G at
+// most 4096, 16 per thread) into s_off[0 .. G], s_off[G] the total, which is
+// returned.  Call from every thread.
+__device__ uint32_t segment_offsets(const uint32_t* cnt, uint32_t G, uint32_t* s_off, uint32_t* s_tmp) {
+    const int tid = threadIdx.x;
     const int per = (int)((G + 255) / 256);
     uint32_t loc[16], sum = 0;
     for (int k2 = 0; k2 < per && k2 < 16; ++k2) {
         const uint32_t i2 = (uint32_t)tid * per + k2;
-        loc[k2] = i2 < G ? a.todo_cnt[(size_t)q * G + i2] : 0u;
+        loc[k2] = i2 < G ? cnt[i2] : 0u;
         sum += loc[k2];
     }
     uint32_t n = 0;
@@ -1476,21 +1407,68 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
     }
     if (tid == 0) s_off[G] = n;
     __syncthreads();
+    return n;
+}
+
+// The segment holding entry e of the list whose offsets s_off holds: the last
+// segment whose offset is <= e.
+__device__ __forceinline__ uint32_t segment_of(const uint32_t* s_off, uint32_t G, uint32_t e) {
+    uint32_t lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A waiting list overflowed its segment (cannot happen: a segment holds every
+// entry its writer can produce; checked anyway).
+__device__ bool list_overflow(const QArgs& a, QState& st) {
+    if (!st.ovf) return false;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.err = 2;
+        atomicOr(a.err_any, 2u);
+    }
+    return true;
+}
+
+// The series of a round whose LB_Keogh is still within the bound get the
+// candidate-side bound, a wave per series; those within it too go to this
+// block's segment of the second list, for the DP kernel.  The waiting list's
+// segments are taken as one list (prefix sums of their counts) and spread
+// evenly over the blocks.  A kernel of its own: it needs few registers, so
+// far more waves hide its row and LDS latency than the DP's register-bound
+// occupancy allows.  Dynamic LDS: the query (L floats), the segment offsets
+// (todo_nseg + 1) and per wave the max and min tables (2 (L + 96) floats).
+__global__ void __launch_bounds__(256) dtw_ec_kernel(QArgs a) {
+    extern __shared__ float s_dyn[];
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_cnt;
+    const int q = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    if (list_overflow(a, st)) return;
+    const int L = a.L, r = a.band;
+    const uint32_t G = a.todo_nseg;
+    float* s_q = s_dyn;
+    uint32_t* s_off = reinterpret_cast<uint32_t*>(s_dyn + L);
+    float* tmax = s_dyn + L + (G + 1) + wave * 2 * (L + 96);
+    float* tmin = tmax + (L + 96);
+    const float* qg = a.queries + (size_t)q * L;
+    for (int j = tid; j < L; j += 256) s_q[j] = qg[j];
+    if (tid == 0) s_cnt = 0;
+    const uint32_t n = segment_offsets(a.todo_cnt + (size_t)q * G, G, s_off, s_tmp);
+    Cand* out = a.ec + (size_t)q * a.ec_cap + (size_t)blockIdx.x * a.ec_seg;
     const uint32_t stride = gridDim.x * 256;
     for (uint32_t base = blockIdx.x * 256; base < n; base += stride) {
-        // ---- the two lower bounds for this batch, a wave per candidate
         const uint32_t e = base + tid;
         Cand t{0.f, 0u};
         bool act = e < n;
         if (act) {
-            // the segment holding entry e: the last whose offset is <= e
-            uint32_t lo = 0, hi = G - 1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= e) lo = mid;
-                else hi = mid - 1;
-            }
-            t = a.todo[(size_t)q * a.todo_cap + (size_t)lo * a.todo_seg + (e - s_off[lo])];
+            const uint32_t sg = segment_of(s_off, G, e);
+            t = a.todo[(size_t)q * a.todo_cap + (size_t)sg * a.todo_seg + (e - s_off[sg])];
             act = !(t.d * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U)));
         }
         // a wave per candidate
@@ -1503,11 +1481,56 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
             const float v = lb_keogh_ec_wave(a.series + (size_t)idx * L, s_q, tmax, tmin, L, r, lane);
             if (lane == l) ec = v;
         }
-        if (act && !(ec * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U)))) s_queue[atomicAdd(&s_nq, 1u)] = t;
-        __syncthreads();
-        drain(false);
+        if (act && !(ec * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U)))) {
+            const uint32_t slot = atomicAdd(&s_cnt, 1u);
+            if (slot < a.ec_seg) out[slot] = t;
+            else st.ovf = 1;
+        }
     }
-    drain(true);
+    __syncthreads();
+    if (tid == 0) a.ec_cnt[(size_t)q * gridDim.x + blockIdx.x] = min(s_cnt, a.ec_seg);
+}
+
+// The fp32 banded DTW of every series the bound kernel passed, a thread each
+// (the list is compacted, so full waves run the DP), spread evenly over the
+// blocks by the prefix sums of the segment counts; those within the bound
+// become candidates, and for k = 1 they lower U.
+template <int W>
+__global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
+    __shared__ float s_q[MESSI_MAX_LEN];
+    __shared__ float s_eu[MESSI_MAX_LEN], s_el[MESSI_MAX_LEN];
+    __shared__ uint32_t s_off[4097];
+    __shared__ uint32_t s_tmp[4];
+    const int q = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    QState& st = a.qs[q];
+    if (st.err) return;
+    if (list_overflow(a, st)) return;
+    const int L = a.L, r = a.band;
+    const float* qg = a.queries + (size_t)q * L;
+    const float* eg = a.env + (size_t)q * 2 * L;
+    for (int j = tid; j < L; j += 256) {
+        s_q[j] = qg[j];
+        s_eu[j] = eg[j];
+        s_el[j] = eg[L + j];
+    }
+    const uint32_t G = a.ec_nseg;
+    const uint32_t n = segment_offsets(a.ec_cnt + (size_t)q * G, G, s_off, s_tmp);
+    unsigned long long ndtw = 0;
+    const uint32_t stride = gridDim.x * 256;
+    for (uint32_t e = blockIdx.x * 256 + tid; e < n; e += stride) {
+        const uint32_t sg = segment_of(s_off, G, e);
+        const Cand c = a.ec[(size_t)q * a.ec_cap + (size_t)sg * a.ec_seg + (e - s_off[sg])];
+        const float U = __uint_as_float(vload(&st.U));
+        if (c.d * (1.0f - kRhoEd) > U) continue;
+        ++ndtw;
+        const float d = dtw_band<W, float>(s_q, a.series + (size_t)c.idx * L, L, r, U, s_eu, s_el, c.d);
+        if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
+            const uint32_t slot = atomicAdd(&st.ncand, 1u);
+            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, c.idx};
+            if (st.k == 1) atomicMin(&st.U, __float_as_uint(d * (1.0f + 2.0f * kRhoDtw)));
+        }
+    }
     if (a.counters) {
         for (int off = 32; off >= 1; off >>= 1) ndtw += __shfl_xor(ndtw, off);
         if (lane == 0 && ndtw) atomicAdd(&a.counters->recheck, ndtw);
@@ -2074,6 +2097,25 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
 // every member of that block's chunks of a round, so it cannot overflow.
 constexpr uint32_t kDtwRoundChunks = 8192;
 
+// Resident blocks of the DP kernel for band width W over the whole device.
+static int dtw_grid(int W) {
+    static int grid[3] = {0, 0, 0};
+    const int wi = W == 16 ? 0 : W == 32 ? 1 : 2;
+    int& blocks = grid[wi];
+    if (!blocks) {
+        int dev = 0, cus = 256, nb = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t p;
+            if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        }
+        const void* f = wi == 0 ? (const void*)dtw_kernel<16> : wi == 1 ? (const void*)dtw_kernel<32>
+                                                                        : (const void*)dtw_kernel<64>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess || nb < 1) nb = 2;
+        blocks = std::min(cus * nb, 4096);
+    }
+    return blocks;
+}
+
 int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
                    int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
     CallArgs c{ix, queries, nq, k, nullptr, MESSI_MODE_FP32, s, out_idx, out_dist};
@@ -2109,6 +2151,30 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     a.todo_seg = seg;
     a.todo_nseg = g_max;
     a.todo_cnt = ws->todo_cnt.as<uint32_t>();
+    // the second list: a segment per block of the bound kernel, each holding
+    // every entry that block can take from the first
+    const unsigned ec_blocks = (unsigned)std::max(1, std::min(4096, 2048 / std::max(1, (int)nq)));
+    const uint32_t ec_seg = (uint32_t)(((uint64_t)todo_cap + (uint64_t)ec_blocks * 256 - 1) /
+                                       ((uint64_t)ec_blocks * 256)) * 256u;
+    const uint32_t ec_cap = ec_blocks * ec_seg;
+    if (ws->ec_slots < (size_t)nq * ec_cap) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(ws->ec.alloc(sizeof(Cand) * (size_t)nq * ec_cap));
+        ws->ec_slots = (size_t)nq * ec_cap;
+        ++ws->gen;
+    }
+    if (ws->ec_cnt_n < (size_t)nq * ec_blocks) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(ws->ec_cnt.alloc(sizeof(uint32_t) * (size_t)nq * ec_blocks));
+        ws->ec_cnt_n = (size_t)nq * ec_blocks;
+        ++ws->gen;
+    }
+    a.ec = ws->ec.as<Cand>();
+    a.ec_cap = ec_cap;
+    a.ec_seg = ec_seg;
+    a.ec_nseg = ec_blocks;
+    a.ec_cnt = ws->ec_cnt.as<uint32_t>();
+    const size_t ec_lds = sizeof(float) * ((size_t)ix->len + g_max + 1 + 4 * 2 * ((size_t)ix->len + 96));
     if (ws->env_floats < (size_t)nq * 2 * ix->len) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         MESSI_TRY(ws->env.alloc(sizeof(float) * (size_t)nq * 2 * ix->len));
@@ -2149,7 +2215,10 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
         if (!h.err) max_nch = std::max<uint64_t>(max_nch, ((uint64_t)h.nmemb + kChunk - 1) / kChunk);
     const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
     const int W = 2 * band + 9 <= 16 ? 16 : 2 * band + 9 <= 32 ? 32 : 64;
-    const unsigned dtw_blocks = (unsigned)std::max(1, scan_grid(kScanDtw) / std::max(1, nq));
+    // the DP kernel's blocks: as many as are resident at once (its grid-stride
+    // loop gives every block the same share, so a second partial wave of
+    // blocks would only add a tail)
+    const unsigned dtw_blocks = (unsigned)std::max(1, dtw_grid(W) / std::max(1, nq));
     const unsigned nqb = (unsigned)((nq + 255) / 256);
     int rounds = 0;
     for (uint64_t c0 = 0, size = std::min<uint64_t>(16, round_max); c0 < max_nch;) {
@@ -2161,6 +2230,8 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
                            dim3(256), 0, s, a);
         MESSI_LAUNCH_CHECK("todo_reset");
         MESSI_TRY(launch_scan(a, vec, 0, kScanDtw, s));
+        hipLaunchKernelGGL(dtw_ec_kernel, dim3(ec_blocks, nq), dim3(256), ec_lds, s, a);
+        MESSI_LAUNCH_CHECK("dtw_ec");
         if (W == 16) hipLaunchKernelGGL(dtw_kernel<16>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
         else if (W == 32) hipLaunchKernelGGL(dtw_kernel<32>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
         else hipLaunchKernelGGL(dtw_kernel<64>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
