@@ -1252,85 +1252,112 @@ __global__ void status_kernel(QArgs a, uint32_t* out) {
 // DTW: banded dynamic time warping in registers
 // --------------------------------------------------------------------------
 // Squared DTW of the query q (LDS) against the series x under a band of
-// half-width r (2r + 1 + 8 <= W), by the textbook recurrence
+// half-width R (a template argument: one instance per band), by the textbook
+// recurrence
 //     D(i, j) = c(i, j) + min(D(i-1, j), D(i, j-1), D(i-1, j-1)).
-// Register slot t of row i holds cell (i, i - r + t); going down a row, slot t
-// reads the row above in slots t + 1 (same column) and t (one column left)
-// and its left neighbour from slot t - 1 of the new row, so the row is
-// updated in place in ascending t.  The x values of row i sit in xw[t] and
-// shift down one slot per row; the value entering the last slot is used at
-// least 8 rows later, which hides its load.
+// Register slot t (0 <= t <= 2R) of row i holds cell (i, i - R + t); going
+// down a row, slot t reads the row above in slots t + 1 (same column) and t
+// (one column left) and its left neighbour from slot t - 1 of the new row, so
+// the row is updated in place in ascending t.  The x values of row i sit in
+// xw[t] and shift down one slot per row; columns outside the series hold
+// +inf, so their cells come out +inf with no test.  The rows go in blocks of
+// kDtwRows: the values a block's rows take in are loaded during the block
+// before, into registers of their own, so no row waits on memory.
 // T = double: the canonical value, each subtraction, product and sum rounded
 // once in fp64 (no fused multiply-add), equal to the plain recurrence in any
 // evaluation order.  T = float: the search value, within a relative 2^-12 of
 // it for L <= 1024 (each path sum is a sequential sum of at most 2L - 1
 // non-negative terms, each term within 3 units of rounding).  It stops, and
 // returns +inf, once a lower bound of the final value exceeds limit: after
-// row i every path still has to match each column j > i + r with some query
+// row i every path still has to match each column j > i + R with some query
 // value inside the envelope [el_j, eu_j], so the final value is at least the
 // row's smallest cell plus the LB_Keogh terms of those columns, which are
 // lbk (the row's LB_Keogh, summed by the scan) less the terms of columns
-// <= i + r summed here.  Both sums are within 2^-13 lbk of their exact
-// values, covered by a slack of 2^-12 lbk.
-template <int W, typename T>
-__device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, int L, int r, float limit,
+// <= i + R summed here (column i + R sits in the last slot of row i).  Both
+// sums are within 2^-13 lbk of their exact values, covered by a slack of
+// 2^-12 lbk.
+constexpr int kDtwRows = 4;  // rows per block of the banded DP
+
+template <int R, typename T>
+__device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, int L, float limit,
                       const float* __restrict__ eu = nullptr, const float* __restrict__ el = nullptr,
                       float lbk = 0.f) {
     constexpr bool F64 = sizeof(T) == 8;
-    const T inf = (T)__builtin_huge_valf();
+    constexpr int W = 2 * R + 1;
+    const float finf = __builtin_huge_valf();
+    const T inf = (T)finf;
     T D[W];
     float xw[W];
 #pragma unroll
     for (int t = 0; t < W; ++t) {
-        D[t] = t == r ? (T)0 : inf;  // the virtual cell (-1, -1) starts the path
-        const int j = t - r;
-        xw[t] = (j >= 0 && j < L) ? x[j] : 0.f;
+        D[t] = t == R ? (T)0 : inf;  // the virtual cell (-1, -1) starts the path
+        const int j = t - R;
+        xw[t] = (j >= 0 && j < L) ? x[j] : finf;
     }
-    // LB_Keogh terms of the columns below r (the first row reaches column r)
+    // LB_Keogh terms of the columns below R (the first row reaches column R),
+    // in column order, from the window: column j sits in slot j + R
     float pre = 0.f;
-    if (!F64)
-        for (int j = 0; j < r && j < L; ++j) pre += keogh_gap(x[j], eu[j], el[j]) * keogh_gap(x[j], eu[j], el[j]);
-    const float slack = lbk * 2.44140625e-04f;
-    for (int i = 0; i < L; ++i) {
-        const float qi = q[i];
-        T left = inf, rowmin = inf;
-        if (!F64 && i + r < L) {
-            const float g = keogh_gap(x[i + r], eu[i + r], el[i + r]);
-            pre += g * g;
-        }
+    if (!F64) {
 #pragma unroll
-        for (int t = 0; t < W; ++t) {
-            const int j = i - r + t;
-            const T above = (t + 1 < W) ? D[t + 1] : inf;
-            T m = D[t] < above ? D[t] : above;
-            m = left < m ? left : m;
-            T v;
-            if (F64) {
-                const double d = __dsub_rn((double)qi, (double)xw[t]);
-                v = (T)__dadd_rn(__dmul_rn(d, d), (double)m);
-            } else {
-                const float d = qi - xw[t];
-                v = (T)(d * d + (float)m);
+        for (int j = 0; j < R; ++j) {
+            if (j < L) {
+                const float g = keogh_gap(xw[j + R], eu[j], el[j]);
+                pre += g * g;
             }
-            v = (t <= 2 * r && j >= 0 && j < L) ? v : inf;
-            D[t] = v;
-            left = v;
-            rowmin = v < rowmin ? v : rowmin;
-        }
-#pragma unroll
-        for (int t = 0; t + 1 < W; ++t) xw[t] = xw[t + 1];
-        const int jn = i + 1 - r + W - 1;
-        xw[W - 1] = jn < L ? x[jn] : 0.f;
-        if (!F64) {
-            const float rest = fmaxf(0.f, lbk - pre - slack);
-            if (((float)rowmin * (1.0f - kRhoDtw) + rest) * (1.0f - 1.0e-6f) > limit) return inf;
         }
     }
-    T out = inf;
+    const float slack = lbk * 2.44140625e-04f;
+    // the column entering the last slot after row i
+    auto take_in = [&](int i) -> float { return (i < L && i + R + 1 < L) ? x[i + R + 1] : finf; };
+    float in_x[kDtwRows];
 #pragma unroll
-    for (int t = 0; t < W; ++t)
-        if (t == r) out = D[t];
-    return out;
+    for (int u = 0; u < kDtwRows; ++u) in_x[u] = take_in(u);
+    for (int i0 = 0; i0 < L; i0 += kDtwRows) {
+        float nx[kDtwRows];
+#pragma unroll
+        for (int u = 0; u < kDtwRows; ++u) nx[u] = take_in(i0 + kDtwRows + u);
+        // each row takes the front of in_x and moves the rest down
+#pragma unroll 1
+        for (int u = 0; u < kDtwRows; ++u) {
+            const int i = i0 + u;
+            if (i >= L) break;
+            const float qi = q[i];
+            T left = inf, rowmin = inf;
+            if (!F64 && i + R < L) {
+                const float g = keogh_gap(xw[W - 1], eu[i + R], el[i + R]);
+                pre += g * g;
+            }
+#pragma unroll
+            for (int t = 0; t < W; ++t) {
+                const T above = (t + 1 < W) ? D[t + 1] : inf;
+                T m = D[t] < above ? D[t] : above;
+                m = left < m ? left : m;
+                T v;
+                if (F64) {
+                    const double d = __dsub_rn((double)qi, (double)xw[t]);
+                    v = (T)__dadd_rn(__dmul_rn(d, d), (double)m);
+                } else {
+                    const float d = qi - xw[t];
+                    v = (T)(d * d + (float)m);
+                }
+                D[t] = v;
+                left = v;
+                rowmin = v < rowmin ? v : rowmin;
+            }
+#pragma unroll
+            for (int t = 0; t + 1 < W; ++t) xw[t] = xw[t + 1];
+            xw[W - 1] = in_x[0];
+#pragma unroll
+            for (int v = 0; v + 1 < kDtwRows; ++v) in_x[v] = in_x[v + 1];
+            if (!F64) {
+                const float rest = fmaxf(0.f, lbk - pre - slack);
+                if (((float)rowmin * (1.0f - kRhoDtw) + rest) * (1.0f - 1.0e-6f) > limit) return inf;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDtwRows; ++u) in_x[u] = nx[u];
+    }
+    return D[R];
 }
 
 // Keep this wave's LDS accesses in program order for the compiler: the
@@ -1491,11 +1518,11 @@ __global__ void __launch_bounds__(256) dtw_ec_kernel(QArgs a) {
     if (tid == 0) a.ec_cnt[(size_t)q * gridDim.x + blockIdx.x] = min(s_cnt, a.ec_seg);
 }
 
-// The fp32 banded DTW of every series the bound kernel passed, a thread each
-// (the list is compacted, so full waves run the DP), spread evenly over the
-// blocks by the prefix sums of the segment counts; those within the bound
-// become candidates, and for k = 1 they lower U.
-template <int W>
+// The fp32 banded DTW (band R) of every series the bound kernel passed, a
+// thread each (the list is compacted, so full waves run the DP), spread evenly
+// over the blocks by the prefix sums of the segment counts; those within the
+// bound become candidates, and for k = 1 they lower U.
+template <int R>
 __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
     __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ float s_eu[MESSI_MAX_LEN], s_el[MESSI_MAX_LEN];
@@ -1506,7 +1533,7 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
     QState& st = a.qs[q];
     if (st.err) return;
     if (list_overflow(a, st)) return;
-    const int L = a.L, r = a.band;
+    const int L = a.L;
     const float* qg = a.queries + (size_t)q * L;
     const float* eg = a.env + (size_t)q * 2 * L;
     for (int j = tid; j < L; j += 256) {
@@ -1524,7 +1551,7 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
         const float U = __uint_as_float(vload(&st.U));
         if (c.d * (1.0f - kRhoEd) > U) continue;
         ++ndtw;
-        const float d = dtw_band<W, float>(s_q, a.series + (size_t)c.idx * L, L, r, U, s_eu, s_el, c.d);
+        const float d = dtw_band<R, float>(s_q, a.series + (size_t)c.idx * L, L, U, s_eu, s_el, c.d);
         if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
             const uint32_t slot = atomicAdd(&st.ncand, 1u);
             if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, c.idx};
@@ -1580,7 +1607,8 @@ __global__ void __launch_bounds__(256) dtw_active_kernel(QArgs a, uint32_t c1) {
     atomicAdd(&a.err_any[2], 1u);
 }
 
-template <int W>
+// DB = 0: Euclidean distances; DB = R + 1: DTW under band R.
+template <int DB>
 __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     __shared__ double s_d[kMaxFinal];
     __shared__ uint32_t s_i[kMaxFinal];
@@ -1624,10 +1652,10 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
         }
         return;
     }
-    if (W > 0) {
+    if constexpr (DB > 0) {
         // DTW: the canonical fp64 value of every candidate, a thread each
         for (uint32_t j = threadIdx.x; j < kept; j += 256)
-            s_d[j] = dtw_band<(W > 0 ? W : 16), double>(s_q, a.series + (size_t)s_i[j] * a.L, a.L, a.band, 0.f);
+            s_d[j] = dtw_band<(DB > 0 ? DB - 1 : 0), double>(s_q, a.series + (size_t)s_i[j] * a.L, a.L, 0.f);
     } else if (kept <= 16) {
         // D64 of every candidate: the squared differences added one after
         // another in index order, each operation rounded once (no fused
@@ -2097,20 +2125,41 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
 // every member of that block's chunks of a round, so it cannot overflow.
 constexpr uint32_t kDtwRoundChunks = 8192;
 
-// Resident blocks of the DP kernel for band width W over the whole device.
-static int dtw_grid(int W) {
-    static int grid[3] = {0, 0, 0};
-    const int wi = W == 16 ? 0 : W == 32 ? 1 : 2;
-    int& blocks = grid[wi];
+// The DP and final kernels of band r (0 <= r <= MESSI_MAX_DTW_BAND): one
+// instance per band, picked at run time.
+template <int R>
+const void* dtw_dp_fn(int r) {
+    if (r == R) return (const void*)dtw_kernel<R>;
+    if constexpr (R > 0) return dtw_dp_fn<R - 1>(r);
+    return nullptr;
+}
+
+template <int R>
+void launch_dtw_dp(int r, dim3 g, hipStream_t s, const QArgs& a) {
+    if (r == R) hipLaunchKernelGGL(dtw_kernel<R>, g, dim3(256), 0, s, a);
+    else if constexpr (R > 0) launch_dtw_dp<R - 1>(r, g, s, a);
+}
+
+template <int R>
+void launch_dtw_final(int r, dim3 g, hipStream_t s, const QArgs& a) {
+    if (r == R) hipLaunchKernelGGL(final_kernel<R + 1>, g, dim3(256), 0, s, a);
+    else if constexpr (R > 0) launch_dtw_final<R - 1>(r, g, s, a);
+}
+
+// Resident blocks of the DP kernel of band r over the whole device.
+static int dtw_grid(int r) {
+    static int grid[MESSI_MAX_DTW_BAND + 1] = {};
+    int& blocks = grid[r];
     if (!blocks) {
         int dev = 0, cus = 256, nb = 0;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t p;
             if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
         }
-        const void* f = wi == 0 ? (const void*)dtw_kernel<16> : wi == 1 ? (const void*)dtw_kernel<32>
-                                                                        : (const void*)dtw_kernel<64>;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, 0) != hipSuccess || nb < 1) nb = 2;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dtw_dp_fn<MESSI_MAX_DTW_BAND>(r), 256, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 2;
         blocks = std::min(cus * nb, 4096);
     }
     return blocks;
@@ -2214,11 +2263,10 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     for (const QState& h : hq)
         if (!h.err) max_nch = std::max<uint64_t>(max_nch, ((uint64_t)h.nmemb + kChunk - 1) / kChunk);
     const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
-    const int W = 2 * band + 9 <= 16 ? 16 : 2 * band + 9 <= 32 ? 32 : 64;
     // the DP kernel's blocks: as many as are resident at once (its grid-stride
     // loop gives every block the same share, so a second partial wave of
     // blocks would only add a tail)
-    const unsigned dtw_blocks = (unsigned)std::max(1, dtw_grid(W) / std::max(1, nq));
+    const unsigned dtw_blocks = (unsigned)std::max(1, dtw_grid(band) / std::max(1, nq));
     const unsigned nqb = (unsigned)((nq + 255) / 256);
     int rounds = 0;
     for (uint64_t c0 = 0, size = std::min<uint64_t>(16, round_max); c0 < max_nch;) {
@@ -2232,9 +2280,7 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
         MESSI_TRY(launch_scan(a, vec, 0, kScanDtw, s));
         hipLaunchKernelGGL(dtw_ec_kernel, dim3(ec_blocks, nq), dim3(256), ec_lds, s, a);
         MESSI_LAUNCH_CHECK("dtw_ec");
-        if (W == 16) hipLaunchKernelGGL(dtw_kernel<16>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
-        else if (W == 32) hipLaunchKernelGGL(dtw_kernel<32>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(dtw_kernel<64>, dim3(dtw_blocks, nq), dim3(256), 0, s, a);
+        launch_dtw_dp<MESSI_MAX_DTW_BAND>(band, dim3(dtw_blocks, nq), s, a);
         MESSI_LAUNCH_CHECK("dtw");
         MESSI_TRY(refresh_bounds(a, s));
         c0 = c1;
@@ -2248,9 +2294,7 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
         if (*ws->h_err == 0) break;
     }
     MESSI_TRY(mark(5));
-    if (W == 16) hipLaunchKernelGGL(final_kernel<16>, dim3(nq), dim3(256), 0, s, a);
-    else if (W == 32) hipLaunchKernelGGL(final_kernel<32>, dim3(nq), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(final_kernel<64>, dim3(nq), dim3(256), 0, s, a);
+    launch_dtw_final<MESSI_MAX_DTW_BAND>(band, dim3(nq), s, a);
     MESSI_LAUNCH_CHECK("final_dtw");
     MESSI_TRY(mark(6));
     MESSI_HIP_TRY(hipMemcpyAsync(ws->h_err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
