@@ -123,6 +123,8 @@ struct QArgs {
     int32_t lg_m;                // ceil(log2 m)
     QCounters* counters;         // nullptr = no counting
     uint32_t* err_any;
+    uint32_t* host_err;          // one-query calls: mapped pinned host word the final kernel stores its error
+                                 //   bit in as well (the host zeroes it first), so no read-back copy is needed
     unsigned long long* prof;    // nullptr = no phase timing; else [blocks][4]
     unsigned long long* blk_cnt; // scan counters per block [blocks][5] (with counters)
     int64_t* out_idx;
@@ -140,6 +142,8 @@ struct Workspace {
     DevBuf todo, env, todo_cnt, ec, ec_cnt;  // DTW search
     size_t todo_slots = 0, env_floats = 0, todo_cnt_n = 0, ec_slots = 0, ec_cnt_n = 0;
     uint32_t* h_err = nullptr;  // pinned copy of the call's error flags
+    uint32_t* h_flag = nullptr;  // mapped, coherent pinned word for one-query calls (host address)
+    uint32_t* d_flag = nullptr;  //   and its device address
     // BF16 path
     int32_t bf_nq = 0;
     size_t bf_pairs_cap = 0, bf_leafq_cap = 0;

@@ -1619,10 +1619,15 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     if (threadIdx.x == 0) s_kept = 0;
     for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
     __syncthreads();
+    // the call's error flags: one bit per kind of per-query failure (with
+    // host_err, a one-query call: this block is the only writer)
+    auto flag = [&](uint32_t bit) {
+        atomicOr(a.err_any, bit);
+        if (a.host_err) *reinterpret_cast<volatile uint32_t*>(a.host_err) = bit;
+    };
     if (st.err) {
-        // the call's error flags: one bit per kind of per-query failure
         const uint32_t e = st.err;
-        if (threadIdx.x == 0) atomicOr(a.err_any, e == 1 ? 1u : e == 2 ? 2u : e == 3 ? 4u : e == 4 ? 8u : 16u);
+        if (threadIdx.x == 0) flag(e == 1 ? 1u : e == 2 ? 2u : e == 3 ? 4u : e == 4 ? 8u : 16u);
         return;
     }
     const float U = __uint_as_float(st.U);
@@ -1630,7 +1635,7 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     if (nc > a.cap) {
         if (threadIdx.x == 0) {
             st.err = 2;
-            atomicOr(a.err_any, 2u);
+            flag(2u);
         }
         return;
     }
@@ -1648,7 +1653,7 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     if (kept > (uint32_t)kMaxFinal || kept < (uint32_t)k) {
         if (threadIdx.x == 0) {
             st.err = kept > (uint32_t)kMaxFinal ? 3u : 4u;
-            atomicOr(a.err_any, kept > (uint32_t)kMaxFinal ? 4u : 8u);
+            flag(kept > (uint32_t)kMaxFinal ? 4u : 8u);
         }
         return;
     }
@@ -1788,7 +1793,7 @@ int Workspace::ensure_stats() {
 Workspace::~Workspace() {
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
-    for (void* p : {(void*)h_counters, (void*)h_prof, (void*)h_blk_cnt, (void*)h_err})
+    for (void* p : {(void*)h_counters, (void*)h_prof, (void*)h_blk_cnt, (void*)h_err, (void*)h_flag})
         if (p) (void)hipHostFree(p);
 }
 
@@ -1823,6 +1828,11 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
         MESSI_TRY(ws->blk_cnt.alloc(sizeof(unsigned long long) * kBlkCnt * 4096));
         MESSI_TRY(ws->lbpart.alloc(sizeof(LbPart) * (size_t)nqa * ((nL + kLeafBlock - 1) / kLeafBlock)));
         if (!ws->h_err) MESSI_HIP_TRY(hipHostMalloc((void**)&ws->h_err, sizeof(uint32_t) * 4, 0));
+        if (!ws->h_flag) {
+            MESSI_HIP_TRY(hipHostMalloc((void**)&ws->h_flag, sizeof(uint32_t) * 4,
+                                        hipHostMallocMapped | hipHostMallocCoherent));
+            MESSI_HIP_TRY(hipHostGetDevicePointer((void**)&ws->d_flag, ws->h_flag, 0));
+        }
         ws->nq = nqa;
         ws->nL = (int32_t)nL;
         ws->max_chunks = mc;
@@ -1995,6 +2005,7 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.counters = counting ? ws->counters.as<QCounters>() : nullptr;
     a.prof = counting ? ws->prof.as<unsigned long long>() : nullptr;
     a.err_any = ws->err.as<uint32_t>();
+    a.host_err = nullptr;
     a.blk_cnt = counting ? ws->blk_cnt.as<unsigned long long>() : nullptr;
     a.out_idx = c.out_idx;
     a.out_dist = c.out_dist;
@@ -2389,9 +2400,16 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     const unsigned long long* hprof = nullptr;
     const unsigned long long* hcnt = nullptr;
     int32_t retries = 0;
+    // one query without statistics: the final kernel stores its error bit in
+    // host memory itself, which saves the read-back copy (a kernel of its own)
+    const bool direct = !timing && nq == 1;
     for (;;) {
+        if (direct) {
+            *reinterpret_cast<volatile uint32_t*>(ws->h_flag) = 0;
+            a.host_err = ws->d_flag;  // (again after a retry's set-up)
+        }
         MESSI_TRY(launch_search(c, a, ws, cap, timing, mark));
-        MESSI_HIP_TRY(hipMemcpyAsync(ws->h_err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (!direct) MESSI_HIP_TRY(hipMemcpyAsync(ws->h_err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         if (a.counters)
             MESSI_HIP_TRY(hipMemcpyAsync(ws->h_counters, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
         if (a.prof && fp32) {
@@ -2403,7 +2421,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
             hcnt = ws->h_blk_cnt;
         }
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        err = *ws->h_err;
+        err = direct ? *reinterpret_cast<volatile uint32_t*>(ws->h_flag) : *ws->h_err;
         if (a.counters) hc = *ws->h_counters;
         // The FP32 scan's own second pass was not enough (more than cap
         // candidates below the k-th buffered distance): search again with a

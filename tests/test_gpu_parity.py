@@ -267,6 +267,10 @@ def test_knn_candidate_overflow_recovers(torch_cuda, messi, datagen_mod, oracle_
         gi, gd, st = ix.knn(torch.from_numpy(q[:1].copy()).cuda(), k, stats=True)
         _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx[:1], od[:1])
         reruns += st["reruns"]
+        # one query without statistics: its error flag comes back through
+        # host memory instead of a copy, retries included
+        gi, gd = ix.knn(torch.from_numpy(q[:1].copy()).cuda(), k)
+        _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx[:1], od[:1])
     assert reruns > 0
     ix.close()
 
