@@ -227,7 +227,10 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     };
     // leaves blockIdx.x * 256 + threadIdx.x, stepping over the query's blocks
     if (l0 < a.nL) bound(lf0, l0);
-    for (int l = l0 + gridDim.x * kLeafBlock; l < a.nL; l += gridDim.x * kLeafBlock) bound(a.leaves[l], l);
+    for (int l = l0 + gridDim.x * kLeafBlock; l < a.nL; l += gridDim.x * kLeafBlock) {
+        const Leaf lf = a.leaves[l];  // a register copy (a reference would read every byte from memory)
+        bound(lf, l);
+    }
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(best, off);
         best = o < best ? o : best;
