@@ -126,3 +126,21 @@ def test_dtw_ties_and_errors(torch_cuda, messi, oracle_mod):
     empty = ix.knn_dtw(qq[:0], 1, 6)
     assert empty[0].shape == (0, 1)
     ix.close()
+
+
+def test_dtw_every_band(torch_cuda, messi, datagen_mod, oracle_mod):
+    """Every band 0 .. MESSI_MAX_DTW_BAND has its own compiled DP and final
+    kernel: each one against the oracle's brute force, on a collection long
+    enough (L = 64) that the widest band still lies inside it."""
+    torch = torch_cuda
+    z = oracle_mod.znorm(datagen_mod.random_walks(1_500, 64, seed=55))
+    q, _ = _queries(datagen_mod, oracle_mod, z, 64, 56)
+    ix = messi.Index(torch.from_numpy(z).cuda(), 8, 8, 40)
+    qd = torch.from_numpy(q).cuda()
+    for band in range(0, 28):
+        _say("dtw every band: band=%d" % band)
+        oi, _, od = oracle_mod.knn_brute_dtw(z, q, 2, band, nthreads=8)
+        gi, gd = ix.knn_dtw(qd, 2, band)
+        np.testing.assert_array_equal(gi.cpu().numpy(), oi)
+        np.testing.assert_array_equal(gd.cpu().numpy(), od)
+    ix.close()
