@@ -1373,46 +1373,87 @@ __device__ __forceinline__ void wave_order() {
 
 // LB_Keogh of the query against the candidate's envelope (the candidate-side
 // bound): every warping path in the band matches q_i with some x_j,
-// |i - j| <= r, and x_j lies inside [min, max] of x over [i - r, i + r], so
-// the sum over i of the squared distance from q_i to that interval is below
-// the DTW.  One wave computes it for one candidate: the row goes into LDS
-// padded with 32 values of -inf / +inf on each side, five in-place doubling
-// steps turn each padded position p into the max (min) of p .. p + 31, and
-// the window of position j (2r + 1 <= 55 values) is covered by the two spans
-// starting at j - r and j + r - 31.  For r < 16 the spans reach past the
-// window: a wider interval, so a smaller but still valid bound.  Within a
-// wave, LDS operations run in program order, so the reads of a step precede
-// its writes.
-__device__ float lb_keogh_ec_wave(const float* __restrict__ x, const float* __restrict__ q, float* tmax,
-                                  float* tmin, int L, int r, int lane) {
-    const float inf = __builtin_huge_valf();
-    const int P = L + 64;  // padded length; reads reach P + 31
-    for (int p = lane; p < P + 32; p += 64) {
-        const int j = p - 32;
-        const bool in = j >= 0 && j < L;
-        const float v = in ? x[j] : 0.f;
-        tmax[p] = in ? v : -inf;
-        tmin[p] = in ? v : inf;
-    }
+// |i - j| <= R, and x_j lies inside [min, max] of x over [i - R, i + R]
+// (clipped to the series), so the sum over i of the squared distance from q_i
+// to that interval is below the DTW.  One wave computes it for one candidate.
+// The row goes into LDS once, padded on each side with copies of its first
+// and last value: a window that reaches past an end contains that end, so the
+// copies change no window's max or min.  Each lane then takes four
+// consecutive positions jb .. jb + 3, reads the 2R + 4 values their windows
+// span with 16-byte reads, forms the max and min of the part the four
+// windows share once, and adds each window's few other values.  R is a
+// template argument, so every register index is fixed.
+constexpr int kEcPad = 32;  // padding on each side of the row (>= R + 3)
+
+// floats per wave's row buffer: a multiple of 4, so every wave's buffer
+// starts on a 16-byte boundary
+__host__ __device__ constexpr int ec_row_floats(int L) { return (L + 2 * kEcPad + 16 + 3) & ~3; }
+
+template <int R>
+__device__ float lb_keogh_ec_wave(const float* __restrict__ x, const float* __restrict__ q, float* row, int L,
+                                  int lane) {
+    constexpr int B0 = (kEcPad - R) & ~3;           // first value read, from jb (16-byte aligned)
+    constexpr int E0 = (kEcPad - R) - B0;           // where position jb - R sits among them
+    constexpr int NV = (E0 + 2 * R + 4 + 3) / 4 * 4;  // values read per lane and group
+    const int RB = ec_row_floats(L);
+    for (int p = lane; p < RB; p += 64) row[p] = x[min(max(p - kEcPad, 0), L - 1)];
     wave_order();
-    for (int h = 1; h < 32; h <<= 1) {
-        for (int c0 = 0; c0 < P; c0 += 64) {
-            const int p = c0 + lane;
-            const float a0 = tmax[p], a1 = tmax[p + h], b0 = tmin[p], b1 = tmin[p + h];
-            wave_order();
-            tmax[p] = fmaxf(a0, a1);
-            tmin[p] = fminf(b0, b1);
-            wave_order();
+    float ec = 0.f;
+    for (int g0 = 0; g0 < L; g0 += 256) {
+        const int jb = g0 + 4 * lane;
+        if (jb < L) {
+            float v[NV];
+#pragma unroll
+            for (int t = 0; t < NV; t += 4) {
+                const float4 f = *reinterpret_cast<const float4*>(row + jb + B0 + t);
+                v[t] = f.x;
+                v[t + 1] = f.y;
+                v[t + 2] = f.z;
+                v[t + 3] = f.w;
+            }
+            // the window of position jb + u is v[E0 + u .. E0 + u + 2R]
+            float cmx = 0.f, cmn = 0.f;
+            if constexpr (R >= 2) {
+                // the part all four share: v[E0 + 3 .. E0 + 2R]
+                cmx = cmn = v[E0 + 3];
+#pragma unroll
+                for (int t = E0 + 4; t <= E0 + 2 * R; ++t) {
+                    cmx = fmaxf(cmx, v[t]);
+                    cmn = fminf(cmn, v[t]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (jb + u < L) {
+                    float mx, mn;
+                    if constexpr (R >= 2) {
+                        mx = cmx;
+                        mn = cmn;
+#pragma unroll
+                        for (int t = E0 + u; t < E0 + 3; ++t) {
+                            mx = fmaxf(mx, v[t]);
+                            mn = fminf(mn, v[t]);
+                        }
+#pragma unroll
+                        for (int t = E0 + 2 * R + 1; t <= E0 + 2 * R + u; ++t) {
+                            mx = fmaxf(mx, v[t]);
+                            mn = fminf(mn, v[t]);
+                        }
+                    } else {
+                        mx = mn = v[E0 + u];
+#pragma unroll
+                        for (int t = E0 + u + 1; t <= E0 + u + 2 * R; ++t) {
+                            mx = fmaxf(mx, v[t]);
+                            mn = fminf(mn, v[t]);
+                        }
+                    }
+                    const float gq = keogh_gap(q[jb + u], mx, mn);
+                    ec = fmaf(gq, gq, ec);
+                }
+            }
         }
     }
-    float ec = 0.f;
-    for (int j = lane; j < L; j += 64) {
-        const int p0 = j - r + 32, p1 = j + r + 1;  // spans [p0, p0 + 31] and [p1, p1 + 31]
-        const float u = fmaxf(tmax[p0], tmax[p1]), l = fminf(tmin[p0], tmin[p1]);
-        const float g = keogh_gap(q[j], u, l);
-        ec = fmaf(g, g, ec);
-    }
-    wave_order();  // the tables are reused for the next candidate
+    wave_order();  // the row buffer is reused for the next candidate
     return dev::wave_sum(ec);
 }
 
@@ -1470,9 +1511,11 @@ __device__ bool list_overflow(const QArgs& a, QState& st) {
 // evenly over the blocks.  A kernel of its own: it needs few registers, so
 // far more waves hide its row and LDS latency than the DP's register-bound
 // occupancy allows.  Dynamic LDS: the query (L floats), the segment offsets
-// (todo_nseg + 1) and per wave the max and min tables (2 (L + 96) floats).
+// (todo_nseg + 1), then, from a 16-byte boundary, per wave the padded row
+// (ec_row_floats(L) floats).  One instance per band R.
+template <int R>
 __global__ void __launch_bounds__(256) dtw_ec_kernel(QArgs a) {
-    extern __shared__ float s_dyn[];
+    extern __shared__ __align__(16) float s_dyn[];
     __shared__ uint32_t s_tmp[4];
     __shared__ uint32_t s_cnt;
     const int q = blockIdx.y;
@@ -1480,12 +1523,11 @@ __global__ void __launch_bounds__(256) dtw_ec_kernel(QArgs a) {
     QState& st = a.qs[q];
     if (st.err) return;
     if (list_overflow(a, st)) return;
-    const int L = a.L, r = a.band;
+    const int L = a.L;
     const uint32_t G = a.todo_nseg;
     float* s_q = s_dyn;
     uint32_t* s_off = reinterpret_cast<uint32_t*>(s_dyn + L);
-    float* tmax = s_dyn + L + (G + 1) + wave * 2 * (L + 96);
-    float* tmin = tmax + (L + 96);
+    float* row = s_dyn + ((L + G + 1 + 3) & ~3u) + wave * ec_row_floats(L);
     const float* qg = a.queries + (size_t)q * L;
     for (int j = tid; j < L; j += 256) s_q[j] = qg[j];
     if (tid == 0) s_cnt = 0;
@@ -1508,7 +1550,7 @@ __global__ void __launch_bounds__(256) dtw_ec_kernel(QArgs a) {
             const int l = __ffsll((long long)m) - 1;
             m &= m - 1;
             const uint32_t idx = __shfl(t.idx, l);
-            const float v = lb_keogh_ec_wave(a.series + (size_t)idx * L, s_q, tmax, tmin, L, r, lane);
+            const float v = lb_keogh_ec_wave<R>(a.series + (size_t)idx * L, s_q, row, L, lane);
             if (lane == l) ec = v;
         }
         if (act && !(ec * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U)))) {
@@ -2155,6 +2197,12 @@ void launch_dtw_dp(int r, dim3 g, hipStream_t s, const QArgs& a) {
 }
 
 template <int R>
+void launch_dtw_ec(int r, dim3 g, size_t lds, hipStream_t s, const QArgs& a) {
+    if (r == R) hipLaunchKernelGGL(dtw_ec_kernel<R>, g, dim3(256), lds, s, a);
+    else if constexpr (R > 0) launch_dtw_ec<R - 1>(r, g, lds, s, a);
+}
+
+template <int R>
 void launch_dtw_final(int r, dim3 g, hipStream_t s, const QArgs& a) {
     if (r == R) hipLaunchKernelGGL(final_kernel<R + 1>, g, dim3(256), 0, s, a);
     else if constexpr (R > 0) launch_dtw_final<R - 1>(r, g, s, a);
@@ -2237,7 +2285,8 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     a.ec_seg = ec_seg;
     a.ec_nseg = ec_blocks;
     a.ec_cnt = ws->ec_cnt.as<uint32_t>();
-    const size_t ec_lds = sizeof(float) * ((size_t)ix->len + g_max + 1 + 4 * 2 * ((size_t)ix->len + 96));
+    const size_t ec_lds = sizeof(float) * ((((size_t)ix->len + g_max + 1 + 3) & ~(size_t)3) +
+                                           4 * (size_t)ec_row_floats(ix->len));
     if (ws->env_floats < (size_t)nq * 2 * ix->len) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         MESSI_TRY(ws->env.alloc(sizeof(float) * (size_t)nq * 2 * ix->len));
@@ -2292,7 +2341,7 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
                            dim3(256), 0, s, a);
         MESSI_LAUNCH_CHECK("todo_reset");
         MESSI_TRY(launch_scan(a, vec, 0, kScanDtw, s));
-        hipLaunchKernelGGL(dtw_ec_kernel, dim3(ec_blocks, nq), dim3(256), ec_lds, s, a);
+        launch_dtw_ec<MESSI_MAX_DTW_BAND>(band, dim3(ec_blocks, nq), ec_lds, s, a);
         MESSI_LAUNCH_CHECK("dtw_ec");
         launch_dtw_dp<MESSI_MAX_DTW_BAND>(band, dim3(dtw_blocks, nq), s, a);
         MESSI_LAUNCH_CHECK("dtw");
