@@ -1389,14 +1389,12 @@ constexpr int kEcPad = 32;  // padding on each side of the row (>= R + 3)
 // starts on a 16-byte boundary
 __host__ __device__ constexpr int ec_row_floats(int L) { return (L + 2 * kEcPad + 16 + 3) & ~3; }
 
+// The bound once the padded row is in the wave's buffer.
 template <int R>
-__device__ float lb_keogh_ec_wave(const float* __restrict__ x, const float* __restrict__ q, float* row, int L,
-                                  int lane) {
+__device__ float lb_keogh_ec_row(const float* __restrict__ q, const float* row, int L, int lane) {
     constexpr int B0 = (kEcPad - R) & ~3;           // first value read, from jb (16-byte aligned)
     constexpr int E0 = (kEcPad - R) - B0;           // where position jb - R sits among them
     constexpr int NV = (E0 + 2 * R + 4 + 3) / 4 * 4;  // values read per lane and group
-    const int RB = ec_row_floats(L);
-    for (int p = lane; p < RB; p += 64) row[p] = x[min(max(p - kEcPad, 0), L - 1)];
     wave_order();
     float ec = 0.f;
     for (int g0 = 0; g0 < L; g0 += 256) {
@@ -1455,6 +1453,28 @@ __device__ float lb_keogh_ec_wave(const float* __restrict__ x, const float* __re
     }
     wave_order();  // the row buffer is reused for the next candidate
     return dev::wave_sum(ec);
+}
+
+template <int R>
+__device__ float lb_keogh_ec_wave(const float* __restrict__ x, const float* __restrict__ q, float* row, int L,
+                                  int lane) {
+    const int RB = ec_row_floats(L);
+    for (int p = lane; p < RB; p += 64) row[p] = x[min(max(p - kEcPad, 0), L - 1)];
+    return lb_keogh_ec_row<R>(q, row, L, lane);
+}
+
+// Padded rows of at most kEcHeld * 64 floats (series of up to 304 values) are
+// held in registers, kEcHeld per lane, so the next candidate's row can load
+// while the wave bounds the current one.
+constexpr int kEcHeld = 6;
+
+__device__ __forceinline__ void ec_row_load(const float* __restrict__ x, int L, int lane, float* v) {
+    const int RB = ec_row_floats(L);
+#pragma unroll
+    for (int k = 0; k < kEcHeld; ++k) {
+        const int p = k * 64 + lane;
+        v[k] = p < RB ? x[min(max(p - kEcPad, 0), L - 1)] : 0.f;
+    }
 }
 
 // Block-wide: the exclusive prefix sums of a query's G segment counts (G at
@@ -1546,12 +1566,33 @@ __global__ void __launch_bounds__(256) dtw_ec_kernel(QArgs a) {
         // a wave per candidate
         float ec = 0.f;
         uint64_t m = __ballot(act);
-        while (m) {
-            const int l = __ffsll((long long)m) - 1;
-            m &= m - 1;
-            const uint32_t idx = __shfl(t.idx, l);
-            const float v = lb_keogh_ec_wave<R>(a.series + (size_t)idx * L, s_q, row, L, lane);
-            if (lane == l) ec = v;
+        if (ec_row_floats(L) <= kEcHeld * 64) {
+            // the next candidate's row loads while this one is bounded
+            const int RB = ec_row_floats(L);
+            float nv[kEcHeld];
+            int l = m ? __ffsll((long long)m) - 1 : -1;
+            if (l >= 0) ec_row_load(a.series + (size_t)__shfl(t.idx, l) * L, L, lane, nv);
+            while (l >= 0) {
+                m &= m - 1;
+                const int ln = m ? __ffsll((long long)m) - 1 : -1;
+#pragma unroll
+                for (int k = 0; k < kEcHeld; ++k) {
+                    const int p = k * 64 + lane;
+                    if (p < RB) row[p] = nv[k];
+                }
+                if (ln >= 0) ec_row_load(a.series + (size_t)__shfl(t.idx, ln) * L, L, lane, nv);
+                const float v = lb_keogh_ec_row<R>(s_q, row, L, lane);
+                if (lane == l) ec = v;
+                l = ln;
+            }
+        } else {
+            while (m) {
+                const int l = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const uint32_t idx = __shfl(t.idx, l);
+                const float v = lb_keogh_ec_wave<R>(a.series + (size_t)idx * L, s_q, row, L, lane);
+                if (lane == l) ec = v;
+            }
         }
         if (act && !(ec * (1.0f - kRhoEd) > __uint_as_float(vload(&st.U)))) {
             const uint32_t slot = atomicAdd(&s_cnt, 1u);
