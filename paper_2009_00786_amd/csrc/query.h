@@ -111,7 +111,7 @@ struct QArgs {
     OrdRec* rec;                 // [nq][nL] the same leaves with start, count, bound, member offset
     uint32_t* chunk_first;       // [nq][max_chunks] order position holding the first member of each chunk
     uint32_t max_chunks;
-    uint32_t* bins;              // [nq][kNB] leaves per bound bin, then their exclusive prefix
+    uint32_t* bins;              // [nq][kNB] leaves per bound bin
     uint32_t* mbins;             // [nq][kNB] members per bound bin
     unsigned long long* cursor;  // [nq][kNB] per bin: (leaves placed << 32 | their members), zeroed per call
     uint32_t* hist;              // [nq][kHistBins] candidate-distance histogram
