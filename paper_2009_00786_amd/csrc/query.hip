@@ -2217,10 +2217,12 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
 // Rounds of the DTW search: the first takes each query's first 16 chunks of
 // its order (its best leaves, for a tight bound early), each later one four
 // times as many, up to kDtwRoundChunks / nq (at least 64).  A round costs a
-// launch of each kernel whatever its size, so the rounds grow fast.  The
+// launch of each kernel and a host synchronisation whatever its size, so the
+// rounds grow fast and the last ones are large (each of the two waiting
+// lists then takes 8 bytes per member of a round: about 270 MB).  The
 // waiting list has a segment per scan block of a query, large enough for
 // every member of that block's chunks of a round, so it cannot overflow.
-constexpr uint32_t kDtwRoundChunks = 8192;
+constexpr uint32_t kDtwRoundChunks = 32768;
 
 // The DP and final kernels of band r (0 <= r <= MESSI_MAX_DTW_BAND): one
 // instance per band, picked at run time.
