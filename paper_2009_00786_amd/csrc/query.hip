@@ -2215,8 +2215,10 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
 }
 
 // Rounds of the DTW search: the first takes each query's first 16 chunks of
-// its order (its best leaves, for a tight bound early), each later one four
-// times as many, up to kDtwRoundChunks / nq (at least 64).  A round costs a
+// its order (its best leaves, for a tight bound early; at most 16K members,
+// so its candidates fit any query's buffer while the bound is still the
+// first one), each later one eight times as many, up to kDtwRoundChunks / nq
+// (at least 64).  A round costs a
 // launch of each kernel and a host synchronisation whatever its size, so the
 // rounds grow fast and the last ones are large (each of the two waiting
 // lists then takes 8 bytes per member of a round: about 270 MB).  The
@@ -2390,7 +2392,7 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
         MESSI_LAUNCH_CHECK("dtw");
         MESSI_TRY(refresh_bounds(a, s));
         c0 = c1;
-        size = std::min<uint64_t>(4 * size, round_max);
+        size = std::min<uint64_t>(8 * size, round_max);
         if (c0 >= max_nch) break;
         // stop early once no query's order goes on below its bound
         hipLaunchKernelGGL(dtw_active_kernel, dim3(nqb), dim3(256), 0, s, a, (uint32_t)c0);
