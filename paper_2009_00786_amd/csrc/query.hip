@@ -2272,13 +2272,18 @@ static int dtw_grid(int r) {
     return blocks;
 }
 
-int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
-                   int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+// One DTW search with a candidate buffer of at least cap_min slots per query;
+// the raw error bits and the buffer size used come back for the caller's
+// retry.
+static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
+                        int64_t* out_idx, float* out_dist, messi_knn_stats* stats, uint32_t cap_min,
+                        uint32_t* cap_used, uint32_t* err_out) {
     CallArgs c{ix, queries, nq, k, nullptr, MESSI_MODE_FP32, s, out_idx, out_dist};
     Workspace* ws = nullptr;
     QArgs a;
     uint32_t cap = 0;
-    MESSI_TRY(setup_call(c, stats != nullptr, &ws, a, cap));
+    MESSI_TRY(setup_call(c, stats != nullptr, &ws, a, cap, cap_min));
+    *cap_used = cap;
     const bool timing = stats != nullptr;
     if (timing) MESSI_TRY(ws->ensure_stats());
     a.band = band;
@@ -2414,6 +2419,7 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
     }
     MESSI_HIP_TRY(hipStreamSynchronize(s));
     const uint32_t err = *ws->h_err;
+    *err_out = err;
     if (timing) {
         QCounters hc = *ws->h_counters;
         for (int bb = 0; bb < sg; ++bb) {
@@ -2450,6 +2456,24 @@ int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k,
         stats->scan_launches = rounds;
     }
     return decode_error(err);
+}
+
+// The DTW search.  For k > 1 the bound is the k-th candidate only from the
+// second round on, so a round can find more candidates within the bound than
+// the buffer holds; then the search runs again with a 16 times larger buffer
+// (twice at most), as the Euclidean search does.
+int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
+                   int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    uint32_t cap_min = 0;
+    for (int tries = 0;; ++tries) {
+        uint32_t cap = 0, err = 0;
+        const int rc = knn_dtw_once(ix, queries, nq, k, band, s, out_idx, out_dist, stats, cap_min, &cap, &err);
+        if (rc == MESSI_EOVERFLOW && (err & 2u) && !(err & 1u) && tries < 2 && cap <= (1u << 26)) {
+            cap_min = cap * 16;
+            continue;
+        }
+        return rc;
+    }
 }
 
 int query_error_code(uint32_t st) {
