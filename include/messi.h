@@ -203,7 +203,9 @@ int messi_export_leaves(const messi_index* index, messi_leaf* host_leaves, uint3
  * |i - j| <= band (a Sakoe-Chiba band); band = 0 is the Euclidean distance.
  * Leaves are visited in ascending envelope bound (per segment, the envelope's
  * extreme values against the node's region), members are bounded by their
- * words, then by LB_Keogh against the envelope, then get their DTW; the final
+ * words, then by LB_Keogh against the envelope, then by the query's distance
+ * to the member's own envelope (its min and max over each band window), then
+ * get their DTW; the final
  * order is the canonical fp64 DTW (every step rounded once, no fused
  * multiply-add).  Outputs as messi_knn_ex: out_idx[nq][k], out_dist[nq][k] =
  * fl32(sqrt(DTW^2)), ascending (distance, index).  Limits: 0 <= band <= 27,
