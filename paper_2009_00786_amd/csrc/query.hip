@@ -1254,102 +1254,80 @@ __global__ void status_kernel(QArgs a, uint32_t* out) {
 // --------------------------------------------------------------------------
 // DTW: banded dynamic time warping in registers
 // --------------------------------------------------------------------------
-// Squared DTW of the query q (LDS) against the series x under a band of
-// half-width R (a template argument: one instance per band), by the textbook
-// recurrence
-//     D(i, j) = c(i, j) + min(D(i-1, j), D(i, j-1), D(i-1, j-1)).
-// Register slot t (0 <= t <= 2R) of row i holds cell (i, i - R + t); going
-// down a row, slot t reads the row above in slots t + 1 (same column) and t
-// (one column left) and its left neighbour from slot t - 1 of the new row, so
-// the row is updated in place in ascending t.  The x values of row i sit in
-// xw[t] and shift down one slot per row; columns outside the series hold
-// +inf, so their cells come out +inf with no test.  The rows go in blocks of
-// kDtwRows: the values a block's rows take in are loaded during the block
-// before, into registers of their own, so no row waits on memory.
+// Squared DTW of the query against the series x under a band of half-width
+// R (a template argument: one instance per band), by the textbook recurrence
+//     D(i, j) = c(i, j) + min(D(i-1, j), D(i, j-1), D(i-1, j-1)),
+// i indexing the query and j the series.  The rows go over j: register slot t
+// (0 <= t <= 2R) of row j holds cell (j - R + t, j); going down a row, slot t
+// reads the row above in slots t + 1 (same query value) and t (one query
+// value back) and its left neighbour from slot t - 1 of the new row, so the
+// row is updated in place in ascending t.  A row needs one value of x per
+// lane; the query values are the same for every lane and come from qp, a
+// copy of the query with +inf outside it (qp[j + t] = q[j - R + t]), so
+// cells outside the matrix come out +inf with no test.  The x values of a
+// block of kDtwRows rows are loaded during the block before.
 // T = double: the canonical value, each subtraction, product and sum rounded
 // once in fp64 (no fused multiply-add), equal to the plain recurrence in any
 // evaluation order.  T = float: the search value, within a relative 2^-12 of
 // it for L <= 1024 (each path sum is a sequential sum of at most 2L - 1
 // non-negative terms, each term within 3 units of rounding).  It stops, and
 // returns +inf, once a lower bound of the final value exceeds limit: after
-// row i every path still has to match each column j > i + R with some query
-// value inside the envelope [el_j, eu_j], so the final value is at least the
-// row's smallest cell plus the LB_Keogh terms of those columns, which are
-// lbk (the row's LB_Keogh, summed by the scan) less the terms of columns
-// <= i + R summed here (column i + R sits in the last slot of row i).  Both
-// sums are within 2^-13 lbk of their exact values, covered by a slack of
-// 2^-12 lbk.
+// row j every path still has to match each x_j', j' > j, with some query
+// value inside the query's envelope [el_j', eu_j'], so the final value is at
+// least the row's smallest cell plus those columns' LB_Keogh terms, which
+// are lbk (the row's LB_Keogh, summed by the scan) less the terms of columns
+// <= j summed here.  Both sums are within 2^-13 lbk of their exact values,
+// covered by a slack of 2^-12 lbk.
 constexpr int kDtwRows = 4;  // rows per block of the banded DP
 
 template <int R, typename T>
-__device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, int L, float limit,
+__device__ T dtw_band(const float* __restrict__ qp, const float* __restrict__ x, int L, float limit,
                       const float* __restrict__ eu = nullptr, const float* __restrict__ el = nullptr,
                       float lbk = 0.f) {
     constexpr bool F64 = sizeof(T) == 8;
     constexpr int W = 2 * R + 1;
-    const float finf = __builtin_huge_valf();
-    const T inf = (T)finf;
+    const T inf = (T)__builtin_huge_valf();
     T D[W];
-    float xw[W];
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-        D[t] = t == R ? (T)0 : inf;  // the virtual cell (-1, -1) starts the path
-        const int j = t - R;
-        xw[t] = (j >= 0 && j < L) ? x[j] : finf;
-    }
-    // LB_Keogh terms of the columns below R (the first row reaches column R),
-    // in column order, from the window: column j sits in slot j + R
+    for (int t = 0; t < W; ++t) D[t] = t == R ? (T)0 : inf;  // the virtual cell (-1, -1) starts the path
     float pre = 0.f;
-    if (!F64) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            if (j < L) {
-                const float g = keogh_gap(xw[j + R], eu[j], el[j]);
-                pre += g * g;
-            }
-        }
-    }
     const float slack = lbk * 2.44140625e-04f;
-    // the column entering the last slot after row i
-    auto take_in = [&](int i) -> float { return (i < L && i + R + 1 < L) ? x[i + R + 1] : finf; };
     float in_x[kDtwRows];
 #pragma unroll
-    for (int u = 0; u < kDtwRows; ++u) in_x[u] = take_in(u);
-    for (int i0 = 0; i0 < L; i0 += kDtwRows) {
+    for (int u = 0; u < kDtwRows; ++u) in_x[u] = u < L ? x[u] : 0.f;
+    for (int j0 = 0; j0 < L; j0 += kDtwRows) {
         float nx[kDtwRows];
 #pragma unroll
-        for (int u = 0; u < kDtwRows; ++u) nx[u] = take_in(i0 + kDtwRows + u);
+        for (int u = 0; u < kDtwRows; ++u) nx[u] = j0 + kDtwRows + u < L ? x[j0 + kDtwRows + u] : 0.f;
         // each row takes the front of in_x and moves the rest down
 #pragma unroll 1
         for (int u = 0; u < kDtwRows; ++u) {
-            const int i = i0 + u;
-            if (i >= L) break;
-            const float qi = q[i];
-            T left = inf, rowmin = inf;
-            if (!F64 && i + R < L) {
-                const float g = keogh_gap(xw[W - 1], eu[i + R], el[i + R]);
+            const int j = j0 + u;
+            if (j >= L) break;
+            const float xj = in_x[0];
+            if (!F64) {
+                const float g = keogh_gap(xj, eu[j], el[j]);
                 pre += g * g;
             }
+            T left = inf, rowmin = inf;
 #pragma unroll
             for (int t = 0; t < W; ++t) {
+                const float qi = qp[j + t];
                 const T above = (t + 1 < W) ? D[t + 1] : inf;
                 T m = D[t] < above ? D[t] : above;
                 m = left < m ? left : m;
                 T v;
                 if (F64) {
-                    const double d = __dsub_rn((double)qi, (double)xw[t]);
+                    const double d = __dsub_rn((double)qi, (double)xj);
                     v = (T)__dadd_rn(__dmul_rn(d, d), (double)m);
                 } else {
-                    const float d = qi - xw[t];
+                    const float d = qi - xj;
                     v = (T)(d * d + (float)m);
                 }
                 D[t] = v;
                 left = v;
                 rowmin = v < rowmin ? v : rowmin;
             }
-#pragma unroll
-            for (int t = 0; t + 1 < W; ++t) xw[t] = xw[t + 1];
-            xw[W - 1] = in_x[0];
 #pragma unroll
             for (int v = 0; v + 1 < kDtwRows; ++v) in_x[v] = in_x[v + 1];
             if (!F64) {
@@ -1361,6 +1339,13 @@ __device__ T dtw_band(const float* __restrict__ q, const float* __restrict__ x, 
         for (int u = 0; u < kDtwRows; ++u) in_x[u] = nx[u];
     }
     return D[R];
+}
+
+// The query with MESSI_MAX_DTW_BAND values of +inf on each side, after all
+// the queries' envelopes in the envelope buffer (dtw_env_kernel writes it).
+constexpr int kQPad = MESSI_MAX_DTW_BAND;
+__device__ __forceinline__ const float* padded_query(const QArgs& a, int q) {
+    return a.env + (size_t)a.nq * 2 * a.L + (size_t)q * (a.L + 2 * kQPad);
 }
 
 // Keep this wave's LDS accesses in program order for the compiler: the
@@ -1610,7 +1595,6 @@ __global__ void __launch_bounds__(256) dtw_ec_kernel(QArgs a) {
 // bound become candidates, and for k = 1 they lower U.
 template <int R>
 __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
-    __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ float s_eu[MESSI_MAX_LEN], s_el[MESSI_MAX_LEN];
     __shared__ uint32_t s_off[4097];
     __shared__ uint32_t s_tmp[4];
@@ -1620,13 +1604,14 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
     if (st.err) return;
     if (list_overflow(a, st)) return;
     const int L = a.L;
-    const float* qg = a.queries + (size_t)q * L;
     const float* eg = a.env + (size_t)q * 2 * L;
     for (int j = tid; j < L; j += 256) {
-        s_q[j] = qg[j];
         s_eu[j] = eg[j];
         s_el[j] = eg[L + j];
     }
+    // the query values of a row are the same in every lane: read from the
+    // padded copy in memory (qp[j + t] = q[j - R + t])
+    const float* qp = padded_query(a, q) + (kQPad - R);
     const uint32_t G = a.ec_nseg;
     const uint32_t n = segment_offsets(a.ec_cnt + (size_t)q * G, G, s_off, s_tmp);
     unsigned long long ndtw = 0;
@@ -1637,7 +1622,7 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
         const float U = __uint_as_float(vload(&st.U));
         if (c.d * (1.0f - kRhoEd) > U) continue;
         ++ndtw;
-        const float d = dtw_band<R, float>(s_q, a.series + (size_t)c.idx * L, L, U, s_eu, s_el, c.d);
+        const float d = dtw_band<R, float>(qp, a.series + (size_t)c.idx * L, L, U, s_eu, s_el, c.d);
         if (d * (1.0f - kRhoDtw) <= __uint_as_float(vload(&st.U))) {
             const uint32_t slot = atomicAdd(&st.ncand, 1u);
             if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, c.idx};
@@ -1651,12 +1636,16 @@ __global__ void __launch_bounds__(256) dtw_kernel(QArgs a) {
 }
 
 // Once per DTW call: every query's LB_Keogh envelope, the largest and the
-// smallest query value within the band of each position.
+// smallest query value within the band of each position; and the query
+// padded with +inf for the DP.
 __global__ void __launch_bounds__(256) dtw_env_kernel(QArgs a) {
     const int q = blockIdx.x;
     const int L = a.L, r = a.band;
     const float* qg = a.queries + (size_t)q * L;
     float* eg = a.env + (size_t)q * 2 * L;
+    float* qp = a.env + (size_t)a.nq * 2 * L + (size_t)q * (L + 2 * kQPad);
+    for (int i = threadIdx.x; i < L + 2 * kQPad; i += 256)
+        qp[i] = (i >= kQPad && i < L + kQPad) ? qg[i - kQPad] : __builtin_huge_valf();
     for (int j = threadIdx.x; j < L; j += 256) {
         const int t0 = max(0, j - r), t1 = min(L - 1, j + r);
         float u = qg[t0], l = u;
@@ -1746,7 +1735,8 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     if constexpr (DB > 0) {
         // DTW: the canonical fp64 value of every candidate, a thread each
         for (uint32_t j = threadIdx.x; j < kept; j += 256)
-            s_d[j] = dtw_band<(DB > 0 ? DB - 1 : 0), double>(s_q, a.series + (size_t)s_i[j] * a.L, a.L, 0.f);
+            s_d[j] = dtw_band<(DB > 0 ? DB - 1 : 0), double>(padded_query(a, q) + (kQPad - (DB - 1)),
+                                                            a.series + (size_t)s_i[j] * a.L, a.L, 0.f);
     } else if (kept <= 16) {
         // D64 of every candidate: the squared differences added one after
         // another in index order, each operation rounded once (no fused
@@ -2337,10 +2327,11 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     a.ec_cnt = ws->ec_cnt.as<uint32_t>();
     const size_t ec_lds = sizeof(float) * ((((size_t)ix->len + g_max + 1 + 3) & ~(size_t)3) +
                                            4 * (size_t)ec_row_floats(ix->len));
-    if (ws->env_floats < (size_t)nq * 2 * ix->len) {
+    const size_t env_floats = (size_t)nq * (3 * (size_t)ix->len + 2 * kQPad);  // envelopes, padded queries
+    if (ws->env_floats < env_floats) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->env.alloc(sizeof(float) * (size_t)nq * 2 * ix->len));
-        ws->env_floats = (size_t)nq * 2 * ix->len;
+        MESSI_TRY(ws->env.alloc(sizeof(float) * env_floats));
+        ws->env_floats = env_floats;
         ++ws->gen;
     }
     a.env = ws->env.as<float>();
