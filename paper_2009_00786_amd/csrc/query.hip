@@ -1287,6 +1287,10 @@ __device__ T dtw_band(const float* __restrict__ qp, const float* __restrict__ x,
     constexpr bool F64 = sizeof(T) == 8;
     constexpr int W = 2 * R + 1;
     const T inf = (T)__builtin_huge_valf();
+    // the padded query is not written during the search: read it as constant
+    // memory, so its values (the same in every lane) come through scalar loads
+    using const_float = const __attribute__((address_space(4))) float;
+    const_float* qc = (const_float*)qp;
     T D[W];
 #pragma unroll
     for (int t = 0; t < W; ++t) D[t] = t == R ? (T)0 : inf;  // the virtual cell (-1, -1) starts the path
@@ -1312,7 +1316,7 @@ __device__ T dtw_band(const float* __restrict__ qp, const float* __restrict__ x,
             T left = inf, rowmin = inf;
 #pragma unroll
             for (int t = 0; t < W; ++t) {
-                const float qi = qp[j + t];
+                const float qi = qc[j + t];
                 const T above = (t + 1 < W) ? D[t + 1] : inf;
                 T m = D[t] < above ? D[t] : above;
                 m = left < m ? left : m;
