@@ -70,12 +70,27 @@ typedef struct {
     uint32_t count;
 } messi_leaf;
 
+/* Options of an index (messi_build_ex); a zeroed struct gives the defaults.
+ * The build reads znorm, bf16_shadow and stream; the others are kept with the
+ * index and govern its searches and servers. */
 typedef struct {
     int32_t znorm;       /* 1: z-normalise `series` in place before summarising (see messi_znorm) */
     int32_t bf16_shadow; /* 1: also keep a BF16 copy of every row, in leaf order, and fp32 squared
                             norms; required by MESSI_MODE_BF16 (costs 2 * len bytes per series) */
     void* stream;        /* hipStream_t for the build; NULL = the null stream */
-} messi_build_opts;
+    int32_t mode;        /* search mode of messi_knn (MESSI_MODE_*; MESSI_MODE_BF16 needs bf16_shadow) */
+    int32_t max_slots;   /* slot cap of a server created on this index with max_slots = 0 (0: 256) */
+    uint64_t budget_bytes; /* device bytes one search workspace (one per stream) may take; a call that
+                              needs more fails with MESSI_ENOMEM (0: no cap).  Also the budget of a
+                              server created with budget_bytes = 0 (0 there: 8 GiB) */
+    int32_t scan_chunk;  /* members per work unit of the ordered scan: 256, 512 or 1024 (0: 1024) */
+    uint32_t cand_cap;   /* candidate slots per query (0: 2^20 for a call of one query, else 64 k per
+                            query, at least 2^14, 2^16 in BF16 mode); at least 2 k is used.  A small
+                            value exercises the overflow recovery described at messi_knn_ex */
+    int32_t row_filter_max_q; /* MESSI_MODE_BF16 calls of at most this many queries take the ordered
+                                 scan with the BF16 row filter instead of the matrix-core filter
+                                 (0: 1; negative: never) */
+} messi_opts;
 
 typedef struct {
     int64_t n;
@@ -138,35 +153,47 @@ typedef struct {
  * leaf_cap >= 1.  Non-finite values -> MESSI_EINVAL. */
 messi_index* messi_build(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
                          int32_t leaf_cap);
+/* The same with options (opts may be NULL: all defaults).  Beyond messi_build's
+ * checks: MESSI_EINVAL for a mode other than MESSI_MODE_*, MESSI_MODE_BF16
+ * without bf16_shadow, scan_chunk not in {0, 256, 512, 1024}, max_slots < 0. */
 messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
-                            int32_t leaf_cap, const messi_build_opts* opts);
+                            int32_t leaf_cap, const messi_opts* opts);
 
 /* Exact k-NN (paper: Query Answering, Algorithms ExactSearch .. CalculateRealDistance,
  * generalised from 1 to k).  queries[nq][len] (device, fp32); out_idx[nq][k]
  * (device, int64) and out_dist[nq][k] (device, fp32) receive, per query, the k
  * series with the smallest (distance, index), ascending; distances are
  * fl32(sqrt(D)), D the squared distance summed in fp64 in index order.
- * 1 <= k <= min(n, 1024); nq == 0 is a no-op.  Synchronous. */
+ * 1 <= k <= min(n, 1024); nq == 0 is a no-op.  Runs in the index's search
+ * mode (messi_opts.mode; MESSI_MODE_FP32 by default) on the null stream.
+ * Synchronous. */
 int messi_knn(const messi_index* index, const float* queries, int32_t nq, int32_t k, int64_t* out_idx,
               float* out_dist);
 
-/* Same, on `stream` (hipStream_t, NULL = null stream), with a search mode
- * (MESSI_MODE_*) and optional counters (stats may be NULL).  The call
- * synchronises `stream` before returning, so that per-query errors (a
+/* Same, with a k per query, a search mode (MESSI_MODE_*), a stream
+ * (hipStream_t, NULL = null stream) and optional counters (stats may be NULL,
+ * host memory).
+ *   k_per_query  device int32[nq]: query q's k, 1 <= k_per_query[q] <= k_max;
+ *                NULL: every query takes k_max
+ *   k_max        1 <= k_max <= min(n, 1024): the row length of the outputs
+ *   out_idx, out_dist  device [nq][k_max]; row q holds query q's k_per_query[q]
+ *                answers, ascending (distance, index), and its remaining
+ *                entries are set to index -1 and distance +inf
+ * The call synchronises `stream` before returning, so that per-query errors (a
  * non-finite query, a candidate-buffer overflow) are reported by its return
  * code.  Concurrent calls on one index from different streams are allowed;
- * each stream gets its own search workspace.
- * Every query keeps a buffer of candidate distances (2^20 slots for a single
- * query, 64 k per query of a batch; the environment variable
- * MESSI_CANDIDATE_CAP overrides this for testing).  If a query's buffer
- * overflows, its scan reruns from the k-th buffered distance; if that
- * overflows too, the call (FP32 mode) retries with a buffer 16 times larger,
- * twice at most.  In BF16 mode a query whose candidates or filter pairs
+ * each stream gets its own search workspace (capped by messi_opts.budget_bytes).
+ * Every query keeps a buffer of candidate distances (messi_opts.cand_cap).  If
+ * a query's buffer overflows, its scan reruns from the k-th buffered distance;
+ * if that overflows too, the call (FP32 mode) retries with a buffer 16 times
+ * larger, twice at most.  In BF16 mode a query whose candidates or filter pairs
  * overflow their buffers is answered again, alone, in FP32 mode.
  * MESSI_EOVERFLOW remains only for inputs with more exact ties at the k-th
- * distance than the buffer can hold. */
-int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t mode,
-                 void* stream, int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
+ * distance than the buffer can hold.  MESSI_EINVAL also for k_per_query
+ * values outside [1, k_max] (checked before any search work). */
+int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, const int32_t* k_per_query,
+                 int32_t k_max, int32_t mode, void* stream, int64_t* out_idx, float* out_dist,
+                 messi_knn_stats* stats);
 
 void messi_free(messi_index* index); /* NULL-safe; synchronises the device */
 
@@ -279,10 +306,12 @@ typedef struct {
  * status, and a query whose BF16 buffers overflow is answered again, alone,
  * in FP32 mode before its result is posted.
  *   budget_bytes  device memory the server may use for per-query state; the
- *                 slot count is min(max_slots, budget_bytes / per-query need)
+ *                 slot count is min(max_slots, budget_bytes / per-query need);
+ *                 0 takes the index's messi_opts.budget_bytes (8 GiB if that is 0)
+ *   max_slots     0 takes the index's messi_opts.max_slots (256 if that is 0)
  *   mode          MESSI_MODE_FP32 or MESSI_MODE_BF16 (needs the BF16 shadow),
  *                 optionally OR-ed with MESSI_SERVER_* flags
- * Returns NULL on error: MESSI_EINVAL (null index, max_slots < 1, bad mode or
+ * Returns NULL on error: MESSI_EINVAL (null index, max_slots < 0, bad mode or
  * flags, BF16 without a shadow), MESSI_ENOMEM (budget below one query's need,
  * or an allocation failed), MESSI_EDEVICE.  The index must outlive the
  * server. */

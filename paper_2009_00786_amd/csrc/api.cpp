@@ -184,15 +184,33 @@ int messi_windows(const float* long_series, int64_t m, int32_t len, int64_t step
     return MESSI_OK;
 }
 
+// The options checked and their defaults filled in (no device call).
+static int check_opts(const messi_opts* opts, messi_opts& o) {
+    o = messi_opts{};
+    if (opts) o = *opts;
+    if (o.mode != MESSI_MODE_FP32 && o.mode != MESSI_MODE_BF16 && o.mode != MESSI_MODE_APPROX)
+        return fail(MESSI_EINVAL, "opts.mode must be a MESSI_MODE_* value");
+    if (o.mode == MESSI_MODE_BF16 && !o.bf16_shadow)
+        return fail(MESSI_EINVAL, "opts.mode = MESSI_MODE_BF16 needs opts.bf16_shadow = 1");
+    if (o.scan_chunk != 0 && o.scan_chunk != 256 && o.scan_chunk != 512 && o.scan_chunk != 1024)
+        return fail(MESSI_EINVAL, "opts.scan_chunk must be 0, 256, 512 or 1024");
+    if (o.max_slots < 0) return fail(MESSI_EINVAL, "opts.max_slots must be >= 0");
+    if (o.znorm != 0 && o.znorm != 1) return fail(MESSI_EINVAL, "opts.znorm must be 0 or 1");
+    if (o.bf16_shadow != 0 && o.bf16_shadow != 1) return fail(MESSI_EINVAL, "opts.bf16_shadow must be 0 or 1");
+    if (o.scan_chunk == 0) o.scan_chunk = 1024;
+    if (o.max_slots == 0) o.max_slots = 256;
+    if (o.row_filter_max_q == 0) o.row_filter_max_q = 1;
+    return MESSI_OK;
+}
+
 messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
-                            int32_t leaf_cap, const messi_build_opts* opts) {
+                            int32_t leaf_cap, const messi_opts* opts) {
     clear_error();
-    if (check_series_args(series, n, len) != MESSI_OK) return nullptr;
     if (segments < 1 || segments > MESSI_MAX_SEGMENTS) {
         fail(MESSI_EINVAL, "segments must be in [1, 16]");
         return nullptr;
     }
-    if (len % segments != 0) {
+    if (len >= 1 && len % segments != 0) {
         fail(MESSI_EINVAL, "len must be a multiple of segments");
         return nullptr;
     }
@@ -204,10 +222,13 @@ messi_index* messi_build_ex(const float* series, int64_t n, int32_t len, int32_t
         fail(MESSI_EINVAL, "leaf_cap must be >= 1");
         return nullptr;
     }
-    messi_build_opts o{};
-    if (opts) o = *opts;
+    messi_opts o;
+    if (check_opts(opts, o) != MESSI_OK) return nullptr;
+    if (check_series_args(series, n, len) != MESSI_OK) return nullptr;
     Index* ix = new Index();
     if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
+    ix->opts = o;
+    ix->opts.stream = nullptr;  // the build's stream only
     int rc = build_index(ix, series, n, len, segments, card_bits, leaf_cap, o);
     if (rc == MESSI_OK && o.bf16_shadow) rc = build_bf16_shadow(ix, (hipStream_t)o.stream);
     if (rc != MESSI_OK) {
@@ -235,7 +256,8 @@ int messi_append(messi_index* index, const float* series, int64_t new_n, void* s
     MESSI_HIP_TRY(hipDeviceSynchronize());  // searches on other streams are done with the old arrays
     Index* nx = new Index();
     nx->device = ix->device;
-    messi_build_opts o{};
+    nx->opts = ix->opts;
+    messi_opts o{};
     o.stream = stream;
     const SplitTab tab{ix->split_keys.as<uint4>(), ix->split_seg.as<uint8_t>(), ix->split_claim.as<uint32_t>(),
                        ix->split_mask};
@@ -302,13 +324,15 @@ int messi_export_leaves(const messi_index* index, messi_leaf* host_leaves, uint3
     return MESSI_OK;
 }
 
-int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t mode, void* stream,
-                 int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, const int32_t* k_per_query,
+                 int32_t k_max, int32_t mode, void* stream, int64_t* out_idx, float* out_dist,
+                 messi_knn_stats* stats) {
     clear_error();
     if (!index) return fail(MESSI_EINVAL, "index is null");
     const Index* ix = reinterpret_cast<const Index*>(index);
     if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
-    if (k < 1 || k > MESSI_MAX_K || (int64_t)k > ix->n) return fail(MESSI_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (k_max < 1 || k_max > MESSI_MAX_K || (int64_t)k_max > ix->n)
+        return fail(MESSI_EINVAL, "k_max must be in [1, min(n, 1024)]");
     if (mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16 && mode != MESSI_MODE_APPROX)
         return fail(MESSI_EINVAL, "unknown mode");
     if (mode == MESSI_MODE_BF16 && !ix->shadow.p)
@@ -318,10 +342,22 @@ int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, int
     if (!queries || !out_idx || !out_dist) return fail(MESSI_EINVAL, "null pointer argument");
     if (!is_device_pointer(queries) || !is_device_pointer(out_idx) || !is_device_pointer(out_dist))
         return fail(MESSI_EINVAL, "queries / out_idx / out_dist must be device pointers");
+    if (k_per_query && !is_device_pointer(k_per_query))
+        return fail(MESSI_EINVAL, "k_per_query must be a device pointer");
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev != ix->device)
         return fail(MESSI_EINVAL, "the index lives on another device");
-    return knn_device(ix, queries, nq, k, mode, (hipStream_t)stream, out_idx, out_dist, stats);
+    if (k_per_query) {
+        // every k is checked before any search work starts
+        std::vector<int32_t> hk((size_t)nq);
+        MESSI_HIP_TRY(hipMemcpyAsync(hk.data(), k_per_query, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost,
+                                     (hipStream_t)stream));
+        MESSI_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+        for (int32_t q = 0; q < nq; ++q)
+            if (hk[(size_t)q] < 1 || hk[(size_t)q] > k_max)
+                return fail(MESSI_EINVAL, "k_per_query values must be in [1, k_max]");
+    }
+    return knn_device(ix, queries, nq, k_max, k_per_query, mode, (hipStream_t)stream, out_idx, out_dist, stats);
 }
 
 int messi_knn_dtw(const messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t band,
@@ -345,7 +381,8 @@ int messi_knn_dtw(const messi_index* index, const float* queries, int32_t nq, in
 
 int messi_knn(const messi_index* index, const float* queries, int32_t nq, int32_t k, int64_t* out_idx,
               float* out_dist) {
-    return messi_knn_ex(index, queries, nq, k, MESSI_MODE_FP32, nullptr, out_idx, out_dist, nullptr);
+    const int32_t mode = index ? reinterpret_cast<const Index*>(index)->opts.mode : MESSI_MODE_FP32;
+    return messi_knn_ex(index, queries, nq, nullptr, k, mode, nullptr, out_idx, out_dist, nullptr);
 }
 
 }  // extern "C"

@@ -603,11 +603,11 @@ int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
     if (ws->qb.bytes < sizeof(uint16_t) * (size_t)nq * Lp || ws->qnorm.bytes < sizeof(float2) * (size_t)nq ||
         ws->qx.bytes < sizeof(uint4) * (size_t)nq) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->qb.alloc(sizeof(uint16_t) * (size_t)nq * Lp));
-        MESSI_TRY(ws->qnorm.alloc(sizeof(float2) * (size_t)nq));
-        MESSI_TRY(ws->qx.alloc(sizeof(uint4) * (size_t)nq));
         ws->bf_nq = 0;  // the batched filter's buffers are sized again on its next call
         ++ws->gen;
+        MESSI_TRY(ws->grow(ix, ws->qb, sizeof(uint16_t) * (size_t)nq * Lp));
+        MESSI_TRY(ws->grow(ix, ws->qnorm, sizeof(float2) * (size_t)nq));
+        MESSI_TRY(ws->grow(ix, ws->qx, sizeof(uint4) * (size_t)nq));
     }
     const BfConsts kc = bf_consts(Lp);
     a.shadow = ix->shadow.as<uint16_t>();
@@ -630,19 +630,23 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     const int nq = a.nq;
     const size_t nL = (size_t)ix->n_leaves;
     const size_t leafq_cap = (size_t)nq * nL;
-    const size_t pairs_cap = std::min<size_t>((size_t)nq * 65536, (size_t)1 << 28);
+    const size_t pairs_cap = bf16_pairs_cap(nq);
     if (ws->bf_nq < nq || ws->bf_pairs_cap < pairs_cap || ws->bf_leafq_cap < leafq_cap) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->qb.alloc(sizeof(uint16_t) * (size_t)nq * Lp));
-        MESSI_TRY(ws->qnorm.alloc(sizeof(float2) * (size_t)nq));
-        MESSI_TRY(ws->qx.alloc(sizeof(uint4) * (size_t)nq));
-        MESSI_TRY(ws->leaf_cnt.alloc(sizeof(uint32_t) * (nL + 1)));
-        MESSI_TRY(ws->leaf_off.alloc(sizeof(uint32_t) * (nL + 1)));
-        MESSI_TRY(ws->leaf_cur.alloc(sizeof(uint32_t) * (nL + 1)));
-        MESSI_TRY(ws->leaf_q.alloc(sizeof(uint32_t) * leafq_cap));
-        MESSI_TRY(ws->pairs.alloc(sizeof(uint2) * pairs_cap));
-        MESSI_TRY(ws->npairs.alloc(sizeof(uint32_t) * 4));
-        MESSI_TRY(ws->leaf_act.alloc(sizeof(uint32_t) * (nL + 1)));
+        // not valid until every buffer is in place (a failed allocation leaves its buffer empty)
+        ws->bf_nq = 0;
+        ws->bf_pairs_cap = ws->bf_leafq_cap = 0;
+        ++ws->gen;
+        MESSI_TRY(ws->grow(ix, ws->qb, sizeof(uint16_t) * (size_t)nq * Lp));
+        MESSI_TRY(ws->grow(ix, ws->qnorm, sizeof(float2) * (size_t)nq));
+        MESSI_TRY(ws->grow(ix, ws->qx, sizeof(uint4) * (size_t)nq));
+        MESSI_TRY(ws->grow(ix, ws->leaf_cnt, sizeof(uint32_t) * (nL + 1)));
+        MESSI_TRY(ws->grow(ix, ws->leaf_off, sizeof(uint32_t) * (nL + 1)));
+        MESSI_TRY(ws->grow(ix, ws->leaf_cur, sizeof(uint32_t) * (nL + 1)));
+        MESSI_TRY(ws->grow(ix, ws->leaf_q, sizeof(uint32_t) * leafq_cap));
+        MESSI_TRY(ws->grow(ix, ws->pairs, sizeof(uint2) * pairs_cap));
+        MESSI_TRY(ws->grow(ix, ws->npairs, sizeof(uint32_t) * 4));
+        MESSI_TRY(ws->grow(ix, ws->leaf_act, sizeof(uint32_t) * (nL + 1)));
         ws->bf_nq = nq;
         ++ws->gen;
         ws->bf_pairs_cap = pairs_cap;

@@ -1108,7 +1108,7 @@ int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_fl
 }
 
 int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t w, int32_t b, int32_t cap,
-                const messi_build_opts& opts, const SplitTab* forced) {
+                const messi_opts& opts, const SplitTab* forced) {
     hipStream_t s = (hipStream_t)opts.stream;
     ix->series = series;
     ix->n = n;

@@ -114,6 +114,7 @@ struct Index {
 
     float bp_host[255];
     messi_info info{};
+    messi_opts opts{};  // as given to the build, defaults filled in (search mode, budgets, scan chunk, ...)
 
     uint64_t device_bytes() const {
         return words.bytes + pos.bytes + leaves.bytes + bp.bytes + sx.bytes + shadow.bytes;
@@ -142,11 +143,13 @@ struct SplitTab {
 // forced (may be null): nodes that split on a given segment whatever the
 // balance (an append keeps the previous index's splits).
 int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t w, int32_t b, int32_t cap,
-                const messi_build_opts& opts, const SplitTab* forced = nullptr);
+                const messi_opts& opts, const SplitTab* forced = nullptr);
 
 // query.hip
-int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
-               int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
+// kq: device int32[nq] of per-query k (nullable: kmax for every query);
+// outputs are [nq][kmax].
+int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
+               hipStream_t s, int64_t* out_idx, float* out_dist, messi_knn_stats* stats);
 // Exact k-NN under DTW with a Sakoe-Chiba band of half-width `band`.
 int knn_dtw_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t band, hipStream_t s,
                    int64_t* out_idx, float* out_dist, messi_knn_stats* stats);

@@ -1,6 +1,8 @@
 // Query-side state shared by the FP32 and BF16 search paths and the server.
 #pragma once
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace messi {
@@ -11,7 +13,7 @@ constexpr int kApproxMax = 4096;     // members of the first leaf evaluated for 
 // of a full leaf, so no wave waits on a second row
 inline int approx_blocks(int nq) { return nq <= 2 ? 512 : nq <= 8 ? 256 : 128; }
 constexpr int kMaxFinal = 4096;      // candidates ordered by fp64 distance per query
-constexpr int kChunk = 1024;         // members per scan work unit
+constexpr int kChunk = 1024;         // most members per scan work unit (the index's scan_chunk: 256, 512 or 1024)
 constexpr int kHistBins = 4096;      // candidate-distance histogram (k > 1 bound)
 
 // Relative error margins (see the exactness notes in query.hip).
@@ -93,6 +95,7 @@ struct QArgs {
     // DTW search
     int32_t band;                // Sakoe-Chiba half-width; < 0: Euclidean search
     float rho_d;                 // relative error margin of the distances kept (ED or DTW)
+    uint32_t chunk;              // members per scan chunk (<= kChunk)
     uint32_t chunk_lo, chunk_hi; // the scan takes chunks [chunk_lo, chunk_hi) of each query's order
     Cand* todo;                  // [nq][todo_nseg][todo_seg] DTW: (LB_Keogh, series) waiting for their DTW,
     uint32_t todo_cap;           //   a segment per scan block of the query; todo_cap = todo_nseg * todo_seg
@@ -157,6 +160,11 @@ struct Workspace {
     unsigned long long* h_prof = nullptr;    // [4096][4]
     unsigned long long* h_blk_cnt = nullptr; // [4096][5]
     int ensure_stats();
+    // device bytes held by the workspace's buffers
+    size_t device_bytes() const;
+    // (Re)allocate b with `bytes` bytes unless that takes the workspace past the
+    // index's budget_bytes option (MESSI_ENOMEM).  b is empty after a failure.
+    int grow(const Index* ix, DevBuf& b, size_t bytes);
     ~Workspace();
 };
 
@@ -171,7 +179,7 @@ int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s);
 
 // Whether a BF16-mode call of nq queries runs the ordered scan with the BF16
 // row filter (few queries) instead of the batched matrix-core filter.
-bool row_filter_path(int32_t mode, int32_t nq, bool matrix_only);
+bool row_filter_path(const Index* ix, int32_t mode, int32_t nq, bool matrix_only);
 
 // For k > 1, lower every query's bound to its current k-th candidate distance.
 int refresh_bounds(QArgs& a, hipStream_t s);
@@ -188,9 +196,12 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
                 uint32_t cap_min = 0, bool matrix_only = false);
 // Default candidate slots per query for a call of nq queries with k <= kmax.
-uint32_t default_cap(int32_t nq, int32_t kmax, int32_t mode);
+uint32_t default_cap(const Index* ix, int32_t nq, int32_t kmax, int32_t mode);
 int knn_error_code(uint32_t err);
 int query_error_code(uint32_t status);
+
+// Slots of the BF16 filter's (query, member) survivor list for a batch of nq.
+inline size_t bf16_pairs_cap(int32_t nq) { return std::min<size_t>((size_t)nq * 65536, (size_t)1 << 28); }
 
 // Device bytes of search workspace one query needs (for a memory budget).
 size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap);

@@ -54,9 +54,6 @@ constexpr int kScanThreads = 256;
 // scan variants: Euclidean; Euclidean with the BF16 row filter; LB_Keogh for DTW
 constexpr int kScanEd = 0, kScanRowFilter = 1, kScanDtw = 2;
 constexpr int kEdBatch = 32;  // survivors gathered before a round of distances
-// BF16 calls of at most this many queries run the ordered scan with the BF16
-// row filter; larger batches share member rows on the matrix-core filter
-constexpr int32_t kRowFilterMaxQ = 1;
 // the row filter runs while U > kRowFilterTau |q|^2 (about twice its rounding
 // bound for |x| = |q|)
 constexpr float kRowFilterTau = 0.03f;
@@ -564,7 +561,7 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
             a.order[(size_t)q * a.nL + t] = (uint32_t)l;
             a.rec[(size_t)q * a.nL + t] = OrdRec{lf.start, lf.count, lbv, moff};
             const uint64_t end = (uint64_t)moff + lf.count;
-            for (uint64_t c = ((uint64_t)moff + kChunk - 1) / kChunk; c * kChunk < end; ++c)
+            for (uint64_t c = ((uint64_t)moff + a.chunk - 1) / a.chunk; c * a.chunk < end; ++c)
                 if (c < a.max_chunks) a.chunk_first[(size_t)q * a.max_chunks + c] = t;
         }
     }
@@ -718,7 +715,7 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
 
 // ---- the ordered scan --------------------------------------------------------
 // The members of the ordered leaves form one list (leaf after leaf in bound
-// order); it is cut into chunks of kChunk members and the G blocks of a query
+// order); it is cut into chunks of a.chunk (<= kChunk) members and the G blocks of a query
 // take chunks j, j + G, j + 2G, ...  Every block does the same amount of
 // member work, and the grid still advances through the order together, so
 // the best leaves are scanned first and U tightens early.  Per chunk:
@@ -827,7 +824,7 @@ scan_kernel(QArgs a) {
         const int k = st.k;
         const float range = st.range;
         // this call's chunks of the query's order: [chunk_lo, chunk_hi)
-        const uint64_t nch = min((nmemb + kChunk - 1) / kChunk, (uint64_t)a.chunk_hi);
+        const uint64_t nch = min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.chunk_hi);
         const uint64_t jb = (uint64_t)a.chunk_lo + (uint64_t)j;
         const uint32_t ncb = nch > jb ? (uint32_t)((nch - jb + G - 1) / G) : 0u;
         if (ncb == 0) continue;
@@ -882,25 +879,25 @@ scan_kernel(QArgs a) {
         // (position t0 + tid, valid if r_ok), into the LDS position arrays;
         // returns how many leaves the chunk spans.  Call from every thread.
         auto commit_positions = [&](uint64_t c, uint32_t t0, const OrdRec& r, bool r_ok, float Uc) -> uint32_t {
-            const uint64_t cbeg = c * kChunk;
+            const uint64_t cbeg = c * a.chunk;
             auto put = [&](uint32_t p, const OrdRec& rr) {
                 s_pbase[p] = rr.start + (uint32_t)cbeg - rr.moff;  // modulo 2^32
                 s_pm[p] = (uint64_t)rr.moff > cbeg ? (uint16_t)(rr.moff - (uint32_t)cbeg) : (uint16_t)0;
                 s_plb[p] = rr.lb;
                 if ((uint64_t)rr.moff >= cbeg && !(rr.lb * (1.0f - kRhoLb) > Uc)) ++c_scanned;
             };
-            bool inc = r_ok && (uint64_t)r.moff < cbeg + kChunk;
+            bool inc = r_ok && (uint64_t)r.moff < cbeg + a.chunk;
             if (inc) put(tid, r);
             int cnt = __syncthreads_count(inc);
             uint32_t np = (uint32_t)cnt;
             // the included leaves are a prefix of the positions from t0; a chunk
             // of many small leaves needs more than one round of records
-            for (uint32_t b0 = kScanThreads; cnt == kScanThreads && b0 < (uint32_t)kChunk; b0 += kScanThreads) {
+            for (uint32_t b0 = kScanThreads; cnt == kScanThreads && b0 < a.chunk; b0 += kScanThreads) {
                 const uint32_t t = t0 + b0 + tid;
                 inc = false;
                 if (t < nsurv) {
                     const OrdRec r2 = recq[t];
-                    inc = (uint64_t)r2.moff < cbeg + kChunk;
+                    inc = (uint64_t)r2.moff < cbeg + a.chunk;
                     if (inc) put(b0 + tid, r2);
                 }
                 cnt = __syncthreads_count(inc);
@@ -945,7 +942,7 @@ scan_kernel(QArgs a) {
             return live;
         };
         auto chunk_len = [&](uint64_t c) -> uint32_t {
-            return (uint32_t)min((uint64_t)kChunk, nmemb - c * kChunk);
+            return (uint32_t)min((uint64_t)a.chunk, nmemb - c * a.chunk);
         };
 
         // ---- prologue: chunk 0 of this block
@@ -1676,7 +1673,7 @@ __global__ void __launch_bounds__(256) dtw_active_kernel(QArgs a, uint32_t c1) {
     if (q >= a.nq) return;
     const QState& st = a.qs[q];
     if (st.err) return;
-    const uint64_t nch = ((uint64_t)st.nmemb + kChunk - 1) / kChunk;
+    const uint64_t nch = ((uint64_t)st.nmemb + a.chunk - 1) / a.chunk;
     if ((uint64_t)c1 >= nch) return;
     const uint32_t t0 = a.chunk_first[(size_t)q * a.max_chunks + c1];
     const float lb0 = a.rec[(size_t)q * a.nL + t0].lb;
@@ -1835,6 +1832,11 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
         a.out_idx[(size_t)q * ks + j] = (int64_t)s_i[j];
         a.out_dist[(size_t)q * ks + j] = (float)__dsqrt_rn(s_d[j]);
     }
+    // a query with k below the row length: the rest of its row is (-1, +inf)
+    for (uint32_t j = (uint32_t)k + threadIdx.x; j < ks; j += 256) {
+        a.out_idx[(size_t)q * ks + j] = -1;
+        a.out_dist[(size_t)q * ks + j] = __uint_as_float(0x7f800000u);
+    }
     if (threadIdx.x == 0 && a.counters) atomicAdd(&a.counters->final_cands, (unsigned long long)kept);
 }
 
@@ -1848,14 +1850,12 @@ std::map<std::pair<const Index*, hipStream_t>, Workspace*> g_ws;
 
 // Candidate slots per query: 2^20 for a single query, 64 k (at least 2^14;
 // 2^16 in BF16 mode, whose rounds append all rechecked survivors within the
-// round's bound) per query of a batch.  MESSI_CANDIDATE_CAP in the environment
-// overrides the default (at least 2 k), to exercise the overflow paths in tests.
-uint32_t default_cap(int32_t nq, int32_t kmax, int32_t mode) {
+// round's bound) per query of a batch.  The index's cand_cap option replaces
+// the default (at least 2 k), e.g. to exercise the overflow paths.
+uint32_t default_cap(const Index* ix, int32_t nq, int32_t kmax, int32_t mode) {
     const uint32_t floor_k = 2u * (uint32_t)kmax;
-    if (const char* v = std::getenv("MESSI_CANDIDATE_CAP")) {
-        const long long x = std::atoll(v);
-        if (x > 0) return std::max<uint32_t>(floor_k, (uint32_t)std::min<long long>(x, 1ll << 30));
-    }
+    if (ix->opts.cand_cap > 0)
+        return std::max<uint32_t>(floor_k, std::min<uint32_t>(ix->opts.cand_cap, 1u << 30));
     if (nq == 1) return 1u << 20;
     const uint32_t lo = mode == MESSI_MODE_BF16 ? (1u << 16) : (1u << 14);
     return std::max<uint32_t>(lo, 64u * (uint32_t)kmax);
@@ -1870,6 +1870,26 @@ int Workspace::ensure_stats() {
     return MESSI_OK;
 }
 
+size_t Workspace::device_bytes() const {
+    size_t t = 0;
+    for (const DevBuf* b : {&qs, &lb, &order, &rec, &chunk_first, &bins, &mbins, &cursor, &hist, &approx_d, &cand,
+                            &counters, &err, &prof, &blk_cnt, &status, &lbpart, &todo, &env, &todo_cnt, &ec, &ec_cnt,
+                            &qb, &qnorm, &qx, &leaf_cnt, &leaf_off, &leaf_cur, &leaf_q, &leaf_act, &pairs, &npairs})
+        t += b->bytes;
+    return t;
+}
+
+int Workspace::grow(const Index* ix, DevBuf& b, size_t bytes) {
+    const uint64_t budget = ix->opts.budget_bytes;
+    if (budget && device_bytes() - b.bytes + bytes > budget) {
+        b.release();
+        set_error(MESSI_ENOMEM, "search workspace of " + std::to_string(device_bytes() + bytes) +
+                                    " bytes exceeds the index's budget_bytes (" + std::to_string(budget) + ")");
+        return MESSI_ENOMEM;
+    }
+    return b.alloc(bytes);
+}
+
 Workspace::~Workspace() {
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -1879,7 +1899,10 @@ Workspace::~Workspace() {
 
 namespace {
 
-uint32_t max_chunks_of(const Index* ix) { return (uint32_t)((ix->n + kChunk - 1) / kChunk + 1); }
+uint32_t max_chunks_of(const Index* ix) {
+    const int64_t ch = ix->opts.scan_chunk;
+    return (uint32_t)((ix->n + ch - 1) / ch + 1);
+}
 
 int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Workspace** out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -1889,24 +1912,28 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
     if (ws->nq < nq || ws->nL != ix->n_leaves) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         const int32_t nqa = std::max(nq, ws->nq);
+        // not valid until every buffer is in place (a failed allocation leaves its buffer empty)
+        ws->nq = 0;
+        ws->nL = 0;
+        ++ws->gen;
         const size_t nL = (size_t)ix->n_leaves;
         const uint32_t mc = max_chunks_of(ix);
-        MESSI_TRY(ws->qs.alloc(sizeof(QState) * nqa));
-        MESSI_TRY(ws->lb.alloc(sizeof(float) * nL * nqa));
-        MESSI_TRY(ws->order.alloc(sizeof(uint32_t) * nL * nqa));
-        MESSI_TRY(ws->rec.alloc(sizeof(OrdRec) * nL * nqa));
-        MESSI_TRY(ws->chunk_first.alloc(sizeof(uint32_t) * (size_t)mc * nqa));
-        MESSI_TRY(ws->bins.alloc(sizeof(uint32_t) * kNB * nqa));
-        MESSI_TRY(ws->mbins.alloc(sizeof(uint32_t) * kNB * nqa));
-        MESSI_TRY(ws->cursor.alloc(sizeof(unsigned long long) * kNB * nqa));
-        MESSI_TRY(ws->hist.alloc(sizeof(uint32_t) * kHistBins * nqa));
-        MESSI_TRY(ws->approx_d.alloc(sizeof(float) * kApproxMax * nqa));
-        MESSI_TRY(ws->status.alloc(sizeof(uint32_t) * nqa));
-        MESSI_TRY(ws->counters.alloc(sizeof(QCounters)));
-        MESSI_TRY(ws->err.alloc(sizeof(uint32_t) * 4));
-        MESSI_TRY(ws->prof.alloc(sizeof(unsigned long long) * 4 * 4096));
-        MESSI_TRY(ws->blk_cnt.alloc(sizeof(unsigned long long) * kBlkCnt * 4096));
-        MESSI_TRY(ws->lbpart.alloc(sizeof(LbPart) * (size_t)nqa * ((nL + kLeafBlock - 1) / kLeafBlock)));
+        MESSI_TRY(ws->grow(ix, ws->qs, sizeof(QState) * nqa));
+        MESSI_TRY(ws->grow(ix, ws->lb, sizeof(float) * nL * nqa));
+        MESSI_TRY(ws->grow(ix, ws->order, sizeof(uint32_t) * nL * nqa));
+        MESSI_TRY(ws->grow(ix, ws->rec, sizeof(OrdRec) * nL * nqa));
+        MESSI_TRY(ws->grow(ix, ws->chunk_first, sizeof(uint32_t) * (size_t)mc * nqa));
+        MESSI_TRY(ws->grow(ix, ws->bins, sizeof(uint32_t) * kNB * nqa));
+        MESSI_TRY(ws->grow(ix, ws->mbins, sizeof(uint32_t) * kNB * nqa));
+        MESSI_TRY(ws->grow(ix, ws->cursor, sizeof(unsigned long long) * kNB * nqa));
+        MESSI_TRY(ws->grow(ix, ws->hist, sizeof(uint32_t) * kHistBins * nqa));
+        MESSI_TRY(ws->grow(ix, ws->approx_d, sizeof(float) * kApproxMax * nqa));
+        MESSI_TRY(ws->grow(ix, ws->status, sizeof(uint32_t) * nqa));
+        MESSI_TRY(ws->grow(ix, ws->counters, sizeof(QCounters)));
+        MESSI_TRY(ws->grow(ix, ws->err, sizeof(uint32_t) * 4));
+        MESSI_TRY(ws->grow(ix, ws->prof, sizeof(unsigned long long) * 4 * 4096));
+        MESSI_TRY(ws->grow(ix, ws->blk_cnt, sizeof(unsigned long long) * kBlkCnt * 4096));
+        MESSI_TRY(ws->grow(ix, ws->lbpart, sizeof(LbPart) * (size_t)nqa * ((nL + kLeafBlock - 1) / kLeafBlock)));
         if (!ws->h_err) MESSI_HIP_TRY(hipHostMalloc((void**)&ws->h_err, sizeof(uint32_t) * 4, 0));
         if (!ws->h_flag) {
             MESSI_HIP_TRY(hipHostMalloc((void**)&ws->h_flag, sizeof(uint32_t) * 4,
@@ -1920,7 +1947,9 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
     }
     if (ws->cand_slots < slots) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->cand.alloc(sizeof(Cand) * slots));
+        ws->cand_slots = 0;
+        ++ws->gen;
+        MESSI_TRY(ws->grow(ix, ws->cand, sizeof(Cand) * slots));
         ws->cand_slots = slots;
         ++ws->gen;
     }
@@ -1986,11 +2015,9 @@ int launch_scan(const QArgs& a, bool vec, int pass, int mode, hipStream_t s) {
 
 }  // namespace
 
-bool row_filter_path(int32_t mode, int32_t nq, bool matrix_only) {
+bool row_filter_path(const Index* ix, int32_t mode, int32_t nq, bool matrix_only) {
     if (mode != MESSI_MODE_BF16 || matrix_only) return false;
-    int32_t max_q = kRowFilterMaxQ;
-    if (const char* v = std::getenv("MESSI_ROW_FILTER_MAX_Q")) max_q = std::atoi(v);
-    return nq <= max_q;
+    return nq <= ix->opts.row_filter_max_q;
 }
 
 int refresh_bounds(QArgs& a, hipStream_t s) {
@@ -2044,7 +2071,7 @@ struct CallArgs {
 int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap, uint32_t cap_min = 0) {
     const Index* ix = c.ix;
     const int32_t nq = c.nq;
-    cap = std::max(default_cap(nq, c.kmax, c.mode), cap_min);
+    cap = std::max(default_cap(ix, nq, c.kmax, c.mode), cap_min);
     // the approximate mode's candidates are the evaluated members of one leaf
     if (c.mode == MESSI_MODE_APPROX) cap = std::max<uint32_t>(cap, (uint32_t)kApproxMax);
     Workspace* ws = nullptr;
@@ -2093,6 +2120,7 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.rho_d = kRhoEd;
     a.chunk_lo = 0;
     a.chunk_hi = 0xffffffffu;
+    a.chunk = (uint32_t)ix->opts.scan_chunk;
     return MESSI_OK;
 }
 
@@ -2136,7 +2164,7 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, nq), dim3(256), 0, s, a);
     MESSI_LAUNCH_CHECK("bin_scatter");
     MESSI_TRY(mark(4));
-    const bool rowf = row_filter_path(mode, nq, c.matrix_only);
+    const bool rowf = row_filter_path(ix, mode, nq, c.matrix_only);
     if (mode == MESSI_MODE_BF16 && !rowf) {
         MESSI_TRY(bf16_scan(ix, a, ws, s, timing));
     } else {
@@ -2287,17 +2315,19 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     const uint32_t g_max = nq <= B ? (uint32_t)((B + nq - 1) / nq) : 1u;
     const uint32_t g_min = nq <= B ? (uint32_t)(B / nq) : 1u;
     const uint64_t round_max = std::max<uint64_t>(64, kDtwRoundChunks / (uint32_t)nq);
-    const uint32_t seg = (uint32_t)((round_max + g_min - 1) / g_min) * (uint32_t)kChunk;
+    const uint32_t seg = (uint32_t)((round_max + g_min - 1) / g_min) * (uint32_t)ix->opts.scan_chunk;
     const uint32_t todo_cap = g_max * seg;
     if (ws->todo_slots < (size_t)nq * todo_cap) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->todo.alloc(sizeof(Cand) * (size_t)nq * todo_cap));
+        ws->todo_slots = 0;
+        MESSI_TRY(ws->grow(ix, ws->todo, sizeof(Cand) * (size_t)nq * todo_cap));
         ws->todo_slots = (size_t)nq * todo_cap;
         ++ws->gen;
     }
     if (ws->todo_cnt_n < (size_t)nq * g_max) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->todo_cnt.alloc(sizeof(uint32_t) * (size_t)nq * g_max));
+        ws->todo_cnt_n = 0;
+        MESSI_TRY(ws->grow(ix, ws->todo_cnt, sizeof(uint32_t) * (size_t)nq * g_max));
         ws->todo_cnt_n = (size_t)nq * g_max;
         ++ws->gen;
     }
@@ -2314,13 +2344,15 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     const uint32_t ec_cap = ec_blocks * ec_seg;
     if (ws->ec_slots < (size_t)nq * ec_cap) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->ec.alloc(sizeof(Cand) * (size_t)nq * ec_cap));
+        ws->ec_slots = 0;
+        MESSI_TRY(ws->grow(ix, ws->ec, sizeof(Cand) * (size_t)nq * ec_cap));
         ws->ec_slots = (size_t)nq * ec_cap;
         ++ws->gen;
     }
     if (ws->ec_cnt_n < (size_t)nq * ec_blocks) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->ec_cnt.alloc(sizeof(uint32_t) * (size_t)nq * ec_blocks));
+        ws->ec_cnt_n = 0;
+        MESSI_TRY(ws->grow(ix, ws->ec_cnt, sizeof(uint32_t) * (size_t)nq * ec_blocks));
         ws->ec_cnt_n = (size_t)nq * ec_blocks;
         ++ws->gen;
     }
@@ -2334,7 +2366,8 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     const size_t env_floats = (size_t)nq * (3 * (size_t)ix->len + 2 * kQPad);  // envelopes, padded queries
     if (ws->env_floats < env_floats) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
-        MESSI_TRY(ws->env.alloc(sizeof(float) * env_floats));
+        ws->env_floats = 0;
+        MESSI_TRY(ws->grow(ix, ws->env, sizeof(float) * env_floats));
         ws->env_floats = env_floats;
         ++ws->gen;
     }
@@ -2369,7 +2402,7 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     MESSI_HIP_TRY(hipStreamSynchronize(s));
     uint64_t max_nch = 0;
     for (const QState& h : hq)
-        if (!h.err) max_nch = std::max<uint64_t>(max_nch, ((uint64_t)h.nmemb + kChunk - 1) / kChunk);
+        if (!h.err) max_nch = std::max<uint64_t>(max_nch, ((uint64_t)h.nmemb + a.chunk - 1) / a.chunk);
     const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
     // the DP kernel's blocks: as many as are resident at once (its grid-stride
     // loop gives every block the same share, so a second partial wave of
@@ -2490,13 +2523,14 @@ size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap) {
                sizeof(uint32_t) * (size_t)max_chunks_of(ix) + kNB * (2 * sizeof(uint32_t) + sizeof(unsigned long long)) +
                sizeof(uint32_t) * kHistBins + sizeof(float) * kApproxMax + sizeof(Cand) * (size_t)cap +
                sizeof(LbPart) * ((nL + kLeafBlock - 1) / kLeafBlock) + sizeof(uint32_t);
-    if (mode == MESSI_MODE_BF16) b += nL * 4 + 16384 * 8 + (size_t)((ix->len + 31) / 32 * 32) * 2 + 8;
+    if (mode == MESSI_MODE_BF16)
+        b += nL * 4 + sizeof(uint2) * bf16_pairs_cap(1) + (size_t)((ix->len + 31) / 32 * 32) * 2 + 8 + 16;
     return b;
 }
 
-int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int32_t mode, hipStream_t s,
-               int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
-    CallArgs c{ix, queries, nq, k, nullptr, mode, s, out_idx, out_dist};
+int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, const int32_t* kq, int32_t mode,
+               hipStream_t s, int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    CallArgs c{ix, queries, nq, k, kq, mode, s, out_idx, out_dist};
     Workspace* ws = nullptr;
     QArgs a;
     uint32_t cap = 0;
@@ -2510,7 +2544,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
     };
     uint32_t err = 0;
     QCounters hc{};
-    const bool rowf = row_filter_path(mode, nq, false);
+    const bool rowf = row_filter_path(ix, mode, nq, false);
     const int sg = scan_grid(rowf ? kScanRowFilter : kScanEd);
     const bool fp32 = mode == MESSI_MODE_FP32 || rowf;  // the ordered scan runs
     const unsigned long long* hprof = nullptr;
@@ -2574,8 +2608,9 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, int
         for (int32_t q = 0; q < nq; ++q) {
             if (query_error_code(st[q]) != MESSI_EOVERFLOW) continue;
             ++fallbacks;
-            const int rc = knn_device(ix, queries + (size_t)q * ix->len, 1, k, MESSI_MODE_FP32, s,
-                                      out_idx + (size_t)q * k, out_dist + (size_t)q * k, nullptr);
+            const int rc = knn_device(ix, queries + (size_t)q * ix->len, 1, k, kq ? kq + q : nullptr,
+                                      MESSI_MODE_FP32, s, out_idx + (size_t)q * k, out_dist + (size_t)q * k,
+                                      nullptr);
             if (rc == MESSI_EOVERFLOW) rest |= 2u;
             else if (rc != MESSI_OK) return rc;
         }

@@ -166,7 +166,7 @@ struct Server {
         *ln.h_err = 0;
         uint32_t cap_min = 0;
         if (ln.batch[0].fp32)
-            cap_min = default_cap(1, kmax, MESSI_MODE_FP32) << (4 * ln.batch[0].grow);
+            cap_min = default_cap(ix, 1, kmax, MESSI_MODE_FP32) << (4 * ln.batch[0].grow);
         const Shape shape{nq, kmax, ln.mode, cap_min};
         bool replayed = false, recorded = false;
         if (use_graphs) {
@@ -200,7 +200,7 @@ struct Server {
             std::lock_guard<std::mutex> lk(mu);
             stats.batches += 1;
             if (ln.mode == MESSI_MODE_BF16) stats.bf16_batches += 1;
-            if (row_filter_path(ln.mode, nq, !row_filter)) stats.row_filter += 1;
+            if (row_filter_path(ix, ln.mode, nq, !row_filter)) stats.row_filter += 1;
             if (recorded) stats.graphs_recorded += 1;
             if (replayed) stats.graph_replays += 1;
             if (!recorded && !replayed) stats.eager_launches += 1;
@@ -341,8 +341,8 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
         set_error(MESSI_EINVAL, "index is null");
         return nullptr;
     }
-    if (max_slots < 1) {
-        set_error(MESSI_EINVAL, "max_slots must be >= 1");
+    if (max_slots < 0) {
+        set_error(MESSI_EINVAL, "max_slots must be >= 0");
         return nullptr;
     }
     const int32_t flags = mode & ~0xff;
@@ -357,6 +357,9 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
         set_error(MESSI_EINVAL, "BF16 serving needs an index built with bf16_shadow = 1");
         return nullptr;
     }
+    // zero takes the index's options
+    if (max_slots == 0) max_slots = ix->opts.max_slots;
+    if (budget_bytes == 0) budget_bytes = ix->opts.budget_bytes ? (size_t)ix->opts.budget_bytes : (size_t)8 << 30;
     const size_t per_q = bytes_per_query(ix, mode);
     const int64_t fit = (int64_t)(budget_bytes / per_q);
     if (fit < 1) {

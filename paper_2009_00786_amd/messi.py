@@ -53,8 +53,10 @@ LEAF_DTYPE = np.dtype([("card", np.uint8, (16,)), ("prefix", np.uint8, (16,)),
                        ("start", np.uint32), ("count", np.uint32)])
 
 
-class BuildOpts(ctypes.Structure):
-    _fields_ = [("znorm", ctypes.c_int32), ("bf16_shadow", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+class Opts(ctypes.Structure):
+    _fields_ = [("znorm", ctypes.c_int32), ("bf16_shadow", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("mode", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64),
+                ("scan_chunk", ctypes.c_int32), ("cand_cap", ctypes.c_uint32), ("row_filter_max_q", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -109,11 +111,11 @@ def load():
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         lib.messi_build.argtypes = [vp, i64, i32, i32, i32, i32]
         lib.messi_build.restype = vp
-        lib.messi_build_ex.argtypes = [vp, i64, i32, i32, i32, i32, ctypes.POINTER(BuildOpts)]
+        lib.messi_build_ex.argtypes = [vp, i64, i32, i32, i32, i32, ctypes.POINTER(Opts)]
         lib.messi_build_ex.restype = vp
         lib.messi_knn.argtypes = [vp, vp, i32, i32, vp, vp]
         lib.messi_knn.restype = ctypes.c_int
-        lib.messi_knn_ex.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, ctypes.POINTER(KnnStats)]
+        lib.messi_knn_ex.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(KnnStats)]
         lib.messi_knn_ex.restype = ctypes.c_int
         lib.messi_free.argtypes = [vp]
         lib.messi_free.restype = None
@@ -204,7 +206,9 @@ class Index:
     """An iSAX index over a CUDA fp32 tensor [n, len]; the tensor is borrowed."""
 
     def __init__(self, series, segments=16, card_bits=8, leaf_cap=2000, znorm=False, bf16_shadow=False,
-                 stream=None):
+                 stream=None, mode=MODE_FP32, max_slots=0, budget_bytes=0, scan_chunk=0, cand_cap=0,
+                 row_filter_max_q=0):
+        """Options as messi_opts (include/messi.h); zeros take the defaults."""
         lib = load()
         if series.is_cuda:
             assert series.is_contiguous()
@@ -212,7 +216,8 @@ class Index:
             ptr = series.data_ptr()
         else:
             n, length, ptr = 0, 0, 0
-        opts = BuildOpts(int(bool(znorm)), int(bool(bf16_shadow)), _stream_ptr(stream))
+        opts = Opts(int(bool(znorm)), int(bool(bf16_shadow)), _stream_ptr(stream), int(mode), int(max_slots),
+                    int(budget_bytes), int(scan_chunk), int(cand_cap), int(row_filter_max_q))
         h = lib.messi_build_ex(ctypes.c_void_p(ptr) if ptr else None, n if series.is_cuda else series.shape[0],
                                length if series.is_cuda else series.shape[1], segments, card_bits, leaf_cap,
                                ctypes.byref(opts))
@@ -266,8 +271,11 @@ class Index:
         _check(load().messi_export_leaves(self._h, leaves.ctypes.data, pos.ctypes.data))
         return leaves, pos
 
-    def knn(self, queries, k: int, mode: int = MODE_FP32, stream=None, stats: bool = False, out=None):
-        """Exact k-NN of CUDA fp32 queries [nq, len] -> (idx int64 [nq, k], dist fp32 [nq, k]) on the GPU."""
+    def knn(self, queries, k: int, mode: int = MODE_FP32, stream=None, stats: bool = False, out=None,
+            k_per_query=None):
+        """Exact k-NN of CUDA fp32 queries [nq, len] -> (idx int64 [nq, k], dist fp32 [nq, k]) on the GPU
+        (messi_knn_ex).  k_per_query: optional CUDA int32 [nq] of per-query k <= k; row q then holds
+        its k_per_query[q] answers followed by (-1, +inf)."""
         import torch
         assert queries.is_cuda and queries.dtype == torch.float32 and queries.is_contiguous()
         nq = queries.shape[0]
@@ -276,13 +284,28 @@ class Index:
             out_dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
         else:
             out_idx, out_dist = out
+        kq = None
+        if k_per_query is not None:
+            assert k_per_query.is_cuda and k_per_query.dtype == torch.int32 and k_per_query.is_contiguous()
+            kq = ctypes.c_void_p(k_per_query.data_ptr())
         st = KnnStats() if stats else None
-        rc = load().messi_knn_ex(self._h, ctypes.c_void_p(queries.data_ptr()), nq, k, mode, _stream_ptr(stream),
+        rc = load().messi_knn_ex(self._h, ctypes.c_void_p(queries.data_ptr()), nq, kq, k, mode, _stream_ptr(stream),
                                  ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_dist.data_ptr()),
                                  ctypes.byref(st) if st is not None else None)
         _check(rc)
         if stats:
             return out_idx, out_dist, {f: getattr(st, f) for f, _ in KnnStats._fields_}
+        return out_idx, out_dist
+
+    def knn_plain(self, queries, k: int):
+        """messi_knn: the synchronous plain call (the index's search mode, null stream)."""
+        import torch
+        assert queries.is_cuda and queries.dtype == torch.float32 and queries.is_contiguous()
+        nq = queries.shape[0]
+        out_idx = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
+        out_dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+        _check(load().messi_knn(self._h, ctypes.c_void_p(queries.data_ptr()), nq, k,
+                                ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_dist.data_ptr())))
         return out_idx, out_dist
 
     def knn_dtw(self, queries, k: int, band: int, stream=None, stats: bool = False, out=None):
@@ -309,7 +332,8 @@ class Index:
 class Server:
     """Continuous-batching request loop over a resident index (messi_server_*)."""
 
-    def __init__(self, index: Index, budget_bytes: int, max_slots: int = 256, mode: int = MODE_BF16):
+    def __init__(self, index: Index, budget_bytes: int = 0, max_slots: int = 0, mode: int = MODE_BF16):
+        """budget_bytes / max_slots 0: the index's options (messi_server_create)."""
         h = load().messi_server_create(index.handle, budget_bytes, max_slots, mode)
         if not h:
             code, msg = last_error()

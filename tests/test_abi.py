@@ -85,3 +85,44 @@ def test_no_device_reports_enodev(lib):
     assert m.messi_build(ctypes.c_void_p(host.ctypes.data), 4, 16, 4, 8, 10) is None
     assert lib.last_error()[0] == lib.MESSI_ENODEV
     assert m.messi_znorm(ctypes.c_void_p(host.ctypes.data), 4, 16, None) == lib.MESSI_ENODEV
+
+
+def _struct_fields(name):
+    """Field names of a typedef'd struct of the header, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text, flags=re.S).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(","):
+            names.append(re.findall(r"\**(\w+)\s*(?:\[\w+\])?\s*$", part.strip())[0])
+    return names
+
+
+@pytest.mark.parametrize("cname,pyname", [("messi_opts", "Opts"), ("messi_info", "Info"),
+                                          ("messi_knn_stats", "KnnStats"), ("messi_leaf", "Leaf"),
+                                          ("messi_server_counters", "ServerStats")])
+def test_binding_structs_match_the_header(lib, cname, pyname):
+    assert [f for f, _ in getattr(lib, pyname)._fields_] == _struct_fields(cname)
+
+
+def test_knn_ex_takes_k_per_query_and_k_max():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    sig = re.search(r"int messi_knn_ex\(([^)]*)\)", text, flags=re.S).group(1)
+    params = [p.strip() for p in sig.split(",")]
+    assert params[3] == "const int32_t* k_per_query" and params[4] == "int32_t k_max"
+
+
+def test_options_checked_before_any_device_call(lib):
+    m = lib.load()
+    ptr = ctypes.c_void_p(16)  # never dereferenced: the options are rejected first
+    for bad in (dict(mode=7), dict(mode=lib.MODE_BF16), dict(scan_chunk=300), dict(max_slots=-1),
+                dict(znorm=2)):
+        o = lib.Opts()
+        for key, v in bad.items():
+            setattr(o, key, v)
+        assert m.messi_build_ex(ptr, 10, 256, 16, 8, 2000, ctypes.byref(o)) is None, bad
+        code, msg = lib.last_error()
+        assert code == lib.MESSI_EINVAL and "opts." in msg, (bad, msg)

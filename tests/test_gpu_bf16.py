@@ -50,7 +50,7 @@ def tiny_bf16(torch_cuda, messi, datagen_mod, oracle_mod):
     rows = datagen_mod.uniform_ints(8, 100_000, 21, 7)
     noisy = datagen_mod.add_noise(z[rows], [0.01, 0.1, 1.0, 0.01, 0.1, 1.0, 0.01, 0.1])
     q = np.concatenate([fresh, noisy])
-    yield {"z": z, "ix": ix, "q": q}
+    yield {"z": z, "ix": ix, "q": q, "t": t}
     ix.close()
 
 
@@ -65,15 +65,16 @@ def test_bf16_batched_matches_oracle(tiny_bf16, oracle_mod, torch_cuda, messi, k
     assert st["series_recheck"] < st["series_distance"]
 
 
-def test_bf16_overflow_falls_back_to_fp32(tiny_bf16, oracle_mod, torch_cuda, messi, monkeypatch):
+def test_bf16_overflow_falls_back_to_fp32(tiny_bf16, oracle_mod, torch_cuda, messi):
     """Candidate buffers far too small for the BF16 rounds: the queries that
     overflow are answered again by the FP32 path, and every answer is exact."""
     w = tiny_bf16
-    monkeypatch.setenv("MESSI_CANDIDATE_CAP", "16")
+    ix = messi.Index(w["t"], 16, 8, 2000, bf16_shadow=True, cand_cap=16)  # t is z-normalised by now
     k = 30
     _say("bf16 overflow fallback k=%d" % k)
     oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"], k, nthreads=8)
-    gi, gd, st = w["ix"].knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=messi.MODE_BF16, stats=True)
+    gi, gd, st = ix.knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=messi.MODE_BF16, stats=True)
+    ix.close()
     _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
     _say("  fallbacks", st["fallbacks"])
     assert st["fallbacks"] > 0
@@ -168,26 +169,28 @@ def test_row_filter_single_queries_match_oracle(tiny_bf16, oracle_mod, torch_cud
     np.testing.assert_array_equal(gd, fd)
 
 
-def test_row_filter_for_a_batch(tiny_bf16, oracle_mod, torch_cuda, messi, monkeypatch):
+def test_row_filter_for_a_batch(tiny_bf16, oracle_mod, torch_cuda, messi):
     """The row-filtered scan over a batch (blocks share the grid across queries)."""
     w = tiny_bf16
-    monkeypatch.setenv("MESSI_ROW_FILTER_MAX_Q", "64")
+    ix = messi.Index(w["t"], 16, 8, 2000, bf16_shadow=True, row_filter_max_q=64)
     for k in (1, 10):
         _say("row filter, batch of %d, k=%d" % (len(w["q"]), k))
         oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"], k, nthreads=8)
-        gi, gd, st = w["ix"].knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=messi.MODE_BF16, stats=True)
+        gi, gd, st = ix.knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=messi.MODE_BF16, stats=True)
         _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
         assert st["bf16_flops"] > 0 and st["bf16_rounds"] == 0
+    ix.close()
 
 
-def test_row_filter_candidate_overflow_recovers(tiny_bf16, oracle_mod, torch_cuda, messi, monkeypatch):
+def test_row_filter_candidate_overflow_recovers(tiny_bf16, oracle_mod, torch_cuda, messi):
     w = tiny_bf16
-    monkeypatch.setenv("MESSI_CANDIDATE_CAP", "16")
+    ix = messi.Index(w["t"], 16, 8, 2000, bf16_shadow=True, cand_cap=16)
     k = 30
     _say("row filter, candidate buffer of 16, k=%d" % k)
     oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"][:4], k, nthreads=8)
-    gi, gd, _ = _one_by_one(w["ix"], w["q"][:4], k, torch_cuda, messi.MODE_BF16)
+    gi, gd, _ = _one_by_one(ix, w["q"][:4], k, torch_cuda, messi.MODE_BF16)
     _check(gi, gd, oidx, od)
+    ix.close()
 
 
 @pytest.mark.parametrize("n,length,w,b,cap,k", BF16_SHAPES)

@@ -146,15 +146,16 @@ def test_dtw_every_band(torch_cuda, messi, datagen_mod, oracle_mod):
     ix.close()
 
 
-def test_dtw_candidate_overflow_recovers(walks128, oracle_mod, messi, torch_cuda, monkeypatch):
+def test_dtw_candidate_overflow_recovers(walks128, oracle_mod, messi, torch_cuda):
     """A candidate buffer far smaller than what the first round's loose bound
     lets through for k > 1: the search runs again with a larger buffer and
     the answers stay exact."""
     w = walks128
-    monkeypatch.setenv("MESSI_CANDIDATE_CAP", "64")
+    ix = messi.Index(torch_cuda.from_numpy(w["z"]).cuda(), 16, 8, 200, cand_cap=64)
     for k in (8, 30):
         _say("dtw overflow recovery k=%d" % k)
         oi, _, od = oracle_mod.knn_brute_dtw(w["z"], w["q"], k, 12, nthreads=8)
-        gi, gd = w["ix"].knn_dtw(torch_cuda.from_numpy(w["q"]).cuda(), k, 12)
+        gi, gd = ix.knn_dtw(torch_cuda.from_numpy(w["q"]).cuda(), k, 12)
         np.testing.assert_array_equal(gi.cpu().numpy(), oi)
         np.testing.assert_array_equal(gd.cpu().numpy(), od)
+    ix.close()

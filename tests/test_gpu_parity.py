@@ -188,6 +188,97 @@ def test_knn_batched(tiny_workload, oracle_mod, datagen_mod, torch_cuda, k):
     _say("  stats", st)
 
 
+def test_plain_messi_knn_entry_point(tiny_workload, oracle_mod):
+    """messi_knn itself: synchronous, the index's default mode (FP32), one query
+    and a batch."""
+    w = tiny_workload
+    _say("messi_knn: single queries k=1 and a batch k=5")
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], w["qz"], 5, nthreads=8)
+    for i in range(3):
+        gi, gd = w["ix"].knn_plain(w["qt"][i:i + 1].contiguous(), 1)
+        _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx[i:i + 1, :1], od[i:i + 1, :1])
+    gi, gd = w["ix"].knn_plain(w["qt"], 5)
+    _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+
+
+@pytest.fixture(scope="module")
+def tiny_bf16_index(tiny_workload, torch_cuda, messi):
+    """A second index over the same rows with the BF16 shadow."""
+    t = torch_cuda.from_numpy(tiny_workload["z"]).cuda()
+    ix = messi.Index(t, 16, 8, 2000, bf16_shadow=True)
+    yield ix
+    ix.close()
+
+
+@pytest.mark.parametrize("mode_name", ["FP32", "BF16"])
+def test_knn_per_query_k(tiny_workload, tiny_bf16_index, oracle_mod, datagen_mod, torch_cuda, messi, mode_name):
+    """messi_knn_ex with k_per_query: row q holds the k_per_query[q] nearest
+    neighbours of query q, then (-1, +inf) up to k_max."""
+    torch = torch_cuda
+    w = tiny_workload
+    rows = datagen_mod.uniform_ints(10, 100_000, 19, 5)
+    qn = datagen_mod.add_noise(w["z"][rows], [0.01, 0.1, 1.0, 0.01, 0.1, 1.0, 0.01, 0.1, 1.0, 0.5])
+    q = np.concatenate([w["qz"], qn])
+    ks = np.array([1, 7, 100, 3, 1, 50, 10, 2, 64, 1, 100, 5, 1, 33, 9, 2, 17, 1, 80, 4], dtype=np.int32)
+    kmax = 100
+    mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
+    _say("per-query k, %s, %d queries, k_max %d" % (mode_name, len(q), kmax))
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], q, kmax, nthreads=8)
+    gi, gd = tiny_bf16_index.knn(torch.from_numpy(q).cuda(), kmax, mode=mode,
+                                 k_per_query=torch.from_numpy(ks).cuda())
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    for i, kq in enumerate(ks):
+        _check_answers(gi[i:i + 1, :kq], gd[i:i + 1, :kq], oidx[i:i + 1, :kq], od[i:i + 1, :kq])
+        assert np.all(gi[i, kq:] == -1) and np.all(np.isposinf(gd[i, kq:]))
+    # a k outside [1, k_max] is rejected before any search
+    bad = torch.from_numpy(np.array([1, 0], dtype=np.int32)).cuda()
+    with pytest.raises(messi.MessiError) as e:
+        tiny_bf16_index.knn(torch.from_numpy(q[:2].copy()).cuda(), 4, k_per_query=bad)
+    assert e.value.code == messi.MESSI_EINVAL
+    bad = torch.from_numpy(np.array([5, 1], dtype=np.int32)).cuda()
+    with pytest.raises(messi.MessiError) as e:
+        tiny_bf16_index.knn(torch.from_numpy(q[:2].copy()).cuda(), 4, k_per_query=bad)
+    assert e.value.code == messi.MESSI_EINVAL
+
+
+@pytest.mark.parametrize("chunk", [256, 512])
+def test_index_options_scan_chunk_and_mode(tiny_workload, oracle_mod, datagen_mod, torch_cuda, messi, chunk):
+    """Index options: a smaller scan chunk gives the same exact answers, and
+    messi_knn runs in the index's own mode (BF16 here)."""
+    torch = torch_cuda
+    w = tiny_workload
+    t = torch.from_numpy(w["z"]).cuda()
+    ix = messi.Index(t, 16, 8, 2000, bf16_shadow=True, scan_chunk=chunk, mode=messi.MODE_BF16)
+    rows = datagen_mod.uniform_ints(4, 100_000, 23, 5)
+    q = np.concatenate([w["qz"][:4], datagen_mod.add_noise(w["z"][rows], [0.01, 0.1, 1.0, 0.3])])
+    for k in (1, 10):
+        _say("scan chunk %d, k=%d: FP32 one at a time, messi_knn (BF16) batched" % (chunk, k))
+        oidx, od, _ = oracle_mod.knn_brute(w["z"], q, k, nthreads=8)
+        for i in range(len(q)):
+            gi, gd = ix.knn(torch.from_numpy(q[i:i + 1].copy()).cuda(), k)
+            _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx[i:i + 1], od[i:i + 1])
+        gi, gd = ix.knn_plain(torch.from_numpy(q).cuda(), k)
+        _check_answers(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    ix.close()
+
+
+def test_workspace_budget(tiny_workload, torch_cuda, messi):
+    """budget_bytes caps a stream's search workspace: a call that needs more
+    fails with MESSI_ENOMEM; a large enough budget answers as usual."""
+    w = tiny_workload
+    t = torch_cuda.from_numpy(w["z"]).cuda()
+    small = messi.Index(t, 16, 8, 2000, budget_bytes=1 << 20)
+    with pytest.raises(messi.MessiError) as e:
+        small.knn(w["qt"][:1].contiguous(), 1)
+    assert e.value.code == messi.MESSI_ENOMEM
+    small.close()
+    big = messi.Index(t, 16, 8, 2000, budget_bytes=64 << 20)
+    a = big.knn(w["qt"][:2].contiguous(), 3)
+    b = w["ix"].knn(w["qt"][:2].contiguous(), 3)
+    assert torch_cuda.equal(a[0], b[0]) and torch_cuda.equal(a[1], b[1])
+    big.close()
+
+
 def test_knn_matches_oracle_isax_counts(tiny_workload, oracle_mod):
     """The oracle's pruned search and the GPU give the same answers."""
     w = tiny_workload
@@ -248,15 +339,14 @@ def test_knn_ties_and_degenerate(torch_cuda, messi, oracle_mod):
     assert list(gi.cpu().numpy()[0]) == [7, 100, 101]
 
 
-def test_knn_candidate_overflow_recovers(torch_cuda, messi, datagen_mod, oracle_mod, monkeypatch):
+def test_knn_candidate_overflow_recovers(torch_cuda, messi, datagen_mod, oracle_mod):
     """A candidate buffer far smaller than what a loose first bound lets
     through: the scan reruns from the k-th buffered distance (and the call
     retries with a larger buffer if even that overflows); answers stay exact."""
     torch = torch_cuda
     z = oracle_mod.znorm(datagen_mod.random_walks(30_000, 64, seed=77, stream=0))
     q = datagen_mod.add_noise(z[[5, 17_000, 29_999]], [1.0, 1.0, 0.5])
-    ix = messi.Index(torch.from_numpy(z).cuda(), 16, 8, 200)
-    monkeypatch.setenv("MESSI_CANDIDATE_CAP", "64")
+    ix = messi.Index(torch.from_numpy(z).cuda(), 16, 8, 200, cand_cap=64)
     reruns = 0
     for k in (1, 8, 30):
         _say("overflow recovery k=%d" % k)

@@ -43,7 +43,7 @@ def served(torch_cuda, messi, datagen_mod, oracle_mod):
     sig = np.array([(0.01, 0.1, 1.0)[i % 3] for i in range(nqueries)])
     q = datagen_mod.add_noise(z[rows], sig)
     ks = np.array([(1, 10, 100)[(i // 3) % 3] for i in range(nqueries)], dtype=np.int32)
-    yield {"z": z, "ix": ix, "q": q, "ks": ks, "n": n}
+    yield {"z": z, "ix": ix, "q": q, "ks": ks, "n": n, "t": t}
     ix.close()
 
 
@@ -69,16 +69,17 @@ def _serve(messi, ix, q, ks, mode, budget, slots, pause):
 
 
 @pytest.mark.parametrize("mode_name,slots,small_cap", [("BF16", 48, False), ("FP32", 1, False), ("BF16", 48, True)])
-def test_results_alone_and_in_the_mix(served, messi, torch_cuda, oracle_mod, monkeypatch, mode_name, slots,
-                                      small_cap):
+def test_results_alone_and_in_the_mix(served, messi, torch_cuda, oracle_mod, mode_name, slots, small_cap):
     """small_cap: candidate buffers so small that BF16 batches overflow; those
     queries must come back exact through the FP32 fallback."""
     w = served
     mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
-    if small_cap:
-        monkeypatch.setenv("MESSI_CANDIDATE_CAP", "16")
+    # with small_cap, a second index over the same (by now z-normalised) rows with 16 candidate slots
+    ix = messi.Index(w["t"], 16, 8, 2000, bf16_shadow=True, cand_cap=16) if small_cap else w["ix"]
     _say("serving %s, %d slots, %d queries, small buffers %s" % (mode_name, slots, len(w["q"]), small_cap))
-    got = _serve(messi, w["ix"], w["q"], w["ks"], mode, 4 << 30, slots, 0.002)
+    got = _serve(messi, ix, w["q"], w["ks"], mode, 4 << 30, slots, 0.002)
+    if small_cap:
+        ix.close()
     assert len(got) == len(w["q"])
     for i in range(len(w["q"])):
         r = got[i]
