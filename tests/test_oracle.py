@@ -337,6 +337,78 @@ def test_d64_definition(oracle_mod):
     assert abs(oracle_mod.d64(a, c) - ref) <= 256 * 2.0 ** -53 * ref
 
 
+def _d64_variants(q, x):
+    """Plausible ways to get D64 wrong, computed with exact rationals and
+    correct rounding: a fused multiply-add per term, a pairwise (adjacent)
+    tree, and the sequential sum taken backwards."""
+    from fractions import Fraction
+    d = [float(a) - float(b) for a, b in zip(q.astype(np.float64), x.astype(np.float64))]
+    fma = 0.0
+    for v in d:
+        fma = float(Fraction(fma) + Fraction(v) * Fraction(v))  # one rounding per term
+    terms = [v * v for v in d]
+    while len(terms) > 1:
+        terms = [terms[i] + terms[i + 1] if i + 1 < len(terms) else terms[i] for i in range(0, len(terms), 2)]
+    rev = 0.0
+    for v in reversed(d):
+        rev = rev + v * v
+    return {"fma": fma, "pairwise": terms[0], "reversed": rev}
+
+
+def test_d64_sequential_without_fma(oracle_mod):
+    # D64 adds the squared differences in index order, the product and the
+    # sum each rounded to fp64.  Worked by hand:
+    #   j = 0: d = 128           -> s = 2^14
+    #   j = 1: d = 2^-19         -> s = 2^14 + 2^-38 (one unit in the last place at 2^14)
+    #   j = 2: d = 1 - 2^-40 (fp32 1 minus fp32 2^-40; exact in fp64)
+    #          d^2 = 1 - 2^-39 + 2^-80 rounds to 1 - 2^-39, and
+    #          2^14 + 2^-38 + 1 - 2^-39 = 16385 + 2^-39 lies halfway between
+    #          16385 (even last bit) and 16385 + 2^-38: ties to even -> 16385.
+    # A fused multiply-add keeps the 2^-80 and rounds up to 16385 + 2^-38.
+    q = np.array([128.0, 2.0 ** -19, 1.0], dtype=np.float32)
+    x = np.array([0.0, 0.0, 2.0 ** -40], dtype=np.float32)
+    assert oracle_mod.d64(q, x) == 16385.0
+    v = _d64_variants(q, x)
+    assert v["fma"] == 16385.0 + 2.0 ** -38
+    # the order: 1 followed by 255 terms of 2^-54 (a quarter unit of 1): in
+    # index order each rounds away and the sum stays exactly 1; a pairwise
+    # tree or the reverse order keeps them (255 * 2^-54 ~ 2^-46)
+    q2 = np.concatenate([[1.0], np.full(255, 2.0 ** -27)]).astype(np.float32)
+    x2 = np.zeros(256, dtype=np.float32)
+    assert oracle_mod.d64(q2, x2) == 1.0
+    v2 = _d64_variants(q2, x2)
+    assert v2["pairwise"] > 1.0 and v2["reversed"] > 1.0 and v2["fma"] == 1.0
+
+
+def test_znorm_fold_halving_fp64_order(oracle_mod):
+    # z-norm sums in fp64 in fold-halving order.  Worked by hand for
+    # x = [2^60, 1, -2^60, 1] (fp32 values, spread beyond fp64's 53 bits):
+    #   fold-halving: (2^60 + -2^60) + (1 + 1) = 2 -> mean 0.5
+    #   (left to right gives 1 -> 0.25; adjacent pairs give 0 -> 0)
+    #   c = x - 0.5 = [2^60, 0.5, -2^60, 0.5] (2^60 - 0.5 rounds to 2^60)
+    #   c^2 folded: (2^120 + 2^120) + (0.25 + 0.25) = 2^121 -> variance 2^119
+    #   z_1 = fl32(0.5 / 2^59.5) = fl32(2^-60.5), z_0 = fl32(fl64(2^60 / fl64(2^59.5)))
+    x = np.array([[2.0 ** 60, 1.0, -(2.0 ** 60), 1.0]], dtype=np.float32)
+    z = oracle_mod.znorm(x)[0]
+    sigma = math.sqrt(2.0 ** 119)
+    assert z[1] == np.float32(0.5 / sigma) and z[3] == z[1]
+    assert z[0] == np.float32(2.0 ** 60 / sigma) and z[2] == -z[0]
+    # the other orders' means would give c_1 = 0.75 or 1.0 instead
+    assert z[1] != np.float32(0.75 / sigma) and z[1] != np.float32(1.0 / sigma)
+    # the same within a longer row: zero padding to a power of two (L = 6 -> 8)
+    # folds element j onto j + 4: (2^60 + -2^60), (1 + 0), (1 + 0), (0 + 0) -> 2
+    y = np.array([[2.0 ** 60, 1.0, 1.0, 0.0, -(2.0 ** 60), 0.0]], dtype=np.float32)
+    zy = oracle_mod.znorm(y)[0]
+    mean = 2.0 / 6.0
+    c = [2.0 ** 60 - mean, 1.0 - mean, 1.0 - mean, -mean, -(2.0 ** 60) - mean, -mean]
+    cc = [v * v for v in c] + [0.0, 0.0]
+    while len(cc) > 1:
+        h = len(cc) // 2
+        cc = [cc[i] + cc[i + h] for i in range(h)]
+    sig = math.sqrt(cc[0] / 6.0)
+    assert zy[1] == np.float32(c[1] / sig) and zy[3] == np.float32(c[3] / sig)
+
+
 def test_mindist_lower_bounds_ed_all_pairs(oracle_mod, datagen_mod):
     L, w, b = 256, 16, 8
     z = oracle_mod.znorm(datagen_mod.random_walks(1500, L, seed=10))
