@@ -135,8 +135,11 @@ typedef struct {
     /* FP32 mode: device time after the first scan pass (candidate fix-up,
        the second pass when needed); ms_scan is then the first pass alone */
     double ms_fixup;
-    /* BF16 mode: queries of a leaf staged in LDS at a time by the filter */
+    /* BF16 mode: queries of a leaf staged in LDS at a time by the filter, and
+       the most queries any leaf had in one round (above the former, the
+       filter stages a leaf's queries in several turns) */
     int32_t bf16_stage_queries;
+    int32_t bf16_max_leaf_queries;
 } messi_knn_stats;
 
 /* ---- index ------------------------------------------------------------- */

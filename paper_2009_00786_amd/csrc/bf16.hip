@@ -182,12 +182,13 @@ __device__ __forceinline__ bool round_leaf(const QArgs& a, int q, uint32_t t, ui
 }
 
 // The round's counters: [0] filter survivors, [1] next active leaf of the
-// filter, [2] active leaves, [3] query slots handed out.  Words, not a memset,
-// so that the whole round can be recorded in a graph.
+// filter, [2] active leaves, [3] query slots handed out; and for the call,
+// [4] the most queries any leaf had in a round (cleared by the first round).
+// Words, not a memset, so that the whole round can be recorded in a graph.
 __global__ void __launch_bounds__(256) round_reset_kernel(uint32_t* __restrict__ leaf_cnt, uint32_t nL,
-                                                          uint32_t* __restrict__ ctr) {
+                                                          uint32_t* __restrict__ ctr, int first) {
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nL; i += gridDim.x * 256) leaf_cnt[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x < 4) ctr[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < (first ? 5 : 4)) ctr[threadIdx.x] = 0;
 }
 
 // Count the queries of every leaf; the first query to reach a leaf appends it
@@ -213,6 +214,7 @@ __global__ void __launch_bounds__(256) leaf_offsets_kernel(const uint32_t* __res
         const uint32_t leaf = leaf_act[i];
         leaf_off[leaf] = atomicAdd(&ctr[3], leaf_cnt[leaf]);
         leaf_cur[leaf] = 0;
+        atomicMax(&ctr[4], leaf_cnt[leaf]);
     }
 }
 
@@ -645,7 +647,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         MESSI_TRY(ws->grow(ix, ws->leaf_cur, sizeof(uint32_t) * (nL + 1)));
         MESSI_TRY(ws->grow(ix, ws->leaf_q, sizeof(uint32_t) * leafq_cap));
         MESSI_TRY(ws->grow(ix, ws->pairs, sizeof(uint2) * pairs_cap));
-        MESSI_TRY(ws->grow(ix, ws->npairs, sizeof(uint32_t) * 4));
+        MESSI_TRY(ws->grow(ix, ws->npairs, sizeof(uint32_t) * 8));
         MESSI_TRY(ws->grow(ix, ws->leaf_act, sizeof(uint32_t) * (nL + 1)));
         ws->bf_nq = nq;
         ++ws->gen;
@@ -707,7 +709,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         const unsigned tbr = (unsigned)((t1 - t0 + 255) / 256);
         const uint32_t r0 = (uint32_t)t0, r1 = (uint32_t)t1;
         hipLaunchKernelGGL(round_reset_kernel, dim3((unsigned)std::min<size_t>((nL + 255) / 256, 1024)), dim3(256), 0,
-                           s, ws->leaf_cnt.as<uint32_t>(), (uint32_t)nL, ws->npairs.as<uint32_t>());
+                           s, ws->leaf_cnt.as<uint32_t>(), (uint32_t)nL, ws->npairs.as<uint32_t>(), round == 0);
         MESSI_LAUNCH_CHECK("round_reset");
         hipLaunchKernelGGL(leaf_count_kernel, dim3(tbr, nq), dim3(256), 0, s, a, r0, r1, ws->leaf_cnt.as<uint32_t>(),
                            ws->leaf_act.as<uint32_t>(), ws->npairs.as<uint32_t>());
@@ -732,8 +734,12 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     }
     ws->bf_rounds = rounds_run;
     ws->bf_ms_filter = ws->bf_ms_recheck = 0;
+    ws->bf_max_leaf_q = 0;
     if (timing) {
+        uint32_t ctr[8];
+        MESSI_HIP_TRY(hipMemcpyAsync(ctr, ws->npairs.p, sizeof(ctr), hipMemcpyDeviceToHost, s));
         MESSI_HIP_TRY(hipStreamSynchronize(s));
+        ws->bf_max_leaf_q = (int)ctr[4];
         for (size_t i = 0; i + 2 < evs.size(); i += 3) {
             float f = 0, r = 0;
             MESSI_HIP_TRY(hipEventElapsedTime(&f, evs[i], evs[i + 1]));

@@ -153,7 +153,7 @@ struct Workspace {
     DevBuf qb, qnorm, qx, leaf_cnt, leaf_off, leaf_cur, leaf_q, leaf_act, pairs, npairs;
     // timing of the BF16 kernels of the last call (filled when timing is on)
     double bf_ms_filter = 0, bf_ms_recheck = 0;
-    int bf_rounds = 0, bf_stage_queries = 0;
+    int bf_rounds = 0, bf_stage_queries = 0, bf_max_leaf_q = 0;
     // statistics read-back: phase events and pinned staging, made on first use
     hipEvent_t ev[8] = {};
     QCounters* h_counters = nullptr;

@@ -2658,6 +2658,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
             stats->ms_bf16_recheck = ws->bf_ms_recheck;
             stats->bf16_rounds = ws->bf_rounds;
             stats->bf16_stage_queries = ws->bf_stage_queries;
+            stats->bf16_max_leaf_queries = ws->bf_max_leaf_q;
             stats->bf16_flops = (int64_t)hc.distance * 2 * Lp;
             stats->scan_launches = ws->bf_rounds;
         }

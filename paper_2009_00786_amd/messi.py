@@ -82,7 +82,7 @@ class KnnStats(ctypes.Structure):
                 ("scan_ms_block_max", ctypes.c_double), ("ms_bf16_filter", ctypes.c_double),
                 ("ms_bf16_recheck", ctypes.c_double), ("bf16_flops", ctypes.c_int64), ("bf16_rounds", ctypes.c_int32),
                 ("reruns", ctypes.c_int32), ("fallbacks", ctypes.c_int32), ("ms_fixup", ctypes.c_double),
-                ("bf16_stage_queries", ctypes.c_int32)]
+                ("bf16_stage_queries", ctypes.c_int32), ("bf16_max_leaf_queries", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):

@@ -221,3 +221,79 @@ def test_row_filter_ties_and_unnormalised(torch_cuda, messi, oracle_mod):
         gi, gd, _ = _one_by_one(ix, q, k, torch, messi.MODE_BF16)
         _check(gi, gd, oidx, od)
     ix.close()
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_bf16_batch_of_1024_with_crowded_leaves(tiny_bf16, oracle_mod, datagen_mod, torch_cuda, messi, k):
+    """The batched workload's shape: one call of 1024 queries, half fresh
+    walks and half dataset rows plus noise -- here 3 rows with 300 noisy copies
+    each, so that a leaf is visited by more queries than the filter stages at
+    once and it stages that leaf's queries in several turns."""
+    w = tiny_bf16
+    fresh = oracle_mod.znorm(datagen_mod.random_walks(100, 256, seed=datagen_mod.SEED_QUERY,
+                                                      stream=datagen_mod.STREAM_QUERY, row0=4000))
+    base = datagen_mod.uniform_ints(3, 100_000, 33, 7)
+    rows = np.repeat(base, 300)
+    sig = np.where(np.arange(900) % 10 == 9, 0.1, 0.01)
+    crowd = datagen_mod.add_noise(w["z"][rows], sig, row0=7000)
+    more = datagen_mod.add_noise(w["z"][datagen_mod.uniform_ints(24, 100_000, 34, 7)],
+                                 [(0.01, 0.1, 1.0)[i % 3] for i in range(24)], row0=9000)
+    q = np.concatenate([fresh, crowd, more]).astype(np.float32)
+    assert len(q) == 1024
+    _say("bf16 batch of 1024 (900 around 3 rows), k=%d" % k)
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], q, k, nthreads=16)
+    gi, gd, st = w["ix"].knn(torch_cuda.from_numpy(q).cuda(), k, mode=messi.MODE_BF16, stats=True)
+    _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    _say("  staged per turn %d, most queries on a leaf %d, fallbacks %d" % (
+        st["bf16_stage_queries"], st["bf16_max_leaf_queries"], st["fallbacks"]))
+    assert st["bf16_max_leaf_queries"] > st["bf16_stage_queries"]
+
+
+# ---------------------------------------------------------------------------
+# the Gaussian-mixture collection (L = 128, integer rows, then z-normalised)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def mixture128(torch_cuda, messi, datagen_mod, oracle_mod):
+    """100,000 rows of length 128 from the mixture of 1000 clusters (centres
+    U[0,255], sigma 20, clipped and rounded to integers), z-normalised;
+    16 segments (m = 8), 8 bits, leaf capacity 2000.  Queries: dataset rows
+    plus noise (sigma cycling 0.01, 0.1, 1) and fresh mixture draws."""
+    torch = torch_cuda
+    cen = datagen_mod.mixture_centres(1000, 128)
+    x = datagen_mod.mixture(100_000, 128, cen)
+    z = oracle_mod.znorm(x)
+    t = torch.from_numpy(x).cuda()
+    ix = messi.Index(t, 16, 8, 2000, znorm=True, bf16_shadow=True)
+    np.testing.assert_array_equal(t.cpu().numpy(), z)
+    fresh = oracle_mod.znorm(datagen_mod.mixture(12, 128, cen, seed=datagen_mod.SEED_QUERY,
+                                                 stream=datagen_mod.STREAM_QUERY))
+    rows = datagen_mod.uniform_ints(12, 100_000, 41, 7)
+    noisy = datagen_mod.add_noise(z[rows], [(0.01, 0.1, 1.0)[i % 3] for i in range(12)])
+    q = np.empty((24, 128), dtype=np.float32)
+    q[0::2], q[1::2] = fresh, noisy
+    yield {"z": z, "ix": ix, "q": q}
+    ix.close()
+
+
+def test_mixture_words_and_leaves(mixture128, oracle_mod):
+    w = mixture128
+    words = oracle_mod.words(w["z"], 16, 8)
+    np.testing.assert_array_equal(w["ix"].export_words(), words)
+    ol, op = oracle_mod.build_leaves(words, 8, 2000)
+    gl, gp = w["ix"].export_leaves()
+    np.testing.assert_array_equal(gl.view(np.uint8), ol.view(np.uint8))
+    np.testing.assert_array_equal(gp, op)
+
+
+@pytest.mark.parametrize("mode_name", ["FP32", "BF16"])
+def test_mixture_knn_matches_oracle(mixture128, oracle_mod, torch_cuda, messi, mode_name):
+    w = mixture128
+    mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
+    k = 10
+    _say("mixture 100000 x 128, %s, k=%d: batched and one at a time" % (mode_name, k))
+    oidx, od, _ = oracle_mod.knn_brute(w["z"], w["q"], k, nthreads=16)
+    gi, gd = w["ix"].knn(torch_cuda.from_numpy(w["q"]).cuda(), k, mode=mode)
+    _check(gi.cpu().numpy(), gd.cpu().numpy(), oidx, od)
+    si, sd, _ = _one_by_one(w["ix"], w["q"], k, torch_cuda, mode)
+    _check(si, sd, oidx, od)

@@ -2,8 +2,14 @@
 fp32 in HBM), 16 segments, 8-bit symbols, leaf capacity 2000 -- the index the
 benchmark builds, in the same launch configuration.
 
-The oracle cannot hold the collection, so it checks sampled outputs one by one
-and properties that hold at any size:
+The complete comparison (test_fullsize_against_oracle): the raw collection is
+regenerated chunk by chunk, z-normalised and summarised by the oracle on the
+host (every word compared), the oracle partitions all 100M words (every leaf
+record and the whole position array compared), and the oracle's brute force
+over all 100M rows answers the 100 queries the benchmark times (one at a time
+on the GPU, exact 1-NN): indices bit-exact, distances those of fp64.
+
+Beyond that, sampled outputs and properties that hold at any size:
   * iSAX words of 4096 random rows, each regenerated on the host and
     z-normalised and summarised by the oracle: bit-exact;
   * the leaves partition the collection (every series once, ranges
@@ -15,6 +21,10 @@ and properties that hold at any size:
     the oracle's canonical fp64 distances of the returned rows, no row of a
     1M-row block beats the returned k-th distance, and the BF16 batch returns
     the same answers as the FP32 single-query path, bit for bit."""
+import concurrent.futures
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -138,3 +148,69 @@ def test_fullsize_knn(full, datagen_mod, oracle_mod, messi, torch_cuda, k):
         # a global answer that lies in the block is among the block's own k best
         for j in np.nonzero(inside)[0]:
             assert idx[i, j] in bi_[i]
+
+
+def _host_threads():
+    """The host share a one-GPU job gets (16 threads), fewer on a smaller host."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def test_fullsize_against_oracle(full, datagen_mod, oracle_mod, messi, torch_cuda):
+    """Words, leaves and the 100 benchmark queries' answers at 100M x 256,
+    all against the oracle (see the module docstring)."""
+    torch = torch_cuda
+    ix = full["ix"]
+    nth = _host_threads()
+    pool = concurrent.futures.ThreadPoolExecutor(nth)
+    qraw = datagen_mod.random_walks(100, L, seed=datagen_mod.SEED_QUERY, stream=datagen_mod.STREAM_QUERY)
+    qz = oracle_mod.znorm(qraw)
+    # the GPU side: the benchmark's calls, one query at a time
+    _say("full size: 100 benchmark queries, one at a time on the GPU")
+    qt = torch.from_numpy(qraw).cuda()
+    messi.znorm_(qt)
+    np.testing.assert_array_equal(qt.cpu().numpy(), qz)
+    gi = np.zeros((100, 1), dtype=np.int64)
+    gd = np.zeros((100, 1), dtype=np.float32)
+    for i in range(100):
+        a, b = ix.knn_plain(qt[i:i + 1].contiguous(), 1)
+        gi[i], gd[i] = a.cpu().numpy()[0], b.cpu().numpy()[0]
+    words_gpu = ix.export_words()
+    # the oracle side, chunk by chunk
+    best_d = np.full(100, np.inf)
+    best_i = np.full(100, -1, dtype=np.int64)
+    owords = np.empty((N, 16), dtype=np.uint8)
+    raw_dev = torch.empty((CHUNK, L), dtype=torch.float32, device="cuda")
+    t0 = time.time()
+    for r0 in range(0, N, CHUNK):
+        datagen_mod.gpu_random_walks(raw_dev, row0=r0)  # the seeded generator (not the library)
+        raw = raw_dev.cpu().numpy()
+        pieces = np.array_split(np.arange(CHUNK), nth)
+        zs = list(pool.map(lambda ix_: oracle_mod.znorm(raw[ix_[0]:ix_[-1] + 1]), pieces))
+        z = np.concatenate(zs)
+        del zs, raw
+        ws = list(pool.map(lambda zz: oracle_mod.words(zz, 16, 8), np.array_split(z, nth)))
+        owords[r0:r0 + CHUNK] = np.concatenate(ws)
+        np.testing.assert_array_equal(words_gpu[r0:r0 + CHUNK], owords[r0:r0 + CHUNK])
+        bi, bd, _ = oracle_mod.knn_brute(z, qz, 1, nthreads=nth, row_offset=r0)
+        better = (bd[:, 0] < best_d) | ((bd[:, 0] == best_d) & (bi[:, 0] < best_i))
+        best_d = np.where(better, bd[:, 0], best_d)
+        best_i = np.where(better, bi[:, 0], best_i)
+        del z
+        _say("  oracle rows %d..%d: words equal, brute force merged (%.0f s)" % (r0, r0 + CHUNK, time.time() - t0))
+    del raw_dev
+    pool.shutdown()
+    np.testing.assert_array_equal(gi[:, 0], best_i)
+    np.testing.assert_array_equal(gd[:, 0], np.sqrt(best_d).astype(np.float32))
+    _say("full size: 100 answers equal the oracle's brute force; partitioning 100M words on the host")
+    oleaves, opos = oracle_mod.build_leaves(owords, 8, 2000)
+    del owords
+    gleaves, gpos = ix.export_leaves()
+    assert len(gleaves) == len(oleaves)
+    np.testing.assert_array_equal(gleaves.view(np.uint8), oleaves.view(np.uint8))
+    np.testing.assert_array_equal(gpos, opos)
+    _say("full size: %d leaves and the position array equal the oracle's (%.0f s)" % (len(oleaves),
+                                                                                   time.time() - t0))
