@@ -102,6 +102,8 @@ typedef struct {
     uint64_t device_bytes;   /* device memory the index owns */
     float data_absmax;       /* max |x| over the collection (used for the bound's slack) */
     double ms_znorm, ms_summarize, ms_bucket, ms_split, ms_finalize, ms_shadow, ms_total;
+    int32_t fine_segments;   /* segments of the fine summary the search reads before a row (0: none) */
+    int32_t fine_length;     /* values per fine segment */
 } messi_info;
 
 /* Per-call counters and timings of messi_knn_ex (totals over the call's queries).
@@ -110,7 +112,7 @@ typedef struct {
     int64_t leaves_total;     /* n_leaves * nq */
     int64_t leaves_kept;      /* (query, leaf) pairs whose bound did not exceed the first upper bound */
     int64_t leaves_scanned;   /* pairs whose members were examined */
-    int64_t series_bounded;   /* per-series lower bounds computed */
+    int64_t series_bounded;   /* per-series lower bounds computed (coarse words in the ordered scan) */
     int64_t series_distance;  /* fp32 distances (FP32 mode) or BF16 filter evaluations (BF16 mode) */
     int64_t series_abandoned; /* fp32 distances stopped early */
     int64_t series_recheck;   /* BF16 mode: compensated fp32 rechecks */
@@ -140,6 +142,15 @@ typedef struct {
        filter stages a leaf's queries in several turns) */
     int32_t bf16_stage_queries;
     int32_t bf16_max_leaf_queries;
+    /* ordered scan: members whose full word was bounded (those that passed
+       their coarse word's bound; series_bounded counts the coarse bounds),
+       and members bounded by their fine summary (those that passed the word
+       bound, when the index has a fine summary) */
+    int64_t series_word_bounded;
+    int64_t series_fine_bounded;
+    /* FP32 mode, calls of one query: device time of the scan's first kernel
+       (coarse-word and word bounds), within ms_scan */
+    double ms_scan_coarse;
 } messi_knn_stats;
 
 /* ---- index ------------------------------------------------------------- */

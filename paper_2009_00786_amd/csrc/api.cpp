@@ -87,6 +87,8 @@ static void fill_info(Index* ix) {
     in.has_bf16 = ix->shadow.p != nullptr;
     in.device_bytes = ix->device_bytes();
     in.data_absmax = ix->absmax;
+    in.fine_segments = ix->wf;
+    in.fine_length = ix->mf;
 }
 
 // Take over everything src holds (src keeps dst's old buffers, to be freed).
@@ -100,10 +102,12 @@ static void adopt(Index* dst, Index* src) {
     std::swap(dst->split_mask, src->split_mask);
     std::swap(dst->n_inner, src->n_inner);
     std::swap(dst->info, src->info);
+    std::swap(dst->wf, src->wf);
+    std::swap(dst->mf, src->mf);
     DevBuf* a[] = {&dst->words, &dst->pos, &dst->leaves, &dst->bp, &dst->sx, &dst->shadow, &dst->split_keys,
-                   &dst->split_seg, &dst->split_claim};
+                   &dst->split_seg, &dst->split_claim, &dst->cwords, &dst->fwords};
     DevBuf* b[] = {&src->words, &src->pos, &src->leaves, &src->bp, &src->sx, &src->shadow, &src->split_keys,
-                   &src->split_seg, &src->split_claim};
+                   &src->split_seg, &src->split_claim, &src->cwords, &src->fwords};
     for (size_t i = 0; i < sizeof(a) / sizeof(a[0]); ++i) {
         DevBuf t = std::move(*a[i]);
         *a[i] = std::move(*b[i]);

@@ -404,6 +404,7 @@ struct SegArgs {
     uint16_t* keys;         // [n]
     uint32_t* absmax;       // float bits, atomicMax
     int* nonfinite;
+    uint8_t* fine;          // [n][kFineStride] fine summary (nullptr: none); m a power of two
 };
 
 template <int M, int R, bool VEC>
@@ -425,6 +426,14 @@ __global__ void __launch_bounds__(256) summarize_seg_kernel(SegArgs a) {
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const float inv_m = 1.0f / (float)m;
     const bool pow2_m = (m & (m - 1)) == 0;
+    // symbol of a PAA value: a first guess from its cell, corrected by one comparison each way
+    auto symbol = [&](float p) -> int {
+        const float cf = fminf(fmaxf(__fmul_rn(__fadd_rn(p, 8.0f), 256.0f), 0.0f), (float)(kCells - 1));
+        int s = s_cell[(int)cf];
+        if (s > 0 && s_bp[s] > p) --s;
+        else if (s < A - 1 && s_bp[s + 1] <= p) ++s;
+        return s;
+    };
     uint32_t amax_bits = 0;
     for (int64_t blk0 = wave_id * R; blk0 < n_blocks; blk0 += n_waves * R) {
         float v[R][M];
@@ -452,6 +461,30 @@ __global__ void __launch_bounds__(256) summarize_seg_kernel(SegArgs a) {
 #pragma unroll
             for (int k = 0; k < M; ++k) mx = max(mx, __float_as_uint(v[r][k]) & 0x7fffffffu);
             amax_bits = max(amax_bits, mx);
+            if (a.fine != nullptr) {
+                // the fine summary (m == M here): F sub-segments of MF values,
+                // each summed by fold-halving and scaled, and their symbols
+                constexpr int F = M >= 4 ? 4 : M;
+                constexpr int MF = M / F;
+                uint32_t packed = 0;
+#pragma unroll
+                for (int t = 0; t < F; ++t) {
+                    float f[MF];
+#pragma unroll
+                    for (int i = 0; i < MF; ++i) f[i] = v[r][t * MF + i];
+#pragma unroll
+                    for (int h = MF / 2; h >= 1; h /= 2)
+#pragma unroll
+                        for (int i = 0; i < h; ++i) f[i] = __fadd_rn(f[i], f[i + h]);
+                    packed |= (uint32_t)symbol(__fmul_rn(f[0], 1.0f / (float)MF)) << (8 * t);
+                }
+                uint8_t* dst = a.fine + (size_t)row * kFineStride + seg * F;
+                if (live) {
+                    if (F == 4) *reinterpret_cast<uint32_t*>(dst) = packed;
+                    else if (F == 2) *reinterpret_cast<uint16_t*>(dst) = (uint16_t)packed;
+                    else *dst = (uint8_t)packed;
+                }
+            }
             // fold-halving over the (zero-padded) segment
 #pragma unroll
             for (int h = M / 2; h >= 1; h /= 2) {
@@ -459,10 +492,7 @@ __global__ void __launch_bounds__(256) summarize_seg_kernel(SegArgs a) {
                 for (int k = 0; k < h; ++k) v[r][k] = __fadd_rn(v[r][k], v[r][k + h]);
             }
             const float p = pow2_m ? __fmul_rn(v[r][0], inv_m) : __fdiv_rn(v[r][0], (float)m);
-            const float cf = fminf(fmaxf(__fmul_rn(__fadd_rn(p, 8.0f), 256.0f), 0.0f), (float)(kCells - 1));
-            int s = s_cell[(int)cf];
-            if (s > 0 && s_bp[s] > p) --s;
-            else if (s < A - 1 && s_bp[s + 1] <= p) ++s;
+            const int s = symbol(p);
             if (live) a.words[(size_t)row * 16 + seg] = (uint8_t)s;
             const uint64_t top = dev::ballot(lane_on && ((s >> (a.b - 1)) & 1));
             if (live && seg == 0) {
@@ -521,6 +551,81 @@ void cell_table(const float* bp, int card_bits, uint8_t* cells) {
         int cnt = 0;
         for (int j = 0; j < nb; ++j) cnt += bp[j] <= x;
         cells[c] = (uint8_t)cnt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fine summary on its own (builds whose summarise pass does not produce it:
+// z-normalisation fused into the summary): one thread per (row, fine
+// segment) of MF values, summed by fold-halving and scaled; the symbol by
+// binary search over the breakpoints.
+// ---------------------------------------------------------------------------
+template <int MF>
+__global__ void __launch_bounds__(256) fine_kernel(const float* __restrict__ in, int64_t n, int L, int wf,
+                                                   const float* __restrict__ bp, int b, uint8_t* __restrict__ fine) {
+    __shared__ float s_bp[256];
+    const int A = 1 << b;
+    for (int i = threadIdx.x; i < A - 1; i += blockDim.x) s_bp[i] = bp[i];
+    __syncthreads();
+    const int64_t total = n * (int64_t)wf;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = id / wf;
+        const int j = (int)(id - row * wf);
+        const float* src = in + (size_t)row * (size_t)L + (size_t)j * MF;
+        float f[MF];
+#pragma unroll
+        for (int i = 0; i < MF; ++i) f[i] = src[i];
+#pragma unroll
+        for (int h = MF / 2; h >= 1; h /= 2)
+#pragma unroll
+            for (int i = 0; i < h; ++i) f[i] = __fadd_rn(f[i], f[i + h]);
+        const float p = __fmul_rn(f[0], 1.0f / (float)MF);
+        int lo = 0, hi = A - 1;  // the number of breakpoints <= p
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_bp[mid - 1] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        fine[(size_t)row * kFineStride + j] = (uint8_t)lo;
+    }
+}
+
+int launch_fine(const float* in, int64_t n, int L, int wf, int mf, const float* bp, int b, uint8_t* fine,
+                hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>((n * wf + 255) / 256, 16 * (int64_t)device_cu_count());
+    switch (mf) {
+#define MESSI_FINE_CASE(MM) \
+    case MM: hipLaunchKernelGGL(fine_kernel<MM>, dim3(blocks), dim3(256), 0, s, in, n, L, wf, bp, b, fine); break;
+        MESSI_FINE_CASE(1)
+        MESSI_FINE_CASE(2)
+        MESSI_FINE_CASE(4)
+        MESSI_FINE_CASE(8)
+        MESSI_FINE_CASE(16)
+#undef MESSI_FINE_CASE
+        default:
+            set_error(MESSI_EINVAL, "fine segments of more than 16 values are not built");
+            return MESSI_EINVAL;
+    }
+    MESSI_LAUNCH_CHECK("fine");
+    return MESSI_OK;
+}
+
+// Coarse words in leaf order: each symbol cut to its top min(b, 4) bits (a
+// shift by sh = b - min(b, 4)), segments 2j and 2j + 1 in byte j.
+__global__ void __launch_bounds__(256) coarse_kernel(const uint4* __restrict__ words, int64_t n, int sh,
+                                                     uint2* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 wv = words[i];
+        const uint32_t in[4] = {wv.x, wv.y, wv.z, wv.w};
+        uint32_t o[2] = {0u, 0u};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t hi = (in[j >> 1] >> (16 * (j & 1))) & 255u;      // segment 2j
+            const uint32_t lo = (in[j >> 1] >> (16 * (j & 1) + 8)) & 255u;  // segment 2j + 1
+            o[j >> 2] |= (((hi >> sh) << 4) | (lo >> sh)) << (8 * (j & 3));
+        }
+        out[i] = make_uint2(o[0], o[1]);
     }
 }
 
@@ -1159,6 +1264,12 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     a.nonfinite = reinterpret_cast<int*>(cnt + 0);
     if (w < 16) MESSI_HIP_TRY(hipMemsetAsync(W[0].p, 0, sizeof(uint4) * (size_t)n, s));
     const bool seg_path = !opts.znorm && a.m <= 64;
+    // the fine summary: F sub-segments per segment (none unless m is a power of two in [2, 64])
+    const int fF = fine_per_segment(a.m);
+    ix->wf = fF ? w * fF : 0;
+    ix->mf = fF ? a.m / fF : 0;
+    ix->fwords.release();
+    if (ix->wf) MESSI_TRY(ix->fwords.alloc((size_t)kFineStride * (size_t)n));
     DevBuf cells;
     if (seg_path) {
         uint8_t hc[kCells];
@@ -1183,6 +1294,7 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
         sa.keys = K[0].as<uint16_t>();
         sa.absmax = cnt + 1;
         sa.nonfinite = reinterpret_cast<int*>(cnt + 0);
+        sa.fine = ix->wf ? ix->fwords.as<uint8_t>() : nullptr;
         MESSI_TRY(launch_summarize_seg(sa, s));
     } else {
         MESSI_TRY((launch_summarize<false, true>(a, r.E, s)));
@@ -1196,6 +1308,12 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
         return MESSI_EINVAL;
     }
     memcpy(&ix->absmax, &flags[1], sizeof(float));
+    if (ix->wf && !seg_path) {
+        // the summarise pass that ran does not write the fine summary: a pass of its own
+        tm.start();
+        MESSI_TRY(launch_fine(series, n, len, ix->wf, ix->mf, ix->bp.as<float>(), b, ix->fwords.as<uint8_t>(), s));
+        ix->info.ms_summarize += tm.stop_ms();
+    }
 
     // ---- 2. bucket by root key (stable LSD radix, 8-bit digits)
     tm.start();
@@ -1390,6 +1508,10 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     hipLaunchKernelGGL(leaf_order_kernel, dim3((n_leaves + 255) / 256), dim3(256), 0, s, leaves_raw.as<Leaf>(),
                        n_leaves, bm.as<uint32_t>(), rank.as<uint32_t>(), ix->leaves.as<Leaf>());
     MESSI_LAUNCH_CHECK("leaf_order");
+    MESSI_TRY(ix->cwords.alloc(sizeof(uint2) * (size_t)n));
+    hipLaunchKernelGGL(coarse_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 16 * (int64_t)device_cu_count())),
+                       dim3(256), 0, s, W[fin].as<uint4>(), n, b - std::min(b, 4), ix->cwords.as<uint2>());
+    MESSI_LAUNCH_CHECK("coarse");
     MESSI_HIP_TRY(hipStreamSynchronize(s));
     ix->info.ms_finalize = tm.stop_ms();
 

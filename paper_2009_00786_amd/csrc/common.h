@@ -89,6 +89,16 @@ static_assert(sizeof(Leaf) == 40, "leaf layout");
 
 // ---- the index -------------------------------------------------------------
 
+// Row stride in bytes of the fine summaries (at most 64 segments).
+constexpr int kFineStride = 64;
+
+// Fine summary of an index of segment length m: F = min(4, m) fine segments
+// per segment when m is a power of two in [2, 64], else none.
+inline int fine_per_segment(int m) {
+    if (m < 2 || m > 64 || (m & (m - 1)) != 0) return 0;
+    return m < 4 ? m : 4;
+}
+
 struct Index {
     int device = 0;
     const float* series = nullptr;  // borrowed, [n][len]
@@ -104,6 +114,12 @@ struct Index {
     DevBuf bp;      // float [2^b - 1] breakpoints
     DevBuf sx;      // uint2 [n]: BF16 (|x| up, beta high, beta low, 0) per member, leaf order (bf16 shadow only)
     DevBuf shadow;  // bf16 [n][len] rows in leaf order (bf16 shadow only)
+    // Summaries the search reads before a member's word and before its row:
+    DevBuf cwords;  // uint2 [n], leaf order: the word's symbols cut to their top 4 bits, two per byte
+                    //   (byte j = segment 2j in the high nibble, 2j + 1 in the low one)
+    DevBuf fwords;  // uint8 [n][kFineStride], input order: symbols of the PAA over wf segments of
+                    //   mf values (empty when wf == 0)
+    int32_t wf = 0, mf = 0;  // fine segments and their length (wf * mf == len), 0: no fine summary
     // the partition's internal nodes and their split segments, as an
     // open-addressing table keyed by (card, prefix): appends keep these splits
     DevBuf split_keys;   // uint4 [2][slots]: card bytes, prefix bytes
@@ -117,7 +133,8 @@ struct Index {
     messi_opts opts{};  // as given to the build, defaults filled in (search mode, budgets, scan chunk, ...)
 
     uint64_t device_bytes() const {
-        return words.bytes + pos.bytes + leaves.bytes + bp.bytes + sx.bytes + shadow.bytes;
+        return words.bytes + pos.bytes + leaves.bytes + bp.bytes + sx.bytes + shadow.bytes + cwords.bytes +
+               fwords.bytes;
     }
     ~Index();
 };

@@ -15,6 +15,7 @@ inline int approx_blocks(int nq) { return nq <= 2 ? 512 : nq <= 8 ? 256 : 128; }
 constexpr int kMaxFinal = 4096;      // candidates ordered by fp64 distance per query
 constexpr int kChunk = 1024;         // most members per scan work unit (the index's scan_chunk: 256, 512 or 1024)
 constexpr int kHistBins = 4096;      // candidate-distance histogram (k > 1 bound)
+constexpr int kSplitMaxQ = 1;        // calls of at most this many queries run the split Euclidean scan
 
 // Relative error margins (see the exactness notes in query.hip).
 constexpr float kRhoEd = 1.52587890625e-05f;  // 2^-16, fp32 squared-distance error margin
@@ -41,10 +42,11 @@ struct LbPart {
     uint32_t pad;
 };
 
-// Scan statistics per block: scanned leaves, bounded members, members that
-// reached the distance stage, abandoned, bytes read x 16, fp32 distances after
-// a BF16 row test, BF16 rows tested.
-constexpr int kBlkCnt = 7;
+// Scan statistics per block: scanned leaves, members bounded by their coarse
+// word, members that reached the distance stage, abandoned, bytes read, fp32
+// distances after a BF16 row test, BF16 rows tested, members bounded by their
+// full word, members bounded by their fine summary.
+constexpr int kBlkCnt = 9;
 
 // Per-query search state (device).
 struct QState {
@@ -66,7 +68,7 @@ struct QState {
     uint32_t kstride;        // output row stride
     int32_t hbase;           // histogram bin of a distance = (float bits >> 16) - hbase, clamped
     uint32_t rerun;          // the scan runs a second pass from a tightened bound
-    uint32_t pad1;
+    float qamax;             // largest |value| of the query
 };
 
 // Counters accumulated over a call (device).
@@ -79,6 +81,10 @@ struct QArgs {
     int64_t n;
     int32_t L, w, m, b;
     const uint4* words;
+    const uint2* cwords;         // [n] coarse words, leaf order
+    const uint8_t* fwords;       // [n][kFineStride] fine summaries, input order (nullptr: none)
+    int32_t wf, mf, lg_mf;       // fine segments, their length, ceil(log2 mf)
+    int32_t csh;                 // coarse symbol = symbol >> csh
     const uint32_t* pos;
     const Leaf* leaves;
     int32_t nL;
@@ -121,6 +127,8 @@ struct QArgs {
     float* approx_d;             // [nq][kApproxMax]
     LbPart* lbpart;              // [nq][leaf-bound blocks]
     Cand* cand;                  // [nq][cap]
+    uint32_t* seg;               // split scan: [nq][max_chunks][chunk] word survivors of each chunk (nullptr: no split)
+    uint32_t* segcnt;            // split scan: [nq][max_chunks] their counts
     uint32_t cap;
     float absmax_data;
     int32_t lg_m;                // ceil(log2 m)
@@ -142,6 +150,8 @@ struct Workspace {
     uint32_t max_chunks = 0;
     DevBuf qs, lb, order, rec, chunk_first, bins, mbins, cursor, hist, approx_d, cand, counters, err, prof, blk_cnt,
         status, lbpart;
+    DevBuf seg, segcnt;  // split scan (calls of at most kSplitMaxQ queries)
+    int32_t seg_nq = 0;
     DevBuf todo, env, todo_cnt, ec, ec_cnt;  // DTW search
     size_t todo_slots = 0, env_floats = 0, todo_cnt_n = 0, ec_slots = 0, ec_cnt_n = 0;
     uint32_t* h_err = nullptr;  // pinned copy of the call's error flags
@@ -155,7 +165,7 @@ struct Workspace {
     double bf_ms_filter = 0, bf_ms_recheck = 0;
     int bf_rounds = 0, bf_stage_queries = 0, bf_max_leaf_q = 0;
     // statistics read-back: phase events and pinned staging, made on first use
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[9] = {};
     QCounters* h_counters = nullptr;
     unsigned long long* h_prof = nullptr;    // [4096][4]
     unsigned long long* h_blk_cnt = nullptr; // [4096][5]

@@ -161,6 +161,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
         if (threadIdx.x == 0) {
             st.norm2 = qs.norm2;
             st.delta = qs.delta;
+            st.qamax = qs.amax;
             st.U = 0x7f800000u;  // +inf until the first bound
             st.ncand = 0;
             st.nmemb = 0;
@@ -720,9 +721,15 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
 // member work, and the grid still advances through the order together, so
 // the best leaves are scanned first and U tightens early.  Per chunk:
 //   positions  the chunk's leaves (start, bound, member offset) into LDS
-//   words      per member: leaf bound against U, then its 16-byte word
-//   filter     the member's own word bound from the LDS table; survivors
-//              compacted into LDS
+//   coarse     per member: leaf bound against U, then the bound of its 8-byte
+//              coarse word (every symbol cut to 4 bits, two per byte) from
+//              one LDS table per byte: 8 lookups
+//   word       per coarse survivor (a few percent): its 16-byte word and
+//              series index, read together; the word's own bound (region
+//              edges from LDS); survivors compacted into LDS
+//   fine       (ED) per word survivor, its fine summary (64 bytes: the PAA
+//              over 64 segments at L = 256): a tighter bound that keeps
+//              about one in ten of them
 //   distances  16 lanes per row, each row read whole (1 KB per pass)
 //   bound      k = 1: atomicMin of U; k > 1: histogram, then U from it
 // The steps are software-pipelined one chunk deep: the next chunk's leaf
@@ -751,7 +758,9 @@ scan_kernel(QArgs a) {
     constexpr bool SH = MODE == kScanRowFilter;
     constexpr bool DTW = MODE == kScanDtw;
     constexpr int kPer = kChunk / kScanThreads;
-    __shared__ float s_D[16 * 256];
+    __shared__ float s_C[8 * 256];           // coarse bound: per byte value of byte j, its two segments' terms
+    __shared__ float2 s_rb[256];             // each symbol's region widened by the query's delta (lo, hi)
+    __shared__ float s_plo[16], s_phi[16];   // the query's interval per segment
     // the query; with SH none (the rare fp32 rows read it from L2); with DTW
     // its envelope, upper then lower
     __shared__ float s_q[SH ? 1 : DTW ? 2 * MESSI_MAX_LEN : MESSI_MAX_LEN];
@@ -788,7 +797,7 @@ scan_kernel(QArgs a) {
         G = 1;
     }
     uint32_t c_scanned = 0, c_bounded = 0, c_dist = 0, c_abandon = 0, c_bytes = 0;  // this thread's share
-    uint32_t c_rck = 0, c_bft = 0;
+    uint32_t c_rck = 0, c_bft = 0, c_wordb = 0;
     const int npc = SH ? (a.Lp >> 3) : 0;  // 16-byte pieces of a BF16 row
     // optional per-block phase timing, kept by thread 0 in LDS: control,
     // member filter, distances, last mark, start
@@ -833,19 +842,39 @@ scan_kernel(QArgs a) {
             const int A = 1 << a.b;
             const float delta = st.delta;
             const float mf = (float)a.m;
-            for (int idx = tid; idx < a.w * A; idx += kScanThreads) {
-                const int i = idx / A, c = idx % A;
-                const float pl = st.paa[i], ph = st.paa_hi[i];
-                float d = 0.f;
-                if (c > 0) {
-                    const float lo = a.bp[c - 1] - delta;
-                    if (ph < lo) d = lo - ph;
+            const float inf = __uint_as_float(0x7f800000u);
+            for (int c = tid; c < A; c += kScanThreads)
+                s_rb[c] = make_float2(c > 0 ? a.bp[c - 1] - delta : -inf, c < A - 1 ? a.bp[c] + delta : inf);
+            if (tid < 16) {
+                s_plo[tid] = st.paa[tid];
+                s_phi[tid] = st.paa_hi[tid];
+            }
+            // byte j of a coarse word: coarse symbols of segments 2j (high
+            // nibble) and 2j + 1; coarse symbol c covers the symbols
+            // [c << csh, (c + 1) << csh)
+            for (int idx = tid; idx < 8 * 256; idx += kScanThreads) {
+                const int j = idx >> 8, byte = idx & 255;
+                float t = 0.f;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = 2 * j + h;
+                    const int c = h == 0 ? byte >> 4 : byte & 15;
+                    if (i < a.w) {
+                        const int s0 = c << a.csh, s1 = (c + 1) << a.csh;
+                        const float pl = st.paa[i], ph = st.paa_hi[i];
+                        float d = 0.f;
+                        if (s0 > 0 && s0 < A) {
+                            const float lo = a.bp[s0 - 1] - delta;
+                            if (ph < lo) d = lo - ph;
+                        }
+                        if (s1 < A) {
+                            const float hi = a.bp[s1 - 1] + delta;
+                            if (pl > hi) d = pl - hi;
+                        }
+                        t += mf * (d * d);
+                    }
                 }
-                if (c < A - 1) {
-                    const float hi = a.bp[c] + delta;
-                    if (pl > hi) d = pl - hi;
-                }
-                s_D[i * 256 + c] = mf * (d * d);
+                s_C[idx] = t;
             }
             if (DTW) {
                 // the query's LB_Keogh envelope (dtw_env_kernel)
@@ -923,8 +952,8 @@ scan_kernel(QArgs a) {
             }
             return lo;
         };
-        // This thread's members of a chunk: leaf bound against U, then the word.
-        auto issue_words = [&](uint32_t np, uint32_t clen, float Uc, uint4* wd) -> uint32_t {
+        // This thread's members of a chunk: leaf bound against U, then the coarse word.
+        auto issue_words = [&](uint32_t np, uint32_t clen, float Uc, uint2* cw) -> uint32_t {
             uint32_t live = 0;
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
@@ -937,7 +966,7 @@ scan_kernel(QArgs a) {
                         mp = s_pbase[lf] + f;
                     }
                 }
-                wd[r] = (live & (1u << r)) ? a.words[mp] : make_uint4(0, 0, 0, 0);
+                cw[r] = (live & (1u << r)) ? a.cwords[mp] : make_uint2(0, 0);
             }
             return live;
         };
@@ -960,8 +989,8 @@ scan_kernel(QArgs a) {
         float Uc = s_Ublk;
         uint32_t np = commit_positions(jb, t0n, rn, rn_ok, Uc);
         if (np == 0 || s_stop || chunk_stops(Uc)) continue;
-        uint4 wd[kPer];
-        uint32_t live = issue_words(np, chunk_len(jb), Uc, wd);
+        uint2 cw[kPer];
+        uint32_t live = issue_words(np, chunk_len(jb), Uc, cw);
         tick(0);
         for (uint32_t i = 0;; ++i) {
             const uint64_t c = jb + (uint64_t)i * G;
@@ -973,34 +1002,59 @@ scan_kernel(QArgs a) {
                 rn_ok = t0n + tid < nsurv;
                 if (rn_ok) rn = recq[t0n + tid];
             }
-            // ---- filter this chunk: each member's own word bound
+            // ---- filter this chunk: each member's coarse word bound
             const float Uf = s_Ublk;
-            uint32_t keepmask = 0, nkeep = 0;
+            uint32_t bmask = 0;
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
                 if (live & (1u << r)) {
                     float sum = 0.f;
 #pragma unroll
-                    for (int i2 = 0; i2 < 16; ++i2)
-                        if (i2 < a.w) sum += s_D[i2 * 256 + word_byte(wd[r], i2)];
-                    if (!(sum * (1.0f - kRhoLb) > Uf)) {
-                        keepmask |= 1u << r;
-                        ++nkeep;
+                    for (int j2 = 0; j2 < 8; ++j2) {
+                        const uint32_t half = j2 < 4 ? cw[r].x : cw[r].y;
+                        sum += s_C[j2 * 256 + ((half >> (8 * (j2 & 3))) & 255u)];
                     }
+                    if (!(sum * (1.0f - kRhoLb) > Uf)) bmask |= 1u << r;
                     ++c_bounded;
                 }
             }
-            // series index of every survivor, in flight during the compaction
-            // (with SH its leaf-order position: the BF16 row's index)
+            // ---- the coarse survivors' words and series indices (with SH the
+            // leaf-order position: the BF16 row's index), read together
+            uint4 wd[kPer];
             uint32_t gi[kPer];
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
                 gi[r] = 0;
-                if (keepmask & (1u << r)) {
+                wd[r] = make_uint4(0, 0, 0, 0);
+                if (bmask & (1u << r)) {
                     // the chunk's leaves are still in LDS (the next chunk's are committed below)
                     const uint32_t f = r * kScanThreads + tid;
                     const uint32_t mp = s_pbase[member_leaf(np, f)] + f;
+                    wd[r] = a.words[mp];
                     gi[r] = SH ? mp : a.pos[mp];
+                }
+            }
+            // ---- each coarse survivor's own word bound
+            uint32_t keepmask = 0, nkeep = 0;
+            const float mseg = (float)a.m;
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                if (bmask & (1u << r)) {
+                    float sum = 0.f;
+#pragma unroll
+                    for (int i2 = 0; i2 < 16; ++i2) {
+                        if (i2 < a.w) {
+                            const float2 rg = s_rb[word_byte(wd[r], i2)];
+                            const float pl = s_plo[i2], ph = s_phi[i2];
+                            const float d = ph < rg.x ? rg.x - ph : (pl > rg.y ? pl - rg.y : 0.f);
+                            sum += mseg * (d * d);
+                        }
+                    }
+                    if (!(sum * (1.0f - kRhoLb) > Uf)) {
+                        keepmask |= 1u << r;
+                        ++nkeep;
+                    }
+                    ++c_wordb;
                 }
             }
             uint32_t total;
@@ -1027,9 +1081,9 @@ scan_kernel(QArgs a) {
             // next chunk lies wholly above U
             if (s_stop) break;
             if (more && (npn == 0 || chunk_stops(Uc))) more = false;
-            uint4 wdn[kPer];
+            uint2 cwn[kPer];
             uint32_t liven = 0;
-            if (more) liven = issue_words(npn, chunk_len(c + G), Uc, wdn);
+            if (more) liven = issue_words(npn, chunk_len(c + G), Uc, cwn);
             tick(0);
             // distances wait until a batch of survivors has gathered (or the
             // block's last chunk), so each round of row loads is well filled
@@ -1166,7 +1220,7 @@ scan_kernel(QArgs a) {
                         acc = p;  // the full distance
                     }
                 }
-                if (act && ql == 0 && !from_rck) ++c_dist;
+                if (act && ql == 0 && !(SH && from_rck)) ++c_dist;
                 if (DTW) {
                     // LB_Keogh within the bound: the series waits for its DTW, in
                     // this block's own segment of the list (a counter in LDS: one
@@ -1206,7 +1260,7 @@ scan_kernel(QArgs a) {
             np = npn;
             live = liven;
 #pragma unroll
-            for (int r = 0; r < kPer; ++r) wd[r] = wdn[r];
+            for (int r = 0; r < kPer; ++r) cw[r] = cwn[r];
         }
         __syncthreads();
         if (DTW && tid == 0) a.todo_cnt[(size_t)q * a.todo_nseg + j] = min(s_ntodo, a.todo_seg);
@@ -1223,9 +1277,12 @@ scan_kernel(QArgs a) {
         // per-block totals in plain stores (the host adds them up): same-address
         // atomics from every block at once would serialise at the end of the grid
         __shared__ unsigned long long s_cnt[4][kBlkCnt];
+        // bytes: rows, 8 per coarse word, 16 per word (+ 4 for the series
+        // index, read with it unless SH), the fine summary's 16-byte pieces
         unsigned long long v[kBlkCnt] = {c_scanned, c_bounded, c_dist, c_abandon,
-                                         (unsigned long long)c_bytes / 16 + (unsigned long long)c_bounded * 16ull,
-                                         c_rck, c_bft};
+                                         (unsigned long long)c_bytes / 16 + (unsigned long long)c_bounded * 8ull +
+                                             (unsigned long long)c_wordb * (SH ? 16ull : 20ull),
+                                         c_rck, c_bft, c_wordb, 0ull};
         for (int i = 0; i < kBlkCnt; ++i)
             for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
         if (lane == 0)
@@ -1235,6 +1292,1192 @@ scan_kernel(QArgs a) {
             const unsigned long long t = s_cnt[0][tid] + s_cnt[1][tid] + s_cnt[2][tid] + s_cnt[3][tid];
             unsigned long long* p = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
             *p = (pass == 0 && a.chunk_lo == 0 ? 0ull : *p) + t;
+        }
+    }
+}
+
+// ---- the flat Euclidean scan ---------------------------------------------------
+// The same ordered member list and chunks as scan_kernel, but a chunk is the
+// work of one wave, and the waves of a block share only the query's tables:
+// no barrier between chunks.  Wave i of a query's W waves takes chunks i,
+// i + W, i + 2W, ...  (W is thousands: the first pass over the chunks runs
+// on every wave at once, the later ones after U has tightened.)  Per chunk:
+//   records    the chunk's leaves (one per lane, 64 at a time)
+//   coarse     per member: its leaf's bound against U, then its coarse word
+//              (8 bytes) against the coarse table; survivors' leaf-order
+//              positions into the wave's list in LDS (ballot compaction)
+//   word       per listed member, its word and series index read together,
+//              the word's bound; survivors' series indices kept in the list
+//   fine       per listed series, its fine summary (4 lanes per series)
+//   distances  16 lanes per row, early abandoning; k = 1: atomicMin of U;
+//              k > 1: candidate buffer and histogram, U from the histogram
+// Each stage compacts the list in place: a round writes only below the
+// entries it has read.  Only the member loads are many per lane; the later
+// stages touch a few percent of the members each.
+constexpr int kFlatList = kChunk;  // list entries per wave: a chunk's members at most
+constexpr int kFlatIssue = 8;      // coarse words in flight per lane
+
+// Lower U from the histogram of candidate distances (one wave).
+__device__ void wave_hist_refresh(const QArgs& a, int q, QState& st, float& U) {
+    const uint32_t* h = a.hist + (size_t)q * kHistBins;
+    constexpr int kPer = kHistBins / 64;
+    const int lane = threadIdx.x & 63;
+    uint32_t sum = 0;
+#pragma unroll 8
+    for (int i = 0; i < kPer; ++i) sum += vload(h + lane * kPer + i);
+    // exclusive prefix over the lanes
+    uint32_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    const uint32_t excl = incl - sum;
+    const uint32_t k = (uint32_t)st.k;
+    if (excl < k && incl >= k) {
+        uint32_t c = excl, b = 0;
+        for (int i = 0; i < kPer; ++i) {
+            const uint32_t v = vload(h + lane * kPer + i);
+            if (c < k && c + v >= k) {
+                b = lane * kPer + i;
+                break;
+            }
+            c += v;
+        }
+        const int32_t e = (int32_t)b + 1 + st.hbase;  // upper edge of bin b, as float bits >> 16
+        if (b < (uint32_t)(kHistBins - 1) && e > 0 && e < 0x7f80) {
+            const uint32_t ub = __float_as_uint(upper_u(__uint_as_float((uint32_t)e << 16)));
+            atomicMin(&st.U, ub);
+        }
+    }
+    U = fminf(U, __uint_as_float(vload(&st.U)));
+}
+
+template <bool VEC, int pass>
+__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)))
+flat_scan_kernel(QArgs a) {
+    __shared__ float s_C[8 * 256];
+    __shared__ float2 s_rb[256];
+    __shared__ float2 s_rf[256];
+    __shared__ float s_plo[16], s_phi[16];
+    __shared__ float s_pf[64];
+    __shared__ float s_bp[256];
+    __shared__ __align__(16) float s_q[MESSI_MAX_LEN];
+    __shared__ uint32_t s_list[kScanThreads / 64][kFlatList];
+    __shared__ OrdRec s_rec[kScanThreads / 64][64];  // per wave: a window of the chunk's leaves
+    __shared__ uint32_t s_flag;
+    __shared__ unsigned long long s_t0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int quarter = lane >> 4, ql = lane & 15;
+    const uint64_t lt_mask = dev::lanemask_lt();
+    uint32_t* list = s_list[wave];
+    OrdRec* wrec = s_rec[wave];
+    const int nq = a.nq;
+    const int L = a.L;
+    const int nchunk = (L + 63) / 64;
+    const int B = gridDim.x;
+    constexpr int kWaves = kScanThreads / 64;
+    int q0, qstep, j, G;
+    if (nq <= B) {
+        q0 = blockIdx.x % nq;
+        qstep = nq;
+        j = blockIdx.x / nq;
+        G = (B - q0 + nq - 1) / nq;
+    } else {
+        q0 = blockIdx.x;
+        qstep = B;
+        j = 0;
+        G = 1;
+    }
+    const bool timing = a.prof != nullptr;
+    if (timing && tid == 0) s_t0 = wall_clock64();
+    uint32_t c_scanned = 0, c_bounded = 0, c_dist = 0, c_abandon = 0, c_wordb = 0, c_fine = 0;
+    unsigned long long c_rowb = 0;
+    bool worked = false;
+    for (int q = q0; q < nq; q += qstep) {
+        QState& st = a.qs[q];
+        if (tid == 0) s_flag = (st.err != 0 || st.nsurv == 0 || (pass == 1 && st.rerun == 0)) ? 1u : 0u;
+        __syncthreads();
+        const bool skip = s_flag != 0;
+        __syncthreads();
+        if (skip) continue;
+        worked = true;
+        const uint32_t nsurv = st.nsurv;
+        const uint64_t nmemb = st.nmemb;
+        const int k = st.k;
+        const float range = st.range;
+        const uint64_t nch = min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.chunk_hi);
+        const bool fine = a.fwords != nullptr;
+        // ---- the query's tables: the breakpoints, the query's summary and
+        // the query itself are read into LDS first (one load per thread),
+        // then the tables are computed from LDS
+        {
+            const int A = 1 << a.b;
+            const float inf = __uint_as_float(0x7f800000u);
+            for (int c = tid; c < A - 1; c += kScanThreads) s_bp[c] = a.bp[c];
+            if (tid < 16) {
+                s_plo[tid] = st.paa[tid];
+                s_phi[tid] = st.paa_hi[tid];
+            }
+            for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
+            const float delta = st.delta;
+            const float qamax = st.qamax;
+            __syncthreads();
+            const float mf = (float)a.m;
+            for (int c = tid; c < A; c += kScanThreads)
+                s_rb[c] = make_float2(c > 0 ? s_bp[c - 1] - delta : -inf, c < A - 1 ? s_bp[c] + delta : inf);
+            for (int idx = tid; idx < 8 * 256; idx += kScanThreads) {
+                const int j2 = idx >> 8, byte = idx & 255;
+                float t = 0.f;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = 2 * j2 + h;
+                    const int c = h == 0 ? byte >> 4 : byte & 15;
+                    if (i < a.w) {
+                        const int s0 = c << a.csh, s1 = (c + 1) << a.csh;
+                        const float pl = s_plo[i], ph = s_phi[i];
+                        float d = 0.f;
+                        if (s0 > 0 && s0 < A) {
+                            const float lo = s_bp[s0 - 1] - delta;
+                            if (ph < lo) d = lo - ph;
+                        }
+                        if (s1 < A) {
+                            const float hi = s_bp[s1 - 1] + delta;
+                            if (pl > hi) d = pl - hi;
+                        }
+                        t += mf * (d * d);
+                    }
+                }
+                s_C[idx] = t;
+            }
+            if (fine) {
+                const float u = 5.9604644775390625e-08f;  // 2^-24
+                const float df = 1.01f * (2.f * (float)(a.lg_mf + 1) * u * a.absmax_data +
+                                          2.f * (float)(a.mf + 1) * u * qamax);
+                for (int c = tid; c < A; c += kScanThreads)
+                    s_rf[c] = make_float2(c > 0 ? s_bp[c - 1] - df : -inf, c < A - 1 ? s_bp[c] + df : inf);
+                for (int jj = tid; jj < a.wf; jj += kScanThreads) {
+                    float sum = 0.f;
+                    for (int i = 0; i < a.mf; ++i) sum += s_q[jj * a.mf + i];
+                    s_pf[jj] = sum / (float)a.mf;
+                }
+            }
+            __syncthreads();
+        }
+        const uint32_t* cfq = a.chunk_first + (size_t)q * a.max_chunks;
+        const OrdRec* recq = a.rec + (size_t)q * a.nL;
+        const uint64_t WG = (uint64_t)G * kWaves;
+        const float mseg = (float)a.m;
+        float U = __uint_as_float(vload(&st.U));
+        // Round t of this wave takes chunk t W + i for even t and
+        // t W + W - 1 - i for odd t (a snake over the order): the wave that
+        // takes one of the first, heaviest chunks of a round takes one of the
+        // last, lightest of the next.  The first chunk's leaf position and
+        // records load now, each later one's while its predecessor is filtered.
+        const uint64_t wi = (uint64_t)j * kWaves + wave;
+        auto chunk_of = [&](uint64_t t) -> uint64_t {
+            return (uint64_t)a.chunk_lo + t * WG + ((t & 1) ? WG - 1 - wi : wi);
+        };
+        uint64_t rt = 0;
+        uint64_t c = chunk_of(0);
+        uint32_t tw_n = c < nch ? cfq[c] : 0u;
+        OrdRec r_n{0u, 0u, 0.f, 0xffffffffu};
+        if (c < nch && tw_n + lane < nsurv) r_n = recq[tw_n + lane];
+        for (; (uint64_t)a.chunk_lo + rt * WG < nch; c = chunk_of(++rt)) {
+            if (c >= nch) continue;  // the last round's chunks end before this wave's place
+            if (vload(&st.ovf)) break;  // this pass overflowed: it is redone from a tighter bound
+            U = fminf(U, __uint_as_float(vload(&st.U)));
+            const uint64_t cbeg = c * a.chunk;
+            const uint64_t cend = min(cbeg + a.chunk, nmemb);
+            uint32_t tw = tw_n;  // the order position of the chunk's first leaf
+            OrdRec r = r_n;
+            const uint64_t cn = chunk_of(rt + 1);
+            if (cn < nch) tw_n = cfq[cn];
+            uint32_t n1 = 0;
+            bool stop = false;
+            // ---- coarse: a window of up to 64 of the chunk's leaves at a time
+            for (bool first = true;; first = false) {
+                if (!first) {
+                    r = OrdRec{0u, 0u, 0.f, 0xffffffffu};
+                    if (tw + lane < nsurv) r = recq[tw + lane];
+                }
+                const bool rin = tw + lane < nsurv && (uint64_t)r.moff < cend;
+                const uint32_t nin = (uint32_t)__popcll(__ballot(rin));  // a prefix of the lanes
+                wrec[lane] = r;
+                dev::wave_sync();
+                if (first) {
+                    // bins ascend along the order: a chunk whose first leaf lies
+                    // in a bin wholly above U ends this wave's part of the order
+                    const float lb0 = wrec[0].lb;
+                    const float low = (float)bin_of(lb0, range) * (range / (float)kNB);
+                    if (lb0 * (1.0f - kRhoLb) > U && low * (1.0f - 2.0f * kRhoLb) > U) {
+                        stop = true;
+                        break;
+                    }
+                }
+                if (rin && (uint64_t)r.moff >= cbeg && !(r.lb * (1.0f - kRhoLb) > U)) ++c_scanned;
+                const uint64_t wbeg = max(cbeg, (uint64_t)wrec[0].moff);
+                const OrdRec rl = wrec[nin - 1];
+                const uint64_t wend = min(cend, (uint64_t)rl.moff + (uint64_t)rl.count);
+                // Each member's leaf: with at most four leaves in the window their
+                // ends, bases (start - member offset, mod 2^32) and bounds sit in
+                // scalar registers and a member picks its leaf by comparisons;
+                // otherwise a walk over the window's records in LDS.
+                const bool few = nin <= 4;
+                uint32_t e_s[4], b_s[4];
+                float l_s[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    e_s[t] = (uint32_t)__builtin_amdgcn_readlane((int)(r.moff + r.count), t);
+                    b_s[t] = (uint32_t)__builtin_amdgcn_readlane((int)(r.start - r.moff), t);
+                    l_s[t] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.lb), t));
+                }
+                const uint32_t wb = (uint32_t)wbeg, we = (uint32_t)wend;
+                int p = 0;  // the walk's leaf in the window (advances with the lane's members)
+                for (uint32_t g0 = wb; g0 < we; g0 += 64 * kFlatIssue) {
+                    uint2 cw[kFlatIssue];
+                    uint32_t mpv[kFlatIssue];
+                    uint32_t live = 0;
+#pragma unroll
+                    for (int i = 0; i < kFlatIssue; ++i) {
+                        const uint32_t g = g0 + (uint32_t)i * 64 + lane;
+                        cw[i] = make_uint2(0u, 0u);
+                        mpv[i] = 0;
+                        if (g < we) {
+                            uint32_t bs;
+                            float lbv;
+                            if (few) {
+                                bs = b_s[0];
+                                lbv = l_s[0];
+#pragma unroll
+                                for (int t = 1; t < 4; ++t)
+                                    if (t < (int)nin && g >= e_s[t - 1]) {
+                                        bs = b_s[t];
+                                        lbv = l_s[t];
+                                    }
+                            } else {
+                                while (p + 1 < (int)nin && wrec[p + 1].moff <= g) ++p;
+                                const OrdRec rp = wrec[p];
+                                bs = rp.start - rp.moff;
+                                lbv = rp.lb;
+                            }
+                            if (!(lbv * (1.0f - kRhoLb) > U)) {
+                                live |= 1u << i;
+                                mpv[i] = bs + g;
+                                cw[i] = a.cwords[mpv[i]];
+                            }
+                        }
+                    }
+                    // the next chunk's records, in flight while this chunk is filtered
+                    if (first && g0 == wb) {
+                        r_n = OrdRec{0u, 0u, 0.f, 0xffffffffu};
+                        if (cn < nch && tw_n + lane < nsurv) r_n = recq[tw_n + lane];
+                    }
+#pragma unroll
+                    for (int i = 0; i < kFlatIssue; ++i) {
+                        bool keep = false;
+                        if (live & (1u << i)) {
+                            float sum = 0.f;
+#pragma unroll
+                            for (int j2 = 0; j2 < 8; ++j2) {
+                                const uint32_t half = j2 < 4 ? cw[i].x : cw[i].y;
+                                sum += s_C[j2 * 256 + ((half >> (8 * (j2 & 3))) & 255u)];
+                            }
+                            keep = !(sum * (1.0f - kRhoLb) > U);
+                            ++c_bounded;
+                        }
+                        const uint64_t bal = __ballot(keep);
+                        if (keep) list[n1 + __popcll(bal & lt_mask)] = mpv[i];
+                        n1 += (uint32_t)__popcll(bal);
+                    }
+                }
+                if (nin < 64 || wend >= cend) break;
+                tw += 64;
+                dev::wave_sync();  // every lane is done with this window's records
+            }
+            if (stop) break;
+            dev::wave_sync();
+            // ---- word: each listed member's word and series index, read
+            // together, kWordIssue per lane in flight
+            constexpr int kWordIssue = 4;
+            uint32_t n2 = 0;
+            for (uint32_t e0 = 0; e0 < n1; e0 += 64 * kWordIssue) {
+                uint4 wd[kWordIssue];
+                uint32_t gi[kWordIssue];
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    wd[t] = make_uint4(0u, 0u, 0u, 0u);
+                    gi[t] = 0;
+                    if (e < n1) {
+                        const uint32_t mp = list[e];
+                        wd[t] = a.words[mp];
+                        gi[t] = a.pos[mp];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    bool keep = false;
+                    if (e < n1) {
+                        float sum = 0.f;
+#pragma unroll
+                        for (int i2 = 0; i2 < 16; ++i2) {
+                            if (i2 < a.w) {
+                                const float2 rg = s_rb[word_byte(wd[t], i2)];
+                                const float pl = s_plo[i2], ph = s_phi[i2];
+                                const float d = ph < rg.x ? rg.x - ph : (pl > rg.y ? pl - rg.y : 0.f);
+                                sum += mseg * (d * d);
+                            }
+                        }
+                        keep = !(sum * (1.0f - kRhoLb) > U);
+                        ++c_wordb;
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    if (keep) list[n2 + __popcll(bal & lt_mask)] = gi[t];
+                    n2 += (uint32_t)__popcll(bal);
+                }
+            }
+            dev::wave_sync();
+            // ---- fine: 4 lanes per series, 16 series per round, kFineIssue
+            // rounds in flight
+            constexpr int kFineIssue = 4;
+            uint32_t n3 = n2;
+            // with at most half a list of word survivors, each fine survivor's
+            // bound is kept in the list's upper half (for the best-first rows)
+            const bool keep_lb = fine && n2 <= (uint32_t)(kFlatList / 2);
+            float* llb = reinterpret_cast<float*>(list + kFlatList / 2);
+            if (fine && n2) {
+                n3 = 0;
+                const int g4 = lane >> 2, l4 = lane & 3;
+                const float mfine = (float)a.mf;
+                const bool part = l4 * 16 < a.wf;
+                for (uint32_t e0 = 0; e0 < n2; e0 += 16 * kFineIssue) {
+                    uint4 fv[kFineIssue];
+                    uint32_t gx[kFineIssue];
+#pragma unroll
+                    for (int t = 0; t < kFineIssue; ++t) {
+                        const uint32_t e = e0 + (uint32_t)t * 16 + g4;
+                        fv[t] = make_uint4(0u, 0u, 0u, 0u);
+                        gx[t] = 0;
+                        if (e < n2) {
+                            gx[t] = list[e];
+                            if (part)
+                                fv[t] = *reinterpret_cast<const uint4*>(a.fwords + (size_t)gx[t] * kFineStride +
+                                                                        l4 * 16);
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < kFineIssue; ++t) {
+                        if (e0 + (uint32_t)t * 16 >= n2) break;  // the rest of the batch is empty
+                        const uint32_t e = e0 + (uint32_t)t * 16 + g4;
+                        const bool act = e < n2;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int tt = 0; tt < 16; ++tt) {
+                            const int jf = l4 * 16 + tt;
+                            if (jf < a.wf) {
+                                const float2 rg = s_rf[word_byte(fv[t], tt)];
+                                const float pv = s_pf[jf];
+                                const float d = pv < rg.x ? rg.x - pv : (pv > rg.y ? pv - rg.y : 0.f);
+                                acc = fmaf(d, d, acc);
+                            }
+                        }
+                        acc += __shfl_xor(acc, 1, 4);
+                        acc += __shfl_xor(acc, 2, 4);
+                        const float lbf = acc * mfine;
+                        const bool keep = act && l4 == 0 && !(lbf * (1.0f - kRhoLb) > U);
+                        if (act && l4 == 0) ++c_fine;
+                        const uint64_t bal = __ballot(keep);
+                        if (keep) {
+                            const uint32_t o = n3 + (uint32_t)__popcll(bal & lt_mask);
+                            list[o] = gx[t];
+                            if (keep_lb) llb[o] = lbf;
+                        }
+                        n3 += (uint32_t)__popcll(bal);
+                    }
+                }
+                dev::wave_sync();
+            }
+            // ---- distances: 16 lanes per row, 4 rows per round; U stays one
+            // value across the wave (a row's 16 lanes must agree on abandoning)
+            uint32_t appended = 0;
+            auto rows = [&](uint32_t eb, uint32_t ee) {
+            for (uint32_t e0 = eb; e0 < ee; e0 += 4) {
+                float Unew = U;
+                const uint32_t e = e0 + quarter;
+                const bool act = e < ee;
+                const uint32_t gidx = act ? list[e] : 0u;
+                bool alive = act;
+                const float* row = a.series + (size_t)gidx * L;
+                float acc = 0.f;
+                for (int g = 0; g < nchunk; g += 4) {
+                    if (alive) {
+                        if (VEC) {
+                            float4 x[4];
+#pragma unroll
+                            for (int cc = 0; cc < 4; ++cc) {
+                                const int j0 = (g + cc) * 64 + ql * 4;
+                                x[cc] = (g + cc < nchunk && j0 < L) ? *reinterpret_cast<const float4*>(row + j0)
+                                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+                            }
+#pragma unroll
+                            for (int cc = 0; cc < 4; ++cc) {
+                                const int j0 = (g + cc) * 64 + ql * 4;
+                                if (g + cc < nchunk && j0 < L) {
+                                    const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
+                                    const float d0 = y.x - x[cc].x, d1 = y.y - x[cc].y;
+                                    const float d2 = y.z - x[cc].z, d3 = y.w - x[cc].w;
+                                    acc = fmaf(d0, d0, acc);
+                                    acc = fmaf(d1, d1, acc);
+                                    acc = fmaf(d2, d2, acc);
+                                    acc = fmaf(d3, d3, acc);
+                                }
+                            }
+                        } else {
+#pragma unroll
+                            for (int cc = 0; cc < 4; ++cc) {
+#pragma unroll
+                                for (int e2 = 0; e2 < 4; ++e2) {
+                                    const int jj = (g + cc) * 64 + ql * 4 + e2;
+                                    if (g + cc < nchunk && jj < L) {
+                                        const float d = s_q[jj] - row[jj];
+                                        acc = fmaf(d, d, acc);
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    float pp = acc;
+                    pp += __shfl_xor(pp, 8, 16);
+                    pp += __shfl_xor(pp, 4, 16);
+                    pp += __shfl_xor(pp, 2, 16);
+                    pp += __shfl_xor(pp, 1, 16);
+                    pp = __shfl(pp, quarter * 16, 64);
+                    if (alive && ql == 0) c_rowb += (uint64_t)min(4, nchunk - g) * 256u;
+                    if (g + 4 < nchunk) {
+                        if (alive && pp * (1.0f - kRhoEd) > U) {
+                            alive = false;
+                            if (ql == 0) ++c_abandon;
+                        }
+                    } else {
+                        acc = pp;  // the full distance
+                    }
+                }
+                if (act && ql == 0) ++c_dist;
+                if (alive && ql == 0 && acc * (1.0f - kRhoEd) <= U) {
+                    const float d = acc;
+                    const uint32_t slot = atomicAdd(&st.ncand, 1u);
+                    if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx};
+                    else st.ovf = 1;
+                    ++appended;
+                    if (k == 1) {
+                        const uint32_t ub = __float_as_uint(upper_u(d));
+                        atomicMin(&st.U, ub);
+                        Unew = fminf(Unew, __uint_as_float(ub));
+                    } else {
+                        atomicAdd(&a.hist[(size_t)q * kHistBins + hist_bin(d, st.hbase)], 1u);
+                    }
+                }
+                for (int off = 32; off >= 1; off >>= 1) Unew = fminf(Unew, __shfl_xor(Unew, off));
+                U = Unew;
+            }
+            };
+            if (keep_lb && k == 1 && n3 > 4) {
+                // Best first: the series of smallest fine bound alone (the fine
+                // bound is close to the distance, so that row usually sets U
+                // near its final value), then the others that its U leaves.
+                float bl = __uint_as_float(0x7f800000u);
+                uint32_t be = 0;
+                for (uint32_t e = lane; e < n3; e += 64)
+                    if (llb[e] < bl) {
+                        bl = llb[e];
+                        be = e;
+                    }
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const float ob = __shfl_xor(bl, off);
+                    const uint32_t oe = __shfl_xor(be, off);
+                    if (ob < bl || (ob == bl && oe < be)) {
+                        bl = ob;
+                        be = oe;
+                    }
+                }
+                dev::wave_sync();
+                if (lane == 0) {
+                    const uint32_t t0 = list[0];
+                    const float f0 = llb[0];
+                    list[0] = list[be];
+                    llb[0] = llb[be];
+                    list[be] = t0;
+                    llb[be] = f0;
+                }
+                dev::wave_sync();
+                rows(0, 1);
+                uint32_t nk = 0;
+                for (uint32_t e0 = 1; e0 < n3; e0 += 64) {
+                    const uint32_t e = e0 + lane;
+                    uint32_t gv = 0;
+                    float fv = 0.f;
+                    bool keep = false;
+                    if (e < n3) {
+                        gv = list[e];
+                        fv = llb[e];
+                        keep = !(fv * (1.0f - kRhoLb) > U);
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    if (keep) {
+                        const uint32_t o = nk + (uint32_t)__popcll(bal & lt_mask);
+                        list[o] = gv;
+                        llb[o] = fv;
+                    }
+                    nk += (uint32_t)__popcll(bal);
+                }
+                dev::wave_sync();
+                rows(0, nk);
+            } else {
+                rows(0, n3);
+            }
+            if (k > 1 && __ballot(appended != 0)) wave_hist_refresh(a, q, st, U);
+            dev::wave_sync();  // the list is refilled by the next chunk
+        }
+        __syncthreads();  // the tables are rebuilt for the block's next query
+    }
+    if (timing && tid == 0 && (pass == 0 || worked)) {
+        unsigned long long* pr = a.prof + (size_t)blockIdx.x * 4;
+        const unsigned long long v[4] = {0ull, 0ull, 0ull, wall_clock64() - s_t0};
+        const bool first = pass == 0 && a.chunk_lo == 0;
+        for (int i = 0; i < 4; ++i) pr[i] = (first ? 0ull : pr[i]) + v[i];
+    }
+    if (a.blk_cnt) {
+        __shared__ unsigned long long s_cnt[kWaves][kBlkCnt];
+        const unsigned long long fine_b = 16ull * (unsigned long long)((a.wf + 15) / 16);
+        unsigned long long v[kBlkCnt] = {c_scanned, c_bounded, c_dist, c_abandon,
+                                         c_rowb + (unsigned long long)c_bounded * 8ull +
+                                             (unsigned long long)c_wordb * 20ull +
+                                             (unsigned long long)c_fine * fine_b,
+                                         0ull, 0ull, c_wordb, c_fine};
+        for (int i = 0; i < kBlkCnt; ++i)
+            for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
+        if (lane == 0)
+            for (int i = 0; i < kBlkCnt; ++i) s_cnt[wave][i] = v[i];
+        __syncthreads();
+        if (tid < kBlkCnt && (pass == 0 || worked)) {
+            unsigned long long t = 0;
+            for (int w2 = 0; w2 < kWaves; ++w2) t += s_cnt[w2][tid];
+            unsigned long long* pp = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
+            *pp = (pass == 0 && a.chunk_lo == 0 ? 0ull : *pp) + t;
+        }
+    }
+}
+
+
+// ---- the split Euclidean scan -------------------------------------------------
+// For calls of few queries the flat scan runs as two kernels.  The first
+// (coarse and word bounds) is light on registers, so more of its waves fit a
+// CU and more member reads are in flight; it stores the survivors of chunk c
+// at the chunk's own place in a[q].seg (a chunk's members at most, so it
+// cannot overflow) and their count in segcnt.  The second (fine bound and
+// distances) takes the survivors of a block's chunks as one list, 16 series
+// per wave and round, so the survivors of one heavy chunk are shared by the
+// block's waves.  U comes from the first bound (and, in the second kernel,
+// from the distances as they are found).
+
+// Block-wide: the query's coarse table and word regions (as the flat scan's).
+__device__ void coarse_word_tables(const QArgs& a, const QState& st, float* s_bp, float* s_plo, float* s_phi,
+                                   float2* s_rb, float* s_C) {
+    const int tid = threadIdx.x;
+    const int A = 1 << a.b;
+    const float inf = __uint_as_float(0x7f800000u);
+    for (int c = tid; c < A - 1; c += blockDim.x) s_bp[c] = a.bp[c];
+    if (tid < 16) {
+        s_plo[tid] = st.paa[tid];
+        s_phi[tid] = st.paa_hi[tid];
+    }
+    const float delta = st.delta;
+    __syncthreads();
+    const float mf = (float)a.m;
+    for (int c = tid; c < A; c += blockDim.x)
+        s_rb[c] = make_float2(c > 0 ? s_bp[c - 1] - delta : -inf, c < A - 1 ? s_bp[c] + delta : inf);
+    for (int idx = tid; idx < 8 * 256; idx += blockDim.x) {
+        const int j2 = idx >> 8, byte = idx & 255;
+        float t = 0.f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = 2 * j2 + h;
+            const int c = h == 0 ? byte >> 4 : byte & 15;
+            if (i < a.w) {
+                const int s0 = c << a.csh, s1 = (c + 1) << a.csh;
+                const float pl = s_plo[i], ph = s_phi[i];
+                float d = 0.f;
+                if (s0 > 0 && s0 < A) {
+                    const float lo = s_bp[s0 - 1] - delta;
+                    if (ph < lo) d = lo - ph;
+                }
+                if (s1 < A) {
+                    const float hi = s_bp[s1 - 1] + delta;
+                    if (pl > hi) d = pl - hi;
+                }
+                t += mf * (d * d);
+            }
+        }
+        s_C[idx] = t;
+    }
+    __syncthreads();
+}
+
+template <int pass>
+__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(5)))
+flat_coarse_kernel(QArgs a) {
+    __shared__ float s_C[8 * 256];
+    __shared__ float2 s_rb[256];
+    __shared__ float s_plo[16], s_phi[16];
+    __shared__ float s_bp[256];
+    __shared__ uint32_t s_list[kScanThreads / 64][kFlatList];
+    __shared__ OrdRec s_rec[kScanThreads / 64][64];
+    __shared__ uint32_t s_flag;
+    constexpr int kWaves = kScanThreads / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt_mask = dev::lanemask_lt();
+    uint32_t* list = s_list[wave];
+    OrdRec* wrec = s_rec[wave];
+    const int nq = a.nq;
+    const int B = gridDim.x;
+    // one query per block (the host runs the split scan only for nq <= blocks)
+    const int q = blockIdx.x % nq;
+    const int j = blockIdx.x / nq;
+    const int G = (B - q + nq - 1) / nq;
+    uint32_t c_scanned = 0, c_bounded = 0, c_wordb = 0;
+    QState& st = a.qs[q];
+    if (tid == 0) s_flag = (st.err != 0 || st.nsurv == 0 || (pass == 1 && st.rerun == 0)) ? 1u : 0u;
+    __syncthreads();
+    const bool skip = s_flag != 0;
+    __syncthreads();
+    if (!skip) {
+        const uint32_t nsurv = st.nsurv;
+        const uint64_t nmemb = st.nmemb;
+        const float range = st.range;
+        const uint64_t nch = min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.max_chunks);
+        coarse_word_tables(a, st, s_bp, s_plo, s_phi, s_rb, s_C);
+        const uint32_t* cfq = a.chunk_first + (size_t)q * a.max_chunks;
+        const OrdRec* recq = a.rec + (size_t)q * a.nL;
+        uint32_t* segq = a.seg + (size_t)q * a.max_chunks * a.chunk;
+        uint32_t* cntq = a.segcnt + (size_t)q * a.max_chunks;
+        const uint64_t WG = (uint64_t)G * kWaves;
+        const float mseg = (float)a.m;
+        const float U = __uint_as_float(vload(&st.U));
+        const uint64_t wi = (uint64_t)j * kWaves + wave;
+        auto chunk_of = [&](uint64_t t) -> uint64_t { return t * WG + ((t & 1) ? WG - 1 - wi : wi); };
+        uint64_t rt = 0;
+        uint64_t c = chunk_of(0);
+        uint32_t tw_n = c < nch ? cfq[c] : 0u;
+        OrdRec r_n{0u, 0u, 0.f, 0xffffffffu};
+        if (c < nch && tw_n + lane < nsurv) r_n = recq[tw_n + lane];
+        bool stopped = false;  // this wave's later chunks lie beyond U: their counts are 0
+        for (; rt * WG < nch; c = chunk_of(++rt)) {
+            if (c >= nch) continue;
+            if (stopped) {
+                if (lane == 0) cntq[c] = 0;
+                continue;
+            }
+            const uint32_t cbeg = (uint32_t)(c * a.chunk);
+            const uint32_t cend = (uint32_t)min(c * a.chunk + a.chunk, nmemb);
+            uint32_t tw = tw_n;
+            OrdRec r = r_n;
+            const uint64_t cn = chunk_of(rt + 1);
+            if (cn < nch) tw_n = cfq[cn];
+            uint32_t n1 = 0;
+            // ---- coarse: a window of up to 64 of the chunk's leaves at a time
+            for (bool first = true;; first = false) {
+                if (!first) {
+                    r = OrdRec{0u, 0u, 0.f, 0xffffffffu};
+                    if (tw + lane < nsurv) r = recq[tw + lane];
+                }
+                const bool rin = tw + lane < nsurv && r.moff < cend;
+                const uint32_t nin = (uint32_t)__popcll(__ballot(rin));
+                wrec[lane] = r;
+                dev::wave_sync();
+                if (first) {
+                    const float lb0 = wrec[0].lb;
+                    const float low = (float)bin_of(lb0, range) * (range / (float)kNB);
+                    if (lb0 * (1.0f - kRhoLb) > U && low * (1.0f - 2.0f * kRhoLb) > U) {
+                        stopped = true;
+                        break;
+                    }
+                }
+                if (rin && r.moff >= cbeg && !(r.lb * (1.0f - kRhoLb) > U)) ++c_scanned;
+                const uint32_t wb = max(cbeg, wrec[0].moff);
+                const OrdRec rl = wrec[nin - 1];
+                const uint32_t we = (uint32_t)min((uint64_t)cend, (uint64_t)rl.moff + (uint64_t)rl.count);
+                const bool few = nin <= 4;
+                uint32_t e_s[4], b_s[4];
+                float l_s[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    e_s[t] = (uint32_t)__builtin_amdgcn_readlane((int)(r.moff + r.count), t);
+                    b_s[t] = (uint32_t)__builtin_amdgcn_readlane((int)(r.start - r.moff), t);
+                    l_s[t] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.lb), t));
+                }
+                int p = 0;
+                for (uint32_t g0 = wb; g0 < we; g0 += 64 * kFlatIssue) {
+                    uint2 cw[kFlatIssue];
+                    uint32_t mpv[kFlatIssue];
+                    uint32_t live = 0;
+#pragma unroll
+                    for (int i = 0; i < kFlatIssue; ++i) {
+                        const uint32_t g = g0 + (uint32_t)i * 64 + lane;
+                        cw[i] = make_uint2(0u, 0u);
+                        mpv[i] = 0;
+                        if (g < we) {
+                            uint32_t bs;
+                            float lbv;
+                            if (few) {
+                                bs = b_s[0];
+                                lbv = l_s[0];
+#pragma unroll
+                                for (int t = 1; t < 4; ++t)
+                                    if (t < (int)nin && g >= e_s[t - 1]) {
+                                        bs = b_s[t];
+                                        lbv = l_s[t];
+                                    }
+                            } else {
+                                while (p + 1 < (int)nin && wrec[p + 1].moff <= g) ++p;
+                                const OrdRec rp = wrec[p];
+                                bs = rp.start - rp.moff;
+                                lbv = rp.lb;
+                            }
+                            if (!(lbv * (1.0f - kRhoLb) > U)) {
+                                live |= 1u << i;
+                                mpv[i] = bs + g;
+                                cw[i] = a.cwords[mpv[i]];
+                            }
+                        }
+                    }
+                    if (first && g0 == wb) {
+                        r_n = OrdRec{0u, 0u, 0.f, 0xffffffffu};
+                        if (cn < nch && tw_n + lane < nsurv) r_n = recq[tw_n + lane];
+                    }
+#pragma unroll
+                    for (int i = 0; i < kFlatIssue; ++i) {
+                        bool keep = false;
+                        if (live & (1u << i)) {
+                            float sum = 0.f;
+#pragma unroll
+                            for (int j2 = 0; j2 < 8; ++j2) {
+                                const uint32_t half = j2 < 4 ? cw[i].x : cw[i].y;
+                                sum += s_C[j2 * 256 + ((half >> (8 * (j2 & 3))) & 255u)];
+                            }
+                            keep = !(sum * (1.0f - kRhoLb) > U);
+                            ++c_bounded;
+                        }
+                        const uint64_t bal = __ballot(keep);
+                        if (keep) list[n1 + __popcll(bal & lt_mask)] = mpv[i];
+                        n1 += (uint32_t)__popcll(bal);
+                    }
+                }
+                if (nin < 64 || we >= cend) break;
+                tw += 64;
+                dev::wave_sync();
+            }
+            if (stopped) {
+                if (lane == 0) cntq[c] = 0;
+                continue;
+            }
+            dev::wave_sync();
+            // ---- word: the listed members' words and series indices, read
+            // together; survivors straight to the chunk's segment
+            constexpr int kWordIssue = 4;
+            uint32_t n2 = 0;
+            uint32_t* segc = segq + (size_t)c * a.chunk;
+            for (uint32_t e0 = 0; e0 < n1; e0 += 64 * kWordIssue) {
+                uint4 wd[kWordIssue];
+                uint32_t gi[kWordIssue];
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    wd[t] = make_uint4(0u, 0u, 0u, 0u);
+                    gi[t] = 0;
+                    if (e < n1) {
+                        const uint32_t mp = list[e];
+                        wd[t] = a.words[mp];
+                        gi[t] = a.pos[mp];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    bool keep = false;
+                    if (e < n1) {
+                        float sum = 0.f;
+#pragma unroll
+                        for (int i2 = 0; i2 < 16; ++i2) {
+                            if (i2 < a.w) {
+                                const float2 rg = s_rb[word_byte(wd[t], i2)];
+                                const float pl = s_plo[i2], ph = s_phi[i2];
+                                const float d = ph < rg.x ? rg.x - ph : (pl > rg.y ? pl - rg.y : 0.f);
+                                sum += mseg * (d * d);
+                            }
+                        }
+                        keep = !(sum * (1.0f - kRhoLb) > U);
+                        ++c_wordb;
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    if (keep) segc[n2 + __popcll(bal & lt_mask)] = gi[t];
+                    n2 += (uint32_t)__popcll(bal);
+                }
+            }
+            if (lane == 0) cntq[c] = n2;
+            dev::wave_sync();  // the list is refilled by the next chunk
+        }
+    }
+    if (a.blk_cnt) {
+        __shared__ unsigned long long s_cnt[kWaves][3];
+        unsigned long long v[3] = {c_scanned, c_bounded, c_wordb};
+        for (int i = 0; i < 3; ++i)
+            for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
+        if (lane == 0)
+            for (int i = 0; i < 3; ++i) s_cnt[wave][i] = v[i];
+        __syncthreads();
+        if (tid < kBlkCnt) {
+            // slots of the statistics: scanned, coarse-bounded, word-bounded (bytes: 8 + 20 each)
+            unsigned long long t = 0;
+            if (tid == 0 || tid == 1 || tid == 4 || tid == 7)
+                for (int w2 = 0; w2 < kWaves; ++w2) {
+                    const unsigned long long sc = s_cnt[w2][0], cb = s_cnt[w2][1], wbn = s_cnt[w2][2];
+                    t += tid == 0 ? sc : tid == 1 ? cb : tid == 7 ? wbn : cb * 8ull + wbn * 20ull;
+                }
+            unsigned long long* pp = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
+            *pp = (pass == 0 ? 0ull : *pp) + t;
+        }
+    }
+}
+
+// One wave's distances for the series list[eb, ee) (16 lanes per row, 4 rows
+// per round; U one value across the wave): k = 1 lowers U with each
+// distance; k > 1 appends to the candidate buffer and the histogram.
+template <bool VEC>
+__device__ void wave_rows(const QArgs& a, QState& st, int q, int k, const uint32_t* list, uint32_t eb, uint32_t ee,
+                          const float* s_q, float& U, uint32_t& appended, uint32_t& c_dist, uint32_t& c_abandon,
+                          unsigned long long& c_rowb) {
+    const int lane = threadIdx.x & 63;
+    const int quarter = lane >> 4, ql = lane & 15;
+    const int L = a.L;
+    const int nchunk = (L + 63) / 64;
+    for (uint32_t e0 = eb; e0 < ee; e0 += 4) {
+        float Unew = U;
+        const uint32_t e = e0 + quarter;
+        const bool act = e < ee;
+        const uint32_t gidx = act ? list[e] : 0u;
+        bool alive = act;
+        const float* row = a.series + (size_t)gidx * L;
+        float acc = 0.f;
+        for (int g = 0; g < nchunk; g += 4) {
+            if (alive) {
+                if (VEC) {
+                    float4 x[4];
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+                        const int j0 = (g + cc) * 64 + ql * 4;
+                        x[cc] = (g + cc < nchunk && j0 < L) ? *reinterpret_cast<const float4*>(row + j0)
+                                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+                        const int j0 = (g + cc) * 64 + ql * 4;
+                        if (g + cc < nchunk && j0 < L) {
+                            const float4 y = *reinterpret_cast<const float4*>(s_q + j0);
+                            const float d0 = y.x - x[cc].x, d1 = y.y - x[cc].y;
+                            const float d2 = y.z - x[cc].z, d3 = y.w - x[cc].w;
+                            acc = fmaf(d0, d0, acc);
+                            acc = fmaf(d1, d1, acc);
+                            acc = fmaf(d2, d2, acc);
+                            acc = fmaf(d3, d3, acc);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+#pragma unroll
+                        for (int e2 = 0; e2 < 4; ++e2) {
+                            const int jj = (g + cc) * 64 + ql * 4 + e2;
+                            if (g + cc < nchunk && jj < L) {
+                                const float d = s_q[jj] - row[jj];
+                                acc = fmaf(d, d, acc);
+                            }
+                        }
+                    }
+                }
+            }
+            float pp = acc;
+            pp += __shfl_xor(pp, 8, 16);
+            pp += __shfl_xor(pp, 4, 16);
+            pp += __shfl_xor(pp, 2, 16);
+            pp += __shfl_xor(pp, 1, 16);
+            pp = __shfl(pp, quarter * 16, 64);
+            if (alive && ql == 0) c_rowb += (uint64_t)min(4, nchunk - g) * 256u;
+            if (g + 4 < nchunk) {
+                if (alive && pp * (1.0f - kRhoEd) > U) {
+                    alive = false;
+                    if (ql == 0) ++c_abandon;
+                }
+            } else {
+                acc = pp;  // the full distance
+            }
+        }
+        if (act && ql == 0) ++c_dist;
+        if (alive && ql == 0 && acc * (1.0f - kRhoEd) <= U) {
+            const float d = acc;
+            const uint32_t slot = atomicAdd(&st.ncand, 1u);
+            if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{d, gidx};
+            else st.ovf = 1;
+            ++appended;
+            if (k == 1) {
+                const uint32_t ub = __float_as_uint(upper_u(d));
+                atomicMin(&st.U, ub);
+                Unew = fminf(Unew, __uint_as_float(ub));
+            } else {
+                atomicAdd(&a.hist[(size_t)q * kHistBins + hist_bin(d, st.hbase)], 1u);
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) Unew = fminf(Unew, __shfl_xor(Unew, off));
+        U = Unew;
+    }
+}
+
+constexpr int kRefineList = 512;  // fine survivors a wave holds before it computes their distances
+
+template <bool VEC, int pass>
+__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)))
+flat_refine_kernel(QArgs a) {
+    __shared__ float2 s_rf[256];
+    __shared__ float s_pf[64];
+    __shared__ float s_bp[256];
+    __shared__ __align__(16) float s_q[MESSI_MAX_LEN];
+    __shared__ uint32_t s_cpre[kScanThreads + 1];  // exclusive prefix of the survivor counts of a batch of chunks
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_list[kScanThreads / 64][kRefineList];
+    __shared__ float s_llb[kScanThreads / 64][kRefineList];
+    __shared__ uint32_t s_flag;
+    constexpr int kWaves = kScanThreads / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt_mask = dev::lanemask_lt();
+    uint32_t* list = s_list[wave];
+    float* llb = s_llb[wave];
+    const int nq = a.nq;
+    const int B = gridDim.x;
+    const int q = blockIdx.x % nq;
+    const int j = blockIdx.x / nq;
+    const int G = (B - q + nq - 1) / nq;
+    const int L = a.L;
+    uint32_t c_dist = 0, c_abandon = 0, c_fine = 0;
+    unsigned long long c_rowb = 0;
+    QState& st = a.qs[q];
+    if (tid == 0) s_flag = (st.err != 0 || st.nsurv == 0 || (pass == 1 && st.rerun == 0)) ? 1u : 0u;
+    __syncthreads();
+    const bool skip = s_flag != 0;
+    __syncthreads();
+    if (!skip) {
+        const int k = st.k;
+        const uint64_t nmemb = st.nmemb;
+        const uint64_t nch = min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.max_chunks);
+        const bool fine = a.fwords != nullptr;
+        const int A = 1 << a.b;
+        const float inf = __uint_as_float(0x7f800000u);
+        for (int c = tid; c < A - 1; c += kScanThreads) s_bp[c] = a.bp[c];
+        for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
+        const float qamax = st.qamax;
+        __syncthreads();
+        if (fine) {
+            // the fine regions, widened by the fp32 error of a fine PAA value of
+            // data and query, and the query's fine PAA
+            const float u = 5.9604644775390625e-08f;  // 2^-24
+            const float df = 1.01f * (2.f * (float)(a.lg_mf + 1) * u * a.absmax_data +
+                                      2.f * (float)(a.mf + 1) * u * qamax);
+            for (int c = tid; c < A; c += kScanThreads)
+                s_rf[c] = make_float2(c > 0 ? s_bp[c - 1] - df : -inf, c < A - 1 ? s_bp[c] + df : inf);
+            for (int jj = tid; jj < a.wf; jj += kScanThreads) {
+                float sum = 0.f;
+                for (int i = 0; i < a.mf; ++i) sum += s_q[jj * a.mf + i];
+                s_pf[jj] = sum / (float)a.mf;
+            }
+        }
+        __syncthreads();
+        const uint32_t* segq = a.seg + (size_t)q * a.max_chunks * a.chunk;
+        const uint32_t* cntq = a.segcnt + (size_t)q * a.max_chunks;
+        float U = __uint_as_float(vload(&st.U));
+        uint32_t n3 = 0, appended = 0;
+        // the distances of the wave's list, best first for k = 1
+        auto flush = [&]() {
+            U = fminf(U, __uint_as_float(vload(&st.U)));  // other waves' distances
+            if (n3 > 4 && k == 1) {
+                float bl = inf;
+                uint32_t be = 0;
+                for (uint32_t e = lane; e < n3; e += 64)
+                    if (llb[e] < bl) {
+                        bl = llb[e];
+                        be = e;
+                    }
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const float ob = __shfl_xor(bl, off);
+                    const uint32_t oe = __shfl_xor(be, off);
+                    if (ob < bl || (ob == bl && oe < be)) {
+                        bl = ob;
+                        be = oe;
+                    }
+                }
+                dev::wave_sync();
+                if (lane == 0) {
+                    const uint32_t t0 = list[0];
+                    const float f0 = llb[0];
+                    list[0] = list[be];
+                    llb[0] = llb[be];
+                    list[be] = t0;
+                    llb[be] = f0;
+                }
+                dev::wave_sync();
+                wave_rows<VEC>(a, st, q, k, list, 0, 1, s_q, U, appended, c_dist, c_abandon, c_rowb);
+                uint32_t nk = 0;
+                for (uint32_t e0 = 1; e0 < n3; e0 += 64) {
+                    const uint32_t e = e0 + lane;
+                    uint32_t gv = 0;
+                    float fv = 0.f;
+                    bool keep = false;
+                    if (e < n3) {
+                        gv = list[e];
+                        fv = llb[e];
+                        keep = !(fv * (1.0f - kRhoLb) > U);
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    if (keep) {
+                        const uint32_t o = nk + (uint32_t)__popcll(bal & lt_mask);
+                        list[o] = gv;
+                        llb[o] = fv;
+                    }
+                    nk += (uint32_t)__popcll(bal);
+                }
+                dev::wave_sync();
+                wave_rows<VEC>(a, st, q, k, list, 0, nk, s_q, U, appended, c_dist, c_abandon, c_rowb);
+            } else {
+                wave_rows<VEC>(a, st, q, k, list, 0, n3, s_q, U, appended, c_dist, c_abandon, c_rowb);
+            }
+            n3 = 0;
+            dev::wave_sync();
+        };
+        // this block's chunks j, j + G, ..., kScanThreads of them at a time
+        for (uint64_t cb = 0; (uint64_t)j + cb * G < nch; cb += kScanThreads) {
+            const uint64_t cme = (uint64_t)j + (cb + tid) * G;
+            const uint32_t cnt = cme < nch ? cntq[cme] : 0u;
+            uint32_t total;
+            const uint32_t ex = block_exclusive_scan(cnt, s_tmp, total);
+            s_cpre[tid] = ex;
+            if (tid == 0) s_cpre[kScanThreads] = total;
+            __syncthreads();
+            // survivor e of the batch: chunk (largest i with s_cpre[i] <= e) and place in it
+            auto entry = [&](uint32_t e) -> uint32_t {
+                int lo = 0, hi = kScanThreads - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_cpre[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint64_t cc = (uint64_t)j + (cb + (uint64_t)lo) * G;
+                return segq[cc * a.chunk + (e - s_cpre[lo])];
+            };
+            if (fine) {
+                // 4 lanes per series, 16 series per wave and round
+                constexpr int kFineIssue = 4;
+                const int g4 = lane >> 2, l4 = lane & 3;
+                const float mfine = (float)a.mf;
+                const bool part = l4 * 16 < a.wf;
+                for (uint32_t e0 = (uint32_t)wave * 16 * kFineIssue; e0 < total; e0 += kWaves * 16 * kFineIssue) {
+                    uint4 fv[kFineIssue];
+                    uint32_t gx[kFineIssue];
+#pragma unroll
+                    for (int t = 0; t < kFineIssue; ++t) {
+                        const uint32_t e = e0 + (uint32_t)t * 16 + g4;
+                        gx[t] = e < total ? entry(e) : 0u;
+                    }
+#pragma unroll
+                    for (int t = 0; t < kFineIssue; ++t) {
+                        const uint32_t e = e0 + (uint32_t)t * 16 + g4;
+                        fv[t] = make_uint4(0u, 0u, 0u, 0u);
+                        if (e < total && part)
+                            fv[t] = *reinterpret_cast<const uint4*>(a.fwords + (size_t)gx[t] * kFineStride + l4 * 16);
+                    }
+#pragma unroll
+                    for (int t = 0; t < kFineIssue; ++t) {
+                        if (e0 + (uint32_t)t * 16 >= total) break;
+                        const uint32_t e = e0 + (uint32_t)t * 16 + g4;
+                        const bool act = e < total;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int tt = 0; tt < 16; ++tt) {
+                            const int jf = l4 * 16 + tt;
+                            if (jf < a.wf) {
+                                const float2 rg = s_rf[word_byte(fv[t], tt)];
+                                const float pv = s_pf[jf];
+                                const float d = pv < rg.x ? rg.x - pv : (pv > rg.y ? pv - rg.y : 0.f);
+                                acc = fmaf(d, d, acc);
+                            }
+                        }
+                        acc += __shfl_xor(acc, 1, 4);
+                        acc += __shfl_xor(acc, 2, 4);
+                        const float lbf = acc * mfine;
+                        const bool keep = act && l4 == 0 && !(lbf * (1.0f - kRhoLb) > U);
+                        if (act && l4 == 0) ++c_fine;
+                        const uint64_t bal = __ballot(keep);
+                        if (keep) {
+                            const uint32_t o = n3 + (uint32_t)__popcll(bal & lt_mask);
+                            list[o] = gx[t];
+                            llb[o] = lbf;
+                        }
+                        n3 += (uint32_t)__popcll(bal);
+                    }
+                    if (n3 > (uint32_t)(kRefineList - 16 * kFineIssue)) {
+                        dev::wave_sync();
+                        flush();
+                    }
+                }
+            } else {
+                // no fine summary: the word survivors' distances directly
+                for (uint32_t e0 = (uint32_t)wave * 64; e0 < total; e0 += kScanThreads) {
+                    const uint32_t e = e0 + lane;
+                    const bool act = e < total;
+                    const uint32_t gv = act ? entry(e) : 0u;
+                    const uint64_t bal = __ballot(act);
+                    if (act) {
+                        const uint32_t o = n3 + (uint32_t)__popcll(bal & lt_mask);
+                        list[o] = gv;
+                        llb[o] = 0.f;
+                    }
+                    n3 += (uint32_t)__popcll(bal);
+                    if (n3 > (uint32_t)(kRefineList - 64)) {
+                        dev::wave_sync();
+                        flush();
+                    }
+                }
+            }
+            __syncthreads();  // every wave is done with this batch's prefix sums
+        }
+        dev::wave_sync();
+        if (n3) flush();
+        if (k > 1 && __ballot(appended != 0)) wave_hist_refresh(a, q, st, U);
+    }
+    if (a.blk_cnt) {
+        __shared__ unsigned long long s_cnt[kWaves][4];
+        const unsigned long long fine_b = 16ull * (unsigned long long)((a.wf + 15) / 16);
+        unsigned long long v[4] = {c_dist, c_abandon, c_fine, c_rowb};
+        for (int i = 0; i < 4; ++i)
+            for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
+        if (lane == 0)
+            for (int i = 0; i < 4; ++i) s_cnt[wave][i] = v[i];
+        __syncthreads();
+        if (tid < kBlkCnt && (tid == 2 || tid == 3 || tid == 4 || tid == 8)) {
+            // added to the coarse kernel's slots: distances, abandoned, bytes (rows, fine), fine-bounded
+            unsigned long long t = 0;
+            for (int w2 = 0; w2 < kWaves; ++w2)
+                t += tid == 2 ? s_cnt[w2][0] : tid == 3 ? s_cnt[w2][1] : tid == 8 ? s_cnt[w2][2]
+                                                                               : s_cnt[w2][3] + s_cnt[w2][2] * fine_b;
+            unsigned long long* pp = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
+            *pp = (tid == 4 ? *pp : (pass == 0 ? 0ull : *pp)) + t;
         }
     }
 }
@@ -1873,7 +3116,9 @@ int Workspace::ensure_stats() {
 size_t Workspace::device_bytes() const {
     size_t t = 0;
     for (const DevBuf* b : {&qs, &lb, &order, &rec, &chunk_first, &bins, &mbins, &cursor, &hist, &approx_d, &cand,
-                            &counters, &err, &prof, &blk_cnt, &status, &lbpart, &todo, &env, &todo_cnt, &ec, &ec_cnt,
+                            &counters, &err, &prof, &blk_cnt, &status, &lbpart, &seg, &segcnt, &todo, &env,
+                            &todo_cnt,
+                            &ec, &ec_cnt,
                             &qb, &qnorm, &qx, &leaf_cnt, &leaf_off, &leaf_cur, &leaf_q, &leaf_act, &pairs, &npairs})
         t += b->bytes;
     return t;
@@ -1945,6 +3190,17 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
         ws->max_chunks = mc;
         ++ws->gen;
     }
+    if (nq <= kSplitMaxQ && (ws->seg_nq < nq || ws->seg.bytes < sizeof(uint32_t) * (size_t)ws->max_chunks *
+                                                                  (size_t)ix->opts.scan_chunk * (size_t)nq)) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        ws->seg_nq = 0;
+        ++ws->gen;
+        MESSI_TRY(ws->grow(ix, ws->seg, sizeof(uint32_t) * (size_t)ws->max_chunks * (size_t)ix->opts.scan_chunk *
+                                            (size_t)kSplitMaxQ));
+        MESSI_TRY(ws->grow(ix, ws->segcnt, sizeof(uint32_t) * (size_t)ws->max_chunks * (size_t)kSplitMaxQ));
+        ws->seg_nq = kSplitMaxQ;
+        ++ws->gen;
+    }
     if (ws->cand_slots < slots) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         ws->cand_slots = 0;
@@ -1970,8 +3226,8 @@ int scan_grid(int mode) {
         }
         int per = 4;
         const void* fns[3][4] = {
-            {(const void*)scan_kernel<true, 0, kScanEd>, (const void*)scan_kernel<true, 1, kScanEd>,
-             (const void*)scan_kernel<false, 0, kScanEd>, (const void*)scan_kernel<false, 1, kScanEd>},
+            {(const void*)flat_scan_kernel<true, 0>, (const void*)flat_scan_kernel<true, 1>,
+             (const void*)flat_scan_kernel<false, 0>, (const void*)flat_scan_kernel<false, 1>},
             {(const void*)scan_kernel<true, 0, kScanRowFilter>, (const void*)scan_kernel<true, 1, kScanRowFilter>,
              (const void*)scan_kernel<false, 0, kScanRowFilter>, (const void*)scan_kernel<false, 1, kScanRowFilter>},
             {(const void*)scan_kernel<true, 0, kScanDtw>, (const void*)scan_kernel<false, 0, kScanDtw>, nullptr,
@@ -1986,10 +3242,51 @@ int scan_grid(int mode) {
     return blocks;
 }
 
+// Grids of the split scan's kernels: as many blocks as fit at once; the
+// coarse kernel's is the larger (its per-block statistics slots cover the
+// refine kernel's).
+int split_grid(int which) {
+    static int grid[2] = {0, 0};
+    if (!grid[0]) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t p;
+            if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        }
+        int n1 = 0, n2 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, (const void*)flat_coarse_kernel<0>, kScanThreads, 0) !=
+                hipSuccess || n1 < 1)
+            n1 = 4;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, (const void*)flat_refine_kernel<true, 0>, kScanThreads,
+                                                         0) != hipSuccess || n2 < 1)
+            n2 = 4;
+        grid[1] = std::min(cus * n2, 4096);
+        grid[0] = std::max(std::min(cus * n1, 4096), grid[1]);
+    }
+    return grid[which];
+}
+
 // One pass of the ordered scan in the variant the call needs (the DTW
 // variant has no second pass).
-int launch_scan(const QArgs& a, bool vec, int pass, int mode, hipStream_t s) {
+// `between` (may be null): an event recorded between the split scan's kernels.
+int launch_scan(const QArgs& a, bool vec, int pass, int mode, hipStream_t s, hipEvent_t between = nullptr) {
     const dim3 g(scan_grid(mode)), b(kScanThreads);
+    if (mode == kScanEd && a.seg) {
+        const dim3 g1(split_grid(0)), g2(split_grid(1));
+        if (pass) hipLaunchKernelGGL((flat_coarse_kernel<1>), g1, b, 0, s, a);
+        else hipLaunchKernelGGL((flat_coarse_kernel<0>), g1, b, 0, s, a);
+        MESSI_LAUNCH_CHECK("scan_coarse");
+        if (between) MESSI_HIP_TRY(hipEventRecord(between, s));
+        if (vec) {
+            if (pass) hipLaunchKernelGGL((flat_refine_kernel<true, 1>), g2, b, 0, s, a);
+            else hipLaunchKernelGGL((flat_refine_kernel<true, 0>), g2, b, 0, s, a);
+        } else {
+            if (pass) hipLaunchKernelGGL((flat_refine_kernel<false, 1>), g2, b, 0, s, a);
+            else hipLaunchKernelGGL((flat_refine_kernel<false, 0>), g2, b, 0, s, a);
+        }
+        MESSI_LAUNCH_CHECK("scan_refine");
+        return MESSI_OK;
+    }
     if (mode == kScanDtw) {
         if (vec) hipLaunchKernelGGL((scan_kernel<true, 0, kScanDtw>), g, b, 0, s, a);
         else hipLaunchKernelGGL((scan_kernel<false, 0, kScanDtw>), g, b, 0, s, a);
@@ -1999,13 +3296,13 @@ int launch_scan(const QArgs& a, bool vec, int pass, int mode, hipStream_t s) {
     const bool sh = mode == kScanRowFilter;
     const int v = (vec ? 4 : 0) | (pass ? 2 : 0) | (sh ? 1 : 0);
     switch (v) {
-        case 0: hipLaunchKernelGGL((scan_kernel<false, 0, kScanEd>), g, b, 0, s, a); break;
+        case 0: hipLaunchKernelGGL((flat_scan_kernel<false, 0>), g, b, 0, s, a); break;
         case 1: hipLaunchKernelGGL((scan_kernel<false, 0, kScanRowFilter>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((scan_kernel<false, 1, kScanEd>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((flat_scan_kernel<false, 1>), g, b, 0, s, a); break;
         case 3: hipLaunchKernelGGL((scan_kernel<false, 1, kScanRowFilter>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((scan_kernel<true, 0, kScanEd>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((flat_scan_kernel<true, 0>), g, b, 0, s, a); break;
         case 5: hipLaunchKernelGGL((scan_kernel<true, 0, kScanRowFilter>), g, b, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((scan_kernel<true, 1, kScanEd>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((flat_scan_kernel<true, 1>), g, b, 0, s, a); break;
         default: hipLaunchKernelGGL((scan_kernel<true, 1, kScanRowFilter>), g, b, 0, s, a); break;
     }
     if (pass) MESSI_LAUNCH_CHECK("rescan");
@@ -2068,6 +3365,48 @@ struct CallArgs {
     bool matrix_only = false;  // BF16: keep few queries on the matrix-core filter
 };
 
+// The call's arguments that do not depend on where its workspace lives.
+void fill_call_args(const CallArgs& c, uint32_t cap, QArgs& a) {
+    const Index* ix = c.ix;
+    a = QArgs{};
+    a.series = ix->series;
+    a.n = ix->n;
+    a.L = ix->len;
+    a.w = ix->w;
+    a.m = ix->len / ix->w;
+    a.b = ix->b;
+    a.words = ix->words.as<uint4>();
+    a.cwords = ix->cwords.as<uint2>();
+    a.fwords = ix->wf ? ix->fwords.as<uint8_t>() : nullptr;
+    a.wf = ix->wf;
+    a.mf = ix->mf;
+    {
+        int lgf = 0;
+        while ((1 << lgf) < ix->mf) ++lgf;
+        a.lg_mf = lgf;
+    }
+    a.csh = ix->b - std::min(ix->b, 4);
+    a.pos = ix->pos.as<uint32_t>();
+    a.leaves = ix->leaves.as<Leaf>();
+    a.nL = (int32_t)ix->n_leaves;
+    a.bp = ix->bp.as<float>();
+    a.queries = c.queries;
+    a.nq = c.nq;
+    a.cap = cap;
+    a.absmax_data = ix->absmax;
+    int lg = 0;
+    while ((1 << lg) < a.m) ++lg;
+    a.lg_m = lg;
+    a.host_err = nullptr;
+    a.out_idx = c.out_idx;
+    a.out_dist = c.out_dist;
+    a.band = -1;
+    a.rho_d = kRhoEd;
+    a.chunk_lo = 0;
+    a.chunk_hi = 0xffffffffu;
+    a.chunk = (uint32_t)ix->opts.scan_chunk;
+}
+
 int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap, uint32_t cap_min = 0) {
     const Index* ix = c.ix;
     const int32_t nq = c.nq;
@@ -2077,20 +3416,7 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     Workspace* ws = nullptr;
     MESSI_TRY(get_workspace(ix, c.s, nq, cap, &ws));
     *wsp = ws;
-    a = QArgs{};
-    a.series = ix->series;
-    a.n = ix->n;
-    a.L = ix->len;
-    a.w = ix->w;
-    a.m = ix->len / ix->w;
-    a.b = ix->b;
-    a.words = ix->words.as<uint4>();
-    a.pos = ix->pos.as<uint32_t>();
-    a.leaves = ix->leaves.as<Leaf>();
-    a.nL = (int32_t)ix->n_leaves;
-    a.bp = ix->bp.as<float>();
-    a.queries = c.queries;
-    a.nq = nq;
+    fill_call_args(c, cap, a);
     a.qs = ws->qs.as<QState>();
     a.lb = ws->lb.as<float>();
     a.order = ws->order.as<uint32_t>();
@@ -2104,23 +3430,12 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.approx_d = ws->approx_d.as<float>();
     a.lbpart = ws->lbpart.as<LbPart>();
     a.cand = ws->cand.as<Cand>();
-    a.cap = cap;
-    a.absmax_data = ix->absmax;
-    int lg = 0;
-    while ((1 << lg) < a.m) ++lg;
-    a.lg_m = lg;
+    a.seg = nq <= ws->seg_nq ? ws->seg.as<uint32_t>() : nullptr;
+    a.segcnt = nq <= ws->seg_nq ? ws->segcnt.as<uint32_t>() : nullptr;
     a.counters = counting ? ws->counters.as<QCounters>() : nullptr;
     a.prof = counting ? ws->prof.as<unsigned long long>() : nullptr;
     a.err_any = ws->err.as<uint32_t>();
-    a.host_err = nullptr;
     a.blk_cnt = counting ? ws->blk_cnt.as<unsigned long long>() : nullptr;
-    a.out_idx = c.out_idx;
-    a.out_dist = c.out_dist;
-    a.band = -1;
-    a.rho_d = kRhoEd;
-    a.chunk_lo = 0;
-    a.chunk_hi = 0xffffffffu;
-    a.chunk = (uint32_t)ix->opts.scan_chunk;
     return MESSI_OK;
 }
 
@@ -2173,7 +3488,7 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
             MESSI_TRY(bf16_row_prep(ix, a, ws, s));
             a.rf_tau = kRowFilterTau;
         }
-        MESSI_TRY(launch_scan(a, vec, 0, rowf ? kScanRowFilter : kScanEd, s));
+        MESSI_TRY(launch_scan(a, vec, 0, rowf ? kScanRowFilter : kScanEd, s, timing && ws ? ws->ev[8] : nullptr));
         MESSI_TRY(mark(7));
         // k > 1: exact k-th bound and compaction, and a second pass for a
         // query whose buffer overflowed (that pass exits at once otherwise).
@@ -2450,6 +3765,7 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     *err_out = err;
     if (timing) {
         QCounters hc = *ws->h_counters;
+        unsigned long long word_b = 0;
         for (int bb = 0; bb < sg; ++bb) {
             const unsigned long long* h = ws->h_blk_cnt + (size_t)bb * kBlkCnt;
             hc.scanned += h[0];
@@ -2457,6 +3773,7 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
             hc.distance += h[2];
             hc.abandoned += h[3];
             hc.bytes += h[4];
+            word_b += h[7];
         }
         float ms[7] = {0, 0, 0, 0, 0, 0, 0};
         MESSI_HIP_TRY(hipEventElapsedTime(&ms[1], ev[0], ev[2]));
@@ -2481,6 +3798,7 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
         stats->series_recheck = (int64_t)hc.recheck;
         stats->candidates = (int64_t)hc.final_cands;
         stats->bytes_scan = (int64_t)hc.bytes;
+        stats->series_word_bounded = (int64_t)word_b;
         stats->scan_launches = rounds;
     }
     return decode_error(err);
@@ -2545,7 +3863,10 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
     uint32_t err = 0;
     QCounters hc{};
     const bool rowf = row_filter_path(ix, mode, nq, false);
-    const int sg = scan_grid(rowf ? kScanRowFilter : kScanEd);
+    // the split Euclidean scan (few queries): its two kernels keep no block
+    // timing, and its statistics slots span the coarse kernel's grid
+    const bool split = mode == MESSI_MODE_FP32 && a.seg != nullptr;
+    const int sg = split ? split_grid(0) : scan_grid(rowf ? kScanRowFilter : kScanEd);
     const bool fp32 = mode == MESSI_MODE_FP32 || rowf;  // the ordered scan runs
     const unsigned long long* hprof = nullptr;
     const unsigned long long* hcnt = nullptr;
@@ -2563,11 +3884,13 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         if (a.counters)
             MESSI_HIP_TRY(hipMemcpyAsync(ws->h_counters, a.counters, sizeof(QCounters), hipMemcpyDeviceToHost, s));
         if (a.prof && fp32) {
-            MESSI_HIP_TRY(hipMemcpyAsync(ws->h_prof, a.prof, sizeof(unsigned long long) * 4 * sg,
-                                         hipMemcpyDeviceToHost, s));
+            if (!split) {
+                MESSI_HIP_TRY(hipMemcpyAsync(ws->h_prof, a.prof, sizeof(unsigned long long) * 4 * sg,
+                                             hipMemcpyDeviceToHost, s));
+                hprof = ws->h_prof;
+            }
             MESSI_HIP_TRY(hipMemcpyAsync(ws->h_blk_cnt, a.blk_cnt, sizeof(unsigned long long) * kBlkCnt * sg,
                                          hipMemcpyDeviceToHost, s));
-            hprof = ws->h_prof;
             hcnt = ws->h_blk_cnt;
         }
         MESSI_HIP_TRY(hipStreamSynchronize(s));
@@ -2583,7 +3906,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         }
         break;
     }
-    unsigned long long bf_rows = 0;
+    unsigned long long bf_rows = 0, word_b = 0, fine_b = 0;
     for (int bb = 0; hcnt && bb < sg; ++bb) {
         const unsigned long long* h = hcnt + (size_t)bb * kBlkCnt;
         hc.scanned += h[0];
@@ -2593,6 +3916,8 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         hc.bytes += h[4];
         hc.recheck += h[5];
         bf_rows += h[6];
+        word_b += h[7];
+        fine_b += h[8];
     }
     // BF16 mode: a query whose candidates or filter pairs overflowed their
     // buffers is answered again, alone, by the FP32 path (which reruns and
@@ -2630,6 +3955,11 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         if (fp32) {
             float scan_only = 0.f;
             MESSI_HIP_TRY(hipEventElapsedTime(&scan_only, ev[4], ev[7]));
+            if (split) {
+                float coarse = 0.f;
+                MESSI_HIP_TRY(hipEventElapsedTime(&coarse, ev[4], ev[8]));
+                stats->ms_scan_coarse = coarse;
+            }
             stats->ms_scan = scan_only;
             stats->ms_fixup = ms[4] - scan_only;
         } else {
@@ -2646,6 +3976,8 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         stats->series_recheck = (int64_t)hc.recheck;
         stats->candidates = (int64_t)hc.final_cands;
         stats->bytes_scan = (int64_t)hc.bytes;
+        stats->series_word_bounded = (int64_t)word_b;
+        stats->series_fine_bounded = (int64_t)fine_b;
         stats->scan_launches = (hc.reruns ? 2 : 1) + 2 * retries;
         stats->reruns = (int32_t)hc.reruns + retries;
         stats->fallbacks = fallbacks;

@@ -66,7 +66,7 @@ class Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64), ("data_absmax", ctypes.c_float),
                 ("ms_znorm", ctypes.c_double), ("ms_summarize", ctypes.c_double), ("ms_bucket", ctypes.c_double),
                 ("ms_split", ctypes.c_double), ("ms_finalize", ctypes.c_double), ("ms_shadow", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("fine_segments", ctypes.c_int32), ("fine_length", ctypes.c_int32)]
 
 
 class KnnStats(ctypes.Structure):
@@ -82,7 +82,9 @@ class KnnStats(ctypes.Structure):
                 ("scan_ms_block_max", ctypes.c_double), ("ms_bf16_filter", ctypes.c_double),
                 ("ms_bf16_recheck", ctypes.c_double), ("bf16_flops", ctypes.c_int64), ("bf16_rounds", ctypes.c_int32),
                 ("reruns", ctypes.c_int32), ("fallbacks", ctypes.c_int32), ("ms_fixup", ctypes.c_double),
-                ("bf16_stage_queries", ctypes.c_int32), ("bf16_max_leaf_queries", ctypes.c_int32)]
+                ("bf16_stage_queries", ctypes.c_int32), ("bf16_max_leaf_queries", ctypes.c_int32),
+                ("series_word_bounded", ctypes.c_int64), ("series_fine_bounded", ctypes.c_int64),
+                ("ms_scan_coarse", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
