@@ -209,6 +209,29 @@ int messi_knn_ex(const messi_index* index, const float* queries, int32_t nq, con
                  int32_t k_max, int32_t mode, void* stream, int64_t* out_idx, float* out_dist,
                  messi_knn_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the exact
+ * FP32 search of messi_knn_ex (MESSI_MODE_FP32, one k for every query) with
+ * no allocation of any kind.  Its search buffers live in one array of static
+ * device memory of MESSI_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * library's load until the process ends; the caller passes only the inputs
+ * and outputs (device pointers, as messi_knn_ex; out_* are [nq][k]).  The
+ * buffers need about 24 bytes per leaf and query plus the candidate buffer
+ * (at least 8 MiB for one query, 128 KiB per query of a batch below
+ * k = 256, 512 bytes per unit of k above that); a call that needs more than
+ * the array holds fails with MESSI_ENOMEM before any device work.  The
+ * candidate buffer takes whatever the array has left, and an overflow of it
+ * returns MESSI_EOVERFLOW (no retry with a larger buffer).  Every call on a
+ * GPU shares that GPU's array: the library serialises the calls of a process
+ * (each returns after its stream has finished the work), and calls that
+ * overlap on one GPU from outside that lock (another copy of the library)
+ * would race.  The array keeps the last call's contents; the kernels clear
+ * what must start at zero.  Synchronises `stream` (hipStream_t, NULL = null
+ * stream).  Errors as messi_knn_ex. */
+#define MESSI_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int messi_knn_noalloc(const messi_index* index, const float* queries, int32_t nq, int32_t k, void* stream,
+                      int64_t* out_idx, float* out_dist);
+
 void messi_free(messi_index* index); /* NULL-safe; synchronises the device */
 
 int messi_index_info(const messi_index* index, messi_info* out);

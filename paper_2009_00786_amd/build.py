@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmessi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MESSI_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "breakpoints.cpp", "scan.hip", "build.hip", "query.hip", "bf16.hip", "server.cpp"]
+SOURCES = ["api.cpp", "breakpoints.cpp", "scan.hip", "build.hip", "query.hip", "bf16.hip", "server.cpp", "noalloc.hip"]
 HEADERS = ["common.h", "scan.h", "query.h"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed fp32 ALU instructions.

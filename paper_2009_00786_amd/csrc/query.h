@@ -205,6 +205,15 @@ int refresh_bounds(QArgs& a, hipStream_t s);
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
                 uint32_t cap_min = 0, bool matrix_only = false);
+// Exact FP32 k-NN of nq queries at one k (as knn_enqueue in MESSI_MODE_FP32)
+// with every search buffer carved from the device region [base, base + bytes)
+// (256-byte aligned) instead of a workspace: allocates nothing.  The
+// candidate buffers take the room left after the fixed buffers.  MESSI_ENOMEM
+// when even the default candidate buffer does not fit.  Waits for the stream;
+// the region's earlier contents do not matter (the kernels clear what must
+// start at zero).
+int knn_view(const Index* ix, const float* queries, int32_t nq, int32_t k, hipStream_t s, int64_t* out_idx,
+             float* out_dist, void* base, size_t bytes);
 // Default candidate slots per query for a call of nq queries with k <= kmax.
 uint32_t default_cap(const Index* ix, int32_t nq, int32_t kmax, int32_t mode);
 int knn_error_code(uint32_t err);

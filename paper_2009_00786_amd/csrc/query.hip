@@ -3551,6 +3551,90 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
     return MESSI_OK;
 }
 
+// ---- a search whose buffers lie in one caller-provided device region ----
+namespace {
+
+// Byte offsets of a call's buffers in the region, each 256-byte aligned; the
+// candidate buffers come last, so that they take whatever room is left.
+struct ViewLayout {
+    size_t err, qs, lb, order, rec, chunk_first, bins, mbins, cursor, hist, approx_d, lbpart, cand;
+};
+
+ViewLayout view_layout(const Index* ix, int32_t nq) {
+    const size_t nL = (size_t)ix->n_leaves, q = (size_t)nq;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = (o + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    ViewLayout v{};
+    v.err = take(sizeof(uint32_t) * 4);
+    v.qs = take(sizeof(QState) * q);
+    v.lb = take(sizeof(float) * nL * q);
+    v.order = take(sizeof(uint32_t) * nL * q);
+    v.rec = take(sizeof(OrdRec) * nL * q);
+    v.chunk_first = take(sizeof(uint32_t) * (size_t)max_chunks_of(ix) * q);
+    v.bins = take(sizeof(uint32_t) * kNB * q);
+    v.mbins = take(sizeof(uint32_t) * kNB * q);
+    v.cursor = take(sizeof(unsigned long long) * kNB * q);
+    v.hist = take(sizeof(uint32_t) * kHistBins * q);
+    v.approx_d = take(sizeof(float) * kApproxMax * q);
+    v.lbpart = take(sizeof(LbPart) * q * ((nL + kLeafBlock - 1) / kLeafBlock));
+    v.cand = o;
+    return v;
+}
+
+}  // namespace
+
+int knn_view(const Index* ix, const float* queries, int32_t nq, int32_t k, hipStream_t s, int64_t* out_idx,
+             float* out_dist, void* base, size_t bytes) {
+    if (((uintptr_t)base & 255u) != 0) {
+        set_error(MESSI_EINVAL, "search region must be 256-byte aligned");
+        return MESSI_EINVAL;
+    }
+    const ViewLayout v = view_layout(ix, nq);
+    const uint32_t cap0 = default_cap(ix, nq, k, MESSI_MODE_FP32);
+    const size_t need = v.cand + sizeof(Cand) * (size_t)cap0 * (size_t)nq;
+    if (need > bytes) {
+        set_error(MESSI_ENOMEM, "the search needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                                    std::to_string(bytes) + " bytes of the fixed region");
+        return MESSI_ENOMEM;
+    }
+    // every candidate slot the region holds (at least the default buffer), so
+    // an overflow, which cannot be retried with a larger buffer here, is rarer
+    const size_t fit = (bytes - v.cand) / (sizeof(Cand) * (size_t)nq);
+    const uint32_t cap = (uint32_t)std::min<size_t>(fit, (size_t)1 << 28);
+    CallArgs c{ix, queries, nq, k, nullptr, MESSI_MODE_FP32, s, out_idx, out_dist};
+    QArgs a;
+    fill_call_args(c, cap, a);
+    char* b = static_cast<char*>(base);
+    a.err_any = reinterpret_cast<uint32_t*>(b + v.err);
+    a.qs = reinterpret_cast<QState*>(b + v.qs);
+    a.lb = reinterpret_cast<float*>(b + v.lb);
+    a.order = reinterpret_cast<uint32_t*>(b + v.order);
+    a.rec = reinterpret_cast<OrdRec*>(b + v.rec);
+    a.chunk_first = reinterpret_cast<uint32_t*>(b + v.chunk_first);
+    a.max_chunks = max_chunks_of(ix);
+    a.bins = reinterpret_cast<uint32_t*>(b + v.bins);
+    a.mbins = reinterpret_cast<uint32_t*>(b + v.mbins);
+    a.cursor = reinterpret_cast<unsigned long long*>(b + v.cursor);
+    a.hist = reinterpret_cast<uint32_t*>(b + v.hist);
+    a.approx_d = reinterpret_cast<float*>(b + v.approx_d);
+    a.lbpart = reinterpret_cast<LbPart*>(b + v.lbpart);
+    a.cand = reinterpret_cast<Cand*>(b + v.cand);
+    a.seg = nullptr;  // the single-kernel scan (no survivor segments)
+    a.segcnt = nullptr;
+    a.counters = nullptr;
+    a.prof = nullptr;
+    a.blk_cnt = nullptr;
+    MESSI_TRY(launch_search(c, a, nullptr, cap, false, [](int) { return MESSI_OK; }));
+    uint32_t err = 0;
+    MESSI_HIP_TRY(hipMemcpyAsync(&err, a.err_any, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    return decode_error(err);
+}
+
 // Rounds of the DTW search: the first takes each query's first 16 chunks of
 // its order (its best leaves, for a tight bound early; at most 16K members,
 // so its candidates fit any query's buffer while the bound is still the

@@ -31,7 +31,7 @@ MAX_K = 1024
 EXPORTED = [
     "messi_build", "messi_build_ex", "messi_knn", "messi_knn_ex", "messi_free", "messi_index_info",
     "messi_export_words", "messi_export_leaves", "messi_znorm", "messi_windows", "messi_knn_dtw", "messi_append",
-    "messi_breakpoints",
+    "messi_breakpoints", "messi_knn_noalloc",
     "messi_last_error",
     "messi_server_create", "messi_server_submit", "messi_server_poll", "messi_server_stats", "messi_server_clock_ms",
     "messi_server_destroy",
@@ -119,6 +119,8 @@ def load():
         lib.messi_knn.restype = ctypes.c_int
         lib.messi_knn_ex.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(KnnStats)]
         lib.messi_knn_ex.restype = ctypes.c_int
+        lib.messi_knn_noalloc.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+        lib.messi_knn_noalloc.restype = ctypes.c_int
         lib.messi_free.argtypes = [vp]
         lib.messi_free.restype = None
         lib.messi_index_info.argtypes = [vp, ctypes.POINTER(Info)]
@@ -308,6 +310,18 @@ class Index:
         out_dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
         _check(load().messi_knn(self._h, ctypes.c_void_p(queries.data_ptr()), nq, k,
                                 ctypes.c_void_p(out_idx.data_ptr()), ctypes.c_void_p(out_dist.data_ptr())))
+        return out_idx, out_dist
+
+    def knn_noalloc(self, queries, k: int, out, stream=None):
+        """messi_knn_noalloc: the FP32 exact search with its buffers in the library's
+        static device array.  `out` = (idx int64 [nq, k], dist fp32 [nq, k]), CUDA,
+        caller-allocated (the call itself allocates nothing)."""
+        import torch
+        assert queries.is_cuda and queries.dtype == torch.float32 and queries.is_contiguous()
+        out_idx, out_dist = out
+        _check(load().messi_knn_noalloc(self._h, ctypes.c_void_p(queries.data_ptr()), queries.shape[0], k,
+                                        _stream_ptr(stream), ctypes.c_void_p(out_idx.data_ptr()),
+                                        ctypes.c_void_p(out_dist.data_ptr())))
         return out_idx, out_dist
 
     def knn_dtw(self, queries, k: int, band: int, stream=None, stats: bool = False, out=None):
