@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(256) summarize_seg_kernel(SegArgs a) {
             amax_bits = max(amax_bits, mx);
             if (a.fine != nullptr) {
                 // the fine summary (m == M here): F sub-segments of MF values,
-                // each summed by fold-halving and scaled, and their symbols
+                // each summed by fold-halving and scaled, and their 8-bit codes
                 constexpr int F = M >= 4 ? 4 : M;
                 constexpr int MF = M / F;
                 uint32_t packed = 0;
@@ -476,7 +476,7 @@ __global__ void __launch_bounds__(256) summarize_seg_kernel(SegArgs a) {
                     for (int h = MF / 2; h >= 1; h /= 2)
 #pragma unroll
                         for (int i = 0; i < h; ++i) f[i] = __fadd_rn(f[i], f[i + h]);
-                    packed |= (uint32_t)symbol(__fmul_rn(f[0], 1.0f / (float)MF)) << (8 * t);
+                    packed |= (uint32_t)fine_code(__fmul_rn(f[0], 1.0f / (float)MF)) << (8 * t);
                 }
                 uint8_t* dst = a.fine + (size_t)row * kFineStride + seg * F;
                 if (live) {
@@ -557,16 +557,11 @@ void cell_table(const float* bp, int card_bits, uint8_t* cells) {
 // ---------------------------------------------------------------------------
 // Fine summary on its own (builds whose summarise pass does not produce it:
 // z-normalisation fused into the summary): one thread per (row, fine
-// segment) of MF values, summed by fold-halving and scaled; the symbol by
-// binary search over the breakpoints.
+// segment) of MF values, summed by fold-halving and scaled, and its code.
 // ---------------------------------------------------------------------------
 template <int MF>
 __global__ void __launch_bounds__(256) fine_kernel(const float* __restrict__ in, int64_t n, int L, int wf,
-                                                   const float* __restrict__ bp, int b, uint8_t* __restrict__ fine) {
-    __shared__ float s_bp[256];
-    const int A = 1 << b;
-    for (int i = threadIdx.x; i < A - 1; i += blockDim.x) s_bp[i] = bp[i];
-    __syncthreads();
+                                                   uint8_t* __restrict__ fine) {
     const int64_t total = n * (int64_t)wf;
     for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
          id += (int64_t)gridDim.x * blockDim.x) {
@@ -580,23 +575,15 @@ __global__ void __launch_bounds__(256) fine_kernel(const float* __restrict__ in,
         for (int h = MF / 2; h >= 1; h /= 2)
 #pragma unroll
             for (int i = 0; i < h; ++i) f[i] = __fadd_rn(f[i], f[i + h]);
-        const float p = __fmul_rn(f[0], 1.0f / (float)MF);
-        int lo = 0, hi = A - 1;  // the number of breakpoints <= p
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_bp[mid - 1] <= p) lo = mid;
-            else hi = mid - 1;
-        }
-        fine[(size_t)row * kFineStride + j] = (uint8_t)lo;
+        fine[(size_t)row * kFineStride + j] = (uint8_t)fine_code(__fmul_rn(f[0], 1.0f / (float)MF));
     }
 }
 
-int launch_fine(const float* in, int64_t n, int L, int wf, int mf, const float* bp, int b, uint8_t* fine,
-                hipStream_t s) {
+int launch_fine(const float* in, int64_t n, int L, int wf, int mf, uint8_t* fine, hipStream_t s) {
     const int blocks = (int)std::min<int64_t>((n * wf + 255) / 256, 16 * (int64_t)device_cu_count());
     switch (mf) {
 #define MESSI_FINE_CASE(MM) \
-    case MM: hipLaunchKernelGGL(fine_kernel<MM>, dim3(blocks), dim3(256), 0, s, in, n, L, wf, bp, b, fine); break;
+    case MM: hipLaunchKernelGGL(fine_kernel<MM>, dim3(blocks), dim3(256), 0, s, in, n, L, wf, fine); break;
         MESSI_FINE_CASE(1)
         MESSI_FINE_CASE(2)
         MESSI_FINE_CASE(4)
@@ -1311,7 +1298,7 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     if (ix->wf && !seg_path) {
         // the summarise pass that ran does not write the fine summary: a pass of its own
         tm.start();
-        MESSI_TRY(launch_fine(series, n, len, ix->wf, ix->mf, ix->bp.as<float>(), b, ix->fwords.as<uint8_t>(), s));
+        MESSI_TRY(launch_fine(series, n, len, ix->wf, ix->mf, ix->fwords.as<uint8_t>(), s));
         ix->info.ms_summarize += tm.stop_ms();
     }
 

@@ -92,6 +92,16 @@ static_assert(sizeof(Leaf) == 40, "leaf layout");
 // Row stride in bytes of the fine summaries (at most 64 segments).
 constexpr int kFineStride = 64;
 
+// A fine summary value p is stored as the 8-bit code floor((fl(p + 4) * 32)),
+// clamped to [0, 255]: steps of 1/32 over [-4, 4).  Code c stands for
+// [c / 32 - 4, (c + 1) / 32 - 4) (open-ended for 0 and 255); fl(p + 4) is off
+// by at most 2^-22 from p + 4, which the search adds to its widening.
+__host__ __device__ inline int fine_code(float p) {
+    const float t = (p + 4.0f) * 32.0f;
+    return (int)fminf(fmaxf(t, 0.0f), 255.0f);
+}
+constexpr float kFineCodeSlack = 4.76837158203125e-07f;  // 2^-21: twice the rounding of p + 4
+
 // Fine summary of an index of segment length m: F = min(4, m) fine segments
 // per segment when m is a power of two in [2, 64], else none.
 inline int fine_per_segment(int m) {

@@ -69,6 +69,8 @@ struct QState {
     int32_t hbase;           // histogram bin of a distance = (float bits >> 16) - hbase, clamped
     uint32_t rerun;          // the scan runs a second pass from a tightened bound
     float qamax;             // largest |value| of the query
+    uint32_t skip_start;     // first member of the leaf whose distances the first bound appended
+                             //   as candidates (the scan's first pass skips it); ~0: none
 };
 
 // Counters accumulated over a call (device).
@@ -85,6 +87,7 @@ struct QArgs {
     const uint8_t* fwords;       // [n][kFineStride] fine summaries, input order (nullptr: none)
     int32_t wf, mf, lg_mf;       // fine segments, their length, ceil(log2 mf)
     int32_t csh;                 // coarse symbol = symbol >> csh
+    int32_t skip_approx;         // 1: the first bound's leaf is appended as candidates, not scanned (split scan)
     const uint32_t* pos;
     const Leaf* leaves;
     int32_t nL;

@@ -162,6 +162,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
             st.norm2 = qs.norm2;
             st.delta = qs.delta;
             st.qamax = qs.amax;
+            st.skip_start = 0xffffffffu;
             st.U = 0x7f800000u;  // +inf until the first bound
             st.ncand = 0;
             st.nmemb = 0;
@@ -468,6 +469,12 @@ __global__ void __launch_bounds__(256) approx_cands_kernel(QArgs a, uint32_t nlb
 // --------------------------------------------------------------------------
 // order: counting sort of the surviving leaves into bound bins
 // --------------------------------------------------------------------------
+// Candidate-distance histogram bin of d (top 16 float bits, from hbase).
+__device__ __forceinline__ uint32_t hist_bin(float d, int32_t hbase) {
+    const int32_t b = (int32_t)(__float_as_uint(d) >> 16) - hbase;
+    return (uint32_t)min(max(b, 0), kHistBins - 1);
+}
+
 __device__ __forceinline__ int bin_of(float lbv, float range) {
     const float f = lbv / range * (float)kNB;
     if (!(f >= 0.f)) return 0;
@@ -492,6 +499,30 @@ __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a, uint32_t nlb) {
     }
     const FirstBound f = first_bound(a, q, st.k, nlb, sm);
     if (blockIdx.x == 0 && threadIdx.x == 0) store_first_bound(st, f);
+    if (blockIdx.x == 0 && a.skip_approx) {
+        // The first bound's members are exactly one leaf (the one of smallest
+        // bound, of at least k and at most kApproxMax members): their fp32
+        // distances, already computed, go to the candidates here (those within
+        // the first bound), and the scan's first pass skips the leaf.
+        const uint32_t leaf = (uint32_t)(f.best & 0xffffffffull);
+        const Leaf lf = a.leaves[leaf];
+        uint32_t r0, cnt;
+        approx_range(a, leaf, st.k, r0, cnt);
+        if (r0 == lf.start && cnt == lf.count && !isinf(f.U0)) {
+            const float* d = a.approx_d + (size_t)q * kApproxMax;
+            const int32_t hb = (int32_t)(__float_as_uint(f.U0) >> 16) - (kHistBins - 2);  // as store_first_bound
+            for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+                const float di = d[i];
+                if (di * (1.0f - kRhoEd) <= f.U0) {
+                    const uint32_t slot = atomicAdd(&st.ncand, 1u);
+                    if (slot < a.cap) a.cand[(size_t)q * a.cap + slot] = Cand{di, a.pos[r0 + i]};
+                    else st.ovf = 1;
+                    if (st.k > 1) atomicAdd(&a.hist[(size_t)q * kHistBins + hist_bin(di, hb)], 1u);
+                }
+            }
+            if (threadIdx.x == 0) st.skip_start = lf.start;
+        }
+    }
     __syncthreads();
     const float U0 = f.U0, range = f.range();
     for (int l = blockIdx.x * kLeafBlock + threadIdx.x; l < a.nL; l += gridDim.x * kLeafBlock) {
@@ -600,10 +631,6 @@ __device__ __forceinline__ float bf16_dot8(const uint4& x, const uint4& y, float
     return acc;
 }
 
-__device__ __forceinline__ uint32_t hist_bin(float d, int32_t hbase) {
-    const int32_t b = (int32_t)(__float_as_uint(d) >> 16) - hbase;
-    return (uint32_t)min(max(b, 0), kHistBins - 1);
-}
 
 // Lower U from the histogram (block-wide; call from every thread).
 __device__ void hist_refresh(const QArgs& a, int q, QState& st, uint32_t* s_tmp, float* s_Ublk) {
@@ -1452,9 +1479,9 @@ flat_scan_kernel(QArgs a) {
             if (fine) {
                 const float u = 5.9604644775390625e-08f;  // 2^-24
                 const float df = 1.01f * (2.f * (float)(a.lg_mf + 1) * u * a.absmax_data +
-                                          2.f * (float)(a.mf + 1) * u * qamax);
-                for (int c = tid; c < A; c += kScanThreads)
-                    s_rf[c] = make_float2(c > 0 ? s_bp[c - 1] - df : -inf, c < A - 1 ? s_bp[c] + df : inf);
+                                          2.f * (float)(a.mf + 1) * u * qamax) + kFineCodeSlack;
+                for (int c = tid; c < 256; c += kScanThreads)
+                    s_rf[c] = make_float2(c > 0 ? (float)c * 0.03125f - 4.0f - df : -inf, c < 255 ? (float)(c + 1) * 0.03125f - 4.0f + df : inf);
                 for (int jj = tid; jj < a.wf; jj += kScanThreads) {
                     float sum = 0.f;
                     for (int i = 0; i < a.mf; ++i) sum += s_q[jj * a.mf + i];
@@ -1964,6 +1991,7 @@ flat_coarse_kernel(QArgs a) {
         const uint64_t WG = (uint64_t)G * kWaves;
         const float mseg = (float)a.m;
         const float U = __uint_as_float(vload(&st.U));
+        const uint32_t skip = st.skip_start;
         const uint64_t wi = (uint64_t)j * kWaves + wave;
         auto chunk_of = [&](uint64_t t) -> uint64_t { return t * WG + ((t & 1) ? WG - 1 - wi : wi); };
         uint64_t rt = 0;
@@ -2003,6 +2031,12 @@ flat_coarse_kernel(QArgs a) {
                         break;
                     }
                 }
+                if (pass == 0 && r.start == skip) {
+                    // the first bound's leaf: its candidates are in already
+                    r.lb = __uint_as_float(0x7f800000u);
+                    wrec[lane].lb = r.lb;
+                }
+                dev::wave_sync();
                 if (rin && r.moff >= cbeg && !(r.lb * (1.0f - kRhoLb) > U)) ++c_scanned;
                 const uint32_t wb = max(cbeg, wrec[0].moff);
                 const OrdRec rl = wrec[nin - 1];
@@ -2290,9 +2324,9 @@ flat_refine_kernel(QArgs a) {
             // data and query, and the query's fine PAA
             const float u = 5.9604644775390625e-08f;  // 2^-24
             const float df = 1.01f * (2.f * (float)(a.lg_mf + 1) * u * a.absmax_data +
-                                      2.f * (float)(a.mf + 1) * u * qamax);
-            for (int c = tid; c < A; c += kScanThreads)
-                s_rf[c] = make_float2(c > 0 ? s_bp[c - 1] - df : -inf, c < A - 1 ? s_bp[c] + df : inf);
+                                      2.f * (float)(a.mf + 1) * u * qamax) + kFineCodeSlack;
+            for (int c = tid; c < 256; c += kScanThreads)
+                s_rf[c] = make_float2(c > 0 ? (float)c * 0.03125f - 4.0f - df : -inf, c < 255 ? (float)(c + 1) * 0.03125f - 4.0f + df : inf);
             for (int jj = tid; jj < a.wf; jj += kScanThreads) {
                 float sum = 0.f;
                 for (int i = 0; i < a.mf; ++i) sum += s_q[jj * a.mf + i];
@@ -3431,6 +3465,7 @@ int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint
     a.lbpart = ws->lbpart.as<LbPart>();
     a.cand = ws->cand.as<Cand>();
     a.seg = nq <= ws->seg_nq ? ws->seg.as<uint32_t>() : nullptr;
+    a.skip_approx = (a.seg != nullptr && c.mode == MESSI_MODE_FP32) ? 1 : 0;
     a.segcnt = nq <= ws->seg_nq ? ws->segcnt.as<uint32_t>() : nullptr;
     a.counters = counting ? ws->counters.as<QCounters>() : nullptr;
     a.prof = counting ? ws->prof.as<unsigned long long>() : nullptr;
