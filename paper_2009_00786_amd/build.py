@@ -25,7 +25,7 @@ HEADERS = ["common.h", "scan.h", "query.h"]
 # -packed-fp32-ops: keep the compiler from emitting packed fp32 ALU instructions.
 COMMON_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                "-Wall", "-Wno-unused-function"]
+                "-Wall", "-Wno-unused-function", "-Wno-pass-failed"]
 
 
 def _compile(src: str) -> str:

@@ -1343,6 +1343,8 @@ scan_kernel(QArgs a) {
 // stages touch a few percent of the members each.
 constexpr int kFlatList = kChunk;  // list entries per wave: a chunk's members at most
 constexpr int kFlatIssue = 8;      // coarse words in flight per lane
+constexpr int kCoarseList = 1024;  // coarse survivors a wave of the split scan's first kernel holds
+constexpr int kWordIssue = 4;      // words in flight per lane in that kernel's word stage
 
 // Lower U from the histogram of candidate distances (one wave).
 __device__ void wave_hist_refresh(const QArgs& a, int q, QState& st, float& U) {
@@ -1951,14 +1953,18 @@ __device__ void coarse_word_tables(const QArgs& a, const QState& st, float* s_bp
     __syncthreads();
 }
 
+// The occupancy request of 6 is not met (LDS allows five blocks per CU), but
+// it makes the register allocator stay at 99 VGPRs with no spills; that ran
+// 0.123 ms per query against 0.137 ms with a request of 5 (96 VGPRs and
+// three spilled) and 0.133 ms with 4 (117 VGPRs).
 template <int pass>
-__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(6)))
 flat_coarse_kernel(QArgs a) {
     __shared__ float s_C[8 * 256];
     __shared__ float2 s_rb[256];
     __shared__ float s_plo[16], s_phi[16];
     __shared__ float s_bp[256];
-    __shared__ uint32_t s_list[kScanThreads / 64][kFlatList];
+    __shared__ uint32_t s_list[kScanThreads / 64][kCoarseList];
     __shared__ OrdRec s_rec[kScanThreads / 64][64];
     __shared__ uint32_t s_flag;
     constexpr int kWaves = kScanThreads / 64;
@@ -2013,6 +2019,53 @@ flat_coarse_kernel(QArgs a) {
             const uint64_t cn = chunk_of(rt + 1);
             if (cn < nch) tw_n = cfq[cn];
             uint32_t n1 = 0;
+            // ---- word: the listed members' words and series indices, read
+            // together; survivors straight to the chunk's segment (called
+            // when the list could not take another batch, and at the end)
+            uint32_t n2 = 0;
+            uint32_t* segc = segq + (size_t)c * a.chunk;
+            auto word_stage = [&]() {
+            dev::wave_sync();
+            for (uint32_t e0 = 0; e0 < n1; e0 += 64 * kWordIssue) {
+                uint4 wd[kWordIssue];
+                uint32_t gi[kWordIssue];
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    wd[t] = make_uint4(0u, 0u, 0u, 0u);
+                    gi[t] = 0;
+                    if (e < n1) {
+                        const uint32_t mp = list[e];
+                        wd[t] = a.words[mp];
+                        gi[t] = a.pos[mp];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    bool keep = false;
+                    if (e < n1) {
+                        float sum = 0.f;
+#pragma unroll
+                        for (int i2 = 0; i2 < 16; ++i2) {
+                            if (i2 < a.w) {
+                                const float2 rg = s_rb[word_byte(wd[t], i2)];
+                                const float pl = s_plo[i2], ph = s_phi[i2];
+                                const float d = ph < rg.x ? rg.x - ph : (pl > rg.y ? pl - rg.y : 0.f);
+                                sum += mseg * (d * d);
+                            }
+                        }
+                        keep = !(sum * (1.0f - kRhoLb) > U);
+                        ++c_wordb;
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    if (keep) segc[n2 + __popcll(bal & lt_mask)] = gi[t];
+                    n2 += (uint32_t)__popcll(bal);
+                }
+            }
+            n1 = 0;
+            dev::wave_sync();
+            };
             // ---- coarse: a window of up to 64 of the chunk's leaves at a time
             for (bool first = true;; first = false) {
                 if (!first) {
@@ -2106,6 +2159,7 @@ flat_coarse_kernel(QArgs a) {
                         if (keep) list[n1 + __popcll(bal & lt_mask)] = mpv[i];
                         n1 += (uint32_t)__popcll(bal);
                     }
+                    if (n1 > (uint32_t)(kCoarseList - 64 * kFlatIssue)) word_stage();
                 }
                 if (nin < 64 || we >= cend) break;
                 tw += 64;
@@ -2115,49 +2169,7 @@ flat_coarse_kernel(QArgs a) {
                 if (lane == 0) cntq[c] = 0;
                 continue;
             }
-            dev::wave_sync();
-            // ---- word: the listed members' words and series indices, read
-            // together; survivors straight to the chunk's segment
-            constexpr int kWordIssue = 4;
-            uint32_t n2 = 0;
-            uint32_t* segc = segq + (size_t)c * a.chunk;
-            for (uint32_t e0 = 0; e0 < n1; e0 += 64 * kWordIssue) {
-                uint4 wd[kWordIssue];
-                uint32_t gi[kWordIssue];
-#pragma unroll
-                for (int t = 0; t < kWordIssue; ++t) {
-                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
-                    wd[t] = make_uint4(0u, 0u, 0u, 0u);
-                    gi[t] = 0;
-                    if (e < n1) {
-                        const uint32_t mp = list[e];
-                        wd[t] = a.words[mp];
-                        gi[t] = a.pos[mp];
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < kWordIssue; ++t) {
-                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
-                    bool keep = false;
-                    if (e < n1) {
-                        float sum = 0.f;
-#pragma unroll
-                        for (int i2 = 0; i2 < 16; ++i2) {
-                            if (i2 < a.w) {
-                                const float2 rg = s_rb[word_byte(wd[t], i2)];
-                                const float pl = s_plo[i2], ph = s_phi[i2];
-                                const float d = ph < rg.x ? rg.x - ph : (pl > rg.y ? pl - rg.y : 0.f);
-                                sum += mseg * (d * d);
-                            }
-                        }
-                        keep = !(sum * (1.0f - kRhoLb) > U);
-                        ++c_wordb;
-                    }
-                    const uint64_t bal = __ballot(keep);
-                    if (keep) segc[n2 + __popcll(bal & lt_mask)] = gi[t];
-                    n2 += (uint32_t)__popcll(bal);
-                }
-            }
+            word_stage();
             if (lane == 0) cntq[c] = n2;
             dev::wave_sync();  // the list is refilled by the next chunk
         }
