@@ -336,9 +336,10 @@ typedef struct {
  * HIP stream with its own workspace, that run concurrently.  A lane's launch
  * is recorded once per batch shape into a HIP graph and replayed afterwards.
  * In BF16 mode, a query that is alone in the queue when a lane frees up is a
- * launch of one, answered by the ordered scan with the BF16 row filter (see
- * messi_knn; unless MESSI_SERVER_BATCH_ONLY), since a batch of one gains
- * nothing from the matrix-core filter.  A result never
+ * launch of one (unless MESSI_SERVER_BATCH_ONLY), since a batch of one gains
+ * nothing from the matrix-core filter: the FP32 search when the index has a
+ * fine summary (messi_info.fine_segments > 0), else the ordered scan with the
+ * BF16 row filter (see messi_knn_ex).  A result never
  * depends on which queries shared its batch: each query carries its own
  * status, and a query whose BF16 buffers overflow is answered again, alone,
  * in FP32 mode before its result is posted.
@@ -366,7 +367,7 @@ int messi_server_poll(messi_server* server, messi_result* out, int32_t max_out);
 typedef struct {
     int64_t batches;          /* launches (a batch, or one query alone) */
     int64_t bf16_batches;     /* of which in BF16 mode */
-    int64_t row_filter;       /* BF16 launches of one query (the row-filtered scan) */
+    int64_t row_filter;       /* BF16 launches of one query, answered alone (see above) */
     int64_t requeued;         /* queries re-queued after a buffer overflow */
     int64_t eager_launches;   /* launches enqueued operation by operation */
     int64_t graphs_recorded;  /* launches recorded into a new HIP graph (then replayed) */

@@ -704,7 +704,7 @@ __global__ void __launch_bounds__(256) refresh_kernel(QArgs a) {
     refresh_compact(a, q, st, s_hist, s_b, s_tmp);
 }
 
-// After scan pass `pass`.  If the candidate buffer overflowed, the cap
+// After scan pass `pass` (2: between the rounds of pass 0).  If the candidate buffer overflowed, the cap
 // candidates it holds are exact distances of distinct series, so their k-th is
 // a valid bound: take it, empty the buffer and the histogram, and let the
 // second pass rescan from that much tighter bound.  A second overflow means
@@ -718,6 +718,14 @@ __global__ void __launch_bounds__(256) fixup_kernel(QArgs a, int pass) {
     QState& st = a.qs[q];
     if (st.err) return;
     if (pass == 1 && !st.rerun) return;
+    if (st.ovf && pass == 2) {
+        // between the two rounds of a split scan: tighten U from the full
+        // buffer's k-th but keep it (and the overflow) for the end of pass 0
+        const Cand* c = a.cand + (size_t)q * a.cap;
+        const float kth = block_kth([&](uint32_t i) { return c[i].d; }, a.cap, (uint32_t)st.k, s_hist, s_b);
+        if (threadIdx.x == 0 && !isinf(kth) && !isnan(kth)) atomicMin(&st.U, __float_as_uint(upper_u(kth)));
+        return;
+    }
     if (st.ovf) {
         if (pass == 1) {
             if (threadIdx.x == 0) {
@@ -1344,6 +1352,7 @@ scan_kernel(QArgs a) {
 constexpr int kFlatList = kChunk;  // list entries per wave: a chunk's members at most
 constexpr int kFlatIssue = 8;      // coarse words in flight per lane
 constexpr int kCoarseList = 1024;  // coarse survivors a wave of the split scan's first kernel holds
+constexpr uint32_t kSplitFirst = 64;  // chunks of the split scan's first round
 constexpr int kWordIssue = 4;      // words in flight per lane in that kernel's word stage
 
 // Lower U from the histogram of candidate distances (one wave).
@@ -1988,7 +1997,8 @@ flat_coarse_kernel(QArgs a) {
         const uint32_t nsurv = st.nsurv;
         const uint64_t nmemb = st.nmemb;
         const float range = st.range;
-        const uint64_t nch = min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.max_chunks);
+        // this round's chunks: [chunk_lo, nch)
+        const uint64_t nch = min(min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.max_chunks), (uint64_t)a.chunk_hi);
         coarse_word_tables(a, st, s_bp, s_plo, s_phi, s_rb, s_C);
         const uint32_t* cfq = a.chunk_first + (size_t)q * a.max_chunks;
         const OrdRec* recq = a.rec + (size_t)q * a.nL;
@@ -1999,14 +2009,16 @@ flat_coarse_kernel(QArgs a) {
         const float U = __uint_as_float(vload(&st.U));
         const uint32_t skip = st.skip_start;
         const uint64_t wi = (uint64_t)j * kWaves + wave;
-        auto chunk_of = [&](uint64_t t) -> uint64_t { return t * WG + ((t & 1) ? WG - 1 - wi : wi); };
+        auto chunk_of = [&](uint64_t t) -> uint64_t {
+            return (uint64_t)a.chunk_lo + t * WG + ((t & 1) ? WG - 1 - wi : wi);
+        };
         uint64_t rt = 0;
         uint64_t c = chunk_of(0);
         uint32_t tw_n = c < nch ? cfq[c] : 0u;
         OrdRec r_n{0u, 0u, 0.f, 0xffffffffu};
         if (c < nch && tw_n + lane < nsurv) r_n = recq[tw_n + lane];
         bool stopped = false;  // this wave's later chunks lie beyond U: their counts are 0
-        for (; rt * WG < nch; c = chunk_of(++rt)) {
+        for (; (uint64_t)a.chunk_lo + rt * WG < nch; c = chunk_of(++rt)) {
             if (c >= nch) continue;
             if (stopped) {
                 if (lane == 0) cntq[c] = 0;
@@ -2191,7 +2203,7 @@ flat_coarse_kernel(QArgs a) {
                     t += tid == 0 ? sc : tid == 1 ? cb : tid == 7 ? wbn : cb * 8ull + wbn * 20ull;
                 }
             unsigned long long* pp = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
-            *pp = (pass == 0 ? 0ull : *pp) + t;
+            *pp = (pass == 0 && a.chunk_lo == 0 ? 0ull : *pp) + t;
         }
     }
 }
@@ -2323,7 +2335,7 @@ flat_refine_kernel(QArgs a) {
     if (!skip) {
         const int k = st.k;
         const uint64_t nmemb = st.nmemb;
-        const uint64_t nch = min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.max_chunks);
+        const uint64_t nch = min(min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.max_chunks), (uint64_t)a.chunk_hi);
         const bool fine = a.fwords != nullptr;
         const int A = 1 << a.b;
         const float inf = __uint_as_float(0x7f800000u);
@@ -2407,9 +2419,10 @@ flat_refine_kernel(QArgs a) {
             n3 = 0;
             dev::wave_sync();
         };
-        // this block's chunks j, j + G, ..., kScanThreads of them at a time
-        for (uint64_t cb = 0; (uint64_t)j + cb * G < nch; cb += kScanThreads) {
-            const uint64_t cme = (uint64_t)j + (cb + tid) * G;
+        // this block's chunks of the round, chunk_lo + j, + G, ..., kScanThreads of them at a time
+        const uint64_t j0 = (uint64_t)a.chunk_lo + (uint64_t)j;
+        for (uint64_t cb = 0; j0 + cb * G < nch; cb += kScanThreads) {
+            const uint64_t cme = j0 + (cb + tid) * G;
             const uint32_t cnt = cme < nch ? cntq[cme] : 0u;
             uint32_t total;
             const uint32_t ex = block_exclusive_scan(cnt, s_tmp, total);
@@ -2424,7 +2437,7 @@ flat_refine_kernel(QArgs a) {
                     if (s_cpre[mid] <= e) lo = mid;
                     else hi = mid - 1;
                 }
-                const uint64_t cc = (uint64_t)j + (cb + (uint64_t)lo) * G;
+                const uint64_t cc = j0 + (cb + (uint64_t)lo) * G;
                 return segq[cc * a.chunk + (e - s_cpre[lo])];
             };
             if (fine) {
@@ -2523,7 +2536,7 @@ flat_refine_kernel(QArgs a) {
                 t += tid == 2 ? s_cnt[w2][0] : tid == 3 ? s_cnt[w2][1] : tid == 8 ? s_cnt[w2][2]
                                                                                : s_cnt[w2][3] + s_cnt[w2][2] * fine_b;
             unsigned long long* pp = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
-            *pp = (tid == 4 ? *pp : (pass == 0 ? 0ull : *pp)) + t;
+            *pp = (tid == 4 || a.chunk_lo != 0 ? *pp : (pass == 0 ? 0ull : *pp)) + t;
         }
     }
 }
@@ -3535,7 +3548,27 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
             MESSI_TRY(bf16_row_prep(ix, a, ws, s));
             a.rf_tau = kRowFilterTau;
         }
-        MESSI_TRY(launch_scan(a, vec, 0, rowf ? kScanRowFilter : kScanEd, s, timing && ws ? ws->ev[8] : nullptr));
+        if (!rowf && a.seg && c.kmax > 1) {
+            // For k > 1 the split scan runs in two rounds: the best
+            // kSplitFirst chunks (the leaves of smallest bound), U from the
+            // exact k-th candidate, then the rest of the order.  The second
+            // round's coarse kernel bounds against that U, where one round
+            // would use the first bound (the approximate leaf's k-th)
+            // throughout.  For k = 1 the first bound is already close and
+            // the extra launches and the serial first round cost more than
+            // the bytes they save.
+            const uint32_t lo = a.chunk_lo, hi = a.chunk_hi;
+            a.chunk_hi = kSplitFirst;
+            MESSI_TRY(launch_scan(a, vec, 0, kScanEd, s));
+            hipLaunchKernelGGL(fixup_kernel, dim3(nq), dim3(256), 0, s, a, 2);
+            MESSI_LAUNCH_CHECK("fixup");
+            a.chunk_lo = kSplitFirst;
+            a.chunk_hi = hi;
+            MESSI_TRY(launch_scan(a, vec, 0, kScanEd, s, timing && ws ? ws->ev[8] : nullptr));
+            a.chunk_lo = lo;
+        } else {
+            MESSI_TRY(launch_scan(a, vec, 0, rowf ? kScanRowFilter : kScanEd, s, timing && ws ? ws->ev[8] : nullptr));
+        }
         MESSI_TRY(mark(7));
         // k > 1: exact k-th bound and compaction, and a second pass for a
         // query whose buffer overflowed (that pass exits at once otherwise).
@@ -3977,8 +4010,66 @@ size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap) {
     return b;
 }
 
+namespace {
+// Totals of two calls' statistics (counts and times add up).
+void add_stats(messi_knn_stats* t, const messi_knn_stats& u) {
+    t->leaves_total += u.leaves_total;
+    t->leaves_kept += u.leaves_kept;
+    t->leaves_scanned += u.leaves_scanned;
+    t->series_bounded += u.series_bounded;
+    t->series_distance += u.series_distance;
+    t->series_abandoned += u.series_abandoned;
+    t->series_recheck += u.series_recheck;
+    t->candidates += u.candidates;
+    t->bytes_scan += u.bytes_scan;
+    t->ms_total += u.ms_total;
+    t->ms_prep += u.ms_prep;
+    t->ms_leaf_lb += u.ms_leaf_lb;
+    t->ms_approx += u.ms_approx;
+    t->ms_order += u.ms_order;
+    t->ms_scan += u.ms_scan;
+    t->ms_final += u.ms_final;
+    t->scan_launches += u.scan_launches;
+    t->reruns += u.reruns;
+    t->fallbacks += u.fallbacks;
+    t->ms_fixup += u.ms_fixup;
+    t->series_word_bounded += u.series_word_bounded;
+    t->series_fine_bounded += u.series_fine_bounded;
+    t->ms_scan_coarse += u.ms_scan_coarse;
+}
+}  // namespace
+
 int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, const int32_t* kq, int32_t mode,
                hipStream_t s, int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
+    if (mode == MESSI_MODE_FP32 && nq > kSplitMaxQ) {
+        // Several queries in FP32 mode: one after another, each through the
+        // one-query path.  The split scan spreads one query over the whole
+        // GPU, while a batch kernel gives each query only its share of the
+        // blocks, which a hard query (millions of rows within its bound)
+        // cannot afford.  Per-query errors: the first is returned, after
+        // every query has been answered.
+        if (stats) *stats = messi_knn_stats{};
+        messi_knn_stats sub{};
+        int first = MESSI_OK;
+        std::string first_msg;
+        for (int32_t q = 0; q < nq; ++q) {
+            sub = messi_knn_stats{};
+            const int rc = knn_device(ix, queries + (size_t)q * ix->len, 1, k, kq ? kq + q : nullptr, mode, s,
+                                      out_idx + (size_t)q * k, out_dist + (size_t)q * k, stats ? &sub : nullptr);
+            if (rc != MESSI_OK) {
+                if (rc == MESSI_EDEVICE || rc == MESSI_ENOMEM) return rc;
+                if (first == MESSI_OK) {
+                    first = rc;
+                    char buf[512];
+                    messi_last_error(buf, sizeof(buf));
+                    first_msg = buf;
+                }
+            }
+            if (stats) add_stats(stats, sub);
+        }
+        if (first != MESSI_OK) set_error(first, first_msg);
+        return first;
+    }
     CallArgs c{ix, queries, nq, k, kq, mode, s, out_idx, out_dist};
     Workspace* ws = nullptr;
     QArgs a;

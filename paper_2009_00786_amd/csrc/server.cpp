@@ -11,12 +11,13 @@
 // admitted query holds its share of a lane's workspace until it completes.
 //
 // In BF16 mode a lone waiting query (the queue holds at most one when a lane
-// frees up) becomes a launch of one, which the search answers with the
-// ordered scan and its BF16 row filter: a batch of one gains nothing from the
+// frees up) becomes a launch of one: a batch of one gains nothing from the
 // matrix-core filter, whose cost is a pass over the BF16 rows of every leaf
-// the query visits, while the scan bounds each member by its word first and
-// then reads half a row for it.  As soon as queries queue up they go in
-// batches on the matrix-core filter.
+// the query visits.  On an index with a fine summary it runs the FP32
+// search, whose one-query scan bounds each member by its coarse word, word
+// and fine summary before any row; otherwise the ordered scan with the BF16
+// row filter (half a row per member that passes its word).  As soon as
+// queries queue up they go in batches on the matrix-core filter.
 //
 // A lane's whole launch (copies in, the search, copies out) is recorded once
 // per batch shape (query count, largest k, mode, buffer size) into a HIP graph
@@ -89,7 +90,7 @@ constexpr size_t kMaxPending = 1u << 20;
 struct Server {
     const Index* ix = nullptr;
     int32_t mode = MESSI_MODE_BF16;
-    bool row_filter = true;  // BF16 mode: a launch of one query takes the row-filtered scan
+    bool row_filter = true;  // BF16 mode: a launch of one query is answered alone, off the matrix-core filter
     bool use_graphs = true;
     int32_t batch = 1;  // queries per lane
     messi_server_counters stats{};  // guarded by mu
@@ -163,6 +164,10 @@ struct Server {
         }
         ln.kmax = kmax;
         ln.mode = ln.batch[0].fp32 ? MESSI_MODE_FP32 : mode;
+        // a lone query on an index with a fine summary: the FP32 search, whose
+        // one-query scan bounds members by their fine summary (64 bytes) before
+        // any row, where the row-filtered scan reads a 512-byte BF16 row
+        if (ln.mode == MESSI_MODE_BF16 && nq == 1 && row_filter && ix->wf > 0) ln.mode = MESSI_MODE_FP32;
         *ln.h_err = 0;
         uint32_t cap_min = 0;
         if (ln.batch[0].fp32)
@@ -200,7 +205,8 @@ struct Server {
             std::lock_guard<std::mutex> lk(mu);
             stats.batches += 1;
             if (ln.mode == MESSI_MODE_BF16) stats.bf16_batches += 1;
-            if (row_filter_path(ix, ln.mode, nq, !row_filter)) stats.row_filter += 1;
+            if (row_filter_path(ix, ln.mode, nq, !row_filter) || (nq == 1 && row_filter && mode == MESSI_MODE_BF16))
+                stats.row_filter += 1;
             if (recorded) stats.graphs_recorded += 1;
             if (replayed) stats.graph_replays += 1;
             if (!recorded && !replayed) stats.eager_launches += 1;
