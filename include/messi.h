@@ -345,7 +345,15 @@ typedef struct {
  * in FP32 mode before its result is posted.
  *   budget_bytes  device memory the server may use for per-query state; the
  *                 slot count is min(max_slots, budget_bytes / per-query need);
- *                 0 takes the index's messi_opts.budget_bytes (8 GiB if that is 0)
+ *                 0 takes the index's messi_opts.budget_bytes (8 GiB if that is 0).
+ *                 Launches of one query in FP32 take the split scan, whose
+ *                 buffers (4 bytes per series, per lane of up to 4) come out
+ *                 of the budget first when it holds them beside one query per
+ *                 lane; otherwise those launches use the one-kernel scan.
+ *                 A lone query may use its lane's whole candidate buffer; a
+ *                 retry after a candidate-buffer overflow takes 16 times that
+ *                 (256 times on a second retry), beyond the budget until it
+ *                 completes
  *   max_slots     0 takes the index's messi_opts.max_slots (256 if that is 0)
  *   mode          MESSI_MODE_FP32 or MESSI_MODE_BF16 (needs the BF16 shadow),
  *                 optionally OR-ed with MESSI_SERVER_* flags
@@ -373,6 +381,9 @@ typedef struct {
     int64_t graphs_recorded;  /* launches recorded into a new HIP graph (then replayed) */
     int64_t graph_replays;    /* launches that replayed a recorded graph */
     int32_t lanes, batch;     /* lanes and queries per lane */
+    int64_t device_bytes;     /* device memory of the lanes' workspaces and staging at the last launch
+                                 (within budget_bytes); the HIP runtime's own queue and scratch memory
+                                 is not counted */
 } messi_server_counters;
 
 /* Counters of the server so far (host struct, caller-owned).  MESSI_OK or

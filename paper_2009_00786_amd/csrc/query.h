@@ -205,9 +205,16 @@ int refresh_bounds(QArgs& a, hipStream_t s);
 // code, query_error_code a query's status.
 // cap_min raises the per-query candidate buffer above its default.
 // matrix_only keeps a BF16 call of few queries on the matrix-core filter.
+// split = false keeps a one-query FP32 call off the split scan (and its
+// workspace free of the split_scan_bytes it would take).  cap_limit (nonzero)
+// caps the default candidate buffer per query (never below 2 kmax; cap_min
+// still raises it).
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
-                uint32_t cap_min = 0, bool matrix_only = false);
+                uint32_t cap_min = 0, bool matrix_only = false, bool split = true, uint32_t cap_limit = 0);
+// Device bytes of the split scan's survivor segments and counts, held by the
+// workspace of a stream once a one-query FP32 call has run on it.
+size_t split_scan_bytes(const Index* ix);
 // Exact FP32 k-NN of nq queries at one k (as knn_enqueue in MESSI_MODE_FP32)
 // with every search buffer carved from the device region [base, base + bytes)
 // (256-byte aligned) instead of a workspace: allocates nothing.  The

@@ -3208,7 +3208,18 @@ uint32_t max_chunks_of(const Index* ix) {
     return (uint32_t)((ix->n + ch - 1) / ch + 1);
 }
 
-int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Workspace** out) {
+}  // namespace
+
+size_t split_scan_bytes(const Index* ix) {
+    return sizeof(uint32_t) * (size_t)max_chunks_of(ix) * ((size_t)ix->opts.scan_chunk + 1) * (size_t)kSplitMaxQ;
+}
+
+namespace {
+
+// split: the call may take the split scan, whose survivor segments (one slot
+// per member, split_scan_bytes) the workspace then holds.  When they do not
+// fit the index's budget the call goes without them (one flat scan kernel).
+int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, bool split, Workspace** out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace*& ws = g_ws[{ix, s}];
     if (!ws) ws = new Workspace();
@@ -3249,15 +3260,26 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, Work
         ws->max_chunks = mc;
         ++ws->gen;
     }
-    if (nq <= kSplitMaxQ && (ws->seg_nq < nq || ws->seg.bytes < sizeof(uint32_t) * (size_t)ws->max_chunks *
-                                                                  (size_t)ix->opts.scan_chunk * (size_t)nq)) {
+    if (split && nq <= kSplitMaxQ && (ws->seg_nq < nq || ws->seg.bytes < sizeof(uint32_t) * (size_t)ws->max_chunks *
+                                                                            (size_t)ix->opts.scan_chunk * (size_t)nq)) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
         ws->seg_nq = 0;
         ++ws->gen;
-        MESSI_TRY(ws->grow(ix, ws->seg, sizeof(uint32_t) * (size_t)ws->max_chunks * (size_t)ix->opts.scan_chunk *
-                                            (size_t)kSplitMaxQ));
-        MESSI_TRY(ws->grow(ix, ws->segcnt, sizeof(uint32_t) * (size_t)ws->max_chunks * (size_t)kSplitMaxQ));
-        ws->seg_nq = kSplitMaxQ;
+        ws->seg.release();
+        ws->segcnt.release();
+        int rc = ws->grow(ix, ws->seg, sizeof(uint32_t) * (size_t)ws->max_chunks * (size_t)ix->opts.scan_chunk *
+                                           (size_t)kSplitMaxQ);
+        if (rc == MESSI_OK) rc = ws->grow(ix, ws->segcnt, sizeof(uint32_t) * (size_t)ws->max_chunks * (size_t)kSplitMaxQ);
+        if (rc == MESSI_OK) {
+            ws->seg_nq = kSplitMaxQ;
+        } else if (rc == MESSI_ENOMEM) {
+            // over the budget (or the device's memory): go without
+            ws->seg.release();
+            ws->segcnt.release();
+            clear_error();
+        } else {
+            return rc;
+        }
         ++ws->gen;
     }
     if (ws->cand_slots < slots) {
@@ -3388,6 +3410,24 @@ uint64_t workspace_generation(const Index* ix, hipStream_t s) {
     return it == g_ws.end() ? 0 : it->second->gen;
 }
 
+int trim_candidates(const Index* ix, hipStream_t st, size_t slots) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({ix, st});
+    if (it == g_ws.end() || it->second->cand_slots <= slots) return MESSI_OK;
+    Workspace* ws = it->second;
+    MESSI_HIP_TRY(hipStreamSynchronize(st));
+    ws->cand.release();
+    ws->cand_slots = 0;
+    ++ws->gen;
+    return MESSI_OK;
+}
+
+size_t workspace_device_bytes(const Index* ix, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({ix, st});
+    return it == g_ws.end() ? 0 : it->second->device_bytes();
+}
+
 void release_workspace(const Index* ix, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find({ix, st});
@@ -3422,6 +3462,8 @@ struct CallArgs {
     int64_t* out_idx;
     float* out_dist;
     bool matrix_only = false;  // BF16: keep few queries on the matrix-core filter
+    bool split = true;         // FP32, one query: the split scan when its buffers fit
+    uint32_t cap_limit = 0;    // nonzero: the default candidate buffer per query is at most this
 };
 
 // The call's arguments that do not depend on where its workspace lives.
@@ -3469,11 +3511,13 @@ void fill_call_args(const CallArgs& c, uint32_t cap, QArgs& a) {
 int setup_call(const CallArgs& c, bool counting, Workspace** wsp, QArgs& a, uint32_t& cap, uint32_t cap_min = 0) {
     const Index* ix = c.ix;
     const int32_t nq = c.nq;
-    cap = std::max(default_cap(ix, nq, c.kmax, c.mode), cap_min);
+    uint32_t cap_d = default_cap(ix, nq, c.kmax, c.mode);
+    if (c.cap_limit) cap_d = std::min(cap_d, std::max(c.cap_limit, 2u * (uint32_t)c.kmax));
+    cap = std::max(cap_d, cap_min);
     // the approximate mode's candidates are the evaluated members of one leaf
     if (c.mode == MESSI_MODE_APPROX) cap = std::max<uint32_t>(cap, (uint32_t)kApproxMax);
     Workspace* ws = nullptr;
-    MESSI_TRY(get_workspace(ix, c.s, nq, cap, &ws));
+    MESSI_TRY(get_workspace(ix, c.s, nq, cap, c.split && c.mode == MESSI_MODE_FP32, &ws));
     *wsp = ws;
     fill_call_args(c, cap, a);
     a.qs = ws->qs.as<QState>();
@@ -3615,8 +3659,8 @@ int decode_error(uint32_t err) {
 
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
-                uint32_t cap_min, bool matrix_only) {
-    CallArgs c{ix, queries, nq, kmax, kq, mode, s, out_idx, out_dist, matrix_only};
+                uint32_t cap_min, bool matrix_only, bool split, uint32_t cap_limit) {
+    CallArgs c{ix, queries, nq, kmax, kq, mode, s, out_idx, out_dist, matrix_only, split, cap_limit};
     Workspace* ws = nullptr;
     QArgs a;
     uint32_t cap = 0;

@@ -42,6 +42,8 @@
 namespace messi {
 
 void release_workspace(const Index* ix, hipStream_t s);
+size_t workspace_device_bytes(const Index* ix, hipStream_t s);
+int trim_candidates(const Index* ix, hipStream_t s, size_t slots);
 
 namespace {
 
@@ -80,10 +82,14 @@ struct Lane {
     float* h_dist = nullptr;
     uint32_t* h_err = nullptr;
     uint32_t* h_status = nullptr;  // per query of the batch in flight
+    uint32_t cap_min = 0;          // of the launch in flight
     std::vector<Pending> batch;
+    size_t staging_bytes() const { return d_q.bytes + d_k.bytes + d_idx.bytes + d_dist.bytes; }
 };
 
 constexpr size_t kMaxPending = 1u << 20;
+// candidate slots the budget charges per admitted query: enough for any k
+constexpr uint32_t kSlotCap = std::max<uint32_t>(1u << 14, 64u * MESSI_MAX_K);
 
 }  // namespace
 
@@ -91,6 +97,8 @@ struct Server {
     const Index* ix = nullptr;
     int32_t mode = MESSI_MODE_BF16;
     bool row_filter = true;  // BF16 mode: a launch of one query is answered alone, off the matrix-core filter
+    bool split = true;       // FP32 launches of one query take the split scan (its buffers are in the budget)
+    uint32_t lane_cap = kSlotCap;  // candidate slots of a lane (batch x kSlotCap): a lone query may use them all
     bool use_graphs = true;
     int32_t batch = 1;  // queries per lane
     messi_server_counters stats{};  // guarded by mu
@@ -115,7 +123,7 @@ struct Server {
         MESSI_HIP_TRY(hipMemcpyAsync(ln.d_k.p, ln.h_k, sizeof(int32_t) * (size_t)nq, hipMemcpyHostToDevice, ln.s));
         MESSI_TRY(knn_enqueue(ix, ln.d_q.as<float>(), nq, ln.kmax, ln.d_k.as<int32_t>(), ln.mode, ln.s,
                               ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, cap_min,
-                              !row_filter));
+                              !row_filter, split, lane_cap));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.h_idx, ln.d_idx.p, sizeof(int64_t) * (size_t)nq * ln.kmax,
                                      hipMemcpyDeviceToHost, ln.s));
         MESSI_HIP_TRY(hipMemcpyAsync(ln.h_dist, ln.d_dist.p, sizeof(float) * (size_t)nq * ln.kmax,
@@ -169,9 +177,12 @@ struct Server {
         // any row, where the row-filtered scan reads a 512-byte BF16 row
         if (ln.mode == MESSI_MODE_BF16 && nq == 1 && row_filter && ix->wf > 0) ln.mode = MESSI_MODE_FP32;
         *ln.h_err = 0;
+        // a retry after an overflow: 16 times the lane's slots per retry, a
+        // transient excess over the budget (the lane drops it afterwards)
         uint32_t cap_min = 0;
-        if (ln.batch[0].fp32)
-            cap_min = default_cap(ix, 1, kmax, MESSI_MODE_FP32) << (4 * ln.batch[0].grow);
+        if (ln.batch[0].fp32 && ln.batch[0].grow > 0)
+            cap_min = (uint32_t)std::min<uint64_t>((uint64_t)lane_cap << (4 * ln.batch[0].grow), 1ull << 28);
+        ln.cap_min = cap_min;
         const Shape shape{nq, kmax, ln.mode, cap_min};
         bool replayed = false, recorded = false;
         if (use_graphs) {
@@ -201,8 +212,12 @@ struct Server {
         }
         MESSI_HIP_TRY(hipEventRecord(ln.done, ln.s));
         ln.busy = true;
+        // (this thread alone grows the lanes' workspaces)
+        size_t dev_bytes = 0;
+        for (const Lane& l : lanes) dev_bytes += workspace_device_bytes(ix, l.s) + l.staging_bytes();
         {
             std::lock_guard<std::mutex> lk(mu);
+            stats.device_bytes = (int64_t)dev_bytes;
             stats.batches += 1;
             if (ln.mode == MESSI_MODE_BF16) stats.bf16_batches += 1;
             if (row_filter_path(ix, ln.mode, nq, !row_filter) || (nq == 1 && row_filter && mode == MESSI_MODE_BF16))
@@ -256,6 +271,10 @@ struct Server {
         }
         ln.batch.clear();
         ln.busy = false;
+        // a retry's larger candidate buffer goes back (the lane's graphs that
+        // hold its address are re-recorded on their next use)
+        if (ln.cap_min > lane_cap && trim_candidates(ix, ln.s, lane_cap) != MESSI_OK) (void)hipGetLastError();
+        ln.cap_min = 0;
         std::lock_guard<std::mutex> lk(mu);
         stats.requeued += fallbacks;
         for (auto* r : out) ready.push_back(r);
@@ -330,8 +349,7 @@ struct Server {
 // Device bytes one admitted query holds (workspace share + staging), for kmax
 // results; used to turn the memory budget into slots.
 static size_t bytes_per_query(const Index* ix, int32_t mode) {
-    const uint32_t cap = std::max<uint32_t>(1u << 14, 64u * MESSI_MAX_K);
-    return workspace_bytes_per_query(ix, mode, cap) + sizeof(float) * ix->len +
+    return workspace_bytes_per_query(ix, mode, kSlotCap) + sizeof(float) * ix->len +
            (sizeof(int64_t) + sizeof(float)) * MESSI_MAX_K + 256;
 }
 
@@ -367,7 +385,14 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     if (max_slots == 0) max_slots = ix->opts.max_slots;
     if (budget_bytes == 0) budget_bytes = ix->opts.budget_bytes ? (size_t)ix->opts.budget_bytes : (size_t)8 << 30;
     const size_t per_q = bytes_per_query(ix, mode);
-    const int64_t fit = (int64_t)(budget_bytes / per_q);
+    // An FP32 launch of one query (FP32 mode, a lone BF16 query on an index
+    // with a fine summary, a retry) takes the split scan, whose segments each
+    // lane's workspace then holds: they come out of the budget first, if it
+    // holds them beside one query per lane; else those launches go without.
+    const size_t seg_b = split_scan_bytes(ix);
+    const size_t nl_max = (size_t)std::min(4, max_slots);
+    const bool split = budget_bytes >= nl_max * (seg_b + per_q);
+    const int64_t fit = (int64_t)((split ? budget_bytes - nl_max * seg_b : budget_bytes) / per_q);
     if (fit < 1) {
         set_error(MESSI_ENOMEM, "memory budget below the need of one query (" + std::to_string(per_q) + " bytes)");
         return nullptr;
@@ -378,9 +403,11 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     sv->mode = mode;
     sv->row_filter = !(flags & MESSI_SERVER_BATCH_ONLY);
     sv->use_graphs = !(flags & MESSI_SERVER_NO_GRAPHS);
+    sv->split = split;
     sv->device = ix->device;
     const int nl = std::min(4, slots);
-    sv->batch = (slots + nl - 1) / nl;
+    sv->batch = slots / nl;   // (lanes x batch <= slots: within the budget)
+    sv->lane_cap = (uint32_t)std::min<uint64_t>((uint64_t)sv->batch * kSlotCap, 1ull << 28);
     sv->lanes.resize(nl);
     const int L = ix->len;
     int rc = MESSI_OK;
@@ -423,6 +450,11 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
         *ln.h_err = 0;
         if ((rc = knn_enqueue(ix, ln.d_q.as<float>(), (int32_t)B, kw, ln.d_k.as<int32_t>(), mode, ln.s,
                               ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status)) != MESSI_OK)
+            break;
+        // and a launch of one in FP32 (the split scan's segments)
+        if (split && (rc = knn_enqueue(ix, ln.d_q.as<float>(), 1, kw, ln.d_k.as<int32_t>(), MESSI_MODE_FP32, ln.s,
+                                       ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, 0,
+                                       false, true, sv->lane_cap)) != MESSI_OK)
             break;
         if (hipStreamSynchronize(ln.s) != hipSuccess) {
             rc = MESSI_EDEVICE;

@@ -91,7 +91,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_int64), ("bf16_batches", ctypes.c_int64), ("row_filter", ctypes.c_int64),
                 ("requeued", ctypes.c_int64), ("eager_launches", ctypes.c_int64),
                 ("graphs_recorded", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
-                ("lanes", ctypes.c_int32), ("batch", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("batch", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):

@@ -110,6 +110,37 @@ def test_budget_and_argument_errors(served, messi):
     sv.close()
 
 
+@pytest.mark.parametrize("mode_name", ["BF16", "FP32"])
+def test_device_memory_within_budget(served, messi, torch_cuda, mode_name):
+    """A budget that binds (fewer slots than asked for): after creation and
+    waves of queries of every k (lone ones included, which take the FP32
+    split scan), the lanes' workspaces and staging stay within the budget.
+    (The device's free memory also drops by the HIP runtime's own queues and
+    kernel scratch for the lanes' streams, which the budget does not cover:
+    printed, not checked.)"""
+    w = served
+    mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
+    budget = 24 << 20
+    torch_cuda.cuda.synchronize()
+    free0 = torch_cuda.cuda.mem_get_info()[0]
+    sv = messi.Server(w["ix"], budget, 256, mode)
+    try:
+        st0 = sv.stats()
+        assert st0["lanes"] * st0["batch"] < 256   # the budget binds
+        peak = 0
+        for lo, hi in ((0, 40), (40, 41), (41, 81), (81, 82)):   # batches, then a lone query
+            got = _wave(sv, w["q"][lo:hi], w["ks"][lo:hi], list(range(lo, hi)))
+            assert len(got) == hi - lo and all(r["status"] == messi.MESSI_OK for r in got.values())
+            peak = max(peak, sv.stats()["device_bytes"])
+        torch_cuda.cuda.synchronize()
+        used = free0 - torch_cuda.cuda.mem_get_info()[0]
+    finally:
+        sv.close()
+    _say("server %s: workspaces and staging %d bytes, device memory %d bytes, budget %d" %
+         (mode_name, peak, used, budget))
+    assert 0 < peak <= budget
+
+
 def test_bf16_server_needs_shadow(torch_cuda, messi):
     z = torch_cuda.randn((200, 32), device="cuda")
     ix = messi.Index(z, 4, 8, 10)
