@@ -931,9 +931,11 @@ def bench_serving(args):
     results = {}
     modes = [("bf16_server", messi.MODE_BF16, 256)]
     if args.variants:
-        # the same server with one of its two latency devices switched off
+        # the same server with one of its two latency devices switched off,
+        # and the slot engine in place of lanes of batches
         modes += [("bf16_batch_only", messi.MODE_BF16 | messi.SERVER_BATCH_ONLY, 256),
-                  ("bf16_no_graphs", messi.MODE_BF16 | messi.SERVER_NO_GRAPHS, 256)]
+                  ("bf16_no_graphs", messi.MODE_BF16 | messi.SERVER_NO_GRAPHS, 256),
+                  ("bf16_slots", messi.MODE_BF16 | messi.SERVER_SLOTS, 256)]
     if not args.no_fifo:
         modes += [("fp32_fifo", messi.MODE_FP32, 1)]
     for name, mode, slots in modes:

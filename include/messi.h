@@ -327,6 +327,8 @@ typedef struct {
 /* Server mode flags, OR-ed into `mode` of messi_server_create. */
 #define MESSI_SERVER_BATCH_ONLY 0x100 /* BF16: launches of one query also take the matrix-core filter */
 #define MESSI_SERVER_NO_GRAPHS 0x200  /* enqueue every launch eagerly instead of replaying HIP graphs */
+#define MESSI_SERVER_SLOTS 0x400      /* BF16: the slot engine (one graph replay advances every query by a
+                                         window of its leaf order) instead of lanes of batches */
 
 /* A request loop that keeps `index` on the device and answers exact k-NN
  * queries with continuous batching (an extension beyond the paper, which
@@ -356,7 +358,13 @@ typedef struct {
  *                 completes
  *   max_slots     0 takes the index's messi_opts.max_slots (256 if that is 0)
  *   mode          MESSI_MODE_FP32 or MESSI_MODE_BF16 (needs the BF16 shadow),
- *                 optionally OR-ed with MESSI_SERVER_* flags
+ *                 optionally OR-ed with MESSI_SERVER_* flags.  With
+ *                 MESSI_SERVER_SLOTS (BF16) the slots are those of the slot
+ *                 engine: each step (one graph replay) admits queries into
+ *                 free slots, advances every active slot by one filter round
+ *                 over the next window of its leaf order and retires the
+ *                 slots it finishes; one FP32 lane answers lone queries
+ *                 (unless MESSI_SERVER_BATCH_ONLY) and retries
  * Returns NULL on error: MESSI_EINVAL (null index, max_slots < 0, bad mode or
  * flags, BF16 without a shadow), MESSI_ENOMEM (budget below one query's need,
  * or an allocation failed), MESSI_EDEVICE.  The index must outlive the
@@ -381,9 +389,12 @@ typedef struct {
     int64_t graphs_recorded;  /* launches recorded into a new HIP graph (then replayed) */
     int64_t graph_replays;    /* launches that replayed a recorded graph */
     int32_t lanes, batch;     /* lanes and queries per lane */
-    int64_t device_bytes;     /* device memory of the lanes' workspaces and staging at the last launch
-                                 (within budget_bytes); the HIP runtime's own queue and scratch memory
-                                 is not counted */
+    int64_t device_bytes;     /* device memory of the lanes' and the engine's workspaces and staging at
+                                 the last launch (within budget_bytes); the HIP runtime's own queue and
+                                 scratch memory is not counted */
+    int64_t slot_steps;       /* BF16 mode: steps of the slot engine */
+    int64_t slot_admitted;    /* BF16 mode: queries admitted into slots */
+    int64_t slots;            /* BF16 mode: the engine's slots */
 } messi_server_counters;
 
 /* Counters of the server so far (host struct, caller-owned).  MESSI_OK or

@@ -172,7 +172,19 @@ __global__ void __launch_bounds__(256) qprep_bf16_kernel(const float* __restrict
 }
 
 // Positions [t0, t1) of every query's leaf order whose bound does not exceed
-// the query's current U take part in a round.
+// the query's current U take part in a round.  For the serving engine's slots
+// each active slot has its own window instead.
+__device__ __forceinline__ void round_window(const QArgs& a, int q, uint32_t& t0, uint32_t& t1) {
+    if (a.win) {
+        if (a.phase[q] != kSlotActive) {
+            t0 = t1 = 0;
+            return;
+        }
+        t0 = a.win[3 * q];
+        t1 = a.win[3 * q + 1];
+    }
+}
+
 __device__ __forceinline__ bool round_leaf(const QArgs& a, int q, uint32_t t, uint32_t t1, uint32_t& leaf) {
     const QState& st = a.qs[q];
     if (t >= t1 || t >= st.nsurv || st.err) return false;
@@ -197,10 +209,12 @@ __global__ void __launch_bounds__(256) leaf_count_kernel(QArgs a, uint32_t t0, u
                                                          uint32_t* __restrict__ leaf_cnt,
                                                          uint32_t* __restrict__ leaf_act, uint32_t* __restrict__ ctr) {
     const int q = blockIdx.y;
-    const uint32_t t = t0 + blockIdx.x * 256 + threadIdx.x;
-    uint32_t leaf;
-    if (round_leaf(a, q, t, t1, leaf) && atomicAdd(&leaf_cnt[leaf], 1u) == 0u)
-        leaf_act[atomicAdd(&ctr[2], 1u)] = leaf;
+    round_window(a, q, t0, t1);
+    for (uint32_t t = t0 + blockIdx.x * 256 + threadIdx.x; t < t1; t += gridDim.x * 256) {
+        uint32_t leaf;
+        if (round_leaf(a, q, t, t1, leaf) && atomicAdd(&leaf_cnt[leaf], 1u) == 0u)
+            leaf_act[atomicAdd(&ctr[2], 1u)] = leaf;
+    }
 }
 
 // Each active leaf takes a contiguous run of query slots (runs in no
@@ -223,11 +237,13 @@ __global__ void __launch_bounds__(256) leaf_scatter_kernel(QArgs a, uint32_t t0,
                                                            uint32_t* __restrict__ leaf_cur,
                                                            uint32_t* __restrict__ leaf_q, size_t leafq_cap) {
     const int q = blockIdx.y;
-    const uint32_t t = t0 + blockIdx.x * 256 + threadIdx.x;
-    uint32_t leaf;
-    if (round_leaf(a, q, t, t1, leaf)) {
-        const size_t at = (size_t)leaf_off[leaf] + atomicAdd(&leaf_cur[leaf], 1u);
-        if (at < leafq_cap) leaf_q[at] = (uint32_t)q;
+    round_window(a, q, t0, t1);
+    for (uint32_t t = t0 + blockIdx.x * 256 + threadIdx.x; t < t1; t += gridDim.x * 256) {
+        uint32_t leaf;
+        if (round_leaf(a, q, t, t1, leaf)) {
+            const size_t at = (size_t)leaf_off[leaf] + atomicAdd(&leaf_cur[leaf], 1u);
+            if (at < leafq_cap) leaf_q[at] = (uint32_t)q;
+        }
     }
 }
 
@@ -626,7 +642,10 @@ int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
     return MESSI_OK;
 }
 
-int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing) {
+namespace {
+
+// The filter's buffers in the workspace (for a.nq queries) and its arguments.
+int bf16_setup(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, BfArgs& bf, size_t& filter_lds) {
     const int L = ix->len;
     const int Lp = (L + 31) / 32 * 32;
     const int nq = a.nq;
@@ -655,7 +674,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         ws->bf_leafq_cap = leafq_cap;
     }
     const BfConsts kc = bf_consts(Lp);
-    BfArgs bf{};
+    bf = BfArgs{};
     bf.Lp = Lp;
     bf.ksteps = Lp / 32;
     bf.shadow = ix->shadow.as<uint16_t>();
@@ -679,10 +698,25 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     if (qc < 16) qc = 16;
     bf.qc = qc;
     ws->bf_stage_queries = qc;
-    const size_t filter_lds = (size_t)qc * row_bytes;
+    filter_lds = (size_t)qc * row_bytes;
     MESSI_HIP_TRY(hipFuncSetAttribute((const void*)bf16_filter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)filter_lds));
 
+    return MESSI_OK;
+}
+
+}  // namespace
+
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing) {
+    const int L = ix->len;
+    const int Lp = (L + 31) / 32 * 32;
+    const int nq = a.nq;
+    const size_t nL = (size_t)ix->n_leaves;
+    const size_t leafq_cap = (size_t)nq * nL;
+    BfArgs bf;
+    size_t filter_lds = 0;
+    MESSI_TRY(bf16_setup(ix, a, ws, s, bf, filter_lds));
+    const BfConsts kc = bf_consts(Lp);
     hipLaunchKernelGGL(qprep_bf16_kernel, dim3(nq), dim3(256), 0, s, a.queries, L, Lp,
                        std::nextafter((float)kc.c1p, 1.0f), ws->qb.as<uint16_t>(), ws->qnorm.as<float2>(),
                        ws->qx.as<uint4>());
@@ -749,6 +783,45 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
         }
         for (auto e : evs) (void)hipEventDestroy(e);
     }
+    return MESSI_OK;
+}
+
+// One filter round of the serving engine's slots: each slot in kSlotActive
+// over its own window of its leaf order (a.win), the (query, leaf) pairs of
+// all of them grouped by leaf as in a batch round.  The BF16 query rows are
+// prepared for every slot (a slot admitted in this step among them).
+int bf16_slot_round(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
+    const int L = ix->len;
+    const int Lp = (L + 31) / 32 * 32;
+    const int nq = a.nq;
+    const size_t nL = (size_t)ix->n_leaves;
+    BfArgs bf;
+    size_t filter_lds = 0;
+    MESSI_TRY(bf16_setup(ix, a, ws, s, bf, filter_lds));
+    const BfConsts kc = bf_consts(Lp);
+    hipLaunchKernelGGL(qprep_bf16_kernel, dim3(nq), dim3(256), 0, s, a.queries, L, Lp,
+                       std::nextafter((float)kc.c1p, 1.0f), ws->qb.as<uint16_t>(), ws->qnorm.as<float2>(),
+                       ws->qx.as<uint4>());
+    MESSI_LAUNCH_CHECK("qprep_bf16");
+    hipLaunchKernelGGL(round_reset_kernel, dim3((unsigned)std::min<size_t>((nL + 255) / 256, 1024)), dim3(256), 0, s,
+                       ws->leaf_cnt.as<uint32_t>(), (uint32_t)nL, ws->npairs.as<uint32_t>(), 1);
+    MESSI_LAUNCH_CHECK("round_reset");
+    // 16 blocks per slot stride over its window
+    hipLaunchKernelGGL(leaf_count_kernel, dim3(16, nq), dim3(256), 0, s, a, 0u, 0u, ws->leaf_cnt.as<uint32_t>(),
+                       ws->leaf_act.as<uint32_t>(), ws->npairs.as<uint32_t>());
+    MESSI_LAUNCH_CHECK("leaf_count");
+    hipLaunchKernelGGL(leaf_offsets_kernel, dim3((unsigned)std::min<size_t>((nL + 255) / 256, 256)), dim3(256), 0, s,
+                       ws->leaf_cnt.as<uint32_t>(), ws->leaf_act.as<uint32_t>(), ws->leaf_off.as<uint32_t>(),
+                       ws->leaf_cur.as<uint32_t>(), ws->npairs.as<uint32_t>());
+    MESSI_LAUNCH_CHECK("leaf_offsets");
+    hipLaunchKernelGGL(leaf_scatter_kernel, dim3(16, nq), dim3(256), 0, s, a, 0u, 0u, ws->leaf_off.as<uint32_t>(),
+                       ws->leaf_cur.as<uint32_t>(), ws->leaf_q.as<uint32_t>(), (size_t)nq * nL);
+    MESSI_LAUNCH_CHECK("leaf_scatter");
+    const int cus = device_cus();
+    hipLaunchKernelGGL(bf16_filter_kernel, dim3(cus), dim3(kFThreads), filter_lds, s, a, bf);
+    MESSI_LAUNCH_CHECK("bf16_filter");
+    hipLaunchKernelGGL(bf16_recheck_kernel, dim3(cus * 8), dim3(256), 0, s, a, bf);
+    MESSI_LAUNCH_CHECK("bf16_recheck");
     return MESSI_OK;
 }
 

@@ -143,7 +143,21 @@ struct QArgs {
     unsigned long long* blk_cnt; // scan counters per block [blocks][5] (with counters)
     int64_t* out_idx;
     float* out_dist;
+    // the serving engine's slots (nullptr for a plain call): a kernel of the
+    // query head runs for slots in kSlotAdmit only, a filter round for slots in
+    // kSlotActive (over their window of the leaf order), the final kernel for
+    // slots in kSlotFinal
+    uint32_t* phase;             // [nq]
+    uint32_t* win;               // [nq][3]: window of order positions [r0, r1) this step, and the round
 };
+
+// Phases of a slot of the serving engine.
+constexpr uint32_t kSlotFree = 0, kSlotAdmit = 1, kSlotActive = 2, kSlotFinal = 3, kSlotDone = 4;
+
+// Whether the slot of query q sits out a kernel meant for slots in `want`.
+__device__ __forceinline__ bool slot_off(const QArgs& a, int q, uint32_t want) {
+    return a.phase != nullptr && a.phase[q] != want;
+}
 
 // Per-(index, stream) search workspace, grown on demand.
 struct Workspace {
@@ -155,6 +169,8 @@ struct Workspace {
         status, lbpart;
     DevBuf seg, segcnt;  // split scan (calls of at most kSplitMaxQ queries)
     int32_t seg_nq = 0;
+    DevBuf slot_phase, slot_win, slot_q, slot_k;  // the serving engine's slots
+    int32_t slot_n = 0;
     DevBuf todo, env, todo_cnt, ec, ec_cnt;  // DTW search
     size_t todo_slots = 0, env_floats = 0, todo_cnt_n = 0, ec_slots = 0, ec_cnt_n = 0;
     uint32_t* h_err = nullptr;  // pinned copy of the call's error flags
@@ -186,6 +202,9 @@ struct Workspace {
 // shared fp64 final ordering.
 int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing);
 
+// One BF16 filter round of the serving engine's active slots (a.phase, a.win).
+int bf16_slot_round(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s);
+
 // The BF16 row filter of the ordered scan: per query 2 q in BF16, its norms
 // and the extra k-step terms (into the workspace), and the filter's fields of a.
 int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s);
@@ -212,6 +231,31 @@ int refresh_bounds(QArgs& a, hipStream_t s);
 int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax, const int32_t* kq, int32_t mode,
                 hipStream_t s, int64_t* out_idx, float* out_dist, uint32_t* host_err, uint32_t* host_status,
                 uint32_t cap_min = 0, bool matrix_only = false, bool split = true, uint32_t cap_limit = 0);
+// Host-mapped arrays (their device addresses) through which the server and
+// the serving engine's step exchange slots: S slots, rows of the index's length.
+struct SlotIO {
+    const uint32_t* ctl;   // [S] nonzero: the slot takes the query staged for it in this step
+    const float* q;        // [S][L] staged queries
+    const int32_t* k;      // [S] their k
+    uint32_t* phase;       // [S] every slot's phase after the step (kSlot*)
+    uint32_t* status;      // [S] a slot finished in the step: its QState::err (0: answered)
+    int64_t* idx;          // [S][MESSI_MAX_K] a finished slot's answer (row stride MESSI_MAX_K)
+    float* dist;           // [S][MESSI_MAX_K]
+};
+
+// Enqueue one step of the serving engine on s (BF16 mode, an index with the
+// BF16 shadow): slots marked in io.ctl are admitted (the query head: bounds,
+// first bound, leaf order); every active slot takes one filter round over the
+// next window of its leaf order (16 positions, then four times the previous
+// window, at most 65536); a slot whose order is exhausted, or whose next leaf
+// lies in a bin wholly above its U, gets its final answer; io.phase and
+// io.status report every slot.  Capturable in a HIP graph once a first call
+// has sized the workspace (it allocates only when the slot count grows).
+int slot_step_enqueue(const Index* ix, hipStream_t s, int32_t S, const SlotIO& io);
+
+// Device bytes a workspace holds whatever its query count (statistics
+// staging, the BF16 filter's per-leaf counters).
+size_t workspace_fixed_bytes(const Index* ix);
 // Device bytes of the split scan's survivor segments and counts, held by the
 // workspace of a stream once a one-query FP32 call has run on it.
 size_t split_scan_bytes(const Index* ix);

@@ -144,6 +144,7 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
     __shared__ uint32_t s_max[4];
     __shared__ float s_bp[256];
     const int q = blockIdx.y;
+    if (slot_off(a, q, kSlotAdmit)) return;
     const int A = 1 << a.b;
     // this thread's first leaf, in flight while the query summary is formed
     const int l0 = blockIdx.x * kLeafBlock + threadIdx.x;
@@ -353,6 +354,7 @@ __global__ void __launch_bounds__(256) approx_ed_kernel(QArgs a, uint32_t nlb) {
     __shared__ unsigned long long s_min[4];
     __shared__ uint32_t s_max[4];
     const int q = blockIdx.y;
+    if (slot_off(a, q, kSlotAdmit)) return;
     const QState& st = a.qs[q];
     if (st.err) return;
     for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
@@ -491,6 +493,7 @@ __global__ void __launch_bounds__(256) bin_hist_kernel(QArgs a, uint32_t nlb) {
     __shared__ uint32_t hm[kNB];
     __shared__ FirstBoundSmem sm;
     const int q = blockIdx.y;
+    if (slot_off(a, q, kSlotAdmit)) return;
     QState& st = a.qs[q];
     if (st.err) return;
     for (int i = threadIdx.x; i < kNB; i += 256) {
@@ -553,6 +556,7 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(QArgs a) {
     __shared__ uint32_t s_pos[kNB], s_moff[kNB];
     __shared__ uint32_t s_tmp[4];
     const int q = blockIdx.y;
+    if (slot_off(a, q, kSlotAdmit)) return;
     QState& st = a.qs[q];
     if (st.err) return;
     {
@@ -699,6 +703,7 @@ __global__ void __launch_bounds__(256) refresh_kernel(QArgs a) {
     __shared__ uint32_t s_b[2];
     __shared__ uint32_t s_tmp[4];
     const int q = blockIdx.x;
+    if (slot_off(a, q, kSlotActive)) return;
     QState& st = a.qs[q];
     if (st.err) return;
     refresh_compact(a, q, st, s_hist, s_b, s_tmp);
@@ -2985,6 +2990,83 @@ __global__ void __launch_bounds__(256) dtw_active_kernel(QArgs a, uint32_t c1) {
     atomicAdd(&a.err_any[2], 1u);
 }
 
+// ---- the serving engine's slots ---------------------------------------------
+constexpr uint32_t kSlotWin0 = 16;  // first window of a slot's leaf order; each later one is 4x (<= 65536)
+
+// Admissions of the step: a slot the host marked copies its staged query and
+// k from host memory and enters kSlotAdmit.
+__global__ void __launch_bounds__(256) slot_begin_kernel(QArgs a, SlotIO io, float* __restrict__ qdev,
+                                                         int32_t* __restrict__ kdev) {
+    __shared__ uint32_t s_go;
+    const int q = blockIdx.x;
+    if (threadIdx.x == 0) s_go = io.ctl[q];
+    __syncthreads();
+    if (!s_go) return;
+    for (int j = threadIdx.x; j < a.L; j += 256) qdev[(size_t)q * a.L + j] = io.q[(size_t)q * a.L + j];
+    if (threadIdx.x == 0) {
+        kdev[q] = io.k[q];
+        a.phase[q] = kSlotAdmit;
+    }
+}
+
+// After the head: an admitted slot starts its first window (or, if its query
+// is not finite, goes straight to its final kernel, which reports that).
+__global__ void __launch_bounds__(256) slot_activate_kernel(QArgs a) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= a.nq || a.phase[q] != kSlotAdmit) return;
+    const QState& st = a.qs[q];
+    a.win[3 * q] = 0;
+    a.win[3 * q + 1] = min(kSlotWin0, st.nsurv);
+    a.win[3 * q + 2] = 0;
+    a.phase[q] = (st.err || st.nsurv == 0) ? kSlotFinal : kSlotActive;
+}
+
+// After the round (and the bound refresh): a slot whose order is exhausted,
+// or whose next position lies in a bin wholly above U (the scan's own stop
+// rule: every later leaf's bound exceeds U), is final; any other takes its
+// next window.
+__global__ void __launch_bounds__(256) slot_end_kernel(QArgs a) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= a.nq || a.phase[q] != kSlotActive) return;
+    const QState& st = a.qs[q];
+    const uint32_t t = a.win[3 * q + 1];
+    bool stop = st.err != 0 || t >= st.nsurv;
+    if (!stop) {
+        const float lb0 = a.rec[(size_t)q * a.nL + t].lb;
+        const float U = __uint_as_float(st.U);
+        const float low = (float)bin_of(lb0, st.range) * (st.range / (float)kNB);
+        stop = lb0 * (1.0f - kRhoLb) > U && low * (1.0f - 2.0f * kRhoLb) > U;
+    }
+    if (stop) {
+        a.phase[q] = kSlotFinal;
+        return;
+    }
+    const uint32_t r = a.win[3 * q + 2] + 1;
+    const uint32_t width = kSlotWin0 << min(2u * r, 12u);
+    a.win[3 * q] = t;
+    a.win[3 * q + 1] = (uint32_t)min((uint64_t)t + width, (uint64_t)st.nsurv);
+    a.win[3 * q + 2] = r;
+}
+
+// End of the step: final slots are done; every slot's phase (and a done
+// slot's status) goes to the host.
+__global__ void __launch_bounds__(256) slot_report_kernel(QArgs a, SlotIO io) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= a.nq) return;
+    uint32_t ph = a.phase[q];
+    if (ph == kSlotFinal) {
+        ph = kSlotDone;
+        a.phase[q] = ph;
+        io.status[q] = a.qs[q].err;
+    }
+    io.phase[q] = ph;
+}
+
+__global__ void __launch_bounds__(256) slot_clear_kernel(uint32_t* __restrict__ p, uint32_t n) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // DB = 0: Euclidean distances; DB = R + 1: DTW under band R.
 template <int DB>
 __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
@@ -2993,6 +3075,7 @@ __global__ void __launch_bounds__(256) final_kernel(QArgs a) {
     __shared__ float s_q[MESSI_MAX_LEN];
     __shared__ uint32_t s_kept;
     const int q = blockIdx.x;
+    if (slot_off(a, q, kSlotFinal)) return;
     QState& st = a.qs[q];
     if (threadIdx.x == 0) s_kept = 0;
     for (int j = threadIdx.x; j < a.L; j += 256) s_q[j] = a.queries[(size_t)q * a.L + j];
@@ -3175,7 +3258,8 @@ int Workspace::ensure_stats() {
 size_t Workspace::device_bytes() const {
     size_t t = 0;
     for (const DevBuf* b : {&qs, &lb, &order, &rec, &chunk_first, &bins, &mbins, &cursor, &hist, &approx_d, &cand,
-                            &counters, &err, &prof, &blk_cnt, &status, &lbpart, &seg, &segcnt, &todo, &env,
+                            &counters, &err, &prof, &blk_cnt, &status, &lbpart, &seg, &segcnt, &slot_phase,
+                            &slot_win, &slot_q, &slot_k, &todo, &env,
                             &todo_cnt,
                             &ec, &ec_cnt,
                             &qb, &qnorm, &qx, &leaf_cnt, &leaf_off, &leaf_cur, &leaf_q, &leaf_act, &pairs, &npairs})
@@ -3209,6 +3293,12 @@ uint32_t max_chunks_of(const Index* ix) {
 }
 
 }  // namespace
+
+size_t workspace_fixed_bytes(const Index* ix) {
+    const size_t nL1 = (size_t)ix->n_leaves + 1;
+    return sizeof(QCounters) + sizeof(uint32_t) * 4 + sizeof(unsigned long long) * 4 * 4096 +
+           sizeof(unsigned long long) * kBlkCnt * 4096 + sizeof(uint32_t) * (4 * nL1 + 8);
+}
 
 size_t split_scan_bytes(const Index* ix) {
     return sizeof(uint32_t) * (size_t)max_chunks_of(ix) * ((size_t)ix->opts.scan_chunk + 1) * (size_t)kSplitMaxQ;
@@ -3672,6 +3762,63 @@ int knn_enqueue(const Index* ix, const float* queries, int32_t nq, int32_t kmax,
         MESSI_LAUNCH_CHECK("status");
         MESSI_HIP_TRY(hipMemcpyAsync(host_status, ws->status.p, sizeof(uint32_t) * nq, hipMemcpyDeviceToHost, s));
     }
+    return MESSI_OK;
+}
+
+int slot_step_enqueue(const Index* ix, hipStream_t s, int32_t S, const SlotIO& io) {
+    if (S < 1 || !ix->shadow.p) {
+        set_error(MESSI_EINVAL, "serving engine: needs slots and the BF16 shadow");
+        return MESSI_EINVAL;
+    }
+    const int32_t kmax = (int32_t)std::min<int64_t>(MESSI_MAX_K, ix->n);
+    CallArgs c{ix, nullptr, S, kmax, nullptr, MESSI_MODE_BF16, s, io.idx, io.dist};
+    c.split = false;
+    Workspace* ws = nullptr;
+    QArgs a;
+    uint32_t cap = 0;
+    MESSI_TRY(setup_call(c, false, &ws, a, cap));
+    if (ws->slot_n < S) {
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        ws->slot_n = 0;
+        ++ws->gen;
+        MESSI_TRY(ws->grow(ix, ws->slot_phase, sizeof(uint32_t) * (size_t)S));
+        MESSI_TRY(ws->grow(ix, ws->slot_win, sizeof(uint32_t) * 3 * (size_t)S));
+        MESSI_TRY(ws->grow(ix, ws->slot_q, sizeof(float) * (size_t)S * ix->len));
+        MESSI_TRY(ws->grow(ix, ws->slot_k, sizeof(int32_t) * (size_t)S));
+        hipLaunchKernelGGL(slot_clear_kernel, dim3((S + 255) / 256), dim3(256), 0, s, ws->slot_phase.as<uint32_t>(),
+                           (uint32_t)S);
+        MESSI_LAUNCH_CHECK("slot_clear");
+        ws->slot_n = S;
+        ++ws->gen;
+    }
+    a.queries = ws->slot_q.as<float>();
+    a.phase = ws->slot_phase.as<uint32_t>();
+    a.win = ws->slot_win.as<uint32_t>();
+    const unsigned lb_blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((a.nL + kLeafBlock - 1) / kLeafBlock, (8192 + S - 1) / S));
+    const unsigned sb = (unsigned)((S + 255) / 256);
+    hipLaunchKernelGGL(slot_begin_kernel, dim3(S), dim3(256), 0, s, a, io, ws->slot_q.as<float>(),
+                       ws->slot_k.as<int32_t>());
+    MESSI_LAUNCH_CHECK("slot_begin");
+    hipLaunchKernelGGL(leaf_lb_kernel, dim3(lb_blocks, S), dim3(256), 0, s, a, kmax, ws->slot_k.as<int32_t>(),
+                       (uint32_t)MESSI_MAX_K);
+    MESSI_LAUNCH_CHECK("leaf_lb");
+    hipLaunchKernelGGL(approx_ed_kernel, dim3(approx_blocks(S), S), dim3(256), 0, s, a, lb_blocks);
+    MESSI_LAUNCH_CHECK("approx_ed");
+    hipLaunchKernelGGL(bin_hist_kernel, dim3(lb_blocks, S), dim3(256), 0, s, a, lb_blocks);
+    MESSI_LAUNCH_CHECK("bin_hist");
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(lb_blocks, S), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("bin_scatter");
+    hipLaunchKernelGGL(slot_activate_kernel, dim3(sb), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("slot_activate");
+    MESSI_TRY(bf16_slot_round(ix, a, ws, s));
+    MESSI_TRY(refresh_bounds(a, s));
+    hipLaunchKernelGGL(slot_end_kernel, dim3(sb), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("slot_end");
+    hipLaunchKernelGGL(final_kernel<0>, dim3(S), dim3(256), 0, s, a);
+    MESSI_LAUNCH_CHECK("final");
+    hipLaunchKernelGGL(slot_report_kernel, dim3(sb), dim3(256), 0, s, a, io);
+    MESSI_LAUNCH_CHECK("slot_report");
     return MESSI_OK;
 }
 

@@ -19,6 +19,17 @@
 // row filter (half a row per member that passes its word).  As soon as
 // queries queue up they go in batches on the matrix-core filter.
 //
+// With MESSI_SERVER_SLOTS (BF16) the batches give way to a slot engine: S
+// slots on one stream, and a step (one replay of a recorded HIP graph) that
+// admits the queries placed in free slots (their head: bounds, first bound,
+// leaf order), runs one BF16 filter round in which every active slot takes
+// the next window of its own leaf order (16 positions, then four times the
+// last), and finishes every slot whose order is exhausted or whose next leaf
+// lies in a bin wholly above its bound.  A query retires at the end of the
+// step that finishes it; its slot takes a waiting query in the next step.
+// Slots and host exchange queries, phases and answers through mapped pinned
+// memory.  Lone queries and retries go to one FP32 lane.
+//
 // A lane's whole launch (copies in, the search, copies out) is recorded once
 // per batch shape (query count, largest k, mode, buffer size) into a HIP graph
 // and replayed afterwards: the first batch of a shape runs eagerly, which
@@ -87,6 +98,28 @@ struct Lane {
     size_t staging_bytes() const { return d_q.bytes + d_k.bytes + d_idx.bytes + d_dist.bytes; }
 };
 
+// The BF16 serving engine: S slots on one stream, advanced together one step
+// (one replay of a recorded graph) at a time.  Host and device exchange
+// slots through mapped pinned memory (io holds the device addresses).
+struct Engine {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    int32_t S = 0;
+    bool busy = false;
+    uint32_t* h_ctl = nullptr;
+    float* h_q = nullptr;
+    int32_t* h_k = nullptr;
+    uint32_t* h_phase = nullptr;
+    uint32_t* h_status = nullptr;
+    int64_t* h_idx = nullptr;
+    float* h_dist = nullptr;
+    SlotIO io{};
+    std::vector<Pending> held;  // the query each slot holds
+    std::vector<char> used;
+    int32_t n_used = 0;
+    Recorded step;              // the recorded step
+};
+
 constexpr size_t kMaxPending = 1u << 20;
 // candidate slots the budget charges per admitted query: enough for any k
 constexpr uint32_t kSlotCap = std::max<uint32_t>(1u << 14, 64u * MESSI_MAX_K);
@@ -103,6 +136,7 @@ struct Server {
     int32_t batch = 1;  // queries per lane
     messi_server_counters stats{};  // guarded by mu
     std::vector<Lane> lanes;
+    Engine eng;         // BF16 mode: the slot engine (the lanes answer lone queries and retries in FP32)
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Pending> pending;
@@ -281,6 +315,126 @@ struct Server {
         for (auto it = redo.rbegin(); it != redo.rend(); ++it) pending.push_front(std::move(*it));
     }
 
+    // ---- the slot engine ----------------------------------------------------
+    int engine_enqueue() { return slot_step_enqueue(ix, eng.s, eng.S, eng.io); }
+
+    bool engine_record() {
+        if (hipStreamBeginCapture(eng.s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        const int rc = engine_enqueue();
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(eng.s, &g);
+        hipGraphExec_t exec = nullptr;
+        bool ok = rc == MESSI_OK && ec == hipSuccess && g &&
+                  hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+            (void)hipGetLastError();
+            clear_error();
+            if (exec) (void)hipGraphExecDestroy(exec);
+            return false;
+        }
+        eng.step.exec = exec;
+        eng.step.gen = workspace_generation(ix, eng.s);
+        return true;
+    }
+
+    // One step: the recorded graph when it still matches the workspace, else
+    // the step's operations (and a new recording for the next step).
+    int engine_launch() {
+        bool recorded = false, replayed = false;
+        if (use_graphs) {
+            if (eng.step.exec && eng.step.gen != workspace_generation(ix, eng.s)) drop_graph(eng.step);
+            if (!eng.step.exec) recorded = engine_record();
+            if (eng.step.exec) {
+                MESSI_HIP_TRY(hipGraphLaunch(eng.step.exec, eng.s));
+                replayed = !recorded;
+            }
+        }
+        if (!recorded && !replayed) MESSI_TRY(engine_enqueue());
+        MESSI_HIP_TRY(hipEventRecord(eng.done, eng.s));
+        eng.busy = true;
+        size_t dev_bytes = workspace_device_bytes(ix, eng.s);
+        for (const Lane& l : lanes) dev_bytes += workspace_device_bytes(ix, l.s) + l.staging_bytes();
+        std::lock_guard<std::mutex> lk(mu);
+        stats.device_bytes = (int64_t)dev_bytes;
+        stats.slot_steps += 1;
+        stats.batches += 1;
+        stats.bf16_batches += 1;
+        if (recorded) stats.graphs_recorded += 1;
+        if (replayed) stats.graph_replays += 1;
+        if (!recorded && !replayed) stats.eager_launches += 1;
+        return MESSI_OK;
+    }
+
+    // After a step: every slot it finished posts its result (or, after a
+    // buffer overflow, goes back to the queue to be answered alone in FP32).
+    void engine_collect(int launch_status) {
+        const double t = now_ms();
+        std::vector<messi_result*> out;
+        std::vector<Pending> redo;
+        for (int32_t q = 0; q < eng.S; ++q) {
+            eng.h_ctl[q] = 0;
+            if (!eng.used[q]) continue;
+            if (launch_status == MESSI_OK && eng.h_phase[q] != kSlotDone) continue;  // still searching
+            const int status = launch_status != MESSI_OK ? launch_status : query_error_code(eng.h_status[q]);
+            Pending& p = eng.held[q];
+            eng.used[q] = 0;
+            --eng.n_used;
+            if (status == MESSI_EOVERFLOW) {
+                p.fp32 = true;
+                p.grow = 0;
+                redo.push_back(std::move(p));
+                continue;
+            }
+            messi_result* r = new messi_result();
+            std::memset(r, 0, sizeof(*r));
+            r->tag = p.tag;
+            r->k = p.k;
+            r->status = status;
+            r->t_submit_ms = p.t_submit;
+            r->t_done_ms = t;
+            if (status == MESSI_OK) {
+                for (int j = 0; j < r->k; ++j) {
+                    r->idx[j] = eng.h_idx[(size_t)q * MESSI_MAX_K + j];
+                    r->dist[j] = eng.h_dist[(size_t)q * MESSI_MAX_K + j];
+                }
+            }
+            out.push_back(r);
+        }
+        eng.busy = false;
+        std::lock_guard<std::mutex> lk(mu);
+        stats.requeued += (int64_t)redo.size();
+        for (auto* r : out) ready.push_back(r);
+        for (auto it = redo.rbegin(); it != redo.rend(); ++it) pending.push_front(std::move(*it));
+    }
+
+    // Free slots take waiting queries (not the re-queued ones, which the
+    // FP32 lanes answer); true if any slot is in use.
+    bool engine_admit() {
+        std::lock_guard<std::mutex> lk(mu);
+        const int L = ix->len;
+        int32_t q = 0;
+        for (auto it = pending.begin(); it != pending.end() && eng.n_used < eng.S;) {
+            if (it->fp32) {
+                ++it;
+                continue;
+            }
+            while (eng.used[q]) ++q;
+            std::memcpy(eng.h_q + (size_t)q * L, it->q.data(), sizeof(float) * L);
+            eng.h_k[q] = it->k;
+            eng.h_ctl[q] = 1;
+            eng.held[q] = std::move(*it);
+            eng.used[q] = 1;
+            ++eng.n_used;
+            stats.slot_admitted += 1;
+            it = pending.erase(it);
+        }
+        return eng.n_used > 0;
+    }
+
     void run() {
         (void)hipSetDevice(device);
         for (;;) {
@@ -293,43 +447,80 @@ struct Server {
                 complete(ln, q == hipSuccess ? MESSI_OK : MESSI_EDEVICE);
                 progressed = true;
             }
-            bool idle_lanes = false;
+            if (eng.S && eng.busy) {
+                const hipError_t q = hipEventQuery(eng.done);
+                if (q != hipErrorNotReady) {
+                    if (q != hipSuccess) (void)hipGetLastError();
+                    engine_collect(q == hipSuccess ? MESSI_OK : MESSI_EDEVICE);
+                    progressed = true;
+                }
+            }
             for (auto& ln : lanes) {
                 if (ln.busy) continue;
                 {
-                    // a batch, or a re-queued query on its own in FP32 mode
                     std::lock_guard<std::mutex> lk(mu);
-                    while (!pending.empty() && (int32_t)ln.batch.size() < batch) {
-                        const bool alone = pending.front().fp32;
-                        if (alone && !ln.batch.empty()) break;
-                        ln.batch.push_back(std::move(pending.front()));
-                        pending.pop_front();
-                        if (alone) break;
+                    if (eng.S) {
+                        // with the engine: a re-queued query, or a query alone in
+                        // the queue while the engine is idle (unless batch-only)
+                        for (auto it = pending.begin(); it != pending.end(); ++it)
+                            if (it->fp32) {
+                                ln.batch.push_back(std::move(*it));
+                                pending.erase(it);
+                                break;
+                            }
+                        if (ln.batch.empty() && row_filter && pending.size() == 1 && !eng.busy && eng.n_used == 0) {
+                            ln.batch.push_back(std::move(pending.front()));
+                            pending.pop_front();
+                        }
+                    } else {
+                        // a batch, or a re-queued query on its own in FP32 mode
+                        while (!pending.empty() && (int32_t)ln.batch.size() < batch) {
+                            const bool alone = pending.front().fp32;
+                            if (alone && !ln.batch.empty()) break;
+                            ln.batch.push_back(std::move(pending.front()));
+                            pending.pop_front();
+                            if (alone) break;
+                        }
                     }
                 }
-                if (ln.batch.empty()) {
-                    idle_lanes = true;
-                    continue;
-                }
+                if (ln.batch.empty()) continue;
                 const int rc = launch(ln);
                 if (rc != MESSI_OK) complete(ln, rc);
                 progressed = true;
             }
-            bool any_busy = false;
+            if (eng.S && !eng.busy && engine_admit()) {
+                const int rc = engine_launch();
+                if (rc != MESSI_OK) {
+                    clear_error();
+                    engine_collect(rc);
+                }
+                progressed = true;
+            }
+            bool any_busy = eng.busy;
             for (auto& ln : lanes) any_busy |= ln.busy;
             if (stop.load() && !any_busy) {
                 std::lock_guard<std::mutex> lk(mu);
                 if (pending.empty()) break;
             }
             if (!progressed) {
+                // nothing could start: wait for a submission or a launch to end
                 std::unique_lock<std::mutex> lk(mu);
-                if (pending.empty() || !idle_lanes)
-                    cv.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 500));
+                cv.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 500));
             }
         }
     }
 
     ~Server() {
+        if (eng.s) {
+            drop_graph(eng.step);
+            (void)hipStreamSynchronize(eng.s);
+            release_workspace(ix, eng.s);
+            (void)hipStreamDestroy(eng.s);
+        }
+        if (eng.done) (void)hipEventDestroy(eng.done);
+        for (void* p : {(void*)eng.h_ctl, (void*)eng.h_q, (void*)eng.h_k, (void*)eng.h_phase, (void*)eng.h_status,
+                        (void*)eng.h_idx, (void*)eng.h_dist})
+            if (p) (void)hipHostFree(p);
         for (auto& ln : lanes) {
             for (auto& kv : ln.graphs) drop_graph(kv.second);
             if (ln.s) {
@@ -372,7 +563,8 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     const int32_t flags = mode & ~0xff;
     mode &= 0xff;
     if ((mode != MESSI_MODE_FP32 && mode != MESSI_MODE_BF16) ||
-        (flags & ~(MESSI_SERVER_BATCH_ONLY | MESSI_SERVER_NO_GRAPHS))) {
+        (flags & ~(MESSI_SERVER_BATCH_ONLY | MESSI_SERVER_NO_GRAPHS | MESSI_SERVER_SLOTS)) ||
+        ((flags & MESSI_SERVER_SLOTS) && mode != MESSI_MODE_BF16)) {
         set_error(MESSI_EINVAL, "unknown mode");
         return nullptr;
     }
@@ -384,17 +576,27 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     // zero takes the index's options
     if (max_slots == 0) max_slots = ix->opts.max_slots;
     if (budget_bytes == 0) budget_bytes = ix->opts.budget_bytes ? (size_t)ix->opts.budget_bytes : (size_t)8 << 30;
-    const size_t per_q = bytes_per_query(ix, mode);
-    // An FP32 launch of one query (FP32 mode, a lone BF16 query on an index
-    // with a fine summary, a retry) takes the split scan, whose segments each
-    // lane's workspace then holds: they come out of the budget first, if it
-    // holds them beside one query per lane; else those launches go without.
+    const bool engine = (flags & MESSI_SERVER_SLOTS) != 0;
+    // Lanes of batches (up to 4); or, with MESSI_SERVER_SLOTS, the slot
+    // engine and one FP32 lane of one query (lone queries and retries).
+    const size_t per_q = bytes_per_query(ix, engine ? MESSI_MODE_FP32 : mode);
+    const size_t per_slot = engine ? bytes_per_query(ix, MESSI_MODE_BF16) : per_q;
+    // An FP32 launch of one query (FP32 mode, a lone BF16 query, a retry)
+    // takes the split scan, whose segments each lane's workspace then holds:
+    // they come out of the budget first, if it holds them beside one query
+    // per lane (and one slot); else those launches go without.
     const size_t seg_b = split_scan_bytes(ix);
-    const size_t nl_max = (size_t)std::min(4, max_slots);
-    const bool split = budget_bytes >= nl_max * (seg_b + per_q);
-    const int64_t fit = (int64_t)((split ? budget_bytes - nl_max * seg_b : budget_bytes) / per_q);
+    const size_t nl_max = engine ? 1 : (size_t)std::min(4, max_slots);
+    // every workspace (each lane's, the engine's) holds some bytes whatever its size
+    const size_t fixed = (nl_max + (engine ? 1 : 0)) * workspace_fixed_bytes(ix);
+    const size_t need1 = fixed + nl_max * (seg_b + per_q) + (engine ? per_slot : 0);
+    const bool split = budget_bytes >= need1;
+    size_t room = budget_bytes >= fixed ? budget_bytes - fixed : 0;
+    if (split) room -= nl_max * seg_b;
+    if (engine) room = room >= per_q ? room - per_q : 0;  // the FP32 lane's query
+    const int64_t fit = (int64_t)(room / per_slot);
     if (fit < 1) {
-        set_error(MESSI_ENOMEM, "memory budget below the need of one query (" + std::to_string(per_q) + " bytes)");
+        set_error(MESSI_ENOMEM, "memory budget below the need of one query (" + std::to_string(per_slot) + " bytes)");
         return nullptr;
     }
     const int32_t slots = (int32_t)std::min<int64_t>(max_slots, fit);
@@ -405,10 +607,11 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     sv->use_graphs = !(flags & MESSI_SERVER_NO_GRAPHS);
     sv->split = split;
     sv->device = ix->device;
-    const int nl = std::min(4, slots);
-    sv->batch = slots / nl;   // (lanes x batch <= slots: within the budget)
+    const int nl = engine ? 1 : std::min(4, slots);
+    sv->batch = engine ? 1 : slots / nl;   // (lanes x batch <= slots: within the budget)
     sv->lane_cap = (uint32_t)std::min<uint64_t>((uint64_t)sv->batch * kSlotCap, 1ull << 28);
     sv->lanes.resize(nl);
+    const int32_t lane_mode = engine ? MESSI_MODE_FP32 : mode;
     const int L = ix->len;
     int rc = MESSI_OK;
     for (auto& ln : sv->lanes) {
@@ -448,8 +651,9 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
             break;
         }
         *ln.h_err = 0;
-        if ((rc = knn_enqueue(ix, ln.d_q.as<float>(), (int32_t)B, kw, ln.d_k.as<int32_t>(), mode, ln.s,
-                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status)) != MESSI_OK)
+        if ((rc = knn_enqueue(ix, ln.d_q.as<float>(), (int32_t)B, kw, ln.d_k.as<int32_t>(), lane_mode, ln.s,
+                              ln.d_idx.as<int64_t>(), ln.d_dist.as<float>(), ln.h_err, ln.h_status, 0, false, true,
+                              sv->lane_cap)) != MESSI_OK)
             break;
         // and a launch of one in FP32 (the split scan's segments)
         if (split && (rc = knn_enqueue(ix, ln.d_q.as<float>(), 1, kw, ln.d_k.as<int32_t>(), MESSI_MODE_FP32, ln.s,
@@ -460,6 +664,47 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
             rc = MESSI_EDEVICE;
             break;
         }
+    }
+    if (rc == MESSI_OK && engine) {
+        // the engine: mapped pinned slot arrays, its stream, and a first
+        // (empty) step that sizes its workspace
+        Engine& e = sv->eng;
+        const size_t S = (size_t)slots;
+        e.S = slots;
+        e.held.resize(S);
+        e.used.assign(S, 0);
+        const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+        if (hipStreamCreateWithFlags(&e.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&e.h_ctl, sizeof(uint32_t) * S, fl) != hipSuccess ||
+            hipHostMalloc((void**)&e.h_q, sizeof(float) * S * L, fl) != hipSuccess ||
+            hipHostMalloc((void**)&e.h_k, sizeof(int32_t) * S, fl) != hipSuccess ||
+            hipHostMalloc((void**)&e.h_phase, sizeof(uint32_t) * S, fl) != hipSuccess ||
+            hipHostMalloc((void**)&e.h_status, sizeof(uint32_t) * S, fl) != hipSuccess ||
+            hipHostMalloc((void**)&e.h_idx, sizeof(int64_t) * S * MESSI_MAX_K, fl) != hipSuccess ||
+            hipHostMalloc((void**)&e.h_dist, sizeof(float) * S * MESSI_MAX_K, fl) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error(MESSI_ENOMEM, "server: engine stream or pinned buffer allocation failed");
+            rc = MESSI_ENOMEM;
+        }
+        if (rc == MESSI_OK) {
+            std::memset(e.h_ctl, 0, sizeof(uint32_t) * S);
+            void* d = nullptr;
+            auto dev = [&](void* h) -> void* {
+                d = nullptr;
+                if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) rc = MESSI_EDEVICE;
+                return d;
+            };
+            e.io.ctl = (const uint32_t*)dev(e.h_ctl);
+            e.io.q = (const float*)dev(e.h_q);
+            e.io.k = (const int32_t*)dev(e.h_k);
+            e.io.phase = (uint32_t*)dev(e.h_phase);
+            e.io.status = (uint32_t*)dev(e.h_status);
+            e.io.idx = (int64_t*)dev(e.h_idx);
+            e.io.dist = (float*)dev(e.h_dist);
+        }
+        if (rc == MESSI_OK) rc = sv->engine_enqueue();
+        if (rc == MESSI_OK && hipStreamSynchronize(e.s) != hipSuccess) rc = MESSI_EDEVICE;
     }
     if (rc != MESSI_OK) {
         const int code = last_error_code();
@@ -529,6 +774,7 @@ int messi_server_stats(messi_server* server, messi_server_counters* out) {
     *out = sv->stats;
     out->lanes = (int32_t)sv->lanes.size();
     out->batch = sv->batch;
+    out->slots = sv->eng.S;
     return MESSI_OK;
 }
 

@@ -26,6 +26,7 @@ MODE_BF16 = 1
 MODE_APPROX = 2  # approximate: the best leaf's members only (not exact)
 SERVER_BATCH_ONLY = 0x100  # OR into a server mode: launches of one query also use the matrix-core filter
 SERVER_NO_GRAPHS = 0x200   # OR into a server mode: eager launches, no HIP graphs
+SERVER_SLOTS = 0x400       # OR into a BF16 server mode: the slot engine instead of lanes of batches
 MAX_K = 1024
 
 EXPORTED = [
@@ -91,7 +92,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_int64), ("bf16_batches", ctypes.c_int64), ("row_filter", ctypes.c_int64),
                 ("requeued", ctypes.c_int64), ("eager_launches", ctypes.c_int64),
                 ("graphs_recorded", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
-                ("lanes", ctypes.c_int32), ("batch", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("lanes", ctypes.c_int32), ("batch", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("slot_steps", ctypes.c_int64), ("slot_admitted", ctypes.c_int64), ("slots", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):

@@ -47,7 +47,7 @@ def served(torch_cuda, messi, datagen_mod, oracle_mod):
     ix.close()
 
 
-def _serve(messi, ix, q, ks, mode, budget, slots, pause):
+def _serve(messi, ix, q, ks, mode, budget, slots, pause, stats=None):
     sv = messi.Server(ix, budget, slots, mode)
     got = {}
     try:
@@ -63,24 +63,37 @@ def _serve(messi, ix, q, ks, mode, budget, slots, pause):
             for r in sv.poll():
                 got[r["tag"]] = r
             time.sleep(0.001)
+        if stats is not None:
+            stats.update(sv.stats())
     finally:
         sv.close()
     return got
 
 
-@pytest.mark.parametrize("mode_name,slots,small_cap", [("BF16", 48, False), ("FP32", 1, False), ("BF16", 48, True)])
+@pytest.mark.parametrize("mode_name,slots,small_cap", [("BF16", 48, False), ("FP32", 1, False), ("BF16", 48, True),
+                                                       ("BF16-slots", 48, False), ("BF16-slots", 48, True)])
 def test_results_alone_and_in_the_mix(served, messi, torch_cuda, oracle_mod, mode_name, slots, small_cap):
     """small_cap: candidate buffers so small that BF16 batches overflow; those
-    queries must come back exact through the FP32 fallback."""
+    queries must come back exact through the FP32 fallback.  BF16-slots: the
+    slot engine instead of lanes of batches."""
     w = served
-    mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
+    mode = messi.MODE_FP32 if mode_name == "FP32" else messi.MODE_BF16
+    if mode_name == "BF16-slots":
+        mode |= messi.SERVER_SLOTS
     # with small_cap, a second index over the same (by now z-normalised) rows with 16 candidate slots
     ix = messi.Index(w["t"], 16, 8, 2000, bf16_shadow=True, cand_cap=16) if small_cap else w["ix"]
     _say("serving %s, %d slots, %d queries, small buffers %s" % (mode_name, slots, len(w["q"]), small_cap))
-    got = _serve(messi, ix, w["q"], w["ks"], mode, 4 << 30, slots, 0.002)
+    st = {}
+    got = _serve(messi, ix, w["q"], w["ks"], mode, 4 << 30, slots, 0.002, st)
     if small_cap:
         ix.close()
+    _say(st)
     assert len(got) == len(w["q"])
+    if mode_name == "BF16-slots":
+        # the slot engine answered queries (and lone ones may have gone FP32)
+        assert st["slots"] == slots and st["slot_steps"] >= 1 and st["slot_admitted"] >= 1
+    else:
+        assert st["slots"] == 0 and st["slot_steps"] == 0
     for i in range(len(w["q"])):
         r = got[i]
         assert r["status"] == messi.MESSI_OK
@@ -110,7 +123,7 @@ def test_budget_and_argument_errors(served, messi):
     sv.close()
 
 
-@pytest.mark.parametrize("mode_name", ["BF16", "FP32"])
+@pytest.mark.parametrize("mode_name", ["BF16", "FP32", "BF16-slots"])
 def test_device_memory_within_budget(served, messi, torch_cuda, mode_name):
     """A budget that binds (fewer slots than asked for): after creation and
     waves of queries of every k (lone ones included, which take the FP32
@@ -119,14 +132,16 @@ def test_device_memory_within_budget(served, messi, torch_cuda, mode_name):
     kernel scratch for the lanes' streams, which the budget does not cover:
     printed, not checked.)"""
     w = served
-    mode = messi.MODE_BF16 if mode_name == "BF16" else messi.MODE_FP32
+    mode = messi.MODE_FP32 if mode_name == "FP32" else messi.MODE_BF16
+    if mode_name == "BF16-slots":
+        mode |= messi.SERVER_SLOTS
     budget = 24 << 20
     torch_cuda.cuda.synchronize()
     free0 = torch_cuda.cuda.mem_get_info()[0]
     sv = messi.Server(w["ix"], budget, 256, mode)
     try:
         st0 = sv.stats()
-        assert st0["lanes"] * st0["batch"] < 256   # the budget binds
+        assert st0["slots"] + st0["lanes"] * st0["batch"] < 256   # the budget binds
         peak = 0
         for lo, hi in ((0, 40), (40, 41), (41, 81), (81, 82)):   # batches, then a lone query
             got = _wave(sv, w["q"][lo:hi], w["ks"][lo:hi], list(range(lo, hi)))
@@ -162,7 +177,8 @@ def _wave(sv, q, ks, tags):
     return got
 
 
-@pytest.mark.parametrize("mode_name,flags", [("BF16", 0), ("BF16", "batch_only"), ("FP32", 0), ("BF16", "no_graphs")])
+@pytest.mark.parametrize("mode_name,flags", [("BF16", 0), ("BF16", "batch_only"), ("FP32", 0), ("BF16", "no_graphs"),
+                                             ("BF16", "slots"), ("BF16", "slots_no_graphs")])
 def test_graph_replays_match_eager_answers(served, messi, torch_cuda, mode_name, flags):
     """The same waves of queries again and again: batch shapes repeat, so the
     lanes record HIP graphs and replay them; between waves the eager search
@@ -173,6 +189,10 @@ def test_graph_replays_match_eager_answers(served, messi, torch_cuda, mode_name,
         mode |= messi.SERVER_BATCH_ONLY
     elif flags == "no_graphs":
         mode |= messi.SERVER_NO_GRAPHS
+    elif flags == "slots":
+        mode |= messi.SERVER_SLOTS
+    elif flags == "slots_no_graphs":
+        mode |= messi.SERVER_SLOTS | messi.SERVER_NO_GRAPHS
     q = w["q"][:8]
     ks = np.array([10, 10, 1, 1, 100, 100, 10, 10], dtype=np.int32)
     want = {}
@@ -198,7 +218,7 @@ def test_graph_replays_match_eager_answers(served, messi, torch_cuda, mode_name,
         sv.close()
     _say(st)
     assert st["batches"] == st["eager_launches"] + st["graphs_recorded"] + st["graph_replays"]
-    if flags == "no_graphs":
+    if flags in ("no_graphs", "slots_no_graphs"):
         assert st["graphs_recorded"] == 0 and st["graph_replays"] == 0
     else:
         assert st["graphs_recorded"] >= 1 and st["graph_replays"] >= 1
