@@ -936,6 +936,8 @@ def bench_serving(args):
         modes += [("bf16_batch_only", messi.MODE_BF16 | messi.SERVER_BATCH_ONLY, 256),
                   ("bf16_no_graphs", messi.MODE_BF16 | messi.SERVER_NO_GRAPHS, 256),
                   ("bf16_slots", messi.MODE_BF16 | messi.SERVER_SLOTS, 256)]
+    # the FP32 server: lanes of batches on the FP32 matrix-core filter
+    modes += [("fp32_server", messi.MODE_FP32, 256)]
     if not args.no_fifo:
         modes += [("fp32_fifo", messi.MODE_FP32, 1)]
     for name, mode, slots in modes:

@@ -123,16 +123,18 @@ typedef struct {
     /* scan kernel, per block (device wall clock): mean time in leaf control,
        member filtering and distances, mean and max block lifetime */
     double scan_ms_control, scan_ms_filter, scan_ms_distance, scan_ms_block_mean, scan_ms_block_max;
-    /* BF16 mode: device time of the matrix-core filter and of the recheck
-       kernels, and the filter's multiply-add work (2 * padded len per pair) */
+    /* BF16 mode, and FP32 calls of several queries (the FP32 matrix-core
+       filter on the fp32 rows, for rows of a length divisible by 4 and at
+       most 256): device time of the filter and of the recheck kernels; BF16
+       mode only: the filter's multiply-add work (2 * padded len per pair) */
     double ms_bf16_filter, ms_bf16_recheck;
     int64_t bf16_flops;
     int32_t bf16_rounds;
     /* FP32 mode: queries whose candidate buffer overflowed and whose scan was
        run a second time from the k-th buffered distance */
     int32_t reruns;
-    /* BF16 mode: queries answered again by the FP32 path because their
-       candidate or filter-pair buffer overflowed */
+    /* BF16 mode and the FP32 filter: queries answered again by the one-query
+       FP32 path because their candidate or filter-pair buffer overflowed */
     int32_t fallbacks;
     /* FP32 mode: device time after the first scan pass (candidate fix-up,
        the second pass when needed); ms_scan is then the first pass alone */
@@ -344,7 +346,10 @@ typedef struct {
  * BF16 row filter (see messi_knn_ex).  A result never
  * depends on which queries shared its batch: each query carries its own
  * status, and a query whose BF16 buffers overflow is answered again, alone,
- * in FP32 mode before its result is posted.
+ * in FP32 mode before its result is posted.  When most queries of BF16
+ * batches overflow (a moving average above one half), batches take the FP32
+ * matrix-core filter instead (rows of a length divisible by 4, at most 256),
+ * with a BF16 batch every 256 batches.
  *   budget_bytes  device memory the server may use for per-query state; the
  *                 slot count is min(max_slots, budget_bytes / per-query need);
  *                 0 takes the index's messi_opts.budget_bytes (8 GiB if that is 0).

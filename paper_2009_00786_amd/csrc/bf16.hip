@@ -39,6 +39,11 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // With a batch of queries nearly every leaf is visited in every later round,
 // so a round costs a pass over most of the BF16 rows: few rounds.
 constexpr uint32_t kRoundEnds[] = {16u, 0xffffffffu, 0xffffffffu};
+// The FP32 filter's rounds: its test is tight, so the members a round
+// appends are those within the query's bound at the round's start; more,
+// growing rounds keep that bound close to the k-th distance (and the
+// candidate buffers small) on data with many near-equal distances.
+constexpr uint32_t kRoundEndsF32[] = {16u, 128u, 1024u, 8192u, 0xffffffffu};
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -141,6 +146,7 @@ struct BfArgs {
     uint32_t pairs_cap;
     int32_t qc;             // queries of a leaf staged in LDS at a time (multiple of 16)
     float one_minus_h;      // 1 - h, rounded down
+    float f32_c;            // FP32 filter: slack per unit of |q|^2 + |x|^2
 };
 
 // Per query: 2 q in BF16 (an exact doubling of the rounded q), |q|^2 and |q|
@@ -513,6 +519,183 @@ __device__ __forceinline__ void two_sum_merge(float& s, float& c, float s2, floa
 }
 
 // 16 lanes per (query, member) pair, 4 pairs per wave.
+// ---------------------------------------------------------------------------
+// The FP32 filter: the same leaf-major rounds as the BF16 filter, on the fp32
+// rows themselves (no shadow) with the fp32 matrix instruction
+// mfma_f32_16x16x4_f32, for batches whose BF16 margin is too wide to prune
+// (short rows, many near-equal distances) or calls in FP32 mode.
+//   acc = q.x accumulated in fp32 in any order: |acc - q.x| <= gamma_L |q||x|
+//   <= gamma_L (|q|^2 + |x|^2) / 2; |q|^2 is the fp32 rounding of an fp64
+//   sum, |x|^2 an fp32 sum of squares (error <= gamma_{L+1} |x|^2), and the
+//   test's own three roundings add at most 3u (|q|^2 + |x|^2 + 2|acc|).  So
+//     D >= (|q|^2 + |x|^2 - 2 acc) - c (|q|^2 + |x|^2) - 8u |acc|,
+//   c = (4 (L + 2) + 8) u (u = 2^-23, as for the BF16 filter), and a member
+//   is dropped for a query only when that lower bound exceeds U (1 + 2^-20):
+//   the drop is exact, and survivors are rechecked as BF16 survivors are.
+// Layout: the 16x16x4 instruction takes A[i][k] from lane 16k + i and B[k][j]
+// from lane 16k + j, and leaves D[4k' + r][j] in lane 16k' + j.  The k index
+// of the product is permuted: k-step s, sub-index k covers element k E + s of
+// the row (E = Lq / 4), so each lane holds one contiguous quarter of its
+// member's row (float4 loads) and reads one contiguous quarter of a query row
+// from LDS.  F 16-member fragments per wave, QT 16-query tiles per pass.
+// ---------------------------------------------------------------------------
+template <int E, int F>
+__global__ void __launch_bounds__(kFThreads) f32_filter_kernel(QArgs a, BfArgs bf) {
+    extern __shared__ __align__(16) uint8_t s_raw[];
+    constexpr int QT = 2;
+    constexpr int Lq = 4 * E, lda = Lq + 4;  // padded rows: a tile's 16 rows start in different banks
+    const int QC = bf.qc, L = a.L;
+    float* s_q = reinterpret_cast<float*>(s_raw);
+    float* s_thr = s_q + (size_t)QC * lda;  // U (1 + 2^-20) of the query when staged
+    float* s_qn = s_thr + QC;               // |q|^2
+    uint32_t* s_qid = reinterpret_cast<uint32_t*>(s_qn + QC);
+    __shared__ uint32_t s_leaf;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, kb = lane >> 4;
+    const float cq = bf.f32_c, ca = 8.0f * 1.1920928955078125e-07f;
+    unsigned long long c_eval = 0, c_bytes = 0;
+    const uint32_t nact = bf.npairs[2];
+    for (;;) {
+        __syncthreads();  // every wave is done with the previous leaf's LDS
+        if (tid == 0) s_leaf = atomicAdd(&bf.npairs[1], 1u);
+        __syncthreads();
+        const uint32_t li = s_leaf;
+        if (li >= nact) break;
+        const uint32_t leaf = bf.leaf_act[li];
+        const uint32_t cntq = bf.leaf_cnt[leaf];
+        const Leaf lf = a.leaves[leaf];
+        const uint32_t qoff = bf.leaf_off[leaf];
+        for (uint32_t qc0 = 0; qc0 < cntq; qc0 += QC) {
+            const int nqc = (int)min((uint32_t)QC, cntq - qc0);
+            const int nrows = (nqc + 15) & ~15;
+            if (qc0 > 0) __syncthreads();
+            for (int r = tid; r < nrows; r += kFThreads) {
+                if (r < nqc) {
+                    const uint32_t q = bf.leaf_q[qoff + qc0 + r];
+                    s_qid[r] = q;
+                    s_qn[r] = bf.qnorm[q].x;
+                    s_thr[r] = __fmul_rn(__uint_as_float(vload(&a.qs[q].U)), 1.00000095367431640625f);
+                } else {
+                    s_qid[r] = 0xffffffffu;
+                    s_qn[r] = 0.f;
+                    s_thr[r] = -__uint_as_float(0x7f800000u);
+                }
+            }
+            __syncthreads();
+            // the rows, 16 bytes at a time (values past L and rows past nqc are zero)
+            constexpr int chunks = Lq / 4;
+            const int total = nrows * chunks;
+            for (int idx = tid; idx < total; idx += kFThreads) {
+                const int r = idx / chunks, c4 = 4 * (idx % chunks);
+                const uint32_t q = s_qid[r];
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (q != 0xffffffffu && c4 < L) v = *reinterpret_cast<const float4*>(a.queries + (size_t)q * L + c4);
+                *reinterpret_cast<float4*>(&s_q[r * lda + c4]) = v;
+            }
+            __syncthreads();
+            for (uint32_t mt0 = 0; mt0 < lf.count; mt0 += kFWaves * 16 * F) {
+                const uint32_t mb = mt0 + wave * 16 * F;
+                if (mb >= lf.count) continue;
+                float b[F][E];
+                float xn[F];
+                bool mval[F];
+                uint32_t mpos[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const uint32_t mi = mb + f * 16 + col;
+                    mval[f] = mi < lf.count;
+                    mpos[f] = lf.start + (mval[f] ? mi : 0u);
+                    const float* row = a.series + (size_t)a.pos[mpos[f]] * L + kb * E;
+#pragma unroll
+                    for (int j = 0; j < E; j += 4) {
+                        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (mval[f] && kb * E + j < L) v = *reinterpret_cast<const float4*>(row + j);
+                        b[f][j] = v.x;
+                        b[f][j + 1] = v.y;
+                        b[f][j + 2] = v.z;
+                        b[f][j + 3] = v.w;
+                    }
+                    if (mval[f] && kb == 0) c_bytes += (uint64_t)L * 4;
+                    float sq = 0.f;
+#pragma unroll
+                    for (int j = 0; j < E; ++j) sq = fmaf(b[f][j], b[f][j], sq);
+                    sq += __shfl_xor(sq, 16);
+                    sq += __shfl_xor(sq, 32);
+                    xn[f] = sq;
+                }
+                for (int qg0 = 0; qg0 < nqc; qg0 += 16 * QT) {
+                    const int ntile = min(QT, (nqc - qg0 + 15) / 16);
+                    floatx4 acc[QT][F];
+#pragma unroll
+                    for (int t = 0; t < QT; ++t)
+#pragma unroll
+                        for (int f = 0; f < F; ++f) acc[t][f] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    const float* arow = &s_q[(qg0 + col) * lda + kb * E];
+#pragma unroll
+                    for (int j = 0; j < E; j += 4) {
+                        float4 av[QT];
+#pragma unroll
+                        for (int t = 0; t < QT; ++t)
+                            av[t] = t < ntile ? *reinterpret_cast<const float4*>(arow + t * 16 * lda + j)
+                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                        for (int t = 0; t < QT; ++t) {
+                            if (t < ntile) {
+#pragma unroll
+                                for (int f = 0; f < F; ++f) {
+                                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t].x, b[f][j], acc[t][f], 0, 0, 0);
+                                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t].y, b[f][j + 1], acc[t][f], 0, 0, 0);
+                                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t].z, b[f][j + 2], acc[t][f], 0, 0, 0);
+                                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t].w, b[f][j + 3], acc[t][f], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
+                    // acc[t][f][r]: query row qg0 + 16 t + 4 kb + r, member col of fragment f
+#pragma unroll
+                    for (int t = 0; t < QT; ++t) {
+                        if (t >= ntile) continue;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int qi = qg0 + 16 * t + 4 * kb + r;
+                            if (qi >= nqc) continue;
+                            const float thr = s_thr[qi], qn = s_qn[qi];
+#pragma unroll
+                            for (int f = 0; f < F; ++f) {
+                                if (!mval[f]) continue;
+                                ++c_eval;
+                                const float ac = acc[t][f][r];
+                                const float sn = __fadd_rn(qn, xn[f]);
+                                const float est = __fsub_rn(sn, __fadd_rn(ac, ac));
+                                const float slack = __fadd_rn(__fmul_rn(cq, sn), __fmul_rn(ca, fabsf(ac)));
+                                if (!(__fsub_rn(est, slack) > thr)) {
+                                    const uint32_t slot = atomicAdd(bf.npairs, 1u);
+                                    const uint32_t q = s_qid[qi];
+                                    if (slot < bf.pairs_cap) {
+                                        bf.pairs[slot] = make_uint2(q, mpos[f]);
+                                    } else {
+                                        if (a.qs[q].err == 0) a.qs[q].err = 5;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (a.counters) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            c_eval += __shfl_xor(c_eval, off);
+            c_bytes += __shfl_xor(c_bytes, off);
+        }
+        if (lane == 0) {
+            atomicAdd(&a.counters->distance, c_eval);
+            atomicAdd(&a.counters->bytes, c_bytes);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) bf16_recheck_kernel(QArgs a, BfArgs bf) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4, ql = lane & 15;
@@ -620,7 +803,7 @@ int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
     const int nq = a.nq;
     if (ws->qb.bytes < sizeof(uint16_t) * (size_t)nq * Lp || ws->qnorm.bytes < sizeof(float2) * (size_t)nq ||
         ws->qx.bytes < sizeof(uint4) * (size_t)nq) {
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(growth_sync(s));
         ws->bf_nq = 0;  // the batched filter's buffers are sized again on its next call
         ++ws->gen;
         MESSI_TRY(ws->grow(ix, ws->qb, sizeof(uint16_t) * (size_t)nq * Lp));
@@ -645,7 +828,20 @@ int bf16_row_prep(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s) {
 namespace {
 
 // The filter's buffers in the workspace (for a.nq queries) and its arguments.
-int bf16_setup(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, BfArgs& bf, size_t& filter_lds) {
+// FP32 filter instance for rows of L values: E = Lq / 4 floats per lane.
+int f32_filter_e(int L) { return L <= 32 ? 8 : L <= 64 ? 16 : L <= 128 ? 32 : 64; }
+
+const void* f32_filter_fn(int E) {
+    switch (E) {
+        case 8: return (const void*)f32_filter_kernel<8, 2>;
+        case 16: return (const void*)f32_filter_kernel<16, 2>;
+        case 32: return (const void*)f32_filter_kernel<32, 2>;
+        default: return (const void*)f32_filter_kernel<64, 1>;
+    }
+}
+
+int bf16_setup(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, BfArgs& bf, size_t& filter_lds,
+               bool f32 = false) {
     const int L = ix->len;
     const int Lp = (L + 31) / 32 * 32;
     const int nq = a.nq;
@@ -653,7 +849,7 @@ int bf16_setup(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, BfArgs& 
     const size_t leafq_cap = (size_t)nq * nL;
     const size_t pairs_cap = bf16_pairs_cap(nq);
     if (ws->bf_nq < nq || ws->bf_pairs_cap < pairs_cap || ws->bf_leafq_cap < leafq_cap) {
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(growth_sync(s));
         // not valid until every buffer is in place (a failed allocation leaves its buffer empty)
         ws->bf_nq = 0;
         ws->bf_pairs_cap = ws->bf_leafq_cap = 0;
@@ -693,21 +889,31 @@ int bf16_setup(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, BfArgs& 
     // queries staged per leaf: as many as the LDS of one block holds (at most 256)
     int lds_max = 65536;
     (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device);
-    const size_t row_bytes = (size_t)(Lp + 8) * 2 + 24;  // row, alpha, extra k-step, id
+    const int E = f32_filter_e(L);
+    // BF16: row, alpha, extra k-step, id; FP32: padded fp32 row, bound, |q|^2, id
+    const size_t row_bytes = f32 ? (size_t)(4 * E + 4) * 4 + 12 : (size_t)(Lp + 8) * 2 + 24;
     int qc = (int)std::min<size_t>(256, (size_t)(lds_max - 1024) / row_bytes) / 16 * 16;
     if (qc < 16) qc = 16;
     bf.qc = qc;
     ws->bf_stage_queries = qc;
     filter_lds = (size_t)qc * row_bytes;
-    MESSI_HIP_TRY(hipFuncSetAttribute((const void*)bf16_filter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)filter_lds));
+    if (f32) {
+        const double u = std::ldexp(1.0, -23);
+        bf.f32_c = (float)((4.0 * (L + 2) + 8.0) * u);
+    }
+    MESSI_HIP_TRY(hipFuncSetAttribute(f32 ? f32_filter_fn(E) : (const void*)bf16_filter_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)filter_lds));
 
     return MESSI_OK;
 }
 
 }  // namespace
 
-int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing) {
+bool f32_filter_ok(const Index* ix) {
+    return ix->len % 4 == 0 && ix->len <= 256 && (uintptr_t)ix->series % 16 == 0;
+}
+
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing, bool f32) {
     const int L = ix->len;
     const int Lp = (L + 31) / 32 * 32;
     const int nq = a.nq;
@@ -715,7 +921,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     const size_t leafq_cap = (size_t)nq * nL;
     BfArgs bf;
     size_t filter_lds = 0;
-    MESSI_TRY(bf16_setup(ix, a, ws, s, bf, filter_lds));
+    MESSI_TRY(bf16_setup(ix, a, ws, s, bf, filter_lds, f32));
     const BfConsts kc = bf_consts(Lp);
     hipLaunchKernelGGL(qprep_bf16_kernel, dim3(nq), dim3(256), 0, s, a.queries, L, Lp,
                        std::nextafter((float)kc.c1p, 1.0f), ws->qb.as<uint16_t>(), ws->qnorm.as<float2>(),
@@ -739,7 +945,7 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     uint64_t t1 = 0;
     for (int round = 0; t1 < (uint64_t)nL; ++round) {
         const uint64_t t0 = t1;
-        t1 = std::min<uint64_t>(kRoundEnds[std::min(round, 2)], (uint64_t)nL);
+        t1 = std::min<uint64_t>(f32 ? kRoundEndsF32[std::min(round, 4)] : kRoundEnds[std::min(round, 2)], (uint64_t)nL);
         const unsigned tbr = (unsigned)((t1 - t0 + 255) / 256);
         const uint32_t r0 = (uint32_t)t0, r1 = (uint32_t)t1;
         hipLaunchKernelGGL(round_reset_kernel, dim3((unsigned)std::min<size_t>((nL + 255) / 256, 1024)), dim3(256), 0,
@@ -757,8 +963,18 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
                            leafq_cap);
         MESSI_LAUNCH_CHECK("leaf_scatter");
         MESSI_TRY(mark());
-        hipLaunchKernelGGL(bf16_filter_kernel, dim3(cus), dim3(kFThreads), filter_lds, s, a, bf);
-        MESSI_LAUNCH_CHECK("bf16_filter");
+        if (f32) {
+            switch (f32_filter_e(L)) {
+                case 8: hipLaunchKernelGGL((f32_filter_kernel<8, 2>), dim3(cus), dim3(kFThreads), filter_lds, s, a, bf); break;
+                case 16: hipLaunchKernelGGL((f32_filter_kernel<16, 2>), dim3(cus), dim3(kFThreads), filter_lds, s, a, bf); break;
+                case 32: hipLaunchKernelGGL((f32_filter_kernel<32, 2>), dim3(cus), dim3(kFThreads), filter_lds, s, a, bf); break;
+                default: hipLaunchKernelGGL((f32_filter_kernel<64, 1>), dim3(cus), dim3(kFThreads), filter_lds, s, a, bf); break;
+            }
+            MESSI_LAUNCH_CHECK("f32_filter");
+        } else {
+            hipLaunchKernelGGL(bf16_filter_kernel, dim3(cus), dim3(kFThreads), filter_lds, s, a, bf);
+            MESSI_LAUNCH_CHECK("bf16_filter");
+        }
         MESSI_TRY(mark());
         hipLaunchKernelGGL(bf16_recheck_kernel, dim3(cus * 8), dim3(256), 0, s, a, bf);
         MESSI_LAUNCH_CHECK("bf16_recheck");

@@ -151,6 +151,20 @@ struct QArgs {
     uint32_t* win;               // [nq][3]: window of order positions [r0, r1) this step, and the round
 };
 
+// Wait for the stream before a workspace buffer is reallocated.  Refused
+// (MESSI_EDEVICE, nothing waited for) while the stream is being captured
+// into a graph, so that a capture never records an allocation: the caller
+// then runs the launch eagerly, which sizes the workspace.
+inline int growth_sync(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        set_error(MESSI_EDEVICE, "a search workspace would grow while its stream is being captured");
+        return MESSI_EDEVICE;
+    }
+    MESSI_HIP_TRY(hipStreamSynchronize(s));
+    return MESSI_OK;
+}
+
 // Phases of a slot of the serving engine.
 constexpr uint32_t kSlotFree = 0, kSlotAdmit = 1, kSlotActive = 2, kSlotFinal = 3, kSlotDone = 4;
 
@@ -200,7 +214,11 @@ struct Workspace {
 // The batched BF16 filter + compensated fp32 recheck (bf16.hip); runs after the
 // shared prefix (prep, leaf bounds, first bound, leaf order) and before the
 // shared fp64 final ordering.
-int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing);
+// f32: the FP32 filter on the fp32 rows instead (f32_filter_ok(ix) must hold).
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing, bool f32 = false);
+// Whether the FP32 filter takes the index's rows (length a multiple of 4, at
+// most 256, rows 16-byte aligned).
+bool f32_filter_ok(const Index* ix);
 
 // One BF16 filter round of the serving engine's active slots (a.phase, a.win).
 int bf16_slot_round(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s);

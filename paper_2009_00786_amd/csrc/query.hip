@@ -3242,7 +3242,10 @@ uint32_t default_cap(const Index* ix, int32_t nq, int32_t kmax, int32_t mode) {
     if (ix->opts.cand_cap > 0)
         return std::max<uint32_t>(floor_k, std::min<uint32_t>(ix->opts.cand_cap, 1u << 30));
     if (nq == 1) return 1u << 20;
-    const uint32_t lo = mode == MESSI_MODE_BF16 ? (1u << 16) : (1u << 14);
+    // the batch filters (BF16, and FP32 on rows the FP32 filter takes)
+    // append every member within the bound of a round: a larger buffer
+    const bool batch_filter = mode == MESSI_MODE_BF16 || (mode == MESSI_MODE_FP32 && f32_filter_ok(ix));
+    const uint32_t lo = batch_filter ? (1u << 16) : (1u << 14);
     return std::max<uint32_t>(lo, 64u * (uint32_t)kmax);
 }
 
@@ -3315,7 +3318,7 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, bool
     if (!ws) ws = new Workspace();
     const size_t slots = (size_t)cap * (size_t)nq;
     if (ws->nq < nq || ws->nL != ix->n_leaves) {
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(growth_sync(s));
         const int32_t nqa = std::max(nq, ws->nq);
         // not valid until every buffer is in place (a failed allocation leaves its buffer empty)
         ws->nq = 0;
@@ -3352,7 +3355,7 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, bool
     }
     if (split && nq <= kSplitMaxQ && (ws->seg_nq < nq || ws->seg.bytes < sizeof(uint32_t) * (size_t)ws->max_chunks *
                                                                             (size_t)ix->opts.scan_chunk * (size_t)nq)) {
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(growth_sync(s));
         ws->seg_nq = 0;
         ++ws->gen;
         ws->seg.release();
@@ -3373,7 +3376,7 @@ int get_workspace(const Index* ix, hipStream_t s, int32_t nq, uint32_t cap, bool
         ++ws->gen;
     }
     if (ws->cand_slots < slots) {
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(growth_sync(s));
         ws->cand_slots = 0;
         ++ws->gen;
         MESSI_TRY(ws->grow(ix, ws->cand, sizeof(Cand) * slots));
@@ -3676,6 +3679,10 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     const bool rowf = row_filter_path(ix, mode, nq, c.matrix_only);
     if (mode == MESSI_MODE_BF16 && !rowf) {
         MESSI_TRY(bf16_scan(ix, a, ws, s, timing));
+    } else if (mode == MESSI_MODE_FP32 && nq > kSplitMaxQ && ws && f32_filter_ok(ix)) {
+        // several queries in FP32: the leaf-major FP32 filter, one read of a
+        // leaf's rows for all the queries that visit it
+        MESSI_TRY(bf16_scan(ix, a, ws, s, timing, true));
     } else {
         const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
         if (rowf) {
@@ -3778,7 +3785,7 @@ int slot_step_enqueue(const Index* ix, hipStream_t s, int32_t S, const SlotIO& i
     uint32_t cap = 0;
     MESSI_TRY(setup_call(c, false, &ws, a, cap));
     if (ws->slot_n < S) {
-        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        MESSI_TRY(growth_sync(s));
         ws->slot_n = 0;
         ++ws->gen;
         MESSI_TRY(ws->grow(ix, ws->slot_phase, sizeof(uint32_t) * (size_t)S));
@@ -4196,7 +4203,7 @@ size_t workspace_bytes_per_query(const Index* ix, int32_t mode, uint32_t cap) {
                sizeof(uint32_t) * (size_t)max_chunks_of(ix) + kNB * (2 * sizeof(uint32_t) + sizeof(unsigned long long)) +
                sizeof(uint32_t) * kHistBins + sizeof(float) * kApproxMax + sizeof(Cand) * (size_t)cap +
                sizeof(LbPart) * ((nL + kLeafBlock - 1) / kLeafBlock) + sizeof(uint32_t);
-    if (mode == MESSI_MODE_BF16)
+    if (mode == MESSI_MODE_BF16 || (mode == MESSI_MODE_FP32 && f32_filter_ok(ix)))
         b += nL * 4 + sizeof(uint2) * bf16_pairs_cap(1) + (size_t)((ix->len + 31) / 32 * 32) * 2 + 8 + 16;
     return b;
 }
@@ -4232,12 +4239,11 @@ void add_stats(messi_knn_stats* t, const messi_knn_stats& u) {
 
 int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, const int32_t* kq, int32_t mode,
                hipStream_t s, int64_t* out_idx, float* out_dist, messi_knn_stats* stats) {
-    if (mode == MESSI_MODE_FP32 && nq > kSplitMaxQ) {
-        // Several queries in FP32 mode: one after another, each through the
-        // one-query path.  The split scan spreads one query over the whole
-        // GPU, while a batch kernel gives each query only its share of the
-        // blocks, which a hard query (millions of rows within its bound)
-        // cannot afford.  Per-query errors: the first is returned, after
+    if (mode == MESSI_MODE_FP32 && nq > kSplitMaxQ && !f32_filter_ok(ix)) {
+        // Several queries in FP32 mode on rows the FP32 filter does not take:
+        // one after another, each through the one-query path.  The flat batch
+        // kernel gives each query only its share of the blocks, which a hard
+        // query (millions of rows within its bound) cannot afford.  Per-query errors: the first is returned, after
         // every query has been answered.
         if (stats) *stats = messi_knn_stats{};
         messi_knn_stats sub{};
@@ -4280,7 +4286,9 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
     // timing, and its statistics slots span the coarse kernel's grid
     const bool split = mode == MESSI_MODE_FP32 && a.seg != nullptr;
     const int sg = split ? split_grid(0) : scan_grid(rowf ? kScanRowFilter : kScanEd);
-    const bool fp32 = mode == MESSI_MODE_FP32 || rowf;  // the ordered scan runs
+    // several queries in FP32 mode on rows it takes: the leaf-major FP32 filter
+    const bool f32f = mode == MESSI_MODE_FP32 && nq > kSplitMaxQ && f32_filter_ok(ix);
+    const bool fp32 = (mode == MESSI_MODE_FP32 && !f32f) || rowf;  // the ordered scan runs
     const unsigned long long* hprof = nullptr;
     const unsigned long long* hcnt = nullptr;
     int32_t retries = 0;
@@ -4332,11 +4340,11 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         word_b += h[7];
         fine_b += h[8];
     }
-    // BF16 mode: a query whose candidates or filter pairs overflowed their
-    // buffers is answered again, alone, by the FP32 path (which reruns and
-    // grows its own buffer as needed).
+    // BF16 mode and the FP32 filter: a query whose candidates or filter pairs
+    // overflowed their buffers is answered again, alone, by the one-query
+    // FP32 path (which reruns and grows its own buffer as needed).
     int32_t fallbacks = 0;
-    if (mode == MESSI_MODE_BF16 && (err & (2u | 4u | 16u)) && !(err & 1u)) {
+    if ((mode == MESSI_MODE_BF16 || f32f) && (err & (2u | 4u | 16u)) && !(err & 1u)) {
         std::vector<uint32_t> st(nq);
         hipLaunchKernelGGL(status_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, a, ws->status.as<uint32_t>());
         MESSI_LAUNCH_CHECK("status");
@@ -4397,14 +4405,14 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         if (rowf) {
             const int Lp = (ix->len + 31) / 32 * 32;
             stats->bf16_flops = (int64_t)bf_rows * 2 * Lp;
-        } else if (mode == MESSI_MODE_BF16) {
+        } else if (mode == MESSI_MODE_BF16 || f32f) {
             const int Lp = (ix->len + 31) / 32 * 32;
             stats->ms_bf16_filter = ws->bf_ms_filter;
             stats->ms_bf16_recheck = ws->bf_ms_recheck;
             stats->bf16_rounds = ws->bf_rounds;
             stats->bf16_stage_queries = ws->bf_stage_queries;
             stats->bf16_max_leaf_queries = ws->bf_max_leaf_q;
-            stats->bf16_flops = (int64_t)hc.distance * 2 * Lp;
+            stats->bf16_flops = f32f ? 0 : (int64_t)hc.distance * 2 * Lp;
             stats->scan_launches = ws->bf_rounds;
         }
         if (hprof) {

@@ -30,6 +30,13 @@
 // Slots and host exchange queries, phases and answers through mapped pinned
 // memory.  Lone queries and retries go to one FP32 lane.
 //
+// A BF16 batch whose queries mostly overflow the filter's buffers (its
+// margin is too wide for the data: short rows, many near-equal distances)
+// costs a filter pass and then every query again alone; when that share
+// exceeds one half (a moving average over BF16 batches), batches go to the
+// FP32 matrix-core filter instead, with a BF16 batch every 256 to notice
+// when BF16 pays again.
+//
 // A lane's whole launch (copies in, the search, copies out) is recorded once
 // per batch shape (query count, largest k, mode, buffer size) into a HIP graph
 // and replayed afterwards: the first batch of a shape runs eagerly, which
@@ -132,6 +139,12 @@ struct Server {
     bool row_filter = true;  // BF16 mode: a launch of one query is answered alone, off the matrix-core filter
     bool split = true;       // FP32 launches of one query take the split scan (its buffers are in the budget)
     uint32_t lane_cap = kSlotCap;  // candidate slots of a lane (batch x kSlotCap): a lone query may use them all
+    // BF16 mode: the share of a BF16 batch's queries that overflowed (moving
+    // average); above one half, batches go to the FP32 matrix-core filter
+    // (every 256th batch still tries BF16, to notice when it pays again)
+    double bf16_overflow = 0.0;
+    int64_t fp32_batches_since = 0;
+    bool f32_filter = false;  // the index's rows suit the FP32 filter
     bool use_graphs = true;
     int32_t batch = 1;  // queries per lane
     messi_server_counters stats{};  // guarded by mu
@@ -210,6 +223,9 @@ struct Server {
         // one-query scan bounds members by their fine summary (64 bytes) before
         // any row, where the row-filtered scan reads a 512-byte BF16 row
         if (ln.mode == MESSI_MODE_BF16 && nq == 1 && row_filter && ix->wf > 0) ln.mode = MESSI_MODE_FP32;
+        if (ln.mode == MESSI_MODE_BF16 && nq > 1 && f32_filter && bf16_overflow > 0.5) {
+            if (++fp32_batches_since % 256 != 0) ln.mode = MESSI_MODE_FP32;
+        }
         *ln.h_err = 0;
         // a retry after an overflow: 16 times the lane's slots per retry, a
         // transient excess over the budget (the lane drops it afterwards)
@@ -280,8 +296,10 @@ struct Server {
                 Pending p = std::move(ln.batch[i]);
                 fallbacks += 1;
                 if (!p.fp32) {
+                    // alone in FP32 mode; with a larger buffer only if it was
+                    // alone in FP32 mode already
                     p.fp32 = true;
-                    p.grow = ln.mode == MESSI_MODE_FP32 ? 1 : 0;
+                    p.grow = ln.mode == MESSI_MODE_FP32 && ln.batch.size() == 1 ? 1 : 0;
                 } else {
                     ++p.grow;
                 }
@@ -303,13 +321,27 @@ struct Server {
             }
             out.push_back(r);
         }
+        if (ln.mode == MESSI_MODE_BF16 && ln.batch.size() > 1 && launch_status == MESSI_OK)
+            bf16_overflow = 0.75 * bf16_overflow + 0.25 * (double)fallbacks / (double)ln.batch.size();
         ln.batch.clear();
         ln.busy = false;
-        // a retry's larger candidate buffer goes back (the lane's graphs that
-        // hold its address are re-recorded on their next use)
-        if (ln.cap_min > lane_cap && trim_candidates(ix, ln.s, lane_cap) != MESSI_OK) (void)hipGetLastError();
+        // a retry's larger candidate buffer goes back; the lane's graphs hold
+        // its address, and every shape runs eagerly once more (which sizes the
+        // workspace again) before it is recorded
+        if (ln.cap_min > lane_cap) {
+            if (trim_candidates(ix, ln.s, lane_cap) != MESSI_OK) {
+                (void)hipGetLastError();
+                clear_error();
+            }
+            for (auto& kv : ln.graphs) drop_graph(kv.second);
+            ln.graphs.clear();
+            ln.seen.clear();
+        }
         ln.cap_min = 0;
+        size_t dev_bytes = eng.S ? workspace_device_bytes(ix, eng.s) : 0;
+        for (const Lane& l : lanes) dev_bytes += workspace_device_bytes(ix, l.s) + l.staging_bytes();
         std::lock_guard<std::mutex> lk(mu);
+        stats.device_bytes = (int64_t)dev_bytes;
         stats.requeued += fallbacks;
         for (auto* r : out) ready.push_back(r);
         for (auto it = redo.rbegin(); it != redo.rend(); ++it) pending.push_front(std::move(*it));
@@ -606,6 +638,7 @@ messi_server* messi_server_create(const messi_index* index, size_t budget_bytes,
     sv->row_filter = !(flags & MESSI_SERVER_BATCH_ONLY);
     sv->use_graphs = !(flags & MESSI_SERVER_NO_GRAPHS);
     sv->split = split;
+    sv->f32_filter = f32_filter_ok(ix);
     sv->device = ix->device;
     const int nl = engine ? 1 : std::min(4, slots);
     sv->batch = engine ? 1 : slots / nl;   // (lanes x batch <= slots: within the budget)
