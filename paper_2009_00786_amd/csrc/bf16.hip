@@ -39,11 +39,25 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // With a batch of queries nearly every leaf is visited in every later round,
 // so a round costs a pass over most of the BF16 rows: few rounds.
 constexpr uint32_t kRoundEnds[] = {16u, 0xffffffffu, 0xffffffffu};
-// The FP32 filter's rounds: its test is tight, so the members a round
-// appends are those within the query's bound at the round's start; more,
-// growing rounds keep that bound close to the k-th distance (and the
-// candidate buffers small) on data with many near-equal distances.
+// The FP32 filter's rounds when its batch is wide.  Its test is tight, so
+// the members a round appends are those within the query's bound at the
+// round's start.  When the leaf bounds of many of the batch's queries keep
+// more than a quarter of the leaves (data with many near-equal distances),
+// growing rounds keep those bounds close to the k-th distance and the
+// candidate buffers small.  Otherwise the batch takes the BF16 filter's two
+// rounds: fewer rounds share more reads of a leaf's rows among the queries.
 constexpr uint32_t kRoundEndsF32[] = {16u, 128u, 1024u, 8192u, 0xffffffffu};
+
+// Queries whose ordered leaves exceed a quarter of all leaves, into *count.
+__global__ void __launch_bounds__(256) wide_count_kernel(QArgs a, uint32_t* count) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    uint32_t w = 0;
+    if (q < a.nq && a.qs[q].err == 0) w = (uint64_t)a.qs[q].nsurv * 4 > (uint64_t)a.nL ? 1u : 0u;
+    const unsigned long long b = __ballot(w != 0);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (uint32_t)__popcll(b));
+}
+
+__global__ void word_clear_kernel(uint32_t* p) { *p = 0; }
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -182,7 +196,7 @@ __global__ void __launch_bounds__(256) qprep_bf16_kernel(const float* __restrict
 // each active slot has its own window instead.
 __device__ __forceinline__ void round_window(const QArgs& a, int q, uint32_t& t0, uint32_t& t1) {
     if (a.win) {
-        if (a.phase[q] != kSlotActive) {
+        if (a.phase && a.phase[q] != kSlotActive) {
             t0 = t1 = 0;
             return;
         }
@@ -913,7 +927,7 @@ bool f32_filter_ok(const Index* ix) {
     return ix->len % 4 == 0 && ix->len <= 256 && (uintptr_t)ix->series % 16 == 0;
 }
 
-int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing, bool f32) {
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing, bool f32, bool probe) {
     const int L = ix->len;
     const int Lp = (L + 31) / 32 * 32;
     const int nq = a.nq;
@@ -943,9 +957,23 @@ int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timi
     // round every query's bound is refreshed from its candidates, so later
     // rounds are filtered tighter.
     uint64_t t1 = 0;
+    // the FP32 filter: growing rounds for a wide batch (see kRoundEndsF32);
+    // without probe (a launch that may be recorded in a graph: no waiting)
+    // the batch counts as wide
+    bool wide = f32;
+    if (f32 && probe) {
+        uint32_t* cnt = ws->npairs.as<uint32_t>() + 6;
+        hipLaunchKernelGGL(word_clear_kernel, dim3(1), dim3(1), 0, s, cnt);
+        MESSI_LAUNCH_CHECK("word_clear");
+        hipLaunchKernelGGL(wide_count_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, a, cnt);
+        MESSI_LAUNCH_CHECK("wide_count");
+        MESSI_HIP_TRY(hipMemcpyAsync(ws->h_err + 1, cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        MESSI_HIP_TRY(hipStreamSynchronize(s));
+        wide = (uint64_t)ws->h_err[1] * 4 > (uint64_t)nq;
+    }
     for (int round = 0; t1 < (uint64_t)nL; ++round) {
         const uint64_t t0 = t1;
-        t1 = std::min<uint64_t>(f32 ? kRoundEndsF32[std::min(round, 4)] : kRoundEnds[std::min(round, 2)], (uint64_t)nL);
+        t1 = std::min<uint64_t>(wide ? kRoundEndsF32[std::min(round, 4)] : kRoundEnds[std::min(round, 2)], (uint64_t)nL);
         const unsigned tbr = (unsigned)((t1 - t0 + 255) / 256);
         const uint32_t r0 = (uint32_t)t0, r1 = (uint32_t)t1;
         hipLaunchKernelGGL(round_reset_kernel, dim3((unsigned)std::min<size_t>((nL + 255) / 256, 1024)), dim3(256), 0,

@@ -214,8 +214,11 @@ struct Workspace {
 // The batched BF16 filter + compensated fp32 recheck (bf16.hip); runs after the
 // shared prefix (prep, leaf bounds, first bound, leaf order) and before the
 // shared fp64 final ordering.
-// f32: the FP32 filter on the fp32 rows instead (f32_filter_ok(ix) must hold).
-int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing, bool f32 = false);
+// f32: the FP32 filter on the fp32 rows instead (f32_filter_ok(ix) must
+// hold); probe: the call may wait on the stream to see how wide its batch is
+// (else it takes the FP32 filter's growing rounds).
+int bf16_scan(const Index* ix, QArgs& a, Workspace* ws, hipStream_t s, bool timing, bool f32 = false,
+              bool probe = false);
 // Whether the FP32 filter takes the index's rows (length a multiple of 4, at
 // most 256, rows 16-byte aligned).
 bool f32_filter_ok(const Index* ix);

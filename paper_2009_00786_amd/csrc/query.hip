@@ -3557,6 +3557,7 @@ struct CallArgs {
     bool matrix_only = false;  // BF16: keep few queries on the matrix-core filter
     bool split = true;         // FP32, one query: the split scan when its buffers fit
     uint32_t cap_limit = 0;    // nonzero: the default candidate buffer per query is at most this
+    bool probe = false;        // the call may wait on its stream mid-search (not recorded in a graph)
 };
 
 // The call's arguments that do not depend on where its workspace lives.
@@ -3682,7 +3683,7 @@ int launch_search(const CallArgs& c, QArgs& a, Workspace* ws, uint32_t cap, bool
     } else if (mode == MESSI_MODE_FP32 && nq > kSplitMaxQ && ws && f32_filter_ok(ix)) {
         // several queries in FP32: the leaf-major FP32 filter, one read of a
         // leaf's rows for all the queries that visit it
-        MESSI_TRY(bf16_scan(ix, a, ws, s, timing, true));
+        MESSI_TRY(bf16_scan(ix, a, ws, s, timing, true, c.probe));
     } else {
         const bool vec = (a.L % 4 == 0) && ((uintptr_t)a.series % 16 == 0);
         if (rowf) {
@@ -4268,6 +4269,7 @@ int knn_device(const Index* ix, const float* queries, int32_t nq, int32_t k, con
         return first;
     }
     CallArgs c{ix, queries, nq, k, kq, mode, s, out_idx, out_dist};
+    c.probe = true;  // a synchronous call
     Workspace* ws = nullptr;
     QArgs a;
     uint32_t cap = 0;
