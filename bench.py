@@ -303,20 +303,28 @@ def main():
     fine_row = 64 if infos[-1].get("fine_segments", 0) else 0
     summ_bytes = n * (length * 4 + 16 + 2 + fine_row)
     scan_bytes_per_q = agg.get("bytes_scan", 0) / total_q
-    # The queries/s value is bound by the scan, whose first kernel (coarse and
-    # word bounds of every member of the surviving leaves) is the dominant
-    # one: per member 8 bytes of coarse word, and per coarse survivor its
-    # 16-byte word and 4-byte series index.
+    # The queries/s value is bound by the scan's two kernels; the roofline
+    # describes the longer one.  Coarse kernel: per member of the surviving
+    # leaves its 8-byte coarse word, per coarse survivor its 4-byte entry in
+    # the survivor segment.  Refine kernel: per coarse survivor its segment
+    # entry, 16-byte word and 4-byte series index; per word survivor its fine
+    # summary; the rows it reads (the library's byte count of the scan less
+    # the coarse words).
     coarse_ms_per_q = agg.get("ms_scan_coarse", 0.0) / total_q
-    coarse_bytes_per_q = (8 * agg.get("series_bounded", 0) + 20 * agg.get("series_word_bounded", 0)) / total_q
+    refine_ms_per_q = max(0.0, scan_ms_per_q - coarse_ms_per_q)
+    coarse_bytes_per_q = (8 * agg.get("series_bounded", 0) + 4 * agg.get("series_word_bounded", 0)) / total_q
+    refine_bytes_per_q = (agg.get("bytes_scan", 0) - 8 * agg.get("series_bounded", 0)
+                          + 4 * agg.get("series_word_bounded", 0)) / total_q
     rf_summ = {"bound": "hbm", "achieved": summ_bytes / (summ_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "kernel": "summarize_seg_kernel", "bytes_per_launch": summ_bytes,
                "ms_per_launch": summ_ms, "traffic": traffic_from_profiles("summarize_seg_kernel")}
     if coarse_ms_per_q > 0:
-        rf_scan = {"bound": "hbm", "achieved": coarse_bytes_per_q / (coarse_ms_per_q / 1e3) / 1e9,
-                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernel": "flat_coarse_kernel",
-                   "bytes_per_launch": coarse_bytes_per_q, "ms_per_launch": coarse_ms_per_q,
-                   "traffic": traffic_from_profiles("flat_coarse_kernel")}
+        kname, kb, kms = (("flat_coarse_kernel", coarse_bytes_per_q, coarse_ms_per_q) if coarse_ms_per_q >= refine_ms_per_q
+                          else ("flat_refine_kernel", refine_bytes_per_q, refine_ms_per_q))
+        rf_scan = {"bound": "hbm", "achieved": kb / (kms / 1e3) / 1e9,
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernel": kname,
+                   "bytes_per_launch": kb, "ms_per_launch": kms,
+                   "traffic": traffic_from_profiles(kname)}
     else:
         rf_scan = {"bound": "hbm", "achieved": (scan_bytes_per_q / (scan_ms_per_q / 1e3) / 1e9) if scan_ms_per_q else 0.0,
                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernel": "scan", "bytes_per_launch": scan_bytes_per_q,

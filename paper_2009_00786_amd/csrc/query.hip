@@ -1356,9 +1356,8 @@ scan_kernel(QArgs a) {
 // stages touch a few percent of the members each.
 constexpr int kFlatList = kChunk;  // list entries per wave: a chunk's members at most
 constexpr int kFlatIssue = 8;      // coarse words in flight per lane
-constexpr int kCoarseList = 1024;  // coarse survivors a wave of the split scan's first kernel holds
 constexpr uint32_t kSplitFirst = 64;  // chunks of the split scan's first round
-constexpr int kWordIssue = 4;      // words in flight per lane in that kernel's word stage
+constexpr int kWordIssue = 4;      // words in flight per lane in the refine kernel's word stage
 
 // Lower U from the histogram of candidate distances (one wave).
 __device__ void wave_hist_refresh(const QArgs& a, int q, QState& st, float& U) {
@@ -1915,14 +1914,16 @@ flat_scan_kernel(QArgs a) {
 
 // ---- the split Euclidean scan -------------------------------------------------
 // For calls of few queries the flat scan runs as two kernels.  The first
-// (coarse and word bounds) is light on registers, so more of its waves fit a
-// CU and more member reads are in flight; it stores the survivors of chunk c
-// at the chunk's own place in a[q].seg (a chunk's members at most, so it
-// cannot overflow) and their count in segcnt.  The second (fine bound and
-// distances) takes the survivors of a block's chunks as one list, 16 series
-// per wave and round, so the survivors of one heavy chunk are shared by the
-// block's waves.  U comes from the first bound (and, in the second kernel,
-// from the distances as they are found).
+// streams the coarse words (8 bytes per member) and bounds them; it is light
+// on registers, so more of its waves fit a CU and more member reads are in
+// flight.  It stores the coarse survivors (member positions) of chunk c at
+// the chunk's own place in a[q].seg (a chunk's members at most, so it cannot
+// overflow) and their count in segcnt.  The second takes the survivors of a
+// block's chunks as one list: their words and series indices (read together,
+// 64 per wave and round) and the word bound, the fine bound of the word
+// survivors (4 lanes per series), then distances; a heavy chunk's survivors
+// are shared by the block's waves.  U comes from the first bound (and, in
+// the second kernel, from the distances as they are found).
 
 // Block-wide: the query's coarse table and word regions (as the flat scan's).
 __device__ void coarse_word_tables(const QArgs& a, const QState& st, float* s_bp, float* s_plo, float* s_phi,
@@ -1978,13 +1979,11 @@ flat_coarse_kernel(QArgs a) {
     __shared__ float2 s_rb[256];
     __shared__ float s_plo[16], s_phi[16];
     __shared__ float s_bp[256];
-    __shared__ uint32_t s_list[kScanThreads / 64][kCoarseList];
     __shared__ OrdRec s_rec[kScanThreads / 64][64];
     __shared__ uint32_t s_flag;
     constexpr int kWaves = kScanThreads / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt_mask = dev::lanemask_lt();
-    uint32_t* list = s_list[wave];
     OrdRec* wrec = s_rec[wave];
     const int nq = a.nq;
     const int B = gridDim.x;
@@ -2002,7 +2001,7 @@ flat_coarse_kernel(QArgs a) {
         const uint32_t nsurv = st.nsurv;
         const uint64_t nmemb = st.nmemb;
         const float range = st.range;
-        // this round's chunks: [chunk_lo, nch)
+        // (this round's chunks: [chunk_lo, nch))
         const uint64_t nch = min(min((nmemb + a.chunk - 1) / a.chunk, (uint64_t)a.max_chunks), (uint64_t)a.chunk_hi);
         coarse_word_tables(a, st, s_bp, s_plo, s_phi, s_rb, s_C);
         const uint32_t* cfq = a.chunk_first + (size_t)q * a.max_chunks;
@@ -2010,7 +2009,6 @@ flat_coarse_kernel(QArgs a) {
         uint32_t* segq = a.seg + (size_t)q * a.max_chunks * a.chunk;
         uint32_t* cntq = a.segcnt + (size_t)q * a.max_chunks;
         const uint64_t WG = (uint64_t)G * kWaves;
-        const float mseg = (float)a.m;
         const float U = __uint_as_float(vload(&st.U));
         const uint32_t skip = st.skip_start;
         const uint64_t wi = (uint64_t)j * kWaves + wave;
@@ -2035,54 +2033,10 @@ flat_coarse_kernel(QArgs a) {
             OrdRec r = r_n;
             const uint64_t cn = chunk_of(rt + 1);
             if (cn < nch) tw_n = cfq[cn];
+            // the chunk's coarse survivors (member positions) go straight to
+            // its segment: at most a.chunk of them, so it cannot overflow
             uint32_t n1 = 0;
-            // ---- word: the listed members' words and series indices, read
-            // together; survivors straight to the chunk's segment (called
-            // when the list could not take another batch, and at the end)
-            uint32_t n2 = 0;
             uint32_t* segc = segq + (size_t)c * a.chunk;
-            auto word_stage = [&]() {
-            dev::wave_sync();
-            for (uint32_t e0 = 0; e0 < n1; e0 += 64 * kWordIssue) {
-                uint4 wd[kWordIssue];
-                uint32_t gi[kWordIssue];
-#pragma unroll
-                for (int t = 0; t < kWordIssue; ++t) {
-                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
-                    wd[t] = make_uint4(0u, 0u, 0u, 0u);
-                    gi[t] = 0;
-                    if (e < n1) {
-                        const uint32_t mp = list[e];
-                        wd[t] = a.words[mp];
-                        gi[t] = a.pos[mp];
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < kWordIssue; ++t) {
-                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
-                    bool keep = false;
-                    if (e < n1) {
-                        float sum = 0.f;
-#pragma unroll
-                        for (int i2 = 0; i2 < 16; ++i2) {
-                            if (i2 < a.w) {
-                                const float2 rg = s_rb[word_byte(wd[t], i2)];
-                                const float pl = s_plo[i2], ph = s_phi[i2];
-                                const float d = ph < rg.x ? rg.x - ph : (pl > rg.y ? pl - rg.y : 0.f);
-                                sum += mseg * (d * d);
-                            }
-                        }
-                        keep = !(sum * (1.0f - kRhoLb) > U);
-                        ++c_wordb;
-                    }
-                    const uint64_t bal = __ballot(keep);
-                    if (keep) segc[n2 + __popcll(bal & lt_mask)] = gi[t];
-                    n2 += (uint32_t)__popcll(bal);
-                }
-            }
-            n1 = 0;
-            dev::wave_sync();
-            };
             // ---- coarse: a window of up to 64 of the chunk's leaves at a time
             for (bool first = true;; first = false) {
                 if (!first) {
@@ -2173,10 +2127,9 @@ flat_coarse_kernel(QArgs a) {
                             ++c_bounded;
                         }
                         const uint64_t bal = __ballot(keep);
-                        if (keep) list[n1 + __popcll(bal & lt_mask)] = mpv[i];
+                        if (keep) segc[n1 + __popcll(bal & lt_mask)] = mpv[i];
                         n1 += (uint32_t)__popcll(bal);
                     }
-                    if (n1 > (uint32_t)(kCoarseList - 64 * kFlatIssue)) word_stage();
                 }
                 if (nin < 64 || we >= cend) break;
                 tw += 64;
@@ -2186,9 +2139,7 @@ flat_coarse_kernel(QArgs a) {
                 if (lane == 0) cntq[c] = 0;
                 continue;
             }
-            word_stage();
-            if (lane == 0) cntq[c] = n2;
-            dev::wave_sync();  // the list is refilled by the next chunk
+            if (lane == 0) cntq[c] = n1;
         }
     }
     if (a.blk_cnt) {
@@ -2200,7 +2151,8 @@ flat_coarse_kernel(QArgs a) {
             for (int i = 0; i < 3; ++i) s_cnt[wave][i] = v[i];
         __syncthreads();
         if (tid < kBlkCnt) {
-            // slots of the statistics: scanned, coarse-bounded, word-bounded (bytes: 8 + 20 each)
+            // slots of the statistics: scanned, coarse-bounded, word-bounded (0 here: the
+            // refine kernel adds it), bytes (8 per coarse word)
             unsigned long long t = 0;
             if (tid == 0 || tid == 1 || tid == 4 || tid == 7)
                 for (int w2 = 0; w2 < kWaves; ++w2) {
@@ -2306,13 +2258,17 @@ __device__ void wave_rows(const QArgs& a, QState& st, int q, int k, const uint32
 }
 
 constexpr int kRefineList = 512;  // fine survivors a wave holds before it computes their distances
+constexpr int kWordList = 512;    // word survivors a wave holds before it bounds their fine summaries
 
 template <bool VEC, int pass>
 __global__ void __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)))
 flat_refine_kernel(QArgs a) {
     __shared__ float2 s_rf[256];
+    __shared__ float2 s_rb[256];
+    __shared__ float s_plo[16], s_phi[16];
     __shared__ float s_pf[64];
     __shared__ float s_bp[256];
+    __shared__ uint32_t s_wl[kScanThreads / 64][kWordList];
     __shared__ __align__(16) float s_q[MESSI_MAX_LEN];
     __shared__ uint32_t s_cpre[kScanThreads + 1];  // exclusive prefix of the survivor counts of a batch of chunks
     __shared__ uint32_t s_tmp[4];
@@ -2324,13 +2280,14 @@ flat_refine_kernel(QArgs a) {
     const uint64_t lt_mask = dev::lanemask_lt();
     uint32_t* list = s_list[wave];
     float* llb = s_llb[wave];
+    uint32_t* wl = s_wl[wave];
     const int nq = a.nq;
     const int B = gridDim.x;
     const int q = blockIdx.x % nq;
     const int j = blockIdx.x / nq;
     const int G = (B - q + nq - 1) / nq;
     const int L = a.L;
-    uint32_t c_dist = 0, c_abandon = 0, c_fine = 0;
+    uint32_t c_dist = 0, c_abandon = 0, c_fine = 0, c_wordb = 0;
     unsigned long long c_rowb = 0;
     QState& st = a.qs[q];
     if (tid == 0) s_flag = (st.err != 0 || st.nsurv == 0 || (pass == 1 && st.rerun == 0)) ? 1u : 0u;
@@ -2346,8 +2303,16 @@ flat_refine_kernel(QArgs a) {
         const float inf = __uint_as_float(0x7f800000u);
         for (int c = tid; c < A - 1; c += kScanThreads) s_bp[c] = a.bp[c];
         for (int jj = tid; jj < L; jj += kScanThreads) s_q[jj] = a.queries[(size_t)q * L + jj];
+        if (tid < 16) {
+            s_plo[tid] = st.paa[tid];
+            s_phi[tid] = st.paa_hi[tid];
+        }
         const float qamax = st.qamax;
+        const float delta = st.delta;
         __syncthreads();
+        // each symbol's region widened by the query's delta (the word bound)
+        for (int c = tid; c < A; c += kScanThreads)
+            s_rb[c] = make_float2(c > 0 ? s_bp[c - 1] - delta : -inf, c < A - 1 ? s_bp[c] + delta : inf);
         if (fine) {
             // the fine regions, widened by the fp32 error of a fine PAA value of
             // data and query, and the query's fine PAA
@@ -2445,32 +2410,30 @@ flat_refine_kernel(QArgs a) {
                 const uint64_t cc = j0 + (cb + (uint64_t)lo) * G;
                 return segq[cc * a.chunk + (e - s_cpre[lo])];
             };
-            if (fine) {
-                // 4 lanes per series, 16 series per wave and round
+            // the fine bounds of the wave's word survivors wl[0, nw) (4 lanes per
+            // series, 16 series per wave and round); fine survivors to the list
+            auto fine_stage = [&](uint32_t nw) {
                 constexpr int kFineIssue = 4;
                 const int g4 = lane >> 2, l4 = lane & 3;
                 const float mfine = (float)a.mf;
                 const bool part = l4 * 16 < a.wf;
-                for (uint32_t e0 = (uint32_t)wave * 16 * kFineIssue; e0 < total; e0 += kWaves * 16 * kFineIssue) {
+                dev::wave_sync();
+                for (uint32_t e0 = 0; e0 < nw; e0 += 16 * kFineIssue) {
                     uint4 fv[kFineIssue];
                     uint32_t gx[kFineIssue];
 #pragma unroll
                     for (int t = 0; t < kFineIssue; ++t) {
                         const uint32_t e = e0 + (uint32_t)t * 16 + g4;
-                        gx[t] = e < total ? entry(e) : 0u;
-                    }
-#pragma unroll
-                    for (int t = 0; t < kFineIssue; ++t) {
-                        const uint32_t e = e0 + (uint32_t)t * 16 + g4;
+                        gx[t] = e < nw ? wl[e] : 0u;
                         fv[t] = make_uint4(0u, 0u, 0u, 0u);
-                        if (e < total && part)
+                        if (e < nw && part)
                             fv[t] = *reinterpret_cast<const uint4*>(a.fwords + (size_t)gx[t] * kFineStride + l4 * 16);
                     }
 #pragma unroll
                     for (int t = 0; t < kFineIssue; ++t) {
-                        if (e0 + (uint32_t)t * 16 >= total) break;
+                        if (e0 + (uint32_t)t * 16 >= nw) break;
                         const uint32_t e = e0 + (uint32_t)t * 16 + g4;
-                        const bool act = e < total;
+                        const bool act = e < nw;
                         float acc = 0.f;
 #pragma unroll
                         for (int tt = 0; tt < 16; ++tt) {
@@ -2500,25 +2463,68 @@ flat_refine_kernel(QArgs a) {
                         flush();
                     }
                 }
-            } else {
-                // no fine summary: the word survivors' distances directly
-                for (uint32_t e0 = (uint32_t)wave * 64; e0 < total; e0 += kScanThreads) {
-                    const uint32_t e = e0 + lane;
-                    const bool act = e < total;
-                    const uint32_t gv = act ? entry(e) : 0u;
-                    const uint64_t bal = __ballot(act);
-                    if (act) {
-                        const uint32_t o = n3 + (uint32_t)__popcll(bal & lt_mask);
-                        list[o] = gv;
-                        llb[o] = 0.f;
-                    }
-                    n3 += (uint32_t)__popcll(bal);
-                    if (n3 > (uint32_t)(kRefineList - 64)) {
-                        dev::wave_sync();
-                        flush();
+                dev::wave_sync();
+            };
+            // the coarse survivors' words and series indices, read together, and
+            // the word bound; word survivors to wl (or, without a fine summary,
+            // straight to the distance list)
+            const float mseg = (float)a.m;
+            uint32_t nw = 0;
+            for (uint32_t e0 = (uint32_t)wave * 64 * kWordIssue; e0 < total; e0 += kWaves * 64 * kWordIssue) {
+                uint4 wd[kWordIssue];
+                uint32_t gi[kWordIssue];
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    wd[t] = make_uint4(0u, 0u, 0u, 0u);
+                    gi[t] = 0;
+                    if (e < total) {
+                        const uint32_t mp = entry(e);
+                        wd[t] = a.words[mp];
+                        gi[t] = a.pos[mp];
                     }
                 }
+#pragma unroll
+                for (int t = 0; t < kWordIssue; ++t) {
+                    const uint32_t e = e0 + (uint32_t)t * 64 + lane;
+                    bool keep = false;
+                    if (e < total) {
+                        float sum = 0.f;
+#pragma unroll
+                        for (int i2 = 0; i2 < 16; ++i2) {
+                            if (i2 < a.w) {
+                                const float2 rg = s_rb[word_byte(wd[t], i2)];
+                                const float pl = s_plo[i2], ph = s_phi[i2];
+                                const float d = ph < rg.x ? rg.x - ph : (pl > rg.y ? pl - rg.y : 0.f);
+                                sum += mseg * (d * d);
+                            }
+                        }
+                        keep = !(sum * (1.0f - kRhoLb) > U);
+                        ++c_wordb;
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    if (fine) {
+                        if (keep) wl[nw + (uint32_t)__popcll(bal & lt_mask)] = gi[t];
+                        nw += (uint32_t)__popcll(bal);
+                    } else {
+                        if (keep) {
+                            const uint32_t o = n3 + (uint32_t)__popcll(bal & lt_mask);
+                            list[o] = gi[t];
+                            llb[o] = 0.f;
+                        }
+                        n3 += (uint32_t)__popcll(bal);
+                    }
+                }
+                if (fine && nw > (uint32_t)(kWordList - 64 * kWordIssue)) {
+                    fine_stage(nw);
+                    nw = 0;
+                }
+                if (!fine && n3 > (uint32_t)(kRefineList - 64 * kWordIssue)) {
+                    dev::wave_sync();
+                    flush();
+                }
             }
+            if (fine && nw) fine_stage(nw);
             __syncthreads();  // every wave is done with this batch's prefix sums
         }
         dev::wave_sync();
@@ -2526,20 +2532,22 @@ flat_refine_kernel(QArgs a) {
         if (k > 1 && __ballot(appended != 0)) wave_hist_refresh(a, q, st, U);
     }
     if (a.blk_cnt) {
-        __shared__ unsigned long long s_cnt[kWaves][4];
+        __shared__ unsigned long long s_cnt[kWaves][5];
         const unsigned long long fine_b = 16ull * (unsigned long long)((a.wf + 15) / 16);
-        unsigned long long v[4] = {c_dist, c_abandon, c_fine, c_rowb};
-        for (int i = 0; i < 4; ++i)
+        unsigned long long v[5] = {c_dist, c_abandon, c_fine, c_rowb, c_wordb};
+        for (int i = 0; i < 5; ++i)
             for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
         if (lane == 0)
-            for (int i = 0; i < 4; ++i) s_cnt[wave][i] = v[i];
+            for (int i = 0; i < 5; ++i) s_cnt[wave][i] = v[i];
         __syncthreads();
-        if (tid < kBlkCnt && (tid == 2 || tid == 3 || tid == 4 || tid == 8)) {
-            // added to the coarse kernel's slots: distances, abandoned, bytes (rows, fine), fine-bounded
+        if (tid < kBlkCnt && (tid == 2 || tid == 3 || tid == 4 || tid == 7 || tid == 8)) {
+            // added to the coarse kernel's slots: distances, abandoned, bytes (rows, fine
+            // summaries, words and series indices), word-bounded, fine-bounded
             unsigned long long t = 0;
             for (int w2 = 0; w2 < kWaves; ++w2)
                 t += tid == 2 ? s_cnt[w2][0] : tid == 3 ? s_cnt[w2][1] : tid == 8 ? s_cnt[w2][2]
-                                                                               : s_cnt[w2][3] + s_cnt[w2][2] * fine_b;
+                   : tid == 7 ? s_cnt[w2][4]
+                              : s_cnt[w2][3] + s_cnt[w2][2] * fine_b + s_cnt[w2][4] * 20ull;
             unsigned long long* pp = a.blk_cnt + (size_t)blockIdx.x * kBlkCnt + tid;
             *pp = (tid == 4 || a.chunk_lo != 0 ? *pp : (pass == 0 ? 0ull : *pp)) + t;
         }
