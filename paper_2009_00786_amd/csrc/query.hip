@@ -2413,7 +2413,7 @@ flat_refine_kernel(QArgs a) {
             // the fine bounds of the wave's word survivors wl[0, nw) (4 lanes per
             // series, 16 series per wave and round); fine survivors to the list
             auto fine_stage = [&](uint32_t nw) {
-                constexpr int kFineIssue = 4;
+                constexpr int kFineIssue = 2;
                 const int g4 = lane >> 2, l4 = lane & 3;
                 const float mfine = (float)a.mf;
                 const bool part = l4 * 16 < a.wf;
