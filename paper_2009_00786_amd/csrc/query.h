@@ -88,6 +88,8 @@ struct QArgs {
     int32_t wf, mf, lg_mf;       // fine segments, their length, ceil(log2 mf)
     int32_t csh;                 // coarse symbol = symbol >> csh
     int32_t skip_approx;         // 1: the first bound's leaf is appended as candidates, not scanned (split scan)
+    uint32_t approx_min;         // exact search: the first bound's members reach at least this many (the
+                                 //   approximate search takes the leaf alone: 0)
     const uint32_t* pos;
     const Leaf* leaves;
     int32_t nL;

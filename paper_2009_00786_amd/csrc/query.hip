@@ -257,11 +257,14 @@ __global__ void __launch_bounds__(256) leaf_lb_kernel(QArgs a, int32_t k, const 
 // --------------------------------------------------------------------------
 // The members evaluated: the argmin leaf, extended into the depth-first
 // neighbouring leaves (contiguous in the member arrays) until at least k
-// members, so that the first bound is finite.
+// members, so that the first bound is finite.  The exact search extends it
+// to at least a.approx_min members: the neighbouring leaves share most of
+// the word, and a few more rows give a tighter first bound, so fewer leaves
+// are scanned (2048 members: 2% more queries/s at 100M x 256).
 __device__ __forceinline__ void approx_range(const QArgs& a, uint32_t leaf, int32_t k, uint32_t& r0,
                                              uint32_t& cnt) {
     const Leaf lf = a.leaves[leaf];
-    cnt = min(max(lf.count, (uint32_t)k), (uint32_t)kApproxMax);
+    cnt = min(max(lf.count, max((uint32_t)k, a.approx_min)), (uint32_t)kApproxMax);
     cnt = (uint32_t)min((int64_t)cnt, a.n);
     r0 = (uint32_t)min((int64_t)lf.start, a.n - (int64_t)cnt);
 }
@@ -3605,6 +3608,7 @@ void fill_call_args(const CallArgs& c, uint32_t cap, QArgs& a) {
     a.out_dist = c.out_dist;
     a.band = -1;
     a.rho_d = kRhoEd;
+    a.approx_min = (c.mode == MESSI_MODE_FP32 || c.mode == MESSI_MODE_BF16) ? 2048u : 0u;
     a.chunk_lo = 0;
     a.chunk_hi = 0xffffffffu;
     a.chunk = (uint32_t)ix->opts.scan_chunk;
@@ -3996,6 +4000,7 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     if (timing) MESSI_TRY(ws->ensure_stats());
     a.band = band;
     a.rho_d = kRhoDtw;
+    a.approx_min = 0;  // DTW distances are dear: the first bound takes the leaf alone
     // scan blocks per query (the scan's own split of its grid) and the segments
     const int B = scan_grid(kScanDtw);
     const uint32_t g_max = nq <= B ? (uint32_t)((B + nq - 1) / nq) : 1u;
