@@ -83,7 +83,7 @@ typedef struct {
     uint64_t budget_bytes; /* device bytes one search workspace (one per stream) may take; a call that
                               needs more fails with MESSI_ENOMEM (0: no cap).  Also the budget of a
                               server created with budget_bytes = 0 (0 there: 8 GiB) */
-    int32_t scan_chunk;  /* members per work unit of the ordered scan: 256, 512 or 1024 (0: 1024) */
+    int32_t scan_chunk;  /* members per work unit of the ordered scan: 256, 512 or 1024 (0: 512) */
     uint32_t cand_cap;   /* candidate slots per query (0: 2^20 for a call of one query, else 64 k per
                             query, at least 2^14, 2^16 in BF16 mode); at least 2 k is used.  A small
                             value exercises the overflow recovery described at messi_knn_ex */

@@ -201,7 +201,7 @@ static int check_opts(const messi_opts* opts, messi_opts& o) {
     if (o.max_slots < 0) return fail(MESSI_EINVAL, "opts.max_slots must be >= 0");
     if (o.znorm != 0 && o.znorm != 1) return fail(MESSI_EINVAL, "opts.znorm must be 0 or 1");
     if (o.bf16_shadow != 0 && o.bf16_shadow != 1) return fail(MESSI_EINVAL, "opts.bf16_shadow must be 0 or 1");
-    if (o.scan_chunk == 0) o.scan_chunk = 1024;
+    if (o.scan_chunk == 0) o.scan_chunk = 512;
     if (o.max_slots == 0) o.max_slots = 256;
     if (o.row_filter_max_q == 0) o.row_filter_max_q = 1;
     return MESSI_OK;
