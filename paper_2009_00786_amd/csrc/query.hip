@@ -4001,12 +4001,13 @@ static int knn_dtw_once(const Index* ix, const float* queries, int32_t nq, int32
     a.band = band;
     a.rho_d = kRhoDtw;
     a.approx_min = 0;  // DTW distances are dear: the first bound takes the leaf alone
+    a.chunk = kChunk;  // DTW scans (and sizes its rounds) in chunks of 1024 members
     // scan blocks per query (the scan's own split of its grid) and the segments
     const int B = scan_grid(kScanDtw);
     const uint32_t g_max = nq <= B ? (uint32_t)((B + nq - 1) / nq) : 1u;
     const uint32_t g_min = nq <= B ? (uint32_t)(B / nq) : 1u;
     const uint64_t round_max = std::max<uint64_t>(64, kDtwRoundChunks / (uint32_t)nq);
-    const uint32_t seg = (uint32_t)((round_max + g_min - 1) / g_min) * (uint32_t)ix->opts.scan_chunk;
+    const uint32_t seg = (uint32_t)((round_max + g_min - 1) / g_min) * a.chunk;
     const uint32_t todo_cap = g_max * seg;
     if (ws->todo_slots < (size_t)nq * todo_cap) {
         MESSI_HIP_TRY(hipStreamSynchronize(s));
