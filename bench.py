@@ -45,7 +45,8 @@ WORKLOADS = {
     5: dict(name="Gaussian mixture 200M x 128 (1000 centres U[0,255], sigma 20, integers clipped to [0,255]), "
                  "z-normalised; open-loop Poisson at 200, 1000, 5000 queries/s, k=10, half noisy dataset rows and "
                  "half fresh mixture draws; BF16 continuous-batching server vs fp32 single-query FIFO",
-            n=200_000_000, length=128, data="mixture", rates=(200, 1000, 5000), headline_rate=1000),
+            n=200_000_000, length=128, data="mixture", rates=(200, 1000, 5000), headline_rate=1000,
+            server_slots=512),
     6: dict(name="streaming series: one random walk of 100M + 255 points cut into its 100M sliding windows of 256 "
                  "(step 1), z-normalised per window and indexed; exact 1-NN, 100 single queries",
             n=100_000_000, length=256, queries=100, k=1),
@@ -937,15 +938,18 @@ def bench_serving(args):
     budget = 8 << 30
     out = {}
     results = {}
-    modes = [("bf16_server", messi.MODE_BF16, 256)]
+    # server slots: 4 lanes of 64 queries; the mixture's wide queries (the
+    # FP32 filter's growing rounds) gain from batches of 128
+    server_slots = slots = int(wl.get("server_slots", 256))
+    modes = [("bf16_server", messi.MODE_BF16, slots)]
     if args.variants:
         # the same server with one of its two latency devices switched off,
         # and the slot engine in place of lanes of batches
-        modes += [("bf16_batch_only", messi.MODE_BF16 | messi.SERVER_BATCH_ONLY, 256),
-                  ("bf16_no_graphs", messi.MODE_BF16 | messi.SERVER_NO_GRAPHS, 256),
-                  ("bf16_slots", messi.MODE_BF16 | messi.SERVER_SLOTS, 256)]
+        modes += [("bf16_batch_only", messi.MODE_BF16 | messi.SERVER_BATCH_ONLY, slots),
+                  ("bf16_no_graphs", messi.MODE_BF16 | messi.SERVER_NO_GRAPHS, slots),
+                  ("bf16_slots", messi.MODE_BF16 | messi.SERVER_SLOTS, slots)]
     # the FP32 server: lanes of batches on the FP32 matrix-core filter
-    modes += [("fp32_server", messi.MODE_FP32, 256)]
+    modes += [("fp32_server", messi.MODE_FP32, slots)]
     if not args.no_fifo:
         modes += [("fp32_fifo", messi.MODE_FP32, 1)]
     for name, mode, slots in modes:
@@ -996,8 +1000,9 @@ def bench_serving(args):
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "len": length, "segments": 16, "card_bits": 8, "leaf_cap": 2000,
                    "rates": rates, "duration_s": args.duration, "headline_rate": r_head, "budget_bytes": budget,
-                   "mode": "BF16 continuous-batching server (256 slots over 4 streams; batches replayed as HIP "
-                           "graphs; a lone waiting query runs alone in FP32 mode)"},
+                   "mode": "BF16 continuous-batching server (%d slots over 4 streams; batches replayed as HIP "
+                           "graphs; a lone waiting query runs alone in FP32 mode; batches move to the FP32 "
+                           "matrix-core filter while BF16 batches overflow)" % server_slots},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "serving": out,
         "alone_vs_mix": {"sample": len(sample), "mismatches": mism_alone},
