@@ -1167,17 +1167,22 @@ int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_fl
     if (len > 32) {
         int P = 64;
         while (P < len) P <<= 1;
-        const int64_t waves = (n + 3) / 4;  // about 4 rows per wave
-        const int blocks = launch_blocks(waves, 4, 256 * 16);
+        // Reading and rewriting every row in place moves as many bytes as a
+        // copy; what sets its rate is the number of loads in flight over the
+        // chip.  A wide grid (up to 128 blocks of 4 waves per CU, each wave R
+        // rows at a time) measured 4.79 TB/s at L = 256, within 5% of a plain
+        // float4 copy (5.05 TB/s); 4096 blocks of 4-row waves gave 4.37.
         switch (P / 64) {
 #define MESSI_ZN_CASE(EP, R)                                                                                  \
-    case EP:                                                                                                  \
+    case EP: {                                                                                                \
+        const int blocks = launch_blocks(n, 4 * R, 256 * 128);                                                \
         hipLaunchKernelGGL((znorm_strided_kernel<EP, R>), dim3(blocks), dim3(256), 0, s, series, series, n, len, \
                            (int64_t)len, d_flag);                                                             \
-        break;
+        break;                                                                                                \
+    }
             MESSI_ZN_CASE(1, 8)
             MESSI_ZN_CASE(2, 4)
-            MESSI_ZN_CASE(4, 4)
+            MESSI_ZN_CASE(4, 2)
             MESSI_ZN_CASE(8, 2)
             MESSI_ZN_CASE(16, 1)
 #undef MESSI_ZN_CASE
