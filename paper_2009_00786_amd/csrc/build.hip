@@ -33,6 +33,8 @@ constexpr int kTile = 4096;
 constexpr int kBlk = 256;
 constexpr int kRounds = kTile / kBlk;
 
+double inv_len_pow2(int32_t len) { return (len & (len - 1)) == 0 ? 1.0 / (double)len : 0.0; }
+
 int launch_blocks(int64_t work, int per_block, int cap_blocks) {
     int64_t b = (work + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -292,9 +294,11 @@ __device__ __forceinline__ float quotient_f32(double c, double sigma, double rs)
 // Row r is read from in + r * in_stride (in_stride = L for a collection; the
 // window step for the windows of a long series, which overlap) and written to
 // out + r * L.
+// inv_len_pow2 is 1 / L when L is a power of two (then s / L and s * (1 / L)
+// are the same correctly rounded value, and the product is much cheaper), else 0.
 template <int EP, int R>
 __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, float* out, int64_t n, int L,
-                                                            int64_t in_stride, int* nonfinite) {
+                                                            int64_t in_stride, int* nonfinite, double inv_len_pow2) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
     int64_t n_waves = (int64_t)gridDim.x * 4;
@@ -339,7 +343,7 @@ __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, flo
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) s1 = __dadd_rn(s1, __shfl_down(s1, off, 64));
             s1 = __shfl(s1, 0, 64);
-            const double mu = __ddiv_rn(s1, (double)L);
+            const double mu = inv_len_pow2 != 0.0 ? __dmul_rn(s1, inv_len_pow2) : __ddiv_rn(s1, (double)L);
             double c[EP];
 #pragma unroll
             for (int k = 0; k < EP; ++k) {
@@ -355,7 +359,7 @@ __global__ void __launch_bounds__(256) znorm_strided_kernel(const float* in, flo
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) s2 = __dadd_rn(s2, __shfl_down(s2, off, 64));
             s2 = __shfl(s2, 0, 64);
-            const double var = __ddiv_rn(s2, (double)L);
+            const double var = inv_len_pow2 != 0.0 ? __dmul_rn(s2, inv_len_pow2) : __ddiv_rn(s2, (double)L);
             const double sigma = __dsqrt_rn(var);
             const double rs = var == 0.0 ? 0.0 : __ddiv_rn(1.0, sigma);
             if (row < r_end) {
@@ -1142,7 +1146,7 @@ int windows_device(const float* src, int64_t count, int32_t len, int64_t step, b
 #define MESSI_WN_CASE(EP, R)                                                                                      \
     case EP:                                                                                                      \
         hipLaunchKernelGGL((znorm_strided_kernel<EP, R>), dim3(blocks), dim3(256), 0, s, src, out, count, len, step, \
-                           d_flag);                                                                               \
+                           d_flag, inv_len_pow2(len));                                                                               \
         break;
             MESSI_WN_CASE(1, 8)
             MESSI_WN_CASE(2, 4)
@@ -1177,7 +1181,7 @@ int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_fl
     case EP: {                                                                                                \
         const int blocks = launch_blocks(n, 4 * R, 256 * 128);                                                \
         hipLaunchKernelGGL((znorm_strided_kernel<EP, R>), dim3(blocks), dim3(256), 0, s, series, series, n, len, \
-                           (int64_t)len, d_flag);                                                             \
+                           (int64_t)len, d_flag, inv_len_pow2(len));                                                             \
         break;                                                                                                \
     }
             MESSI_ZN_CASE(1, 8)
