@@ -637,55 +637,111 @@ __global__ void __launch_bounds__(kBlk) radix_hist_kernel(const uint16_t* __rest
     hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// The tile's elements are taken a sub-tile of kSub = 1024 at a time: each is
+// ranked within its digit (round, then wave, then lane order: the stable
+// order), placed in LDS sorted by digit, and written from there, so that the
+// elements of one digit leave the block as one contiguous run per sub-tile
+// rather than a short run per round of 256.
+constexpr int kSubRounds = 4;
+constexpr int kSub = kSubRounds * kBlk;
+static_assert(kRounds % kSubRounds == 0, "sub-tiles divide the tile");
+
 __global__ void __launch_bounds__(kBlk) radix_scatter_kernel(const uint16_t* __restrict__ kin,
                                                              const uint4* __restrict__ win,
                                                              const uint32_t* __restrict__ pin, int64_t n, int shift,
                                                              const uint32_t* __restrict__ offs, int64_t n_tiles,
                                                              uint16_t* __restrict__ kout, uint4* __restrict__ wout,
                                                              uint32_t* __restrict__ pout) {
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t base[256];                // digit's next global place for this tile
     __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t woff[4][256];
-    const int tid = threadIdx.x, wave = tid >> 6;
+    __shared__ uint16_t woff[kSubRounds][4][256];  // place within the sub-tile's run of the digit
+    __shared__ uint32_t sstart[256];              // sub-tile: start of each digit's run
+    __shared__ uint32_t wsum[4];
+    __shared__ uint16_t s_key[kSub];
+    __shared__ uint4 s_word[kSub];
+    __shared__ uint32_t s_pos[kSub];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     base[tid] = offs[(int64_t)tid * n_tiles + blockIdx.x];
 #pragma unroll
     for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
-    uint32_t run = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * kTile;
     const uint64_t lt = dev::lanemask_lt();
-    for (int r = 0; r < kRounds; ++r) {
-        const int64_t i = t0 + (int64_t)r * kBlk + tid;
-        const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
-        uint64_t peers = dev::ballot(valid);
+    for (int sub = 0; sub < kRounds / kSubRounds; ++sub) {
+        const int64_t s0 = t0 + (int64_t)sub * kSub;
+        if (s0 >= n) break;  // the same for every thread
+        uint32_t key[kSubRounds], pv[kSubRounds];
+        uint4 wv[kSubRounds];
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const bool on = (d >> bit) & 1u;
-            const uint64_t m = dev::ballot(valid && on);
-            peers &= on ? m : ~m;
+        for (int rr = 0; rr < kSubRounds; ++rr) {
+            const int64_t i = s0 + (int64_t)rr * kBlk + tid;
+            const bool valid = i < n;
+            key[rr] = valid ? kin[i] : 0u;
+            wv[rr] = valid ? win[i] : make_uint4(0u, 0u, 0u, 0u);
+            pv[rr] = valid ? (pin ? pin[i] : (uint32_t)i) : 0u;
         }
-        const int rank = dev::popc64(peers & lt);
-        if (valid && (peers & lt) == 0) wcnt[wave][d] = (uint32_t)dev::popc64(peers);
-        __syncthreads();
-        uint32_t acc = run;
+        int rank[kSubRounds];
+        uint32_t acc = 0;  // thread tid: elements of digit tid in the sub-tile's rounds so far
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t c = wcnt[w][tid];
-            woff[w][tid] = acc;
-            acc += c;
-            wcnt[w][tid] = 0;
+        for (int rr = 0; rr < kSubRounds; ++rr) {
+            const bool valid = s0 + (int64_t)rr * kBlk + tid < n;
+            const uint32_t d = (key[rr] >> shift) & 255u;
+            uint64_t peers = dev::ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool on = (d >> bit) & 1u;
+                const uint64_t m = dev::ballot(valid && on);
+                peers &= on ? m : ~m;
+            }
+            rank[rr] = dev::popc64(peers & lt);
+            if (valid && (peers & lt) == 0) wcnt[wave][d] = (uint32_t)dev::popc64(peers);
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t c = wcnt[w][tid];
+                woff[rr][w][tid] = (uint16_t)acc;
+                acc += c;
+                wcnt[w][tid] = 0;
+            }
+            __syncthreads();
         }
-        run = acc;
+        // start of each digit's run in the sub-tile: exclusive prefix of acc over digits
+        uint32_t x = acc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
         __syncthreads();
-        if (valid) {
-            const uint32_t dst = base[d] + woff[wave][d] + (uint32_t)rank;
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        sstart[tid] = before + x - acc;
+        const uint32_t nsub = wsum[0] + wsum[1] + wsum[2] + wsum[3];  // valid elements of the sub-tile
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < kSubRounds; ++rr) {
+            if (s0 + (int64_t)rr * kBlk + tid < n) {
+                const uint32_t d = (key[rr] >> shift) & 255u;
+                const uint32_t slot = sstart[d] + woff[rr][wave][d] + (uint32_t)rank[rr];
+                s_key[slot] = (uint16_t)key[rr];
+                s_word[slot] = wv[rr];
+                s_pos[slot] = pv[rr];
+            }
+        }
+        __syncthreads();
+        for (uint32_t e = tid; e < nsub; e += kBlk) {
+            const uint32_t k2 = s_key[e];
+            const uint32_t d = (k2 >> shift) & 255u;
+            const uint32_t dst = base[d] + (e - sstart[d]);
             if (dst >= (uint64_t)n) continue;  // cannot happen with consistent offsets
-            kout[dst] = (uint16_t)key;
-            wout[dst] = win[i];
-            pout[dst] = pin ? pin[i] : (uint32_t)i;
+            kout[dst] = (uint16_t)k2;
+            wout[dst] = s_word[e];
+            pout[dst] = s_pos[e];
         }
+        __syncthreads();
+        base[tid] += acc;
+        __syncthreads();
     }
 }
 
