@@ -77,6 +77,7 @@ BUILD_CASES = [
     # n, len, segments, bits, cap
     (100_000, 256, 16, 8, 2000),   # the tiny workload of the paper's setup
     (12289, 128, 16, 8, 100),      # ragged last tile, two series per wave
+    (700, 64, 16, 8, 20),          # fewer rows than one radix sub-tile (1024)
     (4097, 64, 8, 8, 10),
     (3000, 96, 16, 8, 50),         # segment length 6: padded fold-halving path
     (2000, 100, 4, 4, 20),         # length not a power of two, segment length 25
