@@ -74,6 +74,22 @@ __device__ __forceinline__ double fold_halving64(double (&v)[E], int T) {
     return v[0];
 }
 
+// c / sigma rounded to fp32 as fl32(fl64(c / sigma)), with rs = fl64(1 / sigma):
+// c * rs is within 2 fp64 ulps of the exact quotient, so unless it lies within
+// a few fp64 ulps of an fp32 rounding midpoint (or outside the normal fp32
+// range) it rounds to the same fp32 value; otherwise the correctly rounded
+// fp64 quotient is formed.
+__device__ __forceinline__ float quotient_f32(double c, double sigma, double rs) {
+    const double q1 = __dmul_rn(c, rs);  // within 2 fp64 ulps of the exact quotient
+    const uint64_t bits = (uint64_t)__double_as_longlong(q1);
+    const int e = (int)((bits >> 52) & 0x7ff);
+    const uint32_t low = (uint32_t)(bits & ((1ull << 29) - 1));  // the bits below fp32 precision
+    const uint32_t half = 1u << 28;
+    // normal fp32 range, and not near the point where fp32 rounding flips
+    if (e >= 1023 - 126 && e <= 1023 + 127 && (low > half + 8u || low + 8u < half)) return (float)q1;
+    return (float)__ddiv_rn(c, sigma);
+}
+
 struct SumArgs {
     const float* in;
     float* zout;          // z-normalised rows (may equal in); null when not normalising
@@ -85,6 +101,7 @@ struct SumArgs {
     uint16_t* keys;       // [n]
     uint32_t* absmax;     // float bits, atomicMax
     int* nonfinite;
+    double inv_len_pow2;  // 1 / L when L is a power of two (s / L == s * (1 / L) then), else 0
 };
 
 // One kernel for: z-normalise only (SUM = false), summarise only (ZN = false),
@@ -146,7 +163,7 @@ __global__ void __launch_bounds__(256) summarize_kernel(SumArgs a) {
                 for (int k = 0; k < E; ++k) v[k] = (double)x[k];
                 double s1 = fold_halving64<E>(v, T);
                 s1 = __shfl(s1, g * T, 64);
-                const double mu = __ddiv_rn(s1, (double)L);
+                const double mu = a.inv_len_pow2 != 0.0 ? __dmul_rn(s1, a.inv_len_pow2) : __ddiv_rn(s1, (double)L);
                 double c[E];
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
@@ -156,10 +173,11 @@ __global__ void __launch_bounds__(256) summarize_kernel(SumArgs a) {
                 }
                 double s2 = fold_halving64<E>(v, T);
                 s2 = __shfl(s2, g * T, 64);
-                const double var = __ddiv_rn(s2, (double)L);
+                const double var = a.inv_len_pow2 != 0.0 ? __dmul_rn(s2, a.inv_len_pow2) : __ddiv_rn(s2, (double)L);
                 const double sigma = __dsqrt_rn(var);
+                const double rs = var == 0.0 ? 0.0 : __ddiv_rn(1.0, sigma);
 #pragma unroll
-                for (int k = 0; k < E; ++k) x[k] = (var == 0.0) ? 0.f : (float)__ddiv_rn(c[k], sigma);
+                for (int k = 0; k < E; ++k) x[k] = (var == 0.0) ? 0.f : quotient_f32(c[k], sigma, rs);
                 if (live) {
                     float* dst = a.zout + (size_t)row * (size_t)L;
                     if (vec) {
@@ -280,17 +298,6 @@ __global__ void __launch_bounds__(256) summarize_kernel(SumArgs a) {
 // quotient is computed instead -- so the fp32 result is fl32(fl64(c / sigma))
 // in every case.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float quotient_f32(double c, double sigma, double rs) {
-    const double q1 = __dmul_rn(c, rs);  // within 2 fp64 ulps of the exact quotient
-    const uint64_t bits = (uint64_t)__double_as_longlong(q1);
-    const int e = (int)((bits >> 52) & 0x7ff);
-    const uint32_t low = (uint32_t)(bits & ((1ull << 29) - 1));  // the bits below fp32 precision
-    const uint32_t half = 1u << 28;
-    // normal fp32 range, and not near the point where fp32 rounding flips
-    if (e >= 1023 - 126 && e <= 1023 + 127 && (low > half + 8u || low + 8u < half)) return (float)q1;
-    return (float)__ddiv_rn(c, sigma);
-}
-
 // Row r is read from in + r * in_stride (in_stride = L for a collection; the
 // window step for the windows of a long series, which overlap) and written to
 // out + r * L.
@@ -1255,6 +1262,7 @@ int znorm_device(float* series, int64_t n, int32_t len, hipStream_t s, int* d_fl
     SumArgs a{};
     a.in = series;
     a.zout = series;
+    a.inv_len_pow2 = inv_len_pow2(len);
     a.n = n;
     a.L = len;
     a.P = r.P;
@@ -1299,6 +1307,7 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     SumArgs a{};
     a.in = series;
     a.zout = opts.znorm ? const_cast<float*>(series) : nullptr;
+    a.inv_len_pow2 = inv_len_pow2(len);
     a.n = n;
     a.L = len;
     a.P = r.P;
@@ -1315,7 +1324,11 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
     a.absmax = cnt + 1;
     a.nonfinite = reinterpret_cast<int*>(cnt + 0);
     if (w < 16) MESSI_HIP_TRY(hipMemsetAsync(W[0].p, 0, sizeof(uint4) * (size_t)n, s));
-    const bool seg_path = !opts.znorm && a.m <= 64;
+    // Segments of at most 64 values take the segment summariser; a build that
+    // also z-normalises runs the z-normalisation kernel first (the same z
+    // values as the general kernel's fused pass, which reads and writes at
+    // about a third of the rate of the two passes together).
+    const bool seg_path = a.m <= 64;
     // the fine summary: F sub-segments per segment (none unless m is a power of two in [2, 64])
     const int fF = fine_per_segment(a.m);
     ix->wf = fF ? w * fF : 0;
@@ -1329,8 +1342,13 @@ int build_index(Index* ix, const float* series, int64_t n, int32_t len, int32_t 
         MESSI_TRY(cells.alloc(kCells));
         MESSI_HIP_TRY(hipMemcpyAsync(cells.p, hc, kCells, hipMemcpyHostToDevice, s));
     }
+    if (seg_path && opts.znorm) {
+        tm.start();
+        MESSI_TRY(znorm_device(const_cast<float*>(series), n, len, s, reinterpret_cast<int*>(cnt + 0)));
+        ix->info.ms_znorm = tm.stop_ms();
+    }
     tm.start();
-    if (opts.znorm) {
+    if (opts.znorm && !seg_path) {
         MESSI_TRY((launch_summarize<true, true>(a, r.E, s)));
     } else if (seg_path) {
         SegArgs sa{};
