@@ -1360,7 +1360,12 @@ scan_kernel(QArgs a) {
 constexpr int kFlatList = kChunk;  // list entries per wave: a chunk's members at most
 constexpr int kFlatIssue = 8;      // coarse words in flight per lane
 constexpr uint32_t kSplitFirst = 64;  // chunks of the split scan's first round
-constexpr int kWordIssue = 4;      // words in flight per lane in the refine kernel's word stage
+// words in flight per lane in the refine kernel's word stage: each is a chain
+// of two dependent gathers (segment entry, then word and series index), and
+// one chain per lane with more waves resident ran fastest (refine kernel
+// 54.5 us per query at 100M x 256, against 55.7, 60.2, 64.6 and 79.3 us with
+// 2, 3, 4 and 8 chains per lane)
+constexpr int kWordIssue = 1;
 
 // Lower U from the histogram of candidate distances (one wave).
 __device__ void wave_hist_refresh(const QArgs& a, int q, QState& st, float& U) {
